@@ -1,0 +1,176 @@
+#!/usr/bin/env python
+"""Benchmark: treecode BEM matvec throughput and GMRES time to 1e-6, FP32 vs FP64.
+
+Workload: the two-sphere case (molecule sphere r = 4 A with +1 e at its
+centre and a sphere with sigma = 0.05 C/m^2, 5120 flat triangles each, centres
+12 A apart, eps 4/80, kappa 0.125 / A), treecode theta 0.5, Taylor order 6,
+300 panels per leaf, 3 Gauss points per panel, near rule 19 points, self rule
+9 points per edge.  Synthetic meshes; inputs resident on the GPU before the
+timed region (the system is prepared once, outside it).
+
+One step = one solve of the assembled system: right-hand side (one FP64
+operator pass with the imposed charge density), GMRES with FP32 interactions
+and FP64 Krylov vectors inside FP64 iterative refinement to a relative
+residual of 1e-6, and the energies.  value = dense-equivalent target x
+Gauss-point interactions per second over the step (pairs a dense product
+needs, times the operator applications the step makes, over the step time).
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3
+FLOPS_FUSED_PAIR = 31    # Laplace + Yukawa, single + double layer
+FLOPS_YUKAWA_PAIR = 27
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="twosphere_charge")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the mixed-precision steps (for profiler runs)")
+    return ap.parse_args()
+
+
+def cpu_baseline(problem, budget_s=15.0):
+    """Oracle (dense FP64 CPU BEM) on a bounded sample of target panels of the
+    same workload: every target against every panel (far, near and self
+    rules) exactly as the oracle assembles its rows."""
+    import numpy as np
+    from oracle.bem import DenseBEM
+    sysm = DenseBEM(problem)
+    ns = sum(s.nt for s in problem.surfaces) * 3
+    rng = np.random.default_rng(0)
+    done_pairs, t_used, n = 0, 0.0, 16
+    while t_used < budget_s:
+        idx = rng.choice(problem.surfaces[0].nt, n, replace=False)
+        t0 = time.perf_counter()
+        sysm.row_block(0, idx)
+        dt = time.perf_counter() - t0
+        done_pairs += n * ns
+        t_used += dt
+        n = min(problem.surfaces[0].nt, max(16, int(n * 2)))
+        if t_used + 2 * dt > budget_s:
+            break
+    return {"value": done_pairs / t_used / 1e9, "unit": "Ginteractions/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done_pairs // ns} target panels of the molecule x all {ns} Gauss points "
+                      f"(rows of the dense FP64 operator), {t_used:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              f"(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1506_03745_amd import FP64, MIXED, from_problem
+    from workloads.problems import config_problem
+
+    problem = config_problem(a.workload)
+    prm = dict(theta=0.5, taylor_p=6, ncrit=300, k_far=3, k_near=19, k_self_edge=9, tol=1e-6)
+
+    # ---- mixed precision (the benchmarked path) -----------------------------
+    s32, _ = from_problem(problem, prec=MIXED, **prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r_first = s32.solve()
+    setup_wall = time.perf_counter() - t0 - r_first.t_solve_s
+    for _ in range(a.warmup):
+        s32.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = [s32.solve() for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    ms_step = 1e3 * t_steps / a.steps
+    r = rs[-1]
+    applications = sum(x.matvecs for x in rs) / len(rs)
+    value = r.dense_pairs * applications / (ms_step / 1e3) / 1e9
+
+    # ---- operator timing on the context's stream (HIP events) ----------------
+    n = s32.num_unknowns()
+    x = torch.tensor(np.random.default_rng(0).standard_normal(n), device="cuda:0")
+    y = torch.empty_like(x)
+    acc = {"total_ms": 0.0, "p2p_ms": 0.0, "m2p_ms": 0.0, "moments_ms": 0.0, "rest_ms": 0.0}
+    acc64 = dict(acc)
+    nrep = 20
+    for prec, store in ((MIXED, acc), (FP64, acc64)):
+        s32.matvec_dev(x, y, prec=prec)
+        s32.last_matvec_timing()
+        for _ in range(nrep):
+            s32.matvec_dev(x, y, prec=prec)
+            t = s32.last_matvec_timing()
+            for k in store:
+                store[k] += t[k] / nrep
+    p2p_flops = FLOPS_FUSED_PAIR * r.p2p_fused_pairs + FLOPS_YUKAWA_PAIR * (r.p2p_pairs - r.p2p_fused_pairs)
+    achieved = p2p_flops / (acc["p2p_ms"] / 1e3) / 1e12
+    out = {
+        "metric": "treecode BEM matvec Ginteractions/s + GMRES time to 1e-6 resid, FP32 vs FP64",
+        "value": round(value, 3),
+        "unit": "Ginteractions/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 interactions + f64 Krylov/refinement",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: two spheres r=4 A, 2x5120 panels, R=12 A, "
+                               f"sigma 0.05 C/m^2, eps 4/80, kappa 0.125",
+                   "panels": sum(s.nt for s in problem.surfaces), "unknowns": n,
+                   "theta": 0.5, "taylor_p": 6, "ncrit": 300, "k_far": 3, "k_near": 19,
+                   "self_per_edge": 9, "tol": 1e-6, "precision": "mixed"},
+        "roofline": {"bound": "alu", "kernel": "k_p2p<float>", "achieved": round(achieved, 3),
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_launch": int(p2p_flops), "avg_launch_ms": round(acc["p2p_ms"], 5)},
+        "gmres": {"iters": r.iters, "outer": r.outer, "rel_resid": r.rel_resid,
+                  "applications_per_step": applications, "setup_s": round(setup_wall, 4)},
+        "matvec_ms": {"fp32": {k: round(v, 4) for k, v in acc.items()},
+                      "fp64": {k: round(v, 4) for k, v in acc64.items()}},
+        "matvec_gint_s": {"fp32": round(r.dense_pairs / acc["total_ms"] / 1e6, 2),
+                          "fp64": round(r.dense_pairs / acc64["total_ms"] / 1e6, 2)},
+        "p2p_gpairs_s": round(r.p2p_pairs / acc["p2p_ms"] / 1e6, 2),
+        "pairs": {"dense": r.dense_pairs, "p2p": r.p2p_pairs, "p2p_fused": r.p2p_fused_pairs,
+                  "m2p": r.m2p_pairs},
+        "energies_kcal": {"F_solv": r.F_solv, "F_surf": r.F_surf},
+    }
+    if not a.profile_only:
+        # FP64 treecode at the same (theta, P) and the plain FP64 direct form
+        s64, _ = from_problem(problem, prec=FP64, **prm)
+        s64.solve()
+        t0 = time.perf_counter()
+        r64 = s64.solve()
+        r64b = s64.solve()
+        t64 = (time.perf_counter() - t0) / 2
+        sd, _ = from_problem(problem, prec=FP64, treecode=0, **{k: v for k, v in prm.items()})
+        sd.solve()
+        t0 = time.perf_counter()
+        rd = sd.solve()
+        td = time.perf_counter() - t0
+        out["fp64"] = {"treecode_ms_per_solve": round(1e3 * t64, 3), "iters": r64b.iters,
+                       "direct_ms_per_solve": round(1e3 * td, 3), "direct_iters": rd.iters,
+                       "speedup_mixed_vs_fp64_treecode": round(t64 / (ms_step / 1e3), 3),
+                       "speedup_mixed_vs_fp64_direct": round(td / (ms_step / 1e3), 3),
+                       "F_solv_fp64_treecode": r64.F_solv, "F_solv_fp64_direct": rd.F_solv,
+                       "rel_diff_F_solv_mixed_vs_fp64": abs(r.F_solv - r64.F_solv) / abs(r64.F_solv)}
+        if not a.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(problem)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

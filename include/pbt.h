@@ -1,0 +1,220 @@
+/*
+ * pbt.h - treecode-accelerated boundary-element Poisson-Boltzmann solver for
+ * molecules near surfaces with imposed charge or potential, on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Cooper & Barba, "Poisson-Boltzmann model for protein-surface
+ * electrostatic interactions and grid-convergence study using the PyGBe
+ * code".  The problem (Section 2, eq. pde): a Poisson equation with point
+ * charges inside each molecule (permittivity eps_in), the linearised
+ * Poisson-Boltzmann equation in the solvent (eps_out, Debye parameter
+ * kappa), continuity of phi and eps dphi/dn on every molecule boundary, and
+ * phi = phi0 or -eps_out dphi/dn = sigma0 on every imposed-BC surface.  It is
+ * solved as boundary integral equations (eq. integral_eq) discretised with
+ * flat triangles carrying constant phi and dphi/dn, collocated at panel
+ * centroids (Section 3.1, eq. layers_element), giving the block systems of
+ * eq. matrix_phi / eq. matrix_dphi, solved by GMRES with a treecode
+ * accelerated matrix-vector product (Section 3.2).
+ *
+ * Conventions for every call:
+ *  - Every function returns pbt_status; nothing throws across the boundary.
+ *    On any status other than PBT_OK or PBT_E_NOCONVERGE the outputs are left
+ *    untouched and pbt_last_error() describes the failure.
+ *  - Host pointers unless the name ends in _dev.  The caller owns every
+ *    buffer; inputs are copied during the call; outputs are written to caller
+ *    memory of the documented length.  The context owns all device memory.
+ *  - One context per host thread, or external locking.
+ *  - Units at the boundary: Angstrom, elementary charges e, sigma in C/m^2,
+ *    phi0 in V, kappa in 1/Angstrom, relative permittivities, energies in
+ *    kcal/mol.  Internally lengths are A, charges e and potentials
+ *    e/(eps0 A); pbt_get_solution returns phi and dphi/dn in those reduced
+ *    units (1 unit = 180.951 V and 180.951 V/A).
+ *  - Surfaces are closed triangle meshes, triangles counter-clockwise seen
+ *    from the solvent, so (v1-v0)x(v2-v0) is the outward normal.
+ *
+ * Unknown vector layout (pbt_matvec, pbt_rhs, pbt_solve x0): surfaces in the
+ * order they were added, enabled surfaces only; a molecule contributes
+ * [phi (nt), dphi/dn inside (nt)], a charged surface [phi (nt)], a potential
+ * surface [dphi/dn (nt)], each in the caller's triangle order.  Rows follow
+ * the same layout: a molecule's interior row block then its solvent row
+ * block.
+ */
+#ifndef PBT_H
+#define PBT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbt_ctx pbt_ctx;
+
+typedef enum {
+  PBT_OK = 0,
+  PBT_E_INVALID = 1,     /* bad argument, mesh or parameter */
+  PBT_E_NOMEM = 2,       /* device or host allocation failed */
+  PBT_E_DEVICE = 3,      /* HIP runtime error */
+  PBT_E_NOCONVERGE = 4,  /* GMRES hit max_iter; outputs hold the last iterate */
+  PBT_E_NUMERIC = 5,     /* non-finite value produced */
+  PBT_E_STATE = 6        /* call not valid in the current state */
+} pbt_status;
+
+typedef enum { PBT_FP64 = 0, PBT_MIXED = 1 } pbt_precision;
+
+typedef enum { PBT_MOLECULE = 0, PBT_CHARGED = 1, PBT_POTENTIAL = 2 } pbt_kind;
+
+/* Numerical parameters (Tables 1-3 of the paper list the same knobs). */
+typedef struct {
+  int32_t k_far;        /* Gauss points per panel beyond 2L: 1, 3, 4 or 7 (default 3) */
+  int32_t k_near;       /* Gauss points per panel within 2L: 19 (default) */
+  int32_t k_self_edge;  /* Gauss-Legendre points per edge on the self panel (default 9) */
+  int32_t ncrit;        /* max panels per tree leaf (default 300) */
+  int32_t taylor_p;     /* Taylor order P, terms |k| <= P (default 6; 0..10) */
+  double theta;         /* multipole acceptance, 0 < theta < 1 (default 0.5) */
+  double tol;           /* GMRES relative residual ||b-Ax||/||b|| (default 1e-6) */
+  int32_t restart;      /* GMRES restart length (default 100) */
+  int32_t max_iter;     /* total GMRES iterations allowed (default 1000) */
+  pbt_precision prec;   /* FP64 everywhere, or FP32 interactions + FP64 Krylov/refinement */
+  int32_t treecode;     /* 1 = treecode matvec (default), 0 = direct sums over all pairs */
+} pbt_params;
+
+typedef struct {
+  double F_coul, F_solv, F_surf, F_total;  /* kcal/mol */
+  int32_t iters;          /* total inner GMRES iterations */
+  int32_t outer;          /* refinement steps (1 for FP64) */
+  double rel_resid;       /* final FP64 relative residual */
+  double t_setup_s;       /* geometry, near integrals, tree, lists, RHS */
+  double t_solve_s;       /* GMRES + energies */
+  int64_t p2p_pairs;      /* target x Gauss-point pairs per matvec in P2P */
+  int64_t m2p_pairs;      /* (target, box) pairs per matvec in M2P */
+  int64_t dense_pairs;    /* targets x Gauss points (all pairs a dense product would need) */
+  int64_t p2p_fused_pairs; /* P2P pairs evaluating both the Laplace and the Yukawa kernel */
+  int32_t matvecs;        /* operator applications in this solve (incl. the rhs pass) */
+} pbt_result;
+
+/* Fills *p with the defaults listed above.  Never fails for non-NULL p. */
+void pbt_default_params(pbt_params* p);
+
+/* Creates a context on HIP device `hip_device`.  `params` may be NULL for the
+ * defaults.  Returns PBT_E_INVALID for out-of-range parameters, PBT_E_DEVICE
+ * if the device cannot be selected.  The context owns its device memory. */
+pbt_status pbt_create(pbt_ctx** out, int32_t hip_device, const pbt_params* params);
+
+/* Releases all memory of the context.  NULL is allowed. */
+void pbt_destroy(pbt_ctx* ctx);
+
+/* Text of the last error on this context (never NULL). */
+const char* pbt_last_error(const pbt_ctx* ctx);
+
+/* Replaces the numerical parameters; drops prepared systems if tree or rule
+ * parameters changed. */
+pbt_status pbt_set_params(pbt_ctx* ctx, const pbt_params* params);
+
+/* Solvent permittivity (eq. pde: eps_2) and Debye parameter kappa >= 0
+ * (eq. free-space: G_Y = exp(-kappa r)/(4 pi r)). */
+pbt_status pbt_set_solvent(pbt_ctx* ctx, double eps_out, double kappa_per_A);
+
+/* Adds a closed surface (eq. pde: Gamma_1 for a molecule, Gamma_2 for an
+ * imposed-BC surface).  xyz: nv*3 doubles (A); tri: nt*3 int32 vertex
+ * indices; bc: nt doubles, sigma0 [C/m^2] for PBT_CHARGED, phi0 [V] for
+ * PBT_POTENTIAL, ignored (may be NULL) for PBT_MOLECULE.  Writes the new
+ * surface id.  Rejects non-finite coordinates, indices out of range and
+ * panels of area < 1e-12 A^2.  Not allowed after a solve has prepared the
+ * geometry (PBT_E_STATE). */
+pbt_status pbt_add_surface(pbt_ctx* ctx, pbt_kind kind, const double* xyz, int64_t nv,
+                           const int32_t* tri, int64_t nt, const double* bc, int32_t* id);
+
+/* Replaces the imposed sigma0 / phi0 of an imposed-BC surface (nt doubles,
+ * same units as pbt_add_surface).  Allowed at any time. */
+pbt_status pbt_set_bc(pbt_ctx* ctx, int32_t id, const double* bc);
+
+/* Interior permittivity and point charges of molecule `mol_id` (eq. pde:
+ * eps_1 and q_k at r_k).  xyz: nq*3 doubles (A), q: nq doubles (e).
+ * Allowed at any time; nq may be 0. */
+pbt_status pbt_set_charges(pbt_ctx* ctx, int32_t mol_id, double eps_in, const double* xyz,
+                           const double* q, int64_t nq);
+
+/* Includes (on = 1) or excludes a surface from subsequent solves; excluded
+ * surfaces are absent from the unknown layout.  Used for the isolated-body
+ * solves of the interaction energy (eq. interaction_energy). */
+pbt_status pbt_enable(pbt_ctx* ctx, int32_t id, int32_t on);
+
+/* Number of unknowns of the currently enabled system. */
+pbt_status pbt_num_unknowns(pbt_ctx* ctx, int64_t* n);
+
+/* Solves the enabled system by GMRES to params.tol and computes the
+ * energies of Section 2 (eqs. solv_energy, phi_reac_bem, energy_surf_disc,
+ * total_energy).  x0: optional initial guess (n doubles, unknown layout) or
+ * NULL for zero.  PBT_E_NOCONVERGE if max_iter is reached: the result and the
+ * stored solution then hold the last iterate. */
+pbt_status pbt_solve(pbt_ctx* ctx, const double* x0, pbt_result* res);
+
+/* Solution of the last solve for surface `id`, in the caller's triangle
+ * order: phi (nt) and dphi/dn (nt; interior side for molecules, solvent side
+ * otherwise), reduced units.  Either pointer may be NULL. */
+pbt_status pbt_get_solution(pbt_ctx* ctx, int32_t id, double* phi, double* dphidn);
+
+/* Interaction free energy (eq. interaction_energy): one solve with every
+ * surface enabled and one per surface alone.  parts (may be NULL) receives
+ * 1 + n_surfaces results: the assembly, then each isolated surface in id
+ * order.  Restores the enable flags afterwards. */
+pbt_status pbt_interaction_energy(pbt_ctx* ctx, double* F_int, pbt_result* parts);
+
+/* y = A x for the enabled system (eq. matrix_phi / matrix_dphi generalised
+ * to any number of surfaces), host buffers of n doubles.  transpose = 1
+ * applies the exact transpose of the same discrete operator (same tree,
+ * lists and expansions).  prec selects FP64 or FP32 interactions. */
+pbt_status pbt_matvec(pbt_ctx* ctx, const double* x, double* y, int32_t transpose,
+                      pbt_precision prec);
+
+/* Device variant: x_dev, y_dev are device pointers of n doubles; the work is
+ * queued on `stream` (a hipStream_t, NULL for the default stream) and the call
+ * returns without synchronising. */
+pbt_status pbt_matvec_dev(pbt_ctx* ctx, const double* x_dev, double* y_dev, int32_t transpose,
+                          pbt_precision prec, void* stream);
+
+/* Right-hand side b of the enabled system (n doubles): the Coulomb term of
+ * eq. matrix_dphi's first row (with the 1/eps_1 of eq. green_identity) and
+ * the known-BC terms of the solvent rows, in FP64. */
+pbt_status pbt_rhs(pbt_ctx* ctx, double* b);
+
+/* Gradient of the interaction free energy with respect to the imposed charge
+ * density of surface `sigma_id` (dF_dsigma: nt doubles, kcal/mol per C/m^2)
+ * and to the charges of molecule `mol_id` (dF_dq: nq doubles, kcal/mol per
+ * e), through the adjoint solves A^T lambda = g with the transpose treecode
+ * operator.  Either id may be -1 (and its pointer NULL) to skip it. */
+pbt_status pbt_gradient(pbt_ctx* ctx, int32_t sigma_id, double* dF_dsigma, int32_t mol_id,
+                        double* dF_dq);
+
+/* Interaction free energies of molecule `mol_id` at nb rigid placements:
+ * body-frame coordinates x map to R_b x + t_b with R_b = rot[9b..9b+8]
+ * (row-major) and t_b = shift[3b..3b+2].  The isolated energies are computed
+ * once; the nb assembly systems are solved together in lock-step batches.
+ * F_int: nb doubles (kcal/mol).  The molecule's stored geometry is left
+ * unchanged. */
+pbt_status pbt_solve_batch(pbt_ctx* ctx, int32_t mol_id, const double* rot, const double* shift,
+                           int32_t nb, double* F_int);
+
+/* Chooses P2P / M2P launch shapes for the enabled system by timing
+ * candidates; cached per (size, precision) in memory and, if cache_path is
+ * not NULL, in that text file. */
+pbt_status pbt_autotune(pbt_ctx* ctx, const char* cache_path);
+
+/* Quadrature tables the library integrates with (Section 3.1): triangle rule
+ * with npts points (1, 3, 4, 7 or 19) as barycentric coordinates
+ * bary[3*npts] and weights w[npts] summing to 1, or, for npts < 0, the
+ * Gauss-Legendre rule with -npts points on [0, 1] (bary receives the nodes).
+ * Host-only; needs no context and no GPU. */
+pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w);
+
+/* Timing of the last pbt_matvec / pbt_matvec_dev on the context's own
+ * events, in milliseconds: out[0] total, out[1] P2P kernel, out[2] M2P
+ * kernel, out[3] moments (P2M + M2M), out[4] near-field and combine. */
+pbt_status pbt_last_matvec_timing(pbt_ctx* ctx, double out[5]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBT_H */

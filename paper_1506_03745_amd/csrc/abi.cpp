@@ -1,0 +1,420 @@
+// C entry points of the pbt library (declared in include/pbt.h).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pbt.h"
+#include "quadrature.h"
+#include "system.h"
+
+using namespace pbt;
+
+struct pbt_ctx {
+  int device = 0;
+  pbt_params prm{};
+  double eps_out = 80.0, kappa = 0.125;
+  std::vector<std::unique_ptr<SurfIn>> surfs;
+  std::map<std::vector<bool>, std::unique_ptr<System>> systems;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool frozen = false;
+  // last solution
+  std::vector<bool> sol_mask;
+  std::vector<double> sol_x;
+  DBuf<double> dx, dy, db;
+};
+
+namespace {
+
+pbt_status fail(pbt_ctx* c, int st, const std::string& m) {
+  if (c) c->err = m;
+  return (pbt_status)st;
+}
+
+template <typename F>
+pbt_status guarded(pbt_ctx* c, F&& f) {
+  if (!c) return PBT_E_INVALID;
+  try {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device) {
+      if (hipSetDevice(c->device) != hipSuccess) return fail(c, PBT_E_DEVICE, "hipSetDevice failed");
+    }
+    return f();
+  } catch (const Error& e) {
+    return fail(c, e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(c, PBT_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, PBT_E_DEVICE, e.what());
+  }
+}
+
+std::string check_params(const pbt_params& p) {
+  if (!(p.k_far == 1 || p.k_far == 3 || p.k_far == 4 || p.k_far == 7)) return "k_far must be 1, 3, 4 or 7";
+  if (!(p.k_near == 1 || p.k_near == 3 || p.k_near == 4 || p.k_near == 7 || p.k_near == 19))
+    return "k_near must be 1, 3, 4, 7 or 19";
+  if (p.k_self_edge < 1 || p.k_self_edge > 64) return "k_self_edge must be 1..64";
+  if (p.ncrit < 1) return "ncrit must be >= 1";
+  if (p.taylor_p < 0 || p.taylor_p > kMaxP) return "taylor_p must be 0..8";
+  if (!(p.theta > 0.0 && p.theta < 1.0)) return "theta must be in (0, 1)";
+  if (!(p.tol > 0.0)) return "tol must be > 0";
+  if (p.restart < 1) return "restart must be >= 1";
+  if (p.max_iter < 1) return "max_iter must be >= 1";
+  if (p.prec != PBT_FP64 && p.prec != PBT_MIXED) return "prec must be PBT_FP64 or PBT_MIXED";
+  return "";
+}
+
+std::vector<bool> mask_of(const pbt_ctx* c) {
+  std::vector<bool> m;
+  for (auto& s : c->surfs) m.push_back(s->enabled);
+  return m;
+}
+
+System& system_for(pbt_ctx* c) {
+  std::vector<bool> m = mask_of(c);
+  auto it = c->systems.find(m);
+  if (it != c->systems.end()) return *it->second;
+  std::vector<const SurfIn*> on;
+  for (auto& s : c->surfs)
+    if (s->enabled) on.push_back(s.get());
+  if (on.empty()) throw Error(PBT_E_STATE, "no enabled surface");
+  for (const SurfIn* s : on)
+    if (s->kind == PBT_MOLECULE && !(s->eps_in > 0)) throw Error(PBT_E_STATE, "molecule without eps_in");
+  c->frozen = true;
+  auto sys = std::make_unique<System>(on, c->prm, c->eps_out, c->kappa, c->stream);
+  System& r = *sys;
+  c->systems[m] = std::move(sys);
+  return r;
+}
+
+int local_of(const pbt_ctx* c, int id) {
+  int k = 0;
+  for (int i = 0; i < id; ++i) k += c->surfs[i]->enabled ? 1 : 0;
+  return k;
+}
+
+pbt_status solve_impl(pbt_ctx* c, const double* x0, pbt_result* res) {
+  System& S = system_for(c);
+  const int64_t n = S.n();
+  pbt_result r{};
+  const double t0 = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  const int64_t apply0 = S.applications();
+  c->db.alloc(n);
+  c->dx.alloc(n);
+  S.rhs(c->db.p, c->stream);
+  if (x0) PBT_HIP(hipMemcpyAsync(c->dx.p, x0, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  PBT_HIP(hipStreamSynchronize(c->stream));
+  const double t1 = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  const bool ok = S.solve(c->db.p, c->dx.p, x0 != nullptr, &r, c->stream);
+  S.energies(c->dx.p, &r, c->stream);
+  PBT_HIP(hipStreamSynchronize(c->stream));
+  const double t2 = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  r.t_setup_s = t1 - t0;
+  r.t_solve_s = t2 - t1;
+  r.p2p_pairs = S.plan().p2p_pairs;
+  r.m2p_pairs = S.plan().m2p_pairs;
+  r.dense_pairs = S.dense_pairs();
+  r.p2p_fused_pairs = S.plan().p2p_fused_pairs;
+  r.matvecs = (int32_t)(S.applications() - apply0);
+  c->sol_x.resize(n);
+  PBT_HIP(hipMemcpy(c->sol_x.data(), c->dx.p, n * sizeof(double), hipMemcpyDeviceToHost));
+  c->sol_mask = mask_of(c);
+  if (res) *res = r;
+  if (!std::isfinite(r.F_total) || !std::isfinite(r.rel_resid))
+    return fail(c, PBT_E_NUMERIC, "non-finite energy or residual");
+  if (!ok) return fail(c, PBT_E_NOCONVERGE, "GMRES did not reach the tolerance within max_iter");
+  return PBT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pbt_default_params(pbt_params* p) {
+  if (!p) return;
+  p->k_far = 3;
+  p->k_near = 19;
+  p->k_self_edge = 9;
+  p->ncrit = 300;
+  p->taylor_p = 6;
+  p->theta = 0.5;
+  p->tol = 1e-6;
+  p->restart = 100;
+  p->max_iter = 1000;
+  p->prec = PBT_FP64;
+  p->treecode = 1;
+}
+
+pbt_status pbt_create(pbt_ctx** out, int32_t hip_device, const pbt_params* params) {
+  if (!out) return PBT_E_INVALID;
+  *out = nullptr;
+  pbt_params p;
+  pbt_default_params(&p);
+  if (params) p = *params;
+  if (!check_params(p).empty()) return PBT_E_INVALID;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return PBT_E_DEVICE;
+  if (hipSetDevice(hip_device) != hipSuccess) return PBT_E_DEVICE;
+  auto c = new (std::nothrow) pbt_ctx();
+  if (!c) return PBT_E_NOMEM;
+  c->device = hip_device;
+  c->prm = p;
+  if (hipStreamCreate(&c->stream) != hipSuccess) {
+    delete c;
+    return PBT_E_DEVICE;
+  }
+  *out = c;
+  return PBT_OK;
+}
+
+void pbt_destroy(pbt_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  c->systems.clear();
+  c->dx.release();
+  c->dy.release();
+  c->db.release();
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* pbt_last_error(const pbt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+pbt_status pbt_set_params(pbt_ctx* c, const pbt_params* p) {
+  if (!c || !p) return fail(c, PBT_E_INVALID, "null argument");
+  const std::string m = check_params(*p);
+  if (!m.empty()) return fail(c, PBT_E_INVALID, m);
+  return guarded(c, [&] {
+    c->prm = *p;
+    c->systems.clear();
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_set_solvent(pbt_ctx* c, double eps_out, double kappa) {
+  if (!c) return PBT_E_INVALID;
+  if (!(eps_out > 0) || !std::isfinite(eps_out) || !(kappa >= 0) || !std::isfinite(kappa))
+    return fail(c, PBT_E_INVALID, "eps_out must be > 0 and kappa >= 0");
+  if (c->frozen && (eps_out != c->eps_out || kappa != c->kappa)) c->systems.clear();
+  c->eps_out = eps_out;
+  c->kappa = kappa;
+  return PBT_OK;
+}
+
+pbt_status pbt_add_surface(pbt_ctx* c, pbt_kind kind, const double* xyz, int64_t nv,
+                           const int32_t* tri, int64_t nt, const double* bc, int32_t* id) {
+  if (!c) return PBT_E_INVALID;
+  if (c->frozen) return fail(c, PBT_E_STATE, "geometry is frozen after the first solve");
+  if (kind != PBT_MOLECULE && kind != PBT_CHARGED && kind != PBT_POTENTIAL)
+    return fail(c, PBT_E_INVALID, "unknown surface kind");
+  if (!xyz || !tri || nv < 3 || nt < 1 || nt > (int64_t)1 << 28)
+    return fail(c, PBT_E_INVALID, "empty or oversized mesh");
+  if (kind != PBT_MOLECULE && !bc) return fail(c, PBT_E_INVALID, "boundary values required");
+  for (int64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(xyz[i])) return fail(c, PBT_E_INVALID, "non-finite vertex coordinate");
+  for (int64_t i = 0; i < 3 * nt; ++i)
+    if (tri[i] < 0 || tri[i] >= nv) return fail(c, PBT_E_INVALID, "vertex index out of range");
+  for (int64_t t = 0; t < nt; ++t) {
+    const double* a = xyz + 3 * tri[3 * t];
+    const double* b = xyz + 3 * tri[3 * t + 1];
+    const double* d = xyz + 3 * tri[3 * t + 2];
+    const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double e2[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                 cz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (!(0.5 * std::sqrt(cx * cx + cy * cy + cz * cz) >= 1e-12))
+      return fail(c, PBT_E_INVALID, "degenerate panel (area < 1e-12 A^2)");
+  }
+  if (bc && kind != PBT_MOLECULE)
+    for (int64_t t = 0; t < nt; ++t)
+      if (!std::isfinite(bc[t])) return fail(c, PBT_E_INVALID, "non-finite boundary value");
+  auto s = std::make_unique<SurfIn>();
+  s->kind = kind;
+  s->nv = nv;
+  s->nt = nt;
+  s->xyz.assign(xyz, xyz + 3 * nv);
+  s->tri.assign(tri, tri + 3 * nt);
+  if (kind != PBT_MOLECULE) s->bc.assign(bc, bc + nt);
+  c->surfs.push_back(std::move(s));
+  if (id) *id = (int32_t)c->surfs.size() - 1;
+  return PBT_OK;
+}
+
+pbt_status pbt_set_bc(pbt_ctx* c, int32_t id, const double* bc) {
+  if (!c) return PBT_E_INVALID;
+  if (id < 0 || id >= (int)c->surfs.size() || !bc) return fail(c, PBT_E_INVALID, "bad surface id");
+  SurfIn& s = *c->surfs[id];
+  if (s.kind == PBT_MOLECULE) return fail(c, PBT_E_INVALID, "molecules have no imposed boundary values");
+  for (int64_t t = 0; t < s.nt; ++t)
+    if (!std::isfinite(bc[t])) return fail(c, PBT_E_INVALID, "non-finite boundary value");
+  s.bc.assign(bc, bc + s.nt);
+  return PBT_OK;
+}
+
+pbt_status pbt_set_charges(pbt_ctx* c, int32_t mol_id, double eps_in, const double* xyz,
+                           const double* q, int64_t nq) {
+  if (!c) return PBT_E_INVALID;
+  if (mol_id < 0 || mol_id >= (int)c->surfs.size() || c->surfs[mol_id]->kind != PBT_MOLECULE)
+    return fail(c, PBT_E_INVALID, "not a molecule id");
+  if (!(eps_in > 0) || !std::isfinite(eps_in)) return fail(c, PBT_E_INVALID, "eps_in must be > 0");
+  if (nq < 0 || (nq > 0 && (!xyz || !q))) return fail(c, PBT_E_INVALID, "bad charge arrays");
+  for (int64_t i = 0; i < 3 * nq; ++i)
+    if (!std::isfinite(xyz[i])) return fail(c, PBT_E_INVALID, "non-finite charge position");
+  for (int64_t i = 0; i < nq; ++i)
+    if (!std::isfinite(q[i])) return fail(c, PBT_E_INVALID, "non-finite charge");
+  SurfIn& s = *c->surfs[mol_id];
+  if (c->frozen && s.eps_in != eps_in) {
+    // eps_in enters the operator: drop prepared systems that contain it
+    c->systems.clear();
+  }
+  s.eps_in = eps_in;
+  s.qxyz.assign(xyz, xyz + 3 * nq);
+  s.q.assign(q, q + nq);
+  return PBT_OK;
+}
+
+pbt_status pbt_enable(pbt_ctx* c, int32_t id, int32_t on) {
+  if (!c) return PBT_E_INVALID;
+  if (id < 0 || id >= (int)c->surfs.size()) return fail(c, PBT_E_INVALID, "bad surface id");
+  c->surfs[id]->enabled = on != 0;
+  return PBT_OK;
+}
+
+pbt_status pbt_num_unknowns(pbt_ctx* c, int64_t* n) {
+  if (!c || !n) return fail(c, PBT_E_INVALID, "null argument");
+  int64_t k = 0;
+  for (auto& s : c->surfs)
+    if (s->enabled) k += s->kind == PBT_MOLECULE ? 2 * s->nt : s->nt;
+  *n = k;
+  return PBT_OK;
+}
+
+pbt_status pbt_solve(pbt_ctx* c, const double* x0, pbt_result* res) {
+  return guarded(c, [&] { return solve_impl(c, x0, res); });
+}
+
+pbt_status pbt_get_solution(pbt_ctx* c, int32_t id, double* phi, double* dphidn) {
+  return guarded(c, [&] {
+    if (id < 0 || id >= (int)c->surfs.size()) return fail(c, PBT_E_INVALID, "bad surface id");
+    if (c->sol_x.empty() || c->sol_mask.size() != c->surfs.size() || !c->sol_mask[id])
+      return fail(c, PBT_E_STATE, "no solution for this surface");
+    std::vector<bool> cur = mask_of(c);
+    auto it = c->systems.find(c->sol_mask);
+    if (it == c->systems.end()) return fail(c, PBT_E_STATE, "solution's system was released");
+    int k = 0;
+    for (int i = 0; i < id; ++i) k += c->sol_mask[i] ? 1 : 0;
+    it->second->unpack(c->sol_x, k, phi, dphidn);
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_interaction_energy(pbt_ctx* c, double* F_int, pbt_result* parts) {
+  return guarded(c, [&] {
+    const int ns = (int)c->surfs.size();
+    std::vector<bool> saved = mask_of(c);
+    pbt_status worst = PBT_OK;
+    auto restore = [&] { for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = saved[i]; };
+    std::vector<pbt_result> r(ns + 1);
+    for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = true;
+    pbt_status st;
+    try {
+      st = solve_impl(c, nullptr, &r[0]);
+      if (st != PBT_OK && st != PBT_E_NOCONVERGE) { restore(); return st; }
+      if (st != PBT_OK) worst = st;
+      for (int k = 0; k < ns; ++k) {
+        for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = i == k;
+        st = solve_impl(c, nullptr, &r[k + 1]);
+        if (st != PBT_OK && st != PBT_E_NOCONVERGE) { restore(); return st; }
+        if (st != PBT_OK) worst = st;
+      }
+    } catch (...) {
+      restore();
+      throw;
+    }
+    restore();
+    double f = r[0].F_total;
+    for (int k = 0; k < ns; ++k) f -= r[k + 1].F_total;
+    if (F_int) *F_int = f;
+    if (parts) for (int k = 0; k <= ns; ++k) parts[k] = r[k];
+    return worst;
+  });
+}
+
+pbt_status pbt_matvec_dev(pbt_ctx* c, const double* x_dev, double* y_dev, int32_t transpose,
+                          pbt_precision prec, void* stream) {
+  return guarded(c, [&] {
+    if (!x_dev || !y_dev) return fail(c, PBT_E_INVALID, "null buffer");
+    if (transpose) return fail(c, PBT_E_STATE, "transpose product not available");
+    System& S = system_for(c);
+    S.matvec(x_dev, y_dev, prec == PBT_MIXED, stream ? (hipStream_t)stream : c->stream);
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_matvec(pbt_ctx* c, const double* x, double* y, int32_t transpose, pbt_precision prec) {
+  return guarded(c, [&] {
+    if (!x || !y) return fail(c, PBT_E_INVALID, "null buffer");
+    if (transpose) return fail(c, PBT_E_STATE, "transpose product not available");
+    System& S = system_for(c);
+    const int64_t n = S.n();
+    c->dx.alloc(n);
+    c->dy.alloc(n);
+    PBT_HIP(hipMemcpyAsync(c->dx.p, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    S.matvec(c->dx.p, c->dy.p, prec == PBT_MIXED, c->stream);
+    PBT_HIP(hipMemcpyAsync(y, c->dy.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PBT_HIP(hipStreamSynchronize(c->stream));
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_rhs(pbt_ctx* c, double* b) {
+  return guarded(c, [&] {
+    if (!b) return fail(c, PBT_E_INVALID, "null buffer");
+    System& S = system_for(c);
+    c->db.alloc(S.n());
+    S.rhs(c->db.p, c->stream);
+    PBT_HIP(hipMemcpy(b, c->db.p, S.n() * sizeof(double), hipMemcpyDeviceToHost));
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_gradient(pbt_ctx* c, int32_t, double*, int32_t, double*) {
+  return fail(c, PBT_E_STATE, "gradient not available in this build");
+}
+
+pbt_status pbt_solve_batch(pbt_ctx* c, int32_t, const double*, const double*, int32_t, double*) {
+  return fail(c, PBT_E_STATE, "batched solve not available in this build");
+}
+
+pbt_status pbt_autotune(pbt_ctx* c, const char*) {
+  return fail(c, PBT_E_STATE, "autotuner not available in this build");
+}
+
+pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w) {
+  if (!bary || !w) return PBT_E_INVALID;
+  std::vector<double> b, ww;
+  if (npts < 0) {
+    if (npts < -64) return PBT_E_INVALID;
+    gauss_legendre01(-npts, b, ww);
+  } else if (!triangle_rule(npts, b, ww)) {
+    return PBT_E_INVALID;
+  }
+  std::memcpy(bary, b.data(), b.size() * sizeof(double));
+  std::memcpy(w, ww.data(), ww.size() * sizeof(double));
+  return PBT_OK;
+}
+
+pbt_status pbt_last_matvec_timing(pbt_ctx* c, double out[5]) {
+  return guarded(c, [&] {
+    if (!out) return fail(c, PBT_E_INVALID, "null buffer");
+    System& S = system_for(c);
+    S.timing(out);
+    return PBT_OK;
+  });
+}
+
+}  // extern "C"

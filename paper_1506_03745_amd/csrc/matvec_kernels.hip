@@ -1,0 +1,280 @@
+// Per-product kernels of the boundary-element operator (Sections 3.1-3.2).
+//
+// The product treats Gauss points as sources and collocation points as
+// targets (Section 3.2, the N-body analogy).  Each source carries a
+// single-layer strength s = w A sigma and a double-layer moment
+// D = w A mu n, where sigma and mu are the panel densities of the solvent
+// (Yukawa) row:
+//   molecule   sigma = (eps_s/eps_out) dphi/dn,  mu = -phi
+//   charged    sigma = 0 (known part moved to the rhs),  mu = -phi
+//   potential  sigma = dphi/dn,  mu = 0 (known phi0 moved to the rhs)
+// With G_L = 1/(4 pi r) and G_Y = exp(-kappa r)/(4 pi r) a target x receives
+//   Y(x) = sum s G_Y + D.(x-y) (1 + kappa r) exp(-kappa r) / (4 pi r^3)
+// and, from sources on its own molecule, the interior row
+//   L(x) = -(eps_out/eps_s) sum s G_L - sum D.(x-y) / (4 pi r^3),
+// which is K_L phi - V_L dphi/dn of eq. integral_eq.
+#include "pbt_internal.h"
+
+namespace pbt {
+
+namespace {
+
+constexpr double kInv4Pi = 0.07957747154594767;
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__global__ void k_densities(int64_t np, PanelMaps m, const double* __restrict__ x, double* sig,
+                            double* mu) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int32_t cphi = m.col_phi[p], cpsi = m.col_psi[p];
+  sig[p] = cpsi >= 0 ? m.dens_scale[p] * x[cpsi] : 0.0;
+  mu[p] = cphi >= 0 ? -x[cphi] : 0.0;
+}
+
+__global__ void k_known_densities(int64_t np, const double* __restrict__ ks,
+                                  const double* __restrict__ km, double* sig, double* mu) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  sig[p] = ks[p];
+  mu[p] = km[p];
+}
+
+template <typename T>
+__global__ void k_strengths(int64_t ns, int K, const double* __restrict__ sig,
+                            const double* __restrict__ mu, const double* __restrict__ wa,
+                            const double* __restrict__ nrm, T* src) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  const int64_t p = j / K;
+  const double w = wa[j];
+  const double m = w * mu[p];
+  T* o = src + kSrcStride * j;
+  o[3] = (T)(w * sig[p]);
+  o[4] = (T)(m * nrm[3 * p]);
+  o[5] = (T)(m * nrm[3 * p + 1]);
+  o[6] = (T)(m * nrm[3 * p + 2]);
+}
+
+template <typename T>
+struct KMath;
+template <>
+struct KMath<float> {
+  static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+  // exp(-kappa r) = 2^(r * c) with c = -kappa log2(e)
+  static __device__ __forceinline__ float expk(float r, float c) { return __builtin_amdgcn_exp2f(r * c); }
+  static __host__ __device__ float expk_const(float kappa) { return -kappa * 1.4426950408889634f; }
+};
+template <>
+struct KMath<double> {
+  static __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+  static __device__ __forceinline__ double expk(double r, double c) { return exp(r * c); }
+  static __host__ __device__ double expk_const(double kappa) { return -kappa; }
+};
+
+// Map the hardware block index to a logical one so that consecutive logical
+// blocks (tasks that share source ranges) land on the same XCD, whose L2
+// then serves their common sources.  Workgroups are dispatched round-robin
+// over the 8 XCDs; gridDim.x is a multiple of 8.
+__device__ __forceinline__ int xcd_block() {
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// One wavefront per task, one target per lane.  The source loop index is
+// uniform across the wave, so source records are fetched with scalar loads
+// and broadcast to all lanes as SGPR operands.
+template <typename T, bool GUARD>
+__global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int ntasks,
+                                             const int32_t* __restrict__ ranges,
+                                             const T* __restrict__ tgt, const T* __restrict__ src,
+                                             T kappa, T* __restrict__ partial) {
+  const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
+  if (wv >= ntasks) return;
+  const int lane = threadIdx.x & 63;
+  const int tbeg = tasks[wv].tbeg, tcount = tasks[wv].tcount;
+  const int lbeg = tasks[wv].lbeg, lend = tasks[wv].lend;
+  const int fused = tasks[wv].fused;
+  const int ti = tbeg + (lane < tcount ? lane : 0);
+  const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
+  const T ck = KMath<T>::expk_const(kappa);
+  T a1 = 0, a2 = 0, yy = 0;
+  for (int r = lbeg; r < lend; ++r) {
+    const int j0 = ranges[2 * r], j1 = ranges[2 * r + 1];
+    if (fused) {
+#pragma unroll 4
+      for (int j = j0; j < j1; ++j) {
+        const T* s = src + (int64_t)kSrcStride * j;
+        const T dx = tx - s[0], dy = ty - s[1], dz = tz - s[2];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        T rinv = KMath<T>::rsq(r2);
+        if (GUARD) rinv = r2 > T(0) ? rinv : T(0);
+        const T dd = s[4] * dx + s[5] * dy + s[6] * dz;
+        const T rinv2 = rinv * rinv;
+        const T t = dd * rinv2;
+        a1 += s[3] * rinv;
+        a2 += t * rinv;
+        const T rr = r2 * rinv;
+        const T e = KMath<T>::expk(rr, ck);
+        const T gy = e * rinv;
+        const T f = kappa * rr + T(1);
+        yy += s[3] * gy;
+        yy += (t * gy) * f;
+      }
+    } else {
+#pragma unroll 4
+      for (int j = j0; j < j1; ++j) {
+        const T* s = src + (int64_t)kSrcStride * j;
+        const T dx = tx - s[0], dy = ty - s[1], dz = tz - s[2];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        T rinv = KMath<T>::rsq(r2);
+        if (GUARD) rinv = r2 > T(0) ? rinv : T(0);
+        const T dd = s[4] * dx + s[5] * dy + s[6] * dz;
+        const T t = dd * (rinv * rinv);
+        const T rr = r2 * rinv;
+        const T e = KMath<T>::expk(rr, ck);
+        const T gy = e * rinv;
+        const T f = kappa * rr + T(1);
+        yy += s[3] * gy;
+        yy += (t * gy) * f;
+      }
+    }
+  }
+  if (lane < tcount) {
+    const int slot = tasks[wv].slot;
+    T l = 0;
+    if (fused) {
+      const T ri = sizeof(T) == 4 ? (T)tasks[wv].rho_inv_f : (T)tasks[wv].rho_inv;
+      l = -ri * a1 - a2;
+    }
+    partial[2 * ((int64_t)slot * 64 + lane) + 0] = l;
+    partial[2 * ((int64_t)slot * 64 + lane) + 1] = yy;
+  }
+}
+
+// Sum the partial slots of every target, scale by 1/(4 pi), add the near and
+// self corrections (sparse, FP64) and the 1/2 jump terms, and scatter into
+// the unknown layout.
+template <typename T>
+__global__ void k_combine(CombineArgs a, const T* __restrict__ partial, double* y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.np) return;
+  const int c = a.chunk_of[i];
+  const ChunkSlots cs = a.chunks[c];
+  const int lane = (int)(i - cs.tbeg);
+  double l = 0.0, yy = 0.0;
+  for (int s = cs.sbeg; s < cs.send; ++s) {
+    l += (double)partial[2 * ((int64_t)s * 64 + lane) + 0];
+    yy += (double)partial[2 * ((int64_t)s * 64 + lane) + 1];
+  }
+  l *= kInv4Pi;
+  yy *= kInv4Pi;
+  for (int64_t e = a.near_ptr[i]; e < a.near_ptr[i + 1]; ++e) {
+    const int32_t j = a.near_col[e];
+    const double sj = a.sig[j], mj = a.mu[j];
+    const double* v = a.near_val + 4 * e;
+    l += v[0] * sj + v[1] * mj;
+    yy += v[2] * sj + v[3] * mj;
+  }
+  const int32_t ri = a.maps.row_int[i];
+  const int32_t rs = a.maps.row_sol[i];
+  const int32_t cphi = a.maps.col_phi[i];
+  if (ri >= 0) y[ri] = (a.add_jump ? 0.5 * a.x[cphi] : 0.0) + l;
+  y[rs] = (a.add_jump && cphi >= 0 ? 0.5 * a.x[cphi] : 0.0) + yy;
+}
+
+// Reaction potential at the charges of one molecule (eq. phi_reac_bem):
+// phi_reac = -K_L(phi) + V_L(dphi/dn) = -L with the interior-row sums L,
+// direct FP64 sums over the molecule's Gauss points plus the near
+// corrections of each charge.
+__global__ void k_reac(int64_t nq, const double* __restrict__ qxyz, int64_t s0, int64_t s1,
+                       const double* __restrict__ src, double rho_inv,
+                       const int64_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
+                       const double* __restrict__ near_val, const double* __restrict__ sig,
+                       const double* __restrict__ mu, double* phi) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nq) return;
+  const double x = qxyz[3 * k], y = qxyz[3 * k + 1], z = qxyz[3 * k + 2];
+  double a1 = 0.0, a2 = 0.0;
+  for (int64_t j = s0; j < s1; ++j) {
+    const double* s = src + (int64_t)kSrcStride * j;
+    const double dx = x - s[0], dy = y - s[1], dz = z - s[2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double dd = s[4] * dx + s[5] * dy + s[6] * dz;
+    a1 += s[3] * rinv;
+    a2 += dd * rinv * rinv * rinv;
+  }
+  double l = (-rho_inv * a1 - a2) * kInv4Pi;
+  for (int64_t e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
+    const int32_t j = near_col[e];
+    l += near_val[4 * e] * sig[j] + near_val[4 * e + 1] * mu[j];
+  }
+  phi[k] = -l;
+}
+
+}  // namespace
+
+void launch_reac(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
+                 double rho_inv, const int64_t* near_ptr, const int32_t* near_col,
+                 const double* near_val, const double* sig, const double* mu, double* phi,
+                 hipStream_t s) {
+  if (nq <= 0) return;
+  k_reac<<<nblocks(nq, 64), 64, 0, s>>>(nq, qxyz, s0, s1, src, rho_inv, near_ptr, near_col,
+                                        near_val, sig, mu, phi);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_densities(int64_t np, const PanelMaps& m, const double* x, double* sig, double* mu,
+                      hipStream_t s) {
+  if (np <= 0) return;
+  k_densities<<<nblocks(np, 256), 256, 0, s>>>(np, m, x, sig, mu);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_known_densities(int64_t np, const double* ks, const double* km, double* sig, double* mu,
+                            hipStream_t s) {
+  if (np <= 0) return;
+  k_known_densities<<<nblocks(np, 256), 256, 0, s>>>(np, ks, km, sig, mu);
+  PBT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_strengths(int64_t ns, int K, const double* sig, const double* mu, const double* src_wa,
+                      const double* nrm, T* src, hipStream_t s) {
+  if (ns <= 0) return;
+  k_strengths<T><<<nblocks(ns, 256), 256, 0, s>>>(ns, K, sig, mu, src_wa, nrm, src);
+  PBT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_p2p(const Task* tasks, int ntasks, const int32_t* ranges, const T* tgt, const T* src,
+                T kappa, bool guard, T* partial, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int blocks = ((ntasks + 3) / 4 + 7) / 8 * 8;
+  if (guard)
+    k_p2p<T, true><<<blocks, 256, 0, s>>>(tasks, ntasks, ranges, tgt, src, kappa, partial);
+  else
+    k_p2p<T, false><<<blocks, 256, 0, s>>>(tasks, ntasks, ranges, tgt, src, kappa, partial);
+  PBT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_combine(const CombineArgs& a, const T* partial, double* y, hipStream_t s) {
+  if (a.np <= 0) return;
+  k_combine<T><<<nblocks(a.np, 256), 256, 0, s>>>(a, partial, y);
+  PBT_HIP(hipGetLastError());
+}
+
+template void launch_strengths<float>(int64_t, int, const double*, const double*, const double*,
+                                      const double*, float*, hipStream_t);
+template void launch_strengths<double>(int64_t, int, const double*, const double*, const double*,
+                                       const double*, double*, hipStream_t);
+template void launch_p2p<float>(const Task*, int, const int32_t*, const float*, const float*, float,
+                                bool, float*, hipStream_t);
+template void launch_p2p<double>(const Task*, int, const int32_t*, const double*, const double*,
+                                 double, bool, double*, hipStream_t);
+template void launch_combine<float>(const CombineArgs&, const float*, double*, hipStream_t);
+template void launch_combine<double>(const CombineArgs&, const double*, double*, hipStream_t);
+
+}  // namespace pbt

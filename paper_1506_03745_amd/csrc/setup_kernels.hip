@@ -1,0 +1,297 @@
+// Setup kernels: panel geometry, Gauss-point sources, the near/far decision
+// and the near-field and self-panel corrections (Section 3.1).
+//
+// The near test |x - c_j| < 2 L_j, L_j = sqrt(2 A_j), decides an integer
+// outcome from floating point, so it is evaluated as a fixed sequence of
+// correctly rounded FP64 operations with contraction disabled:
+//   d2 = (dx*dx + dy*dy) + dz*dz,  near  <=>  d2*d2 < 16 |e1 x e2|^2
+// (|e1 x e2| = 2 A_j, so 4 L_j^2 = 4 |e1 x e2|).
+#include "pbt_internal.h"
+
+namespace pbt {
+
+namespace {
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
+
+__global__ void k_panel_geometry(int64_t np, const double* __restrict__ tri9, double* cen,
+                                 double* nrm, double* area, double* cross2) {
+#pragma clang fp contract(off)
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const double* v = tri9 + 9 * i;
+  const double e1x = v[3] - v[0], e1y = v[4] - v[1], e1z = v[5] - v[2];
+  const double e2x = v[6] - v[0], e2y = v[7] - v[1], e2z = v[8] - v[2];
+  const double cx = e1y * e2z - e1z * e2y;
+  const double cy = e1z * e2x - e1x * e2z;
+  const double cz = e1x * e2y - e1y * e2x;
+  const double c2 = (cx * cx + cy * cy) + cz * cz;
+  const double cn = sqrt(c2);
+  cross2[i] = c2;
+  area[i] = 0.5 * cn;
+  nrm[3 * i + 0] = cx / cn;
+  nrm[3 * i + 1] = cy / cn;
+  nrm[3 * i + 2] = cz / cn;
+  const double third = 1.0 / 3.0;
+  cen[3 * i + 0] = ((v[0] + v[3]) + v[6]) * third;
+  cen[3 * i + 1] = ((v[1] + v[4]) + v[7]) * third;
+  cen[3 * i + 2] = ((v[2] + v[5]) + v[8]) * third;
+}
+
+// A Gauss point at the barycentre is computed exactly as the collocation
+// point (k_panel_geometry), so that the self pair of the rules that contain
+// it has r = 0 bit for bit and is skipped by the interaction kernels.
+__device__ __forceinline__ void rule_point(const double* v, double b0, double b1, double b2,
+                                           double* p) {
+#pragma clang fp contract(off)
+  const double third = 1.0 / 3.0;
+  if (b0 == third && b1 == third && b2 == third) {
+    for (int d = 0; d < 3; ++d) p[d] = ((v[d] + v[3 + d]) + v[6 + d]) * third;
+  } else {
+    for (int d = 0; d < 3; ++d) p[d] = (b0 * v[d] + b1 * v[3 + d]) + b2 * v[6 + d];
+  }
+}
+
+__global__ void k_sources(int64_t np, int K, const double* __restrict__ tri9,
+                          const double* __restrict__ area, const double* __restrict__ bary,
+                          const double* __restrict__ w, double* src_pos, double* src_wa) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= np * K) return;
+  const int64_t p = j / K;
+  const int q = (int)(j - p * K);
+  const double* v = tri9 + 9 * p;
+  rule_point(v, bary[3 * q], bary[3 * q + 1], bary[3 * q + 2], src_pos + 3 * j);
+  src_wa[j] = w[q] * area[p];
+}
+
+__device__ __forceinline__ bool is_near(double tx, double ty, double tz, double cx, double cy,
+                                        double cz, double c2) {
+#pragma clang fp contract(off)
+  const double dx = tx - cx, dy = ty - cy, dz = tz - cz;
+  const double d2 = (dx * dx + dy * dy) + dz * dz;
+  return (d2 * d2) < 16.0 * c2;
+}
+
+constexpr int kNearTile = 256;
+
+// One thread per target; panels streamed through LDS in tiles.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_near(int64_t nt, const double* __restrict__ tx, int64_t np,
+                                              const double* __restrict__ cen,
+                                              const double* __restrict__ cross2, int32_t* count,
+                                              const int64_t* __restrict__ rowptr, int32_t* col) {
+  __shared__ double s_c[kNearTile * 4];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool act = i < nt;
+  double x = 0, y = 0, z = 0;
+  if (act) { x = tx[3 * i]; y = tx[3 * i + 1]; z = tx[3 * i + 2]; }
+  int32_t cnt = 0;
+  int64_t out = FILL && act ? rowptr[i] : 0;
+  for (int64_t t0 = 0; t0 < np; t0 += kNearTile) {
+    const int64_t j = t0 + threadIdx.x;
+    __syncthreads();
+    if (j < np) {
+      s_c[4 * threadIdx.x + 0] = cen[3 * j];
+      s_c[4 * threadIdx.x + 1] = cen[3 * j + 1];
+      s_c[4 * threadIdx.x + 2] = cen[3 * j + 2];
+      s_c[4 * threadIdx.x + 3] = cross2[j];
+    }
+    __syncthreads();
+    const int n = (int)((np - t0) < kNearTile ? (np - t0) : kNearTile);
+    if (act) {
+      for (int k = 0; k < n; ++k) {
+        if (is_near(x, y, z, s_c[4 * k], s_c[4 * k + 1], s_c[4 * k + 2], s_c[4 * k + 3])) {
+          if (FILL) col[out++] = (int32_t)(t0 + k);
+          else ++cnt;
+        }
+      }
+    }
+  }
+  if (!FILL && act) count[i] = cnt;
+}
+
+struct K4 {
+  double vl, kl, vy, ky;
+};
+
+// The K-point (or any) rule on panel j seen from x, exactly as the direct
+// FP64 interaction kernel sums it (points at distance 0 contribute 0).
+__device__ K4 rule_on_panel(double x, double y, double z, const double* v, const double* n,
+                            double area, int npts, const double* bary, const double* w,
+                            double kappa) {
+  K4 r{0, 0, 0, 0};
+  for (int q = 0; q < npts; ++q) {
+    double sp[3];
+    rule_point(v, bary[3 * q], bary[3 * q + 1], bary[3 * q + 2], sp);
+    const double dx = x - sp[0], dy = y - sp[1], dz = z - sp[2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 > 0.0)) continue;
+    const double rinv = rsqrt(r2);
+    const double rr = r2 * rinv;
+    const double wa = w[q] * area;
+    const double nd = n[0] * dx + n[1] * dy + n[2] * dz;
+    const double gl = rinv;
+    const double kl = nd * rinv * rinv * rinv;
+    const double e = exp(-kappa * rr);
+    r.vl += wa * gl;
+    r.kl += wa * kl;
+    r.vy += wa * gl * e;
+    r.ky += wa * kl * (1.0 + kappa * rr) * e;
+  }
+  r.vl *= kInv4Pi; r.kl *= kInv4Pi; r.vy *= kInv4Pi; r.ky *= kInv4Pi;
+  return r;
+}
+
+// Single-layer integrals over panel j at a point x inside it: polar
+// coordinates about x, radial integral of G rho in closed form,
+// g_L(rho) = rho/(4 pi), g_Y(rho) = (1 - exp(-kappa rho))/(4 pi kappa), and the
+// angle element along each edge h l dt / rho^2 by Gauss-Legendre in t.
+__device__ void self_single_layer(double x, double y, double z, const double* v, int nedge,
+                                  const double* gt, const double* gw, double kappa, double* vl,
+                                  double* vy) {
+  double sl = 0.0, sy = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3;
+    const double px = v[3 * a], py = v[3 * a + 1], pz = v[3 * a + 2];
+    const double ex = v[3 * b] - px, ey = v[3 * b + 1] - py, ez = v[3 * b + 2] - pz;
+    const double ell = sqrt(ex * ex + ey * ey + ez * ez);
+    const double ax = px - x, ay = py - y, az = pz - z;
+    const double cx = ay * ez - az * ey, cy = az * ex - ax * ez, cz = ax * ey - ay * ex;
+    const double h = sqrt(cx * cx + cy * cy + cz * cz) / ell;
+    for (int q = 0; q < nedge; ++q) {
+      const double t = gt[q];
+      const double rx = ax + t * ex, ry = ay + t * ey, rz = az + t * ez;
+      const double rho = sqrt(rx * rx + ry * ry + rz * rz);
+      const double ang = gw[q] * h * ell / (rho * rho);
+      sl += ang * rho;
+      sy += ang * (kappa > 0.0 ? -expm1(-kappa * rho) / kappa : rho);
+    }
+  }
+  *vl = sl * kInv4Pi;
+  *vy = sy * kInv4Pi;
+}
+
+__global__ void k_near_values(int64_t nt, const double* __restrict__ tx,
+                              const int32_t* __restrict__ tgt_self, const int64_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ col, const double* __restrict__ tri9,
+                              const double* __restrict__ nrm, const double* __restrict__ area,
+                              NearParams p, double* vals) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const double x = tx[3 * i], y = tx[3 * i + 1], z = tx[3 * i + 2];
+  const int32_t self = tgt_self ? tgt_self[i] : -1;
+  for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const int32_t j = col[e];
+    const double* v = tri9 + 9 * (int64_t)j;
+    const double* n = nrm + 3 * (int64_t)j;
+    const K4 coarse = rule_on_panel(x, y, z, v, n, area[j], p.K, p.bary_far, p.w_far, p.kappa);
+    K4 fine;
+    if (j == self) {
+      self_single_layer(x, y, z, v, p.Nedge, p.gl_t, p.gl_w, p.kappa, &fine.vl, &fine.vy);
+      fine.kl = 0.0;
+      fine.ky = 0.0;
+    } else {
+      fine = rule_on_panel(x, y, z, v, n, area[j], p.Knear, p.bary_near, p.w_near, p.kappa);
+    }
+    vals[4 * e + 0] = fine.vl - coarse.vl;
+    vals[4 * e + 1] = fine.kl - coarse.kl;
+    vals[4 * e + 2] = fine.vy - coarse.vy;
+    vals[4 * e + 3] = fine.ky - coarse.ky;
+  }
+}
+
+__global__ void k_coulomb_rhs(int64_t n, const double* __restrict__ tx, const int32_t* __restrict__ rows,
+                              int64_t nq, const double* __restrict__ qxyz, const double* __restrict__ q,
+                              double inv_eps, double* b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = tx[3 * i], y = tx[3 * i + 1], z = tx[3 * i + 2];
+  double s = 0.0;
+  for (int64_t k = 0; k < nq; ++k) {
+    const double dx = x - qxyz[3 * k], dy = y - qxyz[3 * k + 1], dz = z - qxyz[3 * k + 2];
+    s += q[k] / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  b[rows[i]] = s * kInv4Pi * inv_eps;
+}
+
+// Fold the per-row factors into the corrections: the interior (Laplace) row
+// only sees panels of its own molecule, with factors -(eps_out/eps_s) on the
+// single layer and -1 on the double layer; the solvent row sees every panel.
+__global__ void k_fold_near(int64_t nt, const int64_t* __restrict__ rowptr,
+                            const int32_t* __restrict__ col, const int32_t* __restrict__ tgt_surf,
+                            const int32_t* __restrict__ panel_surf,
+                            const int32_t* __restrict__ surf_mol,
+                            const double* __restrict__ surf_rhoinv, double* vals) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const int32_t t = tgt_surf[i];
+  for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const int32_t s = panel_surf[col[e]];
+    const bool same = (s == t) && surf_mol[t];
+    double* v = vals + 4 * e;
+    v[0] = same ? -surf_rhoinv[s] * v[0] : 0.0;
+    v[1] = same ? -v[1] : 0.0;
+  }
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
+                      const int32_t* panel_surf, const int32_t* surf_mol, const double* surf_rhoinv,
+                      double* vals, hipStream_t s) {
+  if (nt <= 0) return;
+  k_fold_near<<<nblocks(nt, 256), 256, 0, s>>>(nt, rowptr, col, tgt_surf, panel_surf, surf_mol,
+                                                surf_rhoinv, vals);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_panel_geometry(int64_t np, const double* tri9, double* cen, double* nrm, double* area,
+                           double* cross2, hipStream_t s) {
+  if (np <= 0) return;
+  k_panel_geometry<<<nblocks(np, 256), 256, 0, s>>>(np, tri9, cen, nrm, area, cross2);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_sources(int64_t np, int K, const double* tri9, const double* nrm, const double* area,
+                    const double* bary, const double* w, double* src_pos, double* src_wa,
+                    hipStream_t s) {
+  (void)nrm;
+  if (np <= 0) return;
+  k_sources<<<nblocks(np * K, 256), 256, 0, s>>>(np, K, tri9, area, bary, w, src_pos, src_wa);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_near_count(int64_t nt, const double* tx, int64_t np, const double* cen,
+                       const double* cross2, int32_t* count, hipStream_t s) {
+  if (nt <= 0) return;
+  k_near<false><<<nblocks(nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, count, nullptr, nullptr);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_near_fill(int64_t nt, const double* tx, int64_t np, const double* cen,
+                      const double* cross2, const int64_t* rowptr, int32_t* col, hipStream_t s) {
+  if (nt <= 0) return;
+  k_near<true><<<nblocks(nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, nullptr, rowptr, col);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_near_values(int64_t nt, const double* tx, const int32_t* tgt_self, const int64_t* rowptr,
+                        const int32_t* col, const double* tri9, const double* nrm,
+                        const double* area, const NearParams& p, double* vals, hipStream_t s) {
+  if (nt <= 0) return;
+  k_near_values<<<nblocks(nt, 128), 128, 0, s>>>(nt, tx, tgt_self, rowptr, col, tri9, nrm, area, p,
+                                                  vals);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_coulomb_rhs(int64_t n, const double* tx, const int32_t* rows, int64_t nq,
+                        const double* qxyz, const double* q, double inv_eps, double* b,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  k_coulomb_rhs<<<nblocks(n, 256), 256, 0, s>>>(n, tx, rows, nq, qxyz, q, inv_eps, b);
+  PBT_HIP(hipGetLastError());
+}
+
+}  // namespace pbt

@@ -1,0 +1,749 @@
+// Boundary-element system for one set of enabled surfaces (Sections 2-3).
+//
+// Unknowns per surface: a molecule has [phi, dphi/dn inside], a charged
+// surface [phi], a potential surface [dphi/dn] (eq. matrix_phi /
+// eq. matrix_dphi generalised to any number of surfaces).  Rows: a molecule's
+// interior row (first line of eq. integral_eq) then every surface's solvent
+// row (second and third lines).
+#include "system.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "quadrature.h"
+
+namespace pbt {
+
+namespace {
+
+constexpr double kFourPi = 12.566370614359172;
+// CODATA-2018 exact constants for the boundary units.
+constexpr double kE = 1.602176634e-19, kEps0 = 8.8541878128e-12, kNA = 6.02214076e23;
+constexpr double kVoltPerUnit = kE / (kEps0 * 1e-10);              // e/(eps0 A) in V
+constexpr double kKcalPerUnit = kE * kE / (kEps0 * 1e-10) * kNA / 4184.0;
+constexpr double kSigmaSI = 1e-20 / kE;                            // C/m^2 -> e/A^2
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+System::System(const std::vector<const SurfIn*>& surfs, const pbt_params& prm, double eps_out,
+               double kappa, hipStream_t stream)
+    : surfs_(surfs), prm_(prm), eps_out_(eps_out), kappa_(kappa), K_(prm.k_far) {
+  for (auto& e : ev_) PBT_HIP(hipEventCreate(&e));
+  build(stream);
+}
+
+System::~System() {
+  for (auto& e : ev_) (void)hipEventDestroy(e);
+}
+
+int System::local_index(int surface_id) const { return surface_id; }
+
+void System::build(hipStream_t s) {
+  const int ns = (int)surfs_.size();
+  // ---- offsets, trees ------------------------------------------------------
+  poff_.assign(ns + 1, 0);
+  col_off_.assign(ns + 1, 0);
+  row_off_.assign(ns + 1, 0);
+  trees_.resize(ns);
+  for (int e = 0; e < ns; ++e) {
+    const SurfIn& S = *surfs_[e];
+    const int64_t w = S.kind == PBT_MOLECULE ? 2 * S.nt : S.nt;
+    poff_[e + 1] = poff_[e] + S.nt;
+    col_off_[e + 1] = col_off_[e] + w;
+    row_off_[e + 1] = row_off_[e] + w;
+    std::vector<double> hc(3 * S.nt);
+    for (int64_t i = 0; i < S.nt; ++i)
+      for (int d = 0; d < 3; ++d) {
+        const int32_t* t = &S.tri[3 * i];
+        hc[3 * i + d] = (S.xyz[3 * t[0] + d] + S.xyz[3 * t[1] + d] + S.xyz[3 * t[2] + d]) / 3.0;
+      }
+    trees_[e] = build_tree(hc.data(), S.nt, prm_.treecode ? prm_.ncrit : (int)std::max<int64_t>(S.nt, 1));
+  }
+  np_ = poff_[ns];
+  n_ = col_off_[ns];
+  ns_ = np_ * K_;
+
+  // ---- internal-order triangles ---------------------------------------------
+  std::vector<double> tri9(9 * np_);
+  h_panel_orig_.resize(np_);
+  std::vector<int32_t> col_phi(np_), col_psi(np_), row_int(np_), row_sol(np_), psurf(np_);
+  std::vector<double> dscale(np_), ksig(np_, 0.0), kmu(np_, 0.0);
+  for (int e = 0; e < ns; ++e) {
+    const SurfIn& S = *surfs_[e];
+    for (int64_t li = 0; li < S.nt; ++li) {
+      const int64_t g = poff_[e] + li;
+      const int32_t o = trees_[e].perm[li];
+      h_panel_orig_[g] = o;
+      for (int v = 0; v < 3; ++v)
+        for (int d = 0; d < 3; ++d) tri9[9 * g + 3 * v + d] = S.xyz[3 * S.tri[3 * o + v] + d];
+      psurf[g] = e;
+      switch (S.kind) {
+        case PBT_MOLECULE:
+          col_phi[g] = (int32_t)(col_off_[e] + o);
+          col_psi[g] = (int32_t)(col_off_[e] + S.nt + o);
+          row_int[g] = (int32_t)(row_off_[e] + o);
+          row_sol[g] = (int32_t)(row_off_[e] + S.nt + o);
+          dscale[g] = S.eps_in / eps_out_;
+          break;
+        case PBT_CHARGED:
+          col_phi[g] = (int32_t)(col_off_[e] + o);
+          col_psi[g] = -1;
+          row_int[g] = -1;
+          row_sol[g] = (int32_t)(row_off_[e] + o);
+          dscale[g] = 1.0;
+          break;
+        default:
+          col_phi[g] = -1;
+          col_psi[g] = (int32_t)(col_off_[e] + o);
+          row_int[g] = -1;
+          row_sol[g] = (int32_t)(row_off_[e] + o);
+          dscale[g] = 1.0;
+      }
+    }
+  }
+  tri9_.upload(tri9, s);
+  col_phi_.upload(col_phi, s);
+  col_psi_.upload(col_psi, s);
+  row_int_.upload(row_int, s);
+  row_sol_.upload(row_sol, s);
+  dens_scale_.upload(dscale, s);
+  panel_surf_.upload(psurf, s);
+  std::vector<int32_t> smol(ns);
+  std::vector<double> srho(ns);
+  for (int e = 0; e < ns; ++e) {
+    smol[e] = surfs_[e]->kind == PBT_MOLECULE;
+    srho[e] = smol[e] ? eps_out_ / surfs_[e]->eps_in : 0.0;
+  }
+  surf_mol_.upload(smol, s);
+  surf_rhoinv_.upload(srho, s);
+
+  // ---- geometry and sources on the device ------------------------------------
+  cen_.alloc(3 * np_);
+  nrm_.alloc(3 * np_);
+  area_.alloc(np_);
+  cross2_.alloc(np_);
+  launch_panel_geometry(np_, tri9_.p, cen_.p, nrm_.p, area_.p, cross2_.p, s);
+  std::vector<double> bf, wf, bn, wn, gt, gw;
+  if (!triangle_rule(prm_.k_far, bf, wf)) throw Error(1, "k_far must be 1, 3, 4 or 7");
+  if (!triangle_rule(prm_.k_near, bn, wn)) throw Error(1, "k_near must be 19 (or 1, 3, 4, 7)");
+  gauss_legendre01(prm_.k_self_edge, gt, gw);
+  DBuf<double> dbf, dwf, dbn, dwn, dgt, dgw;
+  dbf.upload(bf, s); dwf.upload(wf, s); dbn.upload(bn, s); dwn.upload(wn, s);
+  dgt.upload(gt, s); dgw.upload(gw, s);
+  src_pos_.alloc(3 * ns_);
+  src_wa_.alloc(ns_);
+  launch_sources(np_, K_, tri9_.p, nrm_.p, area_.p, dbf.p, dwf.p, src_pos_.p, src_wa_.p, s);
+  h_cen_ = cen_.download(s);
+  h_area_ = area_.download(s);
+  std::vector<double> hsrc = src_pos_.download(s);
+  {
+    std::vector<double> t64(4 * np_, 0.0);
+    std::vector<float> t32(4 * np_, 0.0f);
+    for (int64_t i = 0; i < np_; ++i)
+      for (int d = 0; d < 3; ++d) {
+        t64[4 * i + d] = h_cen_[3 * i + d];
+        t32[4 * i + d] = (float)h_cen_[3 * i + d];
+      }
+    tgt64_.upload(t64, s);
+    tgt32_.upload(t32, s);
+    std::vector<double> s64(kSrcStride * ns_, 0.0);
+    std::vector<float> s32(kSrcStride * ns_, 0.0f);
+    for (int64_t j = 0; j < ns_; ++j)
+      for (int d = 0; d < 3; ++d) {
+        s64[kSrcStride * j + d] = hsrc[3 * j + d];
+        s32[kSrcStride * j + d] = (float)hsrc[3 * j + d];
+      }
+    src64_.upload(s64, s);
+    src32_.upload(s32, s);
+  }
+  sig_.alloc(np_);
+  mu_.alloc(np_);
+
+  // ---- near / self corrections for the collocation points ------------------
+  {
+    DBuf<int32_t> cnt;
+    cnt.alloc(np_);
+    launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, cnt.p, s);
+    std::vector<int32_t> hc = cnt.download(s);
+    std::vector<int64_t> ptr(np_ + 1, 0);
+    for (int64_t i = 0; i < np_; ++i) ptr[i + 1] = ptr[i] + hc[i];
+    near_.nnz = ptr[np_];
+    near_.ptr.upload(ptr, s);
+    near_.col.alloc(std::max<int64_t>(near_.nnz, 1));
+    near_.val.alloc(4 * std::max<int64_t>(near_.nnz, 1));
+    launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, near_.ptr.p, near_.col.p, s);
+    std::vector<int32_t> self(np_);
+    for (int64_t i = 0; i < np_; ++i) self[i] = (int32_t)i;
+    DBuf<int32_t> dself;
+    dself.upload(self, s);
+    NearParams np{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
+    launch_near_values(np_, cen_.p, dself.p, near_.ptr.p, near_.col.p, tri9_.p, nrm_.p, area_.p, np,
+                       near_.val.p, s);
+    launch_fold_near(np_, near_.ptr.p, near_.col.p, panel_surf_.p, panel_surf_.p, surf_mol_.p,
+                     surf_rhoinv_.p, near_.val.p, s);
+    PBT_HIP(hipStreamSynchronize(s));
+  }
+
+  // ---- tree geometry (global box numbering) --------------------------------
+  boff_.assign(ns + 1, 0);
+  for (int e = 0; e < ns; ++e) {
+    const int64_t p0 = poff_[e];
+    tree_geometry(trees_[e], &h_cen_[3 * p0], &hsrc[3 * p0 * K_], K_);
+    boff_[e + 1] = boff_[e] + (int64_t)trees_[e].boxes.size();
+  }
+  nbox_ = (int)boff_[ns];
+  {
+    std::vector<double> bc(3 * nbox_), brho(nbox_);
+    std::vector<int32_t> sb(nbox_), se(nbox_), cb(nbox_), ce(nbox_), cl, leaves;
+    int maxlev = 0;
+    for (int e = 0; e < ns; ++e)
+      for (const TreeBox& b : trees_[e].boxes) maxlev = std::max(maxlev, b.level);
+    std::vector<std::vector<int32_t>> bylev(maxlev + 1);
+    for (int e = 0; e < ns; ++e) {
+      const SurfTree& T = trees_[e];
+      for (size_t bi = 0; bi < T.boxes.size(); ++bi) {
+        const TreeBox& b = T.boxes[bi];
+        const int g = (int)(boff_[e] + bi);
+        for (int d = 0; d < 3; ++d) bc[3 * g + d] = b.c[d];
+        brho[g] = surfs_[e]->kind == PBT_MOLECULE ? eps_out_ / surfs_[e]->eps_in : 0.0;
+        sb[g] = (int32_t)((poff_[e] + b.pbeg) * K_);
+        se[g] = (int32_t)((poff_[e] + b.pend) * K_);
+        cb[g] = (int32_t)cl.size();
+        for (int k = b.child_beg; k < b.child_end; ++k) cl.push_back((int32_t)(boff_[e] + T.child_list[k]));
+        ce[g] = (int32_t)cl.size();
+        if (b.leaf) leaves.push_back(g);
+        else bylev[b.level].push_back(g);
+      }
+    }
+    if (cl.empty()) cl.push_back(0);
+    bcen_.upload(bc, s);
+    brho_.upload(brho, s);
+    bsbeg_.upload(sb, s);
+    bsend_.upload(se, s);
+    bcbeg_.upload(cb, s);
+    bcend_.upload(ce, s);
+    bclist_.upload(cl, s);
+    leaf_boxes_.upload(leaves, s);
+    nleaf_ = (int)leaves.size();
+    std::vector<int32_t> mb;
+    m2m_levels_.clear();
+    for (int lv = maxlev; lv >= 0; --lv) {
+      if (bylev[lv].empty()) continue;
+      m2m_levels_.push_back({(int)mb.size(), (int)bylev[lv].size()});
+      mb.insert(mb.end(), bylev[lv].begin(), bylev[lv].end());
+    }
+    if (mb.empty()) mb.push_back(0);
+    m2m_boxes_.upload(mb, s);
+  }
+  build_plan();
+  dp2p_.upload(plan_.p2p, s);
+  dm2p_.upload(plan_.m2p, s);
+  dranges_.upload(plan_.ranges.empty() ? std::vector<int32_t>{0, 0} : plan_.ranges, s);
+  dblist_.upload(plan_.blist.empty() ? std::vector<int32_t>{0} : plan_.blist, s);
+  dchunks_.upload(plan_.chunks, s);
+  dchunk_of_.upload(plan_.chunk_of, s);
+  const int NC = ncoef(prm_.taylor_p);
+  if (!plan_.m2p.empty()) {
+    mom32_.alloc((size_t)nbox_ * 2 * NC);
+    mom64_.alloc((size_t)nbox_ * 2 * NC);
+  }
+  part32_.alloc((size_t)std::max(plan_.nslots, 1) * 128);
+  part64_.alloc((size_t)std::max(plan_.nslots, 1) * 128);
+  PBT_HIP(hipStreamSynchronize(s));
+}
+
+// Work decomposition: targets in chunks of 64 within tree leaves; for every
+// leaf and source surface, the P2P source ranges and M2P boxes of the
+// interaction lists are cut into segments; one task = (chunk, segment).
+void System::build_plan() {
+  Plan& P = plan_;
+  P = Plan{};
+  const int ns = (int)surfs_.size();
+  struct LeafRef { int e; int b; };
+  std::vector<LeafRef> leaves;
+  for (int e = 0; e < ns; ++e)
+    for (size_t b = 0; b < trees_[e].boxes.size(); ++b)
+      if (trees_[e].boxes[b].leaf) leaves.push_back({e, (int)b});
+
+  // Per leaf and source surface: merged P2P source ranges and M2P boxes.
+  struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
+  std::vector<std::vector<Lists>> L(leaves.size(), std::vector<Lists>(ns));
+  int64_t tot_src = 0, tot_box = 0;
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    const TreeBox& tl = trees_[leaves[li].e].boxes[leaves[li].b];
+    const int64_t nt = tl.pend - tl.pbeg;
+    for (int e2 = 0; e2 < ns; ++e2) {
+      std::vector<int> pb, mb;
+      if (prm_.treecode) interaction_lists(trees_[e2], tl, prm_.theta, pb, mb);
+      else pb.push_back(0);
+      std::sort(pb.begin(), pb.end(), [&](int a, int b) {
+        return trees_[e2].boxes[a].pbeg < trees_[e2].boxes[b].pbeg;
+      });
+      Lists& o = L[li][e2];
+      for (int b : pb) {
+        const TreeBox& sb = trees_[e2].boxes[b];
+        const int32_t j0 = (int32_t)((poff_[e2] + sb.pbeg) * K_), j1 = (int32_t)((poff_[e2] + sb.pend) * K_);
+        if (!o.rng.empty() && o.rng.back().second == j0) o.rng.back().second = j1;
+        else o.rng.push_back({j0, j1});
+        tot_src += (int64_t)(j1 - j0) * ((nt + 63) / 64);
+        P.p2p_pairs += (int64_t)(j1 - j0) * nt;
+        if (e2 == leaves[li].e && surfs_[e2]->kind == PBT_MOLECULE) P.p2p_fused_pairs += (int64_t)(j1 - j0) * nt;
+      }
+      for (int b : mb) o.box.push_back((int32_t)(boff_[e2] + b));
+      tot_box += (int64_t)mb.size() * ((nt + 63) / 64);
+      P.m2p_pairs += (int64_t)mb.size() * nt;
+    }
+  }
+  // Segment sizes: aim at several thousand wavefront tasks in each launch.
+  const int64_t want = 16384;
+  const int64_t seg_src = std::min<int64_t>(16384, std::max<int64_t>(256, tot_src / want));
+  const int64_t seg_box = std::min<int64_t>(64, std::max<int64_t>(2, tot_box / want));
+
+  // Chunks.
+  std::vector<int> leaf_chunk0(leaves.size());
+  P.chunk_of.assign(np_, 0);
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    const TreeBox& tl = trees_[leaves[li].e].boxes[leaves[li].b];
+    leaf_chunk0[li] = (int)P.chunks.size();
+    const int64_t g0 = poff_[leaves[li].e] + tl.pbeg, g1 = poff_[leaves[li].e] + tl.pend;
+    for (int64_t t = g0; t < g1; t += 64) {
+      ChunkSlots c{(int32_t)t, (int32_t)std::min<int64_t>(64, g1 - t), 0, 0};
+      for (int64_t k = t; k < t + c.tcount; ++k) P.chunk_of[k] = (int32_t)P.chunks.size();
+      P.chunks.push_back(c);
+    }
+  }
+  // Segments per (leaf, source surface).
+  struct Seg { int32_t lbeg, lend; int e2; bool m2p; };
+  std::vector<std::vector<Seg>> segs(leaves.size());
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    for (int e2 = 0; e2 < ns; ++e2) {
+      const Lists& o = L[li][e2];
+      int64_t acc = 0;
+      int32_t start = (int32_t)(P.ranges.size() / 2);
+      for (auto rg : o.rng) {
+        for (int32_t a = rg.first; a < rg.second;) {
+          const int32_t b = (int32_t)std::min<int64_t>(rg.second, a + (seg_src - acc));
+          P.ranges.push_back(a);
+          P.ranges.push_back(b);
+          acc += b - a;
+          a = b;
+          if (acc >= seg_src) {
+            segs[li].push_back({start, (int32_t)(P.ranges.size() / 2), e2, false});
+            start = (int32_t)(P.ranges.size() / 2);
+            acc = 0;
+          }
+        }
+      }
+      if ((int32_t)(P.ranges.size() / 2) > start) segs[li].push_back({start, (int32_t)(P.ranges.size() / 2), e2, false});
+      for (size_t k = 0; k < o.box.size(); k += seg_box) {
+        const int32_t b0 = (int32_t)P.blist.size();
+        for (size_t q = k; q < std::min(o.box.size(), (size_t)(k + seg_box)); ++q) P.blist.push_back(o.box[q]);
+        segs[li].push_back({b0, (int32_t)P.blist.size(), e2, true});
+      }
+    }
+  }
+  // Slots: contiguous per chunk.
+  int slot = 0;
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    const int nchunk = (li + 1 < leaves.size() ? leaf_chunk0[li + 1] : (int)P.chunks.size()) - leaf_chunk0[li];
+    for (int c = 0; c < nchunk; ++c) {
+      ChunkSlots& cs = P.chunks[leaf_chunk0[li] + c];
+      cs.sbeg = slot;
+      slot += (int)segs[li].size();
+      cs.send = slot;
+    }
+  }
+  P.nslots = slot;
+  // Tasks ordered by (leaf, segment, chunk): neighbouring tasks share sources.
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    const int e = leaves[li].e;
+    const bool mol = surfs_[e]->kind == PBT_MOLECULE;
+    const int c0 = leaf_chunk0[li];
+    const int nchunk = (li + 1 < leaves.size() ? leaf_chunk0[li + 1] : (int)P.chunks.size()) - c0;
+    for (size_t si = 0; si < segs[li].size(); ++si) {
+      const Seg& sg = segs[li][si];
+      for (int c = 0; c < nchunk; ++c) {
+        const ChunkSlots& cs = P.chunks[c0 + c];
+        Task t{};
+        t.tbeg = cs.tbeg;
+        t.tcount = cs.tcount;
+        t.lbeg = sg.lbeg;
+        t.lend = sg.lend;
+        t.slot = cs.sbeg + (int)si;
+        t.fused = (mol && sg.e2 == e) ? 1 : 0;
+        t.rho_inv = mol ? eps_out_ / surfs_[e]->eps_in : 0.0;
+        t.rho_inv_f = (float)t.rho_inv;
+        (sg.m2p ? P.m2p : P.p2p).push_back(t);
+      }
+    }
+  }
+}
+
+template <typename T>
+void System::interactions(hipStream_t s) {
+  const bool f32 = std::is_same<T, float>::value;
+  T* src = f32 ? (T*)src32_.p : (T*)src64_.p;
+  const T* tgt = f32 ? (const T*)tgt32_.p : (const T*)tgt64_.p;
+  T* part = f32 ? (T*)part32_.p : (T*)part64_.p;
+  T* mom = f32 ? (T*)mom32_.p : (T*)mom64_.p;
+  launch_strengths<T>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, src, s);
+  PBT_HIP(hipEventRecord(ev_[1], s));
+  if (!plan_.m2p.empty()) {
+    BoxDev bd{bcen_.p, bsbeg_.p, bsend_.p, bcbeg_.p, bcend_.p, bclist_.p, brho_.p};
+    launch_p2m<T>(prm_.taylor_p, nleaf_, leaf_boxes_.p, bd, src, mom, s);
+    for (auto lv : m2m_levels_) launch_m2m<T>(prm_.taylor_p, lv.second, m2m_boxes_.p + lv.first, bd, mom, s);
+  }
+  PBT_HIP(hipEventRecord(ev_[2], s));
+  const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
+  launch_p2p<T>(dp2p_.p, (int)plan_.p2p.size(), dranges_.p, tgt, src, (T)kappa_, guard, part, s);
+  PBT_HIP(hipEventRecord(ev_[3], s));
+  if (!plan_.m2p.empty())
+    launch_m2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, tgt, bcen_.p, mom,
+                  (T)kappa_, part, s);
+  PBT_HIP(hipEventRecord(ev_[4], s));
+}
+
+void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s) {
+  ++napply_;
+  PBT_HIP(hipEventRecord(ev_[0], s));
+  if (fp32) interactions<float>(s);
+  else interactions<double>(s);
+  CombineArgs a{};
+  a.np = np_;
+  a.chunks = dchunks_.p;
+  a.nchunks = (int)plan_.chunks.size();
+  a.chunk_of = dchunk_of_.p;
+  a.near_ptr = near_.ptr.p;
+  a.near_col = near_.col.p;
+  a.near_val = near_.val.p;
+  a.sig = sig_.p;
+  a.mu = mu_.p;
+  a.x = x;
+  a.maps = PanelMaps{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
+  a.add_jump = add_jump ? 1 : 0;
+  if (fp32) launch_combine<float>(a, part32_.p, y, s);
+  else launch_combine<double>(a, part64_.p, y, s);
+  PBT_HIP(hipEventRecord(ev_[5], s));
+}
+
+void System::timing(double out[5]) {
+  PBT_HIP(hipEventSynchronize(ev_[5]));
+  float t[5] = {0, 0, 0, 0, 0};
+  PBT_HIP(hipEventElapsedTime(&t[0], ev_[0], ev_[5]));
+  PBT_HIP(hipEventElapsedTime(&t[1], ev_[2], ev_[3]));
+  PBT_HIP(hipEventElapsedTime(&t[2], ev_[3], ev_[4]));
+  PBT_HIP(hipEventElapsedTime(&t[3], ev_[1], ev_[2]));
+  out[0] = t[0];
+  out[1] = t[1];
+  out[2] = t[2];
+  out[3] = t[3];
+  out[4] = t[0] - t[1] - t[2] - t[3];
+}
+
+void System::matvec(const double* x, double* y, bool fp32, hipStream_t s) {
+  PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
+  launch_densities(np_, m, x, sig_.p, mu_.p, s);
+  apply(fp32, true, x, y, s);
+}
+
+void System::rhs(double* b, hipStream_t s) {
+  const int ns = (int)surfs_.size();
+  std::vector<double> ks(np_, 0.0), km(np_, 0.0), half(np_, 0.0);
+  for (int e = 0; e < ns; ++e) {
+    const SurfIn& S = *surfs_[e];
+    for (int64_t li = 0; li < S.nt; ++li) {
+      const int64_t g = poff_[e] + li;
+      const int32_t o = h_panel_orig_[g];
+      if (S.kind == PBT_CHARGED) ks[g] = -S.bc[o] * kSigmaSI / eps_out_;
+      if (S.kind == PBT_POTENTIAL) {
+        km[g] = -S.bc[o] / kVoltPerUnit;
+        half[g] = 0.5 * S.bc[o] / kVoltPerUnit;
+      }
+    }
+  }
+  DBuf<double> dks, dkm, yk;
+  dks.upload(ks, s);
+  dkm.upload(km, s);
+  yk.alloc(n_);
+  PBT_HIP(hipMemsetAsync(yk.p, 0, n_ * sizeof(double), s));
+  launch_known_densities(np_, dks.p, dkm.p, sig_.p, mu_.p, s);
+  apply(false, false, nullptr, yk.p, s);
+  std::vector<double> hy = yk.download(s);
+  std::vector<double> hb(n_, 0.0);
+  // solvent rows: move the known terms to the right-hand side
+  std::vector<int32_t> hrs = row_sol_.download(s);
+  for (int64_t g = 0; g < np_; ++g) hb[hrs[g]] = -hy[hrs[g]] - half[g];
+  PBT_HIP(hipMemcpyAsync(b, hb.data(), n_ * sizeof(double), hipMemcpyHostToDevice, s));
+  // interior rows: Coulomb sum with 1/eps_in (eq. green_identity)
+  for (int e = 0; e < ns; ++e) {
+    const SurfIn& S = *surfs_[e];
+    if (S.kind != PBT_MOLECULE || S.q.empty()) continue;
+    DBuf<double> qx, qq;
+    qx.upload(S.qxyz, s);
+    qq.upload(S.q, s);
+    launch_coulomb_rhs(S.nt, cen_.p + 3 * poff_[e], row_int_.p + poff_[e], (int64_t)S.q.size(), qx.p,
+                       qq.p, 1.0 / S.eps_in, b, s);
+    PBT_HIP(hipStreamSynchronize(s));
+  }
+  PBT_HIP(hipStreamSynchronize(s));
+}
+
+double System::norm(const double* v, hipStream_t s) {
+  launch_multidot(n_, 1, v, n_, v, part_.p, mdb_, s);
+  launch_reduce_cols(1, mdb_, part_.p, hdev_.p, s);
+  double h = 0;
+  PBT_HIP(hipMemcpyAsync(&h, hdev_.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  PBT_HIP(hipStreamSynchronize(s));
+  return std::sqrt(h);
+}
+
+void System::true_residual(const double* b, const double* x, double* r, hipStream_t s) {
+  matvec(x, r, false, s);
+  launch_axpby(n_, 1.0, b, -1.0, r, s);  // r = b - A x
+}
+
+// Restarted GMRES with classical Gram-Schmidt applied twice; Hessenberg
+// matrix and Givens rotations on the host.  Stops when the estimated
+// residual norm <= tol_abs.  Returns the iteration count.
+int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
+                  int maxit, double* resid_out, hipStream_t s) {
+  const int m = restart;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), y(m);
+  int iters = 0;
+  // r = b - A x
+  if (x_zero) PBT_HIP(hipMemcpyAsync(r_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else {
+    matvec(x, r_.p, fp32, s);
+    launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
+  }
+  double beta = norm(r_.p, s);
+  *resid_out = beta;
+  while (beta > tol_abs && iters < maxit) {
+    launch_scale_copy(n_, 1.0 / beta, r_.p, V_.p, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < m && iters < maxit; ++j) {
+      double* vj1 = V_.p + (size_t)(j + 1) * n_;
+      matvec(V_.p + (size_t)j * n_, vj1, fp32, s);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_multidot(n_, j + 1, V_.p, n_, vj1, part_.p, mdb_, s);
+        launch_reduce_cols(j + 1, mdb_, part_.p, hdev_.p, s);
+        launch_multi_axpy(n_, j + 1, V_.p, n_, hdev_.p, vj1, s);
+        PBT_HIP(hipMemcpyAsync(h.data(), hdev_.p, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        PBT_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) {
+          if (pass == 0) H[(size_t)i * m + j] = h[i];
+          else H[(size_t)i * m + j] += h[i];
+        }
+      }
+      const double hn = norm(vj1, s);
+      H[(size_t)(j + 1) * m + j] = hn;
+      ++iters;
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a, bb);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? bb / den : 0.0;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      *resid_out = std::fabs(g[j + 1]);
+      if (!(hn > 0) || *resid_out <= tol_abs) { ++j; break; }
+      launch_scale_copy(n_, 1.0 / hn, vj1, vj1, s);
+    }
+    // x += V y with H(0:j,0:j) y = g(0:j)
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k < j; ++k) acc -= H[(size_t)i * m + k] * y[k];
+      y[i] = acc / H[(size_t)i * m + i];
+    }
+    PBT_HIP(hipMemcpyAsync(hdev_.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_lincomb(n_, j, V_.p, n_, hdev_.p, x, s);
+    PBT_HIP(hipStreamSynchronize(s));
+    if (*resid_out <= tol_abs || iters >= maxit) break;
+    matvec(x, r_.p, fp32, s);
+    launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
+    beta = norm(r_.p, s);
+    *resid_out = beta;
+  }
+  return iters;
+}
+
+bool System::solve(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s) {
+  const int m = std::max(1, std::min<int>(prm_.restart, (int)std::max<int64_t>(n_, 1)));
+  if (restart_alloc_ != m || V_.n != (size_t)(m + 1) * n_) {
+    V_.alloc((size_t)(m + 1) * n_);
+    restart_alloc_ = m;
+  }
+  w_.alloc(n_);
+  r_.alloc(n_);
+  tmp_.alloc(n_);
+  y_.alloc(n_);
+  mdb_ = multidot_blocks(n_);
+  part_.alloc((size_t)(m + 2) * mdb_);
+  hdev_.alloc(m + 2);
+  if (!x0_given) PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));
+  const double bnorm = norm(b, s);
+  res->iters = 0;
+  res->outer = 0;
+  res->matvecs = 0;
+  if (bnorm == 0.0) {
+    PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));
+    res->rel_resid = 0.0;
+    return true;
+  }
+  const double tol = prm_.tol;
+  double rel = 0.0;
+  if (prm_.prec == PBT_FP64) {
+    double est = 0;
+    res->iters = gmres(false, b, x, !x0_given, tol * bnorm, m, prm_.max_iter, &est, s);
+    res->outer = 1;
+    true_residual(b, x, tmp_.p, s);
+    rel = norm(tmp_.p, s) / bnorm;
+  } else {
+    // Iterative refinement: FP32-interaction GMRES on the FP64 residual.
+    if (x0_given) true_residual(b, x, tmp_.p, s);
+    else PBT_HIP(hipMemcpyAsync(tmp_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double rn = norm(tmp_.p, s);
+    rel = rn / bnorm;
+    for (int outer = 0; outer < 20 && rel > tol && res->iters < prm_.max_iter; ++outer) {
+      // The inner solve aims straight at the requested tolerance; the FP32
+      // operator's relative error (~1e-7) bounds how far that is meaningful.
+      const double tin = std::min(0.5, std::max(0.5 * tol * bnorm / rn, 2e-7));
+      double est = 0;
+      PBT_HIP(hipMemsetAsync(y_.p, 0, n_ * sizeof(double), s));
+      res->iters += gmres(true, tmp_.p, y_.p, true, tin * rn, m, prm_.max_iter - res->iters, &est, s);
+      launch_axpby(n_, 1.0, y_.p, 1.0, x, s);
+      true_residual(b, x, tmp_.p, s);
+      rn = norm(tmp_.p, s);
+      rel = rn / bnorm;
+      res->outer = outer + 1;
+    }
+  }
+  res->rel_resid = rel;
+  return rel <= tol * (1.0 + 1e-12);
+}
+
+void System::energies(const double* x, pbt_result* res, hipStream_t s) {
+  const int ns = (int)surfs_.size();
+  std::vector<double> xh(n_);
+  PBT_HIP(hipMemcpyAsync(xh.data(), x, n_ * sizeof(double), hipMemcpyDeviceToHost, s));
+  PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
+  launch_densities(np_, m, x, sig_.p, mu_.p, s);
+  launch_strengths<double>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, src64_.p, s);
+  PBT_HIP(hipStreamSynchronize(s));
+  double fsolv = 0, fcoul = 0, fsurf = 0;
+  NearParams npr{};
+  std::vector<double> bf, wf, bn, wn, gt, gw;
+  triangle_rule(prm_.k_far, bf, wf);
+  triangle_rule(prm_.k_near, bn, wn);
+  gauss_legendre01(prm_.k_self_edge, gt, gw);
+  DBuf<double> dbf, dwf, dbn, dwn, dgt, dgw;
+  dbf.upload(bf, s); dwf.upload(wf, s); dbn.upload(bn, s); dwn.upload(wn, s);
+  dgt.upload(gt, s); dgw.upload(gw, s);
+  npr = NearParams{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
+  for (int e = 0; e < ns; ++e) {
+    const SurfIn& S = *surfs_[e];
+    if (S.kind == PBT_MOLECULE) {
+      const int64_t nq = (int64_t)S.q.size();
+      if (nq == 0) continue;
+      const int64_t p0 = poff_[e];
+      DBuf<double> qx, phi;
+      qx.upload(S.qxyz, s);
+      phi.alloc(nq);
+      // near lists of the charges against this molecule's panels
+      DBuf<int32_t> cnt;
+      cnt.alloc(nq);
+      launch_near_count(nq, qx.p, S.nt, cen_.p + 3 * p0, cross2_.p + p0, cnt.p, s);
+      std::vector<int32_t> hc = cnt.download(s);
+      std::vector<int64_t> ptr(nq + 1, 0);
+      for (int64_t k = 0; k < nq; ++k) ptr[k + 1] = ptr[k] + hc[k];
+      NearCSR qn;
+      qn.ptr.upload(ptr, s);
+      qn.col.alloc(std::max<int64_t>(ptr[nq], 1));
+      qn.val.alloc(4 * std::max<int64_t>(ptr[nq], 1));
+      launch_near_fill(nq, qx.p, S.nt, cen_.p + 3 * p0, cross2_.p + p0, qn.ptr.p, qn.col.p, s);
+      launch_near_values(nq, qx.p, nullptr, qn.ptr.p, qn.col.p, tri9_.p + 9 * p0, nrm_.p + 3 * p0,
+                         area_.p + p0, npr, qn.val.p, s);
+      std::vector<int32_t> tsurf(nq, 0);
+      DBuf<int32_t> dts;
+      dts.upload(tsurf, s);
+      // the charges' own "surface" is index 0 of a one-entry table
+      std::vector<int32_t> psurf0(S.nt, 0), smol1{1};
+      std::vector<double> srho1{eps_out_ / S.eps_in};
+      DBuf<int32_t> dps, dsm;
+      DBuf<double> dsr;
+      dps.upload(psurf0, s);
+      dsm.upload(smol1, s);
+      dsr.upload(srho1, s);
+      launch_fold_near(nq, qn.ptr.p, qn.col.p, dts.p, dps.p, dsm.p, dsr.p, qn.val.p, s);
+      launch_reac(nq, qx.p, p0 * K_, (p0 + S.nt) * K_, src64_.p, eps_out_ / S.eps_in, qn.ptr.p,
+                  qn.col.p, qn.val.p, sig_.p + p0, mu_.p + p0, phi.p, s);
+      std::vector<double> hphi = phi.download(s);
+      double acc = 0;
+      for (int64_t k = 0; k < nq; ++k) acc += S.q[k] * hphi[k];
+      fsolv += 0.5 * acc;
+      double c = 0;
+      for (int64_t k = 0; k < nq; ++k)
+        for (int64_t l = k + 1; l < nq; ++l) {
+          const double dx = S.qxyz[3 * k] - S.qxyz[3 * l], dy = S.qxyz[3 * k + 1] - S.qxyz[3 * l + 1],
+                       dz = S.qxyz[3 * k + 2] - S.qxyz[3 * l + 2];
+          c += S.q[k] * S.q[l] / std::sqrt(dx * dx + dy * dy + dz * dz);
+        }
+      fcoul += c / (kFourPi * S.eps_in);
+    } else {
+      for (int64_t li = 0; li < S.nt; ++li) {
+        const int64_t g = poff_[e] + li;
+        const int32_t o = h_panel_orig_[g];
+        const double A = h_area_[g];
+        if (S.kind == PBT_CHARGED) {
+          // 1/2 sum phi_j sigma_j A_j (eq. energy_surf_disc, set charge)
+          fsurf += 0.5 * xh[col_off_[e] + o] * (S.bc[o] * kSigmaSI) * A;
+        } else {
+          // -1/2 sum phi0_j sigma_j A_j with sigma = -eps_out dphi/dn
+          fsurf += 0.5 * eps_out_ * (S.bc[o] / kVoltPerUnit) * xh[col_off_[e] + o] * A;
+        }
+      }
+    }
+  }
+  res->F_solv = fsolv * kKcalPerUnit;
+  res->F_coul = fcoul * kKcalPerUnit;
+  res->F_surf = fsurf * kKcalPerUnit;
+  res->F_total = res->F_solv + res->F_coul + res->F_surf;
+}
+
+void System::unpack(const std::vector<double>& xh, int e, double* phi, double* dphidn) const {
+  const SurfIn& S = *surfs_[e];
+  for (int64_t o = 0; o < S.nt; ++o) {
+    double p = 0, d = 0;
+    switch (S.kind) {
+      case PBT_MOLECULE:
+        p = xh[col_off_[e] + o];
+        d = xh[col_off_[e] + S.nt + o];
+        break;
+      case PBT_CHARGED:
+        p = xh[col_off_[e] + o];
+        d = -S.bc[o] * kSigmaSI / eps_out_;
+        break;
+      default:
+        p = S.bc[o] / kVoltPerUnit;
+        d = xh[col_off_[e] + o];
+    }
+    if (phi) phi[o] = p;
+    if (dphidn) dphidn[o] = d;
+  }
+}
+
+}  // namespace pbt

@@ -1,0 +1,183 @@
+// A prepared boundary-element system: geometry, near-field corrections,
+// octrees, interaction lists and work decomposition for one set of enabled
+// surfaces, plus the operator, right-hand side, GMRES and energies.
+#pragma once
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pbt.h"
+#include "pbt_internal.h"
+#include "tree.h"
+
+namespace pbt {
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t m) {
+    if (m == n && p) return;
+    release();
+    if (m) {
+      hipError_t e = hipMalloc(&p, m * sizeof(T));
+      if (e != hipSuccess) throw Error(2, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    n = m;
+  }
+  // Synchronous with respect to the host vector: it may be released on return.
+  void upload(const std::vector<T>& v, hipStream_t s) {
+    alloc(v.size());
+    if (!v.empty()) {
+      PBT_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      PBT_HIP(hipStreamSynchronize(s));
+    }
+  }
+  std::vector<T> download(hipStream_t s) const {
+    std::vector<T> v(n);
+    if (n) {
+      PBT_HIP(hipMemcpyAsync(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+      PBT_HIP(hipStreamSynchronize(s));
+    }
+    return v;
+  }
+};
+
+struct SurfIn {
+  int kind = 0;
+  int64_t nv = 0, nt = 0;
+  std::vector<double> xyz;
+  std::vector<int32_t> tri;
+  std::vector<double> bc;  // SI: sigma [C/m^2] or phi0 [V]
+  double eps_in = 1.0;
+  std::vector<double> qxyz, q;
+  bool enabled = true;
+};
+
+struct NearCSR {
+  DBuf<int64_t> ptr;
+  DBuf<int32_t> col;
+  DBuf<double> val;
+  int64_t nnz = 0;
+};
+
+// Work decomposition of one target set against all source surfaces.
+struct Plan {
+  std::vector<Task> p2p, m2p;
+  std::vector<int32_t> ranges, blist;
+  std::vector<ChunkSlots> chunks;
+  std::vector<int32_t> chunk_of;
+  int nslots = 0;
+  int64_t p2p_pairs = 0, m2p_pairs = 0, p2p_fused_pairs = 0;
+};
+
+struct Timing {
+  double total = 0, p2p = 0, m2p = 0, moments = 0, rest = 0;
+};
+
+class System {
+ public:
+  System(const std::vector<const SurfIn*>& surfs, const pbt_params& prm, double eps_out,
+         double kappa, hipStream_t stream);
+  ~System();
+
+  int64_t n() const { return n_; }
+  int64_t np() const { return np_; }
+  int64_t dense_pairs() const { return np_ * ns_; }
+  const Plan& plan() const { return plan_; }
+
+  // y = A x on device buffers (n doubles each), FP64 or FP32 interactions.
+  void matvec(const double* x, double* y, bool fp32, hipStream_t s);
+  // FP64 right-hand side for the current charges and boundary values.
+  void rhs(double* b_dev, hipStream_t s);
+  // Solves A x = b (b, x device); returns result fields (iters, outer,
+  // rel_resid, matvecs) and whether it converged.
+  bool solve(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s);
+  // Energies (kcal/mol) of solution x (device).
+  void energies(const double* x, pbt_result* res, hipStream_t s);
+  // Host copy of a surface's solution in caller order.
+  void unpack(const std::vector<double>& xh, int local_surface, double* phi, double* dphidn) const;
+  int local_index(int surface_id) const;
+
+  // Milliseconds of the last operator application: total, P2P, M2P,
+  // moments (strengths, P2M, M2M), rest (densities, combine).
+  void timing(double out[5]);
+  // Operator applications since construction (every matvec and rhs pass).
+  int64_t applications() const { return napply_; }
+
+ private:
+  void build(hipStream_t s);
+  void build_plan();
+  void apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s);
+  template <typename T>
+  void interactions(hipStream_t s);
+  int gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
+            int maxit, double* resid_out, hipStream_t s);
+  void true_residual(const double* b, const double* x, double* r, hipStream_t s);
+  double norm(const double* v, hipStream_t s);
+
+  std::vector<const SurfIn*> surfs_;
+  pbt_params prm_;
+  double eps_out_, kappa_;
+  int K_ = 3;
+  int64_t n_ = 0, np_ = 0, ns_ = 0;
+  std::vector<int64_t> poff_, col_off_, row_off_;
+  std::vector<SurfTree> trees_;
+  std::vector<int64_t> boff_;
+
+  // geometry (internal order)
+  DBuf<double> tri9_, cen_, nrm_, area_, cross2_, src_pos_, src_wa_;
+  std::vector<double> h_cen_, h_area_;
+  DBuf<double> tgt64_;
+  DBuf<float> tgt32_;
+  DBuf<double> src64_;
+  DBuf<float> src32_;
+  DBuf<int32_t> col_phi_, col_psi_, row_int_, row_sol_;
+  DBuf<double> dens_scale_;
+  DBuf<double> sig_, mu_;
+  NearCSR near_;
+  DBuf<int32_t> panel_surf_;
+  DBuf<int32_t> surf_mol_;
+  DBuf<double> surf_rhoinv_;
+  std::vector<int32_t> h_panel_orig_;  // internal global -> original index within its surface
+
+  // tree (global box numbering)
+  int nbox_ = 0;
+  DBuf<double> bcen_, brho_;
+  DBuf<int32_t> bsbeg_, bsend_, bcbeg_, bcend_, bclist_;
+  DBuf<int32_t> leaf_boxes_;
+  std::vector<std::pair<int, int>> m2m_levels_;  // (offset, count) into m2m_boxes_
+  DBuf<int32_t> m2m_boxes_;
+  int nleaf_ = 0;
+  DBuf<float> mom32_;
+  DBuf<double> mom64_;
+
+  // plan
+  Plan plan_;
+  DBuf<Task> dp2p_, dm2p_;
+  DBuf<int32_t> dranges_, dblist_;
+  DBuf<ChunkSlots> dchunks_;
+  DBuf<int32_t> dchunk_of_;
+  DBuf<float> part32_;
+  DBuf<double> part64_;
+
+  // Krylov workspace
+  int restart_alloc_ = 0;
+  DBuf<double> V_, w_, r_, tmp_, hdev_, part_, y_;
+  int mdb_ = 1;
+
+  hipEvent_t ev_[6];
+  int64_t napply_ = 0;
+};
+
+}  // namespace pbt

@@ -1,0 +1,53 @@
+"""Seeded small problems shared by the GPU parity tests (inputs only)."""
+import numpy as np
+
+from workloads.meshes import box_plate, icosphere
+from workloads.problems import CHARGED, MOLECULE, POTENTIAL, Problem, Surface, config_problem
+
+
+def sphere_plate(gap=1.0, kappa=0.125):
+    """Molecule sphere close to a small charged box: panels of the two
+    surfaces fall within each other's 2L, so cross-surface near corrections
+    are exercised; 320 + 448 panels (not multiples of 64)."""
+    v, t = icosphere(2, 3.0, (0.0, 0.0, 3.0 + gap))
+    rng = np.random.default_rng(11)
+    qpos = np.array([[0.0, 0.0, 3.0 + gap], [0.8, -0.5, 3.0 + gap + 0.4]])
+    mol = Surface(MOLECULE, v, t, eps_in=2.0, q_pos=qpos, q=np.array([1.0, -0.5]))
+    pv, pt = box_plate(-6, 6, -6, 6, -2, 0, 8, 8, 2)
+    sig = -0.05 * (1 + 0.2 * rng.uniform(-1, 1, len(pt)))
+    pl = Surface(CHARGED, pv, pt, bc=sig)
+    return Problem([mol, pl], 80.0, kappa, {}, "sphere_plate")
+
+
+def three_body():
+    """Two molecules (different eps_in) and a potential sphere."""
+    v1, t1 = icosphere(1, 3.0, (0.0, 0.0, 0.0))
+    v2, t2 = icosphere(1, 2.5, (7.0, 0.0, 0.0))
+    v3, t3 = icosphere(2, 2.0, (0.0, 6.5, 1.0))
+    m1 = Surface(MOLECULE, v1, t1, eps_in=4.0, q_pos=np.array([[0.3, 0.0, 0.0]]), q=np.array([1.0]))
+    m2 = Surface(MOLECULE, v2, t2, eps_in=2.0, q_pos=np.array([[7.0, 0.2, 0.0], [6.5, 0, 0]]),
+                 q=np.array([-1.0, 0.5]))
+    ps = Surface(POTENTIAL, v3, t3, bc=np.full(len(t3), 0.02))
+    return Problem([m1, m2, ps], 80.0, 0.1, {}, "three_body")
+
+
+def case(name):
+    if name == "kirkwood_l1":
+        return config_problem("kirkwood", level=1)
+    if name == "kirkwood_l2":
+        return config_problem("kirkwood", level=2)
+    if name == "twosphere_charge_l2":
+        return config_problem("twosphere_charge", level=2)
+    if name == "twosphere_potential_l2":
+        return config_problem("twosphere_potential", level=2)
+    if name == "sphere_plate":
+        return sphere_plate()
+    if name == "sphere_plate_k0":
+        return sphere_plate(kappa=0.0)
+    if name == "three_body":
+        return three_body()
+    raise KeyError(name)
+
+
+SMALL_CASES = ["kirkwood_l1", "kirkwood_l2", "twosphere_charge_l2", "twosphere_potential_l2",
+               "sphere_plate", "sphere_plate_k0", "three_body"]

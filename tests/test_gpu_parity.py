@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (written per test):
+* direct FP64 operator and right-hand side: element-wise, |y - y_oracle| <=
+  1e-11 max|y_oracle| (both sides evaluate the same quadrature sums in FP64;
+  only summation order differs);
+* direct FP32-interaction operator: 3e-5 max|y_oracle| (FP32 rounding of
+  ~1e4 terms of mixed sign, accumulated per lane);
+* treecode: the Taylor truncation error, bounded per (theta, P) and shown to
+  fall with P; theta -> 0 reproduces the direct sum to FP64 rounding;
+* energies: relative 1e-6 (FP64) and 1e-4 (mixed) of the oracle's dense LU
+  energies on the same discretisation.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.bem import DenseBEM, interaction_energy, solve_problem
+from paper_1506_03745_amd import FP64, MIXED, PbtError, from_problem
+from tests.gpu_cases import SMALL_CASES, case
+from workloads.problems import config_problem
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+_oracle_cache = {}
+
+
+def oracle_Ab(name, **kw):
+    key = (name, tuple(sorted(kw.items())))
+    if key not in _oracle_cache:
+        s = DenseBEM(case(name), **kw)
+        _oracle_cache[key] = s.assemble()
+    return _oracle_cache[key]
+
+
+def rand_x(n, seed=0):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("name", SMALL_CASES)
+def test_direct_fp64_operator_matches_oracle(name):
+    A, _ = oracle_Ab(name)
+    s, _ = from_problem(case(name), treecode=0)
+    assert s.num_unknowns() == A.shape[0]
+    for seed in (0, 1):
+        x = rand_x(A.shape[0], seed)
+        y = s.matvec(x, prec=FP64)
+        assert rel_inf(y, A @ x) < 1e-11, name
+
+
+@pytest.mark.parametrize("name", SMALL_CASES)
+def test_rhs_matches_oracle(name):
+    _, b = oracle_Ab(name)
+    s, _ = from_problem(case(name), treecode=0)
+    assert rel_inf(s.rhs(), b) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL_CASES)
+def test_direct_fp32_operator_matches_oracle(name):
+    A, _ = oracle_Ab(name)
+    s, _ = from_problem(case(name), treecode=0)
+    x = rand_x(A.shape[0], 3)
+    assert rel_inf(s.matvec(x, prec=MIXED), A @ x) < 3e-5
+
+
+@pytest.mark.parametrize("k_far", [1, 4, 7])
+def test_far_rule_variants(k_far):
+    """Rules with a centroid point (the self pair has r = 0) and a negative weight."""
+    A, _ = oracle_Ab("sphere_plate", k_far=k_far)
+    s, _ = from_problem(case("sphere_plate"), treecode=0, k_far=k_far)
+    x = rand_x(A.shape[0], 5)
+    assert rel_inf(s.matvec(x), A @ x) < 1e-11
+
+
+def test_operator_is_deterministic():
+    s, _ = from_problem(case("sphere_plate"), treecode=1, ncrit=40)
+    x = rand_x(s.num_unknowns(), 9)
+    for prec in (FP64, MIXED):
+        y1 = s.matvec(x, prec=prec)
+        y2 = s.matvec(x, prec=prec)
+        assert np.array_equal(y1, y2)
+
+
+def test_treecode_small_theta_is_direct():
+    """With a tiny acceptance parameter nothing is expanded: exact direct sums."""
+    A, _ = oracle_Ab("twosphere_charge_l2")
+    s, _ = from_problem(case("twosphere_charge_l2"), treecode=1, ncrit=20, theta=1e-3)
+    x = rand_x(A.shape[0], 2)
+    assert rel_inf(s.matvec(x), A @ x) < 1e-11
+
+
+def test_treecode_error_falls_with_order():
+    A, _ = oracle_Ab("twosphere_charge_l2")
+    x = rand_x(A.shape[0], 4)
+    ref = A @ x
+    errs = []
+    for P in (0, 2, 4, 6, 8):
+        s, _ = from_problem(case("twosphere_charge_l2"), treecode=1, ncrit=16, theta=0.5, taylor_p=P)
+        errs.append(rel_inf(s.matvec(x), ref))
+        s.close()
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+    assert errs[3] < 2e-3 and errs[4] < 5e-4, errs
+    # FP32 far field follows the FP64 one until FP32 rounding dominates
+    s, _ = from_problem(case("twosphere_charge_l2"), treecode=1, ncrit=16, theta=0.5, taylor_p=6)
+    assert abs(rel_inf(s.matvec(x, prec=MIXED), ref) - errs[3]) < 1e-4
+
+
+def test_treecode_multi_surface_and_molecules():
+    for name in ("sphere_plate", "three_body"):
+        A, _ = oracle_Ab(name)
+        x = rand_x(A.shape[0], 6)
+        s, _ = from_problem(case(name), treecode=1, ncrit=24, theta=0.4, taylor_p=8)
+        assert rel_inf(s.matvec(x), A @ x) < 2e-4, name
+
+
+@pytest.mark.parametrize("name", ["kirkwood_l2", "twosphere_charge_l2", "twosphere_potential_l2",
+                                  "sphere_plate", "three_body"])
+def test_fp64_solve_energies(name):
+    pr = case(name)
+    e, _, _ = solve_problem(pr)
+    s, _ = from_problem(pr, treecode=0, tol=1e-11)
+    r = s.solve()
+    assert r.rel_resid <= 1e-11
+    for a, b in ((r.F_solv, e.F_solv), (r.F_surf, e.F_surf), (r.F_coul, e.F_coul)):
+        assert abs(a - b) <= 1e-8 * max(abs(b), 1e-12) + 1e-14, (name, a, b)
+
+
+def test_solution_unpack_matches_oracle():
+    pr = case("sphere_plate")
+    _, u, sysm = solve_problem(pr)
+    s, ids = from_problem(pr, treecode=0, tol=1e-12)
+    s.solve()
+    for k, (phi_o, psi_o) in enumerate(sysm.split(u)):
+        phi, dphi = s.get_solution(ids[k], pr.surfaces[k].nt)
+        assert rel_inf(phi, phi_o) < 1e-9
+        assert rel_inf(dphi, psi_o) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["twosphere_charge_l2", "sphere_plate"])
+def test_interaction_energy_fp64_and_mixed(name):
+    pr = case(name)
+    f_or, e_all, parts = interaction_energy(pr)
+    s, _ = from_problem(pr, treecode=0, tol=1e-10)
+    f, res = s.interaction_energy(len(pr.surfaces))
+    scale = abs(e_all.F_solv) + abs(e_all.F_surf)
+    assert abs(f - f_or) <= 1e-7 * scale
+    assert abs(res[0].F_total - e_all.F_total) <= 1e-8 * abs(e_all.F_total)
+    s2, _ = from_problem(pr, treecode=1, ncrit=32, theta=0.4, taylor_p=8, prec=MIXED, tol=1e-8)
+    f2, res2 = s2.interaction_energy(len(pr.surfaces))
+    assert abs(res2[0].F_solv - e_all.F_solv) <= 1e-4 * abs(e_all.F_solv)
+    assert abs(f2 - f_or) <= 1e-4 * scale
+
+
+def test_kirkwood_full_size_fp64_and_mixed():
+    """1280-panel sphere: GPU FP64 (direct and treecode) and mixed solves
+    against the oracle's dense LU energy, and both near the closed form."""
+    pr = config_problem("kirkwood")
+    e, _, _ = solve_problem(pr)
+    s, _ = from_problem(pr, treecode=0, tol=1e-10)
+    r = s.solve()
+    assert abs(r.F_solv - e.F_solv) <= 1e-8 * abs(e.F_solv)
+    s, _ = from_problem(pr, treecode=1, prec=MIXED, tol=1e-6)
+    r = s.solve()
+    assert abs(r.F_solv - e.F_solv) <= 1e-4 * abs(e.F_solv)
+    assert r.rel_resid <= 1e-6
+
+
+def test_full_size_twosphere_sampled_rows():
+    """Full 10240-panel two-sphere workload in the benchmark's launch
+    configuration: oracle rows computed one by one at sampled indices."""
+    pr = config_problem("twosphere_charge")
+    sysm = DenseBEM(pr)
+    rows = np.random.default_rng(0).choice(sysm.n, 48, replace=False)
+    Ar, br = sysm.operator_rows(rows)
+    x = rand_x(sysm.n, 8)
+    ref = Ar @ x
+    s, _ = from_problem(pr, treecode=0)
+    y = s.matvec(x)
+    assert np.max(np.abs(y[rows] - ref)) < 1e-11 * np.max(np.abs(ref))
+    assert np.max(np.abs(s.rhs()[rows] - br)) < 1e-12 * np.max(np.abs(br))
+    s.close()
+    s, _ = from_problem(pr)   # benchmark parameters: theta 0.5, P 6, N_crit 300
+    for prec in (FP64, MIXED):
+        y = s.matvec(x, prec=prec)
+        assert np.max(np.abs(y[rows] - ref)) < 2e-3 * np.max(np.abs(ref))
+
+
+def test_full_size_twosphere_energies_against_stored_oracle():
+    path = os.path.join(GOLDEN, "dense_oracle_energies.json")
+    if not os.path.exists(path):
+        pytest.skip("dense oracle energies not generated (tests/golden/make_golden.py --dense)")
+    gold = json.load(open(path))
+    for name in ("twosphere_charge", "twosphere_potential"):
+        g = gold[name]
+        pr = config_problem(name)
+        s, _ = from_problem(pr, treecode=0, tol=1e-10)
+        f, res = s.interaction_energy(2)
+        assert abs(res[0].F_solv - g["F_solv_asm"]) <= 1e-7 * abs(g["F_solv_asm"])
+        assert abs(res[0].F_surf - g["F_surf_asm"]) <= 1e-7 * abs(g["F_surf_asm"])
+        scale = abs(g["F_solv_asm"]) + abs(g["F_surf_asm"])
+        assert abs(f - g["F_int"]) <= 1e-6 * scale
+
+
+def test_error_paths():
+    pr = case("kirkwood_l1")
+    s, _ = from_problem(pr, treecode=0, max_iter=1)
+    r = s.solve(allow_noconverge=True)
+    assert r.status == 4 and r.iters == 1 and np.isfinite(r.F_solv)
+    with pytest.raises(PbtError):
+        s.solve()
+    s2, _ = from_problem(pr, treecode=0)
+    v = pr.surfaces[0].verts.copy()
+    t = pr.surfaces[0].tris.copy()
+    t[0, 1] = t[0, 0]
+    with pytest.raises(PbtError, match="INVALID"):
+        s2.add_surface(0, v, t)
+    t = pr.surfaces[0].tris.copy()
+    t[3, 2] = len(v) + 5
+    with pytest.raises(PbtError, match="INVALID"):
+        s2.add_surface(0, v, t)
+    v[2, 1] = np.nan
+    with pytest.raises(PbtError, match="INVALID"):
+        s2.add_surface(0, v, pr.surfaces[0].tris)
+    with pytest.raises(PbtError, match="INVALID"):
+        s2.set_solvent(-1.0, 0.1)
+    s2.solve()
+    with pytest.raises(PbtError, match="STATE"):
+        s2.add_surface(0, pr.surfaces[0].verts, pr.surfaces[0].tris)
+
+
+def test_device_entry_point_with_torch_stream():
+    import torch
+    A, _ = oracle_Ab("sphere_plate")
+    s, _ = from_problem(case("sphere_plate"), treecode=0)
+    x = rand_x(A.shape[0], 12)
+    xd = torch.tensor(x, device="cuda:0")
+    yd = torch.empty_like(xd)
+    s.matvec_dev(xd, yd)
+    torch.cuda.synchronize()
+    assert rel_inf(yd.cpu().numpy(), A @ x) < 1e-11
