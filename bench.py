@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the mixed-precision steps (for profiler runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 256 MiB device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -81,6 +83,12 @@ def main():
     from paper_1506_03745_amd import FP64, MIXED, from_problem
     from workloads.problems import config_problem
 
+    if a.copy_calib:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     problem = config_problem(a.workload)
     prm = dict(theta=0.5, taylor_p=6, ncrit=300, k_far=3, k_near=19, k_self_edge=9, tol=1e-6)
 

@@ -19,8 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "pbt")
 LIB = os.path.join(HERE, "libpbt.so")
 
-SOURCES = ["setup_kernels.hip", "matvec_kernels.hip", "taylor.hip", "krylov.hip",
-           "quadrature.cpp", "tree.cpp", "system.cpp", "abi.cpp"]
+SOURCES = ["setup_kernels.hip", "matvec_kernels.hip", "taylor.hip", "krylov.hip", "adjoint.hip",
+           "quadrature.cpp", "tree.cpp", "system.cpp", "system_adjoint.cpp", "abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PBT_OFFLOAD_ARCH", "gfx950")

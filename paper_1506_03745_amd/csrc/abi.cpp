@@ -348,9 +348,10 @@ pbt_status pbt_matvec_dev(pbt_ctx* c, const double* x_dev, double* y_dev, int32_
                           pbt_precision prec, void* stream) {
   return guarded(c, [&] {
     if (!x_dev || !y_dev) return fail(c, PBT_E_INVALID, "null buffer");
-    if (transpose) return fail(c, PBT_E_STATE, "transpose product not available");
     System& S = system_for(c);
-    S.matvec(x_dev, y_dev, prec == PBT_MIXED, stream ? (hipStream_t)stream : c->stream);
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    if (transpose) S.matvec_t(x_dev, y_dev, prec == PBT_MIXED, nullptr, st);
+    else S.matvec(x_dev, y_dev, prec == PBT_MIXED, st);
     return PBT_OK;
   });
 }
@@ -358,13 +359,13 @@ pbt_status pbt_matvec_dev(pbt_ctx* c, const double* x_dev, double* y_dev, int32_
 pbt_status pbt_matvec(pbt_ctx* c, const double* x, double* y, int32_t transpose, pbt_precision prec) {
   return guarded(c, [&] {
     if (!x || !y) return fail(c, PBT_E_INVALID, "null buffer");
-    if (transpose) return fail(c, PBT_E_STATE, "transpose product not available");
     System& S = system_for(c);
     const int64_t n = S.n();
     c->dx.alloc(n);
     c->dy.alloc(n);
     PBT_HIP(hipMemcpyAsync(c->dx.p, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    S.matvec(c->dx.p, c->dy.p, prec == PBT_MIXED, c->stream);
+    if (transpose) S.matvec_t(c->dx.p, c->dy.p, prec == PBT_MIXED, nullptr, c->stream);
+    else S.matvec(c->dx.p, c->dy.p, prec == PBT_MIXED, c->stream);
     PBT_HIP(hipMemcpyAsync(y, c->dy.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     PBT_HIP(hipStreamSynchronize(c->stream));
     return PBT_OK;
@@ -382,8 +383,77 @@ pbt_status pbt_rhs(pbt_ctx* c, double* b) {
   });
 }
 
-pbt_status pbt_gradient(pbt_ctx* c, int32_t, double*, int32_t, double*) {
-  return fail(c, PBT_E_STATE, "gradient not available in this build");
+// One system's contribution: forward solve, adjoint solve, gradient terms.
+// Returns dF_total/dq of molecule `mol` and dF_total/dsigma of surface `sig`
+// (reduced units), looked up by surface identity.
+static pbt_status system_gradient(pbt_ctx* c, int mol, int sig, std::vector<double>* dq,
+                                  std::vector<double>* dsig) {
+  System& S = system_for(c);
+  const int64_t n = S.n();
+  pbt_result r{};
+  DBuf<double> b, x, g, lam;
+  b.alloc(n);
+  x.alloc(n);
+  g.alloc(n);
+  lam.alloc(n);
+  S.rhs(b.p, c->stream);
+  const bool ok1 = S.solve(b.p, x.p, false, &r, c->stream);
+  S.adjoint_rhs(x.p, g.p, c->stream);
+  pbt_result ra{};
+  const bool ok2 = S.solve_t(g.p, lam.p, &ra, c->stream);
+  std::vector<std::vector<double>> gq, gs;
+  S.gradient_terms(x.p, lam.p, gq, gs, c->stream);
+  for (int e = 0; e < S.n_surfaces(); ++e) {
+    if (mol >= 0 && S.surface(e) == c->surfs[mol].get() && dq) *dq = gq[e];
+    if (sig >= 0 && S.surface(e) == c->surfs[sig].get() && dsig) *dsig = gs[e];
+  }
+  if (!ok1 || !ok2) return fail(c, PBT_E_NOCONVERGE, "forward or adjoint GMRES did not converge");
+  return PBT_OK;
+}
+
+pbt_status pbt_gradient(pbt_ctx* c, int32_t sigma_id, double* dF_dsigma, int32_t mol_id, double* dF_dq) {
+  return guarded(c, [&] {
+    const int ns = (int)c->surfs.size();
+    if (sigma_id >= ns || mol_id >= ns || (sigma_id < 0 && mol_id < 0))
+      return fail(c, PBT_E_INVALID, "bad surface ids");
+    if (sigma_id >= 0 && (c->surfs[sigma_id]->kind != PBT_CHARGED || !dF_dsigma))
+      return fail(c, PBT_E_INVALID, "sigma_id must name a charged surface (and dF_dsigma be given)");
+    if (mol_id >= 0 && (c->surfs[mol_id]->kind != PBT_MOLECULE || !dF_dq))
+      return fail(c, PBT_E_INVALID, "mol_id must name a molecule (and dF_dq be given)");
+    std::vector<bool> saved = mask_of(c);
+    auto set_mask = [&](int only) {
+      for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = only < 0 ? true : i == only;
+    };
+    pbt_status worst = PBT_OK;
+    std::vector<double> dq_a, ds_a, dq_i, ds_i;
+    try {
+      set_mask(-1);
+      pbt_status st = system_gradient(c, mol_id, sigma_id, &dq_a, &ds_a);
+      if (st != PBT_OK && st != PBT_E_NOCONVERGE) throw Error(st, c->err);
+      if (st != PBT_OK) worst = st;
+      if (sigma_id >= 0) {
+        set_mask(sigma_id);
+        st = system_gradient(c, -1, sigma_id, nullptr, &ds_i);
+        if (st != PBT_OK && st != PBT_E_NOCONVERGE) throw Error(st, c->err);
+        if (st != PBT_OK) worst = st;
+      }
+      if (mol_id >= 0) {
+        set_mask(mol_id);
+        st = system_gradient(c, mol_id, -1, &dq_i, nullptr);
+        if (st != PBT_OK && st != PBT_E_NOCONVERGE) throw Error(st, c->err);
+        if (st != PBT_OK) worst = st;
+      }
+    } catch (...) {
+      for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = saved[i];
+      throw;
+    }
+    for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = saved[i];
+    if (sigma_id >= 0)
+      for (size_t k = 0; k < ds_a.size(); ++k) dF_dsigma[k] = (ds_a[k] - ds_i[k]) * kKcalPerUnit * kSigmaSI;
+    if (mol_id >= 0)
+      for (size_t k = 0; k < dq_a.size(); ++k) dF_dq[k] = (dq_a[k] - dq_i[k]) * kKcalPerUnit;
+    return worst;
+  });
 }
 
 pbt_status pbt_solve_batch(pbt_ctx* c, int32_t, const double*, const double*, int32_t, double*) {

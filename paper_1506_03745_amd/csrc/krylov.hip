@@ -74,6 +74,14 @@ __global__ void k_lincomb(int64_t n, int m, const double* __restrict__ V, int64_
   y[j] = s;
 }
 
+// y = x / sqrt(*nrm2) (in place allowed)
+__global__ void k_normalize(int64_t n, const double* __restrict__ nrm2, const double* x, double* y) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double v = *nrm2;
+  y[j] = v > 0.0 ? x[j] / sqrt(v) : 0.0;
+}
+
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* y) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= n) return;
@@ -89,9 +97,9 @@ __global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, 
 }  // namespace
 
 int multidot_blocks(int64_t n) {
-  int64_t b = (n + kBS * 4 - 1) / (kBS * 4);
+  int64_t b = (n + kBS - 1) / kBS;
   if (b < 1) b = 1;
-  if (b > 512) b = 512;
+  if (b > 480) b = 480;
   return (int)b;
 }
 
@@ -117,6 +125,12 @@ void launch_lincomb(int64_t n, int m, const double* V, int64_t ldv, const double
                     hipStream_t s) {
   if (n <= 0 || m <= 0) return;
   k_lincomb<<<nblocks(n, 256), 256, 0, s>>>(n, m, V, ldv, c, y);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_normalize(int64_t n, const double* nrm2, const double* x, double* y, hipStream_t s) {
+  if (n <= 0) return;
+  k_normalize<<<nblocks(n, 256), 256, 0, s>>>(n, nrm2, x, y);
   PBT_HIP(hipGetLastError());
 }
 

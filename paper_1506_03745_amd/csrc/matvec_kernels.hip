@@ -154,28 +154,39 @@ __global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int
 
 // Sum the partial slots of every target, scale by 1/(4 pi), add the near and
 // self corrections (sparse, FP64) and the 1/2 jump terms, and scatter into
-// the unknown layout.
+// the unknown layout.  Four lanes share a target (slots and near entries
+// interleaved) and combine with shuffles, to keep enough loads in flight.
 template <typename T>
-__global__ void k_combine(CombineArgs a, const T* __restrict__ partial, double* y) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.np) return;
-  const int c = a.chunk_of[i];
-  const ChunkSlots cs = a.chunks[c];
-  const int lane = (int)(i - cs.tbeg);
-  double l = 0.0, yy = 0.0;
-  for (int s = cs.sbeg; s < cs.send; ++s) {
-    l += (double)partial[2 * ((int64_t)s * 64 + lane) + 0];
-    yy += (double)partial[2 * ((int64_t)s * 64 + lane) + 1];
+__global__ __launch_bounds__(256) void k_combine(CombineArgs a, const T* __restrict__ partial, double* y) {
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 2;
+  const int sub = threadIdx.x & 3;
+  const bool act = i < a.np;
+  double l = 0.0, yy = 0.0, nl = 0.0, ny = 0.0;
+  if (act) {
+    const int c = a.chunk_of[i];
+    const ChunkSlots cs = a.chunks[c];
+    const int lane = (int)(i - cs.tbeg);
+    for (int s = cs.sbeg + sub; s < cs.send; s += 4) {
+      l += (double)partial[2 * ((int64_t)s * 64 + lane) + 0];
+      yy += (double)partial[2 * ((int64_t)s * 64 + lane) + 1];
+    }
+    for (int64_t e = a.near_ptr[i] + sub; e < a.near_ptr[i + 1]; e += 4) {
+      const int32_t j = a.near_col[e];
+      const double sj = a.sig[j], mj = a.mu[j];
+      const double* v = a.near_val + 4 * e;
+      nl += v[0] * sj + v[1] * mj;
+      ny += v[2] * sj + v[3] * mj;
+    }
   }
-  l *= kInv4Pi;
-  yy *= kInv4Pi;
-  for (int64_t e = a.near_ptr[i]; e < a.near_ptr[i + 1]; ++e) {
-    const int32_t j = a.near_col[e];
-    const double sj = a.sig[j], mj = a.mu[j];
-    const double* v = a.near_val + 4 * e;
-    l += v[0] * sj + v[1] * mj;
-    yy += v[2] * sj + v[3] * mj;
+  for (int o = 1; o < 4; o <<= 1) {
+    l += __shfl_xor(l, o, 64);
+    yy += __shfl_xor(yy, o, 64);
+    nl += __shfl_xor(nl, o, 64);
+    ny += __shfl_xor(ny, o, 64);
   }
+  if (!act || sub != 0) return;
+  l = l * kInv4Pi + nl;
+  yy = yy * kInv4Pi + ny;
   const int32_t ri = a.maps.row_int[i];
   const int32_t rs = a.maps.row_sol[i];
   const int32_t cphi = a.maps.col_phi[i];
@@ -186,17 +197,19 @@ __global__ void k_combine(CombineArgs a, const T* __restrict__ partial, double* 
 // Reaction potential at the charges of one molecule (eq. phi_reac_bem):
 // phi_reac = -K_L(phi) + V_L(dphi/dn) = -L with the interior-row sums L,
 // direct FP64 sums over the molecule's Gauss points plus the near
-// corrections of each charge.
-__global__ void k_reac(int64_t nq, const double* __restrict__ qxyz, int64_t s0, int64_t s1,
-                       const double* __restrict__ src, double rho_inv,
-                       const int64_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
-                       const double* __restrict__ near_val, const double* __restrict__ sig,
-                       const double* __restrict__ mu, double* phi) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= nq) return;
+// corrections of each charge.  One block per charge, threads over sources.
+__global__ __launch_bounds__(256) void k_reac(int64_t nq, const double* __restrict__ qxyz, int64_t s0,
+                                              int64_t s1, const double* __restrict__ src, double rho_inv,
+                                              const int64_t* __restrict__ near_ptr,
+                                              const int32_t* __restrict__ near_col,
+                                              const double* __restrict__ near_val,
+                                              const double* __restrict__ sig,
+                                              const double* __restrict__ mu, double* phi) {
+  __shared__ double red[4];
+  const int64_t k = blockIdx.x;
   const double x = qxyz[3 * k], y = qxyz[3 * k + 1], z = qxyz[3 * k + 2];
   double a1 = 0.0, a2 = 0.0;
-  for (int64_t j = s0; j < s1; ++j) {
+  for (int64_t j = s0 + threadIdx.x; j < s1; j += blockDim.x) {
     const double* s = src + (int64_t)kSrcStride * j;
     const double dx = x - s[0], dy = y - s[1], dz = z - s[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -206,11 +219,14 @@ __global__ void k_reac(int64_t nq, const double* __restrict__ qxyz, int64_t s0, 
     a2 += dd * rinv * rinv * rinv;
   }
   double l = (-rho_inv * a1 - a2) * kInv4Pi;
-  for (int64_t e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
+  for (int64_t e = near_ptr[k] + threadIdx.x; e < near_ptr[k + 1]; e += blockDim.x) {
     const int32_t j = near_col[e];
     l += near_val[4 * e] * sig[j] + near_val[4 * e + 1] * mu[j];
   }
-  phi[k] = -l;
+  for (int o = 32; o > 0; o >>= 1) l += __shfl_down(l, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) phi[k] = -(red[0] + red[1] + red[2] + red[3]);
 }
 
 }  // namespace
@@ -220,8 +236,8 @@ void launch_reac(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const d
                  const double* near_val, const double* sig, const double* mu, double* phi,
                  hipStream_t s) {
   if (nq <= 0) return;
-  k_reac<<<nblocks(nq, 64), 64, 0, s>>>(nq, qxyz, s0, s1, src, rho_inv, near_ptr, near_col,
-                                        near_val, sig, mu, phi);
+  k_reac<<<(unsigned)nq, 256, 0, s>>>(nq, qxyz, s0, s1, src, rho_inv, near_ptr, near_col, near_val,
+                                       sig, mu, phi);
   PBT_HIP(hipGetLastError());
 }
 
@@ -262,7 +278,7 @@ void launch_p2p(const Task* tasks, int ntasks, const int32_t* ranges, const T* t
 template <typename T>
 void launch_combine(const CombineArgs& a, const T* partial, double* y, hipStream_t s) {
   if (a.np <= 0) return;
-  k_combine<T><<<nblocks(a.np, 256), 256, 0, s>>>(a, partial, y);
+  k_combine<T><<<nblocks(4 * a.np, 256), 256, 0, s>>>(a, partial, y);
   PBT_HIP(hipGetLastError());
 }
 

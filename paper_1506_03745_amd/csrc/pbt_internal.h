@@ -44,6 +44,14 @@ struct ChunkSlots {
   int32_t tbeg, tcount, sbeg, send;
 };
 
+// Units: lengths in A, charges in e, potentials in e/(eps0 A), energies in
+// e^2/(eps0 A).  CODATA-2018 exact constants for the conversions at the ABI.
+constexpr double kFourPi = 12.566370614359172;
+constexpr double kE = 1.602176634e-19, kEps0 = 8.8541878128e-12, kNA = 6.02214076e23;
+constexpr double kVoltPerUnit = kE / (kEps0 * 1e-10);              // e/(eps0 A) in V
+constexpr double kKcalPerUnit = kE * kE / (kEps0 * 1e-10) * kNA / 4184.0;
+constexpr double kSigmaSI = 1e-20 / kE;                            // C/m^2 -> e/A^2
+
 constexpr int kSrcStride = 8;  // x y z s Dx Dy Dz pad
 constexpr int kTgtStride = 4;  // x y z pad
 
@@ -133,6 +141,48 @@ template <typename T>
 void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
                 const double* box_center, const T* mom, T kappa, T* partial, hipStream_t s);
 
+// --- transpose operator (adjoint.hip) ---------------------------------------
+struct AdjCombineArgs {
+  int64_t np;
+  int K;
+  const ChunkSlots* chunks;   // reverse-P2P slots per 64-source chunk (nullable)
+  const int32_t* chunk_of;    // per source
+  const double* wa;           // per source: w A
+  const double* nrm;          // per panel
+  const int64_t* tptr;        // near corrections by source panel (nullable)
+  const int32_t* trow;        // target panel of each entry
+  const double* tval;         // (cLs, cLm, cYs, cYm)
+  const double* lam;          // row weights (nullable: no near or jump terms)
+  const double* add_sig;      // extra per-panel sigmabar / mubar (nullable)
+  const double* add_mu;
+  PanelMaps maps;
+};
+template <typename T>
+void launch_adj_targets(int64_t np, const double* cen, const int32_t* row_int, const int32_t* row_sol,
+                        const double* lam, T* trec, hipStream_t s);
+template <typename T>
+void launch_p2p_t(const Task* tasks, int ntasks, const int32_t* ranges, const T* src, const T* trec,
+                  T kappa, bool guard, T* partial, hipStream_t s);
+template <typename T>
+void launch_m2p_t(int P, const Task* tasks, int ntasks, const T* trec, const double* bcen, T kappa,
+                  T* mpart, hipStream_t s);
+template <typename T>
+void launch_mbar_reduce(int nbox, int P, const int32_t* sbeg, const int32_t* send, const T* mpart,
+                        T* mbar, hipStream_t s);
+template <typename T>
+void launch_m2m_t(int P, int nbox, const int32_t* boxes, const int32_t* parent, const double* bcen,
+                  T* mbar, hipStream_t s);
+template <typename T>
+void launch_l2p_t(int P, int nleaf, const int32_t* leaves, const BoxDev& bd, const T* src,
+                  const T* mbar, T* far, hipStream_t s);
+template <typename T>
+void launch_combine_t(const AdjCombineArgs& a, const T* partial, const T* far, double* z, double* sigbar,
+                      hipStream_t s);
+void launch_reac_t(int64_t s0, int64_t s1, const double* src, int64_t nq, const double* qxyz,
+                   const double* q, double rho_inv, double* far, hipStream_t s);
+void launch_coulomb_t(int64_t nq, const double* qxyz, int64_t n, const double* tx, const int32_t* rows,
+                      const double* lam, double inv_eps, double* out, hipStream_t s);
+
 // --- Krylov BLAS-1 (krylov.hip) ---------------------------------------------
 void launch_multidot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* part,
                      int nblk, hipStream_t s);
@@ -140,6 +190,7 @@ void launch_reduce_cols(int m, int nblk, const double* part, double* out, hipStr
 void launch_multi_axpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* w,
                        hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+void launch_normalize(int64_t n, const double* nrm2, const double* x, double* y, hipStream_t s);
 void launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
 void launch_lincomb(int64_t n, int m, const double* V, int64_t ldv, const double* c, double* y,
                     hipStream_t s);

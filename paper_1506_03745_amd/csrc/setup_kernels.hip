@@ -72,42 +72,33 @@ __device__ __forceinline__ bool is_near(double tx, double ty, double tz, double 
   return (d2 * d2) < 16.0 * c2;
 }
 
-constexpr int kNearTile = 256;
-
-// One thread per target; panels streamed through LDS in tiles.
+// One wavefront per target, lanes over panels.  The fill pass writes the
+// hits of each 64-panel chunk in panel order (ballot + popcount), so the
+// lists come out sorted exactly as a serial scan would produce them.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_near(int64_t nt, const double* __restrict__ tx, int64_t np,
                                               const double* __restrict__ cen,
                                               const double* __restrict__ cross2, int32_t* count,
                                               const int64_t* __restrict__ rowptr, int32_t* col) {
-  __shared__ double s_c[kNearTile * 4];
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool act = i < nt;
-  double x = 0, y = 0, z = 0;
-  if (act) { x = tx[3 * i]; y = tx[3 * i + 1]; z = tx[3 * i + 2]; }
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= nt) return;  // uniform across the wavefront
+  const double x = tx[3 * i], y = tx[3 * i + 1], z = tx[3 * i + 2];
+  int64_t out = FILL ? rowptr[i] : 0;
   int32_t cnt = 0;
-  int64_t out = FILL && act ? rowptr[i] : 0;
-  for (int64_t t0 = 0; t0 < np; t0 += kNearTile) {
-    const int64_t j = t0 + threadIdx.x;
-    __syncthreads();
-    if (j < np) {
-      s_c[4 * threadIdx.x + 0] = cen[3 * j];
-      s_c[4 * threadIdx.x + 1] = cen[3 * j + 1];
-      s_c[4 * threadIdx.x + 2] = cen[3 * j + 2];
-      s_c[4 * threadIdx.x + 3] = cross2[j];
-    }
-    __syncthreads();
-    const int n = (int)((np - t0) < kNearTile ? (np - t0) : kNearTile);
-    if (act) {
-      for (int k = 0; k < n; ++k) {
-        if (is_near(x, y, z, s_c[4 * k], s_c[4 * k + 1], s_c[4 * k + 2], s_c[4 * k + 3])) {
-          if (FILL) col[out++] = (int32_t)(t0 + k);
-          else ++cnt;
-        }
-      }
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t j0 = 0; j0 < np; j0 += 64) {
+    const int64_t j = j0 + lane;
+    const bool hit = j < np && is_near(x, y, z, cen[3 * j], cen[3 * j + 1], cen[3 * j + 2], cross2[j]);
+    const uint64_t m = __ballot(hit);
+    if (FILL) {
+      if (hit) col[out + __popcll(m & below)] = (int32_t)j;
+      out += __popcll(m);
+    } else {
+      cnt += __popcll(m);
     }
   }
-  if (!FILL && act) count[i] = cnt;
+  if (!FILL && lane == 0) count[i] = cnt;
 }
 
 struct K4 {
@@ -266,14 +257,14 @@ void launch_sources(int64_t np, int K, const double* tri9, const double* nrm, co
 void launch_near_count(int64_t nt, const double* tx, int64_t np, const double* cen,
                        const double* cross2, int32_t* count, hipStream_t s) {
   if (nt <= 0) return;
-  k_near<false><<<nblocks(nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, count, nullptr, nullptr);
+  k_near<false><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, count, nullptr, nullptr);
   PBT_HIP(hipGetLastError());
 }
 
 void launch_near_fill(int64_t nt, const double* tx, int64_t np, const double* cen,
                       const double* cross2, const int64_t* rowptr, int32_t* col, hipStream_t s) {
   if (nt <= 0) return;
-  k_near<true><<<nblocks(nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, nullptr, rowptr, col);
+  k_near<true><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, nullptr, rowptr, col);
   PBT_HIP(hipGetLastError());
 }
 

@@ -18,13 +18,6 @@ namespace pbt {
 
 namespace {
 
-constexpr double kFourPi = 12.566370614359172;
-// CODATA-2018 exact constants for the boundary units.
-constexpr double kE = 1.602176634e-19, kEps0 = 8.8541878128e-12, kNA = 6.02214076e23;
-constexpr double kVoltPerUnit = kE / (kEps0 * 1e-10);              // e/(eps0 A) in V
-constexpr double kKcalPerUnit = kE * kE / (kEps0 * 1e-10) * kNA / 4184.0;
-constexpr double kSigmaSI = 1e-20 / kE;                            // C/m^2 -> e/A^2
-
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -270,6 +263,13 @@ void System::build_plan() {
   for (int e = 0; e < ns; ++e)
     for (size_t b = 0; b < trees_[e].boxes.size(); ++b)
       if (trees_[e].boxes[b].leaf) leaves.push_back({e, (int)b});
+  leaves_.clear();
+  for (const LeafRef& l : leaves) {
+    const TreeBox& tb = trees_[l.e].boxes[l.b];
+    leaves_.push_back({l.e, l.b, poff_[l.e] + tb.pbeg, poff_[l.e] + tb.pend});
+  }
+  lp2p_.assign(leaves.size(), std::vector<std::vector<int>>(ns));
+  lm2p_.assign(leaves.size(), std::vector<std::vector<int>>(ns));
 
   // Per leaf and source surface: merged P2P source ranges and M2P boxes.
   struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
@@ -285,6 +285,8 @@ void System::build_plan() {
       std::sort(pb.begin(), pb.end(), [&](int a, int b) {
         return trees_[e2].boxes[a].pbeg < trees_[e2].boxes[b].pbeg;
       });
+      lp2p_[li][e2] = pb;
+      lm2p_[li][e2] = mb;
       Lists& o = L[li][e2];
       for (int b : pb) {
         const TreeBox& sb = trees_[e2].boxes[b];
@@ -504,7 +506,7 @@ double System::norm(const double* v, hipStream_t s) {
 }
 
 void System::true_residual(const double* b, const double* x, double* r, hipStream_t s) {
-  matvec(x, r, false, s);
+  op(x, r, false, s);
   launch_axpby(n_, 1.0, b, -1.0, r, s);  // r = b - A x
 }
 
@@ -514,12 +516,12 @@ void System::true_residual(const double* b, const double* x, double* r, hipStrea
 int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
                   int maxit, double* resid_out, hipStream_t s) {
   const int m = restart;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(2 * (m + 1) + 1), y(m);
   int iters = 0;
   // r = b - A x
   if (x_zero) PBT_HIP(hipMemcpyAsync(r_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
   else {
-    matvec(x, r_.p, fp32, s);
+    op(x, r_.p, fp32, s);
     launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
   }
   double beta = norm(r_.p, s);
@@ -531,19 +533,23 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol
     int j = 0;
     for (; j < m && iters < maxit; ++j) {
       double* vj1 = V_.p + (size_t)(j + 1) * n_;
-      matvec(V_.p + (size_t)j * n_, vj1, fp32, s);
+      op(V_.p + (size_t)j * n_, vj1, fp32, s);
+      // CGS2: two projections against V_0..V_j, then |w|^2, all on the
+      // device; one copy of (h1, h2, |w|^2) to the host per Arnoldi step.
       for (int pass = 0; pass < 2; ++pass) {
+        double* hp = hdev_.p + pass * (m + 1);
         launch_multidot(n_, j + 1, V_.p, n_, vj1, part_.p, mdb_, s);
-        launch_reduce_cols(j + 1, mdb_, part_.p, hdev_.p, s);
-        launch_multi_axpy(n_, j + 1, V_.p, n_, hdev_.p, vj1, s);
-        PBT_HIP(hipMemcpyAsync(h.data(), hdev_.p, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-        PBT_HIP(hipStreamSynchronize(s));
-        for (int i = 0; i <= j; ++i) {
-          if (pass == 0) H[(size_t)i * m + j] = h[i];
-          else H[(size_t)i * m + j] += h[i];
-        }
+        launch_reduce_cols(j + 1, mdb_, part_.p, hp, s);
+        launch_multi_axpy(n_, j + 1, V_.p, n_, hp, vj1, s);
       }
-      const double hn = norm(vj1, s);
+      double* hn2 = hdev_.p + 2 * (m + 1);
+      launch_multidot(n_, 1, vj1, n_, vj1, part_.p, mdb_, s);
+      launch_reduce_cols(1, mdb_, part_.p, hn2, s);
+      launch_normalize(n_, hn2, vj1, vj1, s);
+      PBT_HIP(hipMemcpyAsync(h.data(), hdev_.p, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      PBT_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h[(m + 1) + i];
+      const double hn = std::sqrt(std::max(h[2 * (m + 1)], 0.0));
       H[(size_t)(j + 1) * m + j] = hn;
       ++iters;
       for (int i = 0; i < j; ++i) {
@@ -561,7 +567,6 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol
       g[j] = cs[j] * g[j];
       *resid_out = std::fabs(g[j + 1]);
       if (!(hn > 0) || *resid_out <= tol_abs) { ++j; break; }
-      launch_scale_copy(n_, 1.0 / hn, vj1, vj1, s);
     }
     // x += V y with H(0:j,0:j) y = g(0:j)
     for (int i = j - 1; i >= 0; --i) {
@@ -573,7 +578,7 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol
     launch_lincomb(n_, j, V_.p, n_, hdev_.p, x, s);
     PBT_HIP(hipStreamSynchronize(s));
     if (*resid_out <= tol_abs || iters >= maxit) break;
-    matvec(x, r_.p, fp32, s);
+    op(x, r_.p, fp32, s);
     launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
     beta = norm(r_.p, s);
     *resid_out = beta;
@@ -582,6 +587,19 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol
 }
 
 bool System::solve(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s) {
+  transpose_ = false;
+  return solve_any(b, x, x0_given, res, s);
+}
+
+bool System::solve_t(const double* g, double* lam, pbt_result* res, hipStream_t s) {
+  build_tplan(s);
+  transpose_ = true;
+  const bool ok = solve_any(g, lam, false, res, s);
+  transpose_ = false;
+  return ok;
+}
+
+bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s) {
   const int m = std::max(1, std::min<int>(prm_.restart, (int)std::max<int64_t>(n_, 1)));
   if (restart_alloc_ != m || V_.n != (size_t)(m + 1) * n_) {
     V_.alloc((size_t)(m + 1) * n_);
@@ -593,7 +611,7 @@ bool System::solve(const double* b, double* x, bool x0_given, pbt_result* res, h
   y_.alloc(n_);
   mdb_ = multidot_blocks(n_);
   part_.alloc((size_t)(m + 2) * mdb_);
-  hdev_.alloc(m + 2);
+  hdev_.alloc(2 * (m + 1) + 2);
   if (!x0_given) PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));
   const double bnorm = norm(b, s);
   res->iters = 0;
@@ -645,53 +663,12 @@ void System::energies(const double* x, pbt_result* res, hipStream_t s) {
   launch_strengths<double>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, src64_.p, s);
   PBT_HIP(hipStreamSynchronize(s));
   double fsolv = 0, fcoul = 0, fsurf = 0;
-  NearParams npr{};
-  std::vector<double> bf, wf, bn, wn, gt, gw;
-  triangle_rule(prm_.k_far, bf, wf);
-  triangle_rule(prm_.k_near, bn, wn);
-  gauss_legendre01(prm_.k_self_edge, gt, gw);
-  DBuf<double> dbf, dwf, dbn, dwn, dgt, dgw;
-  dbf.upload(bf, s); dwf.upload(wf, s); dbn.upload(bn, s); dwn.upload(wn, s);
-  dgt.upload(gt, s); dgw.upload(gw, s);
-  npr = NearParams{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
     if (S.kind == PBT_MOLECULE) {
       const int64_t nq = (int64_t)S.q.size();
       if (nq == 0) continue;
-      const int64_t p0 = poff_[e];
-      DBuf<double> qx, phi;
-      qx.upload(S.qxyz, s);
-      phi.alloc(nq);
-      // near lists of the charges against this molecule's panels
-      DBuf<int32_t> cnt;
-      cnt.alloc(nq);
-      launch_near_count(nq, qx.p, S.nt, cen_.p + 3 * p0, cross2_.p + p0, cnt.p, s);
-      std::vector<int32_t> hc = cnt.download(s);
-      std::vector<int64_t> ptr(nq + 1, 0);
-      for (int64_t k = 0; k < nq; ++k) ptr[k + 1] = ptr[k] + hc[k];
-      NearCSR qn;
-      qn.ptr.upload(ptr, s);
-      qn.col.alloc(std::max<int64_t>(ptr[nq], 1));
-      qn.val.alloc(4 * std::max<int64_t>(ptr[nq], 1));
-      launch_near_fill(nq, qx.p, S.nt, cen_.p + 3 * p0, cross2_.p + p0, qn.ptr.p, qn.col.p, s);
-      launch_near_values(nq, qx.p, nullptr, qn.ptr.p, qn.col.p, tri9_.p + 9 * p0, nrm_.p + 3 * p0,
-                         area_.p + p0, npr, qn.val.p, s);
-      std::vector<int32_t> tsurf(nq, 0);
-      DBuf<int32_t> dts;
-      dts.upload(tsurf, s);
-      // the charges' own "surface" is index 0 of a one-entry table
-      std::vector<int32_t> psurf0(S.nt, 0), smol1{1};
-      std::vector<double> srho1{eps_out_ / S.eps_in};
-      DBuf<int32_t> dps, dsm;
-      DBuf<double> dsr;
-      dps.upload(psurf0, s);
-      dsm.upload(smol1, s);
-      dsr.upload(srho1, s);
-      launch_fold_near(nq, qn.ptr.p, qn.col.p, dts.p, dps.p, dsm.p, dsr.p, qn.val.p, s);
-      launch_reac(nq, qx.p, p0 * K_, (p0 + S.nt) * K_, src64_.p, eps_out_ / S.eps_in, qn.ptr.p,
-                  qn.col.p, qn.val.p, sig_.p + p0, mu_.p + p0, phi.p, s);
-      std::vector<double> hphi = phi.download(s);
+      std::vector<double> hphi = reaction_potential(e, s);
       double acc = 0;
       for (int64_t k = 0; k < nq; ++k) acc += S.q[k] * hphi[k];
       fsolv += 0.5 * acc;

@@ -109,6 +109,20 @@ class System {
   void unpack(const std::vector<double>& xh, int local_surface, double* phi, double* dphidn) const;
   int local_index(int surface_id) const;
 
+  // z = A^T lam (device buffers), the exact transpose of matvec; sigbar
+  // (nullable, np doubles) receives d(lam^T y)/d sigma per panel.
+  void matvec_t(const double* lam, double* z, bool fp32, double* sigbar, hipStream_t s);
+  // Adjoint right-hand side g = dF_total/du at the solution x (device, FP64).
+  void adjoint_rhs(const double* x, double* g, hipStream_t s);
+  // Solves A^T lam = g like solve() does for A.
+  bool solve_t(const double* g, double* lam, pbt_result* res, hipStream_t s);
+  // Gradient of F_total (reduced units) w.r.t. each molecule's charges and
+  // each charged surface's sigma, from the solution x and the adjoint lam.
+  void gradient_terms(const double* x, const double* lam, std::vector<std::vector<double>>& dq,
+                      std::vector<std::vector<double>>& dsig, hipStream_t s);
+  const SurfIn* surface(int e) const { return surfs_[e]; }
+  int n_surfaces() const { return (int)surfs_.size(); }
+
   // Milliseconds of the last operator application: total, P2P, M2P,
   // moments (strengths, P2M, M2M), rest (densities, combine).
   void timing(double out[5]);
@@ -124,6 +138,16 @@ class System {
   int gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
             int maxit, double* resid_out, hipStream_t s);
   void true_residual(const double* b, const double* x, double* r, hipStream_t s);
+  void op(const double* x, double* y, bool fp32, hipStream_t s) {
+    if (transpose_) matvec_t(x, y, fp32, nullptr, s);
+    else matvec(x, y, fp32, s);
+  }
+  bool solve_any(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s);
+  void build_tplan(hipStream_t s);
+  template <typename T>
+  void apply_t(const double* lam, double* z, double* sigbar, hipStream_t s);
+  void charge_near(int e, const double* qx, int64_t nq, NearCSR& out, hipStream_t s);
+  std::vector<double> reaction_potential(int e, hipStream_t s);  // densities already set
   double norm(const double* v, hipStream_t s);
 
   std::vector<const SurfIn*> surfs_;
@@ -178,6 +202,24 @@ class System {
 
   hipEvent_t ev_[6];
   int64_t napply_ = 0;
+  bool transpose_ = false;
+
+  // forward interaction lists per (target leaf, source surface), for the transpose
+  struct LeafInfo { int e; int b; int64_t g0, g1; };
+  std::vector<LeafInfo> leaves_;
+  std::vector<std::vector<std::vector<int>>> lp2p_, lm2p_;
+  // transpose plan
+  bool tplan_ready_ = false;
+  int ntp2p_ = 0, ntm2p_ = 0;
+  DBuf<Task> dtp2p_, dtm2p_;
+  DBuf<int32_t> dtranges_;
+  DBuf<ChunkSlots> dtchunks_;
+  DBuf<int32_t> dtchunk_of_;
+  DBuf<int32_t> dmslot_beg_, dmslot_end_, bparent_, m2mt_boxes_;
+  std::vector<std::pair<int, int>> m2mt_levels_;
+  NearCSR tnear_;
+  DBuf<float> tpart32_, mpart32_, mbar32_, far32_, trec32_;
+  DBuf<double> tpart64_, mpart64_, mbar64_, far64_, trec64_;
 };
 
 }  // namespace pbt
