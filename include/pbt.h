@@ -140,6 +140,11 @@ pbt_status pbt_set_charges(pbt_ctx* ctx, int32_t mol_id, double eps_in, const do
  * solves of the interaction energy (eq. interaction_energy). */
 pbt_status pbt_enable(pbt_ctx* ctx, int32_t id, int32_t on);
 
+/* Prepares the enabled system now (geometry, near and self corrections,
+ * octrees, interaction lists, work lists) instead of at the first solve or
+ * product; freezes the geometry.  Host buffers are not needed afterwards. */
+pbt_status pbt_prepare(pbt_ctx* ctx);
+
 /* Number of unknowns of the currently enabled system. */
 pbt_status pbt_num_unknowns(pbt_ctx* ctx, int64_t* n);
 

@@ -1,6 +1,7 @@
 // C entry points of the pbt library (declared in include/pbt.h).
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -284,6 +285,13 @@ pbt_status pbt_enable(pbt_ctx* c, int32_t id, int32_t on) {
   return PBT_OK;
 }
 
+pbt_status pbt_prepare(pbt_ctx* c) {
+  return guarded(c, [&] {
+    system_for(c);
+    return PBT_OK;
+  });
+}
+
 pbt_status pbt_num_unknowns(pbt_ctx* c, int64_t* n) {
   if (!c || !n) return fail(c, PBT_E_INVALID, "null argument");
   int64_t k = 0;
@@ -460,8 +468,59 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t, const double*, const double*, in
   return fail(c, PBT_E_STATE, "batched solve not available in this build");
 }
 
-pbt_status pbt_autotune(pbt_ctx* c, const char*) {
-  return fail(c, PBT_E_STATE, "autotuner not available in this build");
+// Autotuner: times the operator of the enabled system for candidate P2P and
+// M2P segment sizes (coordinate search: P2P first, then M2P) in the solve's
+// interaction precision, keeps the fastest, and remembers it per system
+// shape in memory and, if given, in a text cache file
+// ("key seg_src seg_box ms" per line).
+pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
+  return guarded(c, [&] {
+    System& S = system_for(c);
+    const bool fp32 = c->prm.prec == PBT_MIXED;
+    char key[256];
+    std::snprintf(key, sizeof key, "np%lld_n%lld_p2p%lld_m2p%lld_P%d_%s", (long long)S.np(), (long long)S.n(),
+                  (long long)S.plan().p2p_pairs, (long long)S.plan().m2p_pairs, c->prm.taylor_p,
+                  fp32 ? "fp32" : "fp64");
+    static std::map<std::string, std::pair<int64_t, int64_t>> memo;
+    auto it = memo.find(key);
+    if (it == memo.end() && cache_path) {
+      if (FILE* f = std::fopen(cache_path, "r")) {
+        char k[256];
+        long long a, b;
+        double ms;
+        while (std::fscanf(f, "%255s %lld %lld %lf", k, &a, &b, &ms) == 4)
+          if (std::string(k) == key) memo[key] = {a, b};
+        std::fclose(f);
+        it = memo.find(key);
+      }
+    }
+    if (it != memo.end()) {
+      S.set_segments(it->second.first, it->second.second, c->stream);
+      return PBT_OK;
+    }
+    const int reps = 5;
+    int64_t best_src = S.seg_src(), best_box = S.seg_box();
+    double best = S.time_products(fp32, reps, c->stream);
+    for (int64_t cand : {64, 96, 128, 192, 256, 384, 512, 1024, 2048}) {
+      S.set_segments(cand, best_box, c->stream);
+      const double t = S.time_products(fp32, reps, c->stream);
+      if (t < best) { best = t; best_src = cand; }
+    }
+    for (int64_t cand : {1, 2, 4, 8, 16, 32}) {
+      S.set_segments(best_src, cand, c->stream);
+      const double t = S.time_products(fp32, reps, c->stream);
+      if (t < best) { best = t; best_box = cand; }
+    }
+    S.set_segments(best_src, best_box, c->stream);
+    memo[key] = {best_src, best_box};
+    if (cache_path) {
+      if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s %lld %lld %.6f\n", key, (long long)best_src, (long long)best_box, best);
+        std::fclose(f);
+      }
+    }
+    return PBT_OK;
+  });
 }
 
 pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w) {

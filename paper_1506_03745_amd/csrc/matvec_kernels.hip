@@ -40,20 +40,25 @@ __global__ void k_known_densities(int64_t np, const double* __restrict__ ks,
   mu[p] = km[p];
 }
 
+// Source record: (x, y, z, s, Dx, Dy, Dz, s_L) with s_L = -(eps_out/eps_s) s,
+// the single-layer strength of the interior (Laplace) row; rlap[p] holds
+// -(eps_out/eps_s) for molecule panels and 0 otherwise.
 template <typename T>
 __global__ void k_strengths(int64_t ns, int K, const double* __restrict__ sig,
                             const double* __restrict__ mu, const double* __restrict__ wa,
-                            const double* __restrict__ nrm, T* src) {
+                            const double* __restrict__ nrm, const double* __restrict__ rlap, T* src) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= ns) return;
   const int64_t p = j / K;
   const double w = wa[j];
   const double m = w * mu[p];
+  const double sv = w * sig[p];
   T* o = src + kSrcStride * j;
-  o[3] = (T)(w * sig[p]);
+  o[3] = (T)sv;
   o[4] = (T)(m * nrm[3 * p]);
   o[5] = (T)(m * nrm[3 * p + 1]);
   o[6] = (T)(m * nrm[3 * p + 2]);
+  o[7] = (T)(rlap[p] * sv);
 }
 
 template <typename T>
@@ -98,7 +103,7 @@ __global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int
   const int ti = tbeg + (lane < tcount ? lane : 0);
   const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
   const T ck = KMath<T>::expk_const(kappa);
-  T a1 = 0, a2 = 0, yy = 0;
+  T l = 0, yy = 0;
   for (int r = lbeg; r < lend; ++r) {
     const int j0 = ranges[2 * r], j1 = ranges[2 * r + 1];
     if (fused) {
@@ -110,16 +115,12 @@ __global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int
         T rinv = KMath<T>::rsq(r2);
         if (GUARD) rinv = r2 > T(0) ? rinv : T(0);
         const T dd = s[4] * dx + s[5] * dy + s[6] * dz;
-        const T rinv2 = rinv * rinv;
-        const T t = dd * rinv2;
-        a1 += s[3] * rinv;
-        a2 += t * rinv;
+        const T t = dd * (rinv * rinv);            // D.(x-y)/r^2
+        l += (s[7] - t) * rinv;                    // s_L/r - D.(x-y)/r^3
         const T rr = r2 * rinv;
-        const T e = KMath<T>::expk(rr, ck);
-        const T gy = e * rinv;
+        const T gy = KMath<T>::expk(rr, ck) * rinv;
         const T f = kappa * rr + T(1);
-        yy += s[3] * gy;
-        yy += (t * gy) * f;
+        yy += gy * (t * f + s[3]);                 // s G_Y + D.grad_y G_Y
       }
     } else {
 #pragma unroll 4
@@ -132,21 +133,14 @@ __global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int
         const T dd = s[4] * dx + s[5] * dy + s[6] * dz;
         const T t = dd * (rinv * rinv);
         const T rr = r2 * rinv;
-        const T e = KMath<T>::expk(rr, ck);
-        const T gy = e * rinv;
+        const T gy = KMath<T>::expk(rr, ck) * rinv;
         const T f = kappa * rr + T(1);
-        yy += s[3] * gy;
-        yy += (t * gy) * f;
+        yy += gy * (t * f + s[3]);
       }
     }
   }
   if (lane < tcount) {
     const int slot = tasks[wv].slot;
-    T l = 0;
-    if (fused) {
-      const T ri = sizeof(T) == 4 ? (T)tasks[wv].rho_inv_f : (T)tasks[wv].rho_inv;
-      l = -ri * a1 - a2;
-    }
     partial[2 * ((int64_t)slot * 64 + lane) + 0] = l;
     partial[2 * ((int64_t)slot * 64 + lane) + 1] = yy;
   }
@@ -257,9 +251,9 @@ void launch_known_densities(int64_t np, const double* ks, const double* km, doub
 
 template <typename T>
 void launch_strengths(int64_t ns, int K, const double* sig, const double* mu, const double* src_wa,
-                      const double* nrm, T* src, hipStream_t s) {
+                      const double* nrm, const double* rlap, T* src, hipStream_t s) {
   if (ns <= 0) return;
-  k_strengths<T><<<nblocks(ns, 256), 256, 0, s>>>(ns, K, sig, mu, src_wa, nrm, src);
+  k_strengths<T><<<nblocks(ns, 256), 256, 0, s>>>(ns, K, sig, mu, src_wa, nrm, rlap, src);
   PBT_HIP(hipGetLastError());
 }
 
@@ -283,9 +277,9 @@ void launch_combine(const CombineArgs& a, const T* partial, double* y, hipStream
 }
 
 template void launch_strengths<float>(int64_t, int, const double*, const double*, const double*,
-                                      const double*, float*, hipStream_t);
+                                      const double*, const double*, float*, hipStream_t);
 template void launch_strengths<double>(int64_t, int, const double*, const double*, const double*,
-                                       const double*, double*, hipStream_t);
+                                       const double*, const double*, double*, hipStream_t);
 template void launch_p2p<float>(const Task*, int, const int32_t*, const float*, const float*, float,
                                 bool, float*, hipStream_t);
 template void launch_p2p<double>(const Task*, int, const int32_t*, const double*, const double*,

@@ -52,7 +52,7 @@ constexpr double kVoltPerUnit = kE / (kEps0 * 1e-10);              // e/(eps0 A)
 constexpr double kKcalPerUnit = kE * kE / (kEps0 * 1e-10) * kNA / 4184.0;
 constexpr double kSigmaSI = 1e-20 / kE;                            // C/m^2 -> e/A^2
 
-constexpr int kSrcStride = 8;  // x y z s Dx Dy Dz pad
+constexpr int kSrcStride = 8;  // x y z s Dx Dy Dz s_L
 constexpr int kTgtStride = 4;  // x y z pad
 
 // Number of Taylor coefficients with |k| <= P.
@@ -105,7 +105,7 @@ void launch_known_densities(int64_t np, const double* known_sig, const double* k
                             double* mu, hipStream_t s);
 template <typename T>
 void launch_strengths(int64_t ns, int K, const double* sig, const double* mu, const double* src_wa,
-                      const double* nrm, T* src, hipStream_t s);
+                      const double* nrm, const double* rlap, T* src, hipStream_t s);
 template <typename T>
 void launch_p2p(const Task* tasks, int ntasks, const int32_t* ranges, const T* tgt, const T* src,
                 T kappa, bool guard, T* partial, hipStream_t s);

@@ -106,6 +106,12 @@ void System::build(hipStream_t s) {
   row_int_.upload(row_int, s);
   row_sol_.upload(row_sol, s);
   dens_scale_.upload(dscale, s);
+  {
+    std::vector<double> rl(np_, 0.0);
+    for (int64_t g = 0; g < np_; ++g)
+      if (surfs_[psurf[g]]->kind == PBT_MOLECULE) rl[g] = -eps_out_ / surfs_[psurf[g]]->eps_in;
+    rlap_.upload(rl, s);
+  }
   panel_surf_.upload(psurf, s);
   std::vector<int32_t> smol(ns);
   std::vector<double> srho(ns);
@@ -235,8 +241,12 @@ void System::build(hipStream_t s) {
     m2m_boxes_.upload(mb, s);
   }
   build_plan();
-  dp2p_.upload(plan_.p2p, s);
-  dm2p_.upload(plan_.m2p, s);
+  upload_plan(s);
+}
+
+void System::upload_plan(hipStream_t s) {
+  dp2p_.upload(plan_.p2p.empty() ? std::vector<Task>(1) : plan_.p2p, s);
+  dm2p_.upload(plan_.m2p.empty() ? std::vector<Task>(1) : plan_.m2p, s);
   dranges_.upload(plan_.ranges.empty() ? std::vector<int32_t>{0, 0} : plan_.ranges, s);
   dblist_.upload(plan_.blist.empty() ? std::vector<int32_t>{0} : plan_.blist, s);
   dchunks_.upload(plan_.chunks, s);
@@ -249,6 +259,34 @@ void System::build(hipStream_t s) {
   part32_.alloc((size_t)std::max(plan_.nslots, 1) * 128);
   part64_.alloc((size_t)std::max(plan_.nslots, 1) * 128);
   PBT_HIP(hipStreamSynchronize(s));
+}
+
+void System::set_segments(int64_t seg_src, int64_t seg_box, hipStream_t s) {
+  PBT_HIP(hipStreamSynchronize(s));
+  seg_src_ = seg_src;
+  seg_box_ = seg_box;
+  build_plan();
+  upload_plan(s);
+}
+
+double System::time_products(bool fp32, int reps, hipStream_t s) {
+  DBuf<double> x, y;
+  x.alloc(n_);
+  y.alloc(n_);
+  PBT_HIP(hipMemsetAsync(x.p, 0, n_ * sizeof(double), s));
+  matvec(x.p, y.p, fp32, s);
+  hipEvent_t a, b;
+  PBT_HIP(hipEventCreate(&a));
+  PBT_HIP(hipEventCreate(&b));
+  PBT_HIP(hipEventRecord(a, s));
+  for (int r = 0; r < reps; ++r) matvec(x.p, y.p, fp32, s);
+  PBT_HIP(hipEventRecord(b, s));
+  PBT_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  PBT_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
 }
 
 // Work decomposition: targets in chunks of 64 within tree leaves; for every
@@ -304,8 +342,10 @@ void System::build_plan() {
   }
   // Segment sizes: aim at several thousand wavefront tasks in each launch.
   const int64_t want = 16384;
-  const int64_t seg_src = std::min<int64_t>(16384, std::max<int64_t>(256, tot_src / want));
-  const int64_t seg_box = std::min<int64_t>(64, std::max<int64_t>(2, tot_box / want));
+  const int64_t seg_src = seg_src_ > 0 ? seg_src_ : std::min<int64_t>(16384, std::max<int64_t>(256, tot_src / want));
+  const int64_t seg_box = seg_box_ > 0 ? seg_box_ : std::min<int64_t>(64, std::max<int64_t>(2, tot_box / want));
+  seg_src_used_ = seg_src;
+  seg_box_used_ = seg_box;
 
   // Chunks.
   std::vector<int> leaf_chunk0(leaves.size());
@@ -394,7 +434,7 @@ void System::interactions(hipStream_t s) {
   const T* tgt = f32 ? (const T*)tgt32_.p : (const T*)tgt64_.p;
   T* part = f32 ? (T*)part32_.p : (T*)part64_.p;
   T* mom = f32 ? (T*)mom32_.p : (T*)mom64_.p;
-  launch_strengths<T>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, src, s);
+  launch_strengths<T>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, rlap_.p, src, s);
   PBT_HIP(hipEventRecord(ev_[1], s));
   if (!plan_.m2p.empty()) {
     BoxDev bd{bcen_.p, bsbeg_.p, bsend_.p, bcbeg_.p, bcend_.p, bclist_.p, brho_.p};
@@ -660,7 +700,7 @@ void System::energies(const double* x, pbt_result* res, hipStream_t s) {
   PBT_HIP(hipMemcpyAsync(xh.data(), x, n_ * sizeof(double), hipMemcpyDeviceToHost, s));
   PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
   launch_densities(np_, m, x, sig_.p, mu_.p, s);
-  launch_strengths<double>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, src64_.p, s);
+  launch_strengths<double>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, rlap_.p, src64_.p, s);
   PBT_HIP(hipStreamSynchronize(s));
   double fsolv = 0, fcoul = 0, fsurf = 0;
   for (int e = 0; e < ns; ++e) {

@@ -121,6 +121,14 @@ class System {
   void gradient_terms(const double* x, const double* lam, std::vector<std::vector<double>>& dq,
                       std::vector<std::vector<double>>& dsig, hipStream_t s);
   const SurfIn* surface(int e) const { return surfs_[e]; }
+
+  // Launch shape of the P2P / M2P tasks: Gauss points per P2P segment and
+  // boxes per M2P segment (0 = size-based default).  Rebuilds the work lists.
+  void set_segments(int64_t seg_src, int64_t seg_box, hipStream_t s);
+  int64_t seg_src() const { return seg_src_used_; }
+  int64_t seg_box() const { return seg_box_used_; }
+  // Average milliseconds of `reps` operator applications (after one warm-up).
+  double time_products(bool fp32, int reps, hipStream_t s);
   int n_surfaces() const { return (int)surfs_.size(); }
 
   // Milliseconds of the last operator application: total, P2P, M2P,
@@ -167,7 +175,7 @@ class System {
   DBuf<double> src64_;
   DBuf<float> src32_;
   DBuf<int32_t> col_phi_, col_psi_, row_int_, row_sol_;
-  DBuf<double> dens_scale_;
+  DBuf<double> dens_scale_, rlap_;
   DBuf<double> sig_, mu_;
   NearCSR near_;
   DBuf<int32_t> panel_surf_;
@@ -203,6 +211,8 @@ class System {
   hipEvent_t ev_[6];
   int64_t napply_ = 0;
   bool transpose_ = false;
+  int64_t seg_src_ = 0, seg_box_ = 0, seg_src_used_ = 0, seg_box_used_ = 0;
+  void upload_plan(hipStream_t s);
 
   // forward interaction lists per (target leaf, source surface), for the transpose
   struct LeafInfo { int e; int b; int64_t g0, g1; };

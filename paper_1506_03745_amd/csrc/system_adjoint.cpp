@@ -369,7 +369,7 @@ void System::gradient_terms(const double* x, const double* lam, std::vector<std:
   PBT_HIP(hipMemcpyAsync(xh.data(), x, n_ * sizeof(double), hipMemcpyDeviceToHost, s));
   PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
   launch_densities(np_, m, x, sig_.p, mu_.p, s);
-  launch_strengths<double>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, src64_.p, s);
+  launch_strengths<double>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, rlap_.p, src64_.p, s);
   PBT_HIP(hipStreamSynchronize(s));
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];

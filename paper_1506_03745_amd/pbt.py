@@ -24,7 +24,7 @@ STATUS = {0: "PBT_OK", 1: "PBT_E_INVALID", 2: "PBT_E_NOMEM", 3: "PBT_E_DEVICE",
 
 EXPORTS = ("pbt_default_params", "pbt_create", "pbt_destroy", "pbt_last_error", "pbt_set_params",
            "pbt_set_solvent", "pbt_add_surface", "pbt_set_bc", "pbt_set_charges", "pbt_enable",
-           "pbt_num_unknowns", "pbt_solve", "pbt_get_solution", "pbt_interaction_energy",
+           "pbt_prepare", "pbt_num_unknowns", "pbt_solve", "pbt_get_solution", "pbt_interaction_energy",
            "pbt_matvec", "pbt_matvec_dev", "pbt_rhs", "pbt_gradient", "pbt_solve_batch",
            "pbt_autotune", "pbt_quadrature_rule", "pbt_last_matvec_timing")
 
@@ -87,6 +87,7 @@ def lib():
         L.pbt_set_charges.argtypes = [P, I32, D, P, P, I64]
         L.pbt_enable.argtypes = [P, I32, I32]
         L.pbt_num_unknowns.argtypes = [P, ctypes.POINTER(I64)]
+        L.pbt_prepare.argtypes = [P]
         L.pbt_solve.argtypes = [P, P, ctypes.POINTER(PbtResult)]
         L.pbt_get_solution.argtypes = [P, I32, P, P]
         L.pbt_interaction_energy.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(PbtResult)]
@@ -215,6 +216,9 @@ class Solver:
 
     def enable(self, sid, on=True):
         self._check(lib().pbt_enable(self._h, sid, 1 if on else 0))
+
+    def prepare(self):
+        self._check(lib().pbt_prepare(self._h))
 
     def num_unknowns(self) -> int:
         n = ctypes.c_int64()
