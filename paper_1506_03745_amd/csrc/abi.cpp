@@ -1,5 +1,6 @@
 // C entry points of the pbt library (declared in include/pbt.h).
 #include <chrono>
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -464,8 +465,104 @@ pbt_status pbt_gradient(pbt_ctx* c, int32_t sigma_id, double* dF_dsigma, int32_t
   });
 }
 
-pbt_status pbt_solve_batch(pbt_ctx* c, int32_t, const double*, const double*, int32_t, double*) {
-  return fail(c, PBT_E_STATE, "batched solve not available in this build");
+// Batched rigid placements (orientation sweep).  Up to kBatch assemblies are
+// put into one block-diagonal system: group g holds the molecule moved by
+// placement g and copies of every other enabled surface; interaction and
+// near lists never cross groups, so each operator launch serves all of them
+// and GMRES advances them in lock-step.  The global relative tolerance is
+// tol / sqrt(G); every group's own relative residual is then checked and the
+// solve continued (from its iterate) until each is below tol.  The isolated
+// energies are computed once (the discrete problem of a rigidly moved body
+// is the same problem up to rounding and, with the treecode, its tree).
+pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const double* shift, int32_t nb,
+                           double* F_int) {
+  return guarded(c, [&] {
+    const int ns = (int)c->surfs.size();
+    if (mol_id < 0 || mol_id >= ns || c->surfs[mol_id]->kind != PBT_MOLECULE)
+      return fail(c, PBT_E_INVALID, "mol_id must name a molecule");
+    if (nb < 0 || (nb > 0 && (!rot || !shift || !F_int))) return fail(c, PBT_E_INVALID, "bad batch arrays");
+    for (int64_t i = 0; i < 9LL * nb; ++i)
+      if (!std::isfinite(rot[i])) return fail(c, PBT_E_INVALID, "non-finite rotation");
+    for (int64_t i = 0; i < 3LL * nb; ++i)
+      if (!std::isfinite(shift[i])) return fail(c, PBT_E_INVALID, "non-finite shift");
+    if (nb == 0) return PBT_OK;
+    std::vector<bool> saved = mask_of(c);
+    auto restore = [&] { for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = saved[i]; };
+    std::vector<int> others;
+    for (int i = 0; i < ns; ++i)
+      if (saved[i] && i != mol_id) others.push_back(i);
+    // isolated energies, once
+    double f_iso = 0.0;
+    pbt_status worst = PBT_OK;
+    try {
+      for (int k : std::vector<int>{mol_id}) (void)k;
+      std::vector<int> comps{mol_id};
+      comps.insert(comps.end(), others.begin(), others.end());
+      for (int k : comps) {
+        for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = i == k;
+        pbt_result r{};
+        pbt_status st = solve_impl(c, nullptr, &r);
+        if (st != PBT_OK && st != PBT_E_NOCONVERGE) { restore(); return st; }
+        if (st != PBT_OK) worst = st;
+        f_iso += r.F_total;
+      }
+    } catch (...) {
+      restore();
+      throw;
+    }
+    restore();
+    const int kBatch = 64;
+    const SurfIn& M = *c->surfs[mol_id];
+    for (int b0 = 0; b0 < nb; b0 += kBatch) {
+      const int G = std::min(kBatch, nb - b0);
+      std::vector<std::unique_ptr<SurfIn>> own;
+      std::vector<const SurfIn*> list;
+      for (int g = 0; g < G; ++g) {
+        const double* R = rot + 9 * (int64_t)(b0 + g);
+        const double* t = shift + 3 * (int64_t)(b0 + g);
+        auto mv = [&](const std::vector<double>& in) {
+          std::vector<double> o(in.size());
+          for (size_t i = 0; i + 2 < in.size(); i += 3)
+            for (int d = 0; d < 3; ++d)
+              o[i + d] = R[3 * d] * in[i] + R[3 * d + 1] * in[i + 1] + R[3 * d + 2] * in[i + 2] + t[d];
+          return o;
+        };
+        auto m = std::make_unique<SurfIn>(M);
+        m->xyz = mv(M.xyz);
+        m->qxyz = mv(M.qxyz);
+        m->group = g;
+        list.push_back(m.get());
+        own.push_back(std::move(m));
+        for (int k : others) {
+          auto o = std::make_unique<SurfIn>(*c->surfs[k]);
+          o->group = g;
+          list.push_back(o.get());
+          own.push_back(std::move(o));
+        }
+      }
+      System S(list, c->prm, c->eps_out, c->kappa, c->stream);
+      const int64_t n = S.n();
+      DBuf<double> b, x;
+      b.alloc(n);
+      x.alloc(n);
+      S.rhs(b.p, c->stream);
+      PBT_HIP(hipMemsetAsync(x.p, 0, n * sizeof(double), c->stream));
+      double tol = c->prm.tol / std::sqrt((double)G);
+      bool ok = false;
+      for (int round = 0; round < 4 && !ok; ++round) {
+        pbt_result r{};
+        S.solve_tol(b.p, x.p, tol, &r, c->stream);
+        std::vector<double> gr = S.group_residuals(b.p, x.p, G, c->stream);
+        ok = *std::max_element(gr.begin(), gr.end()) <= c->prm.tol;
+        tol *= 0.1;
+      }
+      if (!ok) worst = PBT_E_NOCONVERGE;
+      std::vector<pbt_result> e = S.energies_by_group(x.p, G, c->stream);
+      for (int g = 0; g < G; ++g) F_int[b0 + g] = e[g].F_total - f_iso;
+    }
+    if (worst != PBT_OK) return fail(c, worst, "a batched solve did not reach the tolerance");
+    return PBT_OK;
+  });
 }
 
 // Autotuner: times the operator of the enabled system for candidate P2P and

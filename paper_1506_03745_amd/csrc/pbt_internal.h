@@ -66,9 +66,11 @@ void launch_sources(int64_t np, int K, const double* tri9, const double* nrm, co
                     const double* bary, const double* w, double* src_pos, double* src_wa,
                     hipStream_t s);
 void launch_near_count(int64_t nt, const double* tx, int64_t np, const double* cen,
-                       const double* cross2, int32_t* count, hipStream_t s);
+                       const double* cross2, const int32_t* tgrp, const int32_t* pgrp,
+                       const int64_t* grange, int32_t* count, hipStream_t s);
 void launch_near_fill(int64_t nt, const double* tx, int64_t np, const double* cen,
-                      const double* cross2, const int64_t* rowptr, int32_t* col, hipStream_t s);
+                      const double* cross2, const int32_t* tgrp, const int32_t* pgrp,
+                      const int64_t* grange, const int64_t* rowptr, int32_t* col, hipStream_t s);
 struct NearParams {
   int K, Knear, Nedge;
   double kappa;

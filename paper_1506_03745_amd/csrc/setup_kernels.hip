@@ -75,21 +75,31 @@ __device__ __forceinline__ bool is_near(double tx, double ty, double tz, double 
 // One wavefront per target, lanes over panels.  The fill pass writes the
 // hits of each 64-panel chunk in panel order (ballot + popcount), so the
 // lists come out sorted exactly as a serial scan would produce them.
+// Targets and panels of different groups (independent systems solved in
+// one batch) never pair: a target of group g scans only the panel range
+// [grange[2g], grange[2g+1]) and checks pgrp; tgrp / pgrp / grange may be
+// null (one group, all panels).
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_near(int64_t nt, const double* __restrict__ tx, int64_t np,
                                               const double* __restrict__ cen,
-                                              const double* __restrict__ cross2, int32_t* count,
+                                              const double* __restrict__ cross2,
+                                              const int32_t* __restrict__ tgrp,
+                                              const int32_t* __restrict__ pgrp,
+                                              const int64_t* __restrict__ grange, int32_t* count,
                                               const int64_t* __restrict__ rowptr, int32_t* col) {
   const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= nt) return;  // uniform across the wavefront
   const double x = tx[3 * i], y = tx[3 * i + 1], z = tx[3 * i + 2];
+  const int32_t g = tgrp ? tgrp[i] : 0;
   int64_t out = FILL ? rowptr[i] : 0;
   int32_t cnt = 0;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t j0 = 0; j0 < np; j0 += 64) {
+  const int64_t jb = grange ? grange[2 * g] : 0, je = grange ? grange[2 * g + 1] : np;
+  for (int64_t j0 = jb; j0 < je; j0 += 64) {
     const int64_t j = j0 + lane;
-    const bool hit = j < np && is_near(x, y, z, cen[3 * j], cen[3 * j + 1], cen[3 * j + 2], cross2[j]);
+    const bool hit = j < je && (!tgrp || pgrp[j] == g) &&
+                     is_near(x, y, z, cen[3 * j], cen[3 * j + 1], cen[3 * j + 2], cross2[j]);
     const uint64_t m = __ballot(hit);
     if (FILL) {
       if (hit) col[out + __popcll(m & below)] = (int32_t)j;
@@ -255,16 +265,20 @@ void launch_sources(int64_t np, int K, const double* tri9, const double* nrm, co
 }
 
 void launch_near_count(int64_t nt, const double* tx, int64_t np, const double* cen,
-                       const double* cross2, int32_t* count, hipStream_t s) {
+                       const double* cross2, const int32_t* tgrp, const int32_t* pgrp,
+                       const int64_t* grange, int32_t* count, hipStream_t s) {
   if (nt <= 0) return;
-  k_near<false><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, count, nullptr, nullptr);
+  k_near<false><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tgrp, pgrp, grange, count,
+                                                        nullptr, nullptr);
   PBT_HIP(hipGetLastError());
 }
 
 void launch_near_fill(int64_t nt, const double* tx, int64_t np, const double* cen,
-                      const double* cross2, const int64_t* rowptr, int32_t* col, hipStream_t s) {
+                      const double* cross2, const int32_t* tgrp, const int32_t* pgrp,
+                      const int64_t* grange, const int64_t* rowptr, int32_t* col, hipStream_t s) {
   if (nt <= 0) return;
-  k_near<true><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, nullptr, rowptr, col);
+  k_near<true><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tgrp, pgrp, grange, nullptr,
+                                                       rowptr, col);
   PBT_HIP(hipGetLastError());
 }
 

@@ -113,6 +113,26 @@ void System::build(hipStream_t s) {
     rlap_.upload(rl, s);
   }
   panel_surf_.upload(psurf, s);
+  {
+    // groups: ids 0..G-1, each a contiguous panel range (surfaces are added
+    // group by group)
+    std::vector<int32_t> pg(np_);
+    ngroups_ = 1;
+    for (int64_t g = 0; g < np_; ++g) {
+      pg[g] = surfs_[psurf[g]]->group;
+      ngroups_ = std::max(ngroups_, pg[g] + 1);
+    }
+    std::vector<int64_t> gr(2 * ngroups_, 0);
+    for (int k = 0; k < ngroups_; ++k) { gr[2 * k] = np_; gr[2 * k + 1] = 0; }
+    for (int64_t g = 0; g < np_; ++g) {
+      gr[2 * pg[g]] = std::min(gr[2 * pg[g]], g);
+      gr[2 * pg[g] + 1] = std::max(gr[2 * pg[g] + 1], g + 1);
+    }
+    for (int k = 0; k < ngroups_; ++k)
+      if (gr[2 * k] > gr[2 * k + 1]) gr[2 * k] = gr[2 * k + 1] = 0;
+    panel_group_.upload(pg, s);
+    group_range_.upload(gr, s);
+  }
   std::vector<int32_t> smol(ns);
   std::vector<double> srho(ns);
   for (int e = 0; e < ns; ++e) {
@@ -168,7 +188,8 @@ void System::build(hipStream_t s) {
   {
     DBuf<int32_t> cnt;
     cnt.alloc(np_);
-    launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, cnt.p, s);
+    launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, panel_group_.p, panel_group_.p, group_range_.p,
+                      cnt.p, s);
     std::vector<int32_t> hc = cnt.download(s);
     std::vector<int64_t> ptr(np_ + 1, 0);
     for (int64_t i = 0; i < np_; ++i) ptr[i + 1] = ptr[i] + hc[i];
@@ -176,7 +197,8 @@ void System::build(hipStream_t s) {
     near_.ptr.upload(ptr, s);
     near_.col.alloc(std::max<int64_t>(near_.nnz, 1));
     near_.val.alloc(4 * std::max<int64_t>(near_.nnz, 1));
-    launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, near_.ptr.p, near_.col.p, s);
+    launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, panel_group_.p, panel_group_.p, group_range_.p,
+                     near_.ptr.p, near_.col.p, s);
     std::vector<int32_t> self(np_);
     for (int64_t i = 0; i < np_; ++i) self[i] = (int32_t)i;
     DBuf<int32_t> dself;
@@ -318,6 +340,7 @@ void System::build_plan() {
     const int64_t nt = tl.pend - tl.pbeg;
     for (int e2 = 0; e2 < ns; ++e2) {
       std::vector<int> pb, mb;
+      if (surfs_[e2]->group != surfs_[leaves[li].e]->group) continue;  // independent systems
       if (prm_.treecode) interaction_lists(trees_[e2], tl, prm_.theta, pb, mb);
       else pb.push_back(0);
       std::sort(pb.begin(), pb.end(), [&](int a, int b) {
@@ -694,24 +717,25 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
   return rel <= tol * (1.0 + 1e-12);
 }
 
-void System::energies(const double* x, pbt_result* res, hipStream_t s) {
+std::vector<std::array<double, 3>> System::surface_energies(const double* x, hipStream_t s) {
   const int ns = (int)surfs_.size();
+  std::vector<std::array<double, 3>> out(ns, {0.0, 0.0, 0.0});
   std::vector<double> xh(n_);
   PBT_HIP(hipMemcpyAsync(xh.data(), x, n_ * sizeof(double), hipMemcpyDeviceToHost, s));
   PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
   launch_densities(np_, m, x, sig_.p, mu_.p, s);
   launch_strengths<double>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, rlap_.p, src64_.p, s);
   PBT_HIP(hipStreamSynchronize(s));
-  double fsolv = 0, fcoul = 0, fsurf = 0;
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
     if (S.kind == PBT_MOLECULE) {
       const int64_t nq = (int64_t)S.q.size();
       if (nq == 0) continue;
+      // F_solv = 1/2 sum q phi_reac (eq. solv_energy, first line)
       std::vector<double> hphi = reaction_potential(e, s);
       double acc = 0;
       for (int64_t k = 0; k < nq; ++k) acc += S.q[k] * hphi[k];
-      fsolv += 0.5 * acc;
+      out[e][1] = 0.5 * acc;
       double c = 0;
       for (int64_t k = 0; k < nq; ++k)
         for (int64_t l = k + 1; l < nq; ++l) {
@@ -719,26 +743,85 @@ void System::energies(const double* x, pbt_result* res, hipStream_t s) {
                        dz = S.qxyz[3 * k + 2] - S.qxyz[3 * l + 2];
           c += S.q[k] * S.q[l] / std::sqrt(dx * dx + dy * dy + dz * dz);
         }
-      fcoul += c / (kFourPi * S.eps_in);
+      out[e][0] = c / (kFourPi * S.eps_in);
     } else {
+      double f = 0;
       for (int64_t li = 0; li < S.nt; ++li) {
         const int64_t g = poff_[e] + li;
         const int32_t o = h_panel_orig_[g];
         const double A = h_area_[g];
         if (S.kind == PBT_CHARGED) {
           // 1/2 sum phi_j sigma_j A_j (eq. energy_surf_disc, set charge)
-          fsurf += 0.5 * xh[col_off_[e] + o] * (S.bc[o] * kSigmaSI) * A;
+          f += 0.5 * xh[col_off_[e] + o] * (S.bc[o] * kSigmaSI) * A;
         } else {
           // -1/2 sum phi0_j sigma_j A_j with sigma = -eps_out dphi/dn
-          fsurf += 0.5 * eps_out_ * (S.bc[o] / kVoltPerUnit) * xh[col_off_[e] + o] * A;
+          f += 0.5 * eps_out_ * (S.bc[o] / kVoltPerUnit) * xh[col_off_[e] + o] * A;
         }
       }
+      out[e][2] = f;
     }
   }
-  res->F_solv = fsolv * kKcalPerUnit;
-  res->F_coul = fcoul * kKcalPerUnit;
-  res->F_surf = fsurf * kKcalPerUnit;
-  res->F_total = res->F_solv + res->F_coul + res->F_surf;
+  return out;
+}
+
+void System::energies(const double* x, pbt_result* res, hipStream_t s) {
+  double fc = 0, fs = 0, fsu = 0;
+  for (const auto& e : surface_energies(x, s)) {
+    fc += e[0];
+    fs += e[1];
+    fsu += e[2];
+  }
+  res->F_coul = fc * kKcalPerUnit;
+  res->F_solv = fs * kKcalPerUnit;
+  res->F_surf = fsu * kKcalPerUnit;
+  res->F_total = res->F_coul + res->F_solv + res->F_surf;
+}
+
+std::vector<pbt_result> System::energies_by_group(const double* x, int ngroups, hipStream_t s) {
+  std::vector<pbt_result> out(ngroups);
+  const auto se = surface_energies(x, s);
+  for (size_t e = 0; e < se.size(); ++e) {
+    pbt_result& r = out[surfs_[e]->group];
+    r.F_coul += se[e][0] * kKcalPerUnit;
+    r.F_solv += se[e][1] * kKcalPerUnit;
+    r.F_surf += se[e][2] * kKcalPerUnit;
+  }
+  for (auto& r : out) r.F_total = r.F_coul + r.F_solv + r.F_surf;
+  return out;
+}
+
+std::vector<double> System::group_residuals(const double* b, const double* x, int ngroups, hipStream_t s) {
+  DBuf<double> r;
+  r.alloc(n_);
+  transpose_ = false;
+  true_residual(b, x, r.p, s);
+  std::vector<double> hr = r.download(s), hb(n_);
+  PBT_HIP(hipMemcpy(hb.data(), b, n_ * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> num(ngroups, 0.0), den(ngroups, 0.0);
+  for (size_t e = 0; e < surfs_.size(); ++e) {
+    const int g = surfs_[e]->group;
+    for (int64_t i = row_off_[e]; i < row_off_[e + 1]; ++i) {
+      num[g] += hr[i] * hr[i];
+      den[g] += hb[i] * hb[i];
+    }
+  }
+  std::vector<double> out(ngroups);
+  for (int g = 0; g < ngroups; ++g) out[g] = den[g] > 0 ? std::sqrt(num[g] / den[g]) : 0.0;
+  return out;
+}
+
+bool System::solve_tol(const double* b, double* x, double tol, pbt_result* res, hipStream_t s) {
+  const double saved = prm_.tol;
+  prm_.tol = tol;
+  bool ok = false;
+  try {
+    ok = solve(b, x, true, res, s);
+  } catch (...) {
+    prm_.tol = saved;
+    throw;
+  }
+  prm_.tol = saved;
+  return ok;
 }
 
 void System::unpack(const std::vector<double>& xh, int e, double* phi, double* dphidn) const {

@@ -3,6 +3,7 @@
 // surfaces, plus the operator, right-hand side, GMRES and energies.
 #pragma once
 
+#include <array>
 #include <memory>
 #include <string>
 #include <vector>
@@ -62,6 +63,7 @@ struct SurfIn {
   double eps_in = 1.0;
   std::vector<double> qxyz, q;
   bool enabled = true;
+  int group = 0;  // surfaces of different groups belong to independent systems
 };
 
 struct NearCSR {
@@ -105,6 +107,12 @@ class System {
   bool solve(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s);
   // Energies (kcal/mol) of solution x (device).
   void energies(const double* x, pbt_result* res, hipStream_t s);
+  // Energies per group (index = group id), same units.
+  std::vector<pbt_result> energies_by_group(const double* x, int ngroups, hipStream_t s);
+  // Relative residual of each group's block of b - A x (FP64 operator).
+  std::vector<double> group_residuals(const double* b, const double* x, int ngroups, hipStream_t s);
+  // Solves with a given relative tolerance (overrides params.tol).
+  bool solve_tol(const double* b, double* x, double tol, pbt_result* res, hipStream_t s);
   // Host copy of a surface's solution in caller order.
   void unpack(const std::vector<double>& xh, int local_surface, double* phi, double* dphidn) const;
   int local_index(int surface_id) const;
@@ -155,6 +163,8 @@ class System {
   template <typename T>
   void apply_t(const double* lam, double* z, double* sigbar, hipStream_t s);
   void charge_near(int e, const double* qx, int64_t nq, NearCSR& out, hipStream_t s);
+  // Per-surface (F_coul, F_solv, F_surf) in reduced units.
+  std::vector<std::array<double, 3>> surface_energies(const double* x, hipStream_t s);
   std::vector<double> reaction_potential(int e, hipStream_t s);  // densities already set
   double norm(const double* v, hipStream_t s);
 
@@ -178,7 +188,9 @@ class System {
   DBuf<double> dens_scale_, rlap_;
   DBuf<double> sig_, mu_;
   NearCSR near_;
-  DBuf<int32_t> panel_surf_;
+  DBuf<int32_t> panel_surf_, panel_group_;
+  DBuf<int64_t> group_range_;
+  int ngroups_ = 1;
   DBuf<int32_t> surf_mol_;
   DBuf<double> surf_rhoinv_;
   std::vector<int32_t> h_panel_orig_;  // internal global -> original index within its surface

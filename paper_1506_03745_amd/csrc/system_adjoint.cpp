@@ -30,7 +30,7 @@ void System::charge_near(int e, const double* qx, int64_t nq, NearCSR& qn, hipSt
   NearParams npr{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
   DBuf<int32_t> cnt;
   cnt.alloc(nq);
-  launch_near_count(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, cnt.p, s);
+  launch_near_count(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr, cnt.p, s);
   std::vector<int32_t> hc = cnt.download(s);
   std::vector<int64_t> ptr(nq + 1, 0);
   for (int64_t k = 0; k < nq; ++k) ptr[k + 1] = ptr[k] + hc[k];
@@ -38,7 +38,7 @@ void System::charge_near(int e, const double* qx, int64_t nq, NearCSR& qn, hipSt
   qn.ptr.upload(ptr, s);
   qn.col.alloc(std::max<int64_t>(ptr[nq], 1));
   qn.val.alloc(4 * std::max<int64_t>(ptr[nq], 1));
-  launch_near_fill(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, qn.ptr.p, qn.col.p, s);
+  launch_near_fill(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr, qn.ptr.p, qn.col.p, s);
   launch_near_values(nq, qx, nullptr, qn.ptr.p, qn.col.p, tri9_.p + 9 * p0, nrm_.p + 3 * p0,
                      area_.p + p0, npr, qn.val.p, s);
   // the charges and the molecule's panels form a one-surface table
