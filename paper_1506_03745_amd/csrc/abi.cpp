@@ -360,7 +360,7 @@ pbt_status pbt_matvec_dev(pbt_ctx* c, const double* x_dev, double* y_dev, int32_
     System& S = system_for(c);
     hipStream_t st = stream ? (hipStream_t)stream : c->stream;
     if (transpose) S.matvec_t(x_dev, y_dev, prec == PBT_MIXED, nullptr, st);
-    else S.matvec(x_dev, y_dev, prec == PBT_MIXED, st);
+    else S.matvec(x_dev, y_dev, prec == PBT_MIXED, st, true);
     return PBT_OK;
   });
 }
@@ -374,7 +374,7 @@ pbt_status pbt_matvec(pbt_ctx* c, const double* x, double* y, int32_t transpose,
     c->dy.alloc(n);
     PBT_HIP(hipMemcpyAsync(c->dx.p, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (transpose) S.matvec_t(c->dx.p, c->dy.p, prec == PBT_MIXED, nullptr, c->stream);
-    else S.matvec(c->dx.p, c->dy.p, prec == PBT_MIXED, c->stream);
+    else S.matvec(c->dx.p, c->dy.p, prec == PBT_MIXED, c->stream, true);
     PBT_HIP(hipMemcpyAsync(y, c->dy.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     PBT_HIP(hipStreamSynchronize(c->stream));
     return PBT_OK;
@@ -592,7 +592,8 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
       }
     }
     if (it != memo.end()) {
-      S.set_segments(it->second.first, it->second.second, c->stream);
+      S.set_segments(it->second.first, it->second.second / 2, c->stream);
+      S.set_overlap(it->second.second % 2 == 1);
       return PBT_OK;
     }
     const int reps = 5;
@@ -609,10 +610,15 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
       if (t < best) { best = t; best_box = cand; }
     }
     S.set_segments(best_src, best_box, c->stream);
-    memo[key] = {best_src, best_box};
+    // far field on a second stream or after P2P on the same stream
+    const bool ov0 = S.overlap();
+    S.set_overlap(!ov0);
+    if (S.time_products(fp32, reps, c->stream) >= best) S.set_overlap(ov0);
+    memo[key] = {best_src, best_box * 2 + (S.overlap() ? 1 : 0)};
     if (cache_path) {
       if (FILE* f = std::fopen(cache_path, "a")) {
-        std::fprintf(f, "%s %lld %lld %.6f\n", key, (long long)best_src, (long long)best_box, best);
+        std::fprintf(f, "%s %lld %lld %.6f\n", key, (long long)best_src,
+                     (long long)(best_box * 2 + (S.overlap() ? 1 : 0)), best);
         std::fclose(f);
       }
     }

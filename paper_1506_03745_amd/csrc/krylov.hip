@@ -46,6 +46,114 @@ __global__ __launch_bounds__(kBS) void k_multidot(int64_t n, int m, const double
   }
 }
 
+// Arnoldi column j of the Hessenberg matrix from the two Gram-Schmidt passes
+// (h1 + h2) and |w'|^2 (w' = w after the first pass), the previous Givens
+// rotations applied, a new rotation computed and the residual estimate
+// |g_{j+1}| stored in resid[j]; resid[m] receives |w''|^2 for the
+// normalisation.  The wavefront stages the column and the rotations in LDS;
+// lane 0 then applies the rotations in order (at most restart + 1 entries).
+__global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __restrict__ h1,
+                                               const double* __restrict__ h2, const double* __restrict__ hn2,
+                                               double* H, double* cs, double* sn, double* g, double* resid) {
+  extern __shared__ double sh[];   // col[m + 1], c[m], s[m]
+  double* col = sh;
+  double* c = sh + (m + 1);
+  double* sv = c + m;
+  for (int i = threadIdx.x; i <= j; i += 64) {
+    col[i] = h1[i] + h2[i];
+    if (i < j) {
+      c[i] = cs[i];
+      sv[i] = sn[i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // |w''|^2 = |w'|^2 - |h2|^2 (w'' = w' - V h2, V orthonormal)
+    double h2s = 0.0;
+    for (int i = 0; i <= j; ++i) h2s += h2[i] * h2[i];
+    const double nn = fmax(*hn2 - h2s, 0.0);
+    resid[m] = nn;        // |w''|^2 for the normalisation kernel
+    const double hn = sqrt(nn);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = c[i] * a + sv[i] * b;
+      col[i + 1] = -sv[i] * a + c[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = hypot(a, b);
+    const double cj = den > 0 ? a / den : 1.0, sj = den > 0 ? b / den : 0.0;
+    cs[j] = cj;
+    sn[j] = sj;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = cj * gj;
+    resid[j] = hn > 0 ? fabs(sj * gj) : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += 64) H[(size_t)i * m + j] = col[i];
+}
+
+// Partial sums, per block, of the dots of w with V_0..V_{m-1} and, if
+// self_dot, of w.w (output index m); optionally after w -= sum_i hin_i V_i
+// (each thread updates and then reads only its own elements).
+__global__ __launch_bounds__(kBS) void k_pdots(int64_t n, int m, const double* __restrict__ V, int64_t ldv,
+                                               const double* __restrict__ hin, double* __restrict__ w,
+                                               int self_dot, double* __restrict__ part) {
+  __shared__ double red[kBS / 64][8];
+  const int nblk = gridDim.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t stride = (int64_t)nblk * kBS;
+  if (hin) {
+    for (int64_t j = blockIdx.x * (int64_t)kBS + threadIdx.x; j < n; j += stride) {
+      double sj = w[j];
+#pragma unroll 8
+      for (int i = 0; i < m; ++i) sj -= hin[i] * V[(int64_t)i * ldv + j];
+      w[j] = sj;
+    }
+  }
+  const int mq = m + (self_dot ? 1 : 0);
+  for (int i0 = 0; i0 < mq; i0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t j = blockIdx.x * (int64_t)kBS + threadIdx.x; j < n; j += stride) {
+      const double wj = w[j];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q;
+        if (i < mq) acc[q] += (i < m ? V[(int64_t)i * ldv + j] : wj) * wj;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double sq = wave_sum(acc[q]);
+      if (lane == 0) red[wid][q] = sq;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && i0 + (int)threadIdx.x < mq) {
+      double sq = 0;
+      for (int k = 0; k < kBS / 64; ++k) sq += red[k][threadIdx.x];
+      part[(int64_t)(i0 + threadIdx.x) * nblk + blockIdx.x] = sq;
+    }
+    __syncthreads();
+  }
+}
+
+// w = (w - sum_i h_i V_i) / sqrt(*nrm2)  (the second Gram-Schmidt update
+// fused with the normalisation)
+__global__ void k_update_normalize(int64_t n, int m, const double* __restrict__ V, int64_t ldv,
+                                   const double* __restrict__ h, const double* __restrict__ nrm2,
+                                   double* __restrict__ w) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double sj = w[j];
+#pragma unroll 8
+  for (int i = 0; i < m; ++i) sj -= h[i] * V[(int64_t)i * ldv + j];
+  const double v = *nrm2;
+  w[j] = v > 0.0 ? sj / sqrt(v) : 0.0;
+}
+
 __global__ void k_reduce_cols(int m, int nblk, const double* __restrict__ part, double* out) {
   const int i = blockIdx.x;
   double s = 0;
@@ -97,9 +205,9 @@ __global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, 
 }  // namespace
 
 int multidot_blocks(int64_t n) {
-  int64_t b = (n + kBS - 1) / kBS;
+  int64_t b = (n + 63) / 64;
   if (b < 1) b = 1;
-  if (b > 480) b = 480;
+  if (b > 960) b = 960;
   return (int)b;
 }
 
@@ -125,6 +233,25 @@ void launch_lincomb(int64_t n, int m, const double* V, int64_t ldv, const double
                     hipStream_t s) {
   if (n <= 0 || m <= 0) return;
   k_lincomb<<<nblocks(n, 256), 256, 0, s>>>(n, m, V, ldv, c, y);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_pdots(int64_t n, int m, const double* V, int64_t ldv, const double* hin, double* w, int self_dot,
+                  double* part, int nblk, hipStream_t s) {
+  k_pdots<<<nblk, kBS, 0, s>>>(n, m, V, ldv, hin, w, self_dot, part);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_update_normalize(int64_t n, int m, const double* V, int64_t ldv, const double* h,
+                             const double* nrm2, double* w, hipStream_t s) {
+  if (n <= 0) return;
+  k_update_normalize<<<nblocks(n, 256), 256, 0, s>>>(n, m, V, ldv, h, nrm2, w);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_givens(int j, int m, const double* h1, const double* h2, const double* hn2, double* H, double* cs,
+                   double* sn, double* g, double* resid, hipStream_t s) {
+  k_givens<<<1, 64, (size_t)(3 * m + 1) * sizeof(double), s>>>(j, m, h1, h2, hn2, H, cs, sn, g, resid);
   PBT_HIP(hipGetLastError());
 }
 

@@ -61,6 +61,33 @@ __global__ void k_strengths(int64_t ns, int K, const double* __restrict__ sig,
   o[7] = (T)(rlap[p] * sv);
 }
 
+// Same, with the panel densities read straight from the unknowns (and also
+// stored for the near-field combine by the first Gauss point of each panel).
+template <typename T>
+__global__ void k_strengths_x(int64_t ns, int K, PanelMaps m, const double* __restrict__ x,
+                              const double* __restrict__ wa, const double* __restrict__ nrm,
+                              const double* __restrict__ rlap, double* sig, double* mu, T* src) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  const int64_t p = j / K;
+  const int32_t cphi = m.col_phi[p], cpsi = m.col_psi[p];
+  const double sg = cpsi >= 0 ? m.dens_scale[p] * x[cpsi] : 0.0;
+  const double mv = cphi >= 0 ? -x[cphi] : 0.0;
+  if (j == p * K) {
+    sig[p] = sg;
+    mu[p] = mv;
+  }
+  const double w = wa[j];
+  const double mm = w * mv;
+  const double sv = w * sg;
+  T* o = src + kSrcStride * j;
+  o[3] = (T)sv;
+  o[4] = (T)(mm * nrm[3 * p]);
+  o[5] = (T)(mm * nrm[3 * p + 1]);
+  o[6] = (T)(mm * nrm[3 * p + 2]);
+  o[7] = (T)(rlap[p] * sv);
+}
+
 template <typename T>
 struct KMath;
 template <>
@@ -86,17 +113,66 @@ __device__ __forceinline__ int xcd_block() {
   return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
-// One wavefront per task, one target per lane.  The source loop index is
-// uniform across the wave, so source records are fetched with scalar loads
-// and broadcast to all lanes as SGPR operands.
+// One source record (x y z s Dx Dy Dz s_L), aligned so that LDS reads of a
+// record are full-width.
+template <typename T>
+struct alignas(8 * sizeof(T)) SrcRec {
+  T v[8];
+};
+
+// Wave-scope ordering of LDS writes and reads between the lanes of one
+// wavefront (no workgroup barrier: the waves of a block run independent
+// tasks with different trip counts).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Interaction of one target with one source record (eqs. bem_interior and
+// bem_exterior, discrete forms): l accumulates s_L/r - D.(x-y)/r^3, yy
+// accumulates s e^{-kappa r}/r + D.grad_y(e^{-kappa r}/r).
+template <typename T, bool GUARD, bool FUSED>
+__device__ __forceinline__ void p2p_pair(const SrcRec<T>& s, T tx, T ty, T tz, T kappa, T ck, T& l, T& yy) {
+  const T dx = tx - s.v[0], dy = ty - s.v[1], dz = tz - s.v[2];
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  T rinv = KMath<T>::rsq(r2);
+  if (GUARD) rinv = r2 > T(0) ? rinv : T(0);
+  const T dd = s.v[4] * dx + s.v[5] * dy + s.v[6] * dz;
+  const T t = dd * (rinv * rinv);            // D.(x-y)/r^2
+  if (FUSED) l += (s.v[7] - t) * rinv;       // s_L/r - D.(x-y)/r^3
+  const T rr = r2 * rinv;
+  const T gy = KMath<T>::expk(rr, ck) * rinv;
+  const T f = kappa * rr + T(1);
+  yy += gy * (t * f + s.v[3]);               // s G_Y + D.grad_y G_Y
+}
+
+template <typename T, bool GUARD, bool FUSED>
+__device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int cnt, T tx, T ty, T tz, T kappa, T ck,
+                                         T& l, T& yy) {
+  int j = 0;
+  for (; j + 8 <= cnt; j += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) p2p_pair<T, GUARD, FUSED>(tile[j + q], tx, ty, tz, kappa, ck, l, yy);
+  }
+  for (; j < cnt; ++j) p2p_pair<T, GUARD, FUSED>(tile[j], tx, ty, tz, kappa, ck, l, yy);
+}
+
+// One wavefront per task, one target per lane.  The task's source ranges
+// are staged, 64 records at a time, into the wave's own LDS tile with one
+// coalesced load per lane; every lane then reads the same record (an LDS
+// broadcast), so the loads of successive records pipeline in order.
 template <typename T, bool GUARD>
 __global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int ntasks,
                                              const int32_t* __restrict__ ranges,
                                              const T* __restrict__ tgt, const T* __restrict__ src,
                                              T kappa, T* __restrict__ partial) {
+  __shared__ SrcRec<T> tiles[4][64];
   const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
   if (wv >= ntasks) return;
   const int lane = threadIdx.x & 63;
+  SrcRec<T>* tile = tiles[threadIdx.x >> 6];
+  const SrcRec<T>* srec = reinterpret_cast<const SrcRec<T>*>(src);
   const int tbeg = tasks[wv].tbeg, tcount = tasks[wv].tcount;
   const int lbeg = tasks[wv].lbeg, lend = tasks[wv].lend;
   const int fused = tasks[wv].fused;
@@ -104,40 +180,23 @@ __global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int
   const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
   const T ck = KMath<T>::expk_const(kappa);
   T l = 0, yy = 0;
-  for (int r = lbeg; r < lend; ++r) {
-    const int j0 = ranges[2 * r], j1 = ranges[2 * r + 1];
-    if (fused) {
-#pragma unroll 4
-      for (int j = j0; j < j1; ++j) {
-        const T* s = src + (int64_t)kSrcStride * j;
-        const T dx = tx - s[0], dy = ty - s[1], dz = tz - s[2];
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        T rinv = KMath<T>::rsq(r2);
-        if (GUARD) rinv = r2 > T(0) ? rinv : T(0);
-        const T dd = s[4] * dx + s[5] * dy + s[6] * dz;
-        const T t = dd * (rinv * rinv);            // D.(x-y)/r^2
-        l += (s[7] - t) * rinv;                    // s_L/r - D.(x-y)/r^3
-        const T rr = r2 * rinv;
-        const T gy = KMath<T>::expk(rr, ck) * rinv;
-        const T f = kappa * rr + T(1);
-        yy += gy * (t * f + s[3]);                 // s G_Y + D.grad_y G_Y
-      }
-    } else {
-#pragma unroll 4
-      for (int j = j0; j < j1; ++j) {
-        const T* s = src + (int64_t)kSrcStride * j;
-        const T dx = tx - s[0], dy = ty - s[1], dz = tz - s[2];
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        T rinv = KMath<T>::rsq(r2);
-        if (GUARD) rinv = r2 > T(0) ? rinv : T(0);
-        const T dd = s[4] * dx + s[5] * dy + s[6] * dz;
-        const T t = dd * (rinv * rinv);
-        const T rr = r2 * rinv;
-        const T gy = KMath<T>::expk(rr, ck) * rinv;
-        const T f = kappa * rr + T(1);
-        yy += gy * (t * f + s[3]);
-      }
+  int r = lbeg;
+  int cur = r < lend ? ranges[2 * r] : 0;
+  while (r < lend) {
+    // fill: up to 64 records from the remaining ranges, in order
+    int cnt = 0;
+    while (r < lend && cnt < 64) {
+      const int end = ranges[2 * r + 1];
+      const int take = min(end - cur, 64 - cnt);
+      if (lane >= cnt && lane < cnt + take) tile[lane] = srec[cur + (lane - cnt)];
+      cnt += take;
+      cur += take;
+      if (cur == end && ++r < lend) cur = ranges[2 * r];
     }
+    wave_lds_sync();
+    if (fused) p2p_tile<T, GUARD, true>(tile, cnt, tx, ty, tz, kappa, ck, l, yy);
+    else p2p_tile<T, GUARD, false>(tile, cnt, tx, ty, tz, kappa, ck, l, yy);
+    wave_lds_sync();
   }
   if (lane < tcount) {
     const int slot = tasks[wv].slot;
@@ -258,6 +317,15 @@ void launch_strengths(int64_t ns, int K, const double* sig, const double* mu, co
 }
 
 template <typename T>
+void launch_strengths_x(int64_t ns, int K, const PanelMaps& m, const double* x, const double* src_wa,
+                        const double* nrm, const double* rlap, double* sig, double* mu, T* src,
+                        hipStream_t s) {
+  if (ns <= 0) return;
+  k_strengths_x<T><<<nblocks(ns, 256), 256, 0, s>>>(ns, K, m, x, src_wa, nrm, rlap, sig, mu, src);
+  PBT_HIP(hipGetLastError());
+}
+
+template <typename T>
 void launch_p2p(const Task* tasks, int ntasks, const int32_t* ranges, const T* tgt, const T* src,
                 T kappa, bool guard, T* partial, hipStream_t s) {
   if (ntasks <= 0) return;
@@ -280,6 +348,10 @@ template void launch_strengths<float>(int64_t, int, const double*, const double*
                                       const double*, const double*, float*, hipStream_t);
 template void launch_strengths<double>(int64_t, int, const double*, const double*, const double*,
                                        const double*, const double*, double*, hipStream_t);
+template void launch_strengths_x<float>(int64_t, int, const PanelMaps&, const double*, const double*,
+                                        const double*, const double*, double*, double*, float*, hipStream_t);
+template void launch_strengths_x<double>(int64_t, int, const PanelMaps&, const double*, const double*,
+                                         const double*, const double*, double*, double*, double*, hipStream_t);
 template void launch_p2p<float>(const Task*, int, const int32_t*, const float*, const float*, float,
                                 bool, float*, hipStream_t);
 template void launch_p2p<double>(const Task*, int, const int32_t*, const double*, const double*,

@@ -109,6 +109,10 @@ template <typename T>
 void launch_strengths(int64_t ns, int K, const double* sig, const double* mu, const double* src_wa,
                       const double* nrm, const double* rlap, T* src, hipStream_t s);
 template <typename T>
+void launch_strengths_x(int64_t ns, int K, const PanelMaps& m, const double* x, const double* src_wa,
+                        const double* nrm, const double* rlap, double* sig, double* mu, T* src,
+                        hipStream_t s);
+template <typename T>
 void launch_p2p(const Task* tasks, int ntasks, const int32_t* ranges, const T* tgt, const T* src,
                 T kappa, bool guard, T* partial, hipStream_t s);
 struct CombineArgs {
@@ -193,6 +197,12 @@ void launch_multi_axpy(int64_t n, int m, const double* V, int64_t ldv, const dou
                        hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_normalize(int64_t n, const double* nrm2, const double* x, double* y, hipStream_t s);
+void launch_pdots(int64_t n, int m, const double* V, int64_t ldv, const double* hin, double* w, int self_dot,
+                  double* part, int nblk, hipStream_t s);
+void launch_update_normalize(int64_t n, int m, const double* V, int64_t ldv, const double* h,
+                             const double* nrm2, double* w, hipStream_t s);
+void launch_givens(int j, int m, const double* h1, const double* h2, const double* hn2, double* H, double* cs,
+                   double* sn, double* g, double* resid, hipStream_t s);
 void launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
 void launch_lincomb(int64_t n, int m, const double* V, int64_t ldv, const double* c, double* y,
                     hipStream_t s);

@@ -28,11 +28,16 @@ System::System(const std::vector<const SurfIn*>& surfs, const pbt_params& prm, d
                double kappa, hipStream_t stream)
     : surfs_(surfs), prm_(prm), eps_out_(eps_out), kappa_(kappa), K_(prm.k_far) {
   for (auto& e : ev_) PBT_HIP(hipEventCreate(&e));
+  for (auto& e : evm_) PBT_HIP(hipEventCreate(&e));
+  PBT_HIP(hipStreamCreate(&s2_));
   build(stream);
 }
 
 System::~System() {
+  if (s2_) (void)hipStreamSynchronize(s2_);
   for (auto& e : ev_) (void)hipEventDestroy(e);
+  for (auto& e : evm_) (void)hipEventDestroy(e);
+  if (s2_) (void)hipStreamDestroy(s2_);
 }
 
 int System::local_index(int surface_id) const { return surface_id; }
@@ -450,35 +455,57 @@ void System::build_plan() {
   }
 }
 
+// Strengths, then P2P on the caller's stream while the far field (P2M,
+// M2M, M2P) runs on the system's second stream; the two write disjoint
+// partial slots and join before the combine.
 template <typename T>
-void System::interactions(hipStream_t s) {
+void System::interactions(hipStream_t s, const double* x, bool timed) {
   const bool f32 = std::is_same<T, float>::value;
   T* src = f32 ? (T*)src32_.p : (T*)src64_.p;
   const T* tgt = f32 ? (const T*)tgt32_.p : (const T*)tgt64_.p;
   T* part = f32 ? (T*)part32_.p : (T*)part64_.p;
   T* mom = f32 ? (T*)mom32_.p : (T*)mom64_.p;
-  launch_strengths<T>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, rlap_.p, src, s);
-  PBT_HIP(hipEventRecord(ev_[1], s));
-  if (!plan_.m2p.empty()) {
-    BoxDev bd{bcen_.p, bsbeg_.p, bsend_.p, bcbeg_.p, bcend_.p, bclist_.p, brho_.p};
-    launch_p2m<T>(prm_.taylor_p, nleaf_, leaf_boxes_.p, bd, src, mom, s);
-    for (auto lv : m2m_levels_) launch_m2m<T>(prm_.taylor_p, lv.second, m2m_boxes_.p + lv.first, bd, mom, s);
+  if (x) {
+    PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
+    launch_strengths_x<T>(ns_, K_, m, x, src_wa_.p, nrm_.p, rlap_.p, sig_.p, mu_.p, src, s);
+  } else {
+    launch_strengths<T>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, rlap_.p, src, s);
   }
-  PBT_HIP(hipEventRecord(ev_[2], s));
+  const bool far = !plan_.m2p.empty();
+  const bool two = far && overlap_;
+  if (timed || two) PBT_HIP(hipEventRecord(ev_[1], s));
   const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
+  auto far_field = [&](hipStream_t fs) {
+    if (timed) PBT_HIP(hipEventRecord(evm_[0], fs));
+    BoxDev bd{bcen_.p, bsbeg_.p, bsend_.p, bcbeg_.p, bcend_.p, bclist_.p, brho_.p};
+    launch_p2m<T>(prm_.taylor_p, nleaf_, leaf_boxes_.p, bd, src, mom, fs);
+    for (auto lv : m2m_levels_) launch_m2m<T>(prm_.taylor_p, lv.second, m2m_boxes_.p + lv.first, bd, mom, fs);
+    if (timed) PBT_HIP(hipEventRecord(evm_[1], fs));
+    launch_m2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, tgt, bcen_.p, mom, (T)kappa_,
+                  part, fs);
+    if (timed || two) PBT_HIP(hipEventRecord(evm_[2], fs));
+  };
+  if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
   launch_p2p<T>(dp2p_.p, (int)plan_.p2p.size(), dranges_.p, tgt, src, (T)kappa_, guard, part, s);
-  PBT_HIP(hipEventRecord(ev_[3], s));
-  if (!plan_.m2p.empty())
-    launch_m2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, tgt, bcen_.p, mom,
-                  (T)kappa_, part, s);
-  PBT_HIP(hipEventRecord(ev_[4], s));
+  if (timed) PBT_HIP(hipEventRecord(ev_[3], s));
+  if (two) {
+    // P2P (already queued) and the far field on the second stream overlap
+    PBT_HIP(hipStreamWaitEvent(s2_, ev_[1], 0));
+    far_field(s2_);
+    PBT_HIP(hipStreamWaitEvent(s, evm_[2], 0));
+  } else if (far) {
+    far_field(s);
+  }
+  if (timed) PBT_HIP(hipEventRecord(ev_[4], s));
+  far_timed_ = far && timed;
 }
 
-void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s) {
+void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x,
+                   bool timed) {
   ++napply_;
-  PBT_HIP(hipEventRecord(ev_[0], s));
-  if (fp32) interactions<float>(s);
-  else interactions<double>(s);
+  if (timed) PBT_HIP(hipEventRecord(ev_[0], s));
+  if (fp32) interactions<float>(s, from_x ? x : nullptr, timed);
+  else interactions<double>(s, from_x ? x : nullptr, timed);
   CombineArgs a{};
   a.np = np_;
   a.chunks = dchunks_.p;
@@ -494,27 +521,30 @@ void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStre
   a.add_jump = add_jump ? 1 : 0;
   if (fp32) launch_combine<float>(a, part32_.p, y, s);
   else launch_combine<double>(a, part64_.p, y, s);
-  PBT_HIP(hipEventRecord(ev_[5], s));
+  if (timed) PBT_HIP(hipEventRecord(ev_[5], s));
 }
 
 void System::timing(double out[5]) {
   PBT_HIP(hipEventSynchronize(ev_[5]));
-  float t[5] = {0, 0, 0, 0, 0};
+  float t[5] = {0, 0, 0, 0, 0}, a = 0, b = 0;
   PBT_HIP(hipEventElapsedTime(&t[0], ev_[0], ev_[5]));
   PBT_HIP(hipEventElapsedTime(&t[1], ev_[2], ev_[3]));
-  PBT_HIP(hipEventElapsedTime(&t[2], ev_[3], ev_[4]));
-  PBT_HIP(hipEventElapsedTime(&t[3], ev_[1], ev_[2]));
+  if (far_timed_) {
+    PBT_HIP(hipEventSynchronize(evm_[2]));
+    PBT_HIP(hipEventElapsedTime(&t[2], evm_[1], evm_[2]));
+    PBT_HIP(hipEventElapsedTime(&t[3], evm_[0], evm_[1]));
+  }
+  PBT_HIP(hipEventElapsedTime(&a, ev_[0], ev_[1]));
+  PBT_HIP(hipEventElapsedTime(&b, ev_[4], ev_[5]));
   out[0] = t[0];
   out[1] = t[1];
   out[2] = t[2];
   out[3] = t[3];
-  out[4] = t[0] - t[1] - t[2] - t[3];
+  out[4] = a + b;   // strengths + combine (P2P and the far field overlap)
 }
 
-void System::matvec(const double* x, double* y, bool fp32, hipStream_t s) {
-  PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
-  launch_densities(np_, m, x, sig_.p, mu_.p, s);
-  apply(fp32, true, x, y, s);
+void System::matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed) {
+  apply(fp32, true, x, y, s, true, timed);
 }
 
 void System::rhs(double* b, hipStream_t s) {
@@ -573,15 +603,18 @@ void System::true_residual(const double* b, const double* x, double* r, hipStrea
   launch_axpby(n_, 1.0, b, -1.0, r, s);  // r = b - A x
 }
 
-// Restarted GMRES with classical Gram-Schmidt applied twice; Hessenberg
-// matrix and Givens rotations on the host.  Stops when the estimated
-// residual norm <= tol_abs.  Returns the iteration count.
+// Restarted GMRES with classical Gram-Schmidt applied twice.  Everything of
+// an Arnoldi step runs on the device, including the Hessenberg column and
+// its Givens rotation, which leaves the residual estimate |g_{j+1}| in
+// resid[j]; the host enqueues several steps ahead and reads the estimates
+// back once per group, so the GPU does not wait on the host between steps.
+// Steps enqueued past convergence are discarded (the solution uses the
+// columns up to the first estimate <= tol_abs).  Returns the iterations used.
 int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
                   int maxit, double* resid_out, hipStream_t s) {
   const int m = restart;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(2 * (m + 1) + 1), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), y(m), rs(m);
   int iters = 0;
-  // r = b - A x
   if (x_zero) PBT_HIP(hipMemcpyAsync(r_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
   else {
     op(x, r_.p, fp32, s);
@@ -589,58 +622,73 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol
   }
   double beta = norm(r_.p, s);
   *resid_out = beta;
+  double* dH = gm_.p;
+  double* dcs = dH + (size_t)(m + 1) * m;
+  double* dsn = dcs + m;
+  double* dg = dsn + m;
+  double* dres = dg + (m + 1);
   while (beta > tol_abs && iters < maxit) {
     launch_scale_copy(n_, 1.0 / beta, r_.p, V_.p, s);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int j = 0;
-    for (; j < m && iters < maxit; ++j) {
-      double* vj1 = V_.p + (size_t)(j + 1) * n_;
-      op(V_.p + (size_t)j * n_, vj1, fp32, s);
-      // CGS2: two projections against V_0..V_j, then |w|^2, all on the
-      // device; one copy of (h1, h2, |w|^2) to the host per Arnoldi step.
-      for (int pass = 0; pass < 2; ++pass) {
-        double* hp = hdev_.p + pass * (m + 1);
-        launch_multidot(n_, j + 1, V_.p, n_, vj1, part_.p, mdb_, s);
-        launch_reduce_cols(j + 1, mdb_, part_.p, hp, s);
-        launch_multi_axpy(n_, j + 1, V_.p, n_, hp, vj1, s);
+    PBT_HIP(hipMemcpyAsync(dg, g.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+    int j = 0, used = 0;
+    bool done = false;
+    while (j < m && iters + j < maxit && !done) {
+      // enqueue a group of Arnoldi steps sized by the observed convergence
+      // rate (predicted steps to the tolerance, 1..8)
+      int want = 2;
+      if (j >= 2) {
+        const int d = std::min(j, 4);
+        const double r1 = std::max(rs[j - 1], 1e-300), r0 = std::max(rs[j - 1 - d], 1e-300);
+        const double rate = std::pow(r1 / r0, 1.0 / d);
+        if (rate < 0.999) {
+          const double need = std::log(tol_abs / r1) / std::log(rate);
+          want = (int)std::min(8.0, std::max(1.0, std::ceil(need)));
+        } else {
+          want = 4;
+        }
       }
-      double* hn2 = hdev_.p + 2 * (m + 1);
-      launch_multidot(n_, 1, vj1, n_, vj1, part_.p, mdb_, s);
-      launch_reduce_cols(1, mdb_, part_.p, hn2, s);
-      launch_normalize(n_, hn2, vj1, vj1, s);
-      PBT_HIP(hipMemcpyAsync(h.data(), hdev_.p, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      const int group = std::min({want, m - j, maxit - iters - j});
+      for (int k = j; k < j + group; ++k) {
+        double* vj1 = V_.p + (size_t)(k + 1) * n_;
+        op(V_.p + (size_t)k * n_, vj1, fp32, s);
+        double* h1 = hdev_.p;
+        double* h2 = hdev_.p + (m + 1);
+        double* hn2 = hdev_.p + 2 * (m + 1);
+        // pass 1: h1 = V^T w; pass 2: w' = w - V h1, h2 = V^T w', |w'|^2;
+        // then H column and rotation; then w = (w' - V h2) / |w''|
+        launch_pdots(n_, k + 1, V_.p, n_, nullptr, vj1, 0, part_.p, pdb_, s);
+        launch_reduce_cols(k + 1, pdb_, part_.p, h1, s);
+        launch_pdots(n_, k + 1, V_.p, n_, h1, vj1, 1, part_.p, pdb_, s);
+        launch_reduce_cols(k + 2, pdb_, part_.p, h2, s);
+        launch_givens(k, m, h1, h2, h2 + (k + 1), dH, dcs, dsn, dg, dres, s);
+        launch_update_normalize(n_, k + 1, V_.p, n_, h2, dres + m, vj1, s);
+      }
+      PBT_HIP(hipMemcpyAsync(rs.data() + j, dres + j, group * sizeof(double), hipMemcpyDeviceToHost, s));
       PBT_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h[(m + 1) + i];
-      const double hn = std::sqrt(std::max(h[2 * (m + 1)], 0.0));
-      H[(size_t)(j + 1) * m + j] = hn;
-      ++iters;
-      for (int i = 0; i < j; ++i) {
-        const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+      for (int k = j; k < j + group; ++k) {
+        used = k + 1;
+        *resid_out = rs[k];
+        if (rs[k] <= tol_abs) { done = true; break; }
       }
-      const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
-      const double den = std::hypot(a, bb);
-      cs[j] = den > 0 ? a / den : 1.0;
-      sn[j] = den > 0 ? bb / den : 0.0;
-      H[(size_t)j * m + j] = den;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      *resid_out = std::fabs(g[j + 1]);
-      if (!(hn > 0) || *resid_out <= tol_abs) { ++j; break; }
+      nwasted_ += (j + group) - used;
+      j += group;
     }
-    // x += V y with H(0:j,0:j) y = g(0:j)
-    for (int i = j - 1; i >= 0; --i) {
+    iters += used;
+    // x += V y with H(0:used,0:used) y = g(0:used)
+    PBT_HIP(hipMemcpyAsync(H.data(), dH, (size_t)(m + 1) * m * sizeof(double), hipMemcpyDeviceToHost, s));
+    PBT_HIP(hipMemcpyAsync(g.data(), dg, (m + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    PBT_HIP(hipStreamSynchronize(s));
+    for (int i = used - 1; i >= 0; --i) {
       double acc = g[i];
-      for (int k = i + 1; k < j; ++k) acc -= H[(size_t)i * m + k] * y[k];
+      for (int k = i + 1; k < used; ++k) acc -= H[(size_t)i * m + k] * y[k];
       y[i] = acc / H[(size_t)i * m + i];
     }
-    PBT_HIP(hipMemcpyAsync(hdev_.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_lincomb(n_, j, V_.p, n_, hdev_.p, x, s);
+    PBT_HIP(hipMemcpyAsync(hdev_.p, y.data(), used * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_lincomb(n_, used, V_.p, n_, hdev_.p, x, s);
     PBT_HIP(hipStreamSynchronize(s));
-    if (*resid_out <= tol_abs || iters >= maxit) break;
+    if (done || iters >= maxit) break;
     op(x, r_.p, fp32, s);
     launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
     beta = norm(r_.p, s);
@@ -673,8 +721,10 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
   tmp_.alloc(n_);
   y_.alloc(n_);
   mdb_ = multidot_blocks(n_);
-  part_.alloc((size_t)(m + 2) * mdb_);
+  pdb_ = (int)std::min<int64_t>(240, std::max<int64_t>(1, (n_ + 255) / 256));
+  part_.alloc((size_t)(m + 2) * std::max(mdb_, pdb_));
   hdev_.alloc(2 * (m + 1) + 2);
+  gm_.alloc((size_t)(m + 1) * m + 4 * (m + 1) + 4);
   if (!x0_given) PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));
   const double bnorm = norm(b, s);
   res->iters = 0;

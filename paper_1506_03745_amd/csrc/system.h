@@ -98,8 +98,9 @@ class System {
   int64_t dense_pairs() const { return np_ * ns_; }
   const Plan& plan() const { return plan_; }
 
-  // y = A x on device buffers (n doubles each), FP64 or FP32 interactions.
-  void matvec(const double* x, double* y, bool fp32, hipStream_t s);
+  // y = A x on device buffers (n doubles each), FP64 or FP32 interactions;
+  // `timed` records the per-phase events read by timing().
+  void matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed = false);
   // FP64 right-hand side for the current charges and boundary values.
   void rhs(double* b_dev, hipStream_t s);
   // Solves A x = b (b, x device); returns result fields (iters, outer,
@@ -140,17 +141,24 @@ class System {
   int n_surfaces() const { return (int)surfs_.size(); }
 
   // Milliseconds of the last operator application: total, P2P, M2P,
-  // moments (strengths, P2M, M2M), rest (densities, combine).
+  // moments (P2M, M2M), and strengths + combine; P2P and the far field
+  // (moments, M2P) run concurrently on two streams.
   void timing(double out[5]);
-  // Operator applications since construction (every matvec and rhs pass).
-  int64_t applications() const { return napply_; }
+  // Operator applications since construction (every matvec and rhs pass),
+  // not counting speculative Arnoldi steps discarded after convergence.
+  int64_t applications() const { return napply_ - nwasted_; }
+  // Run the far field (moments, M2P) on a second stream, concurrently with
+  // P2P (true), or after it on the caller's stream (false).
+  void set_overlap(bool on) { overlap_ = on; }
+  bool overlap() const { return overlap_; }
 
  private:
   void build(hipStream_t s);
   void build_plan();
-  void apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s);
+  void apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x = false,
+             bool timed = false);
   template <typename T>
-  void interactions(hipStream_t s);
+  void interactions(hipStream_t s, const double* x, bool timed);
   int gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
             int maxit, double* resid_out, hipStream_t s);
   void true_residual(const double* b, const double* x, double* r, hipStream_t s);
@@ -217,12 +225,16 @@ class System {
 
   // Krylov workspace
   int restart_alloc_ = 0;
-  DBuf<double> V_, w_, r_, tmp_, hdev_, part_, y_;
-  int mdb_ = 1;
+  DBuf<double> V_, w_, r_, tmp_, hdev_, part_, y_, gm_;
+  int mdb_ = 1, pdb_ = 1;
 
   hipEvent_t ev_[6];
-  int64_t napply_ = 0;
+  hipStream_t s2_ = nullptr;   // far-field stream (moments, M2P), overlaps P2P
+  hipEvent_t evm_[3];          // on s2_: moments start, M2P start, M2P end
+  int64_t napply_ = 0, nwasted_ = 0;
+  bool overlap_ = false;
   bool transpose_ = false;
+  bool far_timed_ = false;
   int64_t seg_src_ = 0, seg_box_ = 0, seg_src_used_ = 0, seg_box_used_ = 0;
   void upload_plan(hipStream_t s);
 
