@@ -73,7 +73,7 @@ typedef struct {
   int32_t taylor_p;     /* Taylor order P, terms |k| <= P (default 6; 0..10) */
   double theta;         /* multipole acceptance, 0 < theta < 1 (default 0.5) */
   double tol;           /* GMRES relative residual ||b-Ax||/||b|| (default 1e-6) */
-  int32_t restart;      /* GMRES restart length (default 100) */
+  int32_t restart;      /* GMRES restart length, 1..1024 (default 100) */
   int32_t max_iter;     /* total GMRES iterations allowed (default 1000) */
   pbt_precision prec;   /* FP64 everywhere, or FP32 interactions + FP64 Krylov/refinement */
   int32_t treecode;     /* 1 = treecode matvec (default), 0 = direct sums over all pairs */

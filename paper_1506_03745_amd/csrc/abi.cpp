@@ -64,7 +64,7 @@ std::string check_params(const pbt_params& p) {
   if (p.taylor_p < 0 || p.taylor_p > kMaxP) return "taylor_p must be 0..8";
   if (!(p.theta > 0.0 && p.theta < 1.0)) return "theta must be in (0, 1)";
   if (!(p.tol > 0.0)) return "tol must be > 0";
-  if (p.restart < 1) return "restart must be >= 1";
+  if (p.restart < 1 || p.restart > 1024) return "restart must be 1..1024";
   if (p.max_iter < 1) return "max_iter must be >= 1";
   if (p.prec != PBT_FP64 && p.prec != PBT_MIXED) return "prec must be PBT_FP64 or PBT_MIXED";
   return "";

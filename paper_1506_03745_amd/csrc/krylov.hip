@@ -3,6 +3,8 @@
 // applied twice), multi-vector updates and linear combinations.
 #include "pbt_internal.h"
 
+#include <algorithm>
+
 namespace pbt {
 
 namespace {
@@ -46,33 +48,99 @@ __global__ __launch_bounds__(kBS) void k_multidot(int64_t n, int m, const double
   }
 }
 
-// Arnoldi column j of the Hessenberg matrix from the two Gram-Schmidt passes
-// (h1 + h2) and |w'|^2 (w' = w after the first pass), the previous Givens
-// rotations applied, a new rotation computed and the residual estimate
-// |g_{j+1}| stored in resid[j]; resid[m] receives |w''|^2 for the
-// normalisation.  The wavefront stages the column and the rotations in LDS;
-// lane 0 then applies the rotations in order (at most restart + 1 entries).
-__global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __restrict__ h1,
-                                               const double* __restrict__ h2, const double* __restrict__ hn2,
-                                               double* H, double* cs, double* sn, double* g, double* resid) {
-  extern __shared__ double sh[];   // col[m + 1], c[m], s[m]
-  double* col = sh;
-  double* c = sh + (m + 1);
-  double* sv = c + m;
-  for (int i = threadIdx.x; i <= j; i += 64) {
-    col[i] = h1[i] + h2[i];
-    if (i < j) {
-      c[i] = cs[i];
-      sv[i] = sn[i];
+// Block-partial dot products of one Gram-Schmidt pass.  Grid (nbj, nci):
+// blockIdx.x strides over the elements, blockIdx.y picks 8 consecutive
+// outputs i0..i0+7 of V_0..V_{m-1} (and w.w as output m when self_dot).
+// UPDATE: the block first adds up the partials of the previous pass, hpart
+// (m rows of nbj, fixed order, so every block gets the same h bitwise), and
+// dots with w' = w - sum_i h_i V_i formed in registers (w is not written);
+// block (0, 0) stores that h in hout.
+template <bool UPDATE>
+__global__ __launch_bounds__(kBS) void k_gs_dots(int64_t n, int m, const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ w, const double* __restrict__ hpart,
+                                                 double* __restrict__ hout, int self_dot,
+                                                 double* __restrict__ part) {
+  extern __shared__ double hs[];   // [m] (UPDATE)
+  __shared__ double red[kBS / 64][8];
+  const int nbj = gridDim.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (UPDATE) {
+    for (int i = wid; i < m; i += kBS / 64) {
+      double sq = 0;
+      for (int b = lane; b < nbj; b += 64) sq += hpart[(int64_t)i * nbj + b];
+      sq = wave_sum(sq);
+      if (lane == 0) {
+        hs[i] = sq;
+        if (blockIdx.x == 0 && blockIdx.y == 0) hout[i] = sq;
+      }
     }
+    __syncthreads();
+  }
+  const int i0 = blockIdx.y * 8;
+  const int mq = m + (self_dot ? 1 : 0);
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t j = blockIdx.x * (int64_t)kBS + threadIdx.x; j < n; j += (int64_t)nbj * kBS) {
+    double wj = w[j];
+    if (UPDATE) {
+#pragma unroll 8
+      for (int i = 0; i < m; ++i) wj -= hs[i] * V[(int64_t)i * ldv + j];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q;
+      if (i < mq) acc[q] += (i < m ? V[(int64_t)i * ldv + j] : wj) * wj;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double sq = wave_sum(acc[q]);
+    if (lane == 0) red[wid][q] = sq;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && i0 + (int)threadIdx.x < mq) {
+    double sq = 0;
+    for (int k = 0; k < kBS / 64; ++k) sq += red[k][threadIdx.x];
+    part[(int64_t)(i0 + threadIdx.x) * nbj + blockIdx.x] = sq;
+  }
+}
+
+// Arnoldi column j of the Hessenberg matrix: adds up the second pass's
+// partials (h2 and |w'|^2, j + 2 rows of nbj), forms h = h1 + h2 and
+// |w''|^2 = |w'|^2 - |h2|^2 (w'' = w' - V h2 with V orthonormal), applies
+// the previous Givens rotations, computes the new one and stores the
+// residual estimate |g_{j+1}| in resid[j].  Also writes h (hsum) and
+// |w''|^2 (nrm2) for the update and normalisation of w.
+__global__ __launch_bounds__(kBS) void k_arnoldi_col(int j, int m, int nbj, const double* __restrict__ part,
+                                                     const double* __restrict__ h1, double* H, double* cs,
+                                                     double* sn, double* g, double* resid,
+                                                     double* __restrict__ hsum, double* __restrict__ nrm2) {
+  extern __shared__ double sh[];   // col[m + 1], h2[m + 1], c[m], s[m]
+  double* col = sh;
+  double* h2 = sh + (m + 1);
+  double* c = h2 + (m + 1);
+  double* sv = c + m;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = wid; i <= j + 1; i += kBS / 64) {
+    double sq = 0;
+    for (int b = lane; b < nbj; b += 64) sq += part[(int64_t)i * nbj + b];
+    sq = wave_sum(sq);
+    if (lane == 0) h2[i] = sq;
+  }
+  for (int i = threadIdx.x; i < j; i += kBS) {
+    c[i] = cs[i];
+    sv[i] = sn[i];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += kBS) {
+    col[i] = h1[i] + h2[i];
+    hsum[i] = col[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    // |w''|^2 = |w'|^2 - |h2|^2 (w'' = w' - V h2, V orthonormal)
     double h2s = 0.0;
     for (int i = 0; i <= j; ++i) h2s += h2[i] * h2[i];
-    const double nn = fmax(*hn2 - h2s, 0.0);
-    resid[m] = nn;        // |w''|^2 for the normalisation kernel
+    const double nn = fmax(h2[j + 1] - h2s, 0.0);
+    *nrm2 = nn;
     const double hn = sqrt(nn);
     col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
@@ -93,51 +161,7 @@ __global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __res
     resid[j] = hn > 0 ? fabs(sj * gj) : 0.0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i <= j + 1; i += 64) H[(size_t)i * m + j] = col[i];
-}
-
-// Partial sums, per block, of the dots of w with V_0..V_{m-1} and, if
-// self_dot, of w.w (output index m); optionally after w -= sum_i hin_i V_i
-// (each thread updates and then reads only its own elements).
-__global__ __launch_bounds__(kBS) void k_pdots(int64_t n, int m, const double* __restrict__ V, int64_t ldv,
-                                               const double* __restrict__ hin, double* __restrict__ w,
-                                               int self_dot, double* __restrict__ part) {
-  __shared__ double red[kBS / 64][8];
-  const int nblk = gridDim.x;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t stride = (int64_t)nblk * kBS;
-  if (hin) {
-    for (int64_t j = blockIdx.x * (int64_t)kBS + threadIdx.x; j < n; j += stride) {
-      double sj = w[j];
-#pragma unroll 8
-      for (int i = 0; i < m; ++i) sj -= hin[i] * V[(int64_t)i * ldv + j];
-      w[j] = sj;
-    }
-  }
-  const int mq = m + (self_dot ? 1 : 0);
-  for (int i0 = 0; i0 < mq; i0 += 8) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t j = blockIdx.x * (int64_t)kBS + threadIdx.x; j < n; j += stride) {
-      const double wj = w[j];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = i0 + q;
-        if (i < mq) acc[q] += (i < m ? V[(int64_t)i * ldv + j] : wj) * wj;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double sq = wave_sum(acc[q]);
-      if (lane == 0) red[wid][q] = sq;
-    }
-    __syncthreads();
-    if (threadIdx.x < 8 && i0 + (int)threadIdx.x < mq) {
-      double sq = 0;
-      for (int k = 0; k < kBS / 64; ++k) sq += red[k][threadIdx.x];
-      part[(int64_t)(i0 + threadIdx.x) * nblk + blockIdx.x] = sq;
-    }
-    __syncthreads();
-  }
+  for (int i = threadIdx.x; i <= j + 1; i += kBS) H[(size_t)i * m + j] = col[i];
 }
 
 // w = (w - sum_i h_i V_i) / sqrt(*nrm2)  (the second Gram-Schmidt update
@@ -236,9 +260,23 @@ void launch_lincomb(int64_t n, int m, const double* V, int64_t ldv, const double
   PBT_HIP(hipGetLastError());
 }
 
-void launch_pdots(int64_t n, int m, const double* V, int64_t ldv, const double* hin, double* w, int self_dot,
-                  double* part, int nblk, hipStream_t s) {
-  k_pdots<<<nblk, kBS, 0, s>>>(n, m, V, ldv, hin, w, self_dot, part);
+int gs_blocks(int64_t n) { return (int)std::min<int64_t>(240, std::max<int64_t>(1, (n + kBS - 1) / kBS)); }
+
+void launch_gs_dots(int64_t n, int m, const double* V, int64_t ldv, const double* w, const double* hpart,
+                    double* hout, int self_dot, double* part, int nbj, hipStream_t s) {
+  const int mq = m + (self_dot ? 1 : 0);
+  const dim3 grid(nbj, (mq + 7) / 8);
+  if (hpart)
+    k_gs_dots<true><<<grid, kBS, (size_t)m * sizeof(double), s>>>(n, m, V, ldv, w, hpart, hout, self_dot, part);
+  else
+    k_gs_dots<false><<<grid, kBS, 0, s>>>(n, m, V, ldv, w, nullptr, nullptr, self_dot, part);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_arnoldi_col(int j, int m, int nbj, const double* part, const double* h1, double* H, double* cs,
+                        double* sn, double* g, double* resid, double* hsum, double* nrm2, hipStream_t s) {
+  k_arnoldi_col<<<1, kBS, (size_t)(4 * m + 2) * sizeof(double), s>>>(j, m, nbj, part, h1, H, cs, sn, g, resid,
+                                                                     hsum, nrm2);
   PBT_HIP(hipGetLastError());
 }
 
@@ -246,12 +284,6 @@ void launch_update_normalize(int64_t n, int m, const double* V, int64_t ldv, con
                              const double* nrm2, double* w, hipStream_t s) {
   if (n <= 0) return;
   k_update_normalize<<<nblocks(n, 256), 256, 0, s>>>(n, m, V, ldv, h, nrm2, w);
-  PBT_HIP(hipGetLastError());
-}
-
-void launch_givens(int j, int m, const double* h1, const double* h2, const double* hn2, double* H, double* cs,
-                   double* sn, double* g, double* resid, hipStream_t s) {
-  k_givens<<<1, 64, (size_t)(3 * m + 1) * sizeof(double), s>>>(j, m, h1, h2, hn2, H, cs, sn, g, resid);
   PBT_HIP(hipGetLastError());
 }
 

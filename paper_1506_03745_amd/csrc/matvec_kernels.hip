@@ -207,23 +207,25 @@ __global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int
 
 // Sum the partial slots of every target, scale by 1/(4 pi), add the near and
 // self corrections (sparse, FP64) and the 1/2 jump terms, and scatter into
-// the unknown layout.  Four lanes share a target (slots and near entries
-// interleaved) and combine with shuffles, to keep enough loads in flight.
+// the unknown layout.  One block per target chunk: lane = target within the
+// chunk (coalesced slot reads), the kCombineWaves waves split the chunk's
+// slots and each target's near entries, and add up through LDS.
+constexpr int kCombineWaves = 16;
 template <typename T>
-__global__ __launch_bounds__(256) void k_combine(CombineArgs a, const T* __restrict__ partial, double* y) {
-  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 2;
-  const int sub = threadIdx.x & 3;
-  const bool act = i < a.np;
+__global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, const T* __restrict__ partial,
+                                                              double* y) {
+  __shared__ double red[kCombineWaves][4][64];
+  const ChunkSlots cs = a.chunks[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool act = lane < cs.tcount;
+  const int64_t i = cs.tbeg + lane;
   double l = 0.0, yy = 0.0, nl = 0.0, ny = 0.0;
   if (act) {
-    const int c = a.chunk_of[i];
-    const ChunkSlots cs = a.chunks[c];
-    const int lane = (int)(i - cs.tbeg);
-    for (int s = cs.sbeg + sub; s < cs.send; s += 4) {
+    for (int s = cs.sbeg + w; s < cs.send; s += kCombineWaves) {
       l += (double)partial[2 * ((int64_t)s * 64 + lane) + 0];
       yy += (double)partial[2 * ((int64_t)s * 64 + lane) + 1];
     }
-    for (int64_t e = a.near_ptr[i] + sub; e < a.near_ptr[i + 1]; e += 4) {
+    for (int64_t e = a.near_ptr[i] + w; e < a.near_ptr[i + 1]; e += kCombineWaves) {
       const int32_t j = a.near_col[e];
       const double sj = a.sig[j], mj = a.mu[j];
       const double* v = a.near_val + 4 * e;
@@ -231,13 +233,19 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a, const T* __restr
       ny += v[2] * sj + v[3] * mj;
     }
   }
-  for (int o = 1; o < 4; o <<= 1) {
-    l += __shfl_xor(l, o, 64);
-    yy += __shfl_xor(yy, o, 64);
-    nl += __shfl_xor(nl, o, 64);
-    ny += __shfl_xor(ny, o, 64);
+  red[w][0][lane] = l;
+  red[w][1][lane] = yy;
+  red[w][2][lane] = nl;
+  red[w][3][lane] = ny;
+  __syncthreads();
+  if (w != 0 || !act) return;
+  l = yy = nl = ny = 0.0;
+  for (int k = 0; k < kCombineWaves; ++k) {
+    l += red[k][0][lane];
+    yy += red[k][1][lane];
+    nl += red[k][2][lane];
+    ny += red[k][3][lane];
   }
-  if (!act || sub != 0) return;
   l = l * kInv4Pi + nl;
   yy = yy * kInv4Pi + ny;
   const int32_t ri = a.maps.row_int[i];
@@ -339,8 +347,8 @@ void launch_p2p(const Task* tasks, int ntasks, const int32_t* ranges, const T* t
 
 template <typename T>
 void launch_combine(const CombineArgs& a, const T* partial, double* y, hipStream_t s) {
-  if (a.np <= 0) return;
-  k_combine<T><<<nblocks(4 * a.np, 256), 256, 0, s>>>(a, partial, y);
+  if (a.np <= 0 || a.nchunks <= 0) return;
+  k_combine<T><<<a.nchunks, 64 * kCombineWaves, 0, s>>>(a, partial, y);
   PBT_HIP(hipGetLastError());
 }
 

@@ -197,12 +197,17 @@ void launch_multi_axpy(int64_t n, int m, const double* V, int64_t ldv, const dou
                        hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_normalize(int64_t n, const double* nrm2, const double* x, double* y, hipStream_t s);
-void launch_pdots(int64_t n, int m, const double* V, int64_t ldv, const double* hin, double* w, int self_dot,
-                  double* part, int nblk, hipStream_t s);
+// One Arnoldi step's orthogonalisation (classical Gram-Schmidt applied
+// twice): partial dots (pass 1: hpart = null; pass 2: reduces pass 1's
+// partials into hout and dots with w - V h1), the Hessenberg column with its
+// Givens rotation, then w = (w - V (h1 + h2)) / |w''|.
+int gs_blocks(int64_t n);
+void launch_gs_dots(int64_t n, int m, const double* V, int64_t ldv, const double* w, const double* hpart,
+                    double* hout, int self_dot, double* part, int nbj, hipStream_t s);
+void launch_arnoldi_col(int j, int m, int nbj, const double* part, const double* h1, double* H, double* cs,
+                        double* sn, double* g, double* resid, double* hsum, double* nrm2, hipStream_t s);
 void launch_update_normalize(int64_t n, int m, const double* V, int64_t ldv, const double* h,
                              const double* nrm2, double* w, hipStream_t s);
-void launch_givens(int j, int m, const double* h1, const double* h2, const double* hn2, double* H, double* cs,
-                   double* sn, double* g, double* resid, hipStream_t s);
 void launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
 void launch_lincomb(int64_t n, int m, const double* V, int64_t ldv, const double* c, double* y,
                     hipStream_t s);

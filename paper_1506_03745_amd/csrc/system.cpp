@@ -654,16 +654,16 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol
         double* vj1 = V_.p + (size_t)(k + 1) * n_;
         op(V_.p + (size_t)k * n_, vj1, fp32, s);
         double* h1 = hdev_.p;
-        double* h2 = hdev_.p + (m + 1);
-        double* hn2 = hdev_.p + 2 * (m + 1);
-        // pass 1: h1 = V^T w; pass 2: w' = w - V h1, h2 = V^T w', |w'|^2;
-        // then H column and rotation; then w = (w' - V h2) / |w''|
-        launch_pdots(n_, k + 1, V_.p, n_, nullptr, vj1, 0, part_.p, pdb_, s);
-        launch_reduce_cols(k + 1, pdb_, part_.p, h1, s);
-        launch_pdots(n_, k + 1, V_.p, n_, h1, vj1, 1, part_.p, pdb_, s);
-        launch_reduce_cols(k + 2, pdb_, part_.p, h2, s);
-        launch_givens(k, m, h1, h2, h2 + (k + 1), dH, dcs, dsn, dg, dres, s);
-        launch_update_normalize(n_, k + 1, V_.p, n_, h2, dres + m, vj1, s);
+        double* hs = hdev_.p + (m + 1);
+        double* nrm2 = hdev_.p + 2 * (m + 1);
+        double* part1 = part_.p;
+        double* part2 = part_.p + (size_t)(m + 2) * pdb_;
+        // pass 1: partial V^T w; pass 2: h1 = sum of pass 1, partial V^T w'
+        // and |w'|^2 with w' = w - V h1; column, rotation; w = (w - V h) / |w''|
+        launch_gs_dots(n_, k + 1, V_.p, n_, vj1, nullptr, nullptr, 0, part1, pdb_, s);
+        launch_gs_dots(n_, k + 1, V_.p, n_, vj1, part1, h1, 1, part2, pdb_, s);
+        launch_arnoldi_col(k, m, pdb_, part2, h1, dH, dcs, dsn, dg, dres, hs, nrm2, s);
+        launch_update_normalize(n_, k + 1, V_.p, n_, hs, nrm2, vj1, s);
       }
       PBT_HIP(hipMemcpyAsync(rs.data() + j, dres + j, group * sizeof(double), hipMemcpyDeviceToHost, s));
       PBT_HIP(hipStreamSynchronize(s));
@@ -721,8 +721,8 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
   tmp_.alloc(n_);
   y_.alloc(n_);
   mdb_ = multidot_blocks(n_);
-  pdb_ = (int)std::min<int64_t>(240, std::max<int64_t>(1, (n_ + 255) / 256));
-  part_.alloc((size_t)(m + 2) * std::max(mdb_, pdb_));
+  pdb_ = gs_blocks(n_);
+  part_.alloc((size_t)(m + 2) * std::max(mdb_, 2 * pdb_));
   hdev_.alloc(2 * (m + 1) + 2);
   gm_.alloc((size_t)(m + 1) * m + 4 * (m + 1) + 4);
   if (!x0_given) PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));

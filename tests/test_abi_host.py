@@ -72,7 +72,7 @@ def test_invalid_rule_and_params_rejected_on_host():
     with pytest.raises(B.PbtError):
         P.quadrature_rule(5)
     for bad in (dict(theta=1.5), dict(theta=0.0), dict(taylor_p=12), dict(k_far=2), dict(k_near=6),
-                dict(ncrit=0), dict(tol=0.0), dict(restart=0)):
+                dict(ncrit=0), dict(tol=0.0), dict(restart=0), dict(restart=1025)):
         p = B.default_params()
         for k, v in bad.items():
             setattr(p, k, v)
