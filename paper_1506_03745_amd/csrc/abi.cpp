@@ -254,6 +254,7 @@ pbt_status pbt_set_bc(pbt_ctx* c, int32_t id, const double* bc) {
   for (int64_t t = 0; t < s.nt; ++t)
     if (!std::isfinite(bc[t])) return fail(c, PBT_E_INVALID, "non-finite boundary value");
   s.bc.assign(bc, bc + s.nt);
+  ++s.version;
   return PBT_OK;
 }
 
@@ -276,6 +277,7 @@ pbt_status pbt_set_charges(pbt_ctx* c, int32_t mol_id, double eps_in, const doub
   s.eps_in = eps_in;
   s.qxyz.assign(xyz, xyz + 3 * nq);
   s.q.assign(q, q + nq);
+  ++s.version;
   return PBT_OK;
 }
 

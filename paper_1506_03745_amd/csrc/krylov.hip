@@ -220,6 +220,11 @@ __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, doubl
   y[j] = a * x[j] + b * y[j];
 }
 
+__global__ void k_first_unit(int n, double beta, double* g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = i == 0 ? beta : 0.0;
+}
+
 __global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, double* y) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= n) return;
@@ -296,6 +301,12 @@ void launch_normalize(int64_t n, const double* nrm2, const double* x, double* y,
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
   if (n <= 0) return;
   k_axpby<<<nblocks(n, 256), 256, 0, s>>>(n, a, x, b, y);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_first_unit(int n, double beta, double* g, hipStream_t s) {
+  if (n <= 0) return;
+  k_first_unit<<<nblocks(n, 256), 256, 0, s>>>(n, beta, g);
   PBT_HIP(hipGetLastError());
 }
 

@@ -40,6 +40,17 @@ __global__ void k_known_densities(int64_t np, const double* __restrict__ ks,
   mu[p] = km[p];
 }
 
+// Solvent rows of the right-hand side: b = -(A k) - half, with A k the
+// operator applied to the known densities and half the imposed potential's
+// 1/2 jump (zero except on potential surfaces).
+__global__ void k_rhs_solvent(int64_t np, const int32_t* __restrict__ row_sol, const double* __restrict__ ak,
+                              const double* __restrict__ half, double* b) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int32_t r = row_sol[p];
+  b[r] = -ak[r] - half[p];
+}
+
 // Source record: (x, y, z, s, Dx, Dy, Dz, s_L) with s_L = -(eps_out/eps_s) s,
 // the single-layer strength of the interior (Laplace) row; rlap[p] holds
 // -(eps_out/eps_s) for molecule panels and 0 otherwise.
@@ -306,6 +317,13 @@ void launch_densities(int64_t np, const PanelMaps& m, const double* x, double* s
                       hipStream_t s) {
   if (np <= 0) return;
   k_densities<<<nblocks(np, 256), 256, 0, s>>>(np, m, x, sig, mu);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_rhs_solvent(int64_t np, const int32_t* row_sol, const double* ak, const double* half, double* b,
+                        hipStream_t s) {
+  if (np <= 0) return;
+  k_rhs_solvent<<<nblocks(np, 256), 256, 0, s>>>(np, row_sol, ak, half, b);
   PBT_HIP(hipGetLastError());
 }
 

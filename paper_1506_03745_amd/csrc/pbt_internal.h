@@ -209,6 +209,9 @@ void launch_arnoldi_col(int j, int m, int nbj, const double* part, const double*
 void launch_update_normalize(int64_t n, int m, const double* V, int64_t ldv, const double* h,
                              const double* nrm2, double* w, hipStream_t s);
 void launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
+void launch_first_unit(int n, double beta, double* g, hipStream_t s);   // g = beta e_1
+void launch_rhs_solvent(int64_t np, const int32_t* row_sol, const double* ak, const double* half, double* b,
+                        hipStream_t s);
 void launch_lincomb(int64_t n, int m, const double* V, int64_t ldv, const double* c, double* y,
                     hipStream_t s);
 int multidot_blocks(int64_t n);

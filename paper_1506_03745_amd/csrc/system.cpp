@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 
 #include "quadrature.h"
 
@@ -29,6 +30,7 @@ System::System(const std::vector<const SurfIn*>& surfs, const pbt_params& prm, d
     : surfs_(surfs), prm_(prm), eps_out_(eps_out), kappa_(kappa), K_(prm.k_far) {
   for (auto& e : ev_) PBT_HIP(hipEventCreate(&e));
   for (auto& e : evm_) PBT_HIP(hipEventCreate(&e));
+  for (auto& e : evg_) PBT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   PBT_HIP(hipStreamCreate(&s2_));
   build(stream);
 }
@@ -37,6 +39,7 @@ System::~System() {
   if (s2_) (void)hipStreamSynchronize(s2_);
   for (auto& e : ev_) (void)hipEventDestroy(e);
   for (auto& e : evm_) (void)hipEventDestroy(e);
+  for (auto& e : evg_) (void)hipEventDestroy(e);
   if (s2_) (void)hipStreamDestroy(s2_);
 }
 
@@ -547,8 +550,13 @@ void System::matvec(const double* x, double* y, bool fp32, hipStream_t s, bool t
   apply(fp32, true, x, y, s, true, timed);
 }
 
-void System::rhs(double* b, hipStream_t s) {
+// Known densities of the charged (sigma) and potential (phi0) surfaces, in
+// reduced units, and the 1/2 jump of the imposed potential.
+void System::ensure_known(hipStream_t s) {
   const int ns = (int)surfs_.size();
+  std::vector<uint64_t> ver(ns);
+  for (int e = 0; e < ns; ++e) ver[e] = surfs_[e]->version;
+  if (ver == known_ver_ && known_ks_.n == (size_t)np_) return;
   std::vector<double> ks(np_, 0.0), km(np_, 0.0), half(np_, 0.0);
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
@@ -562,40 +570,66 @@ void System::rhs(double* b, hipStream_t s) {
       }
     }
   }
-  DBuf<double> dks, dkm, yk;
-  dks.upload(ks, s);
-  dkm.upload(km, s);
-  yk.alloc(n_);
-  PBT_HIP(hipMemsetAsync(yk.p, 0, n_ * sizeof(double), s));
-  launch_known_densities(np_, dks.p, dkm.p, sig_.p, mu_.p, s);
-  apply(false, false, nullptr, yk.p, s);
-  std::vector<double> hy = yk.download(s);
-  std::vector<double> hb(n_, 0.0);
-  // solvent rows: move the known terms to the right-hand side
-  std::vector<int32_t> hrs = row_sol_.download(s);
-  for (int64_t g = 0; g < np_; ++g) hb[hrs[g]] = -hy[hrs[g]] - half[g];
-  PBT_HIP(hipMemcpyAsync(b, hb.data(), n_ * sizeof(double), hipMemcpyHostToDevice, s));
+  known_ks_.upload(ks, s);
+  known_km_.upload(km, s);
+  known_half_.upload(half, s);
+  known_ver_ = ver;
+}
+
+// Charges of molecule e on the device, their near-field correction rows and
+// the pairwise Coulomb sum, rebuilt when the charges change.
+System::ChargeData& System::charges(int e, hipStream_t s) {
+  if (qdata_.size() != surfs_.size()) {
+    qdata_.clear();
+    for (size_t k = 0; k < surfs_.size(); ++k) qdata_.push_back(std::make_unique<ChargeData>());
+  }
+  ChargeData& d = *qdata_[e];
+  const SurfIn& S = *surfs_[e];
+  if (d.version == S.version) return d;
+  const int64_t nq = (int64_t)S.q.size();
+  d.qx.upload(S.qxyz, s);
+  d.q.upload(S.q, s);
+  d.phi.alloc(nq);
+  if (nq > 0) charge_near(e, d.qx.p, nq, d.qn, s);
+  double c = 0;
+  for (int64_t k = 0; k < nq; ++k)
+    for (int64_t l = k + 1; l < nq; ++l) {
+      const double dx = S.qxyz[3 * k] - S.qxyz[3 * l], dy = S.qxyz[3 * k + 1] - S.qxyz[3 * l + 1],
+                   dz = S.qxyz[3 * k + 2] - S.qxyz[3 * l + 2];
+      c += S.q[k] * S.q[l] / std::sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  d.coulomb = c;
+  d.version = S.version;
+  return d;
+}
+
+// b = [interior rows: (1/eps_in) sum_k q_k G_L(x_i, x_k);  solvent rows:
+// minus the operator applied to the known densities, minus the imposed
+// potential's jump], all on the device.
+void System::rhs(double* b, hipStream_t s) {
+  ensure_known(s);
+  rhs_y_.alloc(n_);
+  launch_known_densities(np_, known_ks_.p, known_km_.p, sig_.p, mu_.p, s);
+  apply(false, false, nullptr, rhs_y_.p, s);
+  PBT_HIP(hipMemsetAsync(b, 0, n_ * sizeof(double), s));
+  launch_rhs_solvent(np_, row_sol_.p, rhs_y_.p, known_half_.p, b, s);
   // interior rows: Coulomb sum with 1/eps_in (eq. green_identity)
-  for (int e = 0; e < ns; ++e) {
+  for (int e = 0; e < (int)surfs_.size(); ++e) {
     const SurfIn& S = *surfs_[e];
     if (S.kind != PBT_MOLECULE || S.q.empty()) continue;
-    DBuf<double> qx, qq;
-    qx.upload(S.qxyz, s);
-    qq.upload(S.q, s);
-    launch_coulomb_rhs(S.nt, cen_.p + 3 * poff_[e], row_int_.p + poff_[e], (int64_t)S.q.size(), qx.p,
-                       qq.p, 1.0 / S.eps_in, b, s);
-    PBT_HIP(hipStreamSynchronize(s));
+    ChargeData& d = charges(e, s);
+    launch_coulomb_rhs(S.nt, cen_.p + 3 * poff_[e], row_int_.p + poff_[e], (int64_t)S.q.size(), d.qx.p,
+                       d.q.p, 1.0 / S.eps_in, b, s);
   }
-  PBT_HIP(hipStreamSynchronize(s));
 }
 
 double System::norm(const double* v, hipStream_t s) {
   launch_multidot(n_, 1, v, n_, v, part_.p, mdb_, s);
   launch_reduce_cols(1, mdb_, part_.p, hdev_.p, s);
-  double h = 0;
-  PBT_HIP(hipMemcpyAsync(&h, hdev_.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  hnorm_.alloc(1);
+  PBT_HIP(hipMemcpyAsync(hnorm_.p, hdev_.p, sizeof(double), hipMemcpyDeviceToHost, s));
   PBT_HIP(hipStreamSynchronize(s));
-  return std::sqrt(h);
+  return std::sqrt(hnorm_.p[0]);
 }
 
 void System::true_residual(const double* b, const double* x, double* r, hipStream_t s) {
@@ -606,14 +640,21 @@ void System::true_residual(const double* b, const double* x, double* r, hipStrea
 // Restarted GMRES with classical Gram-Schmidt applied twice.  Everything of
 // an Arnoldi step runs on the device, including the Hessenberg column and
 // its Givens rotation, which leaves the residual estimate |g_{j+1}| in
-// resid[j]; the host enqueues several steps ahead and reads the estimates
-// back once per group, so the GPU does not wait on the host between steps.
-// Steps enqueued past convergence are discarded (the solution uses the
-// columns up to the first estimate <= tol_abs).  Returns the iterations used.
+// resid[j].  The host enqueues groups of steps, sized from the observed
+// convergence rate, and keeps up to two groups in flight: it reads one
+// group's estimates (pinned memory, an event per group) while the next one
+// runs, so the GPU does not wait on the host between steps.  Steps enqueued
+// past convergence are discarded (the solution uses the columns up to the
+// first estimate <= tol_abs).  Returns the iterations used.
 int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
                   int maxit, double* resid_out, hipStream_t s) {
   const int m = restart;
-  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), y(m), rs(m);
+  // pinned layout: H rows [m * m], g [m + 1], y [m], rs [m]
+  hbuf_.alloc((size_t)m * m + 3 * (size_t)m + 1);
+  double* hH = hbuf_.p;
+  double* hg = hH + (size_t)m * m;
+  double* hy = hg + (m + 1);
+  double* rs = hy + m;
   int iters = 0;
   if (x_zero) PBT_HIP(hipMemcpyAsync(r_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
   else {
@@ -627,67 +668,76 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol
   double* dsn = dcs + m;
   double* dg = dsn + m;
   double* dres = dg + (m + 1);
+  // steps still needed after the first `known` estimates, from the rate of
+  // the last few (a large number while there is no rate yet)
+  auto remaining = [&](int known) -> int {
+    if (known < 3) return 1 << 20;
+    const int d = std::min(known - 1, 4);
+    const double r1 = std::max(rs[known - 1], 1e-300), r0 = std::max(rs[known - 1 - d], 1e-300);
+    const double rate = std::pow(r1 / r0, 1.0 / d);
+    if (!(rate < 0.999)) return 4;
+    return (int)std::min(1e6, std::max(0.0, std::ceil(std::log(tol_abs / r1) / std::log(rate))));
+  };
+  struct Group { int beg, cnt, ev; };
   while (beta > tol_abs && iters < maxit) {
     launch_scale_copy(n_, 1.0 / beta, r_.p, V_.p, s);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    PBT_HIP(hipMemcpyAsync(dg, g.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, s));
-    int j = 0, used = 0;
+    launch_first_unit(m + 1, beta, dg, s);   // g = beta e_1
+    int j = 0, used = 0, known = 0, nev = 0;
     bool done = false;
-    while (j < m && iters + j < maxit && !done) {
-      // enqueue a group of Arnoldi steps sized by the observed convergence
-      // rate (predicted steps to the tolerance, 1..8)
-      int want = 2;
-      if (j >= 2) {
-        const int d = std::min(j, 4);
-        const double r1 = std::max(rs[j - 1], 1e-300), r0 = std::max(rs[j - 1 - d], 1e-300);
-        const double rate = std::pow(r1 / r0, 1.0 / d);
-        if (rate < 0.999) {
-          const double need = std::log(tol_abs / r1) / std::log(rate);
-          want = (int)std::min(8.0, std::max(1.0, std::ceil(need)));
-        } else {
-          want = 4;
+    std::deque<Group> inflight;
+    while (true) {
+      while (inflight.size() < 2 && j < m && iters + j < maxit) {
+        int want = remaining(known) - (j - known);
+        if (!inflight.empty() && want <= 0) break;   // no speculation past the predicted end
+        want = std::max(1, std::min(want, known < 3 ? (j == 0 ? 2 : 4) : 8));
+        const int group = std::min({want, m - j, maxit - iters - j});
+        for (int k = j; k < j + group; ++k) {
+          double* vj1 = V_.p + (size_t)(k + 1) * n_;
+          op(V_.p + (size_t)k * n_, vj1, fp32, s);
+          double* h1 = hdev_.p;
+          double* hs = hdev_.p + (m + 1);
+          double* nrm2 = hdev_.p + 2 * (m + 1);
+          double* part1 = part_.p;
+          double* part2 = part_.p + (size_t)(m + 2) * pdb_;
+          // pass 1: partial V^T w; pass 2: h1 = sum of pass 1, partial V^T w'
+          // and |w'|^2 with w' = w - V h1; column, rotation; w = (w - V h) / |w''|
+          launch_gs_dots(n_, k + 1, V_.p, n_, vj1, nullptr, nullptr, 0, part1, pdb_, s);
+          launch_gs_dots(n_, k + 1, V_.p, n_, vj1, part1, h1, 1, part2, pdb_, s);
+          launch_arnoldi_col(k, m, pdb_, part2, h1, dH, dcs, dsn, dg, dres, hs, nrm2, s);
+          launch_update_normalize(n_, k + 1, V_.p, n_, hs, nrm2, vj1, s);
         }
+        PBT_HIP(hipMemcpyAsync(rs + j, dres + j, group * sizeof(double), hipMemcpyDeviceToHost, s));
+        const int ev = nev++ & 1;
+        PBT_HIP(hipEventRecord(evg_[ev], s));
+        inflight.push_back({j, group, ev});
+        j += group;
       }
-      const int group = std::min({want, m - j, maxit - iters - j});
-      for (int k = j; k < j + group; ++k) {
-        double* vj1 = V_.p + (size_t)(k + 1) * n_;
-        op(V_.p + (size_t)k * n_, vj1, fp32, s);
-        double* h1 = hdev_.p;
-        double* hs = hdev_.p + (m + 1);
-        double* nrm2 = hdev_.p + 2 * (m + 1);
-        double* part1 = part_.p;
-        double* part2 = part_.p + (size_t)(m + 2) * pdb_;
-        // pass 1: partial V^T w; pass 2: h1 = sum of pass 1, partial V^T w'
-        // and |w'|^2 with w' = w - V h1; column, rotation; w = (w - V h) / |w''|
-        launch_gs_dots(n_, k + 1, V_.p, n_, vj1, nullptr, nullptr, 0, part1, pdb_, s);
-        launch_gs_dots(n_, k + 1, V_.p, n_, vj1, part1, h1, 1, part2, pdb_, s);
-        launch_arnoldi_col(k, m, pdb_, part2, h1, dH, dcs, dsn, dg, dres, hs, nrm2, s);
-        launch_update_normalize(n_, k + 1, V_.p, n_, hs, nrm2, vj1, s);
-      }
-      PBT_HIP(hipMemcpyAsync(rs.data() + j, dres + j, group * sizeof(double), hipMemcpyDeviceToHost, s));
-      PBT_HIP(hipStreamSynchronize(s));
-      for (int k = j; k < j + group; ++k) {
+      if (inflight.empty()) break;
+      const Group g = inflight.front();
+      inflight.pop_front();
+      PBT_HIP(hipEventSynchronize(evg_[g.ev]));
+      for (int k = g.beg; k < g.beg + g.cnt; ++k) {
         used = k + 1;
         *resid_out = rs[k];
         if (rs[k] <= tol_abs) { done = true; break; }
       }
-      nwasted_ += (j + group) - used;
-      j += group;
+      known = g.beg + g.cnt;
+      if (done) break;
     }
+    nwasted_ += j - used;
     iters += used;
-    // x += V y with H(0:used,0:used) y = g(0:used)
-    PBT_HIP(hipMemcpyAsync(H.data(), dH, (size_t)(m + 1) * m * sizeof(double), hipMemcpyDeviceToHost, s));
-    PBT_HIP(hipMemcpyAsync(g.data(), dg, (m + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    // x += V y with H(0:used,0:used) y = g(0:used); the H rows and g that
+    // are read were final before any step past `used` was enqueued
+    PBT_HIP(hipMemcpyAsync(hH, dH, (size_t)used * m * sizeof(double), hipMemcpyDeviceToHost, s));
+    PBT_HIP(hipMemcpyAsync(hg, dg, used * sizeof(double), hipMemcpyDeviceToHost, s));
     PBT_HIP(hipStreamSynchronize(s));
     for (int i = used - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int k = i + 1; k < used; ++k) acc -= H[(size_t)i * m + k] * y[k];
-      y[i] = acc / H[(size_t)i * m + i];
+      double acc = hg[i];
+      for (int k = i + 1; k < used; ++k) acc -= hH[(size_t)i * m + k] * hy[k];
+      hy[i] = acc / hH[(size_t)i * m + i];
     }
-    PBT_HIP(hipMemcpyAsync(hdev_.p, y.data(), used * sizeof(double), hipMemcpyHostToDevice, s));
+    PBT_HIP(hipMemcpyAsync(hdev_.p, hy, used * sizeof(double), hipMemcpyHostToDevice, s));
     launch_lincomb(n_, used, V_.p, n_, hdev_.p, x, s);
-    PBT_HIP(hipStreamSynchronize(s));
     if (done || iters >= maxit) break;
     op(x, r_.p, fp32, s);
     launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
@@ -770,11 +820,28 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
 std::vector<std::array<double, 3>> System::surface_energies(const double* x, hipStream_t s) {
   const int ns = (int)surfs_.size();
   std::vector<std::array<double, 3>> out(ns, {0.0, 0.0, 0.0});
-  std::vector<double> xh(n_);
-  PBT_HIP(hipMemcpyAsync(xh.data(), x, n_ * sizeof(double), hipMemcpyDeviceToHost, s));
   PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
   launch_densities(np_, m, x, sig_.p, mu_.p, s);
   launch_strengths<double>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, rlap_.p, src64_.p, s);
+  // reaction potential at every charge (eq. solv_energy), then one readback
+  std::vector<std::vector<double>> phi(ns);
+  bool surf_terms = false;
+  for (int e = 0; e < ns; ++e) {
+    const SurfIn& S = *surfs_[e];
+    if (S.kind != PBT_MOLECULE) {
+      surf_terms = true;
+      continue;
+    }
+    const int64_t nq = (int64_t)S.q.size();
+    if (nq == 0) continue;
+    ChargeData& d = charges(e, s);
+    launch_reac(nq, d.qx.p, poff_[e] * K_, (poff_[e] + S.nt) * K_, src64_.p, eps_out_ / S.eps_in, d.qn.ptr.p,
+                d.qn.col.p, d.qn.val.p, sig_.p + poff_[e], mu_.p + poff_[e], d.phi.p, s);
+    phi[e].resize(nq);
+    PBT_HIP(hipMemcpyAsync(phi[e].data(), d.phi.p, nq * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  std::vector<double> xh(surf_terms ? n_ : 0);
+  if (surf_terms) PBT_HIP(hipMemcpyAsync(xh.data(), x, n_ * sizeof(double), hipMemcpyDeviceToHost, s));
   PBT_HIP(hipStreamSynchronize(s));
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
@@ -782,18 +849,10 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
       const int64_t nq = (int64_t)S.q.size();
       if (nq == 0) continue;
       // F_solv = 1/2 sum q phi_reac (eq. solv_energy, first line)
-      std::vector<double> hphi = reaction_potential(e, s);
       double acc = 0;
-      for (int64_t k = 0; k < nq; ++k) acc += S.q[k] * hphi[k];
+      for (int64_t k = 0; k < nq; ++k) acc += S.q[k] * phi[e][k];
       out[e][1] = 0.5 * acc;
-      double c = 0;
-      for (int64_t k = 0; k < nq; ++k)
-        for (int64_t l = k + 1; l < nq; ++l) {
-          const double dx = S.qxyz[3 * k] - S.qxyz[3 * l], dy = S.qxyz[3 * k + 1] - S.qxyz[3 * l + 1],
-                       dz = S.qxyz[3 * k + 2] - S.qxyz[3 * l + 2];
-          c += S.q[k] * S.q[l] / std::sqrt(dx * dx + dy * dy + dz * dz);
-        }
-      out[e][0] = c / (kFourPi * S.eps_in);
+      out[e][0] = charges(e, s).coulomb / (kFourPi * S.eps_in);
     } else {
       double f = 0;
       for (int64_t li = 0; li < S.nt; ++li) {

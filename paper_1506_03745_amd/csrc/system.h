@@ -54,7 +54,30 @@ struct DBuf {
   }
 };
 
+// Pinned host memory, for readbacks that the host waits on.
+template <typename T>
+struct HBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  HBuf() = default;
+  HBuf(const HBuf&) = delete;
+  HBuf& operator=(const HBuf&) = delete;
+  ~HBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void alloc(size_t m) {
+    if (m <= n && p) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipHostMalloc((void**)&p, m * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) throw Error(2, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    n = m;
+  }
+};
+
 struct SurfIn {
+  uint64_t version = 0;  // bumped whenever bc or the charges change
   int kind = 0;
   int64_t nv = 0, nt = 0;
   std::vector<double> xyz;
@@ -175,6 +198,23 @@ class System {
   std::vector<std::array<double, 3>> surface_energies(const double* x, hipStream_t s);
   std::vector<double> reaction_potential(int e, hipStream_t s);  // densities already set
   double norm(const double* v, hipStream_t s);
+
+  // Device copies of what the right-hand side and the energies need from
+  // the surfaces' inputs, rebuilt when a surface's version changes.
+  struct ChargeData {
+    uint64_t version = ~0ull;
+    DBuf<double> qx, q, phi;
+    NearCSR qn;           // near corrections charge <- molecule panel
+    double coulomb = 0;   // sum over pairs k < l of q_k q_l / r_kl
+  };
+  std::vector<std::unique_ptr<ChargeData>> qdata_;
+  ChargeData& charges(int e, hipStream_t s);
+  std::vector<uint64_t> known_ver_;
+  DBuf<double> known_ks_, known_km_, known_half_, rhs_y_;
+  void ensure_known(hipStream_t s);
+  HBuf<double> hbuf_;          // pinned: Hessenberg rows, g, y, residual estimates
+  HBuf<double> hnorm_;         // pinned: norm readback
+  hipEvent_t evg_[2];          // GMRES group readbacks
 
   std::vector<const SurfIn*> surfs_;
   pbt_params prm_;

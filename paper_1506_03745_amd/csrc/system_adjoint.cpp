@@ -57,15 +57,12 @@ void System::charge_near(int e, const double* qx, int64_t nq, NearCSR& qn, hipSt
 std::vector<double> System::reaction_potential(int e, hipStream_t s) {
   const SurfIn& S = *surfs_[e];
   const int64_t nq = (int64_t)S.q.size();
+  if (nq == 0) return {};
   const int64_t p0 = poff_[e];
-  DBuf<double> qx, phi;
-  qx.upload(S.qxyz, s);
-  phi.alloc(nq);
-  NearCSR qn;
-  charge_near(e, qx.p, nq, qn, s);
-  launch_reac(nq, qx.p, p0 * K_, (p0 + S.nt) * K_, src64_.p, eps_out_ / S.eps_in, qn.ptr.p, qn.col.p,
-              qn.val.p, sig_.p + p0, mu_.p + p0, phi.p, s);
-  return phi.download(s);
+  ChargeData& d = charges(e, s);
+  launch_reac(nq, d.qx.p, p0 * K_, (p0 + S.nt) * K_, src64_.p, eps_out_ / S.eps_in, d.qn.ptr.p, d.qn.col.p,
+              d.qn.val.p, sig_.p + p0, mu_.p + p0, d.phi.p, s);
+  return d.phi.download(s);
 }
 
 // Transposed work lists built from the forward interaction lists:
@@ -305,15 +302,13 @@ void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
     const SurfIn& S = *surfs_[e];
     if (S.kind != PBT_MOLECULE || S.q.empty()) continue;
     const int64_t nq = (int64_t)S.q.size(), p0 = poff_[e];
-    DBuf<double> qx, qq, far;
-    qx.upload(S.qxyz, s);
-    qq.upload(S.q, s);
+    ChargeData& d = charges(e, s);
+    DBuf<double> far;
     far.alloc((size_t)S.nt * K_ * 4);
     // R^T q: far part at every Gauss point of the molecule
-    launch_reac_t(p0 * K_, (p0 + S.nt) * K_, src64_.p, nq, qx.p, qq.p, eps_out_ / S.eps_in, far.p, s);
+    launch_reac_t(p0 * K_, (p0 + S.nt) * K_, src64_.p, nq, d.qx.p, d.q.p, eps_out_ / S.eps_in, far.p, s);
     // near part: phi_reac = -L, so d(q . phi_reac)/d(sigma, mu) = -q (cLs, cLm)
-    NearCSR qn;
-    charge_near(e, qx.p, nq, qn, s);
+    const NearCSR& qn = d.qn;
     std::vector<int64_t> ptr = qn.ptr.download(s);
     std::vector<int32_t> col = qn.col.download(s);
     std::vector<double> val = qn.val.download(s);
