@@ -201,10 +201,19 @@ pbt_status pbt_gradient(pbt_ctx* ctx, int32_t sigma_id, double* dF_dsigma, int32
 pbt_status pbt_solve_batch(pbt_ctx* ctx, int32_t mol_id, const double* rot, const double* shift,
                            int32_t nb, double* F_int);
 
-/* Chooses P2P / M2P launch shapes for the enabled system by timing
- * candidates; cached per (size, precision) in memory and, if cache_path is
- * not NULL, in that text file. */
+/* Chooses P2P / M2P launch shapes and the schedule of the far field against
+ * P2P (one stream, two streams, or one joint launch) for the enabled system
+ * by timing candidates; cached per (size, precision) in memory and, if
+ * cache_path is not NULL, in that text file. */
 pbt_status pbt_autotune(pbt_ctx* ctx, const char* cache_path);
+
+/* Sets the schedule of the far field against P2P for the enabled system
+ * (Section 3.2 splits every product into near-field P2P and far-field
+ * P2M/M2M/M2P): 0 = P2P then the far field on the context's stream,
+ * 1 = the far field on a second stream, concurrently with P2P, 2 = moments
+ * first, then M2P and P2P tasks in one launch.  All three give bitwise the
+ * same products.  PBT_E_INVALID for another mode. */
+pbt_status pbt_set_schedule(pbt_ctx* ctx, int32_t mode);
 
 /* Quadrature tables the library integrates with (Section 3.1): triangle rule
  * with npts points (1, 3, 4, 7 or 19) as barycentric coordinates
@@ -215,7 +224,8 @@ pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w);
 
 /* Timing of the last pbt_matvec / pbt_matvec_dev on the context's own
  * events, in milliseconds: out[0] total, out[1] P2P kernel, out[2] M2P
- * kernel, out[3] moments (P2M + M2M), out[4] near-field and combine. */
+ * kernel, out[3] moments (P2M + M2M), out[4] near-field and combine.  Under
+ * the joint M2P + P2P schedule out[1] is that launch and out[2] is 0. */
 pbt_status pbt_last_matvec_timing(pbt_ctx* ctx, double out[5]);
 
 #ifdef __cplusplus

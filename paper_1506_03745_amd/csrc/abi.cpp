@@ -568,10 +568,11 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
 }
 
 // Autotuner: times the operator of the enabled system for candidate P2P and
-// M2P segment sizes (coordinate search: P2P first, then M2P) in the solve's
+// M2P segment sizes (coordinate search: P2P first, then M2P) and then for
+// the three schedules of the far field against P2P, in the solve's
 // interaction precision, keeps the fastest, and remembers it per system
 // shape in memory and, if given, in a text cache file
-// ("key seg_src seg_box ms" per line).
+// ("key seg_src 4*seg_box+schedule ms" per line).
 pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
   return guarded(c, [&] {
     System& S = system_for(c);
@@ -594,8 +595,8 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
       }
     }
     if (it != memo.end()) {
-      S.set_segments(it->second.first, it->second.second / 2, c->stream);
-      S.set_overlap(it->second.second % 2 == 1);
+      S.set_segments(it->second.first, it->second.second / 4, c->stream);
+      S.set_far_mode((int)(it->second.second % 4));
       return PBT_OK;
     }
     const int reps = 5;
@@ -612,18 +613,31 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
       if (t < best) { best = t; best_box = cand; }
     }
     S.set_segments(best_src, best_box, c->stream);
-    // far field on a second stream or after P2P on the same stream
-    const bool ov0 = S.overlap();
-    S.set_overlap(!ov0);
-    if (S.time_products(fp32, reps, c->stream) >= best) S.set_overlap(ov0);
-    memo[key] = {best_src, best_box * 2 + (S.overlap() ? 1 : 0)};
+    // scheduling of the far field against P2P (serial, two streams, one launch)
+    int best_mode = S.far_mode();
+    for (int mode = 0; mode < 3; ++mode) {
+      if (mode == best_mode) continue;
+      S.set_far_mode(mode);
+      const double t = S.time_products(fp32, reps, c->stream);
+      if (t < best) { best = t; best_mode = mode; }
+    }
+    S.set_far_mode(best_mode);
+    memo[key] = {best_src, best_box * 4 + best_mode};
     if (cache_path) {
       if (FILE* f = std::fopen(cache_path, "a")) {
-        std::fprintf(f, "%s %lld %lld %.6f\n", key, (long long)best_src,
-                     (long long)(best_box * 2 + (S.overlap() ? 1 : 0)), best);
+        std::fprintf(f, "%s %lld %lld %.6f\n", key, (long long)best_src, (long long)(best_box * 4 + best_mode), best);
         std::fclose(f);
       }
     }
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_set_schedule(pbt_ctx* c, int32_t mode) {
+  if (!c) return PBT_E_INVALID;
+  if (mode < 0 || mode > 2) return fail(c, PBT_E_INVALID, "schedule must be 0, 1 or 2");
+  return guarded(c, [&] {
+    system_for(c).set_far_mode(mode);
     return PBT_OK;
   });
 }

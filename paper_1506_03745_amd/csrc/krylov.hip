@@ -18,6 +18,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// out[i] = sum_b part[i * nbj + b] for i < nrows, by a block of kBS
+// threads: eight lanes per row, each adding a strided eighth of the row
+// (independent loads), then a fixed butterfly; the order of the additions
+// is fixed, so every block that calls this gets bitwise the same sums.
+__device__ __forceinline__ void reduce_rows(const double* __restrict__ part, int nrows, int nbj, double* out) {
+  const int sub = threadIdx.x & 7;
+  for (int r0 = 0; r0 < nrows; r0 += kBS / 8) {
+    const int i = r0 + (int)(threadIdx.x >> 3);
+    double sq = 0;
+    if (i < nrows) {
+#pragma unroll 8
+      for (int b = sub; b < nbj; b += 8) sq += part[(int64_t)i * nbj + b];
+    }
+    sq += __shfl_xor(sq, 4, 8);
+    sq += __shfl_xor(sq, 2, 8);
+    sq += __shfl_xor(sq, 1, 8);
+    if (sub == 0 && i < nrows) out[i] = sq;
+  }
+}
+
 // part[i * nblk + blockIdx.x] = sum over this block's strided range of V_i . w
 __global__ __launch_bounds__(kBS) void k_multidot(int64_t n, int m, const double* __restrict__ V,
                                                   int64_t ldv, const double* __restrict__ w,
@@ -65,16 +85,10 @@ __global__ __launch_bounds__(kBS) void k_gs_dots(int64_t n, int m, const double*
   const int nbj = gridDim.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (UPDATE) {
-    for (int i = wid; i < m; i += kBS / 64) {
-      double sq = 0;
-      for (int b = lane; b < nbj; b += 64) sq += hpart[(int64_t)i * nbj + b];
-      sq = wave_sum(sq);
-      if (lane == 0) {
-        hs[i] = sq;
-        if (blockIdx.x == 0 && blockIdx.y == 0) hout[i] = sq;
-      }
-    }
+    reduce_rows(hpart, m, nbj, hs);
     __syncthreads();
+    if (blockIdx.x == 0 && blockIdx.y == 0)
+      for (int i = threadIdx.x; i < m; i += kBS) hout[i] = hs[i];
   }
   const int i0 = blockIdx.y * 8;
   const int mq = m + (self_dot ? 1 : 0);
@@ -104,43 +118,54 @@ __global__ __launch_bounds__(kBS) void k_gs_dots(int64_t n, int m, const double*
   }
 }
 
-// Arnoldi column j of the Hessenberg matrix: adds up the second pass's
-// partials (h2 and |w'|^2, j + 2 rows of nbj), forms h = h1 + h2 and
-// |w''|^2 = |w'|^2 - |h2|^2 (w'' = w' - V h2 with V orthonormal), applies
-// the previous Givens rotations, computes the new one and stores the
-// residual estimate |g_{j+1}| in resid[j].  Also writes h (hsum) and
-// |w''|^2 (nrm2) for the update and normalisation of w.
-__global__ __launch_bounds__(kBS) void k_arnoldi_col(int j, int m, int nbj, const double* __restrict__ part,
-                                                     const double* __restrict__ h1, double* H, double* cs,
-                                                     double* sn, double* g, double* resid,
-                                                     double* __restrict__ hsum, double* __restrict__ nrm2) {
-  extern __shared__ double sh[];   // col[m + 1], h2[m + 1], c[m], s[m]
-  double* col = sh;
-  double* h2 = sh + (m + 1);
-  double* c = h2 + (m + 1);
+// The rest of Arnoldi step j after the second Gram-Schmidt pass.  Every
+// block adds up that pass's partials (h2 and |w'|^2, j + 2 rows of nbj, in
+// a fixed order, so all blocks hold the same values), forms h = h1 + h2 and
+// |w''|^2 = |w'|^2 - |h2|^2 (w'' = w' - V h2 with V orthonormal), and
+// updates its elements: w = (w - V h) / |w''|.  Block 0 also builds the
+// Hessenberg column j: the previous Givens rotations applied, the new one
+// computed, and the residual estimate |g_{j+1}| stored in resid[j].
+__global__ __launch_bounds__(kBS) void k_arnoldi_update(int64_t n, int j, int m, int nbj,
+                                                        const double* __restrict__ part,
+                                                        const double* __restrict__ h1,
+                                                        const double* __restrict__ V, int64_t ldv,
+                                                        double* __restrict__ w, double* H, double* cs,
+                                                        double* sn, double* g, double* resid) {
+  extern __shared__ double sh[];   // h[m], h2[m + 1], col[m + 1], c[m], s[m]
+  __shared__ double nn_s;
+  double* h = sh;
+  double* h2 = h + m;
+  double* col = h2 + (m + 1);
+  double* c = col + (m + 1);
   double* sv = c + m;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i = wid; i <= j + 1; i += kBS / 64) {
-    double sq = 0;
-    for (int b = lane; b < nbj; b += 64) sq += part[(int64_t)i * nbj + b];
-    sq = wave_sum(sq);
-    if (lane == 0) h2[i] = sq;
-  }
-  for (int i = threadIdx.x; i < j; i += kBS) {
-    c[i] = cs[i];
-    sv[i] = sn[i];
+  reduce_rows(part, j + 2, nbj, h2);
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < j; i += kBS) {
+      c[i] = cs[i];
+      sv[i] = sn[i];
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j; i += kBS) {
-    col[i] = h1[i] + h2[i];
-    hsum[i] = col[i];
+    h[i] = h1[i] + h2[i];
+    col[i] = h[i];
   }
-  __syncthreads();
   if (threadIdx.x == 0) {
     double h2s = 0.0;
     for (int i = 0; i <= j; ++i) h2s += h2[i] * h2[i];
-    const double nn = fmax(h2[j + 1] - h2s, 0.0);
-    *nrm2 = nn;
+    nn_s = fmax(h2[j + 1] - h2s, 0.0);
+  }
+  __syncthreads();
+  const double nn = nn_s;
+  const int64_t e = blockIdx.x * (int64_t)kBS + threadIdx.x;
+  if (e < n) {
+    double se = w[e];
+#pragma unroll 8
+    for (int i = 0; i <= j; ++i) se -= h[i] * V[(int64_t)i * ldv + e];
+    w[e] = nn > 0.0 ? se / sqrt(nn) : 0.0;
+  }
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x == 0) {
     const double hn = sqrt(nn);
     col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
@@ -162,20 +187,6 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_col(int j, int m, int nbj, cons
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j + 1; i += kBS) H[(size_t)i * m + j] = col[i];
-}
-
-// w = (w - sum_i h_i V_i) / sqrt(*nrm2)  (the second Gram-Schmidt update
-// fused with the normalisation)
-__global__ void k_update_normalize(int64_t n, int m, const double* __restrict__ V, int64_t ldv,
-                                   const double* __restrict__ h, const double* __restrict__ nrm2,
-                                   double* __restrict__ w) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double sj = w[j];
-#pragma unroll 8
-  for (int i = 0; i < m; ++i) sj -= h[i] * V[(int64_t)i * ldv + j];
-  const double v = *nrm2;
-  w[j] = v > 0.0 ? sj / sqrt(v) : 0.0;
 }
 
 __global__ void k_reduce_cols(int m, int nblk, const double* __restrict__ part, double* out) {
@@ -278,17 +289,12 @@ void launch_gs_dots(int64_t n, int m, const double* V, int64_t ldv, const double
   PBT_HIP(hipGetLastError());
 }
 
-void launch_arnoldi_col(int j, int m, int nbj, const double* part, const double* h1, double* H, double* cs,
-                        double* sn, double* g, double* resid, double* hsum, double* nrm2, hipStream_t s) {
-  k_arnoldi_col<<<1, kBS, (size_t)(4 * m + 2) * sizeof(double), s>>>(j, m, nbj, part, h1, H, cs, sn, g, resid,
-                                                                     hsum, nrm2);
-  PBT_HIP(hipGetLastError());
-}
-
-void launch_update_normalize(int64_t n, int m, const double* V, int64_t ldv, const double* h,
-                             const double* nrm2, double* w, hipStream_t s) {
-  if (n <= 0) return;
-  k_update_normalize<<<nblocks(n, 256), 256, 0, s>>>(n, m, V, ldv, h, nrm2, w);
+void launch_arnoldi_update(int64_t n, int j, int m, int nbj, const double* part, const double* h1,
+                           const double* V, int64_t ldv, double* w, double* H, double* cs, double* sn, double* g,
+                           double* resid, hipStream_t s) {
+  const unsigned blocks = n > 0 ? nblocks(n, kBS) : 1u;
+  k_arnoldi_update<<<blocks, kBS, (size_t)(5 * m + 2) * sizeof(double), s>>>(n, j, m, nbj, part, h1, V, ldv, w,
+                                                                              H, cs, sn, g, resid);
   PBT_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,116 @@
+// Device code shared by the near-field (P2P) kernels: source records staged
+// in per-wavefront LDS tiles and the pairwise interaction of Section 3.2.
+// Included inside namespace pbt { namespace { ... } } of a kernel file.
+#pragma once
+
+template <typename T>
+struct KMath;
+template <>
+struct KMath<float> {
+  static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+  // exp(-kappa r) = 2^(r * c) with c = -kappa log2(e)
+  static __device__ __forceinline__ float expk(float r, float c) { return __builtin_amdgcn_exp2f(r * c); }
+  static __host__ __device__ float expk_const(float kappa) { return -kappa * 1.4426950408889634f; }
+};
+template <>
+struct KMath<double> {
+  static __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+  static __device__ __forceinline__ double expk(double r, double c) { return exp(r * c); }
+  static __host__ __device__ double expk_const(double kappa) { return -kappa; }
+};
+
+// Map the hardware block index to a logical one so that consecutive logical
+// blocks (tasks that share source ranges) land on the same XCD, whose L2
+// then serves their common sources.  Workgroups are dispatched round-robin
+// over the 8 XCDs; gridDim.x is a multiple of 8.
+__device__ __forceinline__ int xcd_block() {
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// One source record (x y z s Dx Dy Dz s_L), aligned so that LDS reads of a
+// record are full-width.
+template <typename T>
+struct alignas(8 * sizeof(T)) SrcRec {
+  T v[8];
+};
+
+// Wave-scope ordering of LDS writes and reads between the lanes of one
+// wavefront (no workgroup barrier: the waves of a block run independent
+// tasks with different trip counts).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Interaction of one target with one source record (eqs. bem_interior and
+// bem_exterior, discrete forms): l accumulates s_L/r - D.(x-y)/r^3, yy
+// accumulates s e^{-kappa r}/r + D.grad_y(e^{-kappa r}/r).
+template <typename T, bool GUARD, bool FUSED>
+__device__ __forceinline__ void p2p_pair(const SrcRec<T>& s, T tx, T ty, T tz, T kappa, T ck, T& l, T& yy) {
+  const T dx = tx - s.v[0], dy = ty - s.v[1], dz = tz - s.v[2];
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  T rinv = KMath<T>::rsq(r2);
+  if (GUARD) rinv = r2 > T(0) ? rinv : T(0);
+  const T dd = s.v[4] * dx + s.v[5] * dy + s.v[6] * dz;
+  const T t = dd * (rinv * rinv);            // D.(x-y)/r^2
+  if (FUSED) l += (s.v[7] - t) * rinv;       // s_L/r - D.(x-y)/r^3
+  const T rr = r2 * rinv;
+  const T gy = KMath<T>::expk(rr, ck) * rinv;
+  const T f = kappa * rr + T(1);
+  yy += gy * (t * f + s.v[3]);               // s G_Y + D.grad_y G_Y
+}
+
+template <typename T, bool GUARD, bool FUSED>
+__device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int cnt, T tx, T ty, T tz, T kappa, T ck,
+                                         T& l, T& yy) {
+  int j = 0;
+  for (; j + 8 <= cnt; j += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) p2p_pair<T, GUARD, FUSED>(tile[j + q], tx, ty, tz, kappa, ck, l, yy);
+  }
+  for (; j < cnt; ++j) p2p_pair<T, GUARD, FUSED>(tile[j], tx, ty, tz, kappa, ck, l, yy);
+}
+
+// One P2P task (Task: 64 targets x a list of source ranges) on one
+// wavefront, one target per lane.  The task's source ranges are staged, 64
+// records at a time, into the wave's own LDS tile with one coalesced load per
+// lane; every lane then reads the same record (an LDS broadcast), so the
+// loads of successive records pipeline in order.
+template <typename T, bool GUARD>
+__device__ __forceinline__ void p2p_task(const Task& task, SrcRec<T>* tile, const int32_t* __restrict__ ranges,
+                                         const T* __restrict__ tgt, const T* __restrict__ src, T kappa,
+                                         T* __restrict__ partial) {
+  const int lane = threadIdx.x & 63;
+  const SrcRec<T>* srec = reinterpret_cast<const SrcRec<T>*>(src);
+  const int tbeg = task.tbeg, tcount = task.tcount;
+  const int lbeg = task.lbeg, lend = task.lend;
+  const int fused = task.fused;
+  const int ti = tbeg + (lane < tcount ? lane : 0);
+  const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
+  const T ck = KMath<T>::expk_const(kappa);
+  T l = 0, yy = 0;
+  int r = lbeg;
+  int cur = r < lend ? ranges[2 * r] : 0;
+  while (r < lend) {
+    // fill: up to 64 records from the remaining ranges, in order
+    int cnt = 0;
+    while (r < lend && cnt < 64) {
+      const int end = ranges[2 * r + 1];
+      const int take = min(end - cur, 64 - cnt);
+      if (lane >= cnt && lane < cnt + take) tile[lane] = srec[cur + (lane - cnt)];
+      cnt += take;
+      cur += take;
+      if (cur == end && ++r < lend) cur = ranges[2 * r];
+    }
+    wave_lds_sync();
+    if (fused) p2p_tile<T, GUARD, true>(tile, cnt, tx, ty, tz, kappa, ck, l, yy);
+    else p2p_tile<T, GUARD, false>(tile, cnt, tx, ty, tz, kappa, ck, l, yy);
+    wave_lds_sync();
+  }
+  if (lane < tcount) {
+    partial[2 * ((int64_t)task.slot * 64 + lane) + 0] = l;
+    partial[2 * ((int64_t)task.slot * 64 + lane) + 1] = yy;
+  }
+}

@@ -143,6 +143,11 @@ void launch_p2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, const T*
                 hipStream_t s);
 template <typename T>
 void launch_m2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, T* mom, hipStream_t s);
+// M2P and P2P tasks in one launch (taylor.hip).
+template <typename T>
+void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
+                    const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
+                    bool guard, T* partial, hipStream_t s);
 template <typename T>
 void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
                 const double* box_center, const T* mom, T kappa, T* partial, hipStream_t s);
@@ -199,15 +204,14 @@ void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hip
 void launch_normalize(int64_t n, const double* nrm2, const double* x, double* y, hipStream_t s);
 // One Arnoldi step's orthogonalisation (classical Gram-Schmidt applied
 // twice): partial dots (pass 1: hpart = null; pass 2: reduces pass 1's
-// partials into hout and dots with w - V h1), the Hessenberg column with its
-// Givens rotation, then w = (w - V (h1 + h2)) / |w''|.
+// partials into hout and dots with w - V h1), then w = (w - V (h1 + h2)) /
+// |w''| together with the Hessenberg column and its Givens rotation.
 int gs_blocks(int64_t n);
 void launch_gs_dots(int64_t n, int m, const double* V, int64_t ldv, const double* w, const double* hpart,
                     double* hout, int self_dot, double* part, int nbj, hipStream_t s);
-void launch_arnoldi_col(int j, int m, int nbj, const double* part, const double* h1, double* H, double* cs,
-                        double* sn, double* g, double* resid, double* hsum, double* nrm2, hipStream_t s);
-void launch_update_normalize(int64_t n, int m, const double* V, int64_t ldv, const double* h,
-                             const double* nrm2, double* w, hipStream_t s);
+void launch_arnoldi_update(int64_t n, int j, int m, int nbj, const double* part, const double* h1,
+                           const double* V, int64_t ldv, double* w, double* H, double* cs, double* sn, double* g,
+                           double* resid, hipStream_t s);
 void launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
 void launch_first_unit(int n, double beta, double* g, hipStream_t s);   // g = beta e_1
 void launch_rhs_solvent(int64_t np, const int32_t* row_sol, const double* ak, const double* half, double* b,

@@ -170,10 +170,12 @@ class System {
   // Operator applications since construction (every matvec and rhs pass),
   // not counting speculative Arnoldi steps discarded after convergence.
   int64_t applications() const { return napply_ - nwasted_; }
-  // Run the far field (moments, M2P) on a second stream, concurrently with
-  // P2P (true), or after it on the caller's stream (false).
-  void set_overlap(bool on) { overlap_ = on; }
-  bool overlap() const { return overlap_; }
+  // How the far field (moments, M2P) and P2P are scheduled:
+  //   0: P2P, then the far field, on the caller's stream;
+  //   1: the far field on a second stream, concurrently with P2P;
+  //   2: moments first, then M2P and P2P tasks in one launch.
+  void set_far_mode(int mode) { far_mode_ = mode; }
+  int far_mode() const { return far_mode_; }
 
  private:
   void build(hipStream_t s);
@@ -248,8 +250,9 @@ class System {
   DBuf<double> bcen_, brho_;
   DBuf<int32_t> bsbeg_, bsend_, bcbeg_, bcend_, bclist_;
   DBuf<int32_t> leaf_boxes_;
-  std::vector<std::pair<int, int>> m2m_levels_;  // (offset, count) into m2m_boxes_
+  int n_m2m_ = 0;                 // internal boxes whose moments M2P reads
   DBuf<int32_t> m2m_boxes_;
+  DBuf<int32_t> bdbeg_, bdend_, bdlist_;  // their leaf descendants
   int nleaf_ = 0;
   DBuf<float> mom32_;
   DBuf<double> mom64_;
@@ -272,7 +275,7 @@ class System {
   hipStream_t s2_ = nullptr;   // far-field stream (moments, M2P), overlaps P2P
   hipEvent_t evm_[3];          // on s2_: moments start, M2P start, M2P end
   int64_t napply_ = 0, nwasted_ = 0;
-  bool overlap_ = false;
+  int far_mode_ = 0;
   bool transpose_ = false;
   bool far_timed_ = false;
   int64_t seg_src_ = 0, seg_box_ = 0, seg_src_used_ = 0, seg_box_used_ = 0;

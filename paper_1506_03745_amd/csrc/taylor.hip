@@ -54,10 +54,7 @@ struct TMath<double> {
   static __device__ __forceinline__ double expm(double x) { return exp(-x); }
 };
 
-__device__ __forceinline__ int xcd_block() {
-  const int per = gridDim.x >> 3;
-  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-}
+#include "near_field.h"
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -65,19 +62,21 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// ---- P2M: one wavefront per (leaf box, coefficient k); lanes over sources.
-// The exponents of k are uniform across the wavefront, so the power loops
-// do not diverge.
+// ---- P2M: one wavefront per (leaf box, coefficient k), four coefficients
+// per block; lanes over sources.  The exponents of k are uniform across the
+// wavefront, so the power loops do not diverge.
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2m(int P, const int32_t* __restrict__ boxes, BoxDev bd,
-                                            const T* __restrict__ src, T* __restrict__ mom) {
+__global__ __launch_bounds__(256) void k_p2m(int P, const int32_t* __restrict__ boxes, BoxDev bd,
+                                             const T* __restrict__ src, T* __restrict__ mom) {
   const int NC = ncoef(P);
   const int b = boxes[blockIdx.x];
-  const int k = blockIdx.y;
-  const int lane = threadIdx.x;
+  const int k = blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+  if (k >= NC) return;
+  const int lane = threadIdx.x & 63;
   const MultiIdx mi = c_midx[k];
   const T cx = (T)bd.center[3 * b], cy = (T)bd.center[3 * b + 1], cz = (T)bd.center[3 * b + 2];
   T ms = 0, md = 0;
+#pragma unroll 4
   for (int j = bd.sbeg[b] + lane; j < bd.send[b]; j += 64) {
     const T* s = src + (int64_t)kSrcStride * j;
     const T hx = s[0] - cx, hy = s[1] - cy, hz = s[2] - cz;
@@ -97,24 +96,29 @@ __global__ __launch_bounds__(64) void k_p2m(int P, const int32_t* __restrict__ b
   }
 }
 
-// ---- M2M: one wavefront per (parent box, coefficient k); lanes over the
-// terms (child, m <= k) of
-//   M_k(parent) = sum_child sum_{m <= k} C(k, m) delta^(k-m) M_m(child),
-// delta = c_child - c_parent (h = y - c_parent = (y - c_child) + delta).
+// ---- M2M: one block per (box, coefficient k); threads over the terms
+// (descendant, m <= k) of
+//   M_k(box) = sum_desc sum_{m <= k} C(k, m) delta^(k-m) M_m(desc),
+// delta = c_desc - c_box (h = y - c_box = (y - c_desc) + delta).  The
+// descendants are the box's leaves, whose moments come from P2M, so every
+// box is done in the same launch.
+constexpr int kM2MThreads = 256;
 template <typename T>
-__global__ __launch_bounds__(64) void k_m2m(int P, const int32_t* __restrict__ boxes, BoxDev bd,
-                                            T* __restrict__ mom) {
+__global__ __launch_bounds__(kM2MThreads) void k_m2m(int P, const int32_t* __restrict__ boxes, BoxDev bd,
+                                                     T* __restrict__ mom) {
+  __shared__ T red[kM2MThreads / 64][2];
   const int NC = ncoef(P);
   const int b = boxes[blockIdx.x];
   const int k = blockIdx.y;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const MultiIdx mk = c_midx[k];
   const int nb = mk.b + 1, nc = mk.c + 1;
   const int nterm = (mk.a + 1) * nb * nc;
   const int c0 = bd.child_beg[b], nchild = bd.child_end[b] - c0;
   const double pcx = bd.center[3 * b], pcy = bd.center[3 * b + 1], pcz = bd.center[3 * b + 2];
   T acc0 = 0, acc1 = 0;
-  for (int t = lane; t < nchild * nterm; t += 64) {
+#pragma unroll 2
+  for (int t = threadIdx.x; t < nchild * nterm; t += kM2MThreads) {
     const int ci = t / nterm, r = t - ci * nterm;
     const int ma = r / (nb * nc), mb = (r / nc) % nb, mc = r % nc;
     const int c = bd.child_list[c0 + ci];
@@ -131,8 +135,18 @@ __global__ __launch_bounds__(64) void k_m2m(int P, const int32_t* __restrict__ b
   acc0 = wave_sum(acc0);
   acc1 = wave_sum(acc1);
   if (lane == 0) {
-    mom[(int64_t)(2 * b) * NC + k] = acc0;
-    mom[(int64_t)(2 * b + 1) * NC + k] = acc1;
+    red[wid][0] = acc0;
+    red[wid][1] = acc1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T s0 = 0, s1 = 0;
+    for (int w = 0; w < kM2MThreads / 64; ++w) {
+      s0 += red[w][0];
+      s1 += red[w][1];
+    }
+    mom[(int64_t)(2 * b) * NC + k] = s0;
+    mom[(int64_t)(2 * b + 1) * NC + k] = s1;
   }
 }
 
@@ -185,20 +199,17 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* __re
   return acc;
 }
 
+// One M2P task (64 targets x a list of boxes) on one wavefront, one target
+// per lane.
 template <typename T, int P>
-__global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int ntasks,
-                                             const int32_t* __restrict__ blist,
-                                             const T* __restrict__ tgt,
-                                             const double* __restrict__ bcen,
-                                             const T* __restrict__ mom, T kappa,
-                                             T* __restrict__ partial) {
+__device__ __forceinline__ void m2p_task(const Task& task, const int32_t* __restrict__ blist,
+                                         const T* __restrict__ tgt, const double* __restrict__ bcen,
+                                         const T* __restrict__ mom, T kappa, T* __restrict__ partial) {
   constexpr int NC = ncoef(P);
-  const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
-  if (wv >= ntasks) return;
   const int lane = threadIdx.x & 63;
-  const int tbeg = tasks[wv].tbeg, tcount = tasks[wv].tcount;
-  const int lbeg = tasks[wv].lbeg, lend = tasks[wv].lend;
-  const int fused = tasks[wv].fused;
+  const int tbeg = task.tbeg, tcount = task.tcount;
+  const int lbeg = task.lbeg, lend = task.lend;
+  const int fused = task.fused;
   const int ti = tbeg + (lane < tcount ? lane : 0);
   const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
   T l = 0, yy = 0;
@@ -210,10 +221,38 @@ __global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int
     if (fused) l += taylor_dot<T, P, false>(Rx, Ry, Rz, kappa, M + NC);
   }
   if (lane < tcount) {
-    const int slot = tasks[wv].slot;
-    partial[2 * ((int64_t)slot * 64 + lane) + 0] = l;
-    partial[2 * ((int64_t)slot * 64 + lane) + 1] = yy;
+    partial[2 * ((int64_t)task.slot * 64 + lane) + 0] = l;
+    partial[2 * ((int64_t)task.slot * 64 + lane) + 1] = yy;
   }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int ntasks,
+                                             const int32_t* __restrict__ blist,
+                                             const T* __restrict__ tgt,
+                                             const double* __restrict__ bcen,
+                                             const T* __restrict__ mom, T kappa,
+                                             T* __restrict__ partial) {
+  const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
+  if (wv >= ntasks) return;
+  m2p_task<T, P>(tasks[wv], blist, tgt, bcen, mom, kappa, partial);
+}
+
+// M2P and P2P tasks in one launch (M2P first): the far field's wavefronts
+// and the near field's share the machine instead of running one after the
+// other.
+template <typename T, int P, bool GUARD>
+__global__ __launch_bounds__(256) void k_m2p_p2p(const Task* __restrict__ m2p, int nm2p,
+                                                 const int32_t* __restrict__ blist,
+                                                 const double* __restrict__ bcen, const T* __restrict__ mom,
+                                                 const Task* __restrict__ p2p, int np2p,
+                                                 const int32_t* __restrict__ ranges, const T* __restrict__ src,
+                                                 const T* __restrict__ tgt, T kappa, T* __restrict__ partial) {
+  __shared__ SrcRec<T> tiles[4][64];
+  const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
+  if (wv < nm2p) m2p_task<T, P>(m2p[wv], blist, tgt, bcen, mom, kappa, partial);
+  else if (wv < nm2p + np2p)
+    p2p_task<T, GUARD>(p2p[wv - nm2p], tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, partial);
 }
 
 bool g_tables_ready[64] = {false};
@@ -246,7 +285,7 @@ void launch_p2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, const T*
                 hipStream_t s) {
   if (nbox <= 0) return;
   upload_tables();
-  k_p2m<T><<<dim3(nbox, ncoef(P)), 64, 0, s>>>(P, boxes, b, src, mom);
+  k_p2m<T><<<dim3(nbox, (ncoef(P) + 3) / 4), 256, 0, s>>>(P, boxes, b, src, mom);
   PBT_HIP(hipGetLastError());
 }
 
@@ -254,7 +293,7 @@ template <typename T>
 void launch_m2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, T* mom, hipStream_t s) {
   if (nbox <= 0) return;
   upload_tables();
-  k_m2m<T><<<dim3(nbox, ncoef(P)), 64, 0, s>>>(P, boxes, b, mom);
+  k_m2m<T><<<dim3(nbox, ncoef(P)), kM2MThreads, 0, s>>>(P, boxes, b, mom);
   PBT_HIP(hipGetLastError());
 }
 
@@ -284,10 +323,46 @@ void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, cons
   PBT_HIP(hipGetLastError());
 }
 
+template <typename T, int P>
+static void m2p_p2p_p(const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
+                      const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
+                      bool guard, T* partial, hipStream_t s) {
+  const int blocks = ((nm2p + np2p + 3) / 4 + 7) / 8 * 8;
+  if (guard)
+    k_m2p_p2p<T, P, true><<<blocks, 256, 0, s>>>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt,
+                                                 kappa, partial);
+  else
+    k_m2p_p2p<T, P, false><<<blocks, 256, 0, s>>>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt,
+                                                  kappa, partial);
+}
+
+template <typename T>
+void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
+                    const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
+                    bool guard, T* partial, hipStream_t s) {
+  if (nm2p + np2p <= 0) return;
+  switch (P) {
+#define PBT_CASE(PP)                                                                                      \
+  case PP:                                                                                                \
+    m2p_p2p_p<T, PP>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt, kappa, guard, partial, s); \
+    break;
+    PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
+#undef PBT_CASE
+    default: throw Error(1, "Taylor order P must be 0..8");
+  }
+  PBT_HIP(hipGetLastError());
+}
+
 template void launch_p2m<float>(int, int, const int32_t*, const BoxDev&, const float*, float*, hipStream_t);
 template void launch_p2m<double>(int, int, const int32_t*, const BoxDev&, const double*, double*, hipStream_t);
 template void launch_m2m<float>(int, int, const int32_t*, const BoxDev&, float*, hipStream_t);
 template void launch_m2m<double>(int, int, const int32_t*, const BoxDev&, double*, hipStream_t);
+template void launch_m2p_p2p<float>(int, const Task*, int, const int32_t*, const double*, const float*,
+                                    const Task*, int, const int32_t*, const float*, const float*, float, bool,
+                                    float*, hipStream_t);
+template void launch_m2p_p2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
+                                     const Task*, int, const int32_t*, const double*, const double*, double, bool,
+                                     double*, hipStream_t);
 template void launch_m2p<float>(int, const Task*, int, const int32_t*, const float*, const double*,
                                 const float*, float, float*, hipStream_t);
 template void launch_m2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,

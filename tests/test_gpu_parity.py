@@ -88,6 +88,21 @@ def test_operator_is_deterministic():
         assert np.array_equal(y1, y2)
 
 
+def test_far_field_schedules_agree_bitwise():
+    """Serial, two-stream and joint-launch schedules compute every partial sum
+    with the same code and order: the products are bitwise equal."""
+    s, _ = from_problem(case("sphere_plate"), treecode=1, ncrit=24, theta=0.5, taylor_p=4)
+    x = rand_x(s.num_unknowns(), 11)
+    for prec in (FP64, MIXED):
+        ys = []
+        for mode in (0, 1, 2):
+            s.set_schedule(mode)
+            ys.append(s.matvec(x, prec=prec))
+        assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
+    with pytest.raises(PbtError):
+        s.set_schedule(3)
+
+
 def test_treecode_small_theta_is_direct():
     """With a tiny acceptance parameter nothing is expanded: exact direct sums."""
     A, _ = oracle_Ab("twosphere_charge_l2")
