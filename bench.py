@@ -26,11 +26,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3          # published MI355X FP32 vector peak (packed FP32 FMA)
+FP32_NONPACKED_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, one FP32 op per lane
 FLOPS_FUSED_PAIR = 29    # Laplace + Yukawa, single + double layer (op list in the design doc)
 FLOPS_YUKAWA_PAIR = 26
 P2P_PROFILE = os.path.join(ROOT, "profiles", "k_p2p_twosphere_charge.json")
-P2P_SOURCE = os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "matvec_kernels.hip")
+P2P_SOURCES = (os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "matvec_kernels.hip"),
+               os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "near_field.h"))
 
 
 def profiled_traffic():
@@ -39,10 +41,11 @@ def profiled_traffic():
     import hashlib
     try:
         prof = json.load(open(P2P_PROFILE))
-        sha = hashlib.sha256(open(P2P_SOURCE, "rb").read()).hexdigest()
+        sha = [hashlib.sha256(open(f, "rb").read()).hexdigest() for f in P2P_SOURCES]
     except (OSError, ValueError):
         return None
-    return prof.get("traffic_bytes_per_launch") if prof.get("source_sha256") == sha else None
+    same = prof.get("source_sha256") == sha[0] and prof.get("header_sha256") == sha[1]
+    return prof.get("traffic_bytes_per_launch") if same else None
 
 
 def parse():
@@ -166,6 +169,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_p2p<float>", "achieved": round(achieved, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": profiled_traffic(),
+                     "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                      "flops_per_launch": int(p2p_flops), "avg_launch_ms": round(acc["p2p_ms"], 5)},
         "gmres": {"iters": r.iters, "outer": r.outer, "rel_resid": r.rel_resid,
                   "applications_per_step": applications, "setup_s": round(setup_wall, 4),
