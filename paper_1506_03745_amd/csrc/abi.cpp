@@ -548,17 +548,9 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
       b.alloc(n);
       x.alloc(n);
       S.rhs(b.p, c->stream);
-      PBT_HIP(hipMemsetAsync(x.p, 0, n * sizeof(double), c->stream));
-      double tol = c->prm.tol / std::sqrt((double)G);
-      bool ok = false;
-      for (int round = 0; round < 4 && !ok; ++round) {
-        pbt_result r{};
-        S.solve_tol(b.p, x.p, tol, &r, c->stream);
-        std::vector<double> gr = S.group_residuals(b.p, x.p, G, c->stream);
-        ok = *std::max_element(gr.begin(), gr.end()) <= c->prm.tol;
-        tol *= 0.1;
-      }
-      if (!ok) worst = PBT_E_NOCONVERGE;
+      // one Krylov space per placement, each to the requested tolerance
+      pbt_result r{};
+      if (!S.solve(b.p, x.p, false, &r, c->stream)) worst = PBT_E_NOCONVERGE;
       std::vector<pbt_result> e = S.energies_by_group(x.p, G, c->stream);
       for (int g = 0; g < G; ++g) F_int[b0 + g] = e[g].F_total - f_iso;
     }

@@ -65,12 +65,16 @@ void launch_panel_geometry(int64_t np, const double* tri9, double* cen, double* 
 void launch_sources(int64_t np, int K, const double* tri9, const double* nrm, const double* area,
                     const double* bary, const double* w, double* src_pos, double* src_wa,
                     hipStream_t s);
+// Near lists (panels closer than 2L): every target scans all np panels
+// (tleaf null) or the candidate ranges of its leaf (CSR lptr / lrange).
 void launch_near_count(int64_t nt, const double* tx, int64_t np, const double* cen,
-                       const double* cross2, const int32_t* tgrp, const int32_t* pgrp,
-                       const int64_t* grange, int32_t* count, hipStream_t s);
+                       const double* cross2, const int32_t* tleaf, const int64_t* lptr,
+                       const int64_t* lrange, int32_t* count, hipStream_t s);
 void launch_near_fill(int64_t nt, const double* tx, int64_t np, const double* cen,
-                      const double* cross2, const int32_t* tgrp, const int32_t* pgrp,
-                      const int64_t* grange, const int64_t* rowptr, int32_t* col, hipStream_t s);
+                      const double* cross2, const int32_t* tleaf, const int64_t* lptr,
+                      const int64_t* lrange, const int64_t* rowptr, int32_t* col, hipStream_t s);
+void launch_pack_points(int64_t np, int64_t ns, const double* cen, const double* src_pos, double* t64, float* t32,
+                        double* s64, float* s32, hipStream_t s);
 struct NearParams {
   int K, Knear, Nedge;
   double kappa;
@@ -194,30 +198,27 @@ void launch_reac_t(int64_t s0, int64_t s1, const double* src, int64_t nq, const 
 void launch_coulomb_t(int64_t nq, const double* qxyz, int64_t n, const double* tx, const int32_t* rows,
                       const double* lam, double inv_eps, double* out, hipStream_t s);
 
-// --- Krylov BLAS-1 (krylov.hip) ---------------------------------------------
-void launch_multidot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* part,
-                     int nblk, hipStream_t s);
-void launch_reduce_cols(int m, int nblk, const double* part, double* out, hipStream_t s);
-void launch_multi_axpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* w,
-                       hipStream_t s);
+// --- Krylov (krylov.hip) ----------------------------------------------------
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
-void launch_normalize(int64_t n, const double* nrm2, const double* x, double* y, hipStream_t s);
-// One Arnoldi step's orthogonalisation (classical Gram-Schmidt applied
-// twice): partial dots (pass 1: hpart = null; pass 2: reduces pass 1's
-// partials into hout and dots with w - V h1), then w = (w - V (h1 + h2)) /
-// |w''| together with the Hessenberg column and its Givens rotation.
+// Krylov kernels (krylov.hip), for G independent systems at once: group g
+// owns the unknowns gu[2g] .. gu[2g+1] (device array) and its own Krylov
+// space.  One Arnoldi step = two Gram-Schmidt passes of partial dots (pass
+// 1: hpart = null; pass 2: reduces pass 1's partials into hout and dots with
+// w - V h1), then w = (w - V (h1 + h2)) / |w''| together with each group's
+// Hessenberg column and Givens rotation.  R = rows reserved per group in
+// the partial and h buffers (restart + 1).
 int gs_blocks(int64_t n);
-void launch_gs_dots(int64_t n, int m, const double* V, int64_t ldv, const double* w, const double* hpart,
-                    double* hout, int self_dot, double* part, int nbj, hipStream_t s);
-void launch_arnoldi_update(int64_t n, int j, int m, int nbj, const double* part, const double* h1,
-                           const double* V, int64_t ldv, double* w, double* H, double* cs, double* sn, double* g,
-                           double* resid, hipStream_t s);
-void launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
-void launch_first_unit(int n, double beta, double* g, hipStream_t s);   // g = beta e_1
+void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int64_t ldv, const double* w,
+                    const double* hpart, double* hout, int self_dot, double* part, int nbj, hipStream_t s);
+void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m, int R, int nbj,
+                           const double* part, const double* h1, const double* V, int64_t ldv, double* w,
+                           double* H, double* cs, double* sn, double* gv, double* resid, hipStream_t s);
+void launch_group_row0(int G, int R, int nbj, const double* part, double* out, hipStream_t s);
+void launch_lincomb(const int64_t* gu, int G, int64_t nmax, int m, int ystride, const double* V, int64_t ldv,
+                    const double* y, double* x, hipStream_t s);
+void launch_start_cycle(const int64_t* gu, int G, int64_t nmax, int m, const double* beta, const double* inv_beta,
+                        const double* r, double* v0, double* gv, hipStream_t s);
 void launch_rhs_solvent(int64_t np, const int32_t* row_sol, const double* ak, const double* half, double* b,
                         hipStream_t s);
-void launch_lincomb(int64_t n, int m, const double* V, int64_t ldv, const double* c, double* y,
-                    hipStream_t s);
-int multidot_blocks(int64_t n);
 
 }  // namespace pbt

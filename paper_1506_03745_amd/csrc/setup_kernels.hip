@@ -8,6 +8,8 @@
 // (|e1 x e2| = 2 A_j, so 4 L_j^2 = 4 |e1 x e2|).
 #include "pbt_internal.h"
 
+#include <algorithm>
+
 namespace pbt {
 
 namespace {
@@ -74,41 +76,67 @@ __device__ __forceinline__ bool is_near(double tx, double ty, double tz, double 
 
 // One wavefront per target, lanes over panels.  The fill pass writes the
 // hits of each 64-panel chunk in panel order (ballot + popcount), so the
-// lists come out sorted exactly as a serial scan would produce them.
-// Targets and panels of different groups (independent systems solved in
-// one batch) never pair: a target of group g scans only the panel range
-// [grange[2g], grange[2g+1]) and checks pgrp; tgrp / pgrp / grange may be
-// null (one group, all panels).
+// lists come out sorted exactly as a serial scan would produce them.  A
+// target scans either every panel [0, np) (tleaf null) or the candidate
+// panel ranges of its leaf, lrange[2r] .. lrange[2r+1] for r in
+// lptr[tleaf[i]] .. lptr[tleaf[i]+1] (increasing and disjoint): the panels
+// left out lie provably farther than the near distance, so both give the
+// same lists.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_near(int64_t nt, const double* __restrict__ tx, int64_t np,
                                               const double* __restrict__ cen,
                                               const double* __restrict__ cross2,
-                                              const int32_t* __restrict__ tgrp,
-                                              const int32_t* __restrict__ pgrp,
-                                              const int64_t* __restrict__ grange, int32_t* count,
+                                              const int32_t* __restrict__ tleaf,
+                                              const int64_t* __restrict__ lptr,
+                                              const int64_t* __restrict__ lrange, int32_t* count,
                                               const int64_t* __restrict__ rowptr, int32_t* col) {
   const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= nt) return;  // uniform across the wavefront
   const double x = tx[3 * i], y = tx[3 * i + 1], z = tx[3 * i + 2];
-  const int32_t g = tgrp ? tgrp[i] : 0;
   int64_t out = FILL ? rowptr[i] : 0;
   int32_t cnt = 0;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t jb = grange ? grange[2 * g] : 0, je = grange ? grange[2 * g + 1] : np;
-  for (int64_t j0 = jb; j0 < je; j0 += 64) {
-    const int64_t j = j0 + lane;
-    const bool hit = j < je && (!tgrp || pgrp[j] == g) &&
-                     is_near(x, y, z, cen[3 * j], cen[3 * j + 1], cen[3 * j + 2], cross2[j]);
-    const uint64_t m = __ballot(hit);
-    if (FILL) {
-      if (hit) col[out + __popcll(m & below)] = (int32_t)j;
-      out += __popcll(m);
-    } else {
-      cnt += __popcll(m);
+  const int64_t r0 = tleaf ? lptr[tleaf[i]] : 0, r1 = tleaf ? lptr[tleaf[i] + 1] : 1;
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t jb = tleaf ? lrange[2 * r] : 0, je = tleaf ? lrange[2 * r + 1] : np;
+    for (int64_t j0 = jb; j0 < je; j0 += 64) {
+      const int64_t j = j0 + lane;
+      const bool hit = j < je && is_near(x, y, z, cen[3 * j], cen[3 * j + 1], cen[3 * j + 2], cross2[j]);
+      const uint64_t m = __ballot(hit);
+      if (FILL) {
+        if (hit) col[out + __popcll(m & below)] = (int32_t)j;
+        out += __popcll(m);
+      } else {
+        cnt += __popcll(m);
+      }
     }
   }
   if (!FILL && lane == 0) count[i] = cnt;
+}
+
+// Target and source records from the device geometry: targets (x, y, z, 0),
+// sources (x, y, z, 0, 0, 0, 0, 0) in FP64 and FP32 (strengths are written
+// per product).
+__global__ void k_pack_points(int64_t np, int64_t ns, const double* __restrict__ cen,
+                              const double* __restrict__ src_pos, double* t64, float* t32, double* s64,
+                              float* s32) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < np) {
+    for (int d = 0; d < 3; ++d) {
+      t64[4 * i + d] = cen[3 * i + d];
+      t32[4 * i + d] = (float)cen[3 * i + d];
+    }
+    t64[4 * i + 3] = 0.0;
+    t32[4 * i + 3] = 0.0f;
+  }
+  if (i < ns) {
+    for (int d = 0; d < 8; ++d) {
+      const double v = d < 3 ? src_pos[3 * i + d] : 0.0;
+      s64[8 * i + d] = v;
+      s32[8 * i + d] = (float)v;
+    }
+  }
 }
 
 struct K4 {
@@ -265,20 +293,28 @@ void launch_sources(int64_t np, int K, const double* tri9, const double* nrm, co
 }
 
 void launch_near_count(int64_t nt, const double* tx, int64_t np, const double* cen,
-                       const double* cross2, const int32_t* tgrp, const int32_t* pgrp,
-                       const int64_t* grange, int32_t* count, hipStream_t s) {
+                       const double* cross2, const int32_t* tleaf, const int64_t* lptr,
+                       const int64_t* lrange, int32_t* count, hipStream_t s) {
   if (nt <= 0) return;
-  k_near<false><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tgrp, pgrp, grange, count,
+  k_near<false><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tleaf, lptr, lrange, count,
                                                         nullptr, nullptr);
   PBT_HIP(hipGetLastError());
 }
 
 void launch_near_fill(int64_t nt, const double* tx, int64_t np, const double* cen,
-                      const double* cross2, const int32_t* tgrp, const int32_t* pgrp,
-                      const int64_t* grange, const int64_t* rowptr, int32_t* col, hipStream_t s) {
+                      const double* cross2, const int32_t* tleaf, const int64_t* lptr,
+                      const int64_t* lrange, const int64_t* rowptr, int32_t* col, hipStream_t s) {
   if (nt <= 0) return;
-  k_near<true><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tgrp, pgrp, grange, nullptr,
+  k_near<true><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tleaf, lptr, lrange, nullptr,
                                                        rowptr, col);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_pack_points(int64_t np, int64_t ns, const double* cen, const double* src_pos, double* t64, float* t32,
+                        double* s64, float* s32, hipStream_t s) {
+  const int64_t n = std::max(np, ns);
+  if (n <= 0) return;
+  k_pack_points<<<nblocks(n, 256), 256, 0, s>>>(np, ns, cen, src_pos, t64, t32, s64, s32);
   PBT_HIP(hipGetLastError());
 }
 

@@ -121,26 +121,6 @@ void System::build(hipStream_t s) {
     rlap_.upload(rl, s);
   }
   panel_surf_.upload(psurf, s);
-  {
-    // groups: ids 0..G-1, each a contiguous panel range (surfaces are added
-    // group by group)
-    std::vector<int32_t> pg(np_);
-    ngroups_ = 1;
-    for (int64_t g = 0; g < np_; ++g) {
-      pg[g] = surfs_[psurf[g]]->group;
-      ngroups_ = std::max(ngroups_, pg[g] + 1);
-    }
-    std::vector<int64_t> gr(2 * ngroups_, 0);
-    for (int k = 0; k < ngroups_; ++k) { gr[2 * k] = np_; gr[2 * k + 1] = 0; }
-    for (int64_t g = 0; g < np_; ++g) {
-      gr[2 * pg[g]] = std::min(gr[2 * pg[g]], g);
-      gr[2 * pg[g] + 1] = std::max(gr[2 * pg[g] + 1], g + 1);
-    }
-    for (int k = 0; k < ngroups_; ++k)
-      if (gr[2 * k] > gr[2 * k + 1]) gr[2 * k] = gr[2 * k + 1] = 0;
-    panel_group_.upload(pg, s);
-    group_range_.upload(gr, s);
-  }
   std::vector<int32_t> smol(ns);
   std::vector<double> srho(ns);
   for (int e = 0; e < ns; ++e) {
@@ -169,55 +149,13 @@ void System::build(hipStream_t s) {
   h_cen_ = cen_.download(s);
   h_area_ = area_.download(s);
   std::vector<double> hsrc = src_pos_.download(s);
-  {
-    std::vector<double> t64(4 * np_, 0.0);
-    std::vector<float> t32(4 * np_, 0.0f);
-    for (int64_t i = 0; i < np_; ++i)
-      for (int d = 0; d < 3; ++d) {
-        t64[4 * i + d] = h_cen_[3 * i + d];
-        t32[4 * i + d] = (float)h_cen_[3 * i + d];
-      }
-    tgt64_.upload(t64, s);
-    tgt32_.upload(t32, s);
-    std::vector<double> s64(kSrcStride * ns_, 0.0);
-    std::vector<float> s32(kSrcStride * ns_, 0.0f);
-    for (int64_t j = 0; j < ns_; ++j)
-      for (int d = 0; d < 3; ++d) {
-        s64[kSrcStride * j + d] = hsrc[3 * j + d];
-        s32[kSrcStride * j + d] = (float)hsrc[3 * j + d];
-      }
-    src64_.upload(s64, s);
-    src32_.upload(s32, s);
-  }
+  tgt64_.alloc(4 * np_);
+  tgt32_.alloc(4 * np_);
+  src64_.alloc(kSrcStride * ns_);
+  src32_.alloc(kSrcStride * ns_);
+  launch_pack_points(np_, ns_, cen_.p, src_pos_.p, tgt64_.p, tgt32_.p, src64_.p, src32_.p, s);
   sig_.alloc(np_);
   mu_.alloc(np_);
-
-  // ---- near / self corrections for the collocation points ------------------
-  {
-    DBuf<int32_t> cnt;
-    cnt.alloc(np_);
-    launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, panel_group_.p, panel_group_.p, group_range_.p,
-                      cnt.p, s);
-    std::vector<int32_t> hc = cnt.download(s);
-    std::vector<int64_t> ptr(np_ + 1, 0);
-    for (int64_t i = 0; i < np_; ++i) ptr[i + 1] = ptr[i] + hc[i];
-    near_.nnz = ptr[np_];
-    near_.ptr.upload(ptr, s);
-    near_.col.alloc(std::max<int64_t>(near_.nnz, 1));
-    near_.val.alloc(4 * std::max<int64_t>(near_.nnz, 1));
-    launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, panel_group_.p, panel_group_.p, group_range_.p,
-                     near_.ptr.p, near_.col.p, s);
-    std::vector<int32_t> self(np_);
-    for (int64_t i = 0; i < np_; ++i) self[i] = (int32_t)i;
-    DBuf<int32_t> dself;
-    dself.upload(self, s);
-    NearParams np{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
-    launch_near_values(np_, cen_.p, dself.p, near_.ptr.p, near_.col.p, tri9_.p, nrm_.p, area_.p, np,
-                       near_.val.p, s);
-    launch_fold_near(np_, near_.ptr.p, near_.col.p, panel_surf_.p, panel_surf_.p, surf_mol_.p,
-                     surf_rhoinv_.p, near_.val.p, s);
-    PBT_HIP(hipStreamSynchronize(s));
-  }
 
   // ---- tree geometry (global box numbering) --------------------------------
   boff_.assign(ns + 1, 0);
@@ -256,6 +194,80 @@ void System::build(hipStream_t s) {
     leaf_boxes_.upload(leaves, s);
     nleaf_ = (int)leaves.size();
   }
+  // ---- near / self corrections for the collocation points ------------------
+  {
+    // candidate panel ranges per target leaf: boxes of the same group whose
+    // centroid sphere comes within 2 L_max (with a rounding margin) of the
+    // leaf's; no panel outside them can pass the near test
+    std::vector<int32_t> tleaf(np_, 0);
+    std::vector<int64_t> lptr{0}, lrange;
+    std::vector<double> lmax(ns, 0.0);
+    for (int e = 0; e < ns; ++e)
+      for (int64_t li = 0; li < surfs_[e]->nt; ++li)
+        lmax[e] = std::max(lmax[e], 2.0 * std::sqrt(2.0 * h_area_[poff_[e] + li]));
+    for (int e = 0; e < ns; ++e) {
+      for (const TreeBox& T : trees_[e].boxes) {
+        if (!T.leaf) continue;
+        const int32_t id = (int32_t)(lptr.size() - 1);
+        for (int64_t g = poff_[e] + T.pbeg; g < poff_[e] + T.pend; ++g) tleaf[g] = id;
+        std::vector<std::pair<int64_t, int64_t>> rg;
+        for (int e2 = 0; e2 < ns; ++e2) {
+          if (surfs_[e2]->group != surfs_[e]->group) continue;
+          const SurfTree& S2 = trees_[e2];
+          std::vector<int> stack{0};
+          while (!stack.empty()) {
+            const TreeBox& B = S2.boxes[stack.back()];
+            stack.pop_back();
+            const double dx = T.tc[0] - B.tc[0], dy = T.tc[1] - B.tc[1], dz = T.tc[2] - B.tc[2];
+            const double reach = (T.tr + B.tr + lmax[e2]) * (1.0 + 1e-9) + 1e-9;
+            if (dx * dx + dy * dy + dz * dz >= reach * reach) continue;
+            if (B.leaf) rg.push_back({poff_[e2] + B.pbeg, poff_[e2] + B.pend});
+            else
+              for (int k = B.child_end - 1; k >= B.child_beg; --k) stack.push_back(S2.child_list[k]);
+          }
+        }
+        std::sort(rg.begin(), rg.end());
+        for (const auto& r : rg) {
+          if (!lrange.empty() && (int64_t)lrange.size() / 2 > lptr.back() && lrange.back() == r.first)
+            lrange.back() = r.second;
+          else {
+            lrange.push_back(r.first);
+            lrange.push_back(r.second);
+          }
+        }
+        lptr.push_back((int64_t)lrange.size() / 2);
+      }
+    }
+    if (lrange.empty()) lrange = {0, 0};
+    DBuf<int32_t> dtleaf;
+    DBuf<int64_t> dlptr, dlrange;
+    dtleaf.upload(tleaf, s);
+    dlptr.upload(lptr, s);
+    dlrange.upload(lrange, s);
+    DBuf<int32_t> cnt;
+    cnt.alloc(np_);
+    launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, cnt.p, s);
+    std::vector<int32_t> hc = cnt.download(s);
+    std::vector<int64_t> ptr(np_ + 1, 0);
+    for (int64_t i = 0; i < np_; ++i) ptr[i + 1] = ptr[i] + hc[i];
+    near_.nnz = ptr[np_];
+    near_.ptr.upload(ptr, s);
+    near_.col.alloc(std::max<int64_t>(near_.nnz, 1));
+    near_.val.alloc(4 * std::max<int64_t>(near_.nnz, 1));
+    launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, near_.ptr.p,
+                     near_.col.p, s);
+    std::vector<int32_t> self(np_);
+    for (int64_t i = 0; i < np_; ++i) self[i] = (int32_t)i;
+    DBuf<int32_t> dself;
+    dself.upload(self, s);
+    NearParams np{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
+    launch_near_values(np_, cen_.p, dself.p, near_.ptr.p, near_.col.p, tri9_.p, nrm_.p, area_.p, np,
+                       near_.val.p, s);
+    launch_fold_near(np_, near_.ptr.p, near_.col.p, panel_surf_.p, panel_surf_.p, surf_mol_.p,
+                     surf_rhoinv_.p, near_.val.p, s);
+    PBT_HIP(hipStreamSynchronize(s));
+  }
+
   build_plan();
   upload_plan(s);
   // Moments of the internal boxes that some M2P task reads, each shifted
@@ -673,13 +685,43 @@ void System::rhs(double* b, hipStream_t s) {
   }
 }
 
-double System::norm(const double* v, hipStream_t s) {
-  launch_multidot(n_, 1, v, n_, v, part_.p, mdb_, s);
-  launch_reduce_cols(1, mdb_, part_.p, hdev_.p, s);
-  hnorm_.alloc(1);
-  PBT_HIP(hipMemcpyAsync(hnorm_.p, hdev_.p, sizeof(double), hipMemcpyDeviceToHost, s));
+// Group layout of the unknowns: the surfaces of a group are consecutive, so
+// each group owns one range of unknowns (rows and columns alike).
+void System::ensure_groups(hipStream_t s) {
+  if (!gu_.empty()) return;
+  const int ns = (int)surfs_.size();
+  int G = 1;
+  for (int e = 0; e < ns; ++e) G = std::max(G, surfs_[e]->group + 1);
+  std::vector<int64_t> gu(2 * G, -1);
+  for (int e = 0; e < ns; ++e) {
+    const int g = surfs_[e]->group;
+    if (gu[2 * g] < 0) gu[2 * g] = col_off_[e];
+    else if (gu[2 * g + 1] != col_off_[e]) throw Error(PBT_E_INVALID, "the surfaces of a group must be consecutive");
+    gu[2 * g + 1] = col_off_[e + 1];
+  }
+  gmax_ = 0;
+  for (int g = 0; g < G; ++g) {
+    if (gu[2 * g] < 0) gu[2 * g] = gu[2 * g + 1] = 0;
+    gmax_ = std::max(gmax_, gu[2 * g + 1] - gu[2 * g]);
+  }
+  G_ = G;
+  dgu_.upload(gu, s);
+  gu_ = gu;
+}
+
+// Euclidean norm of each group's part of v.
+std::vector<double> System::group_norms(const double* v, hipStream_t s) {
+  const int nbj = gs_blocks(gmax_);
+  nrm_part_.alloc((size_t)G_ * nbj + G_);
+  launch_gs_dots(dgu_.p, G_, 0, 1, nullptr, n_, v, nullptr, nullptr, 1, nrm_part_.p, nbj, s);
+  double* out = nrm_part_.p + (size_t)G_ * nbj;
+  launch_group_row0(G_, 1, nbj, nrm_part_.p, out, s);
+  hnorm_.alloc(G_);
+  PBT_HIP(hipMemcpyAsync(hnorm_.p, out, G_ * sizeof(double), hipMemcpyDeviceToHost, s));
   PBT_HIP(hipStreamSynchronize(s));
-  return std::sqrt(hnorm_.p[0]);
+  std::vector<double> r(G_);
+  for (int g = 0; g < G_; ++g) r[g] = std::sqrt(hnorm_.p[g]);
+  return r;
 }
 
 void System::true_residual(const double* b, const double* x, double* r, hipStream_t s) {
@@ -687,53 +729,83 @@ void System::true_residual(const double* b, const double* x, double* r, hipStrea
   launch_axpby(n_, 1.0, b, -1.0, r, s);  // r = b - A x
 }
 
-// Restarted GMRES with classical Gram-Schmidt applied twice.  Everything of
-// an Arnoldi step runs on the device, including the Hessenberg column and
-// its Givens rotation, which leaves the residual estimate |g_{j+1}| in
-// resid[j].  The host enqueues groups of steps, sized from the observed
-// convergence rate, and keeps up to two groups in flight: it reads one
-// group's estimates (pinned memory, an event per group) while the next one
-// runs, so the GPU does not wait on the host between steps.  Steps enqueued
-// past convergence are discarded (the solution uses the columns up to the
-// first estimate <= tol_abs).  Returns the iterations used.
-int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
-                  int maxit, double* resid_out, hipStream_t s) {
-  const int m = restart;
-  // pinned layout: H rows [m * m], g [m + 1], y [m], rs [m]
-  hbuf_.alloc((size_t)m * m + 3 * (size_t)m + 1);
+// Restarted GMRES with classical Gram-Schmidt applied twice, for the G_
+// independent systems of the groups at once (one Krylov space each; the
+// operator is applied to all of them in one product).  Everything of an
+// Arnoldi step runs on the device, including each group's Hessenberg column
+// and Givens rotation, which leave the residual estimates |g_{j+1}| in
+// resid.  The host enqueues groups of steps, sized from the slowest group's
+// observed convergence rate, and keeps up to two in flight: it reads one
+// set of estimates (pinned memory, an event each) while the next runs, so
+// the GPU does not wait on the host between steps.  A group stops at its
+// first estimate <= tol_abs[g]; steps taken after that (for it, or for all
+// groups past the last one's) are discarded.  Returns the most iterations
+// any group used.
+int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std::vector<double>& tol_abs,
+                  int restart, int maxit, std::vector<double>& resid_out, hipStream_t s) {
+  const int m = restart, G = G_, R = m + 1, nbj = pdb_;
+  // pinned: H [G][m + 1][m], g [G][m + 1], y [G][m], rs [G][m], beta [G], 1/beta [G]
+  const size_t HS = (size_t)(m + 1) * m;
+  hbuf_.alloc((size_t)G * (HS + 3 * (size_t)m + 3));
   double* hH = hbuf_.p;
-  double* hg = hH + (size_t)m * m;
-  double* hy = hg + (m + 1);
-  double* rs = hy + m;
+  double* hg = hH + G * HS;
+  double* hy = hg + (size_t)G * (m + 1);
+  double* rs = hy + (size_t)G * m;
+  double* hb = rs + (size_t)G * m;
+  double* dH = gm_.p;
+  double* dcs = dH + G * HS;
+  double* dsn = dcs + (size_t)G * m;
+  double* dg = dsn + (size_t)G * m;
+  double* dres = dg + (size_t)G * (m + 1);
+  double* dbeta = dres + (size_t)G * m;
+  double* dy = dbeta + 2 * (size_t)G;
+  double* h1 = hdev_.p;
+  double* part1 = part_.p;
+  double* part2 = part_.p + (size_t)G * R * nbj;
   int iters = 0;
   if (x_zero) PBT_HIP(hipMemcpyAsync(r_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
   else {
     op(x, r_.p, fp32, s);
     launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
   }
-  double beta = norm(r_.p, s);
-  *resid_out = beta;
-  double* dH = gm_.p;
-  double* dcs = dH + (size_t)(m + 1) * m;
-  double* dsn = dcs + m;
-  double* dg = dsn + m;
-  double* dres = dg + (m + 1);
-  // steps still needed after the first `known` estimates, from the rate of
-  // the last few (a large number while there is no rate yet)
-  auto remaining = [&](int known) -> int {
-    if (known < 3) return 1 << 20;
-    const int d = std::min(known - 1, 4);
-    const double r1 = std::max(rs[known - 1], 1e-300), r0 = std::max(rs[known - 1 - d], 1e-300);
-    const double rate = std::pow(r1 / r0, 1.0 / d);
-    if (!(rate < 0.999)) return 4;
-    return (int)std::min(1e6, std::max(0.0, std::ceil(std::log(tol_abs / r1) / std::log(rate))));
+  std::vector<double> beta = group_norms(r_.p, s);
+  resid_out = beta;
+  auto pending = [&] {
+    for (int g = 0; g < G; ++g)
+      if (beta[g] > tol_abs[g]) return true;
+    return false;
   };
   struct Group { int beg, cnt, ev; };
-  while (beta > tol_abs && iters < maxit) {
-    launch_scale_copy(n_, 1.0 / beta, r_.p, V_.p, s);
-    launch_first_unit(m + 1, beta, dg, s);   // g = beta e_1
-    int j = 0, used = 0, known = 0, nev = 0;
-    bool done = false;
+  while (pending() && iters < maxit) {
+    std::vector<int> used(G, 0);
+    std::vector<char> done(G, 0);
+    for (int g = 0; g < G; ++g) {
+      done[g] = !(beta[g] > tol_abs[g]);
+      hb[g] = beta[g];
+      hb[G + g] = done[g] ? 0.0 : 1.0 / beta[g];
+    }
+    PBT_HIP(hipMemcpyAsync(dbeta, hb, 2 * G * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_start_cycle(dgu_.p, G, gmax_, m, dbeta, dbeta + G, r_.p, V_.p, dg, s);
+    // steps still needed after the first `known` estimates: the largest
+    // prediction over the groups still running, from the rate of their last
+    // few estimates (a large number while there is no rate yet)
+    auto remaining = [&](int known) -> int {
+      if (known < 3) return 1 << 20;
+      int need = 0;
+      for (int g = 0; g < G; ++g) {
+        if (done[g]) continue;
+        const double* r = rs + (size_t)g * m;
+        const int d = std::min(known - 1, 4);
+        const double r1 = std::max(r[known - 1], 1e-300), r0 = std::max(r[known - 1 - d], 1e-300);
+        const double rate = std::pow(r1 / r0, 1.0 / d);
+        const int ng = !(rate < 0.999) ? 4
+                     : (int)std::min(1e6, std::max(0.0, std::ceil(std::log(tol_abs[g] / r1) / std::log(rate))));
+        need = std::max(need, ng);
+      }
+      return need;
+    };
+    int j = 0, known = 0, nev = 0;
+    bool all_done = false;
     std::deque<Group> inflight;
     while (true) {
       while (inflight.size() < 2 && j < m && iters + j < maxit) {
@@ -744,53 +816,65 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, double tol
         for (int k = j; k < j + group; ++k) {
           double* vj1 = V_.p + (size_t)(k + 1) * n_;
           op(V_.p + (size_t)k * n_, vj1, fp32, s);
-          double* h1 = hdev_.p;
-          double* part1 = part_.p;
-          double* part2 = part_.p + (size_t)(m + 2) * pdb_;
           // pass 1: partial V^T w; pass 2: h1 = sum of pass 1, partial V^T w'
-          // and |w'|^2 with w' = w - V h1; then w = (w - V h) / |w''| with the
-          // Hessenberg column and its rotation
-          launch_gs_dots(n_, k + 1, V_.p, n_, vj1, nullptr, nullptr, 0, part1, pdb_, s);
-          launch_gs_dots(n_, k + 1, V_.p, n_, vj1, part1, h1, 1, part2, pdb_, s);
-          launch_arnoldi_update(n_, k, m, pdb_, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, dres, s);
+          // and |w'|^2 with w' = w - V h1; then w = (w - V h) / |w''| with
+          // each group's Hessenberg column and rotation
+          launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, nullptr, 0, part1, nbj, s);
+          launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, h1, 1, part2, nbj, s);
+          launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, dres, s);
         }
-        PBT_HIP(hipMemcpyAsync(rs + j, dres + j, group * sizeof(double), hipMemcpyDeviceToHost, s));
+        PBT_HIP(hipMemcpyAsync(rs, dres, (size_t)G * m * sizeof(double), hipMemcpyDeviceToHost, s));
         const int ev = nev++ & 1;
         PBT_HIP(hipEventRecord(evg_[ev], s));
         inflight.push_back({j, group, ev});
         j += group;
       }
       if (inflight.empty()) break;
-      const Group g = inflight.front();
+      const Group q = inflight.front();
       inflight.pop_front();
-      PBT_HIP(hipEventSynchronize(evg_[g.ev]));
-      for (int k = g.beg; k < g.beg + g.cnt; ++k) {
-        used = k + 1;
-        *resid_out = rs[k];
-        if (rs[k] <= tol_abs) { done = true; break; }
+      PBT_HIP(hipEventSynchronize(evg_[q.ev]));
+      all_done = true;
+      for (int g = 0; g < G; ++g) {
+        if (done[g]) continue;
+        for (int k = q.beg; k < q.beg + q.cnt; ++k) {
+          used[g] = k + 1;
+          resid_out[g] = rs[(size_t)g * m + k];
+          if (rs[(size_t)g * m + k] <= tol_abs[g]) {
+            done[g] = 1;
+            break;
+          }
+        }
+        all_done = all_done && done[g];
       }
-      known = g.beg + g.cnt;
-      if (done) break;
+      known = q.beg + q.cnt;
+      if (all_done) break;
     }
-    nwasted_ += j - used;
-    iters += used;
-    // x += V y with H(0:used,0:used) y = g(0:used); the H rows and g that
-    // are read were final before any step past `used` was enqueued
-    PBT_HIP(hipMemcpyAsync(hH, dH, (size_t)used * m * sizeof(double), hipMemcpyDeviceToHost, s));
-    PBT_HIP(hipMemcpyAsync(hg, dg, used * sizeof(double), hipMemcpyDeviceToHost, s));
+    int umax = 0;
+    for (int g = 0; g < G; ++g) umax = std::max(umax, used[g]);
+    nwasted_ += j - umax;
+    iters += umax;
+    // per group: x += V y with H(0:used,0:used) y = g(0:used); the H rows
+    // and g entries read were final before any later step was enqueued
+    PBT_HIP(hipMemcpyAsync(hH, dH, G * HS * sizeof(double), hipMemcpyDeviceToHost, s));
+    PBT_HIP(hipMemcpyAsync(hg, dg, (size_t)G * (m + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
     PBT_HIP(hipStreamSynchronize(s));
-    for (int i = used - 1; i >= 0; --i) {
-      double acc = hg[i];
-      for (int k = i + 1; k < used; ++k) acc -= hH[(size_t)i * m + k] * hy[k];
-      hy[i] = acc / hH[(size_t)i * m + i];
+    for (int g = 0; g < G; ++g) {
+      const double* Hg = hH + g * HS;
+      double* y = hy + (size_t)g * m;
+      std::fill(y, y + m, 0.0);
+      for (int i = used[g] - 1; i >= 0; --i) {
+        double acc = hg[(size_t)g * (m + 1) + i];
+        for (int k = i + 1; k < used[g]; ++k) acc -= Hg[(size_t)i * m + k] * y[k];
+        y[i] = acc / Hg[(size_t)i * m + i];
+      }
     }
-    PBT_HIP(hipMemcpyAsync(hdev_.p, hy, used * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_lincomb(n_, used, V_.p, n_, hdev_.p, x, s);
-    if (done || iters >= maxit) break;
+    PBT_HIP(hipMemcpyAsync(dy, hy, (size_t)G * m * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_lincomb(dgu_.p, G, gmax_, umax, m, V_.p, n_, dy, x, s);
+    if (all_done || iters >= maxit) break;
     op(x, r_.p, fp32, s);
     launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
-    beta = norm(r_.p, s);
-    *resid_out = beta;
+    beta = group_norms(r_.p, s);
+    resid_out = beta;
   }
   return iters;
 }
@@ -808,56 +892,76 @@ bool System::solve_t(const double* g, double* lam, pbt_result* res, hipStream_t 
   return ok;
 }
 
+// Each group is solved to ||b_g - A_g x_g|| <= tol ||b_g||; res->rel_resid
+// is the largest group's relative FP64 residual (group_rel() has them all).
 bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s) {
-  const int m = std::max(1, std::min<int>(prm_.restart, (int)std::max<int64_t>(n_, 1)));
+  ensure_groups(s);
+  const int G = G_;
+  const int m = std::max(1, std::min<int>(prm_.restart, (int)std::max<int64_t>(gmax_, 1)));
   if (restart_alloc_ != m || V_.n != (size_t)(m + 1) * n_) {
     V_.alloc((size_t)(m + 1) * n_);
     restart_alloc_ = m;
   }
-  w_.alloc(n_);
   r_.alloc(n_);
   tmp_.alloc(n_);
   y_.alloc(n_);
-  mdb_ = multidot_blocks(n_);
-  pdb_ = gs_blocks(n_);
-  part_.alloc((size_t)(m + 2) * std::max(mdb_, 2 * pdb_));
-  hdev_.alloc(2 * (m + 1) + 2);
-  gm_.alloc((size_t)(m + 1) * m + 4 * (m + 1) + 4);
+  pdb_ = gs_blocks(gmax_);
+  part_.alloc(2 * (size_t)G * (m + 1) * pdb_);
+  hdev_.alloc((size_t)G * (m + 1));
+  gm_.alloc((size_t)G * ((size_t)(m + 1) * m + 4 * (size_t)m + 3));
   if (!x0_given) PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));
-  const double bnorm = norm(b, s);
+  const std::vector<double> bn = group_norms(b, s);
   res->iters = 0;
   res->outer = 0;
   res->matvecs = 0;
-  if (bnorm == 0.0) {
+  const double tol = prm_.tol;
+  group_rel_.assign(G, 0.0);
+  auto relmax = [&](const std::vector<double>& rn) {
+    double r = 0;
+    for (int g = 0; g < G; ++g) {
+      group_rel_[g] = bn[g] > 0 ? rn[g] / bn[g] : 0.0;
+      r = std::max(r, group_rel_[g]);
+    }
+    return r;
+  };
+  bool any_b = false;
+  for (double v : bn) any_b = any_b || v > 0;
+  if (!any_b) {
     PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));
     res->rel_resid = 0.0;
     return true;
   }
-  const double tol = prm_.tol;
+  std::vector<double> est(G), tabs(G);
   double rel = 0.0;
   if (prm_.prec == PBT_FP64) {
-    double est = 0;
-    res->iters = gmres(false, b, x, !x0_given, tol * bnorm, m, prm_.max_iter, &est, s);
+    for (int g = 0; g < G; ++g) tabs[g] = tol * bn[g];
+    res->iters = gmres(false, b, x, !x0_given, tabs, m, prm_.max_iter, est, s);
     res->outer = 1;
     true_residual(b, x, tmp_.p, s);
-    rel = norm(tmp_.p, s) / bnorm;
+    rel = relmax(group_norms(tmp_.p, s));
   } else {
     // Iterative refinement: FP32-interaction GMRES on the FP64 residual.
     if (x0_given) true_residual(b, x, tmp_.p, s);
     else PBT_HIP(hipMemcpyAsync(tmp_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
-    double rn = norm(tmp_.p, s);
-    rel = rn / bnorm;
+    std::vector<double> rn = group_norms(tmp_.p, s);
+    rel = relmax(rn);
     for (int outer = 0; outer < 20 && rel > tol && res->iters < prm_.max_iter; ++outer) {
-      // The inner solve aims straight at the requested tolerance; the FP32
-      // operator's relative error (~1e-7) bounds how far that is meaningful.
-      const double tin = std::min(0.5, std::max(0.5 * tol * bnorm / rn, 2e-7));
-      double est = 0;
+      // Each running group's inner solve aims straight at the requested
+      // tolerance; the FP32 operator's relative error (~1e-7) bounds how far
+      // that is meaningful.  Groups already converged stay at rest.
+      for (int g = 0; g < G; ++g) {
+        if (!(bn[g] > 0) || rn[g] <= tol * bn[g]) {
+          tabs[g] = rn[g];
+          continue;
+        }
+        tabs[g] = std::min(0.5, std::max(0.5 * tol * bn[g] / rn[g], 2e-7)) * rn[g];
+      }
       PBT_HIP(hipMemsetAsync(y_.p, 0, n_ * sizeof(double), s));
-      res->iters += gmres(true, tmp_.p, y_.p, true, tin * rn, m, prm_.max_iter - res->iters, &est, s);
+      res->iters += gmres(true, tmp_.p, y_.p, true, tabs, m, prm_.max_iter - res->iters, est, s);
       launch_axpby(n_, 1.0, y_.p, 1.0, x, s);
       true_residual(b, x, tmp_.p, s);
-      rn = norm(tmp_.p, s);
-      rel = rn / bnorm;
+      rn = group_norms(tmp_.p, s);
+      rel = relmax(rn);
       res->outer = outer + 1;
     }
   }
@@ -945,40 +1049,6 @@ std::vector<pbt_result> System::energies_by_group(const double* x, int ngroups, 
   }
   for (auto& r : out) r.F_total = r.F_coul + r.F_solv + r.F_surf;
   return out;
-}
-
-std::vector<double> System::group_residuals(const double* b, const double* x, int ngroups, hipStream_t s) {
-  DBuf<double> r;
-  r.alloc(n_);
-  transpose_ = false;
-  true_residual(b, x, r.p, s);
-  std::vector<double> hr = r.download(s), hb(n_);
-  PBT_HIP(hipMemcpy(hb.data(), b, n_ * sizeof(double), hipMemcpyDeviceToHost));
-  std::vector<double> num(ngroups, 0.0), den(ngroups, 0.0);
-  for (size_t e = 0; e < surfs_.size(); ++e) {
-    const int g = surfs_[e]->group;
-    for (int64_t i = row_off_[e]; i < row_off_[e + 1]; ++i) {
-      num[g] += hr[i] * hr[i];
-      den[g] += hb[i] * hb[i];
-    }
-  }
-  std::vector<double> out(ngroups);
-  for (int g = 0; g < ngroups; ++g) out[g] = den[g] > 0 ? std::sqrt(num[g] / den[g]) : 0.0;
-  return out;
-}
-
-bool System::solve_tol(const double* b, double* x, double tol, pbt_result* res, hipStream_t s) {
-  const double saved = prm_.tol;
-  prm_.tol = tol;
-  bool ok = false;
-  try {
-    ok = solve(b, x, true, res, s);
-  } catch (...) {
-    prm_.tol = saved;
-    throw;
-  }
-  prm_.tol = saved;
-  return ok;
 }
 
 void System::unpack(const std::vector<double>& xh, int e, double* phi, double* dphidn) const {

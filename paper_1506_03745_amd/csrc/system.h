@@ -127,16 +127,15 @@ class System {
   // FP64 right-hand side for the current charges and boundary values.
   void rhs(double* b_dev, hipStream_t s);
   // Solves A x = b (b, x device); returns result fields (iters, outer,
-  // rel_resid, matvecs) and whether it converged.
+  // rel_resid, matvecs) and whether it converged.  The surface groups are
+  // independent systems: each is solved to its own relative tolerance and
+  // rel_resid is the largest group's (group_rel() lists them).
   bool solve(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s);
+  const std::vector<double>& group_rel() const { return group_rel_; }
   // Energies (kcal/mol) of solution x (device).
   void energies(const double* x, pbt_result* res, hipStream_t s);
   // Energies per group (index = group id), same units.
   std::vector<pbt_result> energies_by_group(const double* x, int ngroups, hipStream_t s);
-  // Relative residual of each group's block of b - A x (FP64 operator).
-  std::vector<double> group_residuals(const double* b, const double* x, int ngroups, hipStream_t s);
-  // Solves with a given relative tolerance (overrides params.tol).
-  bool solve_tol(const double* b, double* x, double tol, pbt_result* res, hipStream_t s);
   // Host copy of a surface's solution in caller order.
   void unpack(const std::vector<double>& xh, int local_surface, double* phi, double* dphidn) const;
   int local_index(int surface_id) const;
@@ -184,8 +183,10 @@ class System {
              bool timed = false);
   template <typename T>
   void interactions(hipStream_t s, const double* x, bool timed);
-  int gmres(bool fp32, const double* b, double* x, bool x_zero, double tol_abs, int restart,
-            int maxit, double* resid_out, hipStream_t s);
+  int gmres(bool fp32, const double* b, double* x, bool x_zero, const std::vector<double>& tol_abs,
+            int restart, int maxit, std::vector<double>& resid_out, hipStream_t s);
+  void ensure_groups(hipStream_t s);
+  std::vector<double> group_norms(const double* v, hipStream_t s);
   void true_residual(const double* b, const double* x, double* r, hipStream_t s);
   void op(const double* x, double* y, bool fp32, hipStream_t s) {
     if (transpose_) matvec_t(x, y, fp32, nullptr, s);
@@ -199,7 +200,6 @@ class System {
   // Per-surface (F_coul, F_solv, F_surf) in reduced units.
   std::vector<std::array<double, 3>> surface_energies(const double* x, hipStream_t s);
   std::vector<double> reaction_potential(int e, hipStream_t s);  // densities already set
-  double norm(const double* v, hipStream_t s);
 
   // Device copies of what the right-hand side and the energies need from
   // the surfaces' inputs, rebuilt when a surface's version changes.
@@ -238,9 +238,7 @@ class System {
   DBuf<double> dens_scale_, rlap_;
   DBuf<double> sig_, mu_;
   NearCSR near_;
-  DBuf<int32_t> panel_surf_, panel_group_;
-  DBuf<int64_t> group_range_;
-  int ngroups_ = 1;
+  DBuf<int32_t> panel_surf_;
   DBuf<int32_t> surf_mol_;
   DBuf<double> surf_rhoinv_;
   std::vector<int32_t> h_panel_orig_;  // internal global -> original index within its surface
@@ -268,8 +266,14 @@ class System {
 
   // Krylov workspace
   int restart_alloc_ = 0;
-  DBuf<double> V_, w_, r_, tmp_, hdev_, part_, y_, gm_;
-  int mdb_ = 1, pdb_ = 1;
+  DBuf<double> V_, r_, tmp_, hdev_, part_, y_, gm_, nrm_part_;
+  int pdb_ = 1;
+  // groups of surfaces = independent systems solved side by side
+  int G_ = 1;
+  int64_t gmax_ = 0;                 // unknowns of the largest group
+  std::vector<int64_t> gu_;          // [2G] unknown range of each group
+  DBuf<int64_t> dgu_;
+  std::vector<double> group_rel_;    // last solve: relative residual per group
 
   hipEvent_t ev_[6];
   hipStream_t s2_ = nullptr;   // far-field stream (moments, M2P), overlaps P2P
