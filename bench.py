@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-fd", action="store_true",
+                    help="star_plate_large: skip the central-difference check of the gradient")
     ap.add_argument("--autotune-cache", default=None,
                     help="text cache of tuned launch shapes (read if present, appended otherwise)")
     return ap.parse_args()
@@ -91,12 +93,134 @@ def cpu_baseline(problem, budget_s=15.0):
                       f"(rows of the dense FP64 operator), {t_used:.1f} s"}
 
 
+WORKLOADS = {
+    "twosphere_charge": "two spheres r=4 A, 2x5120 panels, R=12 A, sigma 0.05 C/m^2, eps 4/80, kappa 0.125",
+    "twosphere_potential": "two spheres r=4 A, 2x5120 panels, R=12 A, phi0 0.05 V, eps 4/80, kappa 0.125",
+    "kirkwood": "sphere r=4 A, 1280 panels, +1 e at the centre, eps 4/80, kappa 0.125",
+    "star_plate": "star molecule 32768 panels + 900 charges, 10 A above a 80x80x2 A plate of 20480 panels "
+                  "(sigma -0.05 C/m^2), eps 4/80, kappa 0.125",
+    "orient_sweep": "64 rigid rotations of a 5120-panel sphere molecule (+1 e) 10 A above the 20480-panel "
+                    "plate, solved together (one Krylov space each)",
+    "star_plate_large": "star molecule 65536 panels + 3000 charges, 12 A above a 120x120x2 A plate of 81920 "
+                        "panels; gradient of F_int w.r.t. the plate's sigma and the charges",
+}
+PRM = dict(theta=0.5, taylor_p=6, ncrit=300, k_far=3, k_near=19, k_self_edge=9, tol=1e-6)
+
+
+def common_fields(a, ms_step):
+    return {"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 interactions + f64 Krylov/refinement", "data": "synthetic"}
+
+
+def bench_batch(a):
+    """Orientation sweep: one step = pbt_solve_batch of 64 placements (the
+    isolated energies included), FP32 interactions in FP64 refinement."""
+    import numpy as np
+    from paper_1506_03745_amd import MIXED, from_problem
+    from workloads.problems import config_problem, random_rotations
+    pr = config_problem("orient_sweep")
+    s, ids = from_problem(pr, prec=MIXED, **PRM)
+    s.prepare()
+    R = random_rotations(64, 3)
+    c = pr.surfaces[0].q_pos[0]
+    T = c[None, :] - R @ c            # rotations about the molecule's centre
+    for _ in range(max(a.warmup, 1)):
+        s.solve_batch(ids[0], R.reshape(64, 9), T)
+    t0 = time.perf_counter()
+    stats, f = [], None
+    for _ in range(a.steps):
+        f = s.solve_batch(ids[0], R.reshape(64, 9), T)
+        stats.append(s.last_stats())
+    dt = (time.perf_counter() - t0) / a.steps
+    pairs = sum(x.dense_pairs for x in stats) / len(stats)
+    st = stats[-1]
+    out = {"metric": "treecode BEM matvec Ginteractions/s + GMRES time to 1e-6 resid, FP32 vs FP64",
+           "value": round(pairs / dt / 1e9, 3), "unit": "Ginteractions/s", **common_fields(a, 1e3 * dt),
+           "config": {"workload": f"orient_sweep: {WORKLOADS['orient_sweep']}", "placements": 64,
+                      "unknowns_per_placement": s.num_unknowns(), **{k: v for k, v in PRM.items()},
+                      "precision": "mixed"},
+           "roofline": None,
+           "batch": {"ms_per_placement": round(1e3 * dt / 64, 3), "iters_max": st.iters,
+                     "operator_applications": st.matvecs, "setup_s": round(st.t_setup_s, 4),
+                     "F_int_kcal": {"min": float(f.min()), "max": float(f.max()), "mean": float(f.mean())}}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_gradient(a):
+    """Adjoint gradient at large size: one step = pbt_gradient (three forward
+    and three transposed solves); then central differences of F_int on 20
+    random plate panels and 5 charges (F_int is exactly quadratic in them)."""
+    import numpy as np
+    from paper_1506_03745_amd import MIXED, from_problem
+    from workloads.problems import config_problem
+    pr = config_problem("star_plate_large")
+    mol, plate = pr.surfaces
+    s, ids = from_problem(pr, prec=MIXED, **PRM)
+    s.prepare()
+    if not a.no_autotune:
+        s.autotune(a.autotune_cache)
+    s.gradient(ids[1], plate.nt, ids[0], len(mol.q))
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(a.steps):
+        ds, dq = s.gradient(ids[1], plate.nt, ids[0], len(mol.q))
+        stats.append(s.last_stats())
+    dt = (time.perf_counter() - t0) / a.steps
+    pairs = sum(x.dense_pairs for x in stats) / len(stats)
+    out = {"metric": "treecode BEM matvec Ginteractions/s + GMRES time to 1e-6 resid, FP32 vs FP64",
+           "value": round(pairs / dt / 1e9, 3), "unit": "Ginteractions/s", **common_fields(a, 1e3 * dt),
+           "config": {"workload": f"star_plate_large: {WORKLOADS['star_plate_large']}",
+                      "unknowns": s.num_unknowns(), **PRM, "precision": "mixed"},
+           "roofline": None,
+           "gradient": {"ms": round(1e3 * dt, 2), "operator_applications": stats[-1].matvecs,
+                        "max_abs_dF_dsigma": float(np.abs(ds).max()), "max_abs_dF_dq": float(np.abs(dq).max())}}
+    if not a.no_fd:
+        tight = dict(PRM, tol=1e-10)
+        f, fids = from_problem(pr, prec=MIXED, **tight)
+        gs, gq = f.gradient(fids[1], plate.nt, fids[0], len(mol.q))
+
+        def fint(q, sig):
+            f.set_charges(fids[0], mol.eps_in, mol.q_pos, q)
+            f.set_bc(fids[1], sig)
+            return f.interaction_energy(2)[0]
+
+        rng = np.random.default_rng(6)
+        q0, s0 = mol.q.copy(), plate.bc.copy()
+        err_s, err_q = 0.0, 0.0
+        for j in rng.choice(plate.nt, 20, replace=False):
+            sp, sm = s0.copy(), s0.copy()
+            sp[j] += 0.05
+            sm[j] -= 0.05
+            fd = (fint(q0, sp) - fint(q0, sm)) / 0.1
+            err_s = max(err_s, abs(fd - gs[j]))
+            print(f"fd panel {j}: {fd:.6e} adjoint {gs[j]:.6e}", file=sys.stderr, flush=True)
+        for k in rng.choice(len(q0), 5, replace=False):
+            qp, qm = q0.copy(), q0.copy()
+            qp[k] += 0.5
+            qm[k] -= 0.5
+            fd = (fint(qp, s0) - fint(qm, s0)) / 1.0
+            err_q = max(err_q, abs(fd - gq[k]))
+            print(f"fd charge {k}: {fd:.6e} adjoint {gq[k]:.6e}", file=sys.stderr, flush=True)
+        out["gradient"]["central_differences"] = {
+            "panels": 20, "charges": 5, "tol": 1e-10, "seed": 6,
+            "max_err_rel_dF_dsigma": err_s / float(np.abs(gs).max()),
+            "max_err_rel_dF_dq": err_q / float(np.abs(gq).max()),
+            "mixed_vs_tight_rel_dF_dsigma": float(np.abs(ds - gs).max() / np.abs(gs).max()),
+            "mixed_vs_tight_rel_dF_dq": float(np.abs(dq - gq).max() / np.abs(gq).max())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
               f"(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "orient_sweep":
+        return bench_batch(a)
+    if a.workload == "star_plate_large":
+        return bench_gradient(a)
     import numpy as np
     import torch
 
@@ -110,7 +234,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     problem = config_problem(a.workload)
-    prm = dict(theta=0.5, taylor_p=6, ncrit=300, k_far=3, k_near=19, k_self_edge=9, tol=1e-6)
+    prm = PRM
 
     # ---- mixed precision (the benchmarked path) -----------------------------
     s32, _ = from_problem(problem, prec=MIXED, **prm)
@@ -161,8 +285,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 interactions + f64 Krylov/refinement",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload}: two spheres r=4 A, 2x5120 panels, R=12 A, "
-                               f"sigma 0.05 C/m^2, eps 4/80, kappa 0.125",
+        "config": {"workload": f"{a.workload}: {WORKLOADS.get(a.workload, a.workload)}",
                    "panels": sum(s.nt for s in problem.surfaces), "unknowns": n,
                    "theta": 0.5, "taylor_p": 6, "ncrit": 300, "k_far": 3, "k_near": 19,
                    "self_per_edge": 9, "tol": 1e-6, "precision": "mixed"},

@@ -207,6 +207,15 @@ pbt_status pbt_solve_batch(pbt_ctx* ctx, int32_t mol_id, const double* rot, cons
  * cache_path is not NULL, in that text file. */
 pbt_status pbt_autotune(pbt_ctx* ctx, const char* cache_path);
 
+/* Work of the last pbt_solve, pbt_interaction_energy, pbt_gradient or
+ * pbt_solve_batch call, in a pbt_result whose energy fields are zero:
+ * iters = most GMRES iterations of one solve, matvecs = operator
+ * applications (forward and transposed, every system the call solved),
+ * dense_pairs = the dense-equivalent target x Gauss-point pairs of all those
+ * applications together, t_setup_s = time spent building systems,
+ * t_solve_s = wall time of the whole call.  Host-only. */
+pbt_status pbt_last_stats(pbt_ctx* ctx, pbt_result* out);
+
 /* Sets the schedule of the far field against P2P for the enabled system
  * (Section 3.2 splits every product into near-field P2P and far-field
  * P2M/M2M/M2P): 0 = P2P then the far field on the context's stream,

@@ -1,6 +1,7 @@
 // C entry points of the pbt library (declared in include/pbt.h).
-#include <chrono>
 #include <algorithm>
+#include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -24,6 +25,14 @@ struct pbt_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool frozen = false;
+  // work of the last solve / interaction_energy / gradient / solve_batch call
+  struct CallStats {
+    double t0 = 0, t_setup = 0;
+    int64_t apps = 0, pairs = 0;
+    int32_t iters = 0;
+    std::map<const System*, int64_t> start;
+  } cs;
+  pbt_result last_stats{};
   // last solution
   std::vector<bool> sol_mask;
   std::vector<double> sol_x;
@@ -31,6 +40,17 @@ struct pbt_ctx {
 };
 
 namespace {
+
+double wall_now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Adds the operator applications system S made since it stood at apps0.
+void stats_account(pbt_ctx* c, const System& S, int64_t apps0) {
+  const int64_t d = S.applications() - apps0;
+  c->cs.apps += d;
+  c->cs.pairs += d * S.dense_pairs();
+}
 
 pbt_status fail(pbt_ctx* c, int st, const std::string& m) {
   if (c) c->err = m;
@@ -53,6 +73,28 @@ pbt_status guarded(pbt_ctx* c, F&& f) {
   } catch (const std::exception& e) {
     return fail(c, PBT_E_DEVICE, e.what());
   }
+}
+
+// guarded() plus the work counters read by pbt_last_stats.
+template <typename F>
+pbt_status tracked(pbt_ctx* c, F&& f) {
+  if (!c) return PBT_E_INVALID;
+  c->cs = pbt_ctx::CallStats{};
+  c->cs.t0 = wall_now();
+  for (auto& kv : c->systems) c->cs.start[kv.second.get()] = kv.second->applications();
+  const pbt_status st = guarded(c, f);
+  for (auto& kv : c->systems) {
+    auto it = c->cs.start.find(kv.second.get());
+    stats_account(c, *kv.second, it == c->cs.start.end() ? 0 : it->second);
+  }
+  pbt_result r{};
+  r.iters = c->cs.iters;
+  r.matvecs = (int32_t)std::min<int64_t>(c->cs.apps, INT32_MAX);
+  r.dense_pairs = c->cs.pairs;
+  r.t_setup_s = c->cs.t_setup;
+  r.t_solve_s = wall_now() - c->cs.t0;
+  c->last_stats = r;
+  return st;
 }
 
 std::string check_params(const pbt_params& p) {
@@ -87,7 +129,9 @@ System& system_for(pbt_ctx* c) {
   for (const SurfIn* s : on)
     if (s->kind == PBT_MOLECULE && !(s->eps_in > 0)) throw Error(PBT_E_STATE, "molecule without eps_in");
   c->frozen = true;
+  const double t0 = wall_now();
   auto sys = std::make_unique<System>(on, c->prm, c->eps_out, c->kappa, c->stream);
+  c->cs.t_setup += wall_now() - t0;
   System& r = *sys;
   c->systems[m] = std::move(sys);
   return r;
@@ -122,6 +166,7 @@ pbt_status solve_impl(pbt_ctx* c, const double* x0, pbt_result* res) {
   r.dense_pairs = S.dense_pairs();
   r.p2p_fused_pairs = S.plan().p2p_fused_pairs;
   r.matvecs = (int32_t)(S.applications() - apply0);
+  c->cs.iters = std::max(c->cs.iters, r.iters);
   c->sol_x.resize(n);
   PBT_HIP(hipMemcpy(c->sol_x.data(), c->dx.p, n * sizeof(double), hipMemcpyDeviceToHost));
   c->sol_mask = mask_of(c);
@@ -305,7 +350,7 @@ pbt_status pbt_num_unknowns(pbt_ctx* c, int64_t* n) {
 }
 
 pbt_status pbt_solve(pbt_ctx* c, const double* x0, pbt_result* res) {
-  return guarded(c, [&] { return solve_impl(c, x0, res); });
+  return tracked(c, [&] { return solve_impl(c, x0, res); });
 }
 
 pbt_status pbt_get_solution(pbt_ctx* c, int32_t id, double* phi, double* dphidn) {
@@ -324,7 +369,7 @@ pbt_status pbt_get_solution(pbt_ctx* c, int32_t id, double* phi, double* dphidn)
 }
 
 pbt_status pbt_interaction_energy(pbt_ctx* c, double* F_int, pbt_result* parts) {
-  return guarded(c, [&] {
+  return tracked(c, [&] {
     const int ns = (int)c->surfs.size();
     std::vector<bool> saved = mask_of(c);
     pbt_status worst = PBT_OK;
@@ -423,7 +468,7 @@ static pbt_status system_gradient(pbt_ctx* c, int mol, int sig, std::vector<doub
 }
 
 pbt_status pbt_gradient(pbt_ctx* c, int32_t sigma_id, double* dF_dsigma, int32_t mol_id, double* dF_dq) {
-  return guarded(c, [&] {
+  return tracked(c, [&] {
     const int ns = (int)c->surfs.size();
     if (sigma_id >= ns || mol_id >= ns || (sigma_id < 0 && mol_id < 0))
       return fail(c, PBT_E_INVALID, "bad surface ids");
@@ -478,7 +523,7 @@ pbt_status pbt_gradient(pbt_ctx* c, int32_t sigma_id, double* dF_dsigma, int32_t
 // is the same problem up to rounding and, with the treecode, its tree).
 pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const double* shift, int32_t nb,
                            double* F_int) {
-  return guarded(c, [&] {
+  return tracked(c, [&] {
     const int ns = (int)c->surfs.size();
     if (mol_id < 0 || mol_id >= ns || c->surfs[mol_id]->kind != PBT_MOLECULE)
       return fail(c, PBT_E_INVALID, "mol_id must name a molecule");
@@ -542,7 +587,9 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
           own.push_back(std::move(o));
         }
       }
+      const double ts = wall_now();
       System S(list, c->prm, c->eps_out, c->kappa, c->stream);
+      c->cs.t_setup += wall_now() - ts;
       const int64_t n = S.n();
       DBuf<double> b, x;
       b.alloc(n);
@@ -551,8 +598,10 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
       // one Krylov space per placement, each to the requested tolerance
       pbt_result r{};
       if (!S.solve(b.p, x.p, false, &r, c->stream)) worst = PBT_E_NOCONVERGE;
+      c->cs.iters = std::max(c->cs.iters, r.iters);
       std::vector<pbt_result> e = S.energies_by_group(x.p, G, c->stream);
       for (int g = 0; g < G; ++g) F_int[b0 + g] = e[g].F_total - f_iso;
+      stats_account(c, S, 0);
     }
     if (worst != PBT_OK) return fail(c, worst, "a batched solve did not reach the tolerance");
     return PBT_OK;
@@ -623,6 +672,12 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
     }
     return PBT_OK;
   });
+}
+
+pbt_status pbt_last_stats(pbt_ctx* c, pbt_result* out) {
+  if (!c || !out) return PBT_E_INVALID;
+  *out = c->last_stats;
+  return PBT_OK;
 }
 
 pbt_status pbt_set_schedule(pbt_ctx* c, int32_t mode) {
