@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
 
 #include "quadrature.h"
 
@@ -69,6 +70,12 @@ void System::build(hipStream_t s) {
   np_ = poff_[ns];
   n_ = col_off_[ns];
   ns_ = np_ * K_;
+  {
+    std::map<int, int64_t> gp;   // panels per group
+    for (int e = 0; e < ns; ++e) gp[surfs_[e]->group] += surfs_[e]->nt;
+    dense_pairs_ = 0;
+    for (const auto& kv : gp) dense_pairs_ += kv.second * kv.second * K_;
+  }
 
   // ---- internal-order triangles ---------------------------------------------
   std::vector<double> tri9(9 * np_);
@@ -776,6 +783,16 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
     return false;
   };
   struct Group { int beg, cnt, ev; };
+  // one Arnoldi step: w = A V_k, then pass 1 (partial V^T w), pass 2 (h1 =
+  // sum of pass 1, partial V^T w' and |w'|^2 with w' = w - V h1), then
+  // w = (w - V h) / |w''| with each group's Hessenberg column and rotation
+  auto enqueue_step = [&](int k) {
+    double* vj1 = V_.p + (size_t)(k + 1) * n_;
+    op(V_.p + (size_t)k * n_, vj1, fp32, s);
+    launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, nullptr, 0, part1, nbj, s);
+    launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, h1, 1, part2, nbj, s);
+    launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, dres, s);
+  };
   while (pending() && iters < maxit) {
     std::vector<int> used(G, 0);
     std::vector<char> done(G, 0);
@@ -813,16 +830,7 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
         if (!inflight.empty() && want <= 0) break;   // no speculation past the predicted end
         want = std::max(1, std::min(want, known < 3 ? (j == 0 ? 2 : 4) : 8));
         const int group = std::min({want, m - j, maxit - iters - j});
-        for (int k = j; k < j + group; ++k) {
-          double* vj1 = V_.p + (size_t)(k + 1) * n_;
-          op(V_.p + (size_t)k * n_, vj1, fp32, s);
-          // pass 1: partial V^T w; pass 2: h1 = sum of pass 1, partial V^T w'
-          // and |w'|^2 with w' = w - V h1; then w = (w - V h) / |w''| with
-          // each group's Hessenberg column and rotation
-          launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, nullptr, 0, part1, nbj, s);
-          launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, h1, 1, part2, nbj, s);
-          launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, dres, s);
-        }
+        for (int k = j; k < j + group; ++k) enqueue_step(k);
         PBT_HIP(hipMemcpyAsync(rs, dres, (size_t)G * m * sizeof(double), hipMemcpyDeviceToHost, s));
         const int ev = nev++ & 1;
         PBT_HIP(hipEventRecord(evg_[ev], s));

@@ -118,7 +118,9 @@ class System {
 
   int64_t n() const { return n_; }
   int64_t np() const { return np_; }
-  int64_t dense_pairs() const { return np_ * ns_; }
+  // Target x Gauss-point pairs a dense product evaluates: every target
+  // against every source of its own group (independent systems do not pair).
+  int64_t dense_pairs() const { return dense_pairs_; }
   const Plan& plan() const { return plan_; }
 
   // y = A x on device buffers (n doubles each), FP64 or FP32 interactions;
@@ -270,6 +272,7 @@ class System {
   int pdb_ = 1;
   // groups of surfaces = independent systems solved side by side
   int G_ = 1;
+  int64_t dense_pairs_ = 0;
   int64_t gmax_ = 0;                 // unknowns of the largest group
   std::vector<int64_t> gu_;          // [2G] unknown range of each group
   DBuf<int64_t> dgu_;
