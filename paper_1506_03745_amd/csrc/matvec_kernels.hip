@@ -101,16 +101,16 @@ __global__ void k_strengths_x(int64_t ns, int K, PanelMaps m, const double* __re
 
 #include "near_field.h"
 
-// One wavefront per P2P task (four per block).
+// One wavefront per pair of P2P tasks (four per block).
 template <typename T, bool GUARD>
-__global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int ntasks,
+__global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int npairs,
                                              const int32_t* __restrict__ ranges,
                                              const T* __restrict__ tgt, const T* __restrict__ src,
                                              T kappa, T* __restrict__ partial) {
   __shared__ SrcRec<T> tiles[4][64];
   const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
-  if (wv >= ntasks) return;
-  p2p_task<T, GUARD>(tasks[wv], tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, partial);
+  if (wv >= npairs) return;
+  p2p_task_pair<T, GUARD>(tasks + 2 * wv, tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, partial);
 }
 
 // Sum the partial slots of every target, scale by 1/(4 pi), add the near and
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int
 constexpr int kCombineWaves = 16;
 template <typename T>
 __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, const T* __restrict__ partial,
-                                                              double* y) {
+                                                              const T* __restrict__ ppartial, double* y) {
   __shared__ double red[kCombineWaves][4][64];
   const ChunkSlots cs = a.chunks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -133,6 +133,13 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
     for (int s = cs.sbeg + w; s < cs.send; s += kCombineWaves) {
       l += (double)partial[2 * ((int64_t)s * 64 + lane) + 0];
       yy += (double)partial[2 * ((int64_t)s * 64 + lane) + 1];
+    }
+    const int hl = lane & 31;
+    const int pb = lane < 32 ? cs.hbeg0 : cs.hbeg1, pe = lane < 32 ? cs.hend0 : cs.hend1;
+#pragma unroll 4
+    for (int s = pb + w; s < pe; s += kCombineWaves) {
+      l += (double)ppartial[2 * ((int64_t)s * 32 + hl) + 0];
+      yy += (double)ppartial[2 * ((int64_t)s * 32 + hl) + 1];
     }
 #pragma unroll 2
     for (int64_t e = a.near_ptr[i] + w; e < a.near_ptr[i + 1]; e += kCombineWaves) {
@@ -251,21 +258,21 @@ void launch_strengths_x(int64_t ns, int K, const PanelMaps& m, const double* x, 
 }
 
 template <typename T>
-void launch_p2p(const Task* tasks, int ntasks, const int32_t* ranges, const T* tgt, const T* src,
+void launch_p2p(const Task* tasks, int npairs, const int32_t* ranges, const T* tgt, const T* src,
                 T kappa, bool guard, T* partial, hipStream_t s) {
-  if (ntasks <= 0) return;
-  const int blocks = ((ntasks + 3) / 4 + 7) / 8 * 8;
+  if (npairs <= 0) return;
+  const int blocks = ((npairs + 3) / 4 + 7) / 8 * 8;
   if (guard)
-    k_p2p<T, true><<<blocks, 256, 0, s>>>(tasks, ntasks, ranges, tgt, src, kappa, partial);
+    k_p2p<T, true><<<blocks, 256, 0, s>>>(tasks, npairs, ranges, tgt, src, kappa, partial);
   else
-    k_p2p<T, false><<<blocks, 256, 0, s>>>(tasks, ntasks, ranges, tgt, src, kappa, partial);
+    k_p2p<T, false><<<blocks, 256, 0, s>>>(tasks, npairs, ranges, tgt, src, kappa, partial);
   PBT_HIP(hipGetLastError());
 }
 
 template <typename T>
-void launch_combine(const CombineArgs& a, const T* partial, double* y, hipStream_t s) {
+void launch_combine(const CombineArgs& a, const T* partial, const T* ppartial, double* y, hipStream_t s) {
   if (a.np <= 0 || a.nchunks <= 0) return;
-  k_combine<T><<<a.nchunks, 64 * kCombineWaves, 0, s>>>(a, partial, y);
+  k_combine<T><<<a.nchunks, 64 * kCombineWaves, 0, s>>>(a, partial, ppartial, y);
   PBT_HIP(hipGetLastError());
 }
 
@@ -281,7 +288,7 @@ template void launch_p2p<float>(const Task*, int, const int32_t*, const float*, 
                                 bool, float*, hipStream_t);
 template void launch_p2p<double>(const Task*, int, const int32_t*, const double*, const double*,
                                  double, bool, double*, hipStream_t);
-template void launch_combine<float>(const CombineArgs&, const float*, double*, hipStream_t);
-template void launch_combine<double>(const CombineArgs&, const double*, double*, hipStream_t);
+template void launch_combine<float>(const CombineArgs&, const float*, const float*, double*, hipStream_t);
+template void launch_combine<double>(const CombineArgs&, const double*, const double*, double*, hipStream_t);
 
 }  // namespace pbt

@@ -35,6 +35,29 @@ struct alignas(8 * sizeof(T)) SrcRec {
   T v[8];
 };
 
+// A record read back from LDS in 16-byte pieces (two for FP32, four for
+// FP64), whatever the compiler knows about the base pointer's alignment.
+typedef float pbt_f4 __attribute__((ext_vector_type(4)));
+typedef double pbt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ SrcRec<float> load_rec(const SrcRec<float>* p) {
+  const pbt_f4* q = reinterpret_cast<const pbt_f4*>(p);
+  const pbt_f4 a = q[0], b = q[1];
+  SrcRec<float> r;
+  r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
+  r.v[4] = b.x; r.v[5] = b.y; r.v[6] = b.z; r.v[7] = b.w;
+  return r;
+}
+__device__ __forceinline__ SrcRec<double> load_rec(const SrcRec<double>* p) {
+  const pbt_d2* q = reinterpret_cast<const pbt_d2*>(p);
+  SrcRec<double> r;
+  for (int k = 0; k < 4; ++k) {
+    const pbt_d2 a = q[k];
+    r.v[2 * k] = a.x;
+    r.v[2 * k + 1] = a.y;
+  }
+  return r;
+}
+
 // Wave-scope ordering of LDS writes and reads between the lanes of one
 // wavefront (no workgroup barrier: the waves of a block run independent
 // tasks with different trip counts).
@@ -68,49 +91,55 @@ __device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int cnt, T tx, T
   int j = 0;
   for (; j + 8 <= cnt; j += 8) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) p2p_pair<T, GUARD, FUSED>(tile[j + q], tx, ty, tz, kappa, ck, l, yy);
+    for (int q = 0; q < 8; ++q) p2p_pair<T, GUARD, FUSED>(load_rec(tile + j + q), tx, ty, tz, kappa, ck, l, yy);
   }
-  for (; j < cnt; ++j) p2p_pair<T, GUARD, FUSED>(tile[j], tx, ty, tz, kappa, ck, l, yy);
+  for (; j < cnt; ++j) p2p_pair<T, GUARD, FUSED>(load_rec(tile + j), tx, ty, tz, kappa, ck, l, yy);
 }
 
-// One P2P task (Task: 64 targets x a list of source ranges) on one
-// wavefront, one target per lane.  The task's source ranges are staged, 64
-// records at a time, into the wave's own LDS tile with one coalesced load per
-// lane; every lane then reads the same record (an LDS broadcast), so the
-// loads of successive records pipeline in order.
+// A pair of P2P tasks on one wavefront: lanes 0..31 serve tasks[0], lanes
+// 32..63 tasks[1] (each up to 32 targets, one per lane, with its own source
+// ranges; both have the same `fused`).  Each round, each half stages its next
+// 32 source records into its half of the wave's LDS tile with one coalesced
+// load per lane, padding with zero-strength records far away (they add
+// exactly zero); every lane then reads its half's records in turn (an LDS
+// broadcast per half), so the loads pipeline in order.  Partials [slot][32][2].
 template <typename T, bool GUARD>
-__device__ __forceinline__ void p2p_task(const Task& task, SrcRec<T>* tile, const int32_t* __restrict__ ranges,
-                                         const T* __restrict__ tgt, const T* __restrict__ src, T kappa,
-                                         T* __restrict__ partial) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void p2p_task_pair(const Task* __restrict__ tp, SrcRec<T>* tile,
+                                              const int32_t* __restrict__ ranges, const T* __restrict__ tgt,
+                                              const T* __restrict__ src, T kappa, T* __restrict__ partial) {
+  const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
   const SrcRec<T>* srec = reinterpret_cast<const SrcRec<T>*>(src);
-  const int tbeg = task.tbeg, tcount = task.tcount;
-  const int lbeg = task.lbeg, lend = task.lend;
-  const int fused = task.fused;
-  const int ti = tbeg + (lane < tcount ? lane : 0);
+  const Task t = tp[half];
+  const int fused = tp[0].fused;
+  const int rounds = (max(tp[0].nsrc, tp[1].nsrc) + 31) >> 5;
+  const int ti = t.tbeg + (hl < t.tcount ? hl : 0);
   const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
   const T ck = KMath<T>::expk_const(kappa);
+  SrcRec<T> pad;
+  for (int d = 0; d < 8; ++d) pad.v[d] = d < 3 ? T(1e18) : T(0);
+  SrcRec<T>* mine = tile + 32 * half;
   T l = 0, yy = 0;
-  int r = lbeg;
-  int cur = r < lend ? ranges[2 * r] : 0;
-  while (r < lend) {
-    // fill: up to 64 records from the remaining ranges, in order
+  int r = t.lbeg;
+  int cur = r < t.lend ? ranges[2 * r] : 0;
+  for (int round = 0; round < rounds; ++round) {
+    // fill: up to 32 records of this half's remaining ranges, in order
     int cnt = 0;
-    while (r < lend && cnt < 64) {
+    while (r < t.lend && cnt < 32) {
       const int end = ranges[2 * r + 1];
-      const int take = min(end - cur, 64 - cnt);
-      if (lane >= cnt && lane < cnt + take) tile[lane] = srec[cur + (lane - cnt)];
+      const int take = min(end - cur, 32 - cnt);
+      if (hl >= cnt && hl < cnt + take) mine[hl] = srec[cur + (hl - cnt)];
       cnt += take;
       cur += take;
-      if (cur == end && ++r < lend) cur = ranges[2 * r];
+      if (cur == end && ++r < t.lend) cur = ranges[2 * r];
     }
+    if (hl >= cnt) mine[hl] = pad;
     wave_lds_sync();
-    if (fused) p2p_tile<T, GUARD, true>(tile, cnt, tx, ty, tz, kappa, ck, l, yy);
-    else p2p_tile<T, GUARD, false>(tile, cnt, tx, ty, tz, kappa, ck, l, yy);
+    if (fused) p2p_tile<T, GUARD, true>(mine, 32, tx, ty, tz, kappa, ck, l, yy);
+    else p2p_tile<T, GUARD, false>(mine, 32, tx, ty, tz, kappa, ck, l, yy);
     wave_lds_sync();
   }
-  if (lane < tcount) {
-    partial[2 * ((int64_t)task.slot * 64 + lane) + 0] = l;
-    partial[2 * ((int64_t)task.slot * 64 + lane) + 1] = yy;
+  if (hl < t.tcount) {
+    partial[2 * ((int64_t)t.slot * 32 + hl) + 0] = l;
+    partial[2 * ((int64_t)t.slot * 32 + hl) + 1] = yy;
   }
 }

@@ -28,20 +28,26 @@ struct Error : std::runtime_error {
 // [lbeg, lend) of source ranges (P2P) or source boxes (M2P), and writes its
 // partial (L, Y) sums for its lanes into partial slot `slot`.
 // ---------------------------------------------------------------------------
+// A work item of the interaction kernels: targets tbeg .. tbeg+tcount-1
+// against the source ranges (P2P) or boxes (M2P) lbeg .. lend-1.  An M2P
+// task holds up to 64 targets (one per lane); a P2P task up to 32 (half a
+// wavefront: P2P tasks come in pairs, one per half).
 struct Task {
   int32_t tbeg;    // first target (internal order)
-  int32_t tcount;  // 1..64
+  int32_t tcount;  // 0..64 (M2P), 0..32 (P2P; 0 = an empty half)
   int32_t lbeg, lend;
   int32_t slot;    // partial-sum slot
   int32_t fused;   // 1: Laplace interior row + Yukawa row; 0: Yukawa row only
   float rho_inv_f; // eps_out / eps_source, used by the Laplace row
-  int32_t pad;
+  int32_t nsrc;    // P2P: number of sources in the ranges
   double rho_inv;
 };
 
-// Per-target bookkeeping for the combine step.
+// Per 64-target chunk: its M2P slots [sbeg, send) (64 lanes each) and, per
+// half (targets 0..31 and 32..63), its P2P slots [hbeg, hend) (32 lanes).
 struct ChunkSlots {
   int32_t tbeg, tcount, sbeg, send;
+  int32_t hbeg0, hend0, hbeg1, hend1;
 };
 
 // Units: lengths in A, charges in e, potentials in e/(eps0 A), energies in
@@ -117,7 +123,9 @@ void launch_strengths_x(int64_t ns, int K, const PanelMaps& m, const double* x, 
                         const double* nrm, const double* rlap, double* sig, double* mu, T* src,
                         hipStream_t s);
 template <typename T>
-void launch_p2p(const Task* tasks, int ntasks, const int32_t* ranges, const T* tgt, const T* src,
+// P2P over npairs pairs of tasks (tasks[2w], tasks[2w+1] share wavefront w);
+// partials [slot][32][2].
+void launch_p2p(const Task* tasks, int npairs, const int32_t* ranges, const T* tgt, const T* src,
                 T kappa, bool guard, T* partial, hipStream_t s);
 struct CombineArgs {
   int64_t np;
@@ -130,7 +138,7 @@ struct CombineArgs {
   int add_jump;
 };
 template <typename T>
-void launch_combine(const CombineArgs& a, const T* partial, double* y, hipStream_t s);
+void launch_combine(const CombineArgs& a, const T* partial, const T* ppartial, double* y, hipStream_t s);
 
 // --- Taylor-series far field (taylor.hip) ----------------------------------
 struct BoxDev {
@@ -151,7 +159,7 @@ void launch_m2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, T* mom, 
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
                     const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
-                    bool guard, T* partial, hipStream_t s);
+                    bool guard, T* partial, T* ppartial, hipStream_t s);
 template <typename T>
 void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
                 const double* box_center, const T* mom, T kappa, T* partial, hipStream_t s);

@@ -327,6 +327,8 @@ void System::upload_plan(hipStream_t s) {
   }
   part32_.alloc((size_t)std::max(plan_.nslots, 1) * 128);
   part64_.alloc((size_t)std::max(plan_.nslots, 1) * 128);
+  ppart32_.alloc((size_t)std::max(plan_.npslots, 1) * 64);
+  ppart64_.alloc((size_t)std::max(plan_.npslots, 1) * 64);
   PBT_HIP(hipStreamSynchronize(s));
 }
 
@@ -466,39 +468,99 @@ void System::build_plan() {
       }
     }
   }
-  // Slots: contiguous per chunk.
-  int slot = 0;
+  // Slots.  Per 64-target chunk: its M2P slots (64 lanes), then per half of
+  // the chunk (targets 0..31, 32..63) its P2P slots (32 lanes, own buffer).
+  int slot = 0, pslot = 0;
+  std::vector<int> nseg_p(leaves.size(), 0), nseg_m(leaves.size(), 0);
   for (size_t li = 0; li < leaves.size(); ++li) {
+    for (const Seg& sg : segs[li]) (sg.m2p ? nseg_m : nseg_p)[li]++;
     const int nchunk = (li + 1 < leaves.size() ? leaf_chunk0[li + 1] : (int)P.chunks.size()) - leaf_chunk0[li];
     for (int c = 0; c < nchunk; ++c) {
       ChunkSlots& cs = P.chunks[leaf_chunk0[li] + c];
       cs.sbeg = slot;
-      slot += (int)segs[li].size();
+      slot += nseg_m[li];
       cs.send = slot;
+      cs.hbeg0 = pslot;
+      pslot += nseg_p[li];
+      cs.hend0 = pslot;
+      cs.hbeg1 = cs.hend1 = pslot;
+      if (cs.tcount > 32) {
+        pslot += nseg_p[li];
+        cs.hend1 = pslot;
+      }
     }
   }
   P.nslots = slot;
-  // Tasks ordered by (leaf, segment, chunk): neighbouring tasks share sources.
+  P.npslots = pslot;
+  // M2P tasks ordered by (leaf, segment, chunk).  P2P half tasks (<= 32
+  // targets) likewise; the two halves of a full chunk share a wavefront (same
+  // sources), the other halves are paired across leaves among tasks of the
+  // same kind and similar source count, so lanes are not left idle by leaves
+  // whose size is not a multiple of 64.
+  std::vector<Task> spare;
   for (size_t li = 0; li < leaves.size(); ++li) {
     const int e = leaves[li].e;
     const bool mol = surfs_[e]->kind == PBT_MOLECULE;
     const int c0 = leaf_chunk0[li];
     const int nchunk = (li + 1 < leaves.size() ? leaf_chunk0[li + 1] : (int)P.chunks.size()) - c0;
+    int mi = 0, pi = 0;
     for (size_t si = 0; si < segs[li].size(); ++si) {
       const Seg& sg = segs[li][si];
+      Task t{};
+      t.lbeg = sg.lbeg;
+      t.lend = sg.lend;
+      t.fused = (mol && sg.e2 == e) ? 1 : 0;
+      t.rho_inv = mol ? eps_out_ / surfs_[e]->eps_in : 0.0;
+      t.rho_inv_f = (float)t.rho_inv;
+      if (sg.m2p) {
+        for (int c = 0; c < nchunk; ++c) {
+          const ChunkSlots& cs = P.chunks[c0 + c];
+          t.tbeg = cs.tbeg;
+          t.tcount = cs.tcount;
+          t.slot = cs.sbeg + mi;
+          P.m2p.push_back(t);
+        }
+        ++mi;
+        continue;
+      }
+      t.nsrc = 0;
+      for (int32_t r = sg.lbeg; r < sg.lend; ++r) t.nsrc += P.ranges[2 * r + 1] - P.ranges[2 * r];
       for (int c = 0; c < nchunk; ++c) {
         const ChunkSlots& cs = P.chunks[c0 + c];
-        Task t{};
-        t.tbeg = cs.tbeg;
-        t.tcount = cs.tcount;
-        t.lbeg = sg.lbeg;
-        t.lend = sg.lend;
-        t.slot = cs.sbeg + (int)si;
-        t.fused = (mol && sg.e2 == e) ? 1 : 0;
-        t.rho_inv = mol ? eps_out_ / surfs_[e]->eps_in : 0.0;
-        t.rho_inv_f = (float)t.rho_inv;
-        (sg.m2p ? P.m2p : P.p2p).push_back(t);
+        Task h0 = t, h1 = t;
+        h0.tbeg = cs.tbeg;
+        h0.tcount = std::min(32, cs.tcount);
+        h0.slot = cs.hbeg0 + pi;
+        h1.tbeg = cs.tbeg + 32;
+        h1.tcount = cs.tcount - 32;
+        h1.slot = cs.hbeg1 + pi;
+        if (cs.tcount == 64) {
+          P.p2p.push_back(h0);
+          P.p2p.push_back(h1);
+        } else {
+          spare.push_back(h0);
+          if (h1.tcount > 0) spare.push_back(h1);
+        }
       }
+      ++pi;
+    }
+  }
+  std::stable_sort(spare.begin(), spare.end(), [](const Task& a, const Task& b) {
+    return a.fused != b.fused ? a.fused < b.fused : a.nsrc > b.nsrc;
+  });
+  for (size_t k = 0; k < spare.size();) {
+    P.p2p.push_back(spare[k]);
+    if (k + 1 < spare.size() && spare[k + 1].fused == spare[k].fused) {
+      P.p2p.push_back(spare[k + 1]);
+      k += 2;
+    } else {
+      Task empty = spare[k];   // an empty half: no targets, no sources
+      empty.tcount = 0;
+      empty.lbeg = empty.lend = 0;
+      empty.nsrc = 0;
+      empty.slot = 0;
+      P.p2p.push_back(empty);
+      k += 1;
     }
   }
 }
@@ -512,6 +574,8 @@ void System::interactions(hipStream_t s, const double* x, bool timed) {
   T* src = f32 ? (T*)src32_.p : (T*)src64_.p;
   const T* tgt = f32 ? (const T*)tgt32_.p : (const T*)tgt64_.p;
   T* part = f32 ? (T*)part32_.p : (T*)part64_.p;
+  T* ppart = f32 ? (T*)ppart32_.p : (T*)ppart64_.p;
+  const int npairs = (int)(plan_.p2p.size() / 2);
   T* mom = f32 ? (T*)mom32_.p : (T*)mom64_.p;
   if (x) {
     PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
@@ -548,8 +612,8 @@ void System::interactions(hipStream_t s, const double* x, bool timed) {
       PBT_HIP(hipEventRecord(evm_[2], s));
       PBT_HIP(hipEventRecord(ev_[2], s));
     }
-    launch_m2p_p2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, bcen_.p, mom, dp2p_.p,
-                      (int)plan_.p2p.size(), dranges_.p, src, tgt, (T)kappa_, guard, part, s);
+    launch_m2p_p2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, bcen_.p, mom, dp2p_.p, npairs,
+                      dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
       PBT_HIP(hipEventRecord(ev_[4], s));
@@ -558,7 +622,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed) {
     return;
   }
   if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
-  launch_p2p<T>(dp2p_.p, (int)plan_.p2p.size(), dranges_.p, tgt, src, (T)kappa_, guard, part, s);
+  launch_p2p<T>(dp2p_.p, npairs, dranges_.p, tgt, src, (T)kappa_, guard, ppart, s);
   if (timed) PBT_HIP(hipEventRecord(ev_[3], s));
   if (two) {
     // P2P (already queued) and the far field on the second stream overlap
@@ -591,8 +655,8 @@ void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStre
   a.x = x;
   a.maps = PanelMaps{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
   a.add_jump = add_jump ? 1 : 0;
-  if (fp32) launch_combine<float>(a, part32_.p, y, s);
-  else launch_combine<double>(a, part64_.p, y, s);
+  if (fp32) launch_combine<float>(a, part32_.p, ppart32_.p, y, s);
+  else launch_combine<double>(a, part64_.p, ppart64_.p, y, s);
   if (timed) PBT_HIP(hipEventRecord(ev_[5], s));
 }
 

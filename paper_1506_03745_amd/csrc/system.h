@@ -102,7 +102,8 @@ struct Plan {
   std::vector<int32_t> ranges, blist;
   std::vector<ChunkSlots> chunks;
   std::vector<int32_t> chunk_of;
-  int nslots = 0;
+  int nslots = 0;    // M2P partial slots (64 lanes)
+  int npslots = 0;   // P2P partial slots (32 lanes)
   int64_t p2p_pairs = 0, m2p_pairs = 0, p2p_fused_pairs = 0;
 };
 
@@ -263,8 +264,8 @@ class System {
   DBuf<int32_t> dranges_, dblist_;
   DBuf<ChunkSlots> dchunks_;
   DBuf<int32_t> dchunk_of_;
-  DBuf<float> part32_;
-  DBuf<double> part64_;
+  DBuf<float> part32_, ppart32_;
+  DBuf<double> part64_, ppart64_;
 
   // Krylov workspace
   int restart_alloc_ = 0;

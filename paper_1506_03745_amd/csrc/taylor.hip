@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int
   m2p_task<T, P>(tasks[wv], blist, tgt, bcen, mom, kappa, partial);
 }
 
-// M2P and P2P tasks in one launch (M2P first): the far field's wavefronts
+// M2P tasks and P2P task pairs in one launch (M2P first): the far field's wavefronts
 // and the near field's share the machine instead of running one after the
 // other.
 template <typename T, int P, bool GUARD>
@@ -247,12 +247,13 @@ __global__ __launch_bounds__(256) void k_m2p_p2p(const Task* __restrict__ m2p, i
                                                  const double* __restrict__ bcen, const T* __restrict__ mom,
                                                  const Task* __restrict__ p2p, int np2p,
                                                  const int32_t* __restrict__ ranges, const T* __restrict__ src,
-                                                 const T* __restrict__ tgt, T kappa, T* __restrict__ partial) {
+                                                 const T* __restrict__ tgt, T kappa, T* __restrict__ partial,
+                                                 T* __restrict__ ppartial) {
   __shared__ SrcRec<T> tiles[4][64];
   const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
   if (wv < nm2p) m2p_task<T, P>(m2p[wv], blist, tgt, bcen, mom, kappa, partial);
   else if (wv < nm2p + np2p)
-    p2p_task<T, GUARD>(p2p[wv - nm2p], tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, partial);
+    p2p_task_pair<T, GUARD>(p2p + 2 * (wv - nm2p), tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, ppartial);
 }
 
 bool g_tables_ready[64] = {false};
@@ -326,25 +327,26 @@ void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, cons
 template <typename T, int P>
 static void m2p_p2p_p(const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
                       const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
-                      bool guard, T* partial, hipStream_t s) {
+                      bool guard, T* partial, T* ppartial, hipStream_t s) {
   const int blocks = ((nm2p + np2p + 3) / 4 + 7) / 8 * 8;
   if (guard)
     k_m2p_p2p<T, P, true><<<blocks, 256, 0, s>>>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt,
-                                                 kappa, partial);
+                                                 kappa, partial, ppartial);
   else
     k_m2p_p2p<T, P, false><<<blocks, 256, 0, s>>>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt,
-                                                  kappa, partial);
+                                                  kappa, partial, ppartial);
 }
 
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
                     const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
-                    bool guard, T* partial, hipStream_t s) {
+                    bool guard, T* partial, T* ppartial, hipStream_t s) {
   if (nm2p + np2p <= 0) return;
   switch (P) {
 #define PBT_CASE(PP)                                                                                      \
   case PP:                                                                                                \
-    m2p_p2p_p<T, PP>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt, kappa, guard, partial, s); \
+    m2p_p2p_p<T, PP>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt, kappa, guard, partial, ppartial, \
+                     s);                                                                                  \
     break;
     PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
 #undef PBT_CASE
@@ -359,10 +361,10 @@ template void launch_m2m<float>(int, int, const int32_t*, const BoxDev&, float*,
 template void launch_m2m<double>(int, int, const int32_t*, const BoxDev&, double*, hipStream_t);
 template void launch_m2p_p2p<float>(int, const Task*, int, const int32_t*, const double*, const float*,
                                     const Task*, int, const int32_t*, const float*, const float*, float, bool,
-                                    float*, hipStream_t);
+                                    float*, float*, hipStream_t);
 template void launch_m2p_p2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
                                      const Task*, int, const int32_t*, const double*, const double*, double, bool,
-                                     double*, hipStream_t);
+                                     double*, double*, hipStream_t);
 template void launch_m2p<float>(int, const Task*, int, const int32_t*, const float*, const double*,
                                 const float*, float, float*, hipStream_t);
 template void launch_m2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
