@@ -35,8 +35,9 @@ struct pbt_ctx {
   pbt_result last_stats{};
   // last solution
   std::vector<bool> sol_mask;
-  std::vector<double> sol_x;
-  DBuf<double> dx, dy, db;
+  std::vector<double> sol_x;   // host copy of dsol, made when first asked for
+  bool sol_on_host = false;
+  DBuf<double> dx, dy, db, dsol;
 };
 
 namespace {
@@ -167,8 +168,10 @@ pbt_status solve_impl(pbt_ctx* c, const double* x0, pbt_result* res) {
   r.p2p_fused_pairs = S.plan().p2p_fused_pairs;
   r.matvecs = (int32_t)(S.applications() - apply0);
   c->cs.iters = std::max(c->cs.iters, r.iters);
-  c->sol_x.resize(n);
-  PBT_HIP(hipMemcpy(c->sol_x.data(), c->dx.p, n * sizeof(double), hipMemcpyDeviceToHost));
+  // the solution stays on the device until pbt_get_solution asks for it
+  c->dsol.alloc(n);
+  PBT_HIP(hipMemcpyAsync(c->dsol.p, c->dx.p, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  c->sol_on_host = false;
   c->sol_mask = mask_of(c);
   if (res) *res = r;
   if (!std::isfinite(r.F_total) || !std::isfinite(r.rel_resid))
@@ -356,8 +359,12 @@ pbt_status pbt_solve(pbt_ctx* c, const double* x0, pbt_result* res) {
 pbt_status pbt_get_solution(pbt_ctx* c, int32_t id, double* phi, double* dphidn) {
   return guarded(c, [&] {
     if (id < 0 || id >= (int)c->surfs.size()) return fail(c, PBT_E_INVALID, "bad surface id");
-    if (c->sol_x.empty() || c->sol_mask.size() != c->surfs.size() || !c->sol_mask[id])
+    if (c->sol_mask.empty() || c->sol_mask.size() != c->surfs.size() || !c->sol_mask[id])
       return fail(c, PBT_E_STATE, "no solution for this surface");
+    if (!c->sol_on_host) {
+      c->sol_x = c->dsol.download(c->stream);
+      c->sol_on_host = true;
+    }
     std::vector<bool> cur = mask_of(c);
     auto it = c->systems.find(c->sol_mask);
     if (it == c->systems.end()) return fail(c, PBT_E_STATE, "solution's system was released");

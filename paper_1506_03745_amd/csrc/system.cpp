@@ -813,7 +813,8 @@ void System::true_residual(const double* b, const double* x, double* r, hipStrea
 // groups past the last one's) are discarded.  Returns the most iterations
 // any group used.
 int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std::vector<double>& tol_abs,
-                  int restart, int maxit, std::vector<double>& resid_out, hipStream_t s) {
+                  int restart, int maxit, std::vector<double>& resid_out, hipStream_t s,
+                  const std::vector<double>* b_norms) {
   const int m = restart, G = G_, R = m + 1, nbj = pdb_;
   // pinned: H [G][m + 1][m], g [G][m + 1], y [G][m], rs [G][m], beta [G], 1/beta [G]
   const size_t HS = (size_t)(m + 1) * m;
@@ -839,7 +840,8 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
     op(x, r_.p, fp32, s);
     launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
   }
-  std::vector<double> beta = group_norms(r_.p, s);
+  // with x = 0 the residual is b, whose norms the caller may already have
+  std::vector<double> beta = (x_zero && b_norms) ? *b_norms : group_norms(r_.p, s);
   resid_out = beta;
   auto pending = [&] {
     for (int g = 0; g < G; ++g)
@@ -1007,7 +1009,7 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
   double rel = 0.0;
   if (prm_.prec == PBT_FP64) {
     for (int g = 0; g < G; ++g) tabs[g] = tol * bn[g];
-    res->iters = gmres(false, b, x, !x0_given, tabs, m, prm_.max_iter, est, s);
+    res->iters = gmres(false, b, x, !x0_given, tabs, m, prm_.max_iter, est, s, &bn);
     res->outer = 1;
     true_residual(b, x, tmp_.p, s);
     rel = relmax(group_norms(tmp_.p, s));
@@ -1015,7 +1017,7 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
     // Iterative refinement: FP32-interaction GMRES on the FP64 residual.
     if (x0_given) true_residual(b, x, tmp_.p, s);
     else PBT_HIP(hipMemcpyAsync(tmp_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
-    std::vector<double> rn = group_norms(tmp_.p, s);
+    std::vector<double> rn = x0_given ? group_norms(tmp_.p, s) : bn;
     rel = relmax(rn);
     for (int outer = 0; outer < 20 && rel > tol && res->iters < prm_.max_iter; ++outer) {
       // Each running group's inner solve aims straight at the requested
@@ -1029,7 +1031,7 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
         tabs[g] = std::min(0.5, std::max(0.5 * tol * bn[g] / rn[g], 2e-7)) * rn[g];
       }
       PBT_HIP(hipMemsetAsync(y_.p, 0, n_ * sizeof(double), s));
-      res->iters += gmres(true, tmp_.p, y_.p, true, tabs, m, prm_.max_iter - res->iters, est, s);
+      res->iters += gmres(true, tmp_.p, y_.p, true, tabs, m, prm_.max_iter - res->iters, est, s, &rn);
       launch_axpby(n_, 1.0, y_.p, 1.0, x, s);
       true_residual(b, x, tmp_.p, s);
       rn = group_norms(tmp_.p, s);

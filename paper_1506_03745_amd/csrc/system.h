@@ -187,7 +187,8 @@ class System {
   template <typename T>
   void interactions(hipStream_t s, const double* x, bool timed);
   int gmres(bool fp32, const double* b, double* x, bool x_zero, const std::vector<double>& tol_abs,
-            int restart, int maxit, std::vector<double>& resid_out, hipStream_t s);
+            int restart, int maxit, std::vector<double>& resid_out, hipStream_t s,
+            const std::vector<double>* b_norms = nullptr);
   void ensure_groups(hipStream_t s);
   std::vector<double> group_norms(const double* v, hipStream_t s);
   void true_residual(const double* b, const double* x, double* r, hipStream_t s);
