@@ -84,3 +84,13 @@ def test_struct_layouts_match_header():
     # field order and sizes of the two public structs
     assert ctypes.sizeof(B.PbtParams) == 5 * 4 + 4 + 8 + 8 + 4 * 4
     assert ctypes.sizeof(B.PbtResult) == 4 * 8 + 2 * 4 + 3 * 8 + 4 * 8 + 8
+
+
+def test_richardson_helpers_recover_order_and_limit():
+    from paper_1506_03745_amd.convergence import observed_order, richardson
+    a, b, p = 0.0614, 0.37, 1.0
+    f = [a + b * (0.5 ** k) ** p for k in range(3)]
+    assert abs(observed_order(*f) - p) < 1e-12
+    assert abs(richardson(f[1], f[2], observed_order(*f)) - a) < 1e-12
+    g = [a + b * (0.5 ** k) ** 2 for k in range(3)]
+    assert abs(observed_order(*g) - 2.0) < 1e-12

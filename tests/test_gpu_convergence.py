@@ -1,0 +1,54 @@
+"""Grid convergence on the GPU path (Section 5.1's verification) and the
+relaxed parameter set for sampling many orientations (Table 3's parameters:
+one far-field point, Taylor order 4, tolerance 1e-5).
+
+Bars:
+* two-sphere F_int, levels 2..5 (320..20480 panels per sphere): the error
+  against the series solution falls at every refinement, the observed order
+  of the three finest levels is within 0.2 of the paper's 1.007, and the
+  Richardson-extrapolated value is closer to the series than the finest mesh;
+* relaxed parameters on a batch of placements: within 2 % of the standard
+  parameters' F_int (the paper reports its relaxed runs within 2 %).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1506_03745_amd import MIXED, from_problem
+from paper_1506_03745_amd.convergence import study
+from workloads.problems import config_problem, random_rotations
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+PRM = dict(theta=0.5, taylor_p=6, ncrit=300, k_far=3, k_near=19, k_self_edge=9)
+
+
+def test_two_sphere_grid_convergence():
+    with open(os.path.join(GOLDEN, "twosphere_analytic.json")) as f:
+        exact = json.load(f)["charge"]["F_int"]
+    with open(os.path.join(GOLDEN, "paper_values.json")) as f:
+        paper_order = json.load(f)["twosphere_observed_order"]["value"]
+    res = study(lambda lv: config_problem("twosphere_charge", level=lv), (2, 3, 4, 5), 2, prec=MIXED,
+                tol=1e-8, **PRM)
+    errs = [abs(r["F_int"] - exact) for r in res["levels"]]
+    print("F_int per level:", [r["F_int"] for r in res["levels"]], "order", res["observed_order"],
+          "extrapolated", res["extrapolated_F_int"], "exact", exact)
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+    assert abs(res["observed_order"] - paper_order) < 0.2
+    assert abs(res["extrapolated_F_int"] - exact) < errs[-1]
+
+
+def test_relaxed_parameters_on_a_batch():
+    pr = config_problem("orient_sweep")
+    R = random_rotations(64, 3)[:8]
+    c = pr.surfaces[0].q_pos[0]
+    T = c[None, :] - R @ c
+    s, ids = from_problem(pr, prec=MIXED, tol=1e-6, **PRM)
+    f_std = s.solve_batch(ids[0], R.reshape(-1, 9), T)
+    relaxed = dict(PRM, k_far=1, taylor_p=4)
+    r, rids = from_problem(pr, prec=MIXED, tol=1e-5, **relaxed)
+    f_rel = r.solve_batch(rids[0], R.reshape(-1, 9), T)
+    print("standard", f_std, "relaxed", f_rel)
+    assert np.max(np.abs(f_rel - f_std) / np.abs(f_std)) < 0.02
