@@ -3,10 +3,11 @@ two-sphere verification reports the observed order of convergence of the
 interaction free energy over the three finest meshes; Section 5.2 uses the
 same extrapolation on the protein-surface runs).
 
-Each level refines the mesh once (panel count x4, panel size h / 2).  For
-three consecutive values f1, f2, f3 (coarse to fine) the observed order is
-p = log((f1 - f2) / (f2 - f3)) / log 2 and the extrapolated value
-f3 + (f3 - f2) / (2^p - 1).
+Each level refines the mesh once, multiplying the number of panels N by 4;
+orders are with respect to N, as the paper states them (error ~ N^-p, p ~ 1
+for flat panels with constant unknowns).  For three consecutive values f1,
+f2, f3 (coarse to fine) the observed order is p = log((f1 - f2) / (f2 - f3))
+/ log 4 and the extrapolated value f3 + (f3 - f2) / (4^p - 1).
 
     python -m paper_1506_03745_amd.convergence            # two-sphere, charge
 """
@@ -20,12 +21,12 @@ import time
 from .pbt import MIXED, from_problem
 
 
-def observed_order(f1: float, f2: float, f3: float, ratio: float = 2.0) -> float:
-    """Order p from three values on meshes refined by `ratio` in h."""
+def observed_order(f1: float, f2: float, f3: float, ratio: float = 4.0) -> float:
+    """Order p from three values on meshes whose panel counts grow by `ratio`."""
     return math.log(abs((f1 - f2) / (f2 - f3))) / math.log(ratio)
 
 
-def richardson(f2: float, f3: float, p: float, ratio: float = 2.0) -> float:
+def richardson(f2: float, f3: float, p: float, ratio: float = 4.0) -> float:
     """Extrapolated value from the two finest values and the order p."""
     return f3 + (f3 - f2) / (ratio ** p - 1.0)
 

@@ -14,6 +14,7 @@
 #include <deque>
 #include <map>
 
+#include "parallel.h"
 #include "quadrature.h"
 
 namespace pbt {
@@ -59,6 +60,9 @@ void System::build(hipStream_t s) {
     poff_[e + 1] = poff_[e] + S.nt;
     col_off_[e + 1] = col_off_[e] + w;
     row_off_[e + 1] = row_off_[e] + w;
+  }
+  parallel_for(ns, [&](int64_t e) {
+    const SurfIn& S = *surfs_[e];
     std::vector<double> hc(3 * S.nt);
     for (int64_t i = 0; i < S.nt; ++i)
       for (int d = 0; d < 3; ++d) {
@@ -66,7 +70,7 @@ void System::build(hipStream_t s) {
         hc[3 * i + d] = (S.xyz[3 * t[0] + d] + S.xyz[3 * t[1] + d] + S.xyz[3 * t[2] + d]) / 3.0;
       }
     trees_[e] = build_tree(hc.data(), S.nt, prm_.treecode ? prm_.ncrit : (int)std::max<int64_t>(S.nt, 1));
-  }
+  });
   np_ = poff_[ns];
   n_ = col_off_[ns];
   ns_ = np_ * K_;
@@ -82,7 +86,7 @@ void System::build(hipStream_t s) {
   h_panel_orig_.resize(np_);
   std::vector<int32_t> col_phi(np_), col_psi(np_), row_int(np_), row_sol(np_), psurf(np_);
   std::vector<double> dscale(np_), ksig(np_, 0.0), kmu(np_, 0.0);
-  for (int e = 0; e < ns; ++e) {
+  parallel_for(ns, [&](int64_t e) {
     const SurfIn& S = *surfs_[e];
     for (int64_t li = 0; li < S.nt; ++li) {
       const int64_t g = poff_[e] + li;
@@ -114,7 +118,7 @@ void System::build(hipStream_t s) {
           dscale[g] = 1.0;
       }
     }
-  }
+  });
   tri9_.upload(tri9, s);
   col_phi_.upload(col_phi, s);
   col_psi_.upload(col_psi, s);
@@ -166,11 +170,11 @@ void System::build(hipStream_t s) {
 
   // ---- tree geometry (global box numbering) --------------------------------
   boff_.assign(ns + 1, 0);
-  for (int e = 0; e < ns; ++e) {
+  parallel_for(ns, [&](int64_t e) {
     const int64_t p0 = poff_[e];
     tree_geometry(trees_[e], &h_cen_[3 * p0], &hsrc[3 * p0 * K_], K_);
-    boff_[e + 1] = boff_[e] + (int64_t)trees_[e].boxes.size();
-  }
+  });
+  for (int e = 0; e < ns; ++e) boff_[e + 1] = boff_[e] + (int64_t)trees_[e].boxes.size();
   nbox_ = (int)boff_[ns];
   {
     std::vector<double> bc(3 * nbox_), brho(nbox_);
@@ -212,38 +216,44 @@ void System::build(hipStream_t s) {
     for (int e = 0; e < ns; ++e)
       for (int64_t li = 0; li < surfs_[e]->nt; ++li)
         lmax[e] = std::max(lmax[e], 2.0 * std::sqrt(2.0 * h_area_[poff_[e] + li]));
-    for (int e = 0; e < ns; ++e) {
-      for (const TreeBox& T : trees_[e].boxes) {
-        if (!T.leaf) continue;
-        const int32_t id = (int32_t)(lptr.size() - 1);
-        for (int64_t g = poff_[e] + T.pbeg; g < poff_[e] + T.pend; ++g) tleaf[g] = id;
-        std::vector<std::pair<int64_t, int64_t>> rg;
-        for (int e2 = 0; e2 < ns; ++e2) {
-          if (surfs_[e2]->group != surfs_[e]->group) continue;
-          const SurfTree& S2 = trees_[e2];
-          std::vector<int> stack{0};
-          while (!stack.empty()) {
-            const TreeBox& B = S2.boxes[stack.back()];
-            stack.pop_back();
-            const double dx = T.tc[0] - B.tc[0], dy = T.tc[1] - B.tc[1], dz = T.tc[2] - B.tc[2];
-            const double reach = (T.tr + B.tr + lmax[e2]) * (1.0 + 1e-9) + 1e-9;
-            if (dx * dx + dy * dy + dz * dz >= reach * reach) continue;
-            if (B.leaf) rg.push_back({poff_[e2] + B.pbeg, poff_[e2] + B.pend});
-            else
-              for (int k = B.child_end - 1; k >= B.child_beg; --k) stack.push_back(S2.child_list[k]);
-          }
+    struct TL { int e; const TreeBox* T; };
+    std::vector<TL> tls;
+    for (int e = 0; e < ns; ++e)
+      for (const TreeBox& T : trees_[e].boxes)
+        if (T.leaf) tls.push_back({e, &T});
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> cand(tls.size());
+    parallel_for((int64_t)tls.size(), [&](int64_t k) {
+      const int e = tls[k].e;
+      const TreeBox& T = *tls[k].T;
+      for (int64_t g = poff_[e] + T.pbeg; g < poff_[e] + T.pend; ++g) tleaf[g] = (int32_t)k;
+      std::vector<std::pair<int64_t, int64_t>>& rg = cand[k];
+      for (int e2 = 0; e2 < ns; ++e2) {
+        if (surfs_[e2]->group != surfs_[e]->group) continue;
+        const SurfTree& S2 = trees_[e2];
+        std::vector<int> stack{0};
+        while (!stack.empty()) {
+          const TreeBox& B = S2.boxes[stack.back()];
+          stack.pop_back();
+          const double dx = T.tc[0] - B.tc[0], dy = T.tc[1] - B.tc[1], dz = T.tc[2] - B.tc[2];
+          const double reach = (T.tr + B.tr + lmax[e2]) * (1.0 + 1e-9) + 1e-9;
+          if (dx * dx + dy * dy + dz * dz >= reach * reach) continue;
+          if (B.leaf) rg.push_back({poff_[e2] + B.pbeg, poff_[e2] + B.pend});
+          else
+            for (int c = B.child_end - 1; c >= B.child_beg; --c) stack.push_back(S2.child_list[c]);
         }
-        std::sort(rg.begin(), rg.end());
-        for (const auto& r : rg) {
-          if (!lrange.empty() && (int64_t)lrange.size() / 2 > lptr.back() && lrange.back() == r.first)
-            lrange.back() = r.second;
-          else {
-            lrange.push_back(r.first);
-            lrange.push_back(r.second);
-          }
-        }
-        lptr.push_back((int64_t)lrange.size() / 2);
       }
+      std::sort(rg.begin(), rg.end());
+    });
+    for (const auto& rg : cand) {
+      for (const auto& r : rg) {
+        if (!lrange.empty() && (int64_t)lrange.size() / 2 > lptr.back() && lrange.back() == r.first)
+          lrange.back() = r.second;
+        else {
+          lrange.push_back(r.first);
+          lrange.push_back(r.second);
+        }
+      }
+      lptr.push_back((int64_t)lrange.size() / 2);
     }
     if (lrange.empty()) lrange = {0, 0};
     DBuf<int32_t> dtleaf;
@@ -389,10 +399,12 @@ void System::build_plan() {
   // Per leaf and source surface: merged P2P source ranges and M2P boxes.
   struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
   std::vector<std::vector<Lists>> L(leaves.size(), std::vector<Lists>(ns));
-  int64_t tot_src = 0, tot_box = 0;
-  for (size_t li = 0; li < leaves.size(); ++li) {
+  // (per leaf in parallel; the counts are added up afterwards)
+  std::vector<std::array<int64_t, 5>> cnt(leaves.size(), {0, 0, 0, 0, 0});
+  parallel_for((int64_t)leaves.size(), [&](int64_t li) {
     const TreeBox& tl = trees_[leaves[li].e].boxes[leaves[li].b];
     const int64_t nt = tl.pend - tl.pbeg;
+    std::array<int64_t, 5>& c = cnt[li];   // tot_src, tot_box, p2p, m2p, fused
     for (int e2 = 0; e2 < ns; ++e2) {
       std::vector<int> pb, mb;
       if (surfs_[e2]->group != surfs_[leaves[li].e]->group) continue;  // independent systems
@@ -401,22 +413,30 @@ void System::build_plan() {
       std::sort(pb.begin(), pb.end(), [&](int a, int b) {
         return trees_[e2].boxes[a].pbeg < trees_[e2].boxes[b].pbeg;
       });
-      lp2p_[li][e2] = pb;
-      lm2p_[li][e2] = mb;
       Lists& o = L[li][e2];
       for (int b : pb) {
         const TreeBox& sb = trees_[e2].boxes[b];
         const int32_t j0 = (int32_t)((poff_[e2] + sb.pbeg) * K_), j1 = (int32_t)((poff_[e2] + sb.pend) * K_);
         if (!o.rng.empty() && o.rng.back().second == j0) o.rng.back().second = j1;
         else o.rng.push_back({j0, j1});
-        tot_src += (int64_t)(j1 - j0) * ((nt + 63) / 64);
-        P.p2p_pairs += (int64_t)(j1 - j0) * nt;
-        if (e2 == leaves[li].e && surfs_[e2]->kind == PBT_MOLECULE) P.p2p_fused_pairs += (int64_t)(j1 - j0) * nt;
+        c[0] += (int64_t)(j1 - j0) * ((nt + 63) / 64);
+        c[2] += (int64_t)(j1 - j0) * nt;
+        if (e2 == leaves[li].e && surfs_[e2]->kind == PBT_MOLECULE) c[4] += (int64_t)(j1 - j0) * nt;
       }
       for (int b : mb) o.box.push_back((int32_t)(boff_[e2] + b));
-      tot_box += (int64_t)mb.size() * ((nt + 63) / 64);
-      P.m2p_pairs += (int64_t)mb.size() * nt;
+      c[1] += (int64_t)mb.size() * ((nt + 63) / 64);
+      c[3] += (int64_t)mb.size() * nt;
+      lp2p_[li][e2] = std::move(pb);
+      lm2p_[li][e2] = std::move(mb);
     }
+  });
+  int64_t tot_src = 0, tot_box = 0;
+  for (const auto& c : cnt) {
+    tot_src += c[0];
+    tot_box += c[1];
+    P.p2p_pairs += c[2];
+    P.m2p_pairs += c[3];
+    P.p2p_fused_pairs += c[4];
   }
   // Segment sizes: aim at several thousand wavefront tasks in each launch.
   const int64_t want = 16384;

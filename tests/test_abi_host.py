@@ -88,9 +88,10 @@ def test_struct_layouts_match_header():
 
 def test_richardson_helpers_recover_order_and_limit():
     from paper_1506_03745_amd.convergence import observed_order, richardson
+    # f = a + b N^-p on meshes with N, 4N, 16N panels
     a, b, p = 0.0614, 0.37, 1.0
-    f = [a + b * (0.5 ** k) ** p for k in range(3)]
+    f = [a + b * (0.25 ** k) ** p for k in range(3)]
     assert abs(observed_order(*f) - p) < 1e-12
     assert abs(richardson(f[1], f[2], observed_order(*f)) - a) < 1e-12
-    g = [a + b * (0.5 ** k) ** 2 for k in range(3)]
+    g = [a + b * (0.25 ** k) ** 2 for k in range(3)]
     assert abs(observed_order(*g) - 2.0) < 1e-12
