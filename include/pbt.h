@@ -224,6 +224,10 @@ pbt_status pbt_last_stats(pbt_ctx* ctx, pbt_result* out);
  * same products.  PBT_E_INVALID for another mode. */
 pbt_status pbt_set_schedule(pbt_ctx* ctx, int32_t mode);
 
+/* The schedule the enabled system currently uses (0, 1 or 2, as for
+ * pbt_set_schedule; pbt_autotune may have chosen it) in *mode.  Host-only. */
+pbt_status pbt_get_schedule(pbt_ctx* ctx, int32_t* mode);
+
 /* Quadrature tables the library integrates with (Section 3.1): triangle rule
  * with npts points (1, 3, 4, 7 or 19) as barycentric coordinates
  * bary[3*npts] and weights w[npts] summing to 1, or, for npts < 0, the
@@ -233,7 +237,7 @@ pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w);
 
 /* Timing of the last pbt_matvec / pbt_matvec_dev on the context's own
  * events, in milliseconds: out[0] total, out[1] P2P kernel, out[2] M2P
- * kernel, out[3] moments (P2M + M2M), out[4] near-field and combine.  Under
+ * kernel, out[3] moments (P2M), out[4] strengths, near field and combine.  Under
  * the joint M2P + P2P schedule out[1] is that launch and out[2] is 0. */
 pbt_status pbt_last_matvec_timing(pbt_ctx* ctx, double out[5]);
 

@@ -696,6 +696,14 @@ pbt_status pbt_set_schedule(pbt_ctx* c, int32_t mode) {
   });
 }
 
+pbt_status pbt_get_schedule(pbt_ctx* c, int32_t* mode) {
+  if (!c || !mode) return PBT_E_INVALID;
+  return guarded(c, [&] {
+    *mode = system_for(c).far_mode();
+    return PBT_OK;
+  });
+}
+
 pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w) {
   if (!bary || !w) return PBT_E_INVALID;
   std::vector<double> b, ww;

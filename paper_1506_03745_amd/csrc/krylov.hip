@@ -105,13 +105,17 @@ __global__ __launch_bounds__(kBS) void k_gs_dots(const int64_t* __restrict__ gu,
 // of each group also builds that group's Hessenberg column j: the previous
 // Givens rotations applied, the new one computed, and the residual estimate
 // |g_{j+1}| stored in resid[j].  Per group g: part + g R nbj, h1 + g R,
-// H + g (m + 1) m, cs/sn/resid + g m, gv + g (m + 1).
+// H + g (m + 1) m, cs/sn/resid + g m, gv + g (m + 1).  With SRC the threads
+// run over the group's panels instead of its unknowns and also write the
+// panel densities and the source records (type T) of the new basis vector,
+// which the next operator application then takes as they are.
+template <typename T, bool SRC>
 __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restrict__ gu, int j, int m, int R,
                                                         int nbj, const double* __restrict__ part,
                                                         const double* __restrict__ h1,
                                                         const double* __restrict__ V, int64_t ldv,
                                                         double* __restrict__ w, double* H, double* cs,
-                                                        double* sn, double* gv, double* resid) {
+                                                        double* sn, double* gv, double* resid, NextSrc ns) {
   extern __shared__ double sh[];   // h[m], h2[m + 1], col[m + 1], c[m], s[m]
   __shared__ double nn_s;
   double* h = sh;
@@ -144,12 +148,46 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
   }
   __syncthreads();
   const double nn = nn_s;
-  const int64_t e = u0 + blockIdx.x * (int64_t)kBS + threadIdx.x;
-  if (e < u1) {
+  auto update = [&](int64_t e) {
     double se = w[e];
 #pragma unroll 8
     for (int i = 0; i <= j; ++i) se -= h[i] * V[(int64_t)i * ldv + e];
-    w[e] = nn > 0.0 ? se / sqrt(nn) : 0.0;
+    const double v = nn > 0.0 ? se / sqrt(nn) : 0.0;
+    w[e] = v;
+    return v;
+  };
+  if (!SRC) {
+    const int64_t e = u0 + blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (e < u1) update(e);
+  } else {
+    // one thread per panel of the group, in the unknowns' (original) panel
+    // order so that the V and w accesses are coalesced; the panel's source
+    // records for the next product are written as the strengths kernel
+    // would write them from the updated unknowns
+    const int64_t q = ns.gp[2 * g] + blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (q < ns.gp[2 * g + 1]) {
+      const int64_t p = ns.pinv[q];
+      const int32_t cphi = ns.m.col_phi[p], cpsi = ns.m.col_psi[p];
+      const double vphi = cphi >= 0 ? update(cphi) : 0.0;
+      const double vpsi = cpsi >= 0 ? update(cpsi) : 0.0;
+      const double sg = cpsi >= 0 ? ns.m.dens_scale[p] * vpsi : 0.0;
+      const double mv = cphi >= 0 ? -vphi : 0.0;
+      ns.sig[p] = sg;
+      ns.mu[p] = mv;
+      T* src = reinterpret_cast<T*>(ns.src);
+      for (int k = 0; k < ns.K; ++k) {
+        const int64_t jj = p * ns.K + k;
+        const double wa = ns.wa[jj];
+        const double mm = wa * mv;
+        const double sval = wa * sg;
+        T* o = src + kSrcStride * jj;
+        o[3] = (T)sval;
+        o[4] = (T)(mm * ns.nrm[3 * p]);
+        o[5] = (T)(mm * ns.nrm[3 * p + 1]);
+        o[6] = (T)(mm * ns.nrm[3 * p + 2]);
+        o[7] = (T)(ns.rlap[p] * sval);
+      }
+    }
   }
   if (blockIdx.x != 0) return;
   if (threadIdx.x == 0) {
@@ -235,11 +273,23 @@ void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int
 
 void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m, int R, int nbj,
                            const double* part, const double* h1, const double* V, int64_t ldv, double* w,
-                           double* H, double* cs, double* sn, double* gv, double* resid, hipStream_t s) {
+                           double* H, double* cs, double* sn, double* gv, double* resid, const NextSrc* ns,
+                           hipStream_t s) {
   if (G <= 0) return;
-  const dim3 grid(nmax > 0 ? nblocks(nmax, kBS) : 1u, G);
-  k_arnoldi_update<<<grid, kBS, (size_t)(5 * m + 2) * sizeof(double), s>>>(gu, j, m, R, nbj, part, h1, V, ldv, w,
-                                                                            H, cs, sn, gv, resid);
+  const size_t lds = (size_t)(5 * m + 2) * sizeof(double);
+  if (!ns) {
+    const dim3 grid(nmax > 0 ? nblocks(nmax, kBS) : 1u, G);
+    k_arnoldi_update<double, false><<<grid, kBS, lds, s>>>(gu, j, m, R, nbj, part, h1, V, ldv, w, H, cs, sn, gv,
+                                                           resid, NextSrc{});
+  } else {
+    const dim3 grid(ns->pmax > 0 ? nblocks(ns->pmax, kBS) : 1u, G);
+    if (ns->fp32)
+      k_arnoldi_update<float, true><<<grid, kBS, lds, s>>>(gu, j, m, R, nbj, part, h1, V, ldv, w, H, cs, sn, gv,
+                                                           resid, *ns);
+    else
+      k_arnoldi_update<double, true><<<grid, kBS, lds, s>>>(gu, j, m, R, nbj, part, h1, V, ldv, w, H, cs, sn, gv,
+                                                            resid, *ns);
+  }
   PBT_HIP(hipGetLastError());
 }
 

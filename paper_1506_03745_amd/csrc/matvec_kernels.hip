@@ -127,6 +127,16 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool act = lane < cs.tcount;
   const int64_t i = cs.tbeg + lane;
+  // the output rows and jump terms are read up front (wave 0 writes), so
+  // their latency overlaps the sums instead of following them
+  int32_t ri = -1, rs = 0;
+  double xj = 0.0;
+  if (w == 0 && act) {
+    ri = a.maps.row_int[i];
+    rs = a.maps.row_sol[i];
+    const int32_t cphi = a.maps.col_phi[i];
+    if (a.add_jump && cphi >= 0) xj = 0.5 * a.x[cphi];
+  }
   double l = 0.0, yy = 0.0, nl = 0.0, ny = 0.0;
   if (act) {
 #pragma unroll 4
@@ -165,11 +175,8 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
   }
   l = l * kInv4Pi + nl;
   yy = yy * kInv4Pi + ny;
-  const int32_t ri = a.maps.row_int[i];
-  const int32_t rs = a.maps.row_sol[i];
-  const int32_t cphi = a.maps.col_phi[i];
-  if (ri >= 0) y[ri] = (a.add_jump ? 0.5 * a.x[cphi] : 0.0) + l;
-  y[rs] = (a.add_jump && cphi >= 0 ? 0.5 * a.x[cphi] : 0.0) + yy;
+  if (ri >= 0) y[ri] = xj + l;
+  y[rs] = xj + yy;
 }
 
 // Reaction potential at the charges of one molecule (eq. phi_reac_bem):

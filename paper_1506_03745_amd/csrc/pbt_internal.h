@@ -150,11 +150,20 @@ struct BoxDev {
   const int32_t* child_list;
   const double* rho_inv;  // per box: eps_out/eps_s of its surface (molecule) or 0
 };
+// Moments of the boxes M2P reads, straight from their sources (taylor.hip).
+// A box's sources [sbeg, send) are cut into chunks; chunk idx of nparts
+// writes partial slot slot0 + idx when nparts > 1, and `heads` (the idx 0
+// chunk of every such box) drives the sum of the slots.
+struct MomChunk {
+  int32_t box, sbeg, send;
+  int32_t slot0, nparts, idx;
+};
+constexpr int kMomChunk = 4096;  // sources per chunk (16 a thread)
+constexpr int kMomGroup = 12;    // coefficients per block
+constexpr int mom_groups(int P) { return (ncoef(P) + kMomGroup - 1) / kMomGroup; }
 template <typename T>
-void launch_p2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, const T* src, T* mom,
-                hipStream_t s);
-template <typename T>
-void launch_m2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, T* mom, hipStream_t s);
+void launch_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
+                    const double* bcen, const double* brho, const T* src, T* mom, T* mpart, hipStream_t s);
 // M2P and P2P tasks in one launch (taylor.hip).
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
@@ -218,9 +227,29 @@ void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hip
 int gs_blocks(int64_t n);
 void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int64_t ldv, const double* w,
                     const double* hpart, double* hout, int self_dot, double* part, int nbj, hipStream_t s);
+// Source records of the next Krylov vector, written by the Arnoldi update
+// (the strengths of launch_strengths_x, from the updated unknowns): panels
+// of group g are gp[2g] .. gp[2g+1] in the unknowns' (original) order,
+// pinv maps that order to internal panel indices, pmax is the largest
+// group's panel count; records are float (fp32) or double.
+struct NextSrc {
+  const int64_t* gp;
+  const int32_t* pinv;
+  int64_t pmax;
+  int fp32;
+  PanelMaps m;
+  int K;
+  const double* wa;
+  const double* nrm;
+  const double* rlap;
+  double* sig;
+  double* mu;
+  void* src;
+};
 void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m, int R, int nbj,
                            const double* part, const double* h1, const double* V, int64_t ldv, double* w,
-                           double* H, double* cs, double* sn, double* gv, double* resid, hipStream_t s);
+                           double* H, double* cs, double* sn, double* gv, double* resid, const NextSrc* ns,
+                           hipStream_t s);
 void launch_group_row0(int G, int R, int nbj, const double* part, double* out, hipStream_t s);
 void launch_lincomb(const int64_t* gu, int G, int64_t nmax, int m, int ystride, const double* V, int64_t ldv,
                     const double* y, double* x, hipStream_t s);

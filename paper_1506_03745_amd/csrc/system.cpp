@@ -119,6 +119,12 @@ void System::build(hipStream_t s) {
       }
     }
   });
+  {
+    // original panel order (the unknowns' order) -> internal index
+    std::vector<int32_t> pinv(np_);
+    for (int64_t g = 0; g < np_; ++g) pinv[poff_[psurf[g]] + h_panel_orig_[g]] = (int32_t)g;
+    pinv_.upload(pinv, s);
+  }
   tri9_.upload(tri9, s);
   col_phi_.upload(col_phi, s);
   col_psi_.upload(col_psi, s);
@@ -287,39 +293,36 @@ void System::build(hipStream_t s) {
 
   build_plan();
   upload_plan(s);
-  // Moments of the internal boxes that some M2P task reads, each shifted
-  // straight from its leaf descendants (one launch, no level order).
+  // Moments of every box that some M2P task reads, from its own sources,
+  // in chunks of at most kMomChunk sources.
   {
     std::vector<char> used(nbox_, 0);
     for (int32_t b : plan_.blist) used[b] = 1;
-    std::vector<int32_t> mb, db(nbox_, 0), de(nbox_, 0), dl;
-    for (int e = 0; e < ns; ++e) {
-      const SurfTree& T = trees_[e];
-      for (size_t bi = 0; bi < T.boxes.size(); ++bi) {
-        const int g = (int)(boff_[e] + bi);
-        if (T.boxes[bi].leaf || !used[g]) continue;
-        mb.push_back(g);
-        db[g] = (int32_t)dl.size();
-        std::vector<int32_t> stack{(int32_t)bi};
-        while (!stack.empty()) {
-          const TreeBox& b = T.boxes[stack.back()];
-          stack.pop_back();
-          for (int k = b.child_end - 1; k >= b.child_beg; --k) {
-            const int32_t c = T.child_list[k];
-            if (T.boxes[c].leaf) dl.push_back((int32_t)(boff_[e] + c));
-            else stack.push_back(c);
-          }
-        }
-        de[g] = (int32_t)dl.size();
+    std::vector<MomChunk> ch, heads;
+    int32_t slots = 0;
+    std::vector<int32_t> sb = bsbeg_.download(s), se = bsend_.download(s);
+    for (int b = 0; b < nbox_; ++b) {
+      if (!used[b] || se[b] <= sb[b]) continue;
+      const int32_t n = se[b] - sb[b];
+      const int32_t np = (n + kMomChunk - 1) / kMomChunk;
+      for (int32_t i = 0; i < np; ++i) {
+        const int32_t a0 = sb[b] + (int32_t)((int64_t)n * i / np), a1 = sb[b] + (int32_t)((int64_t)n * (i + 1) / np);
+        ch.push_back(MomChunk{b, a0, a1, np > 1 ? slots : 0, np, i});
+      }
+      if (np > 1) {
+        heads.push_back(MomChunk{b, sb[b], se[b], slots, np, 0});
+        slots += np;
       }
     }
-    n_m2m_ = (int)mb.size();
-    if (mb.empty()) mb.push_back(0);
-    if (dl.empty()) dl.push_back(0);
-    m2m_boxes_.upload(mb, s);
-    bdbeg_.upload(db, s);
-    bdend_.upload(de, s);
-    bdlist_.upload(dl, s);
+    nmchunks_ = (int)ch.size();
+    nmheads_ = (int)heads.size();
+    if (ch.empty()) ch.push_back(MomChunk{0, 0, 0, 0, 1, 0});
+    if (heads.empty()) heads.push_back(MomChunk{0, 0, 0, 0, 1, 0});
+    mchunks_.upload(ch, s);
+    mheads_.upload(heads, s);
+    const size_t NC = (size_t)ncoef(prm_.taylor_p);
+    msum32_.alloc(std::max<size_t>(slots, 1) * 2 * NC);
+    msum64_.alloc(std::max<size_t>(slots, 1) * 2 * NC);
   }
 }
 
@@ -589,7 +592,7 @@ void System::build_plan() {
 // M2M, M2P) runs on the system's second stream; the two write disjoint
 // partial slots and join before the combine.
 template <typename T>
-void System::interactions(hipStream_t s, const double* x, bool timed) {
+void System::interactions(hipStream_t s, const double* x, bool timed, bool src_ready) {
   const bool f32 = std::is_same<T, float>::value;
   T* src = f32 ? (T*)src32_.p : (T*)src64_.p;
   const T* tgt = f32 ? (const T*)tgt32_.p : (const T*)tgt64_.p;
@@ -597,7 +600,9 @@ void System::interactions(hipStream_t s, const double* x, bool timed) {
   T* ppart = f32 ? (T*)ppart32_.p : (T*)ppart64_.p;
   const int npairs = (int)(plan_.p2p.size() / 2);
   T* mom = f32 ? (T*)mom32_.p : (T*)mom64_.p;
-  if (x) {
+  if (src_ready) {
+    // records, sig and mu of x already written (by the Arnoldi update)
+  } else if (x) {
     PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
     launch_strengths_x<T>(ns_, K_, m, x, src_wa_.p, nrm_.p, rlap_.p, sig_.p, mu_.p, src, s);
   } else {
@@ -608,11 +613,9 @@ void System::interactions(hipStream_t s, const double* x, bool timed) {
   const bool fused = far && far_mode_ == 2;
   if (timed || two) PBT_HIP(hipEventRecord(ev_[1], s));
   const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
+  T* msum = f32 ? (T*)msum32_.p : (T*)msum64_.p;
   auto moments = [&](hipStream_t fs) {
-    BoxDev bd{bcen_.p, bsbeg_.p, bsend_.p, bcbeg_.p, bcend_.p, bclist_.p, brho_.p};
-    launch_p2m<T>(prm_.taylor_p, nleaf_, leaf_boxes_.p, bd, src, mom, fs);
-    const BoxDev bdl{bcen_.p, bsbeg_.p, bsend_.p, bdbeg_.p, bdend_.p, bdlist_.p, brho_.p};
-    launch_m2m<T>(prm_.taylor_p, n_m2m_, m2m_boxes_.p, bdl, mom, fs);
+    launch_moments<T>(prm_.taylor_p, nmchunks_, mchunks_.p, nmheads_, mheads_.p, bcen_.p, brho_.p, src, mom, msum, fs);
   };
   auto far_field = [&](hipStream_t fs) {
     if (timed) PBT_HIP(hipEventRecord(evm_[0], fs));
@@ -657,11 +660,11 @@ void System::interactions(hipStream_t s, const double* x, bool timed) {
 }
 
 void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x,
-                   bool timed) {
+                   bool timed, bool src_ready) {
   ++napply_;
   if (timed) PBT_HIP(hipEventRecord(ev_[0], s));
-  if (fp32) interactions<float>(s, from_x ? x : nullptr, timed);
-  else interactions<double>(s, from_x ? x : nullptr, timed);
+  if (fp32) interactions<float>(s, from_x ? x : nullptr, timed, src_ready);
+  else interactions<double>(s, from_x ? x : nullptr, timed, src_ready);
   CombineArgs a{};
   a.np = np_;
   a.chunks = dchunks_.p;
@@ -699,8 +702,8 @@ void System::timing(double out[5]) {
   out[4] = a + b;   // strengths + combine (P2P and the far field overlap)
 }
 
-void System::matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed) {
-  apply(fp32, true, x, y, s, true, timed);
+void System::matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed, bool src_ready) {
+  apply(fp32, true, x, y, s, true, timed, src_ready);
 }
 
 // Known densities of the charged (sigma) and potential (phi0) surfaces, in
@@ -783,20 +786,29 @@ void System::ensure_groups(hipStream_t s) {
   const int ns = (int)surfs_.size();
   int G = 1;
   for (int e = 0; e < ns; ++e) G = std::max(G, surfs_[e]->group + 1);
-  std::vector<int64_t> gu(2 * G, -1);
+  std::vector<int64_t> gu(2 * G, -1), gp(2 * G, -1);
   for (int e = 0; e < ns; ++e) {
     const int g = surfs_[e]->group;
-    if (gu[2 * g] < 0) gu[2 * g] = col_off_[e];
-    else if (gu[2 * g + 1] != col_off_[e]) throw Error(PBT_E_INVALID, "the surfaces of a group must be consecutive");
+    if (gu[2 * g] < 0) {
+      gu[2 * g] = col_off_[e];
+      gp[2 * g] = poff_[e];
+    } else if (gu[2 * g + 1] != col_off_[e]) {
+      throw Error(PBT_E_INVALID, "the surfaces of a group must be consecutive");
+    }
     gu[2 * g + 1] = col_off_[e + 1];
+    gp[2 * g + 1] = poff_[e + 1];
   }
   gmax_ = 0;
+  gpmax_ = 0;
   for (int g = 0; g < G; ++g) {
     if (gu[2 * g] < 0) gu[2 * g] = gu[2 * g + 1] = 0;
+    if (gp[2 * g] < 0) gp[2 * g] = gp[2 * g + 1] = 0;
     gmax_ = std::max(gmax_, gu[2 * g + 1] - gu[2 * g]);
+    gpmax_ = std::max(gpmax_, gp[2 * g + 1] - gp[2 * g]);
   }
   G_ = G;
   dgu_.upload(gu, s);
+  dgp_.upload(gp, s);
   gu_ = gu;
 }
 
@@ -872,12 +884,21 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   // one Arnoldi step: w = A V_k, then pass 1 (partial V^T w), pass 2 (h1 =
   // sum of pass 1, partial V^T w' and |w'|^2 with w' = w - V h1), then
   // w = (w - V h) / |w''| with each group's Hessenberg column and rotation
+  // The forward operator takes the new basis vector's source records from
+  // the update that produced it (step k > 0); the transposed operator starts
+  // from targets instead and does not use them.
+  const bool fuse = !transpose_;
+  const NextSrc nsrc{dgp_.p, pinv_.p, gpmax_, fp32 ? 1 : 0,
+                     PanelMaps{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p},
+                     K_, src_wa_.p, nrm_.p, rlap_.p, sig_.p, mu_.p,
+                     fp32 ? (void*)src32_.p : (void*)src64_.p};
   auto enqueue_step = [&](int k) {
     double* vj1 = V_.p + (size_t)(k + 1) * n_;
-    op(V_.p + (size_t)k * n_, vj1, fp32, s);
+    op(V_.p + (size_t)k * n_, vj1, fp32, s, fuse && k > 0);
     launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, nullptr, 0, part1, nbj, s);
     launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, h1, 1, part2, nbj, s);
-    launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, dres, s);
+    launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, dres,
+                          fuse ? &nsrc : nullptr, s);
   };
   while (pending() && iters < maxit) {
     std::vector<int> used(G, 0);

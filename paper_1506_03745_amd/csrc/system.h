@@ -126,7 +126,8 @@ class System {
 
   // y = A x on device buffers (n doubles each), FP64 or FP32 interactions;
   // `timed` records the per-phase events read by timing().
-  void matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed = false);
+  // src_ready: the source records, sig and mu of x are already in place.
+  void matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed = false, bool src_ready = false);
   // FP64 right-hand side for the current charges and boundary values.
   void rhs(double* b_dev, hipStream_t s);
   // Solves A x = b (b, x device); returns result fields (iters, outer,
@@ -183,18 +184,18 @@ class System {
   void build(hipStream_t s);
   void build_plan();
   void apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x = false,
-             bool timed = false);
+             bool timed = false, bool src_ready = false);
   template <typename T>
-  void interactions(hipStream_t s, const double* x, bool timed);
+  void interactions(hipStream_t s, const double* x, bool timed, bool src_ready);
   int gmres(bool fp32, const double* b, double* x, bool x_zero, const std::vector<double>& tol_abs,
             int restart, int maxit, std::vector<double>& resid_out, hipStream_t s,
             const std::vector<double>* b_norms = nullptr);
   void ensure_groups(hipStream_t s);
   std::vector<double> group_norms(const double* v, hipStream_t s);
   void true_residual(const double* b, const double* x, double* r, hipStream_t s);
-  void op(const double* x, double* y, bool fp32, hipStream_t s) {
+  void op(const double* x, double* y, bool fp32, hipStream_t s, bool src_ready = false) {
     if (transpose_) matvec_t(x, y, fp32, nullptr, s);
-    else matvec(x, y, fp32, s);
+    else matvec(x, y, fp32, s, false, src_ready);
   }
   bool solve_any(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s);
   void build_tplan(hipStream_t s);
@@ -246,15 +247,19 @@ class System {
   DBuf<int32_t> surf_mol_;
   DBuf<double> surf_rhoinv_;
   std::vector<int32_t> h_panel_orig_;  // internal global -> original index within its surface
+  DBuf<int32_t> pinv_;                 // poff + original index -> internal global index
 
   // tree (global box numbering)
   int nbox_ = 0;
   DBuf<double> bcen_, brho_;
   DBuf<int32_t> bsbeg_, bsend_, bcbeg_, bcend_, bclist_;
   DBuf<int32_t> leaf_boxes_;
-  int n_m2m_ = 0;                 // internal boxes whose moments M2P reads
-  DBuf<int32_t> m2m_boxes_;
-  DBuf<int32_t> bdbeg_, bdend_, bdlist_;  // their leaf descendants
+  int nmchunks_ = 0;              // source chunks of the boxes whose moments M2P reads
+  DBuf<MomChunk> mchunks_;
+  DBuf<float> msum32_;            // chunk sums of boxes of several chunks
+  DBuf<double> msum64_;
+  int nmheads_ = 0;               // boxes of several chunks (their first chunks)
+  DBuf<MomChunk> mheads_;
   int nleaf_ = 0;
   DBuf<float> mom32_;
   DBuf<double> mom64_;
@@ -276,8 +281,10 @@ class System {
   int G_ = 1;
   int64_t dense_pairs_ = 0;
   int64_t gmax_ = 0;                 // unknowns of the largest group
+  int64_t gpmax_ = 0;                // panels of the largest group
   std::vector<int64_t> gu_;          // [2G] unknown range of each group
   DBuf<int64_t> dgu_;
+  DBuf<int64_t> dgp_;                // panel range [2g, 2g + 1) of each group
   std::vector<double> group_rel_;    // last solve: relative residual per group
 
   hipEvent_t ev_[6];

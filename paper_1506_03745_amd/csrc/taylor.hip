@@ -34,13 +34,6 @@ __host__ __device__ constexpr int tidx(int a, int b, int c) {
   return (a + b + c) * (a + b + c + 1) * (a + b + c + 2) / 6 + (b + c) * (b + c + 1) / 2 + c;
 }
 
-struct MultiIdx {
-  int8_t a, b, c, n;
-};
-
-__constant__ MultiIdx c_midx[ncoef(kMaxP)];
-__constant__ int8_t c_binom[kMaxP + 1][kMaxP + 1];
-
 template <typename T>
 struct TMath;
 template <>
@@ -56,109 +49,171 @@ struct TMath<double> {
 
 #include "near_field.h"
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
+// ---- Moments (P2M) -----------------------------------------------------------
+// Every box that some M2P task reads gets its moments straight from its own
+// sources (a box's sources are contiguous in tree order), so boxes of all
+// levels are done in one launch with no level-by-level shifting.  Large boxes
+// are cut into chunks of at most kMomChunk sources; one block per (chunk,
+// group of kMomGroup coefficients), threads over the chunk's sources, each
+// thread accumulating the group's coefficients of both rows in registers:
+//   row 0: sum_j s_j h^k + D_j . grad h^k,   row 1: -rho_inv s_j h^k - D_j . grad h^k
+// with grad h^k = (a h^(k-e_x), b h^(k-e_y), c h^(k-e_z)).  The block adds its
+// threads' sums up through LDS in a fixed order.  A box of several chunks has
+// its chunk sums written to partial slots, which a second launch adds in
+// chunk order, so results do not depend on block scheduling.
+constexpr int kMomThreads = 256;
 
-// ---- P2M: one wavefront per (leaf box, coefficient k), four coefficients
-// per block; lanes over sources.  The exponents of k are uniform across the
-// wavefront, so the power loops do not diverge.
-template <typename T>
-__global__ __launch_bounds__(256) void k_p2m(int P, const int32_t* __restrict__ boxes, BoxDev bd,
-                                             const T* __restrict__ src, T* __restrict__ mom) {
-  const int NC = ncoef(P);
-  const int b = boxes[blockIdx.x];
-  const int k = blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-  if (k >= NC) return;
-  const int lane = threadIdx.x & 63;
-  const MultiIdx mi = c_midx[k];
-  const T cx = (T)bd.center[3 * b], cy = (T)bd.center[3 * b + 1], cz = (T)bd.center[3 * b + 2];
-  T ms = 0, md = 0;
-#pragma unroll 4
-  for (int j = bd.sbeg[b] + lane; j < bd.send[b]; j += 64) {
-    const T* s = src + (int64_t)kSrcStride * j;
-    const T hx = s[0] - cx, hy = s[1] - cy, hz = s[2] - cz;
-    T px = 1, py = 1, pz = 1, qx = 0, qy = 0, qz = 0;  // h^a and a h^(a-1)
-    for (int t = 0; t < mi.a; ++t) { qx = qx * hx + px; px *= hx; }
-    for (int t = 0; t < mi.b; ++t) { qy = qy * hy + py; py *= hy; }
-    for (int t = 0; t < mi.c; ++t) { qz = qz * hz + pz; pz *= hz; }
-    ms += s[3] * (px * py * pz);
-    md += s[4] * (qx * py * pz) + s[5] * (px * qy * pz) + s[6] * (px * py * qz);
-  }
-  ms = wave_sum(ms);
-  md = wave_sum(md);
-  if (lane == 0) {
-    const T ri = (T)bd.rho_inv[b];
-    mom[(int64_t)(2 * b) * NC + k] = ms + md;
-    mom[(int64_t)(2 * b + 1) * NC + k] = -ri * ms - md;
-  }
+__host__ __device__ constexpr int midx_n(int k) {
+  int n = 0;
+  while (tidx(n + 1, 0, 0) <= k) ++n;
+  return n;
 }
+__host__ __device__ constexpr int midx_m(int k) {  // b + c
+  const int r = k - tidx(midx_n(k), 0, 0);
+  int m = 0;
+  while ((m + 1) * (m + 2) / 2 <= r) ++m;
+  return m;
+}
+__host__ __device__ constexpr int midx_c(int k) { return k - tidx(midx_n(k), 0, 0) - midx_m(k) * (midx_m(k) + 1) / 2; }
+__host__ __device__ constexpr int midx_b(int k) { return midx_m(k) - midx_c(k); }
+__host__ __device__ constexpr int midx_a(int k) { return midx_n(k) - midx_m(k); }
 
-// ---- M2M: one block per (box, coefficient k); threads over the terms
-// (descendant, m <= k) of
-//   M_k(box) = sum_desc sum_{m <= k} C(k, m) delta^(k-m) M_m(desc),
-// delta = c_desc - c_box (h = y - c_box = (y - c_desc) + delta).  The
-// descendants are the box's leaves, whose moments come from P2M, so every
-// box is done in the same launch.
-constexpr int kM2MThreads = 256;
-template <typename T>
-__global__ __launch_bounds__(kM2MThreads) void k_m2m(int P, const int32_t* __restrict__ boxes, BoxDev bd,
-                                                     T* __restrict__ mom) {
-  __shared__ T red[kM2MThreads / 64][2];
-  const int NC = ncoef(P);
-  const int b = boxes[blockIdx.x];
-  const int k = blockIdx.y;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const MultiIdx mk = c_midx[k];
-  const int nb = mk.b + 1, nc = mk.c + 1;
-  const int nterm = (mk.a + 1) * nb * nc;
-  const int c0 = bd.child_beg[b], nchild = bd.child_end[b] - c0;
-  const double pcx = bd.center[3 * b], pcy = bd.center[3 * b + 1], pcz = bd.center[3 * b + 2];
-  T acc0 = 0, acc1 = 0;
-#pragma unroll 2
-  for (int t = threadIdx.x; t < nchild * nterm; t += kM2MThreads) {
-    const int ci = t / nterm, r = t - ci * nterm;
-    const int ma = r / (nb * nc), mb = (r / nc) % nb, mc = r % nc;
-    const int c = bd.child_list[c0 + ci];
-    const T dx = (T)(bd.center[3 * c] - pcx), dy = (T)(bd.center[3 * c + 1] - pcy),
-            dz = (T)(bd.center[3 * c + 2] - pcz);
-    T coef = (T)(c_binom[mk.a][ma] * c_binom[mk.b][mb] * c_binom[mk.c][mc]);
-    for (int q = ma; q < mk.a; ++q) coef *= dx;
-    for (int q = mb; q < mk.b; ++q) coef *= dy;
-    for (int q = mc; q < mk.c; ++q) coef *= dz;
-    const int m = tidx(ma, mb, mc);
-    acc0 += coef * mom[(int64_t)(2 * c) * NC + m];
-    acc1 += coef * mom[(int64_t)(2 * c + 1) * NC + m];
-  }
-  acc0 = wave_sum(acc0);
-  acc1 = wave_sum(acc1);
-  if (lane == 0) {
-    red[wid][0] = acc0;
-    red[wid][1] = acc1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    T s0 = 0, s1 = 0;
-    for (int w = 0; w < kM2MThreads / 64; ++w) {
-      s0 += red[w][0];
-      s1 += red[w][1];
+template <typename T, int P, int K0, int K1>
+__device__ __forceinline__ void moments_group(const MomChunk& ch, const double* __restrict__ bcen,
+                                              const double* __restrict__ brho, const T* __restrict__ src,
+                                              T* __restrict__ mom, T* __restrict__ mpart,
+                                              T* red /* [kMomThreads][2 (K1-K0) + 1] */) {
+  constexpr int NC = ncoef(P);
+  constexpr int NG = K1 - K0;
+  constexpr int W = 2 * NG + 1;
+  const int b = ch.box;
+  const T cx = (T)bcen[3 * b], cy = (T)bcen[3 * b + 1], cz = (T)bcen[3 * b + 2];
+  const T ri = (T)brho[b];
+  T acc[2 * NG];
+#pragma unroll
+  for (int q = 0; q < 2 * NG; ++q) acc[q] = 0;
+  const SrcRec<T>* srec = reinterpret_cast<const SrcRec<T>*>(src);
+  for (int j = ch.sbeg + (int)threadIdx.x; j < ch.send; j += kMomThreads) {
+    const SrcRec<T> r = load_rec(srec + j);
+    const T hx = r.v[0] - cx, hy = r.v[1] - cy, hz = r.v[2] - cz;
+    const T s = r.v[3], sl = -ri * r.v[3];
+    T px[P + 1], py[P + 1], pz[P + 1], dx[P + 1], dy[P + 1], dz[P + 1];
+    px[0] = py[0] = pz[0] = T(1);
+    dx[0] = dy[0] = dz[0] = T(0);
+#pragma unroll
+    for (int e = 1; e <= P; ++e) {
+      // d*[e] = e D h^(e-1): the derivative factor of the e-th power
+      dx[e] = r.v[4] * (T(e) * px[e - 1]);
+      dy[e] = r.v[5] * (T(e) * py[e - 1]);
+      dz[e] = r.v[6] * (T(e) * pz[e - 1]);
+      px[e] = px[e - 1] * hx;
+      py[e] = py[e - 1] * hy;
+      pz[e] = pz[e - 1] * hz;
     }
-    mom[(int64_t)(2 * b) * NC + k] = s0;
-    mom[(int64_t)(2 * b + 1) * NC + k] = s1;
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+      const int a = midx_a(k), bb = midx_b(k), c = midx_c(k);
+      const T pyz = py[bb] * pz[c];
+      const T hk = px[a] * pyz;
+      T d = 0;
+      if (a) d += dx[a] * pyz;
+      if (bb) d += dy[bb] * (px[a] * pz[c]);
+      if (c) d += dz[c] * (px[a] * py[bb]);
+      acc[2 * (k - K0)] += s * hk + d;
+      acc[2 * (k - K0) + 1] += sl * hk - d;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2 * NG; ++q) red[threadIdx.x * W + q] = acc[q];
+  __syncthreads();
+  // column q (coefficient K0 + q/2, row q%2) over the 256 threads: 8 lanes a
+  // column, each over 32 rows, then a fixed xor butterfly over the 8
+  const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
+  T v = 0;
+  if (q < 2 * NG) {
+#pragma unroll 8
+    for (int i = 0; i < kMomThreads / 8; ++i) v += red[(part + 8 * i) * W + q];
+  }
+  v += __shfl_xor(v, 4, 8);
+  v += __shfl_xor(v, 2, 8);
+  v += __shfl_xor(v, 1, 8);
+  if (q < 2 * NG && part == 0) {
+    const int k = K0 + (q >> 1), row = q & 1;
+    if (ch.nparts == 1) mom[(int64_t)(2 * b + row) * NC + k] = v;
+    else mpart[((int64_t)(ch.slot0 + ch.idx) * NC + k) * 2 + row] = v;
+  }
+}
+
+template <typename T, int P, int G>
+__device__ __forceinline__ void moments_dispatch(const MomChunk& ch, int gi, const double* bcen, const double* brho,
+                                                 const T* src, T* mom, T* mpart, T* red) {
+  constexpr int K0 = G * kMomGroup;
+  if constexpr (K0 < ncoef(P)) {
+    constexpr int K1 = K0 + kMomGroup < ncoef(P) ? K0 + kMomGroup : ncoef(P);
+    if (gi == G) {
+      moments_group<T, P, K0, K1>(ch, bcen, brho, src, mom, mpart, red);
+      return;
+    }
+    moments_dispatch<T, P, G + 1>(ch, gi, bcen, brho, src, mom, mpart, red);
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kMomThreads) void k_moments(const MomChunk* __restrict__ chunks,
+                                                         const double* __restrict__ bcen,
+                                                         const double* __restrict__ brho,
+                                                         const T* __restrict__ src, T* __restrict__ mom,
+                                                         T* __restrict__ mpart) {
+  __shared__ T red[kMomThreads * (2 * kMomGroup + 1)];
+  const MomChunk ch = chunks[blockIdx.x];
+  moments_dispatch<T, P, 0>(ch, (int)blockIdx.y, bcen, brho, src, mom, mpart, red);
+}
+
+// Boxes of several chunks: their moments are the chunk sums added in chunk
+// order.  One block per box, threads over the 2 ncoef(P) values.
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments_sum(const MomChunk* __restrict__ heads, int NC,
+                                                     const T* __restrict__ mpart, T* __restrict__ mom) {
+  const MomChunk h = heads[blockIdx.x];
+  for (int t = threadIdx.x; t < 2 * NC; t += 256) {
+    const int k = t >> 1, row = t & 1;
+    T v = 0;
+    for (int i = 0; i < h.nparts; ++i) v += mpart[((int64_t)(h.slot0 + i) * NC + k) * 2 + row];
+    mom[(int64_t)(2 * h.box + row) * NC + k] = v;
   }
 }
 
 // ---- M2P -------------------------------------------------------------------
+// The recurrences above, evaluated with the first-neighbour sums taken
+// against pre-scaled R: with u = (2n-1)/(n|R|^2) R and v = kappa/(n|R|^2) R,
+//   Laplace  a_k = sum_i u_i a_{k-e_i} - (n-1)/(n|R|^2) sum_i a_{k-2e_i}
+//   Yukawa   a_k = sum_i u_i a_{k-e_i} + sum_i v_i b_{k-e_i}
+//                  - (n-1)/(n|R|^2) sum_i a_{k-2e_i} - kappa/(n|R|^2) sum_i b_{k-2e_i}
+//            b_k = kappa |R|^2/(2n-1) sum_i u_i a_{k-e_i} - kappa/n sum_i a_{k-2e_i}
+// (the same quantities, one multiplication fewer per coefficient).
+// A wave-uniform zero that the compiler cannot see through, produced after
+// v: moment offsets built from it keep a degree's (scalar) moment loads from
+// being hoisted above the arithmetic of the degree two below, which would
+// hold every moment of the box in scalar registers at once and spill them.
+template <typename T>
+__device__ __forceinline__ int zero_after(T v) {
+  int z;
+  __asm__ volatile("s_mov_b32 %0, 0" : "=s"(z) : "v"(v));
+  return z;
+}
+
 template <typename T, int P, bool YUK>
-__device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* __restrict__ M) {
+__device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
   constexpr int NC = ncoef(P);
   T A[NC];
   T B[YUK ? NC : 1];
+  int dz[P + 3];
+#pragma unroll
+  for (int n = 0; n < P + 3; ++n) dz[n] = 0;
   const T R2 = Rx * Rx + Ry * Ry + Rz * Rz;
   const T Rinv = TMath<T>::rsq(R2);
   const T invR2 = Rinv * Rinv;
+  const T kR2 = kappa * R2;
   if (YUK) {
     const T e = TMath<T>::expm(kappa * (R2 * Rinv));
     A[0] = e * Rinv;
@@ -169,10 +224,15 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* __re
   T acc = A[0] * M[0];
 #pragma unroll
   for (int n = 1; n <= P; ++n) {
+    const T* Mn = M + dz[n];
     const T c1 = T(2 * n - 1) / T(n) * invR2;
     const T c2 = T(n - 1) / T(n) * invR2;
-    const T c3 = kappa / T(n) * invR2;
-    const T c4 = kappa / T(n);
+    const T c3 = kappa * (T(1) / T(n)) * invR2;
+    const T c4 = kappa * (T(1) / T(n));
+    const T e4 = kR2 * (T(1) / T(2 * n - 1));
+    const T ux = c1 * Rx, uy = c1 * Ry, uz = c1 * Rz;
+    T vx = 0, vy = 0, vz = 0;
+    if (YUK) { vx = c3 * Rx; vy = c3 * Ry; vz = c3 * Rz; }
 #pragma unroll
     for (int a = n; a >= 0; --a) {
 #pragma unroll
@@ -180,27 +240,30 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* __re
         const int c = n - a - b;
         const int k = tidx(a, b, c);
         T S1 = 0, S2 = 0, T1 = 0, T2 = 0;
-        if (a >= 1) { S1 += Rx * A[tidx(a - 1, b, c)]; if (YUK) T1 += Rx * B[tidx(a - 1, b, c)]; }
-        if (b >= 1) { S1 += Ry * A[tidx(a, b - 1, c)]; if (YUK) T1 += Ry * B[tidx(a, b - 1, c)]; }
-        if (c >= 1) { S1 += Rz * A[tidx(a, b, c - 1)]; if (YUK) T1 += Rz * B[tidx(a, b, c - 1)]; }
-        if (a >= 2) { S2 += A[tidx(a - 2, b, c)]; if (YUK) T2 += B[tidx(a - 2, b, c)]; }
-        if (b >= 2) { S2 += A[tidx(a, b - 2, c)]; if (YUK) T2 += B[tidx(a, b - 2, c)]; }
-        if (c >= 2) { S2 += A[tidx(a, b, c - 2)]; if (YUK) T2 += B[tidx(a, b, c - 2)]; }
+        bool h2 = false;
+        if (a >= 1) { S1 += ux * A[tidx(a - 1, b, c)]; if (YUK) T1 += vx * B[tidx(a - 1, b, c)]; }
+        if (b >= 1) { S1 += uy * A[tidx(a, b - 1, c)]; if (YUK) T1 += vy * B[tidx(a, b - 1, c)]; }
+        if (c >= 1) { S1 += uz * A[tidx(a, b, c - 1)]; if (YUK) T1 += vz * B[tidx(a, b, c - 1)]; }
+        if (a >= 2) { S2 += A[tidx(a - 2, b, c)]; if (YUK) T2 += B[tidx(a - 2, b, c)]; h2 = true; }
+        if (b >= 2) { S2 += A[tidx(a, b - 2, c)]; if (YUK) T2 += B[tidx(a, b - 2, c)]; h2 = true; }
+        if (c >= 2) { S2 += A[tidx(a, b, c - 2)]; if (YUK) T2 += B[tidx(a, b, c - 2)]; h2 = true; }
         if (YUK) {
-          A[k] = c1 * S1 - c2 * S2 + c3 * (T1 - T2);
-          B[k] = c4 * (S1 - S2);
+          A[k] = h2 ? (S1 + T1) - c2 * S2 - c3 * T2 : S1 + T1;
+          if (n < P) B[k] = h2 ? e4 * S1 - c4 * S2 : e4 * S1;
         } else {
-          A[k] = c1 * S1 - c2 * S2;
+          A[k] = h2 ? S1 - c2 * S2 : S1;
         }
-        acc += A[k] * M[k];
+        acc += A[k] * Mn[k];
       }
     }
+    if (n + 2 <= P) dz[n + 2] = zero_after(acc);
   }
   return acc;
 }
 
 // One M2P task (64 targets x a list of boxes) on one wavefront, one target
-// per lane.
+// per lane; the box moments are wave-uniform and read through the scalar
+// cache.
 template <typename T, int P>
 __device__ __forceinline__ void m2p_task(const Task& task, const int32_t* __restrict__ blist,
                                          const T* __restrict__ tgt, const double* __restrict__ bcen,
@@ -256,46 +319,30 @@ __global__ __launch_bounds__(256) void k_m2p_p2p(const Task* __restrict__ m2p, i
     p2p_task_pair<T, GUARD>(p2p + 2 * (wv - nm2p), tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, ppartial);
 }
 
-bool g_tables_ready[64] = {false};
-
-void upload_tables() {
-  int dev = 0;
-  PBT_HIP(hipGetDevice(&dev));
-  if (dev < 64 && g_tables_ready[dev]) return;
-  MultiIdx h[ncoef(kMaxP)];
-  for (int n = 0; n <= kMaxP; ++n)
-    for (int a = n; a >= 0; --a)
-      for (int b = n - a; b >= 0; --b) {
-        const int c = n - a - b;
-        h[tidx(a, b, c)] = MultiIdx{(int8_t)a, (int8_t)b, (int8_t)c, (int8_t)n};
-      }
-  int8_t bin[kMaxP + 1][kMaxP + 1] = {};
-  for (int n = 0; n <= kMaxP; ++n) {
-    bin[n][0] = 1;
-    for (int k = 1; k <= n; ++k) bin[n][k] = (int8_t)(bin[n - 1][k - 1] + (k <= n - 1 ? bin[n - 1][k] : 0));
-  }
-  PBT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_midx), h, sizeof(h)));
-  PBT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_binom), bin, sizeof(bin)));
-  if (dev < 64) g_tables_ready[dev] = true;
-}
-
 }  // namespace
 
-template <typename T>
-void launch_p2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, const T* src, T* mom,
-                hipStream_t s) {
-  if (nbox <= 0) return;
-  upload_tables();
-  k_p2m<T><<<dim3(nbox, (ncoef(P) + 3) / 4), 256, 0, s>>>(P, boxes, b, src, mom);
-  PBT_HIP(hipGetLastError());
+template <typename T, int P>
+static void moments_p(int nchunks, const MomChunk* chunks, const double* bcen, const double* brho, const T* src,
+                      T* mom, T* mpart, hipStream_t s) {
+  k_moments<T, P><<<dim3(nchunks, mom_groups(P)), kMomThreads, 0, s>>>(chunks, bcen, brho, src, mom, mpart);
 }
 
 template <typename T>
-void launch_m2m(int P, int nbox, const int32_t* boxes, const BoxDev& b, T* mom, hipStream_t s) {
-  if (nbox <= 0) return;
-  upload_tables();
-  k_m2m<T><<<dim3(nbox, ncoef(P)), kM2MThreads, 0, s>>>(P, boxes, b, mom);
+void launch_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
+                    const double* bcen, const double* brho, const T* src, T* mom, T* mpart, hipStream_t s) {
+  if (nchunks <= 0) return;
+  switch (P) {
+#define PBT_CASE(PP) \
+  case PP: moments_p<T, PP>(nchunks, chunks, bcen, brho, src, mom, mpart, s); break;
+    PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
+#undef PBT_CASE
+    default: throw Error(1, "Taylor order P must be 0..8");
+  }
   PBT_HIP(hipGetLastError());
+  if (nheads > 0) {
+    k_moments_sum<T><<<nheads, 256, 0, s>>>(heads, ncoef(P), mpart, mom);
+    PBT_HIP(hipGetLastError());
+  }
 }
 
 template <typename T, int P>
@@ -355,10 +402,10 @@ void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, cons
   PBT_HIP(hipGetLastError());
 }
 
-template void launch_p2m<float>(int, int, const int32_t*, const BoxDev&, const float*, float*, hipStream_t);
-template void launch_p2m<double>(int, int, const int32_t*, const BoxDev&, const double*, double*, hipStream_t);
-template void launch_m2m<float>(int, int, const int32_t*, const BoxDev&, float*, hipStream_t);
-template void launch_m2m<double>(int, int, const int32_t*, const BoxDev&, double*, hipStream_t);
+template void launch_moments<float>(int, int, const MomChunk*, int, const MomChunk*, const double*, const double*,
+                                    const float*, float*, float*, hipStream_t);
+template void launch_moments<double>(int, int, const MomChunk*, int, const MomChunk*, const double*, const double*,
+                                     const double*, double*, double*, hipStream_t);
 template void launch_m2p_p2p<float>(int, const Task*, int, const int32_t*, const double*, const float*,
                                     const Task*, int, const int32_t*, const float*, const float*, float, bool,
                                     float*, float*, hipStream_t);

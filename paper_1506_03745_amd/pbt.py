@@ -26,7 +26,8 @@ EXPORTS = ("pbt_default_params", "pbt_create", "pbt_destroy", "pbt_last_error", 
            "pbt_set_solvent", "pbt_add_surface", "pbt_set_bc", "pbt_set_charges", "pbt_enable",
            "pbt_prepare", "pbt_num_unknowns", "pbt_solve", "pbt_get_solution", "pbt_interaction_energy",
            "pbt_matvec", "pbt_matvec_dev", "pbt_rhs", "pbt_gradient", "pbt_solve_batch",
-           "pbt_autotune", "pbt_last_stats", "pbt_set_schedule", "pbt_quadrature_rule", "pbt_last_matvec_timing")
+           "pbt_autotune", "pbt_last_stats", "pbt_set_schedule", "pbt_get_schedule", "pbt_quadrature_rule",
+           "pbt_last_matvec_timing")
 
 
 class PbtParams(ctypes.Structure):
@@ -98,6 +99,7 @@ def lib():
         L.pbt_solve_batch.argtypes = [P, I32, P, P, I32, P]
         L.pbt_autotune.argtypes = [P, ctypes.c_char_p]
         L.pbt_set_schedule.argtypes = [P, I32]
+        L.pbt_get_schedule.argtypes = [P, ctypes.POINTER(I32)]
         L.pbt_last_stats.argtypes = [P, ctypes.POINTER(PbtResult)]
         L.pbt_quadrature_rule.argtypes = [I32, P, P]
         L.pbt_last_matvec_timing.argtypes = [P, P]
@@ -295,6 +297,11 @@ class Solver:
 
     def set_schedule(self, mode):
         self._check(lib().pbt_set_schedule(self._h, int(mode)))
+
+    def schedule(self):
+        m = ctypes.c_int32()
+        self._check(lib().pbt_get_schedule(self._h, ctypes.byref(m)))
+        return m.value
 
 
 def from_problem(problem, device=0, **params) -> tuple[Solver, list[int]]:
