@@ -31,7 +31,7 @@ FP32_NONPACKED_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 G
 FLOPS_FUSED_PAIR = 29    # Laplace + Yukawa, single + double layer (op list in the design doc)
 FLOPS_YUKAWA_PAIR = 26
 P2P_PROFILE = os.path.join(ROOT, "profiles", "k_p2p_twosphere_charge.json")
-P2P_SOURCES = (os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "matvec_kernels.hip"),
+P2P_SOURCES = (os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "p2p.hip"),
                os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "near_field.h"))
 
 
@@ -308,7 +308,8 @@ def main():
         "gmres": {"iters": r.iters, "outer": r.outer, "rel_resid": r.rel_resid,
                   "applications_per_step": applications, "setup_s": round(setup_wall, 4),
                   "autotune_s": round(autotune_s, 3)},
-        "far_field_schedule": {0: "serial", 1: "two streams", 2: "joint M2P + P2P launch"}[schedule],
+        "far_field_schedule": {0: "serial", 1: "two streams", 2: "joint M2P + P2P launch",
+                               3: "moments inside the P2P launch"}[schedule],
         "matvec_ms": {"fp32": {k: round(v, 4) for k, v in acc.items()},
                       "fp64": {k: round(v, 4) for k, v in acc64.items()},
                       "fp32_serial_schedule": {k: round(v, 4) for k, v in acc_serial.items()}},

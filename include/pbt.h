@@ -220,11 +220,12 @@ pbt_status pbt_last_stats(pbt_ctx* ctx, pbt_result* out);
  * (Section 3.2 splits every product into near-field P2P and far-field
  * P2M/M2M/M2P): 0 = P2P then the far field on the context's stream,
  * 1 = the far field on a second stream, concurrently with P2P, 2 = moments
- * first, then M2P and P2P tasks in one launch.  All three give bitwise the
- * same products.  PBT_E_INVALID for another mode. */
+ * first, then M2P and P2P tasks in one launch, 3 = moments and P2P tasks in
+ * one launch, then M2P.  All four give bitwise the same products.
+ * PBT_E_INVALID for another mode. */
 pbt_status pbt_set_schedule(pbt_ctx* ctx, int32_t mode);
 
-/* The schedule the enabled system currently uses (0, 1 or 2, as for
+/* The schedule the enabled system currently uses (0 to 3, as for
  * pbt_set_schedule; pbt_autotune may have chosen it) in *mode.  Host-only. */
 pbt_status pbt_get_schedule(pbt_ctx* ctx, int32_t* mode);
 
@@ -237,8 +238,9 @@ pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w);
 
 /* Timing of the last pbt_matvec / pbt_matvec_dev on the context's own
  * events, in milliseconds: out[0] total, out[1] P2P kernel, out[2] M2P
- * kernel, out[3] moments (P2M), out[4] strengths, near field and combine.  Under
- * the joint M2P + P2P schedule out[1] is that launch and out[2] is 0. */
+ * kernel, out[3] moments (P2M), out[4] strengths, near field and combine.
+ * Under schedule 2 out[1] is the joint M2P + P2P launch and out[2] is 0;
+ * under schedule 3 out[1] is the launch of moments and P2P and out[3] is 0. */
 pbt_status pbt_last_matvec_timing(pbt_ctx* ctx, double out[5]);
 
 #ifdef __cplusplus

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "pbt")
 LIB = os.path.join(HERE, "libpbt.so")
 
-SOURCES = ["setup_kernels.hip", "matvec_kernels.hip", "taylor.hip", "krylov.hip", "adjoint.hip",
+SOURCES = ["setup_kernels.hip", "matvec_kernels.hip", "p2p.hip", "taylor.hip", "krylov.hip", "adjoint.hip",
            "quadrature.cpp", "tree.cpp", "system.cpp", "system_adjoint.cpp", "abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -617,7 +617,7 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
 
 // Autotuner: times the operator of the enabled system for candidate P2P and
 // M2P segment sizes (coordinate search: P2P first, then M2P) and then for
-// the three schedules of the far field against P2P, in the solve's
+// the four schedules of the far field against P2P, in the solve's
 // interaction precision, keeps the fastest, and remembers it per system
 // shape in memory and, if given, in a text cache file
 // ("key seg_src 4*seg_box+schedule ms" per line).
@@ -663,7 +663,7 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
     S.set_segments(best_src, best_box, c->stream);
     // scheduling of the far field against P2P (serial, two streams, one launch)
     int best_mode = S.far_mode();
-    for (int mode = 0; mode < 3; ++mode) {
+    for (int mode = 0; mode < 4; ++mode) {
       if (mode == best_mode) continue;
       S.set_far_mode(mode);
       const double t = S.time_products(fp32, reps, c->stream);
@@ -689,7 +689,7 @@ pbt_status pbt_last_stats(pbt_ctx* c, pbt_result* out) {
 
 pbt_status pbt_set_schedule(pbt_ctx* c, int32_t mode) {
   if (!c) return PBT_E_INVALID;
-  if (mode < 0 || mode > 2) return fail(c, PBT_E_INVALID, "schedule must be 0, 1 or 2");
+  if (mode < 0 || mode > 3) return fail(c, PBT_E_INVALID, "schedule must be 0, 1, 2 or 3");
   return guarded(c, [&] {
     system_for(c).set_far_mode(mode);
     return PBT_OK;

@@ -129,6 +129,28 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
   double* csg = cs + (size_t)g * m;
   double* sng = sn + (size_t)g * m;
   double* gg = gv + (size_t)g * (m + 1);
+  // SRC: eight lanes per panel (below); the panel's unknowns, w and first
+  // basis entries are loaded before the partials are added up, so the memory
+  // round trips overlap
+  const int sub = threadIdx.x & 7, qi = sub & 3;
+  const int64_t q = SRC ? ns.gp[2 * g] + (blockIdx.x * (int64_t)kBS + threadIdx.x) / 8 : 0;
+  const bool on = SRC && q < ns.gp[2 * g + 1];
+  int64_t p = 0;
+  int32_t cphi = -1, cpsi = -1;
+  if (on) {
+    cphi = ns.qcol[2 * q];
+    cpsi = ns.qcol[2 * q + 1];
+    p = ns.pinv[q];
+  }
+  const int32_t e = sub < 4 ? cphi : cpsi;
+  constexpr int kPre = 8;
+  double vr[kPre];
+  double we = 0.0;
+  if (SRC && e >= 0) {
+    we = w[e];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) vr[k] = qi + 4 * k <= j ? V[(int64_t)(qi + 4 * k) * ldv + e] : 0.0;
+  }
   reduce_rows(part + (int64_t)g * R * nbj, j + 2, nbj, h2);
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < j; i += kBS) {
@@ -141,10 +163,12 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     h[i] = h1[(int64_t)g * R + i] + h2[i];
     col[i] = h[i];
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    // |h2|^2 by the first wavefront (lanes over i, fixed butterfly)
     double h2s = 0.0;
-    for (int i = 0; i <= j; ++i) h2s += h2[i] * h2[i];
-    nn_s = fmax(h2[j + 1] - h2s, 0.0);
+    for (int i = threadIdx.x; i <= j; i += 64) h2s += h2[i] * h2[i];
+    h2s = wave_sum(h2s);
+    if (threadIdx.x == 0) nn_s = fmax(h2[j + 1] - h2s, 0.0);
   }
   __syncthreads();
   const double nn = nn_s;
@@ -160,22 +184,37 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     const int64_t e = u0 + blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (e < u1) update(e);
   } else {
-    // one thread per panel of the group, in the unknowns' (original) panel
-    // order so that the V and w accesses are coalesced; the panel's source
-    // records for the next product are written as the strengths kernel
+    // eight lanes per panel of the group, panels in the unknowns' (original)
+    // order so that the V and w accesses are coalesced: lanes 0-3 form the
+    // phi unknown, lanes 4-7 the psi unknown, each lane over every fourth
+    // basis vector, added by a fixed butterfly; then the panel's densities
+    // and source records for the next product, as the strengths kernel
     // would write them from the updated unknowns
-    const int64_t q = ns.gp[2 * g] + blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (q < ns.gp[2 * g + 1]) {
-      const int64_t p = ns.pinv[q];
-      const int32_t cphi = ns.m.col_phi[p], cpsi = ns.m.col_psi[p];
-      const double vphi = cphi >= 0 ? update(cphi) : 0.0;
-      const double vpsi = cpsi >= 0 ? update(cpsi) : 0.0;
+    double acc = 0.0;
+    if (e >= 0) {
+#pragma unroll
+      for (int k = 0; k < kPre; ++k)
+        if (qi + 4 * k <= j) acc += h[qi + 4 * k] * vr[k];
+      for (int i = qi + 4 * kPre; i <= j; i += 4) acc += h[i] * V[(int64_t)i * ldv + e];
+    }
+    acc += __shfl_xor(acc, 1, 8);
+    acc += __shfl_xor(acc, 2, 8);
+    double v = 0.0;
+    if (e >= 0) {
+      v = nn > 0.0 ? (we - acc) / sqrt(nn) : 0.0;
+      if (qi == 0) w[e] = v;
+    }
+    const double vo = __shfl_xor(v, 4, 8);
+    const double vphi = sub < 4 ? v : vo, vpsi = sub < 4 ? vo : v;
+    if (on) {
       const double sg = cpsi >= 0 ? ns.m.dens_scale[p] * vpsi : 0.0;
       const double mv = cphi >= 0 ? -vphi : 0.0;
-      ns.sig[p] = sg;
-      ns.mu[p] = mv;
+      if (sub == 0) {
+        ns.sig[p] = sg;
+        ns.mu[p] = mv;
+      }
       T* src = reinterpret_cast<T*>(ns.src);
-      for (int k = 0; k < ns.K; ++k) {
+      for (int k = sub; k < ns.K; k += 8) {
         const int64_t jj = p * ns.K + k;
         const double wa = ns.wa[jj];
         const double mm = wa * mv;
@@ -192,13 +231,14 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
   if (blockIdx.x != 0) return;
   if (threadIdx.x == 0) {
     const double hn = sqrt(nn);
-    col[j + 1] = hn;
+    // previous rotations: only the carried entry is sequential
+    double a = col[0];
     for (int i = 0; i < j; ++i) {
-      const double a = col[i], b = col[i + 1];
-      col[i] = c[i] * a + sv[i] * b;
-      col[i + 1] = -sv[i] * a + c[i] * b;
+      const double b = col[i + 1], ci = c[i], si = sv[i];
+      col[i] = ci * a + si * b;
+      a = -si * a + ci * b;
     }
-    const double a = col[j], b = col[j + 1];
+    const double b = hn;
     const double den = hypot(a, b);
     const double cj = den > 0 ? a / den : 1.0, sj = den > 0 ? b / den : 0.0;
     csg[j] = cj;
@@ -282,7 +322,7 @@ void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m,
     k_arnoldi_update<double, false><<<grid, kBS, lds, s>>>(gu, j, m, R, nbj, part, h1, V, ldv, w, H, cs, sn, gv,
                                                            resid, NextSrc{});
   } else {
-    const dim3 grid(ns->pmax > 0 ? nblocks(ns->pmax, kBS) : 1u, G);
+    const dim3 grid(ns->pmax > 0 ? nblocks(8 * ns->pmax, kBS) : 1u, G);
     if (ns->fp32)
       k_arnoldi_update<float, true><<<grid, kBS, lds, s>>>(gu, j, m, R, nbj, part, h1, V, ldv, w, H, cs, sn, gv,
                                                            resid, *ns);

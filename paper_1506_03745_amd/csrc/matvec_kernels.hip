@@ -99,20 +99,6 @@ __global__ void k_strengths_x(int64_t ns, int K, PanelMaps m, const double* __re
   o[7] = (T)(rlap[p] * sv);
 }
 
-#include "near_field.h"
-
-// One wavefront per pair of P2P tasks (four per block).
-template <typename T, bool GUARD>
-__global__ __launch_bounds__(256) void k_p2p(const Task* __restrict__ tasks, int npairs,
-                                             const int32_t* __restrict__ ranges,
-                                             const T* __restrict__ tgt, const T* __restrict__ src,
-                                             T kappa, T* __restrict__ partial) {
-  __shared__ SrcRec<T> tiles[4][64];
-  const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
-  if (wv >= npairs) return;
-  p2p_task_pair<T, GUARD>(tasks + 2 * wv, tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, partial);
-}
-
 // Sum the partial slots of every target, scale by 1/(4 pi), add the near and
 // self corrections (sparse, FP64) and the 1/2 jump terms, and scatter into
 // the unknown layout.  One block per target chunk: lane = target within the
@@ -265,18 +251,6 @@ void launch_strengths_x(int64_t ns, int K, const PanelMaps& m, const double* x, 
 }
 
 template <typename T>
-void launch_p2p(const Task* tasks, int npairs, const int32_t* ranges, const T* tgt, const T* src,
-                T kappa, bool guard, T* partial, hipStream_t s) {
-  if (npairs <= 0) return;
-  const int blocks = ((npairs + 3) / 4 + 7) / 8 * 8;
-  if (guard)
-    k_p2p<T, true><<<blocks, 256, 0, s>>>(tasks, npairs, ranges, tgt, src, kappa, partial);
-  else
-    k_p2p<T, false><<<blocks, 256, 0, s>>>(tasks, npairs, ranges, tgt, src, kappa, partial);
-  PBT_HIP(hipGetLastError());
-}
-
-template <typename T>
 void launch_combine(const CombineArgs& a, const T* partial, const T* ppartial, double* y, hipStream_t s) {
   if (a.np <= 0 || a.nchunks <= 0) return;
   k_combine<T><<<a.nchunks, 64 * kCombineWaves, 0, s>>>(a, partial, ppartial, y);
@@ -291,10 +265,6 @@ template void launch_strengths_x<float>(int64_t, int, const PanelMaps&, const do
                                         const double*, const double*, double*, double*, float*, hipStream_t);
 template void launch_strengths_x<double>(int64_t, int, const PanelMaps&, const double*, const double*,
                                          const double*, const double*, double*, double*, double*, hipStream_t);
-template void launch_p2p<float>(const Task*, int, const int32_t*, const float*, const float*, float,
-                                bool, float*, hipStream_t);
-template void launch_p2p<double>(const Task*, int, const int32_t*, const double*, const double*,
-                                 double, bool, double*, hipStream_t);
 template void launch_combine<float>(const CombineArgs&, const float*, const float*, double*, hipStream_t);
 template void launch_combine<double>(const CombineArgs&, const double*, const double*, double*, hipStream_t);
 

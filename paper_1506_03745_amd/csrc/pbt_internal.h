@@ -158,9 +158,15 @@ struct MomChunk {
   int32_t box, sbeg, send;
   int32_t slot0, nparts, idx;
 };
-constexpr int kMomChunk = 4096;  // sources per chunk (16 a thread)
+constexpr int kMomChunk = 1024;  // sources per chunk (4 a thread)
 constexpr int kMomGroup = 12;    // coefficients per block
 constexpr int mom_groups(int P) { return (ncoef(P) + kMomGroup - 1) / kMomGroup; }
+// The same moments in one launch with the P2P task pairs (then the chunk sums).
+template <typename T>
+void launch_p2p_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
+                        const double* bcen, const double* brho, T* mom, T* mpart, const Task* p2p, int npairs,
+                        const int32_t* ranges, const T* src, const T* tgt, T kappa, bool guard, T* ppartial,
+                        hipStream_t s);
 template <typename T>
 void launch_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
                     const double* bcen, const double* brho, const T* src, T* mom, T* mpart, hipStream_t s);
@@ -231,10 +237,12 @@ void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int
 // (the strengths of launch_strengths_x, from the updated unknowns): panels
 // of group g are gp[2g] .. gp[2g+1] in the unknowns' (original) order,
 // pinv maps that order to internal panel indices, pmax is the largest
-// group's panel count; records are float (fp32) or double.
+// group's panel count, qcol gives the (phi, psi) unknowns of each position
+// (-1: none); records are float (fp32) or double.
 struct NextSrc {
   const int64_t* gp;
   const int32_t* pinv;
+  const int32_t* qcol;
   int64_t pmax;
   int fp32;
   PanelMaps m;

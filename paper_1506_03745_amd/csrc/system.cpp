@@ -121,9 +121,15 @@ void System::build(hipStream_t s) {
   });
   {
     // original panel order (the unknowns' order) -> internal index
-    std::vector<int32_t> pinv(np_);
-    for (int64_t g = 0; g < np_; ++g) pinv[poff_[psurf[g]] + h_panel_orig_[g]] = (int32_t)g;
+    std::vector<int32_t> pinv(np_), qcol(2 * np_);
+    for (int64_t g = 0; g < np_; ++g) {
+      const int64_t q = poff_[psurf[g]] + h_panel_orig_[g];
+      pinv[q] = (int32_t)g;
+      qcol[2 * q] = col_phi[g];
+      qcol[2 * q + 1] = col_psi[g];
+    }
     pinv_.upload(pinv, s);
+    qcol_.upload(qcol, s);
   }
   tri9_.upload(tri9, s);
   col_phi_.upload(col_phi, s);
@@ -611,6 +617,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   const bool far = !plan_.m2p.empty();
   const bool two = far && far_mode_ == 1;
   const bool fused = far && far_mode_ == 2;
+  const bool with_mom = far && far_mode_ == 3;
   if (timed || two) PBT_HIP(hipEventRecord(ev_[1], s));
   const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
   T* msum = f32 ? (T*)msum32_.p : (T*)msum64_.p;
@@ -639,6 +646,24 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
                       dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
+      PBT_HIP(hipEventRecord(ev_[4], s));
+    }
+    far_timed_ = timed;
+    return;
+  }
+  if (with_mom) {
+    // moments inside the P2P launch (and its timing), then M2P
+    if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
+    launch_p2p_moments<T>(prm_.taylor_p, nmchunks_, mchunks_.p, nmheads_, mheads_.p, bcen_.p, brho_.p, mom, msum,
+                          dp2p_.p, npairs, dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    if (timed) {
+      PBT_HIP(hipEventRecord(ev_[3], s));
+      PBT_HIP(hipEventRecord(evm_[0], s));
+      PBT_HIP(hipEventRecord(evm_[1], s));
+    }
+    launch_m2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, s);
+    if (timed) {
+      PBT_HIP(hipEventRecord(evm_[2], s));
       PBT_HIP(hipEventRecord(ev_[4], s));
     }
     far_timed_ = timed;
@@ -888,7 +913,7 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   // the update that produced it (step k > 0); the transposed operator starts
   // from targets instead and does not use them.
   const bool fuse = !transpose_;
-  const NextSrc nsrc{dgp_.p, pinv_.p, gpmax_, fp32 ? 1 : 0,
+  const NextSrc nsrc{dgp_.p, pinv_.p, qcol_.p, gpmax_, fp32 ? 1 : 0,
                      PanelMaps{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p},
                      K_, src_wa_.p, nrm_.p, rlap_.p, sig_.p, mu_.p,
                      fp32 ? (void*)src32_.p : (void*)src64_.p};

@@ -248,6 +248,7 @@ class System {
   DBuf<double> surf_rhoinv_;
   std::vector<int32_t> h_panel_orig_;  // internal global -> original index within its surface
   DBuf<int32_t> pinv_;                 // poff + original index -> internal global index
+  DBuf<int32_t> qcol_;                 // the same position -> (phi, psi) unknown indices
 
   // tree (global box numbering)
   int nbox_ = 0;

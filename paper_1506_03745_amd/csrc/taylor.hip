@@ -82,10 +82,9 @@ template <typename T, int P, int K0, int K1>
 __device__ __forceinline__ void moments_group(const MomChunk& ch, const double* __restrict__ bcen,
                                               const double* __restrict__ brho, const T* __restrict__ src,
                                               T* __restrict__ mom, T* __restrict__ mpart,
-                                              T* red /* [kMomThreads][2 (K1-K0) + 1] */) {
+                                              T* red /* [kMomThreads][9] */) {
   constexpr int NC = ncoef(P);
   constexpr int NG = K1 - K0;
-  constexpr int W = 2 * NG + 1;
   const int b = ch.box;
   const T cx = (T)bcen[3 * b], cy = (T)bcen[3 * b + 1], cz = (T)bcen[3 * b + 2];
   const T ri = (T)brho[b];
@@ -123,24 +122,31 @@ __device__ __forceinline__ void moments_group(const MomChunk& ch, const double* 
       acc[2 * (k - K0) + 1] += sl * hk - d;
     }
   }
+  // the block's sums, 8 columns (coefficient K0 + q/2, row q%2) a pass
+  // through LDS: 32 lanes a column, each over 8 rows, then a fixed xor
+  // butterfly over the 32
+  const int col = threadIdx.x >> 5, part = threadIdx.x & 31;
 #pragma unroll
-  for (int q = 0; q < 2 * NG; ++q) red[threadIdx.x * W + q] = acc[q];
-  __syncthreads();
-  // column q (coefficient K0 + q/2, row q%2) over the 256 threads: 8 lanes a
-  // column, each over 32 rows, then a fixed xor butterfly over the 8
-  const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
-  T v = 0;
-  if (q < 2 * NG) {
-#pragma unroll 8
-    for (int i = 0; i < kMomThreads / 8; ++i) v += red[(part + 8 * i) * W + q];
-  }
-  v += __shfl_xor(v, 4, 8);
-  v += __shfl_xor(v, 2, 8);
-  v += __shfl_xor(v, 1, 8);
-  if (q < 2 * NG && part == 0) {
-    const int k = K0 + (q >> 1), row = q & 1;
-    if (ch.nparts == 1) mom[(int64_t)(2 * b + row) * NC + k] = v;
-    else mpart[((int64_t)(ch.slot0 + ch.idx) * NC + k) * 2 + row] = v;
+  for (int q0 = 0; q0 < 2 * NG; q0 += 8) {
+    if (q0) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q0 + q < 2 * NG) red[threadIdx.x * 9 + q] = acc[q0 + q];
+    __syncthreads();
+    T v = 0;
+#pragma unroll
+    for (int i = 0; i < kMomThreads / 32; ++i) v += red[(part + 32 * i) * 9 + col];
+    v += __shfl_xor(v, 16, 32);
+    v += __shfl_xor(v, 8, 32);
+    v += __shfl_xor(v, 4, 32);
+    v += __shfl_xor(v, 2, 32);
+    v += __shfl_xor(v, 1, 32);
+    const int q = q0 + col;
+    if (q < 2 * NG && part == 0) {
+      const int k = K0 + (q >> 1), row = q & 1;
+      if (ch.nparts == 1) mom[(int64_t)(2 * b + row) * NC + k] = v;
+      else mpart[((int64_t)(ch.slot0 + ch.idx) * NC + k) * 2 + row] = v;
+    }
   }
 }
 
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(const MomChunk* __restr
                                                          const double* __restrict__ brho,
                                                          const T* __restrict__ src, T* __restrict__ mom,
                                                          T* __restrict__ mpart) {
-  __shared__ T red[kMomThreads * (2 * kMomGroup + 1)];
+  __shared__ T red[kMomThreads * 9];
   const MomChunk ch = chunks[blockIdx.x];
   moments_dispatch<T, P, 0>(ch, (int)blockIdx.y, bcen, brho, src, mom, mpart, red);
 }
@@ -319,6 +325,36 @@ __global__ __launch_bounds__(256) void k_m2p_p2p(const Task* __restrict__ m2p, i
     p2p_task_pair<T, GUARD>(p2p + 2 * (wv - nm2p), tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, ppartial);
 }
 
+// Moments blocks and P2P task pairs in one launch (moments first, so the
+// short moment blocks start at once and P2P fills the machine around them):
+// nmb = nchunks x mom_groups(P) moment blocks, then the P2P blocks, whose
+// logical order is made XCD-aware on their own range (nmb is a multiple of 8).
+template <typename T, int P, bool GUARD>
+__global__ __launch_bounds__(256) void k_p2p_mom(int nmreal, int nmb, const MomChunk* __restrict__ chunks,
+                                                 const double* __restrict__ bcen,
+                                                 const double* __restrict__ brho, T* __restrict__ mom,
+                                                 T* __restrict__ mpart, const Task* __restrict__ p2p, int npairs,
+                                                 const int32_t* __restrict__ ranges, const T* __restrict__ src,
+                                                 const T* __restrict__ tgt, T kappa, T* __restrict__ ppartial) {
+  constexpr int kTile = 4 * 64 * (int)sizeof(SrcRec<T>);
+  constexpr int kRed = kMomThreads * 9 * (int)sizeof(T);
+  __shared__ __align__(16) unsigned char lds[kTile > kRed ? kTile : kRed];
+  if ((int)blockIdx.x < nmb) {
+    if ((int)blockIdx.x >= nmreal) return;
+    constexpr int ng = mom_groups(P);
+    const int c = (int)blockIdx.x / ng;
+    const MomChunk ch = chunks[c];
+    moments_dispatch<T, P, 0>(ch, (int)blockIdx.x - c * ng, bcen, brho, src, mom, mpart,
+                              reinterpret_cast<T*>(lds));
+    return;
+  }
+  const int l = (int)blockIdx.x - nmb, per = ((int)gridDim.x - nmb) >> 3;
+  const int wv = __builtin_amdgcn_readfirstlane(((l & 7) * per + (l >> 3)) * 4 + (int)(threadIdx.x >> 6));
+  if (wv >= npairs) return;
+  SrcRec<T>* tiles = reinterpret_cast<SrcRec<T>*>(lds);
+  p2p_task_pair<T, GUARD>(p2p + 2 * wv, tiles + 64 * (threadIdx.x >> 6), ranges, tgt, src, kappa, ppartial);
+}
+
 }  // namespace
 
 template <typename T, int P>
@@ -334,6 +370,44 @@ void launch_moments(int P, int nchunks, const MomChunk* chunks, int nheads, cons
   switch (P) {
 #define PBT_CASE(PP) \
   case PP: moments_p<T, PP>(nchunks, chunks, bcen, brho, src, mom, mpart, s); break;
+    PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
+#undef PBT_CASE
+    default: throw Error(1, "Taylor order P must be 0..8");
+  }
+  PBT_HIP(hipGetLastError());
+  if (nheads > 0) {
+    k_moments_sum<T><<<nheads, 256, 0, s>>>(heads, ncoef(P), mpart, mom);
+    PBT_HIP(hipGetLastError());
+  }
+}
+
+template <typename T, int P>
+static void p2p_mom_p(int nchunks, const MomChunk* chunks, const double* bcen, const double* brho, T* mom,
+                      T* mpart, const Task* p2p, int npairs, const int32_t* ranges, const T* src, const T* tgt,
+                      T kappa, bool guard, T* ppartial, hipStream_t s) {
+  const int nmreal = nchunks * mom_groups(P);
+  const int nmb = (nmreal + 7) / 8 * 8;
+  const int blocks = nmb + ((npairs + 3) / 4 + 7) / 8 * 8;
+  if (guard)
+    k_p2p_mom<T, P, true><<<blocks, 256, 0, s>>>(nmreal, nmb, chunks, bcen, brho, mom, mpart, p2p, npairs, ranges, src, tgt,
+                                                 kappa, ppartial);
+  else
+    k_p2p_mom<T, P, false><<<blocks, 256, 0, s>>>(nmreal, nmb, chunks, bcen, brho, mom, mpart, p2p, npairs, ranges, src,
+                                                  tgt, kappa, ppartial);
+}
+
+template <typename T>
+void launch_p2p_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
+                        const double* bcen, const double* brho, T* mom, T* mpart, const Task* p2p, int npairs,
+                        const int32_t* ranges, const T* src, const T* tgt, T kappa, bool guard, T* ppartial,
+                        hipStream_t s) {
+  if (nchunks + npairs <= 0) return;
+  switch (P) {
+#define PBT_CASE(PP)                                                                                             \
+  case PP:                                                                                                       \
+    p2p_mom_p<T, PP>(nchunks, chunks, bcen, brho, mom, mpart, p2p, npairs, ranges, src, tgt, kappa, guard, ppartial, \
+                     s);                                                                                         \
+    break;
     PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
 #undef PBT_CASE
     default: throw Error(1, "Taylor order P must be 0..8");
@@ -402,6 +476,12 @@ void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, cons
   PBT_HIP(hipGetLastError());
 }
 
+template void launch_p2p_moments<float>(int, int, const MomChunk*, int, const MomChunk*, const double*,
+                                        const double*, float*, float*, const Task*, int, const int32_t*, const float*,
+                                        const float*, float, bool, float*, hipStream_t);
+template void launch_p2p_moments<double>(int, int, const MomChunk*, int, const MomChunk*, const double*,
+                                         const double*, double*, double*, const Task*, int, const int32_t*,
+                                         const double*, const double*, double, bool, double*, hipStream_t);
 template void launch_moments<float>(int, int, const MomChunk*, int, const MomChunk*, const double*, const double*,
                                     const float*, float*, float*, hipStream_t);
 template void launch_moments<double>(int, int, const MomChunk*, int, const MomChunk*, const double*, const double*,

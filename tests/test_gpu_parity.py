@@ -89,18 +89,26 @@ def test_operator_is_deterministic():
 
 
 def test_far_field_schedules_agree_bitwise():
-    """Serial, two-stream and joint-launch schedules compute every partial sum
-    with the same code and order: the products are bitwise equal."""
-    s, _ = from_problem(case("sphere_plate"), treecode=1, ncrit=24, theta=0.5, taylor_p=4)
-    x = rand_x(s.num_unknowns(), 11)
-    for prec in (FP64, MIXED):
-        ys = []
-        for mode in (0, 1, 2):
-            s.set_schedule(mode)
-            ys.append(s.matvec(x, prec=prec))
-        assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
-    with pytest.raises(PbtError):
-        s.set_schedule(3)
+    """Serial, two-stream, joint M2P + P2P and P2P-with-moments schedules
+    compute every partial sum with the same code and order: the products are
+    bitwise equal.  The two-sphere system has boxes of more than one moments
+    chunk (the chunk sums are exercised)."""
+    from workloads.problems import config_problem
+    systems = [from_problem(case("sphere_plate"), treecode=1, ncrit=24, theta=0.5, taylor_p=4)[0],
+               from_problem(config_problem("twosphere_charge"), treecode=1, ncrit=300, theta=0.5, taylor_p=6)[0]]
+    for s in systems:
+        x = rand_x(s.num_unknowns(), 11)
+        for prec in (FP64, MIXED):
+            ys = []
+            for mode in (0, 1, 2, 3):
+                s.set_schedule(mode)
+                assert s.schedule() == mode
+                ys.append(s.matvec(x, prec=prec))
+            for y in ys[1:]:
+                assert np.array_equal(ys[0], y)
+        with pytest.raises(PbtError):
+            s.set_schedule(4)
+        s.close()
 
 
 def test_treecode_small_theta_is_direct():
