@@ -173,9 +173,10 @@ pbt_status pbt_interaction_energy(pbt_ctx* ctx, double* F_int, pbt_result* parts
 pbt_status pbt_matvec(pbt_ctx* ctx, const double* x, double* y, int32_t transpose,
                       pbt_precision prec);
 
-/* Device variant: x_dev, y_dev are device pointers of n doubles; the work is
- * queued on `stream` (a hipStream_t, NULL for the default stream) and the call
- * returns without synchronising. */
+/* Device variant: x_dev, y_dev are device pointers of n doubles (same
+ * layout); the work is queued on `stream` (a hipStream_t, NULL for the
+ * context's own stream) and the call returns without synchronising.  It uses
+ * the context's work buffers, so calls on one context must not overlap. */
 pbt_status pbt_matvec_dev(pbt_ctx* ctx, const double* x_dev, double* y_dev, int32_t transpose,
                           pbt_precision prec, void* stream);
 

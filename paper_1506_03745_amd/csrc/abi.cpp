@@ -37,7 +37,7 @@ struct pbt_ctx {
   std::vector<bool> sol_mask;
   std::vector<double> sol_x;   // host copy of dsol, made when first asked for
   bool sol_on_host = false;
-  DBuf<double> dx, dy, db, dsol;
+  DBuf<double> dx, dy, db, dsol, dt;   // dt: a vector in the boundary's layout
 };
 
 namespace {
@@ -153,7 +153,11 @@ pbt_status solve_impl(pbt_ctx* c, const double* x0, pbt_result* res) {
   c->db.alloc(n);
   c->dx.alloc(n);
   S.rhs(c->db.p, c->stream);
-  if (x0) PBT_HIP(hipMemcpyAsync(c->dx.p, x0, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (x0) {
+    c->dt.alloc(n);
+    PBT_HIP(hipMemcpyAsync(c->dt.p, x0, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    S.to_internal(c->dt.p, c->dx.p, c->stream);
+  }
   PBT_HIP(hipStreamSynchronize(c->stream));
   const double t1 = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
   const bool ok = S.solve(c->db.p, c->dx.p, x0 != nullptr, &r, c->stream);
@@ -413,8 +417,13 @@ pbt_status pbt_matvec_dev(pbt_ctx* c, const double* x_dev, double* y_dev, int32_
     if (!x_dev || !y_dev) return fail(c, PBT_E_INVALID, "null buffer");
     System& S = system_for(c);
     hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-    if (transpose) S.matvec_t(x_dev, y_dev, prec == PBT_MIXED, nullptr, st);
-    else S.matvec(x_dev, y_dev, prec == PBT_MIXED, st, true);
+    const int64_t n = S.n();
+    c->dx.alloc(n);
+    c->dy.alloc(n);
+    S.to_internal(x_dev, c->dx.p, st);
+    if (transpose) S.matvec_t(c->dx.p, c->dy.p, prec == PBT_MIXED, nullptr, st);
+    else S.matvec(c->dx.p, c->dy.p, prec == PBT_MIXED, st, true);
+    S.to_boundary(c->dy.p, y_dev, st);
     return PBT_OK;
   });
 }
@@ -426,10 +435,13 @@ pbt_status pbt_matvec(pbt_ctx* c, const double* x, double* y, int32_t transpose,
     const int64_t n = S.n();
     c->dx.alloc(n);
     c->dy.alloc(n);
-    PBT_HIP(hipMemcpyAsync(c->dx.p, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    c->dt.alloc(n);
+    PBT_HIP(hipMemcpyAsync(c->dt.p, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    S.to_internal(c->dt.p, c->dx.p, c->stream);
     if (transpose) S.matvec_t(c->dx.p, c->dy.p, prec == PBT_MIXED, nullptr, c->stream);
     else S.matvec(c->dx.p, c->dy.p, prec == PBT_MIXED, c->stream, true);
-    PBT_HIP(hipMemcpyAsync(y, c->dy.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    S.to_boundary(c->dy.p, c->dt.p, c->stream);
+    PBT_HIP(hipMemcpyAsync(y, c->dt.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     PBT_HIP(hipStreamSynchronize(c->stream));
     return PBT_OK;
   });
@@ -440,8 +452,11 @@ pbt_status pbt_rhs(pbt_ctx* c, double* b) {
     if (!b) return fail(c, PBT_E_INVALID, "null buffer");
     System& S = system_for(c);
     c->db.alloc(S.n());
+    c->dt.alloc(S.n());
     S.rhs(c->db.p, c->stream);
-    PBT_HIP(hipMemcpy(b, c->db.p, S.n() * sizeof(double), hipMemcpyDeviceToHost));
+    S.to_boundary(c->db.p, c->dt.p, c->stream);
+    PBT_HIP(hipMemcpyAsync(b, c->dt.p, S.n() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PBT_HIP(hipStreamSynchronize(c->stream));
     return PBT_OK;
   });
 }

@@ -133,14 +133,12 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
   // basis entries are loaded before the partials are added up, so the memory
   // round trips overlap
   const int sub = threadIdx.x & 7, qi = sub & 3;
-  const int64_t q = SRC ? ns.gp[2 * g] + (blockIdx.x * (int64_t)kBS + threadIdx.x) / 8 : 0;
-  const bool on = SRC && q < ns.gp[2 * g + 1];
-  int64_t p = 0;
+  const int64_t p = SRC ? ns.gp[2 * g] + (blockIdx.x * (int64_t)kBS + threadIdx.x) / 8 : 0;
+  const bool on = SRC && p < ns.gp[2 * g + 1];
   int32_t cphi = -1, cpsi = -1;
   if (on) {
-    cphi = ns.qcol[2 * q];
-    cpsi = ns.qcol[2 * q + 1];
-    p = ns.pinv[q];
+    cphi = ns.m.col_phi[p];
+    cpsi = ns.m.col_psi[p];
   }
   const int32_t e = sub < 4 ? cphi : cpsi;
   constexpr int kPre = 8;
@@ -184,8 +182,8 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     const int64_t e = u0 + blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (e < u1) update(e);
   } else {
-    // eight lanes per panel of the group, panels in the unknowns' (original)
-    // order so that the V and w accesses are coalesced: lanes 0-3 form the
+    // eight lanes per panel of the group (the unknowns follow the panels'
+    // order, so the V and w accesses are coalesced): lanes 0-3 form the
     // phi unknown, lanes 4-7 the psi unknown, each lane over every fourth
     // basis vector, added by a fixed butterfly; then the panel's densities
     // and source records for the next product, as the strengths kernel
@@ -289,6 +287,14 @@ __global__ void k_start_cycle(const int64_t* __restrict__ gu, int m, const doubl
   v0[e] = r[e] * inv_beta[g];
 }
 
+__global__ void k_permute(int64_t n, const int32_t* __restrict__ u2i, const double* __restrict__ in, double* out,
+                          int to_internal) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  if (to_internal) out[u2i[k]] = in[k];
+  else out[k] = in[u2i[k]];
+}
+
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* y) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) y[i] = a * x[i] + b * y[i];
@@ -351,6 +357,13 @@ void launch_start_cycle(const int64_t* gu, int G, int64_t nmax, int m, const dou
   if (G <= 0) return;
   const unsigned nb = std::max(1u, nblocks(nmax, 256));
   k_start_cycle<<<dim3(nb, G), 256, 0, s>>>(gu, m, beta, inv_beta, r, v0, gv);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_permute(int64_t n, const int32_t* u2i, const double* in, double* out, bool to_internal,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  k_permute<<<nblocks(n, 256), 256, 0, s>>>(n, u2i, in, out, to_internal ? 1 : 0);
   PBT_HIP(hipGetLastError());
 }
 

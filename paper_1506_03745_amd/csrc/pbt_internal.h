@@ -235,14 +235,10 @@ void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int
                     const double* hpart, double* hout, int self_dot, double* part, int nbj, hipStream_t s);
 // Source records of the next Krylov vector, written by the Arnoldi update
 // (the strengths of launch_strengths_x, from the updated unknowns): panels
-// of group g are gp[2g] .. gp[2g+1] in the unknowns' (original) order,
-// pinv maps that order to internal panel indices, pmax is the largest
-// group's panel count, qcol gives the (phi, psi) unknowns of each position
-// (-1: none); records are float (fp32) or double.
+// of group g are gp[2g] .. gp[2g+1], pmax is the largest group's panel
+// count; records are float (fp32) or double.
 struct NextSrc {
   const int64_t* gp;
-  const int32_t* pinv;
-  const int32_t* qcol;
   int64_t pmax;
   int fp32;
   PanelMaps m;
@@ -259,6 +255,9 @@ void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m,
                            double* H, double* cs, double* sn, double* gv, double* resid, const NextSrc* ns,
                            hipStream_t s);
 void launch_group_row0(int G, int R, int nbj, const double* part, double* out, hipStream_t s);
+// out[u2i[k]] = in[k] (to_internal) or out[k] = in[u2i[k]] (otherwise), k < n.
+void launch_permute(int64_t n, const int32_t* u2i, const double* in, double* out, bool to_internal,
+                    hipStream_t s);
 void launch_lincomb(const int64_t* gu, int G, int64_t nmax, int m, int ystride, const double* V, int64_t ldv,
                     const double* y, double* x, hipStream_t s);
 void launch_start_cycle(const int64_t* gu, int G, int64_t nmax, int m, const double* beta, const double* inv_beta,

@@ -97,39 +97,42 @@ void System::build(hipStream_t s) {
       psurf[g] = e;
       switch (S.kind) {
         case PBT_MOLECULE:
-          col_phi[g] = (int32_t)(col_off_[e] + o);
-          col_psi[g] = (int32_t)(col_off_[e] + S.nt + o);
-          row_int[g] = (int32_t)(row_off_[e] + o);
-          row_sol[g] = (int32_t)(row_off_[e] + S.nt + o);
+          col_phi[g] = (int32_t)(col_off_[e] + li);
+          col_psi[g] = (int32_t)(col_off_[e] + S.nt + li);
+          row_int[g] = (int32_t)(row_off_[e] + li);
+          row_sol[g] = (int32_t)(row_off_[e] + S.nt + li);
           dscale[g] = S.eps_in / eps_out_;
           break;
         case PBT_CHARGED:
-          col_phi[g] = (int32_t)(col_off_[e] + o);
+          col_phi[g] = (int32_t)(col_off_[e] + li);
           col_psi[g] = -1;
           row_int[g] = -1;
-          row_sol[g] = (int32_t)(row_off_[e] + o);
+          row_sol[g] = (int32_t)(row_off_[e] + li);
           dscale[g] = 1.0;
           break;
         default:
           col_phi[g] = -1;
-          col_psi[g] = (int32_t)(col_off_[e] + o);
+          col_psi[g] = (int32_t)(col_off_[e] + li);
           row_int[g] = -1;
-          row_sol[g] = (int32_t)(row_off_[e] + o);
+          row_sol[g] = (int32_t)(row_off_[e] + li);
           dscale[g] = 1.0;
       }
     }
   });
   {
-    // original panel order (the unknowns' order) -> internal index
-    std::vector<int32_t> pinv(np_), qcol(2 * np_);
+    // The unknowns (and rows) of a surface follow its panels' internal order;
+    // the boundary's layout follows the original order: u2i maps a boundary
+    // index to the internal one.
+    std::vector<int32_t> u2i(n_);
+    h_pinv_.assign(np_, 0);
     for (int64_t g = 0; g < np_; ++g) {
-      const int64_t q = poff_[psurf[g]] + h_panel_orig_[g];
-      pinv[q] = (int32_t)g;
-      qcol[2 * q] = col_phi[g];
-      qcol[2 * q + 1] = col_psi[g];
+      const int e = psurf[g];
+      const int64_t li = g - poff_[e], o = h_panel_orig_[g], nt = surfs_[e]->nt;
+      h_pinv_[poff_[e] + o] = (int32_t)g;
+      u2i[col_off_[e] + o] = (int32_t)(col_off_[e] + li);
+      if (col_off_[e + 1] - col_off_[e] == 2 * nt) u2i[col_off_[e] + nt + o] = (int32_t)(col_off_[e] + nt + li);
     }
-    pinv_.upload(pinv, s);
-    qcol_.upload(qcol, s);
+    u2i_.upload(u2i, s);
   }
   tri9_.upload(tri9, s);
   col_phi_.upload(col_phi, s);
@@ -852,6 +855,14 @@ std::vector<double> System::group_norms(const double* v, hipStream_t s) {
   return r;
 }
 
+void System::to_internal(const double* xu, double* xi, hipStream_t s) const {
+  launch_permute(n_, u2i_.p, xu, xi, true, s);
+}
+
+void System::to_boundary(const double* xi, double* xu, hipStream_t s) const {
+  launch_permute(n_, u2i_.p, xi, xu, false, s);
+}
+
 void System::true_residual(const double* b, const double* x, double* r, hipStream_t s) {
   op(x, r, false, s);
   launch_axpby(n_, 1.0, b, -1.0, r, s);  // r = b - A x
@@ -913,7 +924,7 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   // the update that produced it (step k > 0); the transposed operator starts
   // from targets instead and does not use them.
   const bool fuse = !transpose_;
-  const NextSrc nsrc{dgp_.p, pinv_.p, qcol_.p, gpmax_, fp32 ? 1 : 0,
+  const NextSrc nsrc{dgp_.p, gpmax_, fp32 ? 1 : 0,
                      PanelMaps{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p},
                      K_, src_wa_.p, nrm_.p, rlap_.p, sig_.p, mu_.p,
                      fp32 ? (void*)src32_.p : (void*)src64_.p};
@@ -1153,10 +1164,10 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
         const double A = h_area_[g];
         if (S.kind == PBT_CHARGED) {
           // 1/2 sum phi_j sigma_j A_j (eq. energy_surf_disc, set charge)
-          f += 0.5 * xh[col_off_[e] + o] * (S.bc[o] * kSigmaSI) * A;
+          f += 0.5 * xh[col_off_[e] + li] * (S.bc[o] * kSigmaSI) * A;
         } else {
           // -1/2 sum phi0_j sigma_j A_j with sigma = -eps_out dphi/dn
-          f += 0.5 * eps_out_ * (S.bc[o] / kVoltPerUnit) * xh[col_off_[e] + o] * A;
+          f += 0.5 * eps_out_ * (S.bc[o] / kVoltPerUnit) * xh[col_off_[e] + li] * A;
         }
       }
       out[e][2] = f;
@@ -1194,19 +1205,20 @@ std::vector<pbt_result> System::energies_by_group(const double* x, int ngroups, 
 void System::unpack(const std::vector<double>& xh, int e, double* phi, double* dphidn) const {
   const SurfIn& S = *surfs_[e];
   for (int64_t o = 0; o < S.nt; ++o) {
+    const int64_t li = h_pinv_[poff_[e] + o] - poff_[e];   // unknowns follow the internal order
     double p = 0, d = 0;
     switch (S.kind) {
       case PBT_MOLECULE:
-        p = xh[col_off_[e] + o];
-        d = xh[col_off_[e] + S.nt + o];
+        p = xh[col_off_[e] + li];
+        d = xh[col_off_[e] + S.nt + li];
         break;
       case PBT_CHARGED:
-        p = xh[col_off_[e] + o];
+        p = xh[col_off_[e] + li];
         d = -S.bc[o] * kSigmaSI / eps_out_;
         break;
       default:
         p = S.bc[o] / kVoltPerUnit;
-        d = xh[col_off_[e] + o];
+        d = xh[col_off_[e] + li];
     }
     if (phi) phi[o] = p;
     if (dphidn) dphidn[o] = d;

@@ -126,6 +126,10 @@ class System {
 
   // y = A x on device buffers (n doubles each), FP64 or FP32 interactions;
   // `timed` records the per-phase events read by timing().
+  // Unknown vectors between the boundary's layout (panels of each surface in
+  // their original order) and the internal one (the octree's order).
+  void to_internal(const double* xu, double* xi, hipStream_t s) const;
+  void to_boundary(const double* xi, double* xu, hipStream_t s) const;
   // src_ready: the source records, sig and mu of x are already in place.
   void matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed = false, bool src_ready = false);
   // FP64 right-hand side for the current charges and boundary values.
@@ -247,8 +251,8 @@ class System {
   DBuf<int32_t> surf_mol_;
   DBuf<double> surf_rhoinv_;
   std::vector<int32_t> h_panel_orig_;  // internal global -> original index within its surface
-  DBuf<int32_t> pinv_;                 // poff + original index -> internal global index
-  DBuf<int32_t> qcol_;                 // the same position -> (phi, psi) unknown indices
+  std::vector<int32_t> h_pinv_;        // poff + original index -> internal global index
+  DBuf<int32_t> u2i_;                  // boundary (original-order) unknown index -> internal one
 
   // tree (global box numbering)
   int nbox_ = 0;

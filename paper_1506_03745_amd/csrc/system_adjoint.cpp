@@ -342,8 +342,8 @@ void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
     for (int64_t li = 0; li < S.nt; ++li) {
       const int64_t gi = poff_[e] + li;
       const int32_t o = h_panel_orig_[gi];
-      if (S.kind == PBT_CHARGED) hg[col_off_[e] + o] += S.bc[o] * kSigmaSI * h_area_[gi];
-      else hg[col_off_[e] + o] += eps_out_ * (S.bc[o] / kVoltPerUnit) * h_area_[gi];
+      if (S.kind == PBT_CHARGED) hg[col_off_[e] + li] += S.bc[o] * kSigmaSI * h_area_[gi];
+      else hg[col_off_[e] + li] += eps_out_ * (S.bc[o] / kVoltPerUnit) * h_area_[gi];
     }
   }
   PBT_HIP(hipMemcpyAsync(g, hg.data(), n_ * sizeof(double), hipMemcpyHostToDevice, s));
@@ -385,7 +385,7 @@ void System::gradient_terms(const double* x, const double* lam, std::vector<std:
       for (int64_t li = 0; li < S.nt; ++li) {
         const int64_t gi = poff_[e] + li;
         const int32_t o = h_panel_orig_[gi];
-        dsig[e][o] = 0.5 * (h_area_[gi] * xh[col_off_[e] + o] + hsb[gi] / eps_out_);
+        dsig[e][o] = 0.5 * (h_area_[gi] * xh[col_off_[e] + li] + hsb[gi] / eps_out_);
       }
     }
   }
