@@ -47,14 +47,14 @@ __device__ __forceinline__ void reduce_rows(const double* __restrict__ part, int
 // 8 consecutive outputs i0..i0+7 of V_0..V_{m-1} (and w.w as output m when
 // self_dot).  Partials of group g go to part + g * R * nbj (row stride nbj).
 // UPDATE: the block first adds up the partials of the previous pass (m rows
-// at hpart + g * R * nbj, fixed order, so every block of the group gets the
+// of nbh at hpart + g * R * nbh, fixed order, so every block of the group gets the
 // same h bitwise) and dots with w' = w - sum_i h_i V_i formed in registers
 // (w is not written); block (0, 0) of the group stores that h at hout + g * R.
 template <bool UPDATE>
 __global__ __launch_bounds__(kBS) void k_gs_dots(const int64_t* __restrict__ gu, int m, int R,
                                                  const double* __restrict__ V, int64_t ldv,
                                                  const double* __restrict__ w, const double* __restrict__ hpart,
-                                                 double* __restrict__ hout, int self_dot,
+                                                 int nbh, double* __restrict__ hout, int self_dot,
                                                  double* __restrict__ part) {
   extern __shared__ double hs[];   // [m] (UPDATE)
   __shared__ double red[kBS / 64][8];
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBS) void k_gs_dots(const int64_t* __restrict__ gu,
   const int64_t u0 = gu[2 * g], u1 = gu[2 * g + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (UPDATE) {
-    reduce_rows(hpart + (int64_t)g * R * nbj, m, nbj, hs);
+    reduce_rows(hpart + (int64_t)g * R * nbh, m, nbh, hs);
     __syncthreads();
     if (blockIdx.x == 0 && blockIdx.y == 0)
       for (int i = threadIdx.x; i < m; i += kBS) hout[(int64_t)g * R + i] = hs[i];
@@ -305,15 +305,16 @@ __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, doubl
 int gs_blocks(int64_t n) { return (int)std::min<int64_t>(240, std::max<int64_t>(1, (n + kBS - 1) / kBS)); }
 
 void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int64_t ldv, const double* w,
-                    const double* hpart, double* hout, int self_dot, double* part, int nbj, hipStream_t s) {
+                    const double* hpart, int nbh, double* hout, int self_dot, double* part, int nbj,
+                    hipStream_t s) {
   const int mq = m + (self_dot ? 1 : 0);
   if (G <= 0 || mq <= 0) return;
   const dim3 grid(nbj, (mq + 7) / 8, G);
   if (hpart)
-    k_gs_dots<true><<<grid, kBS, (size_t)m * sizeof(double), s>>>(gu, m, R, V, ldv, w, hpart, hout, self_dot,
-                                                                  part);
+    k_gs_dots<true><<<grid, kBS, (size_t)m * sizeof(double), s>>>(gu, m, R, V, ldv, w, hpart, nbh, hout,
+                                                                  self_dot, part);
   else
-    k_gs_dots<false><<<grid, kBS, 0, s>>>(gu, m, R, V, ldv, w, nullptr, nullptr, self_dot, part);
+    k_gs_dots<false><<<grid, kBS, 0, s>>>(gu, m, R, V, ldv, w, nullptr, 0, nullptr, self_dot, part);
   PBT_HIP(hipGetLastError());
 }
 

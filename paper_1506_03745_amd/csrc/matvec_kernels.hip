@@ -101,7 +101,8 @@ __global__ void k_strengths_x(int64_t ns, int K, PanelMaps m, const double* __re
 
 // Sum the partial slots of every target, scale by 1/(4 pi), add the near and
 // self corrections (sparse, FP64) and the 1/2 jump terms, and scatter into
-// the unknown layout.  One block per target chunk: lane = target within the
+// the unknown layout; optionally also the chunk's share of the first
+// Gram-Schmidt pass over the result (CombineArgs::ndots).  One block per target chunk: lane = target within the
 // chunk (coalesced slot reads), the kCombineWaves waves split the chunk's
 // slots and each target's near entries, and add up through LDS.
 constexpr int kCombineWaves = 16;
@@ -117,11 +118,13 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
   // their latency overlaps the sums instead of following them
   int32_t ri = -1, rs = 0;
   double xj = 0.0;
-  if (w == 0 && act) {
+  if (act) {
     ri = a.maps.row_int[i];
     rs = a.maps.row_sol[i];
-    const int32_t cphi = a.maps.col_phi[i];
-    if (a.add_jump && cphi >= 0) xj = 0.5 * a.x[cphi];
+    if (w == 0) {
+      const int32_t cphi = a.maps.col_phi[i];
+      if (a.add_jump && cphi >= 0) xj = 0.5 * a.x[cphi];
+    }
   }
   double l = 0.0, yy = 0.0, nl = 0.0, ny = 0.0;
   if (act) {
@@ -151,18 +154,39 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
   red[w][2][lane] = nl;
   red[w][3][lane] = ny;
   __syncthreads();
-  if (w != 0 || !act) return;
-  l = yy = nl = ny = 0.0;
-  for (int k = 0; k < kCombineWaves; ++k) {
-    l += red[k][0][lane];
-    yy += red[k][1][lane];
-    nl += red[k][2][lane];
-    ny += red[k][3][lane];
+  __shared__ double yv[2][64];
+  if (w == 0) {
+    double yi = 0.0, ys = 0.0;
+    if (act) {
+      l = yy = nl = ny = 0.0;
+      for (int k = 0; k < kCombineWaves; ++k) {
+        l += red[k][0][lane];
+        yy += red[k][1][lane];
+        nl += red[k][2][lane];
+        ny += red[k][3][lane];
+      }
+      yi = xj + (l * kInv4Pi + nl);
+      ys = xj + (yy * kInv4Pi + ny);
+      if (ri >= 0) y[ri] = yi;
+      else yi = 0.0;
+      y[rs] = ys;
+    }
+    yv[0][lane] = yi;
+    yv[1][lane] = ys;
   }
-  l = l * kInv4Pi + nl;
-  yy = yy * kInv4Pi + ny;
-  if (ri >= 0) y[ri] = xj + l;
-  y[rs] = xj + yy;
+  if (a.ndots <= 0) return;
+  // first Gram-Schmidt pass: this chunk's rows of V_i . y, a wave per i
+  __syncthreads();
+  for (int k = w; k < a.ndots; k += kCombineWaves) {
+    const double* Vk = a.V + (int64_t)k * a.ldv;
+    double pr = 0.0;
+    if (act) {
+      if (ri >= 0) pr = Vk[ri] * yv[0][lane];
+      pr += Vk[rs] * yv[1][lane];
+    }
+    for (int o = 32; o > 0; o >>= 1) pr += __shfl_down(pr, o, 64);
+    if (lane == 0) a.dpart[((int64_t)cs.grp * a.R + k) * a.nbh + cs.lchunk] = pr;
+  }
 }
 
 // Reaction potential at the charges of one molecule (eq. phi_reac_bem):

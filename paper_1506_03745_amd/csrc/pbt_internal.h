@@ -48,6 +48,7 @@ struct Task {
 struct ChunkSlots {
   int32_t tbeg, tcount, sbeg, send;
   int32_t hbeg0, hend0, hbeg1, hend1;
+  int32_t grp, lchunk;   // the targets' group and the chunk's index within it
 };
 
 // Units: lengths in A, charges in e, potentials in e/(eps0 A), energies in
@@ -136,6 +137,11 @@ struct CombineArgs {
   const double* x;               // unknowns (jump terms); may be null when add_jump = 0
   PanelMaps maps;
   int add_jump;
+  // When ndots > 0, also the first Gram-Schmidt pass of the product: the
+  // chunk's part of V_i . y for i < ndots goes to dpart[(grp R + i) nbh + lchunk].
+  int ndots;
+  const double* V; int64_t ldv;
+  double* dpart; int R; int nbh;
 };
 template <typename T>
 void launch_combine(const CombineArgs& a, const T* partial, const T* ppartial, double* y, hipStream_t s);
@@ -231,8 +237,10 @@ void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hip
 // Hessenberg column and Givens rotation.  R = rows reserved per group in
 // the partial and h buffers (restart + 1).
 int gs_blocks(int64_t n);
+// hpart rows have stride nbh (the previous pass's block count).
 void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int64_t ldv, const double* w,
-                    const double* hpart, double* hout, int self_dot, double* part, int nbj, hipStream_t s);
+                    const double* hpart, int nbh, double* hout, int self_dot, double* part, int nbj,
+                    hipStream_t s);
 // Source records of the next Krylov vector, written by the Arnoldi update
 // (the strengths of launch_strengths_x, from the updated unknowns): panels
 // of group g are gp[2g] .. gp[2g+1], pmax is the largest group's panel

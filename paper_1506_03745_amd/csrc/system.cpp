@@ -457,19 +457,23 @@ void System::build_plan() {
   seg_src_used_ = seg_src;
   seg_box_used_ = seg_box;
 
-  // Chunks.
+  // Chunks (numbered per group too, for the Gram-Schmidt partials).
   std::vector<int> leaf_chunk0(leaves.size());
   P.chunk_of.assign(np_, 0);
+  std::map<int, int32_t> gchunks;
   for (size_t li = 0; li < leaves.size(); ++li) {
     const TreeBox& tl = trees_[leaves[li].e].boxes[leaves[li].b];
     leaf_chunk0[li] = (int)P.chunks.size();
+    const int grp = surfs_[leaves[li].e]->group;
     const int64_t g0 = poff_[leaves[li].e] + tl.pbeg, g1 = poff_[leaves[li].e] + tl.pend;
     for (int64_t t = g0; t < g1; t += 64) {
-      ChunkSlots c{(int32_t)t, (int32_t)std::min<int64_t>(64, g1 - t), 0, 0};
+      ChunkSlots c{(int32_t)t, (int32_t)std::min<int64_t>(64, g1 - t), 0, 0, 0, 0, 0, 0, grp, gchunks[grp]++};
       for (int64_t k = t; k < t + c.tcount; ++k) P.chunk_of[k] = (int32_t)P.chunks.size();
       P.chunks.push_back(c);
     }
   }
+  P.nbh = 1;
+  for (const auto& kv : gchunks) P.nbh = std::max(P.nbh, (int)kv.second);
   // Segments per (leaf, source surface).
   struct Seg { int32_t lbeg, lend; int e2; bool m2p; };
   std::vector<std::vector<Seg>> segs(leaves.size());
@@ -688,7 +692,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
 }
 
 void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x,
-                   bool timed, bool src_ready) {
+                   bool timed, bool src_ready, const DotReq* dots) {
   ++napply_;
   if (timed) PBT_HIP(hipEventRecord(ev_[0], s));
   if (fp32) interactions<float>(s, from_x ? x : nullptr, timed, src_ready);
@@ -706,6 +710,14 @@ void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStre
   a.x = x;
   a.maps = PanelMaps{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
   a.add_jump = add_jump ? 1 : 0;
+  if (dots) {
+    a.ndots = dots->ndots;
+    a.V = dots->V;
+    a.ldv = dots->ldv;
+    a.dpart = dots->dpart;
+    a.R = dots->R;
+    a.nbh = plan_.nbh;
+  }
   if (fp32) launch_combine<float>(a, part32_.p, ppart32_.p, y, s);
   else launch_combine<double>(a, part64_.p, ppart64_.p, y, s);
   if (timed) PBT_HIP(hipEventRecord(ev_[5], s));
@@ -730,8 +742,9 @@ void System::timing(double out[5]) {
   out[4] = a + b;   // strengths + combine (P2P and the far field overlap)
 }
 
-void System::matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed, bool src_ready) {
-  apply(fp32, true, x, y, s, true, timed, src_ready);
+void System::matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed, bool src_ready,
+                    const DotReq* dots) {
+  apply(fp32, true, x, y, s, true, timed, src_ready, dots);
 }
 
 // Known densities of the charged (sigma) and potential (phi0) surfaces, in
@@ -844,7 +857,7 @@ void System::ensure_groups(hipStream_t s) {
 std::vector<double> System::group_norms(const double* v, hipStream_t s) {
   const int nbj = gs_blocks(gmax_);
   nrm_part_.alloc((size_t)G_ * nbj + G_);
-  launch_gs_dots(dgu_.p, G_, 0, 1, nullptr, n_, v, nullptr, nullptr, 1, nrm_part_.p, nbj, s);
+  launch_gs_dots(dgu_.p, G_, 0, 1, nullptr, n_, v, nullptr, 0, nullptr, 1, nrm_part_.p, nbj, s);
   double* out = nrm_part_.p + (size_t)G_ * nbj;
   launch_group_row0(G_, 1, nbj, nrm_part_.p, out, s);
   hnorm_.alloc(G_);
@@ -900,8 +913,8 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   double* dbeta = dres + (size_t)G * m;
   double* dy = dbeta + 2 * (size_t)G;
   double* h1 = hdev_.p;
-  double* part1 = part_.p;
-  double* part2 = part_.p + (size_t)G * R * nbj;
+  double* part1 = part_.p;                                            // [G][R][max(nbj, nbh)]
+  double* part2 = part_.p + (size_t)G * R * std::max(nbj, plan_.nbh);  // [G][R][nbj]
   int iters = 0;
   if (x_zero) PBT_HIP(hipMemcpyAsync(r_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
   else {
@@ -928,11 +941,19 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
                      PanelMaps{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p},
                      K_, src_wa_.p, nrm_.p, rlap_.p, sig_.p, mu_.p,
                      fp32 ? (void*)src32_.p : (void*)src64_.p};
+  // The forward operator also forms the first Gram-Schmidt pass as it writes
+  // its result (per-chunk partials, nbh per row).
+  const int nbh = fuse ? plan_.nbh : nbj;
   auto enqueue_step = [&](int k) {
     double* vj1 = V_.p + (size_t)(k + 1) * n_;
-    op(V_.p + (size_t)k * n_, vj1, fp32, s, fuse && k > 0);
-    launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, nullptr, 0, part1, nbj, s);
-    launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, h1, 1, part2, nbj, s);
+    if (fuse) {
+      const DotReq dr{k + 1, V_.p, n_, part1, R};
+      op(V_.p + (size_t)k * n_, vj1, fp32, s, k > 0, &dr);
+    } else {
+      op(V_.p + (size_t)k * n_, vj1, fp32, s);
+      launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, 0, nullptr, 0, part1, nbj, s);
+    }
+    launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, nbh, h1, 1, part2, nbj, s);
     launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, dres,
                           fuse ? &nsrc : nullptr, s);
   };
@@ -1057,7 +1078,9 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
   tmp_.alloc(n_);
   y_.alloc(n_);
   pdb_ = gs_blocks(gmax_);
-  part_.alloc(2 * (size_t)G * (m + 1) * pdb_);
+  part_.alloc((size_t)G * (m + 1) * (pdb_ + std::max(pdb_, plan_.nbh)));
+  // per-chunk partials of groups with fewer chunks than nbh stay zero
+  PBT_HIP(hipMemsetAsync(part_.p, 0, part_.n * sizeof(double), s));
   hdev_.alloc((size_t)G * (m + 1));
   gm_.alloc((size_t)G * ((size_t)(m + 1) * m + 4 * (size_t)m + 3));
   if (!x0_given) PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));

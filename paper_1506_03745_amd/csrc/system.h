@@ -103,6 +103,7 @@ struct Plan {
   std::vector<ChunkSlots> chunks;
   std::vector<int32_t> chunk_of;
   int nslots = 0;    // M2P partial slots (64 lanes)
+  int nbh = 1;       // most target chunks of one group
   int npslots = 0;   // P2P partial slots (32 lanes)
   int64_t p2p_pairs = 0, m2p_pairs = 0, p2p_fused_pairs = 0;
 };
@@ -130,8 +131,18 @@ class System {
   // their original order) and the internal one (the octree's order).
   void to_internal(const double* xu, double* xi, hipStream_t s) const;
   void to_boundary(const double* xi, double* xu, hipStream_t s) const;
-  // src_ready: the source records, sig and mu of x are already in place.
-  void matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed = false, bool src_ready = false);
+  // src_ready: the source records, sig and mu of x are already in place;
+  // dots: also the first Gram-Schmidt pass V_i . y, i < ndots, as per-chunk
+  // partials (dpart rows of plan().nbh, R rows per group).
+  struct DotReq {
+    int ndots;
+    const double* V;
+    int64_t ldv;
+    double* dpart;
+    int R;
+  };
+  void matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed = false, bool src_ready = false,
+              const DotReq* dots = nullptr);
   // FP64 right-hand side for the current charges and boundary values.
   void rhs(double* b_dev, hipStream_t s);
   // Solves A x = b (b, x device); returns result fields (iters, outer,
@@ -188,7 +199,7 @@ class System {
   void build(hipStream_t s);
   void build_plan();
   void apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x = false,
-             bool timed = false, bool src_ready = false);
+             bool timed = false, bool src_ready = false, const DotReq* dots = nullptr);
   template <typename T>
   void interactions(hipStream_t s, const double* x, bool timed, bool src_ready);
   int gmres(bool fp32, const double* b, double* x, bool x_zero, const std::vector<double>& tol_abs,
@@ -197,9 +208,10 @@ class System {
   void ensure_groups(hipStream_t s);
   std::vector<double> group_norms(const double* v, hipStream_t s);
   void true_residual(const double* b, const double* x, double* r, hipStream_t s);
-  void op(const double* x, double* y, bool fp32, hipStream_t s, bool src_ready = false) {
+  void op(const double* x, double* y, bool fp32, hipStream_t s, bool src_ready = false,
+          const DotReq* dots = nullptr) {
     if (transpose_) matvec_t(x, y, fp32, nullptr, s);
-    else matvec(x, y, fp32, s, false, src_ready);
+    else matvec(x, y, fp32, s, false, src_ready, dots);
   }
   bool solve_any(const double* b, double* x, bool x0_given, pbt_result* res, hipStream_t s);
   void build_tplan(hipStream_t s);
