@@ -88,34 +88,53 @@ __device__ __forceinline__ void p2p_pair(const SrcRec<T>& s, T tx, T ty, T tz, T
   yy += gy * (a * (rinv + kappa) + s.v[3]);        // s G_Y + D.grad_y G_Y
 }
 
-template <typename T, bool GUARD, bool FUSED>
-__device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int cnt, T tx, T ty, T tz, T kappa, T ck,
-                                         T& l, T& yy) {
-  int j = 0;
-  for (; j + 8 <= cnt; j += 8) {
+// The records j = grp, grp + F, ... of a 32-record tile (F lane groups per
+// half-wavefront share its targets).
+template <typename T, bool GUARD, bool FUSED, int F>
+__device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int grp, T tx, T ty, T tz, T kappa, T ck, T& l,
+                                         T& yy) {
+  if (F == 1) {
+    // the shape that keeps the fewest records in flight for the compiler:
+    // eight FP32 (two FP64) records per unrolled step
+    constexpr int UF = sizeof(T) == 4 ? 8 : 2;
+    int j = 0;
+    for (; j + UF <= 32; j += UF) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) p2p_pair<T, GUARD, FUSED>(load_rec(tile + j + q), tx, ty, tz, kappa, ck, l, yy);
+      for (int q = 0; q < UF; ++q) p2p_pair<T, GUARD, FUSED>(load_rec(tile + j + q), tx, ty, tz, kappa, ck, l, yy);
+    }
+    return;
   }
-  for (; j < cnt; ++j) p2p_pair<T, GUARD, FUSED>(load_rec(tile + j), tx, ty, tz, kappa, ck, l, yy);
+  constexpr int N = 32 / F;
+  constexpr int U0 = sizeof(T) == 4 ? 8 : 4;
+  constexpr int U = N < U0 ? N : U0;
+  const SrcRec<T>* t0 = tile + grp;
+  for (int q0 = 0; q0 < N; q0 += U) {
+#pragma unroll
+    for (int q = 0; q < U; ++q) p2p_pair<T, GUARD, FUSED>(load_rec(t0 + F * (q0 + q)), tx, ty, tz, kappa, ck, l, yy);
+  }
 }
 
 // A pair of P2P tasks on one wavefront: lanes 0..31 serve tasks[0], lanes
-// 32..63 tasks[1] (each up to 32 targets, one per lane, with its own source
-// ranges; both have the same `fused`).  Each round, each half stages its next
-// 32 source records into its half of the wave's LDS tile with one coalesced
-// load per lane, padding with zero-strength records far away (they add
-// exactly zero); every lane then reads its half's records in turn (an LDS
-// broadcast per half), so the loads pipeline in order.  Partials [slot][32][2].
-template <typename T, bool GUARD>
-__device__ __forceinline__ void p2p_task_pair(const Task* __restrict__ tp, SrcRec<T>* tile,
-                                              const int32_t* __restrict__ ranges, const T* __restrict__ tgt,
-                                              const T* __restrict__ src, T kappa, T* __restrict__ partial) {
+// 32..63 tasks[1] (each up to 32 targets with its own source ranges; both
+// have the same `fused` and the same split F).  Each round, each half stages
+// its next 32 source records into its half of the wave's LDS tile with one
+// coalesced load per lane, padding with zero-strength records far away (they
+// add exactly zero); the half's lanes form F groups of 32/F, each group
+// holding the half's targets (one per lane) and reading every F-th record of
+// the tile (LDS broadcasts), so a half with few targets keeps its lanes busy
+// and needs 1/F of the time per round.  The groups' sums are added by a
+// fixed butterfly.  Partials [slot][32][2].
+template <typename T, bool GUARD, bool FUSED, int F>
+__device__ __forceinline__ void p2p_task_pair_f(const Task* __restrict__ tp, SrcRec<T>* tile,
+                                                const int32_t* __restrict__ ranges, const T* __restrict__ tgt,
+                                                const T* __restrict__ src, T kappa, T* __restrict__ partial) {
+  constexpr int TW = 32 / F;   // targets per half
   const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  const int grp = hl / TW, tl = hl - grp * TW;
   const SrcRec<T>* srec = reinterpret_cast<const SrcRec<T>*>(src);
   const Task t = tp[half];
-  const int fused = tp[0].fused;
   const int rounds = (max(tp[0].nsrc, tp[1].nsrc) + 31) >> 5;
-  const int ti = t.tbeg + (hl < t.tcount ? hl : 0);
+  const int ti = t.tbeg + (tl < t.tcount ? tl : 0);
   const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
   const T ck = KMath<T>::expk_const(kappa);
   SrcRec<T> pad;
@@ -137,12 +156,35 @@ __device__ __forceinline__ void p2p_task_pair(const Task* __restrict__ tp, SrcRe
     }
     if (hl >= cnt) mine[hl] = pad;
     wave_lds_sync();
-    if (fused) p2p_tile<T, GUARD, true>(mine, 32, tx, ty, tz, kappa, ck, l, yy);
-    else p2p_tile<T, GUARD, false>(mine, 32, tx, ty, tz, kappa, ck, l, yy);
+    p2p_tile<T, GUARD, FUSED, F>(mine, grp, tx, ty, tz, kappa, ck, l, yy);
     wave_lds_sync();
   }
-  if (hl < t.tcount) {
-    partial[2 * ((int64_t)t.slot * 32 + hl) + 0] = l;
-    partial[2 * ((int64_t)t.slot * 32 + hl) + 1] = yy;
+  if (F >= 4) {
+    l += __shfl_xor(l, 8, 32);
+    yy += __shfl_xor(yy, 8, 32);
+  }
+  if (F >= 2) {
+    l += __shfl_xor(l, 16, 32);
+    yy += __shfl_xor(yy, 16, 32);
+  }
+  if (grp == 0 && tl < t.tcount) {
+    partial[2 * ((int64_t)t.slot * 32 + tl) + 0] = l;
+    partial[2 * ((int64_t)t.slot * 32 + tl) + 1] = yy;
+  }
+}
+
+template <typename T, bool GUARD>
+__device__ __forceinline__ void p2p_task_pair(const Task* __restrict__ tp, SrcRec<T>* tile,
+                                              const int32_t* __restrict__ ranges, const T* __restrict__ tgt,
+                                              const T* __restrict__ src, T kappa, T* __restrict__ partial) {
+  const int fused = tp[0].fused, split = tp[0].split;
+  if (fused) {
+    if (split == 4) p2p_task_pair_f<T, GUARD, true, 4>(tp, tile, ranges, tgt, src, kappa, partial);
+    else if (split == 2) p2p_task_pair_f<T, GUARD, true, 2>(tp, tile, ranges, tgt, src, kappa, partial);
+    else p2p_task_pair_f<T, GUARD, true, 1>(tp, tile, ranges, tgt, src, kappa, partial);
+  } else {
+    if (split == 4) p2p_task_pair_f<T, GUARD, false, 4>(tp, tile, ranges, tgt, src, kappa, partial);
+    else if (split == 2) p2p_task_pair_f<T, GUARD, false, 2>(tp, tile, ranges, tgt, src, kappa, partial);
+    else p2p_task_pair_f<T, GUARD, false, 1>(tp, tile, ranges, tgt, src, kappa, partial);
   }
 }

@@ -41,6 +41,8 @@ struct Task {
   float rho_inv_f; // eps_out / eps_source, used by the Laplace row
   int32_t nsrc;    // P2P: number of sources in the ranges
   double rho_inv;
+  int32_t split;   // P2P: 1, 2 or 4 lane groups share the half's targets (tcount <= 32 / split),
+  int32_t pad_;    // each taking every split-th source; both halves of a wavefront agree
 };
 
 // Per 64-target chunk: its M2P slots [sbeg, send) (64 lanes each) and, per

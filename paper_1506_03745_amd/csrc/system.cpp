@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -570,6 +572,7 @@ void System::build_plan() {
         h1.tbeg = cs.tbeg + 32;
         h1.tcount = cs.tcount - 32;
         h1.slot = cs.hbeg1 + pi;
+        h0.split = h1.split = 1;
         if (cs.tcount == 64) {
           P.p2p.push_back(h0);
           P.p2p.push_back(h1);
@@ -581,12 +584,17 @@ void System::build_plan() {
       ++pi;
     }
   }
+  // A half of at most 8 (16) targets has its lanes in 4 (2) groups that split
+  // the sources; halves are paired with halves of the same kind and split.
+  for (Task& t : spare) t.split = t.tcount <= 8 ? 4 : t.tcount <= 16 ? 2 : 1;
   std::stable_sort(spare.begin(), spare.end(), [](const Task& a, const Task& b) {
-    return a.fused != b.fused ? a.fused < b.fused : a.nsrc > b.nsrc;
+    if (a.fused != b.fused) return a.fused < b.fused;
+    if (a.split != b.split) return a.split < b.split;
+    return a.nsrc > b.nsrc;
   });
   for (size_t k = 0; k < spare.size();) {
     P.p2p.push_back(spare[k]);
-    if (k + 1 < spare.size() && spare[k + 1].fused == spare[k].fused) {
+    if (k + 1 < spare.size() && spare[k + 1].fused == spare[k].fused && spare[k + 1].split == spare[k].split) {
       P.p2p.push_back(spare[k + 1]);
       k += 2;
     } else {
@@ -598,6 +606,28 @@ void System::build_plan() {
       P.p2p.push_back(empty);
       k += 1;
     }
+  }
+  if (std::getenv("PBT_PLAN_STATS")) {
+    // lane utilisation of the P2P wavefronts: pair evaluations issued (64
+    // lanes x records per round x rounds) against useful target x source pairs
+    double issued = 0, useful = 0;
+    int64_t nsplit[5] = {0, 0, 0, 0, 0}, empty = 0;
+    for (size_t w = 0; w + 1 < P.p2p.size(); w += 2) {
+      const Task& a = P.p2p[w];
+      const Task& b = P.p2p[w + 1];
+      const int rounds = (std::max(a.nsrc, b.nsrc) + 31) / 32;
+      const int f = std::max(1, a.split);
+      issued += 64.0 * (32 / f) * rounds;
+      useful += (double)a.tcount * a.nsrc + (double)b.tcount * b.nsrc;
+      nsplit[f] += 2;
+      empty += (a.tcount == 0) + (b.tcount == 0);
+    }
+    double missued = 0;
+    for (const Task& t : P.m2p) missued += 64.0 * (t.lend - t.lbeg);
+    std::fprintf(stderr, "[plan] p2p waves %zu, halves split 1/2/4: %lld/%lld/%lld, empty halves %lld, "
+                 "lane utilisation %.3f; m2p tasks %zu, m2p lane utilisation %.3f\n",
+                 P.p2p.size() / 2, (long long)nsplit[1], (long long)nsplit[2], (long long)nsplit[4], (long long)empty,
+                 useful / std::max(issued, 1.0), P.m2p.size(), (double)P.m2p_pairs / std::max(missued, 1.0));
   }
 }
 
