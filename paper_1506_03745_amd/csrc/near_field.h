@@ -74,14 +74,24 @@ __device__ __forceinline__ void wave_lds_sync() {
 // With a = D.(x-y)/r the double-layer factors are a (1/r + kappa) for the
 // Yukawa row and a/r for the Laplace row (r^2 (1/r)^2 = 1 taken exactly),
 // one multiplication fewer than forming D.(x-y)/r^2 and 1 + kappa r.
-template <typename T, bool GUARD, bool FUSED>
+// KIND bit 0: also the Laplace row (target and source on one molecule);
+// bit 1: kappa = 0 (salt-free solvent), where the solvent row is the Laplace
+// kernel too and the exponential drops out.
+template <typename T, bool GUARD, int KIND>
 __device__ __forceinline__ void p2p_pair(const SrcRec<T>& s, T tx, T ty, T tz, T kappa, T ck, T& l, T& yy) {
+  constexpr bool FUSED = KIND & 1, SALTFREE = KIND & 2;
   const T dx = tx - s.v[0], dy = ty - s.v[1], dz = tz - s.v[2];
   const T r2 = dx * dx + dy * dy + dz * dz;
   T rinv = KMath<T>::rsq(r2);
   if (GUARD) rinv = r2 > T(0) ? rinv : T(0);
   const T dd = s.v[4] * dx + s.v[5] * dy + s.v[6] * dz;
   const T a = dd * rinv;                           // D.(x-y)/r
+  if (SALTFREE) {
+    const T t = a * rinv;                          // D.(x-y)/r^2
+    if (FUSED) l += (s.v[7] - t) * rinv;
+    yy += (t + s.v[3]) * rinv;
+    return;
+  }
   if (FUSED) l += (s.v[7] - a * rinv) * rinv;      // s_L/r - D.(x-y)/r^3
   const T rr = r2 * rinv;
   const T gy = KMath<T>::expk(rr, ck) * rinv;
@@ -90,7 +100,7 @@ __device__ __forceinline__ void p2p_pair(const SrcRec<T>& s, T tx, T ty, T tz, T
 
 // The records j = grp, grp + F, ... of a 32-record tile (F lane groups per
 // half-wavefront share its targets).
-template <typename T, bool GUARD, bool FUSED, int F>
+template <typename T, bool GUARD, int KIND, int F>
 __device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int grp, T tx, T ty, T tz, T kappa, T ck, T& l,
                                          T& yy) {
   if (F == 1) {
@@ -100,7 +110,7 @@ __device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int grp, T tx, T
     int j = 0;
     for (; j + UF <= 32; j += UF) {
 #pragma unroll
-      for (int q = 0; q < UF; ++q) p2p_pair<T, GUARD, FUSED>(load_rec(tile + j + q), tx, ty, tz, kappa, ck, l, yy);
+      for (int q = 0; q < UF; ++q) p2p_pair<T, GUARD, KIND>(load_rec(tile + j + q), tx, ty, tz, kappa, ck, l, yy);
     }
     return;
   }
@@ -110,7 +120,7 @@ __device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int grp, T tx, T
   const SrcRec<T>* t0 = tile + grp;
   for (int q0 = 0; q0 < N; q0 += U) {
 #pragma unroll
-    for (int q = 0; q < U; ++q) p2p_pair<T, GUARD, FUSED>(load_rec(t0 + F * (q0 + q)), tx, ty, tz, kappa, ck, l, yy);
+    for (int q = 0; q < U; ++q) p2p_pair<T, GUARD, KIND>(load_rec(t0 + F * (q0 + q)), tx, ty, tz, kappa, ck, l, yy);
   }
 }
 
@@ -124,7 +134,7 @@ __device__ __forceinline__ void p2p_tile(const SrcRec<T>* tile, int grp, T tx, T
 // the tile (LDS broadcasts), so a half with few targets keeps its lanes busy
 // and needs 1/F of the time per round.  The groups' sums are added by a
 // fixed butterfly.  Partials [slot][32][2].
-template <typename T, bool GUARD, bool FUSED, int F>
+template <typename T, bool GUARD, int KIND, int F>
 __device__ __forceinline__ void p2p_task_pair_f(const Task* __restrict__ tp, SrcRec<T>* tile,
                                                 const int32_t* __restrict__ ranges, const T* __restrict__ tgt,
                                                 const T* __restrict__ src, T kappa, T* __restrict__ partial) {
@@ -156,7 +166,7 @@ __device__ __forceinline__ void p2p_task_pair_f(const Task* __restrict__ tp, Src
     }
     if (hl >= cnt) mine[hl] = pad;
     wave_lds_sync();
-    p2p_tile<T, GUARD, FUSED, F>(mine, grp, tx, ty, tz, kappa, ck, l, yy);
+    p2p_tile<T, GUARD, KIND, F>(mine, grp, tx, ty, tz, kappa, ck, l, yy);
     wave_lds_sync();
   }
   if (F >= 4) {
@@ -173,18 +183,24 @@ __device__ __forceinline__ void p2p_task_pair_f(const Task* __restrict__ tp, Src
   }
 }
 
+template <typename T, bool GUARD, int KIND>
+__device__ __forceinline__ void p2p_task_pair_k(int split, const Task* __restrict__ tp, SrcRec<T>* tile,
+                                                const int32_t* __restrict__ ranges, const T* __restrict__ tgt,
+                                                const T* __restrict__ src, T kappa, T* __restrict__ partial) {
+  if (split == 4) p2p_task_pair_f<T, GUARD, KIND, 4>(tp, tile, ranges, tgt, src, kappa, partial);
+  else if (split == 2) p2p_task_pair_f<T, GUARD, KIND, 2>(tp, tile, ranges, tgt, src, kappa, partial);
+  else p2p_task_pair_f<T, GUARD, KIND, 1>(tp, tile, ranges, tgt, src, kappa, partial);
+}
+
 template <typename T, bool GUARD>
 __device__ __forceinline__ void p2p_task_pair(const Task* __restrict__ tp, SrcRec<T>* tile,
                                               const int32_t* __restrict__ ranges, const T* __restrict__ tgt,
                                               const T* __restrict__ src, T kappa, T* __restrict__ partial) {
-  const int fused = tp[0].fused, split = tp[0].split;
-  if (fused) {
-    if (split == 4) p2p_task_pair_f<T, GUARD, true, 4>(tp, tile, ranges, tgt, src, kappa, partial);
-    else if (split == 2) p2p_task_pair_f<T, GUARD, true, 2>(tp, tile, ranges, tgt, src, kappa, partial);
-    else p2p_task_pair_f<T, GUARD, true, 1>(tp, tile, ranges, tgt, src, kappa, partial);
-  } else {
-    if (split == 4) p2p_task_pair_f<T, GUARD, false, 4>(tp, tile, ranges, tgt, src, kappa, partial);
-    else if (split == 2) p2p_task_pair_f<T, GUARD, false, 2>(tp, tile, ranges, tgt, src, kappa, partial);
-    else p2p_task_pair_f<T, GUARD, false, 1>(tp, tile, ranges, tgt, src, kappa, partial);
+  const int kind = (tp[0].fused ? 1 : 0) | (kappa == T(0) ? 2 : 0), split = tp[0].split;
+  switch (kind) {
+    case 0: p2p_task_pair_k<T, GUARD, 0>(split, tp, tile, ranges, tgt, src, kappa, partial); break;
+    case 1: p2p_task_pair_k<T, GUARD, 1>(split, tp, tile, ranges, tgt, src, kappa, partial); break;
+    case 2: p2p_task_pair_k<T, GUARD, 2>(split, tp, tile, ranges, tgt, src, kappa, partial); break;
+    default: p2p_task_pair_k<T, GUARD, 3>(split, tp, tile, ranges, tgt, src, kappa, partial); break;
   }
 }

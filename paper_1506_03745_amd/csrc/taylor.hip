@@ -267,10 +267,55 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
   return acc;
 }
 
+// Salt-free solvent (kappa = 0): both rows use the Laplace coefficients, so
+// they are formed once and dotted with both moment rows.
+template <typename T, int P>
+__device__ __forceinline__ void taylor_dot_two(T Rx, T Ry, T Rz, const T* __restrict__ M, T& yy, T& l) {
+  constexpr int NC = ncoef(P);
+  T A[NC];
+  int dz[P + 3];
+#pragma unroll
+  for (int n = 0; n < P + 3; ++n) dz[n] = 0;
+  const T R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+  const T Rinv = TMath<T>::rsq(R2);
+  const T invR2 = Rinv * Rinv;
+  A[0] = Rinv;
+  T a0 = A[0] * M[0], a1 = A[0] * M[NC];
+#pragma unroll
+  for (int n = 1; n <= P; ++n) {
+    const T* Mn = M + dz[n];
+    const T c1 = T(2 * n - 1) / T(n) * invR2;
+    const T c2 = T(n - 1) / T(n) * invR2;
+    const T ux = c1 * Rx, uy = c1 * Ry, uz = c1 * Rz;
+#pragma unroll
+    for (int a = n; a >= 0; --a) {
+#pragma unroll
+      for (int b = n - a; b >= 0; --b) {
+        const int c = n - a - b;
+        const int k = tidx(a, b, c);
+        T S1 = 0, S2 = 0;
+        bool h2 = false;
+        if (a >= 1) S1 += ux * A[tidx(a - 1, b, c)];
+        if (b >= 1) S1 += uy * A[tidx(a, b - 1, c)];
+        if (c >= 1) S1 += uz * A[tidx(a, b, c - 1)];
+        if (a >= 2) { S2 += A[tidx(a - 2, b, c)]; h2 = true; }
+        if (b >= 2) { S2 += A[tidx(a, b - 2, c)]; h2 = true; }
+        if (c >= 2) { S2 += A[tidx(a, b, c - 2)]; h2 = true; }
+        A[k] = h2 ? S1 - c2 * S2 : S1;
+        a0 += A[k] * Mn[k];
+        a1 += A[k] * Mn[NC + k];
+      }
+    }
+    if (n + 2 <= P) dz[n + 2] = zero_after(a0 + a1);
+  }
+  yy += a0;
+  l += a1;
+}
+
 // One M2P task (64 targets x a list of boxes) on one wavefront, one target
 // per lane; the box moments are wave-uniform and read through the scalar
 // cache.
-template <typename T, int P>
+template <typename T, int P, bool SALTFREE>
 __device__ __forceinline__ void m2p_task(const Task& task, const int32_t* __restrict__ blist,
                                          const T* __restrict__ tgt, const double* __restrict__ bcen,
                                          const T* __restrict__ mom, T kappa, T* __restrict__ partial) {
@@ -286,6 +331,11 @@ __device__ __forceinline__ void m2p_task(const Task& task, const int32_t* __rest
     const int b = blist[r];
     const T Rx = tx - (T)bcen[3 * b], Ry = ty - (T)bcen[3 * b + 1], Rz = tz - (T)bcen[3 * b + 2];
     const T* M = mom + (int64_t)(2 * b) * NC;
+    if (SALTFREE) {
+      if (fused) taylor_dot_two<T, P>(Rx, Ry, Rz, M, yy, l);
+      else yy += taylor_dot<T, P, false>(Rx, Ry, Rz, kappa, M);
+      continue;
+    }
     yy += taylor_dot<T, P, true>(Rx, Ry, Rz, kappa, M);
     if (fused) l += taylor_dot<T, P, false>(Rx, Ry, Rz, kappa, M + NC);
   }
@@ -295,7 +345,7 @@ __device__ __forceinline__ void m2p_task(const Task& task, const int32_t* __rest
   }
 }
 
-template <typename T, int P>
+template <typename T, int P, bool SALTFREE>
 __global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int ntasks,
                                              const int32_t* __restrict__ blist,
                                              const T* __restrict__ tgt,
@@ -304,13 +354,13 @@ __global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int
                                              T* __restrict__ partial) {
   const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
   if (wv >= ntasks) return;
-  m2p_task<T, P>(tasks[wv], blist, tgt, bcen, mom, kappa, partial);
+  m2p_task<T, P, SALTFREE>(tasks[wv], blist, tgt, bcen, mom, kappa, partial);
 }
 
 // M2P tasks and P2P task pairs in one launch (M2P first): the far field's wavefronts
 // and the near field's share the machine instead of running one after the
 // other.
-template <typename T, int P, bool GUARD>
+template <typename T, int P, bool GUARD, bool SALTFREE>
 __global__ __launch_bounds__(256) void k_m2p_p2p(const Task* __restrict__ m2p, int nm2p,
                                                  const int32_t* __restrict__ blist,
                                                  const double* __restrict__ bcen, const T* __restrict__ mom,
@@ -320,7 +370,7 @@ __global__ __launch_bounds__(256) void k_m2p_p2p(const Task* __restrict__ m2p, i
                                                  T* __restrict__ ppartial) {
   __shared__ SrcRec<T> tiles[4][64];
   const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
-  if (wv < nm2p) m2p_task<T, P>(m2p[wv], blist, tgt, bcen, mom, kappa, partial);
+  if (wv < nm2p) m2p_task<T, P, SALTFREE>(m2p[wv], blist, tgt, bcen, mom, kappa, partial);
   else if (wv < nm2p + np2p)
     p2p_task_pair<T, GUARD>(p2p + 2 * (wv - nm2p), tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, ppartial);
 }
@@ -423,7 +473,10 @@ template <typename T, int P>
 static void m2p_p(const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
                   const double* bcen, const T* mom, T kappa, T* partial, hipStream_t s) {
   const int blocks = ((ntasks + 3) / 4 + 7) / 8 * 8;
-  k_m2p<T, P><<<blocks, 256, 0, s>>>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial);
+  if (kappa == T(0))
+    k_m2p<T, P, true><<<blocks, 256, 0, s>>>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial);
+  else
+    k_m2p<T, P, false><<<blocks, 256, 0, s>>>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial);
 }
 
 template <typename T>
@@ -450,12 +503,18 @@ static void m2p_p2p_p(const Task* m2p, int nm2p, const int32_t* blist, const dou
                       const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
                       bool guard, T* partial, T* ppartial, hipStream_t s) {
   const int blocks = ((nm2p + np2p + 3) / 4 + 7) / 8 * 8;
-  if (guard)
-    k_m2p_p2p<T, P, true><<<blocks, 256, 0, s>>>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt,
-                                                 kappa, partial, ppartial);
-  else
-    k_m2p_p2p<T, P, false><<<blocks, 256, 0, s>>>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt,
-                                                  kappa, partial, ppartial);
+#define PBT_LAUNCH(G, SF)                                                                                  \
+  k_m2p_p2p<T, P, G, SF><<<blocks, 256, 0, s>>>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt, kappa, \
+                                                partial, ppartial)
+  const bool sf = kappa == T(0);
+  if (guard) {
+    if (sf) PBT_LAUNCH(true, true);
+    else PBT_LAUNCH(true, false);
+  } else {
+    if (sf) PBT_LAUNCH(false, true);
+    else PBT_LAUNCH(false, false);
+  }
+#undef PBT_LAUNCH
 }
 
 template <typename T>

@@ -19,7 +19,7 @@ def sphere_plate(gap=1.0, kappa=0.125):
     return Problem([mol, pl], 80.0, kappa, {}, "sphere_plate")
 
 
-def three_body():
+def three_body(kappa=0.1):
     """Two molecules (different eps_in) and a potential sphere."""
     v1, t1 = icosphere(1, 3.0, (0.0, 0.0, 0.0))
     v2, t2 = icosphere(1, 2.5, (7.0, 0.0, 0.0))
@@ -28,7 +28,7 @@ def three_body():
     m2 = Surface(MOLECULE, v2, t2, eps_in=2.0, q_pos=np.array([[7.0, 0.2, 0.0], [6.5, 0, 0]]),
                  q=np.array([-1.0, 0.5]))
     ps = Surface(POTENTIAL, v3, t3, bc=np.full(len(t3), 0.02))
-    return Problem([m1, m2, ps], 80.0, 0.1, {}, "three_body")
+    return Problem([m1, m2, ps], 80.0, kappa, {}, "three_body")
 
 
 def case(name):
@@ -46,8 +46,10 @@ def case(name):
         return sphere_plate(kappa=0.0)
     if name == "three_body":
         return three_body()
+    if name == "three_body_k0":
+        return three_body(kappa=0.0)
     raise KeyError(name)
 
 
 SMALL_CASES = ["kirkwood_l1", "kirkwood_l2", "twosphere_charge_l2", "twosphere_potential_l2",
-               "sphere_plate", "sphere_plate_k0", "three_body"]
+               "sphere_plate", "sphere_plate_k0", "three_body", "three_body_k0"]

@@ -143,6 +143,38 @@ def test_treecode_multi_surface_and_molecules():
         assert rel_inf(s.matvec(x), A @ x) < 2e-4, name
 
 
+def test_treecode_salt_free_many_body():
+    """kappa = 0 (salt-free solvent): the solvent row is the Laplace kernel, and
+    P2P and M2P take their salt-free forms (no exponential; one set of Taylor
+    coefficients for both rows).  Same bar as the salted multi-surface case,
+    FP64 and mixed."""
+    for name in ("sphere_plate_k0", "three_body_k0"):
+        A, _ = oracle_Ab(name)
+        x = rand_x(A.shape[0], 7)
+        ref = A @ x
+        s, _ = from_problem(case(name), treecode=1, ncrit=24, theta=0.4, taylor_p=8)
+        assert rel_inf(s.matvec(x), ref) < 2e-4, name
+        assert rel_inf(s.matvec(x, prec=MIXED), ref) < 2e-4, name
+        s.close()
+
+
+def test_interaction_energy_salt_free_many_body():
+    """Three bodies in a salt-free solvent: F_int = F(all) - sum F(each alone)
+    against the oracle (FP64 direct to 1e-7, mixed treecode to 1e-4 of
+    |F_solv| + |F_surf|)."""
+    pr = case("three_body_k0")
+    f_or, e_all, _ = interaction_energy(pr)
+    scale = abs(e_all.F_solv) + abs(e_all.F_surf)
+    s, _ = from_problem(pr, treecode=0, tol=1e-10)
+    f, _ = s.interaction_energy(len(pr.surfaces))
+    assert abs(f - f_or) <= 1e-7 * scale
+    s.close()
+    s2, _ = from_problem(pr, treecode=1, ncrit=24, theta=0.4, taylor_p=8, prec=MIXED, tol=1e-8)
+    f2, _ = s2.interaction_energy(len(pr.surfaces))
+    assert abs(f2 - f_or) <= 1e-4 * scale
+    s2.close()
+
+
 @pytest.mark.parametrize("name", ["kirkwood_l2", "twosphere_charge_l2", "twosphere_potential_l2",
                                   "sphere_plate", "three_body"])
 def test_fp64_solve_energies(name):
