@@ -42,7 +42,9 @@ struct Task {
   int32_t nsrc;    // P2P: number of sources in the ranges
   double rho_inv;
   int32_t split;   // P2P: 1, 2 or 4 lane groups share the half's targets (tcount <= 32 / split),
-  int32_t pad_;    // each taking every split-th source; both halves of a wavefront agree
+                   // each taking every split-th source; both halves of a wavefront agree
+  int32_t known;   // 1: the sources lie on a charged or potential surface (the only sources
+                   // with known densities, which the right-hand side sums over)
 };
 
 // Per 64-target chunk: its M2P slots [sbeg, send) (64 lanes each) and, per

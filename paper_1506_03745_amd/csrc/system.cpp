@@ -312,6 +312,9 @@ void System::build(hipStream_t s) {
     std::vector<MomChunk> ch, heads;
     int32_t slots = 0;
     std::vector<int32_t> sb = bsbeg_.download(s), se = bsend_.download(s);
+    std::vector<char> known_box(nbox_, 0);
+    for (int e = 0; e < ns; ++e)
+      for (int64_t b = boff_[e]; b < boff_[e + 1]; ++b) known_box[b] = surfs_[e]->kind != PBT_MOLECULE;
     for (int b = 0; b < nbox_; ++b) {
       if (!used[b] || se[b] <= sb[b]) continue;
       const int32_t n = se[b] - sb[b];
@@ -325,12 +328,22 @@ void System::build(hipStream_t s) {
         slots += np;
       }
     }
+    // the right-hand side's product needs the moments of known boxes only
+    std::vector<MomChunk> chk, headsk;
+    for (const MomChunk& c : ch)
+      if (known_box[c.box]) chk.push_back(c);
+    for (const MomChunk& c : heads)
+      if (known_box[c.box]) headsk.push_back(c);
     nmchunks_ = (int)ch.size();
     nmheads_ = (int)heads.size();
-    if (ch.empty()) ch.push_back(MomChunk{0, 0, 0, 0, 1, 0});
-    if (heads.empty()) heads.push_back(MomChunk{0, 0, 0, 0, 1, 0});
+    nmchunks_known_ = (int)chk.size();
+    nmheads_known_ = (int)headsk.size();
+    for (auto* v : {&ch, &heads, &chk, &headsk})
+      if (v->empty()) v->push_back(MomChunk{0, 0, 0, 0, 1, 0});
     mchunks_.upload(ch, s);
     mheads_.upload(heads, s);
+    mchunks_known_.upload(chk, s);
+    mheads_known_.upload(headsk, s);
     const size_t NC = (size_t)ncoef(prm_.taylor_p);
     msum32_.alloc(std::max<size_t>(slots, 1) * 2 * NC);
     msum64_.alloc(std::max<size_t>(slots, 1) * 2 * NC);
@@ -340,6 +353,8 @@ void System::build(hipStream_t s) {
 void System::upload_plan(hipStream_t s) {
   dp2p_.upload(plan_.p2p.empty() ? std::vector<Task>(1) : plan_.p2p, s);
   dm2p_.upload(plan_.m2p.empty() ? std::vector<Task>(1) : plan_.m2p, s);
+  dp2p_known_.upload(plan_.p2p_known.empty() ? std::vector<Task>(1) : plan_.p2p_known, s);
+  dm2p_known_.upload(plan_.m2p_known.empty() ? std::vector<Task>(1) : plan_.m2p_known, s);
   dranges_.upload(plan_.ranges.empty() ? std::vector<int32_t>{0, 0} : plan_.ranges, s);
   dblist_.upload(plan_.blist.empty() ? std::vector<int32_t>{0} : plan_.blist, s);
   dchunks_.upload(plan_.chunks, s);
@@ -548,6 +563,7 @@ void System::build_plan() {
       t.lbeg = sg.lbeg;
       t.lend = sg.lend;
       t.fused = (mol && sg.e2 == e) ? 1 : 0;
+      t.known = surfs_[sg.e2]->kind != PBT_MOLECULE ? 1 : 0;
       t.rho_inv = mol ? eps_out_ / surfs_[e]->eps_in : 0.0;
       t.rho_inv_f = (float)t.rho_inv;
       if (sg.m2p) {
@@ -607,6 +623,24 @@ void System::build_plan() {
       k += 1;
     }
   }
+  // The right-hand side's product: only the tasks whose sources carry known
+  // densities (a wavefront pair stays together, its other half emptied); the
+  // partial slots of the others are cleared before that product.
+  P.p2p_known.clear();
+  for (size_t w = 0; w + 1 < P.p2p.size(); w += 2) {
+    Task a = P.p2p[w], b = P.p2p[w + 1];
+    if (!a.known && !b.known) continue;
+    for (Task* t : {&a, &b})
+      if (!t->known) {
+        t->lbeg = t->lend = 0;
+        t->nsrc = 0;
+      }
+    P.p2p_known.push_back(a);
+    P.p2p_known.push_back(b);
+  }
+  P.m2p_known.clear();
+  for (const Task& t : P.m2p)
+    if (t.known) P.m2p_known.push_back(t);
   if (std::getenv("PBT_PLAN_STATS")) {
     // lane utilisation of the P2P wavefronts: pair evaluations issued (64
     // lanes x records per round x rounds) against useful target x source pairs
@@ -635,13 +669,13 @@ void System::build_plan() {
 // M2M, M2P) runs on the system's second stream; the two write disjoint
 // partial slots and join before the combine.
 template <typename T>
-void System::interactions(hipStream_t s, const double* x, bool timed, bool src_ready) {
+void System::interactions(hipStream_t s, const double* x, bool timed, bool src_ready, bool known_only) {
   const bool f32 = std::is_same<T, float>::value;
   T* src = f32 ? (T*)src32_.p : (T*)src64_.p;
   const T* tgt = f32 ? (const T*)tgt32_.p : (const T*)tgt64_.p;
   T* part = f32 ? (T*)part32_.p : (T*)part64_.p;
   T* ppart = f32 ? (T*)ppart32_.p : (T*)ppart64_.p;
-  const int npairs = (int)(plan_.p2p.size() / 2);
+  const int npairs = (int)((known_only ? plan_.p2p_known.size() : plan_.p2p.size()) / 2);
   T* mom = f32 ? (T*)mom32_.p : (T*)mom64_.p;
   if (src_ready) {
     // records, sig and mu of x already written (by the Arnoldi update)
@@ -651,6 +685,18 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   } else {
     launch_strengths<T>(ns_, K_, sig_.p, mu_.p, src_wa_.p, nrm_.p, rlap_.p, src, s);
   }
+  // task lists and moment chunks: all sources, or those with known densities
+  const Task* p2p_tasks = known_only ? dp2p_known_.p : dp2p_.p;
+  const Task* m2p_tasks = known_only ? dm2p_known_.p : dm2p_.p;
+  const int nm2p = (int)(known_only ? plan_.m2p_known.size() : plan_.m2p.size());
+  if (known_only) {
+    // slots of the tasks left out must read as zero in the combine
+    PBT_HIP(hipMemsetAsync(part, 0, part_bytes<T>(), s));
+    PBT_HIP(hipMemsetAsync(ppart, 0, ppart_bytes<T>(), s));
+  }
+  const int nmc = known_only ? nmchunks_known_ : nmchunks_, nmh = known_only ? nmheads_known_ : nmheads_;
+  const MomChunk* mch = known_only ? mchunks_known_.p : mchunks_.p;
+  const MomChunk* mhd = known_only ? mheads_known_.p : mheads_.p;
   const bool far = !plan_.m2p.empty();
   const bool two = far && far_mode_ == 1;
   const bool fused = far && far_mode_ == 2;
@@ -659,14 +705,13 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
   T* msum = f32 ? (T*)msum32_.p : (T*)msum64_.p;
   auto moments = [&](hipStream_t fs) {
-    launch_moments<T>(prm_.taylor_p, nmchunks_, mchunks_.p, nmheads_, mheads_.p, bcen_.p, brho_.p, src, mom, msum, fs);
+    launch_moments<T>(prm_.taylor_p, nmc, mch, nmh, mhd, bcen_.p, brho_.p, src, mom, msum, fs);
   };
   auto far_field = [&](hipStream_t fs) {
     if (timed) PBT_HIP(hipEventRecord(evm_[0], fs));
     moments(fs);
     if (timed) PBT_HIP(hipEventRecord(evm_[1], fs));
-    launch_m2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, tgt, bcen_.p, mom, (T)kappa_,
-                  part, fs);
+    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, fs);
     if (timed || two) PBT_HIP(hipEventRecord(evm_[2], fs));
   };
   if (fused) {
@@ -679,7 +724,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
       PBT_HIP(hipEventRecord(evm_[2], s));
       PBT_HIP(hipEventRecord(ev_[2], s));
     }
-    launch_m2p_p2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, bcen_.p, mom, dp2p_.p, npairs,
+    launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks, npairs,
                       dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
@@ -691,14 +736,14 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   if (with_mom) {
     // moments inside the P2P launch (and its timing), then M2P
     if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
-    launch_p2p_moments<T>(prm_.taylor_p, nmchunks_, mchunks_.p, nmheads_, mheads_.p, bcen_.p, brho_.p, mom, msum,
-                          dp2p_.p, npairs, dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    launch_p2p_moments<T>(prm_.taylor_p, nmc, mch, nmh, mhd, bcen_.p, brho_.p, mom, msum, p2p_tasks, npairs,
+                          dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
       PBT_HIP(hipEventRecord(evm_[0], s));
       PBT_HIP(hipEventRecord(evm_[1], s));
     }
-    launch_m2p<T>(prm_.taylor_p, dm2p_.p, (int)plan_.m2p.size(), dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, s);
+    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, s);
     if (timed) {
       PBT_HIP(hipEventRecord(evm_[2], s));
       PBT_HIP(hipEventRecord(ev_[4], s));
@@ -707,7 +752,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     return;
   }
   if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
-  launch_p2p<T>(dp2p_.p, npairs, dranges_.p, tgt, src, (T)kappa_, guard, ppart, s);
+  launch_p2p<T>(p2p_tasks, npairs, dranges_.p, tgt, src, (T)kappa_, guard, ppart, s);
   if (timed) PBT_HIP(hipEventRecord(ev_[3], s));
   if (two) {
     // P2P (already queued) and the far field on the second stream overlap
@@ -722,11 +767,11 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
 }
 
 void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x,
-                   bool timed, bool src_ready, const DotReq* dots) {
+                   bool timed, bool src_ready, const DotReq* dots, bool known_only) {
   ++napply_;
   if (timed) PBT_HIP(hipEventRecord(ev_[0], s));
-  if (fp32) interactions<float>(s, from_x ? x : nullptr, timed, src_ready);
-  else interactions<double>(s, from_x ? x : nullptr, timed, src_ready);
+  if (fp32) interactions<float>(s, from_x ? x : nullptr, timed, src_ready, known_only);
+  else interactions<double>(s, from_x ? x : nullptr, timed, src_ready, known_only);
   CombineArgs a{};
   a.np = np_;
   a.chunks = dchunks_.p;
@@ -837,7 +882,8 @@ void System::rhs(double* b, hipStream_t s) {
   ensure_known(s);
   rhs_y_.alloc(n_);
   launch_known_densities(np_, known_ks_.p, known_km_.p, sig_.p, mu_.p, s);
-  apply(false, false, nullptr, rhs_y_.p, s);
+  // only sources on charged / potential surfaces carry known densities
+  apply(false, false, nullptr, rhs_y_.p, s, false, false, false, nullptr, true);
   PBT_HIP(hipMemsetAsync(b, 0, n_ * sizeof(double), s));
   launch_rhs_solvent(np_, row_sol_.p, rhs_y_.p, known_half_.p, b, s);
   // interior rows: Coulomb sum with 1/eps_in (eq. green_identity)

@@ -99,6 +99,7 @@ struct NearCSR {
 // Work decomposition of one target set against all source surfaces.
 struct Plan {
   std::vector<Task> p2p, m2p;
+  std::vector<Task> p2p_known, m2p_known;   // right-hand side: only known-density sources do work
   std::vector<int32_t> ranges, blist;
   std::vector<ChunkSlots> chunks;
   std::vector<int32_t> chunk_of;
@@ -199,9 +200,14 @@ class System {
   void build(hipStream_t s);
   void build_plan();
   void apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x = false,
-             bool timed = false, bool src_ready = false, const DotReq* dots = nullptr);
+             bool timed = false, bool src_ready = false, const DotReq* dots = nullptr, bool known_only = false);
   template <typename T>
-  void interactions(hipStream_t s, const double* x, bool timed, bool src_ready);
+  void interactions(hipStream_t s, const double* x, bool timed, bool src_ready, bool known_only);
+  // bytes of the M2P / P2P partial-slot buffers in precision T
+  template <typename T>
+  size_t part_bytes() const { return (size_t)std::max(plan_.nslots, 1) * 128 * sizeof(T); }
+  template <typename T>
+  size_t ppart_bytes() const { return (size_t)std::max(plan_.npslots, 1) * 64 * sizeof(T); }
   int gmres(bool fp32, const double* b, double* x, bool x_zero, const std::vector<double>& tol_abs,
             int restart, int maxit, std::vector<double>& resid_out, hipStream_t s,
             const std::vector<double>* b_norms = nullptr);
@@ -277,6 +283,8 @@ class System {
   DBuf<double> msum64_;
   int nmheads_ = 0;               // boxes of several chunks (their first chunks)
   DBuf<MomChunk> mheads_;
+  int nmchunks_known_ = 0, nmheads_known_ = 0;   // the same for boxes of charged / potential surfaces
+  DBuf<MomChunk> mchunks_known_, mheads_known_;
   int nleaf_ = 0;
   DBuf<float> mom32_;
   DBuf<double> mom64_;
@@ -284,6 +292,7 @@ class System {
   // plan
   Plan plan_;
   DBuf<Task> dp2p_, dm2p_;
+  DBuf<Task> dp2p_known_, dm2p_known_;   // the same with tasks of unknown-density sources emptied
   DBuf<int32_t> dranges_, dblist_;
   DBuf<ChunkSlots> dchunks_;
   DBuf<int32_t> dchunk_of_;
