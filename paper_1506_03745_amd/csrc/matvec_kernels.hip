@@ -144,9 +144,16 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
     for (int64_t e = a.near_ptr[i] + w; e < a.near_ptr[i + 1]; e += kCombineWaves) {
       const int32_t j = a.near_col[e];
       const double sj = a.sig[j], mj = a.mu[j];
-      const double* v = a.near_val + 4 * e;
-      nl += v[0] * sj + v[1] * mj;
-      ny += v[2] * sj + v[3] * mj;
+      if (sizeof(T) == 4) {
+        // FP32 interactions: the corrections in FP32 too (one 16-byte load)
+        const float4 v = reinterpret_cast<const float4*>(a.near_val32)[e];
+        nl += (double)v.x * sj + (double)v.y * mj;
+        ny += (double)v.z * sj + (double)v.w * mj;
+      } else {
+        const double* v = a.near_val + 4 * e;
+        nl += v[0] * sj + v[1] * mj;
+        ny += v[2] * sj + v[3] * mj;
+      }
     }
   }
   red[w][0][lane] = l;
@@ -193,6 +200,11 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
 // phi_reac = -K_L(phi) + V_L(dphi/dn) = -L with the interior-row sums L,
 // direct FP64 sums over the molecule's Gauss points plus the near
 // corrections of each charge.  One block per charge, threads over sources.
+__global__ void k_to_f32(int64_t n, const double* __restrict__ in, float* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
 __global__ __launch_bounds__(256) void k_reac(int64_t nq, const double* __restrict__ qxyz, int64_t s0,
                                               int64_t s1, const double* __restrict__ src, double rho_inv,
                                               const int64_t* __restrict__ near_ptr,
@@ -271,6 +283,12 @@ void launch_strengths_x(int64_t ns, int K, const PanelMaps& m, const double* x, 
                         hipStream_t s) {
   if (ns <= 0) return;
   k_strengths_x<T><<<nblocks(ns, 256), 256, 0, s>>>(ns, K, m, x, src_wa, nrm, rlap, sig, mu, src);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_to_f32(int64_t n, const double* in, float* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_to_f32<<<nblocks(n, 256), 256, 0, s>>>(n, in, out);
   PBT_HIP(hipGetLastError());
 }
 

@@ -137,6 +137,7 @@ struct CombineArgs {
   const ChunkSlots* chunks; int nchunks;
   const int32_t* chunk_of;       // per target
   const int64_t* near_ptr; const int32_t* near_col; const double* near_val;  // (cLs, cLm, cYs, cYm)
+  const float* near_val32;       // the same values rounded to FP32 (read by the FP32 combine)
   const double* sig; const double* mu;
   const double* x;               // unknowns (jump terms); may be null when add_jump = 0
   PanelMaps maps;
@@ -149,6 +150,8 @@ struct CombineArgs {
 };
 template <typename T>
 void launch_combine(const CombineArgs& a, const T* partial, const T* ppartial, double* y, hipStream_t s);
+// out[i] = (float)in[i], i < n.
+void launch_to_f32(int64_t n, const double* in, float* out, hipStream_t s);
 
 // --- Taylor-series far field (taylor.hip) ----------------------------------
 struct BoxDev {

@@ -299,6 +299,8 @@ void System::build(hipStream_t s) {
                        near_.val.p, s);
     launch_fold_near(np_, near_.ptr.p, near_.col.p, panel_surf_.p, panel_surf_.p, surf_mol_.p,
                      surf_rhoinv_.p, near_.val.p, s);
+    near_.val32.alloc(near_.val.n);
+    launch_to_f32((int64_t)near_.val.n, near_.val.p, near_.val32.p, s);
     PBT_HIP(hipStreamSynchronize(s));
   }
 
@@ -658,10 +660,11 @@ void System::build_plan() {
     }
     double missued = 0;
     for (const Task& t : P.m2p) missued += 64.0 * (t.lend - t.lbeg);
-    std::fprintf(stderr, "[plan] p2p waves %zu, halves split 1/2/4: %lld/%lld/%lld, empty halves %lld, "
-                 "lane utilisation %.3f; m2p tasks %zu, m2p lane utilisation %.3f\n",
-                 P.p2p.size() / 2, (long long)nsplit[1], (long long)nsplit[2], (long long)nsplit[4], (long long)empty,
-                 useful / std::max(issued, 1.0), P.m2p.size(), (double)P.m2p_pairs / std::max(missued, 1.0));
+    std::fprintf(stderr, "[plan] p2p pairs %lld (fused %lld), waves %zu, halves split 1/2/4: %lld/%lld/%lld, "
+                 "empty halves %lld, lane utilisation %.3f; m2p pairs %lld, tasks %zu, lane utilisation %.3f\n",
+                 (long long)P.p2p_pairs, (long long)P.p2p_fused_pairs, P.p2p.size() / 2, (long long)nsplit[1],
+                 (long long)nsplit[2], (long long)nsplit[4], (long long)empty, useful / std::max(issued, 1.0),
+                 (long long)P.m2p_pairs, P.m2p.size(), (double)P.m2p_pairs / std::max(missued, 1.0));
   }
 }
 
@@ -780,6 +783,7 @@ void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStre
   a.near_ptr = near_.ptr.p;
   a.near_col = near_.col.p;
   a.near_val = near_.val.p;
+  a.near_val32 = near_.val32.p;
   a.sig = sig_.p;
   a.mu = mu_.p;
   a.x = x;

@@ -93,6 +93,7 @@ struct NearCSR {
   DBuf<int64_t> ptr;
   DBuf<int32_t> col;
   DBuf<double> val;
+  DBuf<float> val32;   // FP32 copy for FP32-interaction products (collocation corrections only)
   int64_t nnz = 0;
 };
 
