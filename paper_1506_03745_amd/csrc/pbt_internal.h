@@ -164,25 +164,32 @@ struct BoxDev {
   const double* rho_inv;  // per box: eps_out/eps_s of its surface (molecule) or 0
 };
 // Moments of the boxes M2P reads, straight from their sources (taylor.hip).
-// A box's sources [sbeg, send) are cut into chunks; chunk idx of nparts
-// writes partial slot slot0 + idx when nparts > 1, and `heads` (the idx 0
-// chunk of every such box) drives the sum of the slots.
+// A box's sources [sbeg, send) are one chunk (groups of kMomGroup
+// coefficients a block, or of kMomGroupFine when `fine`: a larger box, its
+// work spread over more blocks) or, for the largest boxes, several chunks:
+// chunk idx of nparts writes partial slot slot0 + idx, and `heads` (the idx 0
+// chunk of every such box) drives the sum of the slots.  The launch runs one
+// block per entry (chunk, coefficient group) of the block list.
 struct MomChunk {
   int32_t box, sbeg, send;
   int32_t slot0, nparts, idx;
+  int32_t fine, pad_;
 };
-constexpr int kMomChunk = 1024;  // sources per chunk (4 a thread)
-constexpr int kMomGroup = 12;    // coefficients per block
-constexpr int mom_groups(int P) { return (ncoef(P) + kMomGroup - 1) / kMomGroup; }
+constexpr int kMomChunk = 1024;     // sources of a plain chunk (4 a thread)
+constexpr int kMomFineMax = 16384;  // largest box done as one fine chunk
+constexpr int kMomGroup = 12;       // coefficients per block
+constexpr int kMomGroupFine = 4;
+constexpr int mom_groups(int P, int gs = kMomGroup) { return (ncoef(P) + gs - 1) / gs; }
 // The same moments in one launch with the P2P task pairs (then the chunk sums).
 template <typename T>
-void launch_p2p_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
-                        const double* bcen, const double* brho, T* mom, T* mpart, const Task* p2p, int npairs,
-                        const int32_t* ranges, const T* src, const T* tgt, T kappa, bool guard, T* ppartial,
-                        hipStream_t s);
+void launch_p2p_moments(int P, int nblocks, const int32_t* mblocks, const MomChunk* chunks, int nheads,
+                        const MomChunk* heads, const double* bcen, const double* brho, T* mom, T* mpart,
+                        const Task* p2p, int npairs, const int32_t* ranges, const T* src, const T* tgt, T kappa,
+                        bool guard, T* ppartial, hipStream_t s);
 template <typename T>
-void launch_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
-                    const double* bcen, const double* brho, const T* src, T* mom, T* mpart, hipStream_t s);
+void launch_moments(int P, int nblocks, const int32_t* mblocks, const MomChunk* chunks, int nheads,
+                    const MomChunk* heads, const double* bcen, const double* brho, const T* src, T* mom, T* mpart,
+                    hipStream_t s);
 // M2P and P2P tasks in one launch (taylor.hip).
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,

@@ -320,15 +320,19 @@ void System::build(hipStream_t s) {
     for (int b = 0; b < nbox_; ++b) {
       if (!used[b] || se[b] <= sb[b]) continue;
       const int32_t n = se[b] - sb[b];
+      if (n <= kMomFineMax) {
+        // one chunk; a box above kMomChunk sources spreads over finer
+        // coefficient groups instead of needing a second launch for sums
+        ch.push_back(MomChunk{b, sb[b], se[b], 0, 1, 0, n > kMomChunk ? 1 : 0, 0});
+        continue;
+      }
       const int32_t np = (n + kMomChunk - 1) / kMomChunk;
       for (int32_t i = 0; i < np; ++i) {
         const int32_t a0 = sb[b] + (int32_t)((int64_t)n * i / np), a1 = sb[b] + (int32_t)((int64_t)n * (i + 1) / np);
-        ch.push_back(MomChunk{b, a0, a1, np > 1 ? slots : 0, np, i});
+        ch.push_back(MomChunk{b, a0, a1, slots, np, i, 0, 0});
       }
-      if (np > 1) {
-        heads.push_back(MomChunk{b, sb[b], se[b], slots, np, 0});
-        slots += np;
-      }
+      heads.push_back(MomChunk{b, sb[b], se[b], slots, np, 0, 0, 0});
+      slots += np;
     }
     // the right-hand side's product needs the moments of known boxes only
     std::vector<MomChunk> chk, headsk;
@@ -336,16 +340,33 @@ void System::build(hipStream_t s) {
       if (known_box[c.box]) chk.push_back(c);
     for (const MomChunk& c : heads)
       if (known_box[c.box]) headsk.push_back(c);
-    nmchunks_ = (int)ch.size();
+    // block lists: (chunk, coefficient group) per block
+    auto blocks_of = [&](const std::vector<MomChunk>& cs) {
+      std::vector<int32_t> bl;
+      for (size_t c = 0; c < cs.size(); ++c) {
+        const int ng = cs[c].fine ? mom_groups(prm_.taylor_p, kMomGroupFine) : mom_groups(prm_.taylor_p);
+        for (int g = 0; g < ng; ++g) {
+          bl.push_back((int32_t)c);
+          bl.push_back(g);
+        }
+      }
+      return bl;
+    };
+    std::vector<int32_t> bl = blocks_of(ch), blk = blocks_of(chk);
+    nmblocks_ = (int)bl.size() / 2;
+    nmblocks_known_ = (int)blk.size() / 2;
     nmheads_ = (int)heads.size();
-    nmchunks_known_ = (int)chk.size();
     nmheads_known_ = (int)headsk.size();
     for (auto* v : {&ch, &heads, &chk, &headsk})
-      if (v->empty()) v->push_back(MomChunk{0, 0, 0, 0, 1, 0});
+      if (v->empty()) v->push_back(MomChunk{0, 0, 0, 0, 1, 0, 0, 0});
+    for (auto* v : {&bl, &blk})
+      if (v->empty()) v->assign(2, 0);
     mchunks_.upload(ch, s);
     mheads_.upload(heads, s);
     mchunks_known_.upload(chk, s);
     mheads_known_.upload(headsk, s);
+    mblocks_.upload(bl, s);
+    mblocks_known_.upload(blk, s);
     const size_t NC = (size_t)ncoef(prm_.taylor_p);
     msum32_.alloc(std::max<size_t>(slots, 1) * 2 * NC);
     msum64_.alloc(std::max<size_t>(slots, 1) * 2 * NC);
@@ -697,7 +718,8 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     PBT_HIP(hipMemsetAsync(part, 0, part_bytes<T>(), s));
     PBT_HIP(hipMemsetAsync(ppart, 0, ppart_bytes<T>(), s));
   }
-  const int nmc = known_only ? nmchunks_known_ : nmchunks_, nmh = known_only ? nmheads_known_ : nmheads_;
+  const int nmb = known_only ? nmblocks_known_ : nmblocks_, nmh = known_only ? nmheads_known_ : nmheads_;
+  const int32_t* mbl = known_only ? mblocks_known_.p : mblocks_.p;
   const MomChunk* mch = known_only ? mchunks_known_.p : mchunks_.p;
   const MomChunk* mhd = known_only ? mheads_known_.p : mheads_.p;
   const bool far = !plan_.m2p.empty();
@@ -708,7 +730,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
   T* msum = f32 ? (T*)msum32_.p : (T*)msum64_.p;
   auto moments = [&](hipStream_t fs) {
-    launch_moments<T>(prm_.taylor_p, nmc, mch, nmh, mhd, bcen_.p, brho_.p, src, mom, msum, fs);
+    launch_moments<T>(prm_.taylor_p, nmb, mbl, mch, nmh, mhd, bcen_.p, brho_.p, src, mom, msum, fs);
   };
   auto far_field = [&](hipStream_t fs) {
     if (timed) PBT_HIP(hipEventRecord(evm_[0], fs));
@@ -739,7 +761,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   if (with_mom) {
     // moments inside the P2P launch (and its timing), then M2P
     if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
-    launch_p2p_moments<T>(prm_.taylor_p, nmc, mch, nmh, mhd, bcen_.p, brho_.p, mom, msum, p2p_tasks, npairs,
+    launch_p2p_moments<T>(prm_.taylor_p, nmb, mbl, mch, nmh, mhd, bcen_.p, brho_.p, mom, msum, p2p_tasks, npairs,
                           dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));

@@ -278,13 +278,15 @@ class System {
   DBuf<double> bcen_, brho_;
   DBuf<int32_t> bsbeg_, bsend_, bcbeg_, bcend_, bclist_;
   DBuf<int32_t> leaf_boxes_;
-  int nmchunks_ = 0;              // source chunks of the boxes whose moments M2P reads
-  DBuf<MomChunk> mchunks_;
+  int nmblocks_ = 0;              // moments blocks: (chunk, coefficient group) pairs
+  DBuf<int32_t> mblocks_;
+  DBuf<MomChunk> mchunks_;        // source chunks of the boxes whose moments M2P reads
   DBuf<float> msum32_;            // chunk sums of boxes of several chunks
   DBuf<double> msum64_;
   int nmheads_ = 0;               // boxes of several chunks (their first chunks)
   DBuf<MomChunk> mheads_;
-  int nmchunks_known_ = 0, nmheads_known_ = 0;   // the same for boxes of charged / potential surfaces
+  int nmblocks_known_ = 0, nmheads_known_ = 0;   // the same for boxes of charged / potential surfaces
+  DBuf<int32_t> mblocks_known_;
   DBuf<MomChunk> mchunks_known_, mheads_known_;
   int nleaf_ = 0;
   DBuf<float> mom32_;

@@ -150,29 +150,42 @@ __device__ __forceinline__ void moments_group(const MomChunk& ch, const double* 
   }
 }
 
-template <typename T, int P, int G>
+template <typename T, int P, int GS, int G>
 __device__ __forceinline__ void moments_dispatch(const MomChunk& ch, int gi, const double* bcen, const double* brho,
                                                  const T* src, T* mom, T* mpart, T* red) {
-  constexpr int K0 = G * kMomGroup;
+  constexpr int K0 = G * GS;
   if constexpr (K0 < ncoef(P)) {
-    constexpr int K1 = K0 + kMomGroup < ncoef(P) ? K0 + kMomGroup : ncoef(P);
+    constexpr int K1 = K0 + GS < ncoef(P) ? K0 + GS : ncoef(P);
     if (gi == G) {
       moments_group<T, P, K0, K1>(ch, bcen, brho, src, mom, mpart, red);
       return;
     }
-    moments_dispatch<T, P, G + 1>(ch, gi, bcen, brho, src, mom, mpart, red);
+    moments_dispatch<T, P, GS, G + 1>(ch, gi, bcen, brho, src, mom, mpart, red);
   }
 }
 
+// One moments block: entry b of the block list is (chunk, coefficient group);
+// a chunk marked fine takes groups of kMomGroupFine coefficients (a large box
+// done by one chunk, its work spread over more blocks), otherwise kMomGroup.
 template <typename T, int P>
-__global__ __launch_bounds__(kMomThreads) void k_moments(const MomChunk* __restrict__ chunks,
+__device__ __forceinline__ void moments_block(int b, const int32_t* __restrict__ mblocks,
+                                              const MomChunk* __restrict__ chunks, const double* bcen,
+                                              const double* brho, const T* src, T* mom, T* mpart, T* red) {
+  const MomChunk ch = chunks[mblocks[2 * b]];
+  const int gi = mblocks[2 * b + 1];
+  if (ch.fine) moments_dispatch<T, P, kMomGroupFine, 0>(ch, gi, bcen, brho, src, mom, mpart, red);
+  else moments_dispatch<T, P, kMomGroup, 0>(ch, gi, bcen, brho, src, mom, mpart, red);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kMomThreads) void k_moments(const int32_t* __restrict__ mblocks,
+                                                         const MomChunk* __restrict__ chunks,
                                                          const double* __restrict__ bcen,
                                                          const double* __restrict__ brho,
                                                          const T* __restrict__ src, T* __restrict__ mom,
                                                          T* __restrict__ mpart) {
   __shared__ T red[kMomThreads * 9];
-  const MomChunk ch = chunks[blockIdx.x];
-  moments_dispatch<T, P, 0>(ch, (int)blockIdx.y, bcen, brho, src, mom, mpart, red);
+  moments_block<T, P>((int)blockIdx.x, mblocks, chunks, bcen, brho, src, mom, mpart, red);
 }
 
 // Boxes of several chunks: their moments are the chunk sums added in chunk
@@ -377,10 +390,11 @@ __global__ __launch_bounds__(256) void k_m2p_p2p(const Task* __restrict__ m2p, i
 
 // Moments blocks and P2P task pairs in one launch (moments first, so the
 // short moment blocks start at once and P2P fills the machine around them):
-// nmb = nchunks x mom_groups(P) moment blocks, then the P2P blocks, whose
+// nmb moment blocks (the block list, padded to a multiple of 8), then the P2P blocks, whose
 // logical order is made XCD-aware on their own range (nmb is a multiple of 8).
 template <typename T, int P, bool GUARD>
-__global__ __launch_bounds__(256) void k_p2p_mom(int nmreal, int nmb, const MomChunk* __restrict__ chunks,
+__global__ __launch_bounds__(256) void k_p2p_mom(int nmreal, int nmb, const int32_t* __restrict__ mblocks,
+                                                 const MomChunk* __restrict__ chunks,
                                                  const double* __restrict__ bcen,
                                                  const double* __restrict__ brho, T* __restrict__ mom,
                                                  T* __restrict__ mpart, const Task* __restrict__ p2p, int npairs,
@@ -391,11 +405,7 @@ __global__ __launch_bounds__(256) void k_p2p_mom(int nmreal, int nmb, const MomC
   __shared__ __align__(16) unsigned char lds[kTile > kRed ? kTile : kRed];
   if ((int)blockIdx.x < nmb) {
     if ((int)blockIdx.x >= nmreal) return;
-    constexpr int ng = mom_groups(P);
-    const int c = (int)blockIdx.x / ng;
-    const MomChunk ch = chunks[c];
-    moments_dispatch<T, P, 0>(ch, (int)blockIdx.x - c * ng, bcen, brho, src, mom, mpart,
-                              reinterpret_cast<T*>(lds));
+    moments_block<T, P>((int)blockIdx.x, mblocks, chunks, bcen, brho, src, mom, mpart, reinterpret_cast<T*>(lds));
     return;
   }
   const int l = (int)blockIdx.x - nmb, per = ((int)gridDim.x - nmb) >> 3;
@@ -408,18 +418,19 @@ __global__ __launch_bounds__(256) void k_p2p_mom(int nmreal, int nmb, const MomC
 }  // namespace
 
 template <typename T, int P>
-static void moments_p(int nchunks, const MomChunk* chunks, const double* bcen, const double* brho, const T* src,
-                      T* mom, T* mpart, hipStream_t s) {
-  k_moments<T, P><<<dim3(nchunks, mom_groups(P)), kMomThreads, 0, s>>>(chunks, bcen, brho, src, mom, mpart);
+static void moments_p(int nblocks, const int32_t* mblocks, const MomChunk* chunks, const double* bcen,
+                      const double* brho, const T* src, T* mom, T* mpart, hipStream_t s) {
+  k_moments<T, P><<<nblocks, kMomThreads, 0, s>>>(mblocks, chunks, bcen, brho, src, mom, mpart);
 }
 
 template <typename T>
-void launch_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
-                    const double* bcen, const double* brho, const T* src, T* mom, T* mpart, hipStream_t s) {
-  if (nchunks <= 0) return;
+void launch_moments(int P, int nblocks, const int32_t* mblocks, const MomChunk* chunks, int nheads,
+                    const MomChunk* heads, const double* bcen, const double* brho, const T* src, T* mom, T* mpart,
+                    hipStream_t s) {
+  if (nblocks <= 0) return;
   switch (P) {
 #define PBT_CASE(PP) \
-  case PP: moments_p<T, PP>(nchunks, chunks, bcen, brho, src, mom, mpart, s); break;
+  case PP: moments_p<T, PP>(nblocks, mblocks, chunks, bcen, brho, src, mom, mpart, s); break;
     PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
 #undef PBT_CASE
     default: throw Error(1, "Taylor order P must be 0..8");
@@ -432,31 +443,30 @@ void launch_moments(int P, int nchunks, const MomChunk* chunks, int nheads, cons
 }
 
 template <typename T, int P>
-static void p2p_mom_p(int nchunks, const MomChunk* chunks, const double* bcen, const double* brho, T* mom,
-                      T* mpart, const Task* p2p, int npairs, const int32_t* ranges, const T* src, const T* tgt,
-                      T kappa, bool guard, T* ppartial, hipStream_t s) {
-  const int nmreal = nchunks * mom_groups(P);
+static void p2p_mom_p(int nmreal, const int32_t* mblocks, const MomChunk* chunks, const double* bcen,
+                      const double* brho, T* mom, T* mpart, const Task* p2p, int npairs, const int32_t* ranges,
+                      const T* src, const T* tgt, T kappa, bool guard, T* ppartial, hipStream_t s) {
   const int nmb = (nmreal + 7) / 8 * 8;
   const int blocks = nmb + ((npairs + 3) / 4 + 7) / 8 * 8;
   if (guard)
-    k_p2p_mom<T, P, true><<<blocks, 256, 0, s>>>(nmreal, nmb, chunks, bcen, brho, mom, mpart, p2p, npairs, ranges, src, tgt,
-                                                 kappa, ppartial);
+    k_p2p_mom<T, P, true><<<blocks, 256, 0, s>>>(nmreal, nmb, mblocks, chunks, bcen, brho, mom, mpart, p2p, npairs,
+                                                 ranges, src, tgt, kappa, ppartial);
   else
-    k_p2p_mom<T, P, false><<<blocks, 256, 0, s>>>(nmreal, nmb, chunks, bcen, brho, mom, mpart, p2p, npairs, ranges, src,
-                                                  tgt, kappa, ppartial);
+    k_p2p_mom<T, P, false><<<blocks, 256, 0, s>>>(nmreal, nmb, mblocks, chunks, bcen, brho, mom, mpart, p2p,
+                                                  npairs, ranges, src, tgt, kappa, ppartial);
 }
 
 template <typename T>
-void launch_p2p_moments(int P, int nchunks, const MomChunk* chunks, int nheads, const MomChunk* heads,
-                        const double* bcen, const double* brho, T* mom, T* mpart, const Task* p2p, int npairs,
-                        const int32_t* ranges, const T* src, const T* tgt, T kappa, bool guard, T* ppartial,
-                        hipStream_t s) {
-  if (nchunks + npairs <= 0) return;
+void launch_p2p_moments(int P, int nblocks, const int32_t* mblocks, const MomChunk* chunks, int nheads,
+                        const MomChunk* heads, const double* bcen, const double* brho, T* mom, T* mpart,
+                        const Task* p2p, int npairs, const int32_t* ranges, const T* src, const T* tgt, T kappa,
+                        bool guard, T* ppartial, hipStream_t s) {
+  if (nblocks + npairs <= 0) return;
   switch (P) {
-#define PBT_CASE(PP)                                                                                             \
-  case PP:                                                                                                       \
-    p2p_mom_p<T, PP>(nchunks, chunks, bcen, brho, mom, mpart, p2p, npairs, ranges, src, tgt, kappa, guard, ppartial, \
-                     s);                                                                                         \
+#define PBT_CASE(PP)                                                                                               \
+  case PP:                                                                                                         \
+    p2p_mom_p<T, PP>(nblocks, mblocks, chunks, bcen, brho, mom, mpart, p2p, npairs, ranges, src, tgt, kappa, guard, \
+                     ppartial, s);                                                                                 \
     break;
     PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
 #undef PBT_CASE
@@ -535,16 +545,17 @@ void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, cons
   PBT_HIP(hipGetLastError());
 }
 
-template void launch_p2p_moments<float>(int, int, const MomChunk*, int, const MomChunk*, const double*,
-                                        const double*, float*, float*, const Task*, int, const int32_t*, const float*,
-                                        const float*, float, bool, float*, hipStream_t);
-template void launch_p2p_moments<double>(int, int, const MomChunk*, int, const MomChunk*, const double*,
-                                         const double*, double*, double*, const Task*, int, const int32_t*,
-                                         const double*, const double*, double, bool, double*, hipStream_t);
-template void launch_moments<float>(int, int, const MomChunk*, int, const MomChunk*, const double*, const double*,
-                                    const float*, float*, float*, hipStream_t);
-template void launch_moments<double>(int, int, const MomChunk*, int, const MomChunk*, const double*, const double*,
-                                     const double*, double*, double*, hipStream_t);
+template void launch_p2p_moments<float>(int, int, const int32_t*, const MomChunk*, int, const MomChunk*,
+                                        const double*, const double*, float*, float*, const Task*, int,
+                                        const int32_t*, const float*, const float*, float, bool, float*, hipStream_t);
+template void launch_p2p_moments<double>(int, int, const int32_t*, const MomChunk*, int, const MomChunk*,
+                                         const double*, const double*, double*, double*, const Task*, int,
+                                         const int32_t*, const double*, const double*, double, bool, double*,
+                                         hipStream_t);
+template void launch_moments<float>(int, int, const int32_t*, const MomChunk*, int, const MomChunk*, const double*,
+                                    const double*, const float*, float*, float*, hipStream_t);
+template void launch_moments<double>(int, int, const int32_t*, const MomChunk*, int, const MomChunk*,
+                                     const double*, const double*, const double*, double*, double*, hipStream_t);
 template void launch_m2p_p2p<float>(int, const Task*, int, const int32_t*, const double*, const float*,
                                     const Task*, int, const int32_t*, const float*, const float*, float, bool,
                                     float*, float*, hipStream_t);
