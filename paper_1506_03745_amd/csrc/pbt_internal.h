@@ -97,9 +97,10 @@ struct NearParams {
 void launch_near_values(int64_t nt, const double* tx, const int32_t* tgt_self, const int64_t* rowptr,
                         const int32_t* col, const double* tri9, const double* nrm,
                         const double* area, const NearParams& p, double* vals, hipStream_t s);
+// tgt_surf null: every target belongs to surface tsurf.
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
                       const int32_t* panel_surf, const int32_t* surf_mol, const double* surf_rhoinv,
-                      double* vals, hipStream_t s);
+                      double* vals, hipStream_t s, int32_t tsurf = 0);
 void launch_reac(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
                  double rho_inv, const int64_t* near_ptr, const int32_t* near_col,
                  const double* near_val, const double* sig, const double* mu, double* phi,

@@ -247,13 +247,13 @@ __global__ void k_coulomb_rhs(int64_t n, const double* __restrict__ tx, const in
 // only sees panels of its own molecule, with factors -(eps_out/eps_s) on the
 // single layer and -1 on the double layer; the solvent row sees every panel.
 __global__ void k_fold_near(int64_t nt, const int64_t* __restrict__ rowptr,
-                            const int32_t* __restrict__ col, const int32_t* __restrict__ tgt_surf,
+                            const int32_t* __restrict__ col, const int32_t* __restrict__ tgt_surf, int32_t tsurf,
                             const int32_t* __restrict__ panel_surf,
                             const int32_t* __restrict__ surf_mol,
                             const double* __restrict__ surf_rhoinv, double* vals) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nt) return;
-  const int32_t t = tgt_surf[i];
+  const int32_t t = tgt_surf ? tgt_surf[i] : tsurf;
   for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
     const int32_t s = panel_surf[col[e]];
     const bool same = (s == t) && surf_mol[t];
@@ -269,9 +269,9 @@ inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
                       const int32_t* panel_surf, const int32_t* surf_mol, const double* surf_rhoinv,
-                      double* vals, hipStream_t s) {
+                      double* vals, hipStream_t s, int32_t tsurf) {
   if (nt <= 0) return;
-  k_fold_near<<<nblocks(nt, 256), 256, 0, s>>>(nt, rowptr, col, tgt_surf, panel_surf, surf_mol,
+  k_fold_near<<<nblocks(nt, 256), 256, 0, s>>>(nt, rowptr, col, tgt_surf, tsurf, panel_surf, surf_mol,
                                                 surf_rhoinv, vals);
   PBT_HIP(hipGetLastError());
 }

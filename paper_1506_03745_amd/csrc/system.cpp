@@ -168,9 +168,14 @@ void System::build(hipStream_t s) {
   if (!triangle_rule(prm_.k_far, bf, wf)) throw Error(1, "k_far must be 1, 3, 4 or 7");
   if (!triangle_rule(prm_.k_near, bn, wn)) throw Error(1, "k_near must be 19 (or 1, 3, 4, 7)");
   gauss_legendre01(prm_.k_self_edge, gt, gw);
-  DBuf<double> dbf, dwf, dbn, dwn, dgt, dgw;
-  dbf.upload(bf, s); dwf.upload(wf, s); dbn.upload(bn, s); dwn.upload(wn, s);
-  dgt.upload(gt, s); dgw.upload(gw, s);
+  // the rules on the device, kept for later near-correction tables
+  qtab_[0].upload(bf, s);
+  qtab_[1].upload(wf, s);
+  qtab_[2].upload(bn, s);
+  qtab_[3].upload(wn, s);
+  qtab_[4].upload(gt, s);
+  qtab_[5].upload(gw, s);
+  DBuf<double>&dbf = qtab_[0], &dwf = qtab_[1], &dbn = qtab_[2], &dwn = qtab_[3], &dgt = qtab_[4], &dgw = qtab_[5];
   src_pos_.alloc(3 * ns_);
   src_wa_.alloc(ns_);
   launch_sources(np_, K_, tri9_.p, nrm_.p, area_.p, dbf.p, dwf.p, src_pos_.p, src_wa_.p, s);
@@ -445,27 +450,39 @@ void System::build_plan() {
     const TreeBox& tb = trees_[l.e].boxes[l.b];
     leaves_.push_back({l.e, l.b, poff_[l.e] + tb.pbeg, poff_[l.e] + tb.pend});
   }
-  lp2p_.assign(leaves.size(), std::vector<std::vector<int>>(ns));
-  lm2p_.assign(leaves.size(), std::vector<std::vector<int>>(ns));
+  // the surfaces of each group (a leaf only interacts with its own group's)
+  group_surfs_.clear();
+  for (int e = 0; e < ns; ++e) {
+    const int g = surfs_[e]->group;
+    if ((int)group_surfs_.size() <= g) group_surfs_.resize(g + 1);
+    group_surfs_[g].push_back(e);
+  }
+  lp2p_.assign(leaves.size(), {});
+  lm2p_.assign(leaves.size(), {});
 
-  // Per leaf and source surface: merged P2P source ranges and M2P boxes.
+  // Per leaf and source surface of its group (k-th of group_surfs_): merged
+  // P2P source ranges and M2P boxes.
   struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
-  std::vector<std::vector<Lists>> L(leaves.size(), std::vector<Lists>(ns));
+  std::vector<std::vector<Lists>> L(leaves.size());
   // (per leaf in parallel; the counts are added up afterwards)
   std::vector<std::array<int64_t, 5>> cnt(leaves.size(), {0, 0, 0, 0, 0});
   parallel_for((int64_t)leaves.size(), [&](int64_t li) {
     const TreeBox& tl = trees_[leaves[li].e].boxes[leaves[li].b];
     const int64_t nt = tl.pend - tl.pbeg;
     std::array<int64_t, 5>& c = cnt[li];   // tot_src, tot_box, p2p, m2p, fused
-    for (int e2 = 0; e2 < ns; ++e2) {
+    const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
+    L[li].resize(gsf.size());
+    lp2p_[li].resize(gsf.size());
+    lm2p_[li].resize(gsf.size());
+    for (size_t k2 = 0; k2 < gsf.size(); ++k2) {
+      const int e2 = gsf[k2];
       std::vector<int> pb, mb;
-      if (surfs_[e2]->group != surfs_[leaves[li].e]->group) continue;  // independent systems
       if (prm_.treecode) interaction_lists(trees_[e2], tl, prm_.theta, pb, mb);
       else pb.push_back(0);
       std::sort(pb.begin(), pb.end(), [&](int a, int b) {
         return trees_[e2].boxes[a].pbeg < trees_[e2].boxes[b].pbeg;
       });
-      Lists& o = L[li][e2];
+      Lists& o = L[li][k2];
       for (int b : pb) {
         const TreeBox& sb = trees_[e2].boxes[b];
         const int32_t j0 = (int32_t)((poff_[e2] + sb.pbeg) * K_), j1 = (int32_t)((poff_[e2] + sb.pend) * K_);
@@ -478,8 +495,8 @@ void System::build_plan() {
       for (int b : mb) o.box.push_back((int32_t)(boff_[e2] + b));
       c[1] += (int64_t)mb.size() * ((nt + 63) / 64);
       c[3] += (int64_t)mb.size() * nt;
-      lp2p_[li][e2] = std::move(pb);
-      lm2p_[li][e2] = std::move(mb);
+      lp2p_[li][k2] = std::move(pb);
+      lm2p_[li][k2] = std::move(mb);
     }
   });
   int64_t tot_src = 0, tot_box = 0;
@@ -518,8 +535,10 @@ void System::build_plan() {
   struct Seg { int32_t lbeg, lend; int e2; bool m2p; };
   std::vector<std::vector<Seg>> segs(leaves.size());
   for (size_t li = 0; li < leaves.size(); ++li) {
-    for (int e2 = 0; e2 < ns; ++e2) {
-      const Lists& o = L[li][e2];
+    const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
+    for (size_t k2 = 0; k2 < gsf.size(); ++k2) {
+      const int e2 = gsf[k2];
+      const Lists& o = L[li][k2];
       int64_t acc = 0;
       int32_t start = (int32_t)(P.ranges.size() / 2);
       for (auto rg : o.rng) {

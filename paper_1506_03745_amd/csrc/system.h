@@ -272,6 +272,7 @@ class System {
   std::vector<int32_t> h_panel_orig_;  // internal global -> original index within its surface
   std::vector<int32_t> h_pinv_;        // poff + original index -> internal global index
   DBuf<int32_t> u2i_;                  // boundary (original-order) unknown index -> internal one
+  DBuf<double> qtab_[6];               // far rule (bary, w), near rule (bary, w), edge rule (t, w)
 
   // tree (global box numbering)
   int nbox_ = 0;
@@ -326,9 +327,11 @@ class System {
   int64_t seg_src_ = 0, seg_box_ = 0, seg_src_used_ = 0, seg_box_used_ = 0;
   void upload_plan(hipStream_t s);
 
-  // forward interaction lists per (target leaf, source surface), for the transpose
+  // forward interaction lists per (target leaf, k-th source surface of the
+  // leaf's group in group_surfs_), for the transpose
   struct LeafInfo { int e; int b; int64_t g0, g1; };
   std::vector<LeafInfo> leaves_;
+  std::vector<std::vector<int>> group_surfs_;   // surfaces of each group, in order
   std::vector<std::vector<std::vector<int>>> lp2p_, lm2p_;
   // transpose plan
   bool tplan_ready_ = false;

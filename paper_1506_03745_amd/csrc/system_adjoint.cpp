@@ -20,14 +20,8 @@ namespace pbt {
 void System::charge_near(int e, const double* qx, int64_t nq, NearCSR& qn, hipStream_t s) {
   const SurfIn& S = *surfs_[e];
   const int64_t p0 = poff_[e];
-  std::vector<double> bf, wf, bn, wn, gt, gw;
-  triangle_rule(prm_.k_far, bf, wf);
-  triangle_rule(prm_.k_near, bn, wn);
-  gauss_legendre01(prm_.k_self_edge, gt, gw);
-  DBuf<double> dbf, dwf, dbn, dwn, dgt, dgw;
-  dbf.upload(bf, s); dwf.upload(wf, s); dbn.upload(bn, s); dwn.upload(wn, s);
-  dgt.upload(gt, s); dgw.upload(gw, s);
-  NearParams npr{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
+  NearParams npr{K_, prm_.k_near, prm_.k_self_edge, kappa_, qtab_[0].p, qtab_[1].p, qtab_[2].p, qtab_[3].p,
+                 qtab_[4].p, qtab_[5].p};
   DBuf<int32_t> cnt;
   cnt.alloc(nq);
   launch_near_count(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr, cnt.p, s);
@@ -41,16 +35,9 @@ void System::charge_near(int e, const double* qx, int64_t nq, NearCSR& qn, hipSt
   launch_near_fill(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr, qn.ptr.p, qn.col.p, s);
   launch_near_values(nq, qx, nullptr, qn.ptr.p, qn.col.p, tri9_.p + 9 * p0, nrm_.p + 3 * p0,
                      area_.p + p0, npr, qn.val.p, s);
-  // the charges and the molecule's panels form a one-surface table
-  std::vector<int32_t> tsurf(nq, 0), psurf0(S.nt, 0), smol1{1};
-  std::vector<double> srho1{eps_out_ / S.eps_in};
-  DBuf<int32_t> dts, dps, dsm;
-  DBuf<double> dsr;
-  dts.upload(tsurf, s);
-  dps.upload(psurf0, s);
-  dsm.upload(smol1, s);
-  dsr.upload(srho1, s);
-  launch_fold_near(nq, qn.ptr.p, qn.col.p, dts.p, dps.p, dsm.p, dsr.p, qn.val.p, s);
+  // the charges count as targets of surface e (columns are local to its panels)
+  launch_fold_near(nq, qn.ptr.p, qn.col.p, nullptr, panel_surf_.p + p0, surf_mol_.p, surf_rhoinv_.p, qn.val.p, s,
+                   e);
   PBT_HIP(hipStreamSynchronize(s));
 }
 
@@ -79,8 +66,10 @@ void System::build_tplan(hipStream_t s) {
   for (size_t li = 0; li < leaves_.size(); ++li) {
     const LeafInfo& L = leaves_[li];
     const bool mol = surfs_[L.e]->kind == PBT_MOLECULE;
-    for (int e2 = 0; e2 < ns; ++e2)
-      for (int b2 : lp2p_[li][e2]) {
+    const std::vector<int>& gsf = group_surfs_[surfs_[L.e]->group];
+    for (size_t k2 = 0; k2 < gsf.size(); ++k2)
+      for (int b2 : lp2p_[li][k2]) {
+        const int e2 = gsf[k2];
         lists[{e2, b2}].push_back({L.g0, L.g1, (mol && e2 == L.e) ? 1 : 0});
         const TreeBox& sb = trees_[e2].boxes[b2];
         work += (L.g1 - L.g0) * (int64_t)((sb.pend - sb.pbeg) * K_ + 63) / 64;
@@ -156,8 +145,10 @@ void System::build_tplan(hipStream_t s) {
   for (size_t li = 0; li < leaves_.size(); ++li) {
     const LeafInfo& L = leaves_[li];
     const bool mol = surfs_[L.e]->kind == PBT_MOLECULE;
-    for (int e2 = 0; e2 < ns; ++e2)
-      for (int b : lm2p_[li][e2]) {
+    const std::vector<int>& gsf = group_surfs_[surfs_[L.e]->group];
+    for (size_t k2 = 0; k2 < gsf.size(); ++k2)
+      for (int b : lm2p_[li][k2]) {
+        const int e2 = gsf[k2];
         const int gb = (int)(boff_[e2] + b);
         for (int64_t t0 = L.g0; t0 < L.g1; t0 += 64) {
           Task t{};
