@@ -23,17 +23,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // out[i] = sum_b part[i * nbj + b] for i < nrows, by a block of kBS
-// threads: eight lanes per row, each adding a strided eighth of the row
-// (independent loads), then a fixed butterfly; the order of the additions
-// is fixed, so every block that calls this gets bitwise the same sums.
+// threads: eight lanes per row, each adding a strided eighth of the row in
+// increasing b, then a fixed butterfly.  The loads of a lane are issued in
+// batches of kRowBatch before any of them is added (one memory round trip
+// per batch instead of one per few loads); out-of-range slots add an exact
+// zero.  The order of the additions is fixed, so every block that calls
+// this gets bitwise the same sums.
+constexpr int kRowBatch = 32;
 __device__ __forceinline__ void reduce_rows(const double* __restrict__ part, int nrows, int nbj, double* out) {
   const int sub = threadIdx.x & 7;
   for (int r0 = 0; r0 < nrows; r0 += kBS / 8) {
     const int i = r0 + (int)(threadIdx.x >> 3);
     double sq = 0;
     if (i < nrows) {
-#pragma unroll 8
-      for (int b = sub; b < nbj; b += 8) sq += part[(int64_t)i * nbj + b];
+      const double* row = part + (int64_t)i * nbj;
+      for (int b0 = 0; b0 < nbj; b0 += 8 * kRowBatch) {
+        double t[kRowBatch];
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q) {
+          const int b = b0 + sub + 8 * q;
+          t[q] = b < nbj ? row[b] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q) sq += t[q];
+      }
     }
     sq += __shfl_xor(sq, 4, 8);
     sq += __shfl_xor(sq, 2, 8);
@@ -62,25 +75,54 @@ __global__ __launch_bounds__(kBS) void k_gs_dots(const int64_t* __restrict__ gu,
   const int g = blockIdx.z;
   const int64_t u0 = gu[2 * g], u1 = gu[2 * g + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * 8;
+  const int mq = m + (self_dot ? 1 : 0);
+  const int64_t j0 = u0 + blockIdx.x * (int64_t)kBS + threadIdx.x;
+  // UPDATE: the thread's first element and its first kPre basis entries are
+  // loaded before the partials of the previous pass are added up, so those
+  // memory round trips overlap
+  constexpr int kPre = UPDATE ? 32 : 1;
+  double vpre[kPre];
+  double wpre = 0.0;
+  if (UPDATE && j0 < u1) {
+    wpre = w[j0];
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) vpre[q] = q < m ? V[(int64_t)q * ldv + j0] : 0.0;
+  }
   if (UPDATE) {
     reduce_rows(hpart + (int64_t)g * R * nbh, m, nbh, hs);
     __syncthreads();
     if (blockIdx.x == 0 && blockIdx.y == 0)
       for (int i = threadIdx.x; i < m; i += kBS) hout[(int64_t)g * R + i] = hs[i];
   }
-  const int i0 = blockIdx.y * 8;
-  const int mq = m + (self_dot ? 1 : 0);
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t j = u0 + blockIdx.x * (int64_t)kBS + threadIdx.x; j < u1; j += (int64_t)nbj * kBS) {
-    double wj = w[j];
+  for (int64_t j = j0; j < u1; j += (int64_t)nbj * kBS) {
+    // the rows of this block's dots (the same rows as some of the update's:
+    // cache hits), issued before the update's chain of products
+    double vd[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vd[q] = i0 + q < m ? V[(int64_t)(i0 + q) * ldv + j] : 0.0;
+    double wj;
     if (UPDATE) {
+      int i = 0;
+      if (j == j0) {
+        wj = wpre;
+#pragma unroll
+        for (int q = 0; q < kPre; ++q)
+          if (q < m) wj -= hs[q] * vpre[q];
+        i = kPre;
+      } else {
+        wj = w[j];
+      }
 #pragma unroll 8
-      for (int i = 0; i < m; ++i) wj -= hs[i] * V[(int64_t)i * ldv + j];
+      for (; i < m; ++i) wj -= hs[i] * V[(int64_t)i * ldv + j];
+    } else {
+      wj = w[j];
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int i = i0 + q;
-      if (i < mq) acc[q] += (i < m ? V[(int64_t)i * ldv + j] : wj) * wj;
+      if (i < mq) acc[q] += (i < m ? vd[q] : wj) * wj;
     }
   }
 #pragma unroll
@@ -140,6 +182,18 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     cphi = ns.m.col_phi[p];
     cpsi = ns.m.col_psi[p];
   }
+  // the panel's geometry for the source records (independent of the
+  // unknowns, so issued with them)
+  double wa0 = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0, rl = 0.0, dsc = 0.0;
+  if (on) {
+    if (sub < ns.K) wa0 = ns.wa[p * ns.K + sub];
+    n0 = ns.nrm[3 * p];
+    n1 = ns.nrm[3 * p + 1];
+    n2 = ns.nrm[3 * p + 2];
+    rl = ns.rlap[p];
+    dsc = ns.m.dens_scale[p];
+  }
+  const double h1v = (int)threadIdx.x <= j ? h1[(int64_t)g * R + threadIdx.x] : 0.0;
   const int32_t e = sub < 4 ? cphi : cpsi;
   constexpr int kPre = 8;
   double vr[kPre];
@@ -158,7 +212,7 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j; i += kBS) {
-    h[i] = h1[(int64_t)g * R + i] + h2[i];
+    h[i] = (i == (int)threadIdx.x ? h1v : h1[(int64_t)g * R + i]) + h2[i];
     col[i] = h[i];
   }
   if (threadIdx.x < 64) {
@@ -205,7 +259,7 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     const double vo = __shfl_xor(v, 4, 8);
     const double vphi = sub < 4 ? v : vo, vpsi = sub < 4 ? vo : v;
     if (on) {
-      const double sg = cpsi >= 0 ? ns.m.dens_scale[p] * vpsi : 0.0;
+      const double sg = cpsi >= 0 ? dsc * vpsi : 0.0;
       const double mv = cphi >= 0 ? -vphi : 0.0;
       if (sub == 0) {
         ns.sig[p] = sg;
@@ -214,15 +268,15 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
       T* src = reinterpret_cast<T*>(ns.src);
       for (int k = sub; k < ns.K; k += 8) {
         const int64_t jj = p * ns.K + k;
-        const double wa = ns.wa[jj];
+        const double wa = k == sub ? wa0 : ns.wa[jj];
         const double mm = wa * mv;
         const double sval = wa * sg;
         T* o = src + kSrcStride * jj;
         o[3] = (T)sval;
-        o[4] = (T)(mm * ns.nrm[3 * p]);
-        o[5] = (T)(mm * ns.nrm[3 * p + 1]);
-        o[6] = (T)(mm * ns.nrm[3 * p + 2]);
-        o[7] = (T)(ns.rlap[p] * sval);
+        o[4] = (T)(mm * n0);
+        o[5] = (T)(mm * n1);
+        o[6] = (T)(mm * n2);
+        o[7] = (T)(rl * sval);
       }
     }
   }

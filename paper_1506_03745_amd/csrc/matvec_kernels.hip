@@ -111,7 +111,9 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
                                                               const T* __restrict__ ppartial, double* y) {
   __shared__ double red[kCombineWaves][4][64];
   const ChunkSlots cs = a.chunks[blockIdx.x];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index is uniform: held in a scalar register, so the slot and
+  // row addresses below are scalar bases plus the lane's offset
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const bool act = lane < cs.tcount;
   const int64_t i = cs.tbeg + lane;
   // the output rows and jump terms are read up front (wave 0 writes), so
@@ -124,6 +126,20 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
     if (w == 0) {
       const int32_t cphi = a.maps.col_phi[i];
       if (a.add_jump && cphi >= 0) xj = 0.5 * a.x[cphi];
+    }
+  }
+  // the basis entries of this wave's first two Gram-Schmidt rows (below),
+  // also loaded up front
+  double vp[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  if (act) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int k = w + t * kCombineWaves;
+      if (k < a.ndots) {
+        const double* Vk = a.V + (int64_t)k * a.ldv;
+        if (ri >= 0) vp[t][0] = Vk[ri];
+        vp[t][1] = Vk[rs];
+      }
     }
   }
   double l = 0.0, yy = 0.0, nl = 0.0, ny = 0.0;
@@ -161,17 +177,21 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
   red[w][2][lane] = nl;
   red[w][3][lane] = ny;
   __syncthreads();
+  // wave q < 4 adds up sum q over the waves (in wave order) into red[0][q]
+  if (w < 4) {
+    double t = 0.0;
+    for (int k = 0; k < kCombineWaves; ++k) t += red[k][w][lane];
+    red[0][w][lane] = t;
+  }
+  __syncthreads();
   __shared__ double yv[2][64];
   if (w == 0) {
     double yi = 0.0, ys = 0.0;
     if (act) {
-      l = yy = nl = ny = 0.0;
-      for (int k = 0; k < kCombineWaves; ++k) {
-        l += red[k][0][lane];
-        yy += red[k][1][lane];
-        nl += red[k][2][lane];
-        ny += red[k][3][lane];
-      }
+      l = red[0][0][lane];
+      yy = red[0][1][lane];
+      nl = red[0][2][lane];
+      ny = red[0][3][lane];
       yi = xj + (l * kInv4Pi + nl);
       ys = xj + (yy * kInv4Pi + ny);
       if (ri >= 0) y[ri] = yi;
@@ -184,12 +204,14 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
   if (a.ndots <= 0) return;
   // first Gram-Schmidt pass: this chunk's rows of V_i . y, a wave per i
   __syncthreads();
-  for (int k = w; k < a.ndots; k += kCombineWaves) {
+  for (int k = w, t = 0; k < a.ndots; k += kCombineWaves, ++t) {
     const double* Vk = a.V + (int64_t)k * a.ldv;
     double pr = 0.0;
     if (act) {
-      if (ri >= 0) pr = Vk[ri] * yv[0][lane];
-      pr += Vk[rs] * yv[1][lane];
+      const double v0 = t == 0 ? vp[0][0] : t == 1 ? vp[1][0] : (ri >= 0 ? Vk[ri] : 0.0);
+      const double v1 = t == 0 ? vp[0][1] : t == 1 ? vp[1][1] : Vk[rs];
+      if (ri >= 0) pr = v0 * yv[0][lane];
+      pr += v1 * yv[1][lane];
     }
     for (int o = 32; o > 0; o >>= 1) pr += __shfl_down(pr, o, 64);
     if (lane == 0) a.dpart[((int64_t)cs.grp * a.R + k) * a.nbh + cs.lchunk] = pr;
