@@ -1006,11 +1006,12 @@ void System::true_residual(const double* b, const double* x, double* r, hipStrea
 // independent systems of the groups at once (one Krylov space each; the
 // operator is applied to all of them in one product).  Everything of an
 // Arnoldi step runs on the device, including each group's Hessenberg column
-// and Givens rotation, which leave the residual estimates |g_{j+1}| in
-// resid.  The host enqueues groups of steps, sized from the slowest group's
-// observed convergence rate, and keeps up to two in flight: it reads one
-// set of estimates (pinned memory, an event each) while the next runs, so
-// the GPU does not wait on the host between steps.  A group stops at its
+// and Givens rotation, which store the residual estimates |g_{j+1}|
+// straight into pinned host memory (no copy on the stream).  The host
+// enqueues groups of steps, sized from the slowest group's observed
+// convergence rate, and keeps up to two in flight: it reads the estimates
+// of one group (after its event) while the next runs, so the GPU does not
+// wait on the host between steps.  A group stops at its
 // first estimate <= tol_abs[g]; steps taken after that (for it, or for all
 // groups past the last one's) are discarded.  Returns the most iterations
 // any group used.
@@ -1030,8 +1031,7 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   double* dcs = dH + G * HS;
   double* dsn = dcs + (size_t)G * m;
   double* dg = dsn + (size_t)G * m;
-  double* dres = dg + (size_t)G * (m + 1);
-  double* dbeta = dres + (size_t)G * m;
+  double* dbeta = dg + (size_t)G * (m + 1) + (size_t)G * m;
   double* dy = dbeta + 2 * (size_t)G;
   double* h1 = hdev_.p;
   double* part1 = part_.p;                                            // [G][R][max(nbj, nbh)]
@@ -1075,7 +1075,7 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
       launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, 0, nullptr, 0, part1, nbj, s);
     }
     launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, nbh, h1, 1, part2, nbj, s);
-    launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, dres,
+    launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, rs,
                           fuse ? &nsrc : nullptr, s);
   };
   while (pending() && iters < maxit) {
@@ -1116,7 +1116,6 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
         want = std::max(1, std::min(want, known < 3 ? (j == 0 ? 2 : 4) : 8));
         const int group = std::min({want, m - j, maxit - iters - j});
         for (int k = j; k < j + group; ++k) enqueue_step(k);
-        PBT_HIP(hipMemcpyAsync(rs, dres, (size_t)G * m * sizeof(double), hipMemcpyDeviceToHost, s));
         const int ev = nev++ & 1;
         PBT_HIP(hipEventRecord(evg_[ev], s));
         inflight.push_back({j, group, ev});
