@@ -16,12 +16,13 @@ study using the PyGBe code"):
 * ``integrals``  panel geometry, the near/far/self decision and the four
                  panel integrals V_L, K_L, V_Y, K_Y (eq. layers_element).
 * ``bem``        dense block assembly of eq. matrix_phi / matrix_dphi for any
-                 number of molecules and charged/potential surfaces, LU solve,
+                 number of molecules and charged/potential surfaces, and of
+                 Stern layers (one more interface per molecule), LU solve,
                  and the energies of Section 2 (eqs. solv_energy,
                  phi_reac_bem, energy_surf_disc, total_energy,
                  interaction_energy).
 * ``analytic``   the two-sphere series solution of Section 4 and the
-                 isolated-body closed forms.
+                 isolated-body closed forms (with a Stern shell too).
 * ``adjoint``    gradients of the interaction free energy through the dense
                  transpose.
 

@@ -128,6 +128,20 @@ def born_kirkwood(q, d, eps_in, eps_out, kappa):
     return q * q / (8.0 * math.pi * d) * (1.0 / (eps_out * (1.0 + kappa * d)) - 1.0 / eps_in)
 
 
+def born_kirkwood_stern(q, a, b, eps_in, eps_stern, eps_out, kappa):
+    """Solvation energy of a charge at the centre of a sphere of radius a
+    (eps_in) inside a concentric salt-free shell a < r < b (eps_stern) in a
+    screened solvent (eps_out, kappa).  Outside b the potential is
+    A exp(-kappa r) / r, in the shell q / (4 pi eps_stern r) + D, inside
+    q / (4 pi eps_in r) + C; continuity of phi and eps dphi/dr at b and a
+    gives A, D and C, and F = q C / 2:
+        q^2 / (8 pi) * (1 / (eps_stern a) - 1 / (eps_in a)
+                        + 1 / (eps_out b (1 + kappa b)) - 1 / (eps_stern b)).
+    With b = a it is born_kirkwood."""
+    return q * q / (8.0 * math.pi) * (1.0 / (eps_stern * a) - 1.0 / (eps_in * a)
+                                      + 1.0 / (eps_out * b * (1.0 + kappa * b)) - 1.0 / (eps_stern * b))
+
+
 def charged_sphere_energy(sigma, d, eps_out, kappa):
     """Free energy 1/2 Q phi(d) of an isolated sphere carrying Q = 4 pi d^2 sigma
     in a screened solvent, phi(d) = Q / (4 pi eps_out d (1 + kappa d))."""

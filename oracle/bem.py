@@ -1,27 +1,43 @@
-"""Dense collocation BEM for molecules and charged / potential surfaces.
+"""Dense collocation BEM for molecules, Stern layers and charged / potential
+surfaces.
 
 Sections 2 and 3 of the paper, written out for any number of surfaces in one
 solvent (the paper's eq. matrix_phi and eq. matrix_dphi are the case of one
 molecule and one surface; its conclusion notes that an imposed-BC surface
-adds one block row and a molecule boundary two).
+adds one block row and a molecule boundary two).  A Stern surface (the extra
+interfaces of Section 2's closing remarks: an ion-exclusion layer) encloses
+one molecule and bounds a salt-free region of its own permittivity between
+that molecule and the ionic solvent; it carries two unknowns and two rows
+like a molecule.
+
+Every surface separates two regions.  A region is the solvent (Yukawa,
+eps_out, kappa), the interior of a molecule (Laplace, eps_in, with the point
+charges) or the layer inside a Stern surface (Laplace, that surface's eps_in,
+no charges).  A molecule enclosed by a Stern surface has that layer outside
+it; every other surface has the solvent outside.
 
 Unknowns per surface, in problem order:
-    molecule   [phi (N), dphi/dn inside (N)]
+    molecule, stern   [phi (N), dphi/dn inside (N)]
     charged    [phi (N)]          (dphi/dn = -sigma / eps_out is known)
     potential  [dphi/dn (N)]      (phi = phi0 is known)
 Rows per surface, in problem order:
-    molecule   [interior row (N), solvent row (N)]
+    molecule, stern   [row of the inside region (N), row of the outside region (N)]
     charged / potential   [solvent row (N)]
 
-Interior row of molecule t at collocation point x_i (eq. integral_eq, first
-line, with the 1/eps_1 of eq. green_identity kept on the right):
-    phi_i / 2 + sum_j K_L[i,j] phi_j - V_L[i,j] psi_j
-        = (1 / eps_t) sum_k q_k / (4 pi |x_i - r_k|)
-Solvent row of surface t (eq. integral_eq, second and third lines):
-    u_i / 2 + sum_s sum_j ( -K_Y[i,j] phi_out_j + V_Y[i,j] psi_out_j ) = 0
-with u = phi (molecule, charged) or phi0 (potential), phi_out = phi or phi0,
-psi_out = (eps_s / eps_out) psi (molecule), -sigma / eps_out (charged) or
-the unknown psi (potential).  Known terms move to the right-hand side.
+The row of region R at collocation point x_i of surface t is Green's
+representation of R (eq. green_identity) taken to the boundary (eq.
+integral_eq): u_i / 2, plus for the surface whose inside is R (seen from
+inside, Laplace)
+    + K_L[i,j] phi_j - V_L[i,j] psi_j,
+plus for every surface s with R outside it (seen from outside, with R's
+kernel G_R: Yukawa in the solvent, Laplace in a Stern layer)
+    - K_R[i,j] phi_out_j + V_R[i,j] psi_out_j,
+equal to (1 / eps_t) sum_k q_k / (4 pi |x_i - r_k|) when R is the interior
+of molecule t and to 0 otherwise.  Here u = phi (molecule, stern, charged)
+or phi0 (potential), phi_out = phi or phi0, psi_out = (eps_s / eps_R) psi
+(molecule, stern), -sigma / eps_out (charged) or the unknown psi
+(potential).  Known terms move to the right-hand side.  Without Stern
+surfaces these are the interior and solvent rows of eq. integral_eq.
 
 Energies (Section 2, Energy calculation), in reduced units then kcal/mol:
     F_solv = 1/2 sum_k q_k phi_reac(r_k),            (eq. solv_energy, first line)
@@ -30,7 +46,8 @@ Energies (Section 2, Energy calculation), in reduced units then kcal/mol:
            = 1/2 eps_out sum_j phi0_j psi_j A_j      (set potential, with
              sigma = -eps_out dphi/dn so that F = -1/2 sum phi0 sigma A)
     F_coul = sum_{k<l} q_k q_l / (4 pi eps_t r_kl)
-    F_total = F_coul + F_surf + F_solv,  F_int = F_total(all) - sum F_total(each)
+    F_total = F_coul + F_surf + F_solv,  F_int = F_total(all) - sum F_total(each),
+    a molecule and its Stern surface forming one component.
 """
 from __future__ import annotations
 
@@ -42,7 +59,9 @@ import scipy.linalg
 from .integrals import Panels, layer_blocks
 from .units import FOUR_PI, energy_to_kcal, sigma_to_reduced, volts_to_reduced
 
-MOLECULE, CHARGED, POTENTIAL = 0, 1, 2
+MOLECULE, CHARGED, POTENTIAL, STERN = 0, 1, 2, 3
+TWO_ROWS = (MOLECULE, STERN)
+SOLVENT = -1
 
 
 @dataclass
@@ -60,27 +79,46 @@ class DenseBEM:
     """Dense BEM system of a problem (``workloads.Problem``-like object)."""
 
     def __init__(self, problem, k_far=3, k_near=19, k_self_edge=9, enabled=None):
-        surfs = list(problem.surfaces)
-        if enabled is not None:
-            surfs = [s for s, on in zip(surfs, enabled) if on]
+        allsurfs = list(problem.surfaces)
+        on = [True] * len(allsurfs) if enabled is None else list(enabled)
+        keep = [i for i, o in enumerate(on) if o]
+        new_index = {i: k for k, i in enumerate(keep)}
+        surfs = [allsurfs[i] for i in keep]
         self.surfs = surfs
         self.eps_out = float(problem.eps_out)
         self.kappa = float(problem.kappa)
         self.k_far, self.k_near, self.k_self_edge = k_far, k_near, k_self_edge
         self.panels = [Panels(s.verts, s.tris) for s in surfs]
+        # the region outside each surface: the solvent, or the layer of the
+        # Stern surface that encloses it (the region inside surface k is k)
+        self.outer = [SOLVENT] * len(surfs)
+        for k, s in enumerate(surfs):
+            if s.kind == STERN:
+                par = getattr(s, "parent", -1)
+                if par not in new_index or surfs[new_index[par]].kind != MOLECULE:
+                    raise ValueError("a Stern surface needs its molecule in the same system")
+                if self.outer[new_index[par]] != SOLVENT:
+                    raise ValueError("one Stern surface per molecule")
+                self.outer[new_index[par]] = k
         # unknown and row offsets
         self.col_off, self.row_off = [], []
         c = r = 0
         for s in surfs:
             self.col_off.append(c)
             self.row_off.append(r)
-            w = 2 * s.nt if s.kind == MOLECULE else s.nt
+            w = 2 * s.nt if s.kind in TWO_ROWS else s.nt
             c += w
             r += w
         self.n = c
         # boundary data in reduced units
         self.sigma = [sigma_to_reduced(np.asarray(s.bc)) if s.kind == CHARGED else None for s in surfs]
         self.phi0 = [volts_to_reduced(np.asarray(s.bc)) if s.kind == POTENTIAL else None for s in surfs]
+
+    def region_eps(self, R):
+        return self.eps_out if R == SOLVENT else float(self.surfs[R].eps_in)
+
+    def region_kappa(self, R):
+        return self.kappa if R == SOLVENT else 0.0
 
     # -- blocks ------------------------------------------------------------
     def _blocks(self, t, s, rows=None):
@@ -92,42 +130,56 @@ class DenseBEM:
         return layer_blocks(x, ps, self.kappa, self.k_far, self.k_near, self.k_self_edge,
                             self_idx=self_idx)
 
-    def row_block(self, t, rows=None):
-        """Rows of the operator and right-hand side for target surface t.
-
-        Returns (A_int, b_int, A_sol, b_sol); the interior pair is None unless
-        t is a molecule.  ``rows`` selects panels of surface t."""
+    def region_row(self, t, R, rows=None):
+        """Rows (panels ``rows`` of surface t) of the equation of region R,
+        which must be one of the two regions surface t separates."""
         st = self.surfs[t]
-        nt = st.nt
-        idx = np.arange(nt) if rows is None else np.asarray(rows)
+        idx = np.arange(st.nt) if rows is None else np.asarray(rows)
         m = len(idx)
-        A_sol = np.zeros((m, self.n))
-        b_sol = np.zeros(m)
-        A_int = b_int = None
+        A = np.zeros((m, self.n))
+        b = np.zeros(m)
+        ct = self.col_off[t]
+        if st.kind == POTENTIAL:
+            b -= 0.5 * self.phi0[t][idx]
+        else:
+            A[np.arange(m), ct + idx] += 0.5
+        eps_R = self.region_eps(R)
         for s, ss in enumerate(self.surfs):
+            inside = R == s
+            outside = self.outer[s] == R
+            if not (inside or outside):
+                continue
             vl, kl, vy, ky = self._blocks(t, s, idx)
             cs = self.col_off[s]
             ns = ss.nt
-            if s == t and st.kind == MOLECULE:
-                A_int = np.zeros((m, self.n))
-                A_int[:, cs:cs + ns] = kl
-                A_int[np.arange(m), cs + idx] += 0.5
-                A_int[:, cs + ns:cs + 2 * ns] = -vl
-                b_int = self._coulomb_rhs(st, self.panels[t].centroid[idx])
-            if ss.kind == MOLECULE:
-                A_sol[:, cs:cs + ns] += -ky
-                A_sol[:, cs + ns:cs + 2 * ns] += (ss.eps_in / self.eps_out) * vy
+            if inside:
+                A[:, cs:cs + ns] += kl
+                A[:, cs + ns:cs + 2 * ns] += -vl
+                continue
+            v, k = (vy, ky) if self.region_kappa(R) != 0.0 else (vl, kl)
+            if ss.kind in TWO_ROWS:
+                A[:, cs:cs + ns] += -k
+                A[:, cs + ns:cs + 2 * ns] += (ss.eps_in / eps_R) * v
             elif ss.kind == CHARGED:
-                A_sol[:, cs:cs + ns] += -ky
-                b_sol += vy @ (self.sigma[s] / self.eps_out)
+                A[:, cs:cs + ns] += -k
+                b += v @ (self.sigma[s] / self.eps_out)
             else:
-                A_sol[:, cs:cs + ns] += vy
-                b_sol += ky @ self.phi0[s]
-        ct = self.col_off[t]
-        if st.kind in (MOLECULE, CHARGED):
-            A_sol[np.arange(m), ct + idx] += 0.5
-        else:
-            b_sol -= 0.5 * self.phi0[t][idx]
+                A[:, cs:cs + ns] += v
+                b += k @ self.phi0[s]
+        if R == t and st.kind == MOLECULE:
+            b += self._coulomb_rhs(st, self.panels[t].centroid[idx])
+        return A, b
+
+    def row_block(self, t, rows=None):
+        """Rows of the operator and right-hand side for target surface t.
+
+        Returns (A_int, b_int, A_sol, b_sol): the rows of the region inside t
+        (None unless t is a molecule or a Stern surface) and of the region
+        outside it.  ``rows`` selects panels of surface t."""
+        A_int = b_int = None
+        if self.surfs[t].kind in TWO_ROWS:
+            A_int, b_int = self.region_row(t, t, rows)
+        A_sol, b_sol = self.region_row(t, self.outer[t], rows)
         return A_int, b_int, A_sol, b_sol
 
     def _coulomb_rhs(self, s, x):
@@ -141,7 +193,7 @@ class DenseBEM:
         for t, st in enumerate(self.surfs):
             A_int, b_int, A_sol, b_sol = self.row_block(t)
             r = self.row_off[t]
-            if st.kind == MOLECULE:
+            if st.kind in TWO_ROWS:
                 A[r:r + st.nt] = A_int
                 b[r:r + st.nt] = b_int
                 r += st.nt
@@ -156,12 +208,12 @@ class DenseBEM:
         b = np.zeros(len(rows))
         for t, st in enumerate(self.surfs):
             r0 = self.row_off[t]
-            w = 2 * st.nt if st.kind == MOLECULE else st.nt
+            w = 2 * st.nt if st.kind in TWO_ROWS else st.nt
             sel = np.nonzero((rows >= r0) & (rows < r0 + w))[0]
             if len(sel) == 0:
                 continue
             loc = rows[sel] - r0
-            if st.kind == MOLECULE:
+            if st.kind in TWO_ROWS:
                 ii = sel[loc < st.nt]
                 if len(ii):
                     A_int, b_int, _, _ = self.row_block(t, loc[loc < st.nt])
@@ -186,7 +238,7 @@ class DenseBEM:
         out = []
         for s, ss in enumerate(self.surfs):
             c = self.col_off[s]
-            if ss.kind == MOLECULE:
+            if ss.kind in TWO_ROWS:
                 out.append((u[c:c + ss.nt], u[c + ss.nt:c + 2 * ss.nt]))
             elif ss.kind == CHARGED:
                 out.append((u[c:c + ss.nt], -self.sigma[s] / self.eps_out))
@@ -209,7 +261,7 @@ class DenseBEM:
                 fc += coulomb_energy(ss.q_pos, ss.q, ss.eps_in)
             elif ss.kind == CHARGED:
                 fsurf += 0.5 * np.sum(phi * self.sigma[s] * self.panels[s].area)
-            else:
+            elif ss.kind == POTENTIAL:
                 fsurf += 0.5 * self.eps_out * np.sum(self.phi0[s] * psi * self.panels[s].area)
         return Energies(energy_to_kcal(fc), energy_to_kcal(fs), energy_to_kcal(fsurf))
 
@@ -233,13 +285,24 @@ def solve_problem(problem, k_far=3, k_near=19, k_self_edge=9, enabled=None):
     return sysm.energies(u), u, sysm
 
 
+def components(problem):
+    """Enabled-surface masks of the isolated components: each molecule with
+    its Stern surface, and each charged or potential surface alone."""
+    surfs = list(problem.surfaces)
+    out = []
+    for i, s in enumerate(surfs):
+        if s.kind == STERN:
+            continue
+        out.append([j == i or (t.kind == STERN and getattr(t, "parent", -1) == i) for j, t in enumerate(surfs)])
+    return out
+
+
 def interaction_energy(problem, **kw):
     """F_int = F_total(assembly) - sum over components F_total(isolated)
-    (eq. interaction_energy).  Components are the surfaces."""
+    (eq. interaction_energy)."""
     e_all, _, _ = solve_problem(problem, **kw)
     parts = []
-    for i in range(len(problem.surfaces)):
-        en = [j == i for j in range(len(problem.surfaces))]
+    for en in components(problem):
         e_i, _, _ = solve_problem(problem, enabled=en, **kw)
         parts.append(e_i)
     return e_all.F_total - sum(p.F_total for p in parts), e_all, parts

@@ -112,6 +112,30 @@ def test_kirkwood_convergence():
     assert 0.85 < _order(errs) < 1.15
 
 
+def test_kirkwood_stern_closed_form_limits():
+    """The Stern-shell closed form reduces to Born/Kirkwood for a shell of
+    zero thickness, and for a shell with the solvent's permittivity and no
+    screening (the layer then changes nothing)."""
+    q, a, e1, e2, k = 1.0, 4.0, 4.0, 80.0, 0.125
+    assert abs(analytic.born_kirkwood_stern(q, a, a, e1, 20.0, e2, k)
+               - analytic.born_kirkwood(q, a, e1, e2, k)) < 1e-15
+    assert abs(analytic.born_kirkwood_stern(q, a, 7.0, e1, e2, e2, 0.0)
+               - analytic.born_kirkwood(q, a, e1, e2, 0.0)) < 1e-15
+
+
+def test_kirkwood_stern_convergence():
+    """Dense BEM of a charged sphere inside a Stern sphere (two interfaces,
+    four block rows) converges at first order in N to the closed form."""
+    exact = energy_to_kcal(analytic.born_kirkwood_stern(1.0, 4.0, 6.0, 4.0, 20.0, 80.0, 0.125))
+    errs = []
+    for lv in (1, 2, 3):
+        e, _, _ = solve_problem(config_problem("kirkwood_stern", level=lv))
+        errs.append((e.F_solv - exact) / exact)
+    assert abs(errs[-1]) < 5e-3
+    assert abs(errs[0]) > abs(errs[1]) > abs(errs[2])
+    assert 0.85 < _order(errs) < 1.15
+
+
 @pytest.mark.parametrize("case", ["charge", "potential"])
 def test_two_sphere_interaction_convergence(case):
     """F_int of the dense BEM against the series, levels 1..3 (80..1280 panels

@@ -2,11 +2,17 @@
 
 A :class:`Problem` is a list of surfaces in one solvent.  Each surface is a
 dielectric molecule boundary (with interior permittivity and point charges),
-a surface with imposed charge density, or a surface with imposed potential.
+a surface with imposed charge density, a surface with imposed potential, or
+a Stern surface: a closed surface around one molecule that bounds a
+salt-free layer between the molecule and the ionic solvent.
 
 Named workloads (sizes are panel counts):
 
 * ``kirkwood``     sphere r = 4 A, 1280 panels, +1 e at the centre.
+* ``kirkwood_stern`` the same sphere inside a Stern (ion-exclusion) sphere of
+  r = 6 A (1280 panels, salt-free layer of permittivity 20).
+* ``stern_plate``  that pair (320 + 320 panels) 14 A above a 40 x 40 x 2 A
+  charged plate (1536 panels).
 * ``twosphere_charge`` / ``twosphere_potential``  molecule sphere (r = 4 A,
   +1 e centre, 5120 panels) and a second sphere (r = 4 A, 5120 panels) 12 A
   away on z with sigma = 0.05 C/m^2 or phi = 0.05 V.
@@ -26,8 +32,8 @@ import numpy as np
 
 from .meshes import box_plate, icosphere, star_surface
 
-MOLECULE, CHARGED, POTENTIAL = 0, 1, 2
-KIND_NAMES = {MOLECULE: "molecule", CHARGED: "charged", POTENTIAL: "potential"}
+MOLECULE, CHARGED, POTENTIAL, STERN = 0, 1, 2, 3
+KIND_NAMES = {MOLECULE: "molecule", CHARGED: "charged", POTENTIAL: "potential", STERN: "stern"}
 
 
 @dataclass
@@ -36,9 +42,10 @@ class Surface:
     verts: np.ndarray            # (nv, 3) float64, Angstrom
     tris: np.ndarray             # (nt, 3) int32, CCW seen from the solvent
     bc: np.ndarray | None = None  # (nt,) sigma [C/m^2] or phi0 [V]
-    eps_in: float = 1.0           # molecule interior permittivity
+    eps_in: float = 1.0           # molecule interior permittivity (Stern: of the layer)
     q_pos: np.ndarray | None = None  # (nq, 3) Angstrom
     q: np.ndarray | None = None      # (nq,) e
+    parent: int = -1              # Stern surface: index of the molecule it encloses
 
     @property
     def nt(self) -> int:
@@ -103,6 +110,13 @@ def sphere_molecule(level=4, radius=4.0, center=(0.0, 0.0, 0.0), charge=1.0, eps
                    q_pos=np.asarray([center], dtype=np.float64), q=np.array([charge]))
 
 
+def stern_sphere(parent, level=4, radius=6.0, center=(0.0, 0.0, 0.0), eps_in=80.0):
+    """Ion-exclusion (Stern) surface: a sphere around molecule ``parent`` (its
+    index in the problem), enclosing a salt-free layer of permittivity eps_in."""
+    v, t = icosphere(level, radius, center)
+    return Surface(STERN, v, t, eps_in=eps_in, parent=parent)
+
+
 def plate(half_x, half_y, thick, n_xy, n_long, n_z, sigma):
     v, t = box_plate(-half_x, half_x, -half_y, half_y, -thick, 0.0, n_xy, n_long, n_z)
     bc = np.full(len(t), sigma, dtype=np.float64) if np.isscalar(sigma) else np.asarray(sigma)
@@ -118,7 +132,7 @@ def star_molecule(levels, shape_seed, n_charges, charge_seed, gap, eps_in=4.0):
 
 
 CONFIG_NAMES = ("kirkwood", "twosphere_charge", "twosphere_potential", "star_plate",
-                "orient_sweep", "star_plate_large", "star_plate_twin")
+                "orient_sweep", "star_plate_large", "star_plate_twin", "kirkwood_stern", "stern_plate")
 
 DEFAULT_PARAMS = dict(k_far=3, k_near=19, k_self_edge=9, ncrit=300, taylor_p=6, theta=0.5, tol=1e-6)
 
@@ -132,6 +146,18 @@ def config_problem(name: str, level: int | None = None, rotation: int | None = N
         lv = 3 if level is None else level
         s = sphere_molecule(lv, 4.0)
         return Problem([s], 80.0, 0.125, p, name)
+    if name == "kirkwood_stern":
+        # sphere r = 4 A (+1 e at the centre) inside a Stern sphere r = 6 A;
+        # the layer's permittivity 20 (not 80) makes its every term visible
+        # in the solvation energy
+        lv = 3 if level is None else level
+        return Problem([sphere_molecule(lv, 4.0), stern_sphere(0, lv, 6.0, eps_in=20.0)], 80.0, 0.125, p, name)
+    if name == "stern_plate":
+        # the Stern-layer sphere pair 14 A above a charged plate
+        lv = 2 if level is None else level
+        c = (0.0, 0.0, 14.0)
+        pl = plate(20.0, 20.0, 2.0, 16, 32, 2, -0.05)
+        return Problem([sphere_molecule(lv, 4.0, c), stern_sphere(0, lv, 6.0, c), pl], 80.0, 0.125, p, name)
     if name in ("twosphere_charge", "twosphere_potential"):
         lv = 4 if level is None else level
         mol = sphere_molecule(lv, 4.0)
