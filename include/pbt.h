@@ -62,7 +62,7 @@ typedef enum {
 
 typedef enum { PBT_FP64 = 0, PBT_MIXED = 1 } pbt_precision;
 
-typedef enum { PBT_MOLECULE = 0, PBT_CHARGED = 1, PBT_POTENTIAL = 2 } pbt_kind;
+typedef enum { PBT_MOLECULE = 0, PBT_CHARGED = 1, PBT_POTENTIAL = 2, PBT_STERN = 3 } pbt_kind;
 
 /* Numerical parameters (Tables 1-3 of the paper list the same knobs). */
 typedef struct {
@@ -116,12 +116,13 @@ pbt_status pbt_set_params(pbt_ctx* ctx, const pbt_params* params);
 pbt_status pbt_set_solvent(pbt_ctx* ctx, double eps_out, double kappa_per_A);
 
 /* Adds a closed surface (eq. pde: Gamma_1 for a molecule, Gamma_2 for an
- * imposed-BC surface).  xyz: nv*3 doubles (A); tri: nt*3 int32 vertex
- * indices; bc: nt doubles, sigma0 [C/m^2] for PBT_CHARGED, phi0 [V] for
- * PBT_POTENTIAL, ignored (may be NULL) for PBT_MOLECULE.  Writes the new
- * surface id.  Rejects non-finite coordinates, indices out of range and
- * panels of area < 1e-12 A^2.  Not allowed after a solve has prepared the
- * geometry (PBT_E_STATE). */
+ * imposed-BC surface; PBT_STERN: the outer interface of an ion-exclusion
+ * layer around one molecule, which pbt_set_stern names).  xyz: nv*3 doubles
+ * (A); tri: nt*3 int32 vertex indices; bc: nt doubles, sigma0 [C/m^2] for
+ * PBT_CHARGED, phi0 [V] for PBT_POTENTIAL, ignored (may be NULL) for
+ * PBT_MOLECULE and PBT_STERN.  Writes the new surface id.  Rejects
+ * non-finite coordinates, indices out of range and panels of area < 1e-12
+ * A^2.  Not allowed after a solve has prepared the geometry (PBT_E_STATE). */
 pbt_status pbt_add_surface(pbt_ctx* ctx, pbt_kind kind, const double* xyz, int64_t nv,
                            const int32_t* tri, int64_t nt, const double* bc, int32_t* id);
 
@@ -134,6 +135,21 @@ pbt_status pbt_set_bc(pbt_ctx* ctx, int32_t id, const double* bc);
  * Allowed at any time; nq may be 0. */
 pbt_status pbt_set_charges(pbt_ctx* ctx, int32_t mol_id, double eps_in, const double* xyz,
                            const double* q, int64_t nq);
+
+/* Stern layer (the extra interfaces of Section 2's closing remarks): the
+ * PBT_STERN surface `stern_id` encloses molecule `mol_id` and bounds a
+ * salt-free layer of permittivity eps_layer between the molecule and the
+ * ionic solvent.  In the layer the potential obeys the Laplace equation;
+ * its Green's representation gives the molecule's outside row (Laplace
+ * kernel, the molecule's psi scaled by eps_in / eps_layer, the Stern
+ * surface seen from inside) and the Stern surface's inside row; the Stern
+ * surface's outside row is the solvent's (Yukawa).  The Stern surface
+ * carries phi and dphi/dn (layer side), like a molecule.  One Stern surface
+ * per molecule; both must be enabled together in a solve (PBT_E_STATE
+ * otherwise).  pbt_matvec with transpose = 1, pbt_gradient and
+ * pbt_solve_batch do not take Stern surfaces (PBT_E_INVALID).  Before the
+ * geometry is frozen (PBT_E_STATE after). */
+pbt_status pbt_set_stern(pbt_ctx* ctx, int32_t stern_id, int32_t mol_id, double eps_layer);
 
 /* Includes (on = 1) or excludes a surface from subsequent solves; excluded
  * surfaces are absent from the unknown layout.  Used for the isolated-body
@@ -156,14 +172,17 @@ pbt_status pbt_num_unknowns(pbt_ctx* ctx, int64_t* n);
 pbt_status pbt_solve(pbt_ctx* ctx, const double* x0, pbt_result* res);
 
 /* Solution of the last solve for surface `id`, in the caller's triangle
- * order: phi (nt) and dphi/dn (nt; interior side for molecules, solvent side
- * otherwise), reduced units.  Either pointer may be NULL. */
+ * order: phi (nt) and dphi/dn (nt; interior side for molecules and Stern
+ * surfaces, solvent side otherwise), reduced units.  Either pointer may be
+ * NULL. */
 pbt_status pbt_get_solution(pbt_ctx* ctx, int32_t id, double* phi, double* dphidn);
 
 /* Interaction free energy (eq. interaction_energy): one solve with every
- * surface enabled and one per surface alone.  parts (may be NULL) receives
- * 1 + n_surfaces results: the assembly, then each isolated surface in id
- * order.  Restores the enable flags afterwards. */
+ * surface enabled and one per component alone (a molecule together with
+ * its Stern surface; each other surface by itself).  parts (may be NULL)
+ * receives 1 + n_surfaces results: the assembly, then each isolated
+ * component at its surface id (a Stern surface's entry stays zero).
+ * Restores the enable flags afterwards. */
 pbt_status pbt_interaction_energy(pbt_ctx* ctx, double* F_int, pbt_result* parts);
 
 /* y = A x for the enabled system (eq. matrix_phi / matrix_dphi generalised

@@ -178,8 +178,15 @@ __device__ __forceinline__ void p2p_task_pair_f(const Task* __restrict__ tp, Src
     yy += __shfl_xor(yy, 16, 32);
   }
   if (grp == 0 && tl < t.tcount) {
-    partial[2 * ((int64_t)t.slot * 32 + tl) + 0] = l;
-    partial[2 * ((int64_t)t.slot * 32 + tl) + 1] = yy;
+    T o0 = l, o1 = yy;
+    if (t.form & kFormDropOut) o1 = T(0);
+    if (t.form & kFormSwap) {
+      const T sw = o0;
+      o0 = o1;
+      o1 = sw;
+    }
+    partial[2 * ((int64_t)t.slot * 32 + tl) + 0] = o0;
+    partial[2 * ((int64_t)t.slot * 32 + tl) + 1] = o1;
   }
 }
 
@@ -196,6 +203,9 @@ template <typename T, bool GUARD>
 __device__ __forceinline__ void p2p_task_pair(const Task* __restrict__ tp, SrcRec<T>* tile,
                                               const int32_t* __restrict__ ranges, const T* __restrict__ tgt,
                                               const T* __restrict__ src, T kappa, T* __restrict__ partial) {
+  // both halves agree on fused, split and kFormKz (an outside sum inside a
+  // salt-free layer takes kappa = 0)
+  if (tp[0].form & kFormKz) kappa = T(0);
   const int kind = (tp[0].fused ? 1 : 0) | (kappa == T(0) ? 2 : 0), split = tp[0].split;
   switch (kind) {
     case 0: p2p_task_pair_k<T, GUARD, 0>(split, tp, tile, ranges, tgt, src, kappa, partial); break;

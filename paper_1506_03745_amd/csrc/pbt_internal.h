@@ -43,9 +43,19 @@ struct Task {
   double rho_inv;
   int32_t split;   // P2P: 1, 2 or 4 lane groups share the half's targets (tcount <= 32 / split),
                    // each taking every split-th source; both halves of a wavefront agree
-  int32_t known;   // 1: the sources lie on a charged or potential surface (the only sources
+  int16_t known;   // 1: the sources lie on a charged or potential surface (the only sources
                    // with known densities, which the right-hand side sums over)
+  int16_t form;    // kForm* bits: how the two sums map to the two rows (Stern layers)
 };
+
+// Task::form bits.  A target row gets a source surface's sum in one of three
+// forms: as seen from inside the surface (the Laplace sum of the interior
+// row), as seen from outside it with the Yukawa kernel, or as seen from
+// outside with the Laplace kernel (inside a salt-free Stern layer).  The
+// task computes its usual pair (Laplace sum, outside sum); kFormKz takes
+// kappa = 0 for the outside sum, kFormDropOut discards it, and kFormSwap
+// stores the pair in the opposite rows (outside sum to the interior row).
+constexpr int kFormKz = 1, kFormSwap = 2, kFormDropOut = 4;
 
 // Per 64-target chunk: its M2P slots [sbeg, send) (64 lanes each) and, per
 // half (targets 0..31 and 32..63), its P2P slots [hbeg, hend) (32 lanes).
@@ -99,7 +109,7 @@ void launch_near_values(int64_t nt, const double* tx, const int32_t* tgt_self, c
                         const double* area, const NearParams& p, double* vals, hipStream_t s);
 // tgt_surf null: every target belongs to surface tsurf.
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
-                      const int32_t* panel_surf, const int32_t* surf_mol, const double* surf_rhoinv,
+                      const int32_t* panel_surf, const uint8_t* forms, int nsurf, const double* surf_rhoinv,
                       double* vals, hipStream_t s, int32_t tsurf = 0);
 void launch_reac(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
                  double rho_inv, const int64_t* near_ptr, const int32_t* near_col,

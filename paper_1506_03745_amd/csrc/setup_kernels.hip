@@ -243,23 +243,34 @@ __global__ void k_coulomb_rhs(int64_t n, const double* __restrict__ tx, const in
   b[rows[i]] = s * kInv4Pi * inv_eps;
 }
 
-// Fold the per-row factors into the corrections: the interior (Laplace) row
-// only sees panels of its own molecule, with factors -(eps_out/eps_s) on the
-// single layer and -1 on the double layer; the solvent row sees every panel.
+// Fold the per-row factors into the corrections.  forms[t * nsurf + s]
+// says in which form target surface t's two rows (bits 0-1: interior row,
+// bits 2-3: outside row) see source surface s: 0 not at all, 1 from inside
+// (Laplace, factors -(eps_outside/eps_s) on the single layer and -1 on the
+// double layer), 2 from outside with the Yukawa kernel (the raw Yukawa
+// values), 3 from outside with the Laplace kernel (the raw Laplace values).
+// Without Stern layers the interior row sees its own molecule from inside
+// and the outside row sees every surface with the Yukawa kernel.
+__device__ __forceinline__ void fold_pair(int f, double vl, double kl, double vy, double ky, double rhoinv,
+                                          double* a) {
+  a[0] = f == 1 ? -rhoinv * vl : f == 2 ? vy : f == 3 ? vl : 0.0;
+  a[1] = f == 1 ? -kl : f == 2 ? ky : f == 3 ? kl : 0.0;
+}
+
 __global__ void k_fold_near(int64_t nt, const int64_t* __restrict__ rowptr,
                             const int32_t* __restrict__ col, const int32_t* __restrict__ tgt_surf, int32_t tsurf,
-                            const int32_t* __restrict__ panel_surf,
-                            const int32_t* __restrict__ surf_mol,
+                            const int32_t* __restrict__ panel_surf, const uint8_t* __restrict__ forms, int nsurf,
                             const double* __restrict__ surf_rhoinv, double* vals) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nt) return;
   const int32_t t = tgt_surf ? tgt_surf[i] : tsurf;
   for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
     const int32_t s = panel_surf[col[e]];
-    const bool same = (s == t) && surf_mol[t];
+    const int f = forms[(int64_t)t * nsurf + s];
     double* v = vals + 4 * e;
-    v[0] = same ? -surf_rhoinv[s] * v[0] : 0.0;
-    v[1] = same ? -v[1] : 0.0;
+    const double vl = v[0], kl = v[1], vy = v[2], ky = v[3];
+    fold_pair(f & 3, vl, kl, vy, ky, surf_rhoinv[s], v);
+    fold_pair((f >> 2) & 3, vl, kl, vy, ky, surf_rhoinv[s], v + 2);
   }
 }
 
@@ -268,10 +279,10 @@ inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 }  // namespace
 
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
-                      const int32_t* panel_surf, const int32_t* surf_mol, const double* surf_rhoinv,
+                      const int32_t* panel_surf, const uint8_t* forms, int nsurf, const double* surf_rhoinv,
                       double* vals, hipStream_t s, int32_t tsurf) {
   if (nt <= 0) return;
-  k_fold_near<<<nblocks(nt, 256), 256, 0, s>>>(nt, rowptr, col, tgt_surf, tsurf, panel_surf, surf_mol,
+  k_fold_near<<<nblocks(nt, 256), 256, 0, s>>>(nt, rowptr, col, tgt_surf, tsurf, panel_surf, forms, nsurf,
                                                 surf_rhoinv, vals);
   PBT_HIP(hipGetLastError());
 }

@@ -49,8 +49,52 @@ System::~System() {
 
 int System::local_index(int surface_id) const { return surface_id; }
 
+// Regions and forms (Section 2's representation formula per region, with
+// the extra interfaces of a Stern layer: a salt-free layer of its own
+// permittivity between one molecule and the solvent).  The row of region R
+// on a surface sees the surface whose inside is R from inside and every
+// surface with R outside it from outside, with R's kernel.
+void System::build_regions() {
+  const int ns = (int)surfs_.size();
+  outer_.assign(ns, -1);
+  has_stern_ = false;
+  for (int e = 0; e < ns; ++e) {
+    const SurfIn& S = *surfs_[e];
+    if (S.kind != PBT_STERN) continue;
+    has_stern_ = true;
+    int par = -1;
+    for (int k = 0; k < ns; ++k)
+      if (surfs_[k] == S.stern_parent) par = k;
+    if (par < 0) throw Error(PBT_E_STATE, "a Stern surface is enabled without its molecule");
+    if (surfs_[par]->group != S.group) throw Error(PBT_E_STATE, "a Stern surface and its molecule in different groups");
+    if (outer_[par] >= 0) throw Error(PBT_E_STATE, "a molecule with two Stern surfaces");
+    outer_[par] = e;
+  }
+  eps_o_.assign(ns, eps_out_);
+  for (int e = 0; e < ns; ++e)
+    if (outer_[e] >= 0) eps_o_[e] = surfs_[outer_[e]]->eps_in;
+  // forms: the interior row of t is the region t; its outside row the region
+  // outer_[t] (-1: the solvent, Yukawa; a Stern surface's layer: Laplace)
+  h_forms_.assign((size_t)ns * ns, 0);
+  // (the solvent's form is the Yukawa one also when kappa = 0: the kernels
+  // then take their kappa = 0 path themselves)
+  auto seen = [&](int R, int src) -> int {
+    if (R >= 0 && R == src) return 1;          // R is the inside of src
+    if (outer_[src] == R) return R < 0 ? 2 : 3;  // src seen from outside
+    return 0;
+  };
+  for (int t = 0; t < ns; ++t)
+    for (int src = 0; src < ns; ++src) {
+      if (surfs_[t]->group != surfs_[src]->group) continue;
+      const int fi = two_rows(t) ? seen(t, src) : 0;
+      const int fo = seen(outer_[t], src);
+      h_forms_[(size_t)t * ns + src] = (uint8_t)(fi | (fo << 2));
+    }
+}
+
 void System::build(hipStream_t s) {
   const int ns = (int)surfs_.size();
+  build_regions();
   // ---- offsets, trees ------------------------------------------------------
   poff_.assign(ns + 1, 0);
   col_off_.assign(ns + 1, 0);
@@ -58,7 +102,7 @@ void System::build(hipStream_t s) {
   trees_.resize(ns);
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
-    const int64_t w = S.kind == PBT_MOLECULE ? 2 * S.nt : S.nt;
+    const int64_t w = two_rows(e) ? 2 * S.nt : S.nt;
     poff_[e + 1] = poff_[e] + S.nt;
     col_off_[e + 1] = col_off_[e] + w;
     row_off_[e + 1] = row_off_[e] + w;
@@ -99,11 +143,12 @@ void System::build(hipStream_t s) {
       psurf[g] = e;
       switch (S.kind) {
         case PBT_MOLECULE:
+        case PBT_STERN:
           col_phi[g] = (int32_t)(col_off_[e] + li);
           col_psi[g] = (int32_t)(col_off_[e] + S.nt + li);
           row_int[g] = (int32_t)(row_off_[e] + li);
           row_sol[g] = (int32_t)(row_off_[e] + S.nt + li);
-          dscale[g] = S.eps_in / eps_out_;
+          dscale[g] = S.eps_in / eps_o_[e];
           break;
         case PBT_CHARGED:
           col_phi[g] = (int32_t)(col_off_[e] + li);
@@ -145,18 +190,19 @@ void System::build(hipStream_t s) {
   {
     std::vector<double> rl(np_, 0.0);
     for (int64_t g = 0; g < np_; ++g)
-      if (surfs_[psurf[g]]->kind == PBT_MOLECULE) rl[g] = -eps_out_ / surfs_[psurf[g]]->eps_in;
+      if (two_rows(psurf[g])) rl[g] = -eps_o_[psurf[g]] / surfs_[psurf[g]]->eps_in;
     rlap_.upload(rl, s);
   }
   panel_surf_.upload(psurf, s);
   std::vector<int32_t> smol(ns);
   std::vector<double> srho(ns);
   for (int e = 0; e < ns; ++e) {
-    smol[e] = surfs_[e]->kind == PBT_MOLECULE;
-    srho[e] = smol[e] ? eps_out_ / surfs_[e]->eps_in : 0.0;
+    smol[e] = two_rows(e);
+    srho[e] = smol[e] ? eps_o_[e] / surfs_[e]->eps_in : 0.0;
   }
   surf_mol_.upload(smol, s);
   surf_rhoinv_.upload(srho, s);
+  forms_.upload(h_forms_, s);
 
   // ---- geometry and sources on the device ------------------------------------
   cen_.alloc(3 * np_);
@@ -207,7 +253,7 @@ void System::build(hipStream_t s) {
         const TreeBox& b = T.boxes[bi];
         const int g = (int)(boff_[e] + bi);
         for (int d = 0; d < 3; ++d) bc[3 * g + d] = b.c[d];
-        brho[g] = surfs_[e]->kind == PBT_MOLECULE ? eps_out_ / surfs_[e]->eps_in : 0.0;
+        brho[g] = two_rows(e) ? eps_o_[e] / surfs_[e]->eps_in : 0.0;
         sb[g] = (int32_t)((poff_[e] + b.pbeg) * K_);
         se[g] = (int32_t)((poff_[e] + b.pend) * K_);
         cb[g] = (int32_t)cl.size();
@@ -302,7 +348,7 @@ void System::build(hipStream_t s) {
     NearParams np{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
     launch_near_values(np_, cen_.p, dself.p, near_.ptr.p, near_.col.p, tri9_.p, nrm_.p, area_.p, np,
                        near_.val.p, s);
-    launch_fold_near(np_, near_.ptr.p, near_.col.p, panel_surf_.p, panel_surf_.p, surf_mol_.p,
+    launch_fold_near(np_, near_.ptr.p, near_.col.p, panel_surf_.p, panel_surf_.p, forms_.p, ns,
                      surf_rhoinv_.p, near_.val.p, s);
     near_.val32.alloc(near_.val.n);
     launch_to_f32((int64_t)near_.val.n, near_.val.p, near_.val32.p, s);
@@ -321,7 +367,7 @@ void System::build(hipStream_t s) {
     std::vector<int32_t> sb = bsbeg_.download(s), se = bsend_.download(s);
     std::vector<char> known_box(nbox_, 0);
     for (int e = 0; e < ns; ++e)
-      for (int64_t b = boff_[e]; b < boff_[e + 1]; ++b) known_box[b] = surfs_[e]->kind != PBT_MOLECULE;
+      for (int64_t b = boff_[e]; b < boff_[e + 1]; ++b) known_box[b] = !two_rows(e);
     for (int b = 0; b < nbox_; ++b) {
       if (!used[b] || se[b] <= sb[b]) continue;
       const int32_t n = se[b] - sb[b];
@@ -476,6 +522,9 @@ void System::build_plan() {
     lm2p_[li].resize(gsf.size());
     for (size_t k2 = 0; k2 < gsf.size(); ++k2) {
       const int e2 = gsf[k2];
+      const int f = form(leaves[li].e, e2);
+      if (f == 0) continue;   // neither row of the leaf's surface sees e2
+      const bool fused_pair = (f & 3) != 0 && (f >> 2) != 0;
       std::vector<int> pb, mb;
       if (prm_.treecode) interaction_lists(trees_[e2], tl, prm_.theta, pb, mb);
       else pb.push_back(0);
@@ -490,7 +539,7 @@ void System::build_plan() {
         else o.rng.push_back({j0, j1});
         c[0] += (int64_t)(j1 - j0) * ((nt + 63) / 64);
         c[2] += (int64_t)(j1 - j0) * nt;
-        if (e2 == leaves[li].e && surfs_[e2]->kind == PBT_MOLECULE) c[4] += (int64_t)(j1 - j0) * nt;
+        if (fused_pair) c[4] += (int64_t)(j1 - j0) * nt;
       }
       for (int b : mb) o.box.push_back((int32_t)(boff_[e2] + b));
       c[1] += (int64_t)mb.size() * ((nt + 63) / 64);
@@ -595,7 +644,7 @@ void System::build_plan() {
   std::vector<Task> spare;
   for (size_t li = 0; li < leaves.size(); ++li) {
     const int e = leaves[li].e;
-    const bool mol = surfs_[e]->kind == PBT_MOLECULE;
+    const bool mol = two_rows(e);
     const int c0 = leaf_chunk0[li];
     const int nchunk = (li + 1 < leaves.size() ? leaf_chunk0[li + 1] : (int)P.chunks.size()) - c0;
     int mi = 0, pi = 0;
@@ -604,9 +653,20 @@ void System::build_plan() {
       Task t{};
       t.lbeg = sg.lbeg;
       t.lend = sg.lend;
-      t.fused = (mol && sg.e2 == e) ? 1 : 0;
-      t.known = surfs_[sg.e2]->kind != PBT_MOLECULE ? 1 : 0;
-      t.rho_inv = mol ? eps_out_ / surfs_[e]->eps_in : 0.0;
+      // the rows' forms of the source surface: (inside, Yukawa) is the usual
+      // fused pair; the others occur with Stern layers
+      const int f = form(e, sg.e2), fi = f & 3, fo = f >> 2;
+      t.fused = fi == 1 ? 1 : 0;
+      t.form = 0;
+      if (fi == 1 && fo == 3) t.form = kFormKz;                            // molecule in its layer
+      else if (fi == 0 && fo == 1) {                                       // its Stern surface, from inside
+        t.fused = 1;
+        t.form = kFormKz | kFormDropOut | kFormSwap;
+      } else if (fi == 3 && fo == 0) t.form = kFormKz | kFormSwap;         // the molecule inside, from outside
+      else if (!((fi == 1 && fo == 2) || (fi == 0 && fo == 2)))
+        throw Error(PBT_E_STATE, "unsupported arrangement of surfaces");
+      t.known = two_rows(sg.e2) ? 0 : 1;
+      t.rho_inv = mol ? eps_o_[e] / surfs_[e]->eps_in : 0.0;
       t.rho_inv_f = (float)t.rho_inv;
       if (sg.m2p) {
         for (int c = 0; c < nchunk; ++c) {
@@ -645,14 +705,17 @@ void System::build_plan() {
   // A half of at most 8 (16) targets has its lanes in 4 (2) groups that split
   // the sources; halves are paired with halves of the same kind and split.
   for (Task& t : spare) t.split = t.tcount <= 8 ? 4 : t.tcount <= 16 ? 2 : 1;
-  std::stable_sort(spare.begin(), spare.end(), [](const Task& a, const Task& b) {
+  auto kz = [](const Task& t) { return (t.form & kFormKz) ? 1 : 0; };
+  std::stable_sort(spare.begin(), spare.end(), [&](const Task& a, const Task& b) {
     if (a.fused != b.fused) return a.fused < b.fused;
+    if (kz(a) != kz(b)) return kz(a) < kz(b);
     if (a.split != b.split) return a.split < b.split;
     return a.nsrc > b.nsrc;
   });
   for (size_t k = 0; k < spare.size();) {
     P.p2p.push_back(spare[k]);
-    if (k + 1 < spare.size() && spare[k + 1].fused == spare[k].fused && spare[k + 1].split == spare[k].split) {
+    if (k + 1 < spare.size() && spare[k + 1].fused == spare[k].fused && kz(spare[k + 1]) == kz(spare[k]) &&
+        spare[k + 1].split == spare[k].split) {
       P.p2p.push_back(spare[k + 1]);
       k += 2;
     } else {
@@ -1274,6 +1337,7 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
   bool surf_terms = false;
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
+    if (S.kind == PBT_STERN) continue;   // no charges, no imposed values
     if (S.kind != PBT_MOLECULE) {
       surf_terms = true;
       continue;
@@ -1281,7 +1345,7 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
     const int64_t nq = (int64_t)S.q.size();
     if (nq == 0) continue;
     ChargeData& d = charges(e, s);
-    launch_reac(nq, d.qx.p, poff_[e] * K_, (poff_[e] + S.nt) * K_, src64_.p, eps_out_ / S.eps_in, d.qn.ptr.p,
+    launch_reac(nq, d.qx.p, poff_[e] * K_, (poff_[e] + S.nt) * K_, src64_.p, eps_o_[e] / S.eps_in, d.qn.ptr.p,
                 d.qn.col.p, d.qn.val.p, sig_.p + poff_[e], mu_.p + poff_[e], d.phi.p, s);
     phi[e].resize(nq);
     PBT_HIP(hipMemcpyAsync(phi[e].data(), d.phi.p, nq * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1291,6 +1355,7 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
   PBT_HIP(hipStreamSynchronize(s));
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
+    if (S.kind == PBT_STERN) continue;
     if (S.kind == PBT_MOLECULE) {
       const int64_t nq = (int64_t)S.q.size();
       if (nq == 0) continue;
@@ -1352,6 +1417,7 @@ void System::unpack(const std::vector<double>& xh, int e, double* phi, double* d
     double p = 0, d = 0;
     switch (S.kind) {
       case PBT_MOLECULE:
+      case PBT_STERN:
         p = xh[col_off_[e] + li];
         d = xh[col_off_[e] + S.nt + li];
         break;

@@ -87,6 +87,7 @@ struct SurfIn {
   std::vector<double> qxyz, q;
   bool enabled = true;
   int group = 0;  // surfaces of different groups belong to independent systems
+  const SurfIn* stern_parent = nullptr;  // Stern surface: the molecule it encloses
 };
 
 struct NearCSR {
@@ -173,6 +174,9 @@ class System {
   void gradient_terms(const double* x, const double* lam, std::vector<std::vector<double>>& dq,
                       std::vector<std::vector<double>>& dsig, hipStream_t s);
   const SurfIn* surface(int e) const { return surfs_[e]; }
+  // Whether some enabled surface is a Stern layer (the transpose, gradient
+  // and batched paths do not take them).
+  bool has_stern() const { return has_stern_; }
 
   // Launch shape of the P2P / M2P tasks: Gauss points per P2P segment and
   // boxes per M2P segment (0 = size-based default).  Rebuilds the work lists.
@@ -249,6 +253,21 @@ class System {
   std::vector<const SurfIn*> surfs_;
   pbt_params prm_;
   double eps_out_, kappa_;
+  // Regions: every surface separates the region inside it from the one
+  // outside, which is the solvent or the salt-free layer of the Stern
+  // surface enclosing it (outer_[e] = that surface, or -1); eps_o_[e] is the
+  // outside region's permittivity.  forms_[t * ns + s]: how the rows of
+  // surface t see surface s (bits 0-1 interior row, 2-3 outside row; 0 not
+  // at all, 1 from inside, 2 from outside with the Yukawa kernel, 3 from
+  // outside with the Laplace kernel).
+  std::vector<int> outer_;
+  std::vector<double> eps_o_;
+  std::vector<uint8_t> h_forms_;
+  DBuf<uint8_t> forms_;
+  bool has_stern_ = false;
+  bool two_rows(int e) const { return surfs_[e]->kind == PBT_MOLECULE || surfs_[e]->kind == PBT_STERN; }
+  int form(int t, int s) const { return h_forms_[(size_t)t * surfs_.size() + s]; }
+  void build_regions();
   int K_ = 3;
   int64_t n_ = 0, np_ = 0, ns_ = 0;
   std::vector<int64_t> poff_, col_off_, row_off_;

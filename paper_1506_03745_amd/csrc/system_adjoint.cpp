@@ -36,8 +36,8 @@ void System::charge_near(int e, const double* qx, int64_t nq, NearCSR& qn, hipSt
   launch_near_values(nq, qx, nullptr, qn.ptr.p, qn.col.p, tri9_.p + 9 * p0, nrm_.p + 3 * p0,
                      area_.p + p0, npr, qn.val.p, s);
   // the charges count as targets of surface e (columns are local to its panels)
-  launch_fold_near(nq, qn.ptr.p, qn.col.p, nullptr, panel_surf_.p + p0, surf_mol_.p, surf_rhoinv_.p, qn.val.p, s,
-                   e);
+  launch_fold_near(nq, qn.ptr.p, qn.col.p, nullptr, panel_surf_.p + p0, forms_.p, (int)surfs_.size(),
+                   surf_rhoinv_.p, qn.val.p, s, e);
   PBT_HIP(hipStreamSynchronize(s));
 }
 
@@ -47,7 +47,7 @@ std::vector<double> System::reaction_potential(int e, hipStream_t s) {
   if (nq == 0) return {};
   const int64_t p0 = poff_[e];
   ChargeData& d = charges(e, s);
-  launch_reac(nq, d.qx.p, p0 * K_, (p0 + S.nt) * K_, src64_.p, eps_out_ / S.eps_in, d.qn.ptr.p, d.qn.col.p,
+  launch_reac(nq, d.qx.p, p0 * K_, (p0 + S.nt) * K_, src64_.p, eps_o_[e] / S.eps_in, d.qn.ptr.p, d.qn.col.p,
               d.qn.val.p, sig_.p + p0, mu_.p + p0, d.phi.p, s);
   return d.phi.download(s);
 }
@@ -58,6 +58,7 @@ std::vector<double> System::reaction_potential(int e, hipStream_t s) {
 // by box, the near corrections re-indexed by source panel, and the M2M^T
 // schedule (levels from the root down).
 void System::build_tplan(hipStream_t s) {
+  if (has_stern_) throw Error(PBT_E_INVALID, "the transposed operator does not take Stern surfaces");
   if (tplan_ready_) return;
   const int ns = (int)surfs_.size();
   // (surface, source leaf) -> target ranges (g0, g1, fused)
@@ -286,6 +287,7 @@ void System::matvec_t(const double* lam, double* z, bool fp32, double* sigbar, h
 }
 
 void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
+  if (has_stern_) throw Error(PBT_E_INVALID, "the adjoint does not take Stern surfaces");
   const int ns = (int)surfs_.size();
   PBT_HIP(hipMemsetAsync(g, 0, n_ * sizeof(double), s));
   PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
@@ -343,6 +345,7 @@ void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
 
 void System::gradient_terms(const double* x, const double* lam, std::vector<std::vector<double>>& dq,
                             std::vector<std::vector<double>>& dsig, hipStream_t s) {
+  if (has_stern_) throw Error(PBT_E_INVALID, "the adjoint does not take Stern surfaces");
   const int ns = (int)surfs_.size();
   dq.assign(ns, {});
   dsig.assign(ns, {});

@@ -337,6 +337,9 @@ __device__ __forceinline__ void m2p_task(const Task& task, const int32_t* __rest
   const int tbeg = task.tbeg, tcount = task.tcount;
   const int lbeg = task.lbeg, lend = task.lend;
   const int fused = task.fused;
+  // an outside sum inside a salt-free Stern layer: kappa = 0 (the Yukawa
+  // recurrence then reduces to the Laplace one)
+  if (task.form & kFormKz) kappa = T(0);
   const int ti = tbeg + (lane < tcount ? lane : 0);
   const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
   T l = 0, yy = 0;
@@ -353,8 +356,15 @@ __device__ __forceinline__ void m2p_task(const Task& task, const int32_t* __rest
     if (fused) l += taylor_dot<T, P, false>(Rx, Ry, Rz, kappa, M + NC);
   }
   if (lane < tcount) {
-    partial[2 * ((int64_t)task.slot * 64 + lane) + 0] = l;
-    partial[2 * ((int64_t)task.slot * 64 + lane) + 1] = yy;
+    T o0 = l, o1 = yy;
+    if (task.form & kFormDropOut) o1 = T(0);
+    if (task.form & kFormSwap) {
+      const T sw = o0;
+      o0 = o1;
+      o1 = sw;
+    }
+    partial[2 * ((int64_t)task.slot * 64 + lane) + 0] = o0;
+    partial[2 * ((int64_t)task.slot * 64 + lane) + 1] = o1;
   }
 }
 

@@ -2,7 +2,7 @@
 import numpy as np
 
 from workloads.meshes import box_plate, icosphere
-from workloads.problems import CHARGED, MOLECULE, POTENTIAL, Problem, Surface, config_problem
+from workloads.problems import CHARGED, MOLECULE, POTENTIAL, STERN, Problem, Surface, config_problem
 
 
 def sphere_plate(gap=1.0, kappa=0.125):
@@ -31,6 +31,24 @@ def three_body(kappa=0.1):
     return Problem([m1, m2, ps], 80.0, kappa, {}, "three_body")
 
 
+def stern_plate(kappa=0.125):
+    """Molecule sphere (r = 3 A, two charges) in a thin Stern shell (r = 3.6
+    A, layer permittivity 20) 0.9 A above a charged box: the molecule and its
+    Stern surface, and the Stern surface and the box, are within each other's
+    2L, so near corrections of every channel are exercised; 320 + 320 + 384
+    panels."""
+    c = (0.0, 0.0, 4.5)
+    v, t = icosphere(2, 3.0, c)
+    qpos = np.array([c, [0.8, -0.5, 4.9]])
+    mol = Surface(MOLECULE, v, t, eps_in=2.0, q_pos=qpos, q=np.array([1.0, -0.5]))
+    sv, st = icosphere(2, 3.6, c)
+    stern = Surface(STERN, sv, st, eps_in=20.0, parent=0)
+    rng = np.random.default_rng(12)
+    pv, pt = box_plate(-6, 6, -6, 6, -2, 0, 8, 8, 2)
+    pl = Surface(CHARGED, pv, pt, bc=-0.05 * (1 + 0.2 * rng.uniform(-1, 1, len(pt))))
+    return Problem([mol, stern, pl], 80.0, kappa, {}, "stern_plate")
+
+
 def case(name):
     if name == "kirkwood_l1":
         return config_problem("kirkwood", level=1)
@@ -48,8 +66,17 @@ def case(name):
         return three_body()
     if name == "three_body_k0":
         return three_body(kappa=0.0)
+    if name == "kirkwood_stern_l1":
+        return config_problem("kirkwood_stern", level=1)
+    if name == "kirkwood_stern_l2":
+        return config_problem("kirkwood_stern", level=2)
+    if name == "stern_plate":
+        return stern_plate()
+    if name == "stern_plate_k0":
+        return stern_plate(kappa=0.0)
     raise KeyError(name)
 
 
 SMALL_CASES = ["kirkwood_l1", "kirkwood_l2", "twosphere_charge_l2", "twosphere_potential_l2",
-               "sphere_plate", "sphere_plate_k0", "three_body", "three_body_k0"]
+               "sphere_plate", "sphere_plate_k0", "three_body", "three_body_k0",
+               "kirkwood_stern_l1", "stern_plate", "stern_plate_k0"]

@@ -175,6 +175,89 @@ def test_interaction_energy_salt_free_many_body():
     s2.close()
 
 
+def test_treecode_stern_layers():
+    """Stern layers: the molecule's outside row is the layer's Laplace
+    equation (the molecule seen from outside with kappa = 0, its Stern
+    surface seen from inside), the Stern surface's inside row the same
+    equation and its outside row the solvent's.  Treecode, FP64 and mixed,
+    salted and salt-free, against the oracle at the multi-surface bar; the
+    four far-field schedules agree bitwise."""
+    for name in ("stern_plate", "stern_plate_k0"):
+        A, _ = oracle_Ab(name)
+        x = rand_x(A.shape[0], 9)
+        ref = A @ x
+        s, _ = from_problem(case(name), treecode=1, ncrit=24, theta=0.4, taylor_p=8)
+        assert rel_inf(s.matvec(x), ref) < 2e-4, name
+        ys = []
+        for mode in range(4):
+            s.set_schedule(mode)
+            ys.append(s.matvec(x, prec=MIXED))
+        assert rel_inf(ys[0], ref) < 2e-4, name
+        for y in ys[1:]:
+            assert np.array_equal(y, ys[0]), name
+        s.close()
+
+
+def test_stern_energies_and_interaction():
+    """Energies of Stern systems against the oracle's dense LU (FP64 direct to
+    1e-8, mixed treecode to 1e-4), and the interaction energy with a molecule
+    and its Stern surface isolated together."""
+    for name in ("kirkwood_stern_l2", "stern_plate"):
+        pr = case(name)
+        e, _, _ = solve_problem(pr)
+        s, _ = from_problem(pr, treecode=0, tol=1e-11)
+        r = s.solve()
+        for a, b in ((r.F_solv, e.F_solv), (r.F_surf, e.F_surf), (r.F_coul, e.F_coul)):
+            assert abs(a - b) <= 1e-8 * max(abs(b), 1e-12) + 1e-14, (name, a, b)
+        s.close()
+    pr = case("stern_plate")
+    f_or, e_all, _ = interaction_energy(pr)
+    scale = abs(e_all.F_solv) + abs(e_all.F_surf)
+    s, _ = from_problem(pr, treecode=0, tol=1e-10)
+    f, res = s.interaction_energy(len(pr.surfaces))
+    assert abs(f - f_or) <= 1e-7 * scale
+    assert res[2].F_total == 0.0   # the Stern surface is no component of its own
+    s.close()
+    s2, _ = from_problem(pr, treecode=1, ncrit=24, theta=0.4, taylor_p=8, prec=MIXED, tol=1e-8)
+    f2, _ = s2.interaction_energy(len(pr.surfaces))
+    assert abs(f2 - f_or) <= 1e-4 * scale
+    s2.close()
+
+
+def test_kirkwood_stern_against_closed_form():
+    """A charge at the centre of a sphere inside a Stern shell (1280 + 1280
+    panels, mixed-precision treecode): F_solv within the first-order
+    discretisation error of the closed form (the oracle is 0.33 % off at
+    this mesh), which is 5.7 % away from the same sphere without the layer."""
+    from oracle import analytic
+    from oracle.units import energy_to_kcal
+    exact = energy_to_kcal(analytic.born_kirkwood_stern(1.0, 4.0, 6.0, 4.0, 20.0, 80.0, 0.125))
+    s, _ = from_problem(config_problem("kirkwood_stern", level=3), prec=MIXED, tol=1e-8)
+    r = s.solve()
+    assert abs(r.F_solv - exact) <= 5e-3 * abs(exact)
+    s.close()
+
+
+def test_stern_unsupported_paths():
+    """Paths without Stern-layer support refuse instead of computing
+    something else; a Stern surface cannot be solved without its molecule."""
+    pr = case("stern_plate")
+    s, ids = from_problem(pr, treecode=0)
+    n = s.num_unknowns()
+    with pytest.raises(PbtError, match="INVALID"):
+        s.matvec(np.ones(n), transpose=True)
+    with pytest.raises(PbtError, match="INVALID"):
+        s.gradient(ids[2], pr.surfaces[2].nt, ids[0], 2)
+    with pytest.raises(PbtError, match="INVALID"):
+        s.solve_batch(ids[0], np.eye(3)[None], np.zeros((1, 3)))
+    s.close()
+    s2, ids2 = from_problem(pr, treecode=0)
+    s2.enable(ids2[0], False)
+    with pytest.raises(PbtError, match="STATE"):
+        s2.solve()
+    s2.close()
+
+
 @pytest.mark.parametrize("name", ["kirkwood_l2", "twosphere_charge_l2", "twosphere_potential_l2",
                                   "sphere_plate", "three_body"])
 def test_fp64_solve_energies(name):
