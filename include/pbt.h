@@ -62,7 +62,7 @@ typedef enum {
 
 typedef enum { PBT_FP64 = 0, PBT_MIXED = 1 } pbt_precision;
 
-typedef enum { PBT_MOLECULE = 0, PBT_CHARGED = 1, PBT_POTENTIAL = 2, PBT_STERN = 3 } pbt_kind;
+typedef enum { PBT_MOLECULE = 0, PBT_CHARGED = 1, PBT_POTENTIAL = 2, PBT_STERN = 3, PBT_CAVITY = 4 } pbt_kind;
 
 /* Numerical parameters (Tables 1-3 of the paper list the same knobs). */
 typedef struct {
@@ -117,10 +117,11 @@ pbt_status pbt_set_solvent(pbt_ctx* ctx, double eps_out, double kappa_per_A);
 
 /* Adds a closed surface (eq. pde: Gamma_1 for a molecule, Gamma_2 for an
  * imposed-BC surface; PBT_STERN: the outer interface of an ion-exclusion
- * layer around one molecule, which pbt_set_stern names).  xyz: nv*3 doubles
- * (A); tri: nt*3 int32 vertex indices; bc: nt doubles, sigma0 [C/m^2] for
- * PBT_CHARGED, phi0 [V] for PBT_POTENTIAL, ignored (may be NULL) for
- * PBT_MOLECULE and PBT_STERN.  Writes the new surface id.  Rejects
+ * layer around one molecule, which pbt_set_stern names; PBT_CAVITY: the
+ * boundary of a solvent-filled cavity inside one molecule, which
+ * pbt_set_cavity names).  xyz: nv*3 doubles (A); tri: nt*3 int32 vertex
+ * indices; bc: nt doubles, sigma0 [C/m^2] for PBT_CHARGED, phi0 [V] for
+ * PBT_POTENTIAL, ignored (may be NULL) for the other kinds.  Writes the new surface id.  Rejects
  * non-finite coordinates, indices out of range and panels of area < 1e-12
  * A^2.  Not allowed after a solve has prepared the geometry (PBT_E_STATE). */
 pbt_status pbt_add_surface(pbt_ctx* ctx, pbt_kind kind, const double* xyz, int64_t nv,
@@ -151,6 +152,20 @@ pbt_status pbt_set_charges(pbt_ctx* ctx, int32_t mol_id, double eps_in, const do
  * geometry is frozen (PBT_E_STATE after). */
 pbt_status pbt_set_stern(pbt_ctx* ctx, int32_t stern_id, int32_t mol_id, double eps_layer);
 
+/* Solvent-filled cavity (the other nested interface of Section 2's closing
+ * remarks): the PBT_CAVITY surface `cav_id` lies inside molecule `mol_id`
+ * and encloses a salt-free, charge-free region of permittivity eps_cavity.
+ * The molecule's interior equation then holds on both its own surface and
+ * the cavity's (Laplace kernel, eps_in; the cavity seen from outside with
+ * its psi scaled by eps_cavity / eps_in, the molecule's charges on the
+ * right-hand side), and the cavity's inside row is the cavity's Laplace
+ * equation; the reaction potential at the charges includes the cavity's
+ * terms.  A molecule may hold several cavities; each must be enabled
+ * with its molecule (PBT_E_STATE otherwise).  Like Stern surfaces, not
+ * taken by the transpose, pbt_gradient or pbt_solve_batch (PBT_E_INVALID).
+ * Before the geometry is frozen (PBT_E_STATE after). */
+pbt_status pbt_set_cavity(pbt_ctx* ctx, int32_t cav_id, int32_t mol_id, double eps_cavity);
+
 /* Includes (on = 1) or excludes a surface from subsequent solves; excluded
  * surfaces are absent from the unknown layout.  Used for the isolated-body
  * solves of the interaction energy (eq. interaction_energy). */
@@ -172,16 +187,17 @@ pbt_status pbt_num_unknowns(pbt_ctx* ctx, int64_t* n);
 pbt_status pbt_solve(pbt_ctx* ctx, const double* x0, pbt_result* res);
 
 /* Solution of the last solve for surface `id`, in the caller's triangle
- * order: phi (nt) and dphi/dn (nt; interior side for molecules and Stern
- * surfaces, solvent side otherwise), reduced units.  Either pointer may be
+ * order: phi (nt) and dphi/dn (nt; interior side for molecules, Stern
+ * surfaces and cavities, solvent side otherwise), reduced units.  Either pointer may be
  * NULL. */
 pbt_status pbt_get_solution(pbt_ctx* ctx, int32_t id, double* phi, double* dphidn);
 
 /* Interaction free energy (eq. interaction_energy): one solve with every
  * surface enabled and one per component alone (a molecule together with
- * its Stern surface; each other surface by itself).  parts (may be NULL)
- * receives 1 + n_surfaces results: the assembly, then each isolated
- * component at its surface id (a Stern surface's entry stays zero).
+ * its Stern surface and cavities; each other surface by itself).  parts
+ * (may be NULL) receives 1 + n_surfaces results: the assembly, then each
+ * isolated component at its surface id (Stern and cavity entries stay
+ * zero).
  * Restores the enable flags afterwards. */
 pbt_status pbt_interaction_energy(pbt_ctx* ctx, double* F_int, pbt_result* parts);
 

@@ -59,8 +59,8 @@ import scipy.linalg
 from .integrals import Panels, layer_blocks
 from .units import FOUR_PI, energy_to_kcal, sigma_to_reduced, volts_to_reduced
 
-MOLECULE, CHARGED, POTENTIAL, STERN = 0, 1, 2, 3
-TWO_ROWS = (MOLECULE, STERN)
+MOLECULE, CHARGED, POTENTIAL, STERN, CAVITY = 0, 1, 2, 3, 4
+TWO_ROWS = (MOLECULE, STERN, CAVITY)
 SOLVENT = -1
 
 
@@ -93,10 +93,13 @@ class DenseBEM:
         # Stern surface that encloses it (the region inside surface k is k)
         self.outer = [SOLVENT] * len(surfs)
         for k, s in enumerate(surfs):
-            if s.kind == STERN:
+            if s.kind in (STERN, CAVITY):
                 par = getattr(s, "parent", -1)
                 if par not in new_index or surfs[new_index[par]].kind != MOLECULE:
-                    raise ValueError("a Stern surface needs its molecule in the same system")
+                    raise ValueError("a Stern surface or cavity needs its molecule in the same system")
+                if s.kind == CAVITY:
+                    self.outer[k] = new_index[par]
+                    continue
                 if self.outer[new_index[par]] != SOLVENT:
                     raise ValueError("one Stern surface per molecule")
                 self.outer[new_index[par]] = k
@@ -166,8 +169,10 @@ class DenseBEM:
             else:
                 A[:, cs:cs + ns] += v
                 b += k @ self.phi0[s]
-        if R == t and st.kind == MOLECULE:
-            b += self._coulomb_rhs(st, self.panels[t].centroid[idx])
+        if R != SOLVENT and self.surfs[R].kind == MOLECULE:
+            # the molecule's charges lie in its region, whichever of the
+            # region's boundaries (the molecule's or a cavity's) t is
+            b += self._coulomb_rhs(self.surfs[R], self.panels[t].centroid[idx])
         return A, b
 
     def row_block(self, t, rows=None):
@@ -246,18 +251,31 @@ class DenseBEM:
                 out.append((self.phi0[s], u[c:c + ss.nt]))
         return out
 
-    def reaction_potential(self, s, phi, psi):
-        """phi_reac at the charges of molecule s (eq. phi_reac_bem)."""
+    def reaction_potential(self, s, phi, psi, parts=None):
+        """phi_reac at the charges of molecule s (eq. phi_reac_bem): the
+        molecule's boundary seen from inside, and each cavity of it seen
+        from outside (Laplace kernel, psi scaled by eps_cavity / eps_in)."""
         ss = self.surfs[s]
         vl, kl, _, _ = layer_blocks(ss.q_pos, self.panels[s], self.kappa, self.k_far,
                                     self.k_near, self.k_self_edge, self_idx=None)
-        return -kl @ phi + vl @ psi
+        out = -kl @ phi + vl @ psi
+        cavities = [c for c, sc in enumerate(self.surfs) if sc.kind == CAVITY and self.outer[c] == s]
+        if cavities and parts is None:
+            raise ValueError("the cavities' densities are needed")
+        for c in cavities:
+            sc = self.surfs[c]
+            vc, kc, _, _ = layer_blocks(ss.q_pos, self.panels[c], self.kappa, self.k_far,
+                                        self.k_near, self.k_self_edge, self_idx=None)
+            pc, qc = parts[c]
+            out += kc @ pc - (sc.eps_in / ss.eps_in) * (vc @ qc)
+        return out
 
     def energies(self, u) -> Energies:
         fc = fs = fsurf = 0.0
-        for s, (ss, (phi, psi)) in enumerate(zip(self.surfs, self.split(u))):
+        parts = self.split(u)
+        for s, (ss, (phi, psi)) in enumerate(zip(self.surfs, parts)):
             if ss.kind == MOLECULE:
-                fs += 0.5 * np.dot(ss.q, self.reaction_potential(s, phi, psi))
+                fs += 0.5 * np.dot(ss.q, self.reaction_potential(s, phi, psi, parts))
                 fc += coulomb_energy(ss.q_pos, ss.q, ss.eps_in)
             elif ss.kind == CHARGED:
                 fsurf += 0.5 * np.sum(phi * self.sigma[s] * self.panels[s].area)
@@ -291,9 +309,10 @@ def components(problem):
     surfs = list(problem.surfaces)
     out = []
     for i, s in enumerate(surfs):
-        if s.kind == STERN:
+        if s.kind in (STERN, CAVITY):
             continue
-        out.append([j == i or (t.kind == STERN and getattr(t, "parent", -1) == i) for j, t in enumerate(surfs)])
+        out.append([j == i or (t.kind in (STERN, CAVITY) and getattr(t, "parent", -1) == i)
+                    for j, t in enumerate(surfs)])
     return out
 
 

@@ -3,8 +3,8 @@
 The work runs in libpbt.so (HIP kernels for gfx950 behind the C ABI of
 include/pbt.h); ``pbt`` is its ctypes binding and ``build`` compiles it.
 """
-from .pbt import (CHARGED, FP64, MIXED, MOLECULE, POTENTIAL, PbtError, Result, Solver, from_problem,
-                  lib, quadrature_rule)
+from .pbt import (CAVITY, CHARGED, FP64, MIXED, MOLECULE, POTENTIAL, STERN, PbtError, Result, Solver,
+                  from_problem, lib, quadrature_rule)
 
 __all__ = ["Solver", "from_problem", "lib", "quadrature_rule", "PbtError", "Result",
-           "MOLECULE", "CHARGED", "POTENTIAL", "FP64", "MIXED"]
+           "MOLECULE", "CHARGED", "POTENTIAL", "STERN", "CAVITY", "FP64", "MIXED"]

@@ -130,7 +130,8 @@ System& system_for(pbt_ctx* c) {
   for (const SurfIn* s : on)
     if (s->kind == PBT_MOLECULE && !(s->eps_in > 0)) throw Error(PBT_E_STATE, "molecule without eps_in");
   for (const SurfIn* s : on)
-    if (s->kind == PBT_STERN && !s->stern_parent) throw Error(PBT_E_STATE, "Stern surface without its molecule");
+    if ((s->kind == PBT_STERN || s->kind == PBT_CAVITY) && !s->parent)
+      throw Error(PBT_E_STATE, "Stern surface or cavity without its molecule");
   c->frozen = true;
   const double t0 = wall_now();
   auto sys = std::make_unique<System>(on, c->prm, c->eps_out, c->kappa, c->stream);
@@ -265,7 +266,8 @@ pbt_status pbt_add_surface(pbt_ctx* c, pbt_kind kind, const double* xyz, int64_t
                            const int32_t* tri, int64_t nt, const double* bc, int32_t* id) {
   if (!c) return PBT_E_INVALID;
   if (c->frozen) return fail(c, PBT_E_STATE, "geometry is frozen after the first solve");
-  if (kind != PBT_MOLECULE && kind != PBT_CHARGED && kind != PBT_POTENTIAL && kind != PBT_STERN)
+  if (kind != PBT_MOLECULE && kind != PBT_CHARGED && kind != PBT_POTENTIAL && kind != PBT_STERN &&
+      kind != PBT_CAVITY)
     return fail(c, PBT_E_INVALID, "unknown surface kind");
   if (!xyz || !tri || nv < 3 || nt < 1 || nt > (int64_t)1 << 28)
     return fail(c, PBT_E_INVALID, "empty or oversized mesh");
@@ -305,8 +307,8 @@ pbt_status pbt_set_bc(pbt_ctx* c, int32_t id, const double* bc) {
   if (!c) return PBT_E_INVALID;
   if (id < 0 || id >= (int)c->surfs.size() || !bc) return fail(c, PBT_E_INVALID, "bad surface id");
   SurfIn& s = *c->surfs[id];
-  if (s.kind == PBT_MOLECULE || s.kind == PBT_STERN)
-    return fail(c, PBT_E_INVALID, "molecules and Stern surfaces have no imposed boundary values");
+  if (s.kind != PBT_CHARGED && s.kind != PBT_POTENTIAL)
+    return fail(c, PBT_E_INVALID, "only charged and potential surfaces have imposed boundary values");
   for (int64_t t = 0; t < s.nt; ++t)
     if (!std::isfinite(bc[t])) return fail(c, PBT_E_INVALID, "non-finite boundary value");
   s.bc.assign(bc, bc + s.nt);
@@ -347,10 +349,24 @@ pbt_status pbt_set_stern(pbt_ctx* c, int32_t stern_id, int32_t mol_id, double ep
   if (!(eps_layer > 0) || !std::isfinite(eps_layer)) return fail(c, PBT_E_INVALID, "eps_layer must be > 0");
   if (c->frozen) return fail(c, PBT_E_STATE, "geometry is frozen after the first solve");
   for (int k = 0; k < ns; ++k)
-    if (k != stern_id && c->surfs[k]->stern_parent == c->surfs[mol_id].get())
+    if (k != stern_id && c->surfs[k]->kind == PBT_STERN && c->surfs[k]->parent == c->surfs[mol_id].get())
       return fail(c, PBT_E_INVALID, "the molecule already has a Stern surface");
-  c->surfs[stern_id]->stern_parent = c->surfs[mol_id].get();
+  c->surfs[stern_id]->parent = c->surfs[mol_id].get();
   c->surfs[stern_id]->eps_in = eps_layer;
+  return PBT_OK;
+}
+
+pbt_status pbt_set_cavity(pbt_ctx* c, int32_t cav_id, int32_t mol_id, double eps_cavity) {
+  if (!c) return PBT_E_INVALID;
+  const int ns = (int)c->surfs.size();
+  if (cav_id < 0 || cav_id >= ns || c->surfs[cav_id]->kind != PBT_CAVITY)
+    return fail(c, PBT_E_INVALID, "not a cavity id");
+  if (mol_id < 0 || mol_id >= ns || c->surfs[mol_id]->kind != PBT_MOLECULE)
+    return fail(c, PBT_E_INVALID, "not a molecule id");
+  if (!(eps_cavity > 0) || !std::isfinite(eps_cavity)) return fail(c, PBT_E_INVALID, "eps_cavity must be > 0");
+  if (c->frozen) return fail(c, PBT_E_STATE, "geometry is frozen after the first solve");
+  c->surfs[cav_id]->parent = c->surfs[mol_id].get();
+  c->surfs[cav_id]->eps_in = eps_cavity;
   return PBT_OK;
 }
 
@@ -372,7 +388,7 @@ pbt_status pbt_num_unknowns(pbt_ctx* c, int64_t* n) {
   if (!c || !n) return fail(c, PBT_E_INVALID, "null argument");
   int64_t k = 0;
   for (auto& s : c->surfs)
-    if (s->enabled) k += (s->kind == PBT_MOLECULE || s->kind == PBT_STERN) ? 2 * s->nt : s->nt;
+    if (s->enabled) k += (s->kind == PBT_CHARGED || s->kind == PBT_POTENTIAL) ? s->nt : 2 * s->nt;
   *n = k;
   return PBT_OK;
 }
@@ -414,11 +430,11 @@ pbt_status pbt_interaction_energy(pbt_ctx* c, double* F_int, pbt_result* parts) 
       if (st != PBT_OK && st != PBT_E_NOCONVERGE) { restore(); return st; }
       if (st != PBT_OK) worst = st;
       for (int k = 0; k < ns; ++k) {
-        // a molecule is isolated together with its Stern surface; a Stern
-        // surface is no component of its own (its entry stays zero)
-        if (c->surfs[k]->kind == PBT_STERN) continue;
+        // a molecule is isolated together with its Stern surface and
+        // cavities, which are no components of their own (entries stay zero)
+        if (c->surfs[k]->kind == PBT_STERN || c->surfs[k]->kind == PBT_CAVITY) continue;
         for (int i = 0; i < ns; ++i)
-          c->surfs[i]->enabled = i == k || c->surfs[i]->stern_parent == c->surfs[k].get();
+          c->surfs[i]->enabled = i == k || c->surfs[i]->parent == c->surfs[k].get();
         st = solve_impl(c, nullptr, &r[k + 1]);
         if (st != PBT_OK && st != PBT_E_NOCONVERGE) { restore(); return st; }
         if (st != PBT_OK) worst = st;
@@ -524,8 +540,8 @@ pbt_status pbt_gradient(pbt_ctx* c, int32_t sigma_id, double* dF_dsigma, int32_t
     if (mol_id >= 0 && (c->surfs[mol_id]->kind != PBT_MOLECULE || !dF_dq))
       return fail(c, PBT_E_INVALID, "mol_id must name a molecule (and dF_dq be given)");
     for (int i = 0; i < ns; ++i)
-      if (c->surfs[i]->kind == PBT_STERN)
-        return fail(c, PBT_E_INVALID, "the gradient does not take Stern surfaces");
+      if (c->surfs[i]->kind == PBT_STERN || c->surfs[i]->kind == PBT_CAVITY)
+        return fail(c, PBT_E_INVALID, "the gradient does not take Stern surfaces or cavities");
     std::vector<bool> saved = mask_of(c);
     auto set_mask = [&](int only) {
       for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = only < 0 ? true : i == only;
@@ -583,8 +599,8 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
     for (int64_t i = 0; i < 3LL * nb; ++i)
       if (!std::isfinite(shift[i])) return fail(c, PBT_E_INVALID, "non-finite shift");
     for (int i = 0; i < ns; ++i)
-      if (c->surfs[i]->kind == PBT_STERN && c->surfs[i]->enabled)
-        return fail(c, PBT_E_INVALID, "batched placements do not take Stern surfaces");
+      if ((c->surfs[i]->kind == PBT_STERN || c->surfs[i]->kind == PBT_CAVITY) && c->surfs[i]->enabled)
+        return fail(c, PBT_E_INVALID, "batched placements do not take Stern surfaces or cavities");
     if (nb == 0) return PBT_OK;
     std::vector<bool> saved = mask_of(c);
     auto restore = [&] { for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = saved[i]; };

@@ -258,7 +258,51 @@ __global__ __launch_bounds__(256) void k_reac(int64_t nq, const double* __restri
   if (threadIdx.x == 0) phi[k] = -(red[0] + red[1] + red[2] + red[3]);
 }
 
+// A cavity's part of the reaction potential at the charges of its molecule:
+// the cavity is seen from outside with the Laplace kernel (its sources'
+// single-layer strengths already carry eps_cavity / eps_in), i.e. minus the
+// outside-form sum sum_j (s_j / r + D_j . (x - y_j) / r^3) / (4 pi) plus its
+// near corrections, added to phi.  One block per charge.
+__global__ __launch_bounds__(256) void k_reac_cavity(int64_t nq, const double* __restrict__ qxyz, int64_t s0,
+                                                     int64_t s1, const double* __restrict__ src,
+                                                     const int64_t* __restrict__ near_ptr,
+                                                     const int32_t* __restrict__ near_col,
+                                                     const double* __restrict__ near_val,
+                                                     const double* __restrict__ sig,
+                                                     const double* __restrict__ mu, double* phi) {
+  __shared__ double red[4];
+  const int64_t k = blockIdx.x;
+  const double x = qxyz[3 * k], y = qxyz[3 * k + 1], z = qxyz[3 * k + 2];
+  double a1 = 0.0, a2 = 0.0;
+  for (int64_t j = s0 + threadIdx.x; j < s1; j += blockDim.x) {
+    const double* s = src + (int64_t)kSrcStride * j;
+    const double dx = x - s[0], dy = y - s[1], dz = z - s[2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double dd = s[4] * dx + s[5] * dy + s[6] * dz;
+    a1 += s[3] * rinv;
+    a2 += dd * rinv * rinv * rinv;
+  }
+  double l = (a1 + a2) * kInv4Pi;
+  for (int64_t e = near_ptr[k] + threadIdx.x; e < near_ptr[k + 1]; e += blockDim.x) {
+    const int32_t j = near_col[e];
+    l += near_val[4 * e] * sig[j] + near_val[4 * e + 1] * mu[j];
+  }
+  for (int o = 32; o > 0; o >>= 1) l += __shfl_down(l, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) phi[k] -= red[0] + red[1] + red[2] + red[3];
+}
+
 }  // namespace
+
+void launch_reac_cavity(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
+                        const int64_t* near_ptr, const int32_t* near_col, const double* near_val,
+                        const double* sig, const double* mu, double* phi, hipStream_t s) {
+  if (nq <= 0) return;
+  k_reac_cavity<<<(unsigned)nq, 256, 0, s>>>(nq, qxyz, s0, s1, src, near_ptr, near_col, near_val, sig, mu, phi);
+  PBT_HIP(hipGetLastError());
+}
 
 void launch_reac(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
                  double rho_inv, const int64_t* near_ptr, const int32_t* near_col,

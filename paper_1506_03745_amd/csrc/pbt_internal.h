@@ -111,6 +111,9 @@ void launch_near_values(int64_t nt, const double* tx, const int32_t* tgt_self, c
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
                       const int32_t* panel_surf, const uint8_t* forms, int nsurf, const double* surf_rhoinv,
                       double* vals, hipStream_t s, int32_t tsurf = 0);
+void launch_reac_cavity(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
+                        const int64_t* near_ptr, const int32_t* near_col, const double* near_val,
+                        const double* sig, const double* mu, double* phi, hipStream_t s);
 void launch_reac(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
                  double rho_inv, const int64_t* near_ptr, const int32_t* near_col,
                  const double* near_val, const double* sig, const double* mu, double* phi,

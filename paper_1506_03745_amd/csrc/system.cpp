@@ -57,16 +57,21 @@ int System::local_index(int surface_id) const { return surface_id; }
 void System::build_regions() {
   const int ns = (int)surfs_.size();
   outer_.assign(ns, -1);
-  has_stern_ = false;
+  has_nested_ = false;
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
-    if (S.kind != PBT_STERN) continue;
-    has_stern_ = true;
+    if (S.kind != PBT_STERN && S.kind != PBT_CAVITY) continue;
+    has_nested_ = true;
     int par = -1;
     for (int k = 0; k < ns; ++k)
-      if (surfs_[k] == S.stern_parent) par = k;
-    if (par < 0) throw Error(PBT_E_STATE, "a Stern surface is enabled without its molecule");
-    if (surfs_[par]->group != S.group) throw Error(PBT_E_STATE, "a Stern surface and its molecule in different groups");
+      if (surfs_[k] == S.parent) par = k;
+    if (par < 0) throw Error(PBT_E_STATE, "a Stern surface or cavity is enabled without its molecule");
+    if (surfs_[par]->group != S.group)
+      throw Error(PBT_E_STATE, "a Stern surface or cavity and its molecule in different groups");
+    if (S.kind == PBT_CAVITY) {
+      outer_[e] = par;   // the cavity lies in the molecule's interior
+      continue;
+    }
     if (outer_[par] >= 0) throw Error(PBT_E_STATE, "a molecule with two Stern surfaces");
     outer_[par] = e;
   }
@@ -74,7 +79,8 @@ void System::build_regions() {
   for (int e = 0; e < ns; ++e)
     if (outer_[e] >= 0) eps_o_[e] = surfs_[outer_[e]]->eps_in;
   // forms: the interior row of t is the region t; its outside row the region
-  // outer_[t] (-1: the solvent, Yukawa; a Stern surface's layer: Laplace)
+  // outer_[t] (-1: the solvent, Yukawa; a Stern surface's layer or a
+  // molecule's interior: Laplace)
   h_forms_.assign((size_t)ns * ns, 0);
   // (the solvent's form is the Yukawa one also when kappa = 0: the kernels
   // then take their kappa = 0 path themselves)
@@ -144,6 +150,7 @@ void System::build(hipStream_t s) {
       switch (S.kind) {
         case PBT_MOLECULE:
         case PBT_STERN:
+        case PBT_CAVITY:
           col_phi[g] = (int32_t)(col_off_[e] + li);
           col_psi[g] = (int32_t)(col_off_[e] + S.nt + li);
           row_int[g] = (int32_t)(row_off_[e] + li);
@@ -970,7 +977,16 @@ System::ChargeData& System::charges(int e, hipStream_t s) {
   d.qx.upload(S.qxyz, s);
   d.q.upload(S.q, s);
   d.phi.alloc(nq);
-  if (nq > 0) charge_near(e, d.qx.p, nq, d.qn, s);
+  if (nq > 0) charge_near(e, e, d.qx.p, nq, d.qn, s);
+  // near corrections of the charges against each cavity of the molecule
+  d.cav.clear();
+  d.cav_qn.clear();
+  for (int c = 0; c < (int)surfs_.size(); ++c)
+    if (surfs_[c]->kind == PBT_CAVITY && outer_[c] == e && nq > 0) {
+      d.cav.push_back(c);
+      d.cav_qn.push_back(std::make_unique<NearCSR>());
+      charge_near(c, e, d.qx.p, nq, *d.cav_qn.back(), s);
+    }
   double c = 0;
   for (int64_t k = 0; k < nq; ++k)
     for (int64_t l = k + 1; l < nq; ++l) {
@@ -994,13 +1010,18 @@ void System::rhs(double* b, hipStream_t s) {
   apply(false, false, nullptr, rhs_y_.p, s, false, false, false, nullptr, true);
   PBT_HIP(hipMemsetAsync(b, 0, n_ * sizeof(double), s));
   launch_rhs_solvent(np_, row_sol_.p, rhs_y_.p, known_half_.p, b, s);
-  // interior rows: Coulomb sum with 1/eps_in (eq. green_identity)
+  // rows of a molecule's interior (its own interior rows and its cavities'
+  // outside rows): Coulomb sum with 1/eps_in (eq. green_identity)
   for (int e = 0; e < (int)surfs_.size(); ++e) {
     const SurfIn& S = *surfs_[e];
     if (S.kind != PBT_MOLECULE || S.q.empty()) continue;
     ChargeData& d = charges(e, s);
     launch_coulomb_rhs(S.nt, cen_.p + 3 * poff_[e], row_int_.p + poff_[e], (int64_t)S.q.size(), d.qx.p,
                        d.q.p, 1.0 / S.eps_in, b, s);
+    for (int c = 0; c < (int)surfs_.size(); ++c)
+      if (surfs_[c]->kind == PBT_CAVITY && outer_[c] == e)
+        launch_coulomb_rhs(surfs_[c]->nt, cen_.p + 3 * poff_[c], row_sol_.p + poff_[c], (int64_t)S.q.size(),
+                           d.qx.p, d.q.p, 1.0 / S.eps_in, b, s);
   }
 }
 
@@ -1337,7 +1358,7 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
   bool surf_terms = false;
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
-    if (S.kind == PBT_STERN) continue;   // no charges, no imposed values
+    if (S.kind == PBT_STERN || S.kind == PBT_CAVITY) continue;   // no charges, no imposed values
     if (S.kind != PBT_MOLECULE) {
       surf_terms = true;
       continue;
@@ -1347,6 +1368,12 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
     ChargeData& d = charges(e, s);
     launch_reac(nq, d.qx.p, poff_[e] * K_, (poff_[e] + S.nt) * K_, src64_.p, eps_o_[e] / S.eps_in, d.qn.ptr.p,
                 d.qn.col.p, d.qn.val.p, sig_.p + poff_[e], mu_.p + poff_[e], d.phi.p, s);
+    for (size_t k = 0; k < d.cav.size(); ++k) {
+      const int c = d.cav[k];
+      const NearCSR& cq = *d.cav_qn[k];
+      launch_reac_cavity(nq, d.qx.p, poff_[c] * K_, (poff_[c] + surfs_[c]->nt) * K_, src64_.p, cq.ptr.p, cq.col.p,
+                         cq.val.p, sig_.p + poff_[c], mu_.p + poff_[c], d.phi.p, s);
+    }
     phi[e].resize(nq);
     PBT_HIP(hipMemcpyAsync(phi[e].data(), d.phi.p, nq * sizeof(double), hipMemcpyDeviceToHost, s));
   }
@@ -1355,7 +1382,7 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
   PBT_HIP(hipStreamSynchronize(s));
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
-    if (S.kind == PBT_STERN) continue;
+    if (S.kind == PBT_STERN || S.kind == PBT_CAVITY) continue;
     if (S.kind == PBT_MOLECULE) {
       const int64_t nq = (int64_t)S.q.size();
       if (nq == 0) continue;
@@ -1418,6 +1445,7 @@ void System::unpack(const std::vector<double>& xh, int e, double* phi, double* d
     switch (S.kind) {
       case PBT_MOLECULE:
       case PBT_STERN:
+      case PBT_CAVITY:
         p = xh[col_off_[e] + li];
         d = xh[col_off_[e] + S.nt + li];
         break;

@@ -87,7 +87,7 @@ struct SurfIn {
   std::vector<double> qxyz, q;
   bool enabled = true;
   int group = 0;  // surfaces of different groups belong to independent systems
-  const SurfIn* stern_parent = nullptr;  // Stern surface: the molecule it encloses
+  const SurfIn* parent = nullptr;  // Stern surface: the molecule it encloses; cavity: the molecule around it
 };
 
 struct NearCSR {
@@ -174,9 +174,9 @@ class System {
   void gradient_terms(const double* x, const double* lam, std::vector<std::vector<double>>& dq,
                       std::vector<std::vector<double>>& dsig, hipStream_t s);
   const SurfIn* surface(int e) const { return surfs_[e]; }
-  // Whether some enabled surface is a Stern layer (the transpose, gradient
-  // and batched paths do not take them).
-  bool has_stern() const { return has_stern_; }
+  // Whether some enabled surface is a Stern layer or a cavity (the
+  // transpose, gradient and batched paths do not take them).
+  bool has_nested() const { return has_nested_; }
 
   // Launch shape of the P2P / M2P tasks: Gauss points per P2P segment and
   // boxes per M2P segment (0 = size-based default).  Rebuilds the work lists.
@@ -228,7 +228,9 @@ class System {
   void build_tplan(hipStream_t s);
   template <typename T>
   void apply_t(const double* lam, double* z, double* sigbar, hipStream_t s);
-  void charge_near(int e, const double* qx, int64_t nq, NearCSR& out, hipStream_t s);
+  // near corrections of nq points (charges of molecule t_surf) against the
+  // panels of surface e, folded as surface t_surf's interior row sees e
+  void charge_near(int e, int t_surf, const double* qx, int64_t nq, NearCSR& out, hipStream_t s);
   // Per-surface (F_coul, F_solv, F_surf) in reduced units.
   std::vector<std::array<double, 3>> surface_energies(const double* x, hipStream_t s);
   std::vector<double> reaction_potential(int e, hipStream_t s);  // densities already set
@@ -239,6 +241,8 @@ class System {
     uint64_t version = ~0ull;
     DBuf<double> qx, q, phi;
     NearCSR qn;           // near corrections charge <- molecule panel
+    std::vector<int> cav;                            // the molecule's cavities
+    std::vector<std::unique_ptr<NearCSR>> cav_qn;    // near corrections charge <- cavity panel
     double coulomb = 0;   // sum over pairs k < l of q_k q_l / r_kl
   };
   std::vector<std::unique_ptr<ChargeData>> qdata_;
@@ -254,9 +258,10 @@ class System {
   pbt_params prm_;
   double eps_out_, kappa_;
   // Regions: every surface separates the region inside it from the one
-  // outside, which is the solvent or the salt-free layer of the Stern
-  // surface enclosing it (outer_[e] = that surface, or -1); eps_o_[e] is the
-  // outside region's permittivity.  forms_[t * ns + s]: how the rows of
+  // outside, which is the solvent, the salt-free layer of the Stern surface
+  // enclosing it, or (for a cavity) the interior of its molecule (outer_[e]
+  // = that surface, or -1 for the solvent); eps_o_[e] is the outside
+  // region's permittivity.  forms_[t * ns + s]: how the rows of
   // surface t see surface s (bits 0-1 interior row, 2-3 outside row; 0 not
   // at all, 1 from inside, 2 from outside with the Yukawa kernel, 3 from
   // outside with the Laplace kernel).
@@ -264,8 +269,10 @@ class System {
   std::vector<double> eps_o_;
   std::vector<uint8_t> h_forms_;
   DBuf<uint8_t> forms_;
-  bool has_stern_ = false;
-  bool two_rows(int e) const { return surfs_[e]->kind == PBT_MOLECULE || surfs_[e]->kind == PBT_STERN; }
+  bool has_nested_ = false;
+  bool two_rows(int e) const {
+    return surfs_[e]->kind == PBT_MOLECULE || surfs_[e]->kind == PBT_STERN || surfs_[e]->kind == PBT_CAVITY;
+  }
   int form(int t, int s) const { return h_forms_[(size_t)t * surfs_.size() + s]; }
   void build_regions();
   int K_ = 3;

@@ -17,7 +17,7 @@
 
 namespace pbt {
 
-void System::charge_near(int e, const double* qx, int64_t nq, NearCSR& qn, hipStream_t s) {
+void System::charge_near(int e, int t_surf, const double* qx, int64_t nq, NearCSR& qn, hipStream_t s) {
   const SurfIn& S = *surfs_[e];
   const int64_t p0 = poff_[e];
   NearParams npr{K_, prm_.k_near, prm_.k_self_edge, kappa_, qtab_[0].p, qtab_[1].p, qtab_[2].p, qtab_[3].p,
@@ -35,9 +35,10 @@ void System::charge_near(int e, const double* qx, int64_t nq, NearCSR& qn, hipSt
   launch_near_fill(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr, qn.ptr.p, qn.col.p, s);
   launch_near_values(nq, qx, nullptr, qn.ptr.p, qn.col.p, tri9_.p + 9 * p0, nrm_.p + 3 * p0,
                      area_.p + p0, npr, qn.val.p, s);
-  // the charges count as targets of surface e (columns are local to its panels)
+  // the charges count as targets of surface t_surf (columns are local to
+  // the panels of e)
   launch_fold_near(nq, qn.ptr.p, qn.col.p, nullptr, panel_surf_.p + p0, forms_.p, (int)surfs_.size(),
-                   surf_rhoinv_.p, qn.val.p, s, e);
+                   surf_rhoinv_.p, qn.val.p, s, t_surf);
   PBT_HIP(hipStreamSynchronize(s));
 }
 
@@ -58,7 +59,7 @@ std::vector<double> System::reaction_potential(int e, hipStream_t s) {
 // by box, the near corrections re-indexed by source panel, and the M2M^T
 // schedule (levels from the root down).
 void System::build_tplan(hipStream_t s) {
-  if (has_stern_) throw Error(PBT_E_INVALID, "the transposed operator does not take Stern surfaces");
+  if (has_nested_) throw Error(PBT_E_INVALID, "the transposed operator does not take Stern surfaces or cavities");
   if (tplan_ready_) return;
   const int ns = (int)surfs_.size();
   // (surface, source leaf) -> target ranges (g0, g1, fused)
@@ -287,7 +288,7 @@ void System::matvec_t(const double* lam, double* z, bool fp32, double* sigbar, h
 }
 
 void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
-  if (has_stern_) throw Error(PBT_E_INVALID, "the adjoint does not take Stern surfaces");
+  if (has_nested_) throw Error(PBT_E_INVALID, "the adjoint does not take Stern surfaces or cavities");
   const int ns = (int)surfs_.size();
   PBT_HIP(hipMemsetAsync(g, 0, n_ * sizeof(double), s));
   PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
@@ -345,7 +346,7 @@ void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
 
 void System::gradient_terms(const double* x, const double* lam, std::vector<std::vector<double>>& dq,
                             std::vector<std::vector<double>>& dsig, hipStream_t s) {
-  if (has_stern_) throw Error(PBT_E_INVALID, "the adjoint does not take Stern surfaces");
+  if (has_nested_) throw Error(PBT_E_INVALID, "the adjoint does not take Stern surfaces or cavities");
   const int ns = (int)surfs_.size();
   dq.assign(ns, {});
   dsig.assign(ns, {});

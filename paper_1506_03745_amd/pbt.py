@@ -16,14 +16,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpbt.so")
 
-MOLECULE, CHARGED, POTENTIAL, STERN = 0, 1, 2, 3
+MOLECULE, CHARGED, POTENTIAL, STERN, CAVITY = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 
 STATUS = {0: "PBT_OK", 1: "PBT_E_INVALID", 2: "PBT_E_NOMEM", 3: "PBT_E_DEVICE",
           4: "PBT_E_NOCONVERGE", 5: "PBT_E_NUMERIC", 6: "PBT_E_STATE"}
 
 EXPORTS = ("pbt_default_params", "pbt_create", "pbt_destroy", "pbt_last_error", "pbt_set_params",
-           "pbt_set_solvent", "pbt_add_surface", "pbt_set_bc", "pbt_set_charges", "pbt_set_stern", "pbt_enable",
+           "pbt_set_solvent", "pbt_add_surface", "pbt_set_bc", "pbt_set_charges", "pbt_set_stern",
+           "pbt_set_cavity", "pbt_enable",
            "pbt_prepare", "pbt_num_unknowns", "pbt_solve", "pbt_get_solution", "pbt_interaction_energy",
            "pbt_matvec", "pbt_matvec_dev", "pbt_rhs", "pbt_gradient", "pbt_solve_batch",
            "pbt_autotune", "pbt_last_stats", "pbt_set_schedule", "pbt_get_schedule", "pbt_quadrature_rule",
@@ -87,6 +88,7 @@ def lib():
         L.pbt_set_bc.argtypes = [P, I32, P]
         L.pbt_set_charges.argtypes = [P, I32, D, P, P, I64]
         L.pbt_set_stern.argtypes = [P, I32, I32, D]
+        L.pbt_set_cavity.argtypes = [P, I32, I32, D]
         L.pbt_enable.argtypes = [P, I32, I32]
         L.pbt_num_unknowns.argtypes = [P, ctypes.POINTER(I64)]
         L.pbt_prepare.argtypes = [P]
@@ -222,6 +224,9 @@ class Solver:
     def set_stern(self, stern_id, mol_id, eps_layer):
         self._check(lib().pbt_set_stern(self._h, stern_id, mol_id, float(eps_layer)))
 
+    def set_cavity(self, cav_id, mol_id, eps_cavity):
+        self._check(lib().pbt_set_cavity(self._h, cav_id, mol_id, float(eps_cavity)))
+
     def enable(self, sid, on=True):
         self._check(lib().pbt_enable(self._h, sid, 1 if on else 0))
 
@@ -325,4 +330,6 @@ def from_problem(problem, device=0, **params) -> tuple[Solver, list[int]]:
     for surf, sid in zip(problem.surfaces, ids):
         if surf.kind == STERN:
             s.set_stern(sid, ids[surf.parent], surf.eps_in)
+        elif surf.kind == CAVITY:
+            s.set_cavity(sid, ids[surf.parent], surf.eps_in)
     return s, ids

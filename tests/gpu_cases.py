@@ -2,7 +2,7 @@
 import numpy as np
 
 from workloads.meshes import box_plate, icosphere
-from workloads.problems import CHARGED, MOLECULE, POTENTIAL, STERN, Problem, Surface, config_problem
+from workloads.problems import CAVITY, CHARGED, MOLECULE, POTENTIAL, STERN, Problem, Surface, config_problem
 
 
 def sphere_plate(gap=1.0, kappa=0.125):
@@ -49,6 +49,18 @@ def stern_plate(kappa=0.125):
     return Problem([mol, stern, pl], 80.0, kappa, {}, "stern_plate")
 
 
+def nested_plate(kappa=0.125):
+    """The Stern case with a water cavity (r = 1 A, 80 panels, permittivity
+    80) inside the molecule, 0.6 A from its surface and 0.4 A from a charge:
+    every nested channel at once (molecule, cavity, Stern layer, solvent,
+    plate)."""
+    pr = stern_plate(kappa)
+    v, t = icosphere(1, 1.0, (-1.2, 0.7, 4.3))
+    pr.surfaces.append(Surface(CAVITY, v, t, eps_in=80.0, parent=0))
+    pr.name = "nested_plate"
+    return pr
+
+
 def case(name):
     if name == "kirkwood_l1":
         return config_problem("kirkwood", level=1)
@@ -74,9 +86,13 @@ def case(name):
         return stern_plate()
     if name == "stern_plate_k0":
         return stern_plate(kappa=0.0)
+    if name == "kirkwood_water_cavity_l1":
+        return config_problem("kirkwood_water_cavity", level=1)
+    if name == "nested_plate":
+        return nested_plate()
     raise KeyError(name)
 
 
 SMALL_CASES = ["kirkwood_l1", "kirkwood_l2", "twosphere_charge_l2", "twosphere_potential_l2",
                "sphere_plate", "sphere_plate_k0", "three_body", "three_body_k0",
-               "kirkwood_stern_l1", "stern_plate", "stern_plate_k0"]
+               "kirkwood_stern_l1", "stern_plate", "stern_plate_k0", "kirkwood_water_cavity_l1", "nested_plate"]

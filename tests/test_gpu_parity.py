@@ -181,8 +181,10 @@ def test_treecode_stern_layers():
     surface seen from inside), the Stern surface's inside row the same
     equation and its outside row the solvent's.  Treecode, FP64 and mixed,
     salted and salt-free, against the oracle at the multi-surface bar; the
-    four far-field schedules agree bitwise."""
-    for name in ("stern_plate", "stern_plate_k0"):
+    four far-field schedules agree bitwise.  nested_plate adds a water
+    cavity inside the molecule (its outside row is the molecule's interior
+    equation)."""
+    for name in ("stern_plate", "stern_plate_k0", "nested_plate"):
         A, _ = oracle_Ab(name)
         x = rand_x(A.shape[0], 9)
         ref = A @ x
@@ -199,10 +201,11 @@ def test_treecode_stern_layers():
 
 
 def test_stern_energies_and_interaction():
-    """Energies of Stern systems against the oracle's dense LU (FP64 direct to
-    1e-8, mixed treecode to 1e-4), and the interaction energy with a molecule
-    and its Stern surface isolated together."""
-    for name in ("kirkwood_stern_l2", "stern_plate"):
+    """Energies of Stern and cavity systems against the oracle's dense LU
+    (FP64 direct to 1e-8, mixed treecode to 1e-4; the reaction potential
+    includes the cavity's terms), and the interaction energy with a molecule
+    isolated together with its Stern surface and cavity."""
+    for name in ("kirkwood_stern_l2", "stern_plate", "kirkwood_water_cavity_l1", "nested_plate"):
         pr = case(name)
         e, _, _ = solve_problem(pr)
         s, _ = from_problem(pr, treecode=0, tol=1e-11)
@@ -210,13 +213,14 @@ def test_stern_energies_and_interaction():
         for a, b in ((r.F_solv, e.F_solv), (r.F_surf, e.F_surf), (r.F_coul, e.F_coul)):
             assert abs(a - b) <= 1e-8 * max(abs(b), 1e-12) + 1e-14, (name, a, b)
         s.close()
-    pr = case("stern_plate")
+    pr = case("nested_plate")
     f_or, e_all, _ = interaction_energy(pr)
     scale = abs(e_all.F_solv) + abs(e_all.F_surf)
     s, _ = from_problem(pr, treecode=0, tol=1e-10)
     f, res = s.interaction_energy(len(pr.surfaces))
     assert abs(f - f_or) <= 1e-7 * scale
-    assert res[2].F_total == 0.0   # the Stern surface is no component of its own
+    # the Stern surface and the cavity are no components of their own
+    assert res[2].F_total == 0.0 and res[4].F_total == 0.0
     s.close()
     s2, _ = from_problem(pr, treecode=1, ncrit=24, theta=0.4, taylor_p=8, prec=MIXED, tol=1e-8)
     f2, _ = s2.interaction_energy(len(pr.surfaces))
@@ -256,6 +260,17 @@ def test_stern_unsupported_paths():
     with pytest.raises(PbtError, match="STATE"):
         s2.solve()
     s2.close()
+    pr3 = case("nested_plate")
+    s3, ids3 = from_problem(pr3, treecode=0)
+    with pytest.raises(PbtError, match="INVALID"):
+        s3.matvec(np.ones(s3.num_unknowns()), transpose=True)
+    s3.enable(ids3[1], False)   # the Stern surface off: molecule, cavity and plate remain
+    s3.solve()
+    s3.enable(ids3[0], False)   # the cavity without its molecule
+    s3.enable(ids3[1], True)
+    with pytest.raises(PbtError, match="STATE"):
+        s3.solve()
+    s3.close()
 
 
 @pytest.mark.parametrize("name", ["kirkwood_l2", "twosphere_charge_l2", "twosphere_potential_l2",

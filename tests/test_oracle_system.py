@@ -136,6 +136,25 @@ def test_kirkwood_stern_convergence():
     assert 0.85 < _order(errs) < 1.15
 
 
+def test_fictitious_cavity_converges_to_kirkwood():
+    """A cavity whose permittivity equals the molecule's is no interface at
+    all: the dense BEM with it (two more block rows, the cavity's terms in
+    the molecule's interior equation and in the reaction potential)
+    converges at first order to Kirkwood's closed form, and its difference
+    to the system without the cavity falls like 1/N."""
+    exact = energy_to_kcal(analytic.born_kirkwood(1.0, 4.0, 4.0, 80.0, 0.125))
+    errs, diffs = [], []
+    for lv in (1, 2, 3):
+        e, _, _ = solve_problem(config_problem("kirkwood_cavity", level=lv))
+        e0, _, _ = solve_problem(config_problem("kirkwood", level=lv))
+        errs.append((e.F_solv - exact) / exact)
+        diffs.append(e.F_solv - e0.F_solv)
+    assert abs(errs[-1]) < 5e-3
+    assert abs(errs[0]) > abs(errs[1]) > abs(errs[2])
+    assert 0.85 < _order(errs) < 1.15
+    assert 0.85 < _order(diffs) < 1.15
+
+
 @pytest.mark.parametrize("case", ["charge", "potential"])
 def test_two_sphere_interaction_convergence(case):
     """F_int of the dense BEM against the series, levels 1..3 (80..1280 panels

@@ -2,9 +2,10 @@
 
 A :class:`Problem` is a list of surfaces in one solvent.  Each surface is a
 dielectric molecule boundary (with interior permittivity and point charges),
-a surface with imposed charge density, a surface with imposed potential, or
-a Stern surface: a closed surface around one molecule that bounds a
-salt-free layer between the molecule and the ionic solvent.
+a surface with imposed charge density, a surface with imposed potential, a
+Stern surface (a closed surface around one molecule that bounds a salt-free
+layer between the molecule and the ionic solvent), or a cavity (a closed
+surface inside one molecule around a salt-free, charge-free region).
 
 Named workloads (sizes are panel counts):
 
@@ -13,6 +14,9 @@ Named workloads (sizes are panel counts):
   r = 6 A (1280 panels, salt-free layer of permittivity 20).
 * ``stern_plate``  that pair (320 + 320 panels) 14 A above a 40 x 40 x 2 A
   charged plate (1536 panels).
+* ``kirkwood_cavity`` / ``kirkwood_water_cavity`` the Kirkwood sphere with a
+  salt-free cavity (r = 1 A, 1280 panels, 2.2 A off the charge) of
+  permittivity 4 (the molecule's: a fictitious interface) or 80 (water).
 * ``twosphere_charge`` / ``twosphere_potential``  molecule sphere (r = 4 A,
   +1 e centre, 5120 panels) and a second sphere (r = 4 A, 5120 panels) 12 A
   away on z with sigma = 0.05 C/m^2 or phi = 0.05 V.
@@ -32,8 +36,9 @@ import numpy as np
 
 from .meshes import box_plate, icosphere, star_surface
 
-MOLECULE, CHARGED, POTENTIAL, STERN = 0, 1, 2, 3
-KIND_NAMES = {MOLECULE: "molecule", CHARGED: "charged", POTENTIAL: "potential", STERN: "stern"}
+MOLECULE, CHARGED, POTENTIAL, STERN, CAVITY = 0, 1, 2, 3, 4
+KIND_NAMES = {MOLECULE: "molecule", CHARGED: "charged", POTENTIAL: "potential", STERN: "stern",
+              CAVITY: "cavity"}
 
 
 @dataclass
@@ -45,7 +50,7 @@ class Surface:
     eps_in: float = 1.0           # molecule interior permittivity (Stern: of the layer)
     q_pos: np.ndarray | None = None  # (nq, 3) Angstrom
     q: np.ndarray | None = None      # (nq,) e
-    parent: int = -1              # Stern surface: index of the molecule it encloses
+    parent: int = -1              # Stern surface: the molecule it encloses; cavity: the one enclosing it
 
     @property
     def nt(self) -> int:
@@ -117,6 +122,13 @@ def stern_sphere(parent, level=4, radius=6.0, center=(0.0, 0.0, 0.0), eps_in=80.
     return Surface(STERN, v, t, eps_in=eps_in, parent=parent)
 
 
+def cavity_sphere(parent, level=2, radius=1.5, center=(0.0, 0.0, 0.0), eps_in=80.0):
+    """Solvent-filled (salt-free) cavity inside molecule ``parent``: a
+    sphere of permittivity eps_in without charges."""
+    v, t = icosphere(level, radius, center)
+    return Surface(CAVITY, v, t, eps_in=eps_in, parent=parent)
+
+
 def plate(half_x, half_y, thick, n_xy, n_long, n_z, sigma):
     v, t = box_plate(-half_x, half_x, -half_y, half_y, -thick, 0.0, n_xy, n_long, n_z)
     bc = np.full(len(t), sigma, dtype=np.float64) if np.isscalar(sigma) else np.asarray(sigma)
@@ -132,7 +144,8 @@ def star_molecule(levels, shape_seed, n_charges, charge_seed, gap, eps_in=4.0):
 
 
 CONFIG_NAMES = ("kirkwood", "twosphere_charge", "twosphere_potential", "star_plate",
-                "orient_sweep", "star_plate_large", "star_plate_twin", "kirkwood_stern", "stern_plate")
+                "orient_sweep", "star_plate_large", "star_plate_twin", "kirkwood_stern", "stern_plate",
+                "kirkwood_cavity", "kirkwood_water_cavity")
 
 DEFAULT_PARAMS = dict(k_far=3, k_near=19, k_self_edge=9, ncrit=300, taylor_p=6, theta=0.5, tol=1e-6)
 
@@ -152,6 +165,15 @@ def config_problem(name: str, level: int | None = None, rotation: int | None = N
         # in the solvation energy
         lv = 3 if level is None else level
         return Problem([sphere_molecule(lv, 4.0), stern_sphere(0, lv, 6.0, eps_in=20.0)], 80.0, 0.125, p, name)
+    if name in ("kirkwood_cavity", "kirkwood_water_cavity"):
+        # the Kirkwood sphere (r = 4 A, +1 e at the centre) with a cavity of
+        # r = 1 A centred 2.2 A off the charge; with the cavity's permittivity
+        # equal to the molecule's (kirkwood_cavity) the interface is
+        # fictitious and the energy is Kirkwood's
+        lv = 3 if level is None else level
+        eps_c = 4.0 if name == "kirkwood_cavity" else 80.0
+        return Problem([sphere_molecule(lv, 4.0), cavity_sphere(0, lv, 1.0, (2.2, 0.0, 0.0), eps_c)],
+                       80.0, 0.125, p, name)
     if name == "stern_plate":
         # the Stern-layer sphere pair 14 A above a charged plate
         lv = 2 if level is None else level
