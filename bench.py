@@ -35,10 +35,16 @@ P2P_SOURCES = (os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "p2p.hip"),
                os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "near_field.h"))
 
 
-def profiled_traffic():
+PROFILED_WORKLOAD = "twosphere_charge"   # the workload of the committed counter summary
+
+
+def profiled_traffic(workload):
     """HBM bytes per P2P launch from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel source changed since the counters were taken or
+    the counters were taken on another workload."""
     import hashlib
+    if workload != PROFILED_WORKLOAD:
+        return None
     try:
         prof = json.load(open(P2P_PROFILE))
         sha = [hashlib.sha256(open(f, "rb").read()).hexdigest() for f in P2P_SOURCES]
@@ -99,6 +105,8 @@ WORKLOADS = {
     "kirkwood": "sphere r=4 A, 1280 panels, +1 e at the centre, eps 4/80, kappa 0.125",
     "star_plate": "star molecule 32768 panels + 900 charges, 10 A above a 80x80x2 A plate of 20480 panels "
                   "(sigma -0.05 C/m^2), eps 4/80, kappa 0.125",
+    "star_plate_stern": "star_plate with a Stern (ion-exclusion) surface 2 A outside the molecule, 32768 "
+                        "panels, salt-free layer of permittivity 80",
     "orient_sweep": "64 rigid rotations of a 5120-panel sphere molecule (+1 e) 10 A above the 20480-panel "
                     "plate, solved together (one Krylov space each)",
     "star_plate_large": "star molecule 65536 panels + 3000 charges, 12 A above a 120x120x2 A plate of 81920 "
@@ -302,7 +310,7 @@ def main():
                    "self_per_edge": 9, "tol": 1e-6, "precision": "mixed"},
         "roofline": {"bound": "alu", "kernel": "k_p2p<float>", "achieved": round(achieved, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": profiled_traffic(),
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": profiled_traffic(a.workload),
                      "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                      "flops_per_launch": int(p2p_flops), "avg_launch_ms": round(acc_serial["p2p_ms"], 5)},
         "gmres": {"iters": r.iters, "outer": r.outer, "rel_resid": r.rel_resid,

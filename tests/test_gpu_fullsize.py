@@ -56,6 +56,12 @@ def test_star_plate_sampled_rows():
     _sampled_rows_check(config_problem("star_plate"), 32, 30)
 
 
+def test_star_plate_stern_sampled_rows():
+    """The nested-interface path at full size: molecule, Stern surface and
+    plate (86016 panels)."""
+    _sampled_rows_check(config_problem("star_plate_stern"), 32, 31)
+
+
 def test_star_plate_large_sampled_rows():
     _sampled_rows_check(config_problem("star_plate_large"), 16, 50)
 

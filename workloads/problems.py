@@ -14,6 +14,9 @@ Named workloads (sizes are panel counts):
   r = 6 A (1280 panels, salt-free layer of permittivity 20).
 * ``stern_plate``  that pair (320 + 320 panels) 14 A above a 40 x 40 x 2 A
   charged plate (1536 panels).
+* ``star_plate_stern`` star_plate with a Stern surface 2 A outside the
+  molecule (the star mesh pushed out radially, 32768 panels, layer
+  permittivity 80).
 * ``kirkwood_cavity`` / ``kirkwood_water_cavity`` the Kirkwood sphere with a
   salt-free cavity (r = 1 A, 1280 panels, 2.2 A off the charge) of
   permittivity 4 (the molecule's: a fictitious interface) or 80 (water).
@@ -143,9 +146,20 @@ def star_molecule(levels, shape_seed, n_charges, charge_seed, gap, eps_in=4.0):
     return Surface(MOLECULE, v + shift, t, eps_in=eps_in, q_pos=qp + shift, q=qv)
 
 
+def star_stern(levels, shape_seed, gap, thickness=2.0, eps_layer=80.0, parent=0):
+    """Stern surface of ``star_molecule(levels, shape_seed, ..., gap)``: the
+    same star mesh pushed out radially by ``thickness`` A (a closed surface
+    around the molecule; its lowest point is below the molecule's)."""
+    v, t, _ = star_surface(levels, shape_seed)
+    r = np.linalg.norm(v, axis=1)
+    vs = v * ((r + thickness) / r)[:, None]
+    shift = np.array([0.0, 0.0, gap - v[:, 2].min()])
+    return Surface(STERN, vs + shift, t, eps_in=eps_layer, parent=parent)
+
+
 CONFIG_NAMES = ("kirkwood", "twosphere_charge", "twosphere_potential", "star_plate",
                 "orient_sweep", "star_plate_large", "star_plate_twin", "kirkwood_stern", "stern_plate",
-                "kirkwood_cavity", "kirkwood_water_cavity")
+                "kirkwood_cavity", "kirkwood_water_cavity", "star_plate_stern")
 
 DEFAULT_PARAMS = dict(k_far=3, k_near=19, k_self_edge=9, ncrit=300, taylor_p=6, theta=0.5, tol=1e-6)
 
@@ -193,6 +207,12 @@ def config_problem(name: str, level: int | None = None, rotation: int | None = N
         mol = star_molecule(12, 1, 900, 2, 10.0)
         pl = plate(40.0, 40.0, 2.0, 64, 128, 4, -0.05)
         return Problem([mol, pl], 80.0, 0.125, p, name)
+    if name == "star_plate_stern":
+        # star_plate with a 2 A Stern layer (permittivity 80, no ions) around
+        # the molecule
+        mol = star_molecule(12, 1, 900, 2, 10.0)
+        pl = plate(40.0, 40.0, 2.0, 64, 128, 4, -0.05)
+        return Problem([mol, star_stern(12, 1, 10.0), pl], 80.0, 0.125, p, name)
     if name == "orient_sweep":
         lv = 4 if level is None else level
         v, t = icosphere(lv, 4.0, (0.0, 0.0, 0.0))
