@@ -317,7 +317,10 @@ def main():
                   "applications_per_step": applications, "setup_s": round(setup_wall, 4),
                   "autotune_s": round(autotune_s, 3)},
         "far_field_schedule": {0: "serial", 1: "two streams", 2: "joint M2P + P2P launch",
-                               3: "moments inside the P2P launch"}[schedule],
+                               3: "moments inside the P2P launch",
+                               4: "moments with 7/8 of P2P, then M2P with 1/8 of P2P",
+                               5: "moments with 3/4 of P2P, then M2P with 1/4 of P2P",
+                               6: "moments with 1/2 of P2P, then M2P with 1/2 of P2P"}[schedule],
         "matvec_ms": {"fp32": {k: round(v, 4) for k, v in acc.items()},
                       "fp64": {k: round(v, 4) for k, v in acc64.items()},
                       "fp32_serial_schedule": {k: round(v, 4) for k, v in acc_serial.items()}},

@@ -238,7 +238,7 @@ pbt_status pbt_solve_batch(pbt_ctx* ctx, int32_t mol_id, const double* rot, cons
                            int32_t nb, double* F_int);
 
 /* Chooses P2P / M2P launch shapes and the schedule of the far field against
- * P2P (one stream, two streams, or one joint launch) for the enabled system
+ * P2P (the seven schedules of pbt_set_schedule) for the enabled system
  * by timing candidates; cached per (size, precision) in memory and, if
  * cache_path is not NULL, in that text file. */
 pbt_status pbt_autotune(pbt_ctx* ctx, const char* cache_path);
@@ -257,11 +257,13 @@ pbt_status pbt_last_stats(pbt_ctx* ctx, pbt_result* out);
  * P2M/M2M/M2P): 0 = P2P then the far field on the context's stream,
  * 1 = the far field on a second stream, concurrently with P2P, 2 = moments
  * first, then M2P and P2P tasks in one launch, 3 = moments and P2P tasks in
- * one launch, then M2P.  All four give bitwise the same products.
- * PBT_E_INVALID for another mode. */
+ * one launch, then M2P, 4 / 5 / 6 = moments with 7/8, 3/4 or 1/2 of the P2P
+ * pairs in one launch, then M2P with the other P2P pairs in one launch.
+ * All seven give bitwise the same products.  PBT_E_INVALID for another
+ * mode. */
 pbt_status pbt_set_schedule(pbt_ctx* ctx, int32_t mode);
 
-/* The schedule the enabled system currently uses (0 to 3, as for
+/* The schedule the enabled system currently uses (0 to 6, as for
  * pbt_set_schedule; pbt_autotune may have chosen it) in *mode.  Host-only. */
 pbt_status pbt_get_schedule(pbt_ctx* ctx, int32_t* mode);
 
@@ -276,7 +278,9 @@ pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w);
  * events, in milliseconds: out[0] total, out[1] P2P kernel, out[2] M2P
  * kernel, out[3] moments (P2M), out[4] strengths, near field and combine.
  * Under schedule 2 out[1] is the joint M2P + P2P launch and out[2] is 0;
- * under schedule 3 out[1] is the launch of moments and P2P and out[3] is 0. */
+ * under schedule 3 out[1] is the launch of moments and P2P and out[3] is 0;
+ * under schedules 4-6 out[1] is the launch of moments and part of P2P,
+ * out[2] the joint M2P + P2P launch and out[3] is 0. */
 pbt_status pbt_last_matvec_timing(pbt_ctx* ctx, double out[5]);
 
 #ifdef __cplusplus

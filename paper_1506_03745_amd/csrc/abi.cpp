@@ -683,6 +683,8 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
 // interaction precision, keeps the fastest, and remembers it per system
 // shape in memory and, if given, in a text cache file
 // ("key seg_src 4*seg_box+schedule ms" per line).
+constexpr int kFarModes = 7;   // far-field schedules (System::set_far_mode)
+
 pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
   return guarded(c, [&] {
     System& S = system_for(c);
@@ -705,8 +707,8 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
       }
     }
     if (it != memo.end()) {
-      S.set_segments(it->second.first, it->second.second / 4, c->stream);
-      S.set_far_mode((int)(it->second.second % 4));
+      S.set_segments(it->second.first, it->second.second / 8, c->stream);
+      S.set_far_mode((int)(it->second.second % 8));
       return PBT_OK;
     }
     const int reps = 5;
@@ -723,19 +725,20 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
       if (t < best) { best = t; best_box = cand; }
     }
     S.set_segments(best_src, best_box, c->stream);
-    // scheduling of the far field against P2P (serial, two streams, one launch)
+    // scheduling of the far field against P2P (serial, two streams, joint
+    // launches, moments inside P2P, and that with part of P2P joined to M2P)
     int best_mode = S.far_mode();
-    for (int mode = 0; mode < 4; ++mode) {
+    for (int mode = 0; mode < kFarModes; ++mode) {
       if (mode == best_mode) continue;
       S.set_far_mode(mode);
       const double t = S.time_products(fp32, reps, c->stream);
       if (t < best) { best = t; best_mode = mode; }
     }
     S.set_far_mode(best_mode);
-    memo[key] = {best_src, best_box * 4 + best_mode};
+    memo[key] = {best_src, best_box * 8 + best_mode};
     if (cache_path) {
       if (FILE* f = std::fopen(cache_path, "a")) {
-        std::fprintf(f, "%s %lld %lld %.6f\n", key, (long long)best_src, (long long)(best_box * 4 + best_mode), best);
+        std::fprintf(f, "%s %lld %lld %.6f\n", key, (long long)best_src, (long long)(best_box * 8 + best_mode), best);
         std::fclose(f);
       }
     }
@@ -751,7 +754,7 @@ pbt_status pbt_last_stats(pbt_ctx* c, pbt_result* out) {
 
 pbt_status pbt_set_schedule(pbt_ctx* c, int32_t mode) {
   if (!c) return PBT_E_INVALID;
-  if (mode < 0 || mode > 3) return fail(c, PBT_E_INVALID, "schedule must be 0, 1, 2 or 3");
+  if (mode < 0 || mode >= kFarModes) return fail(c, PBT_E_INVALID, "schedule must be 0..6");
   return guarded(c, [&] {
     system_for(c).set_far_mode(mode);
     return PBT_OK;

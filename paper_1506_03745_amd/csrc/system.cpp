@@ -815,6 +815,10 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   const bool two = far && far_mode_ == 1;
   const bool fused = far && far_mode_ == 2;
   const bool with_mom = far && far_mode_ == 3;
+  // 4..6: moments inside a launch with part of the P2P tasks, then M2P with
+  // the rest of them in one launch (P2P fills the M2P launch's tail); the
+  // share of the P2P pairs in the second launch is 1/8, 1/4 or 1/2
+  const bool split = far && far_mode_ >= 4 && far_mode_ <= 6;
   if (timed || two) PBT_HIP(hipEventRecord(ev_[1], s));
   const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
   T* msum = f32 ? (T*)msum32_.p : (T*)msum64_.p;
@@ -842,6 +846,25 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
                       dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
+      PBT_HIP(hipEventRecord(ev_[4], s));
+    }
+    far_timed_ = timed;
+    return;
+  }
+  if (split) {
+    const int nb = (int)((int64_t)npairs >> (7 - far_mode_)), na = npairs - nb;
+    if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
+    launch_p2p_moments<T>(prm_.taylor_p, nmb, mbl, mch, nmh, mhd, bcen_.p, brho_.p, mom, msum, p2p_tasks, na,
+                          dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    if (timed) {
+      PBT_HIP(hipEventRecord(ev_[3], s));
+      PBT_HIP(hipEventRecord(evm_[0], s));
+      PBT_HIP(hipEventRecord(evm_[1], s));
+    }
+    launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks + 2 * (int64_t)na, nb,
+                      dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
+    if (timed) {
+      PBT_HIP(hipEventRecord(evm_[2], s));
       PBT_HIP(hipEventRecord(ev_[4], s));
     }
     far_timed_ = timed;

@@ -197,7 +197,10 @@ class System {
   // How the far field (moments, M2P) and P2P are scheduled:
   //   0: P2P, then the far field, on the caller's stream;
   //   1: the far field on a second stream, concurrently with P2P;
-  //   2: moments first, then M2P and P2P tasks in one launch.
+  //   2: moments first, then M2P and P2P tasks in one launch;
+  //   3: moments inside the P2P launch, then M2P;
+  //   4, 5, 6: moments inside a launch with 7/8, 3/4 or 1/2 of the P2P
+  //      pairs, then M2P and the remaining P2P pairs in one launch.
   void set_far_mode(int mode) { far_mode_ = mode; }
   int far_mode() const { return far_mode_; }
 

@@ -89,25 +89,27 @@ def test_operator_is_deterministic():
 
 
 def test_far_field_schedules_agree_bitwise():
-    """Serial, two-stream, joint M2P + P2P and P2P-with-moments schedules
-    compute every partial sum with the same code and order: the products are
-    bitwise equal.  The two-sphere system has boxes of more than one moments
-    chunk (the chunk sums are exercised)."""
+    """Serial, two-stream, joint M2P + P2P, P2P-with-moments and split
+    schedules compute every partial sum with the same code and order: the
+    products are bitwise equal.  The two-sphere system has boxes of one fine
+    moments chunk (up to 16384 sources), the star/plate system boxes of
+    several chunks (their chunk sums are exercised)."""
     from workloads.problems import config_problem
     systems = [from_problem(case("sphere_plate"), treecode=1, ncrit=24, theta=0.5, taylor_p=4)[0],
-               from_problem(config_problem("twosphere_charge"), treecode=1, ncrit=300, theta=0.5, taylor_p=6)[0]]
+               from_problem(config_problem("twosphere_charge"), treecode=1, ncrit=300, theta=0.5, taylor_p=6)[0],
+               from_problem(config_problem("star_plate"), treecode=1, ncrit=300, theta=0.5, taylor_p=6)[0]]
     for s in systems:
         x = rand_x(s.num_unknowns(), 11)
         for prec in (FP64, MIXED):
             ys = []
-            for mode in (0, 1, 2, 3):
+            for mode in range(7):
                 s.set_schedule(mode)
                 assert s.schedule() == mode
                 ys.append(s.matvec(x, prec=prec))
             for y in ys[1:]:
                 assert np.array_equal(ys[0], y)
         with pytest.raises(PbtError):
-            s.set_schedule(4)
+            s.set_schedule(7)
         s.close()
 
 
@@ -181,7 +183,7 @@ def test_treecode_stern_layers():
     surface seen from inside), the Stern surface's inside row the same
     equation and its outside row the solvent's.  Treecode, FP64 and mixed,
     salted and salt-free, against the oracle at the multi-surface bar; the
-    four far-field schedules agree bitwise.  nested_plate adds a water
+    seven far-field schedules agree bitwise.  nested_plate adds a water
     cavity inside the molecule (its outside row is the molecule's interior
     equation)."""
     for name in ("stern_plate", "stern_plate_k0", "nested_plate"):
@@ -191,7 +193,7 @@ def test_treecode_stern_layers():
         s, _ = from_problem(case(name), treecode=1, ncrit=24, theta=0.4, taylor_p=8)
         assert rel_inf(s.matvec(x), ref) < 2e-4, name
         ys = []
-        for mode in range(4):
+        for mode in range(7):
             s.set_schedule(mode)
             ys.append(s.matvec(x, prec=MIXED))
         assert rel_inf(ys[0], ref) < 2e-4, name
