@@ -147,9 +147,10 @@ pbt_status pbt_set_charges(pbt_ctx* ctx, int32_t mol_id, double eps_in, const do
  * surface's outside row is the solvent's (Yukawa).  The Stern surface
  * carries phi and dphi/dn (layer side), like a molecule.  One Stern surface
  * per molecule; both must be enabled together in a solve (PBT_E_STATE
- * otherwise).  pbt_matvec with transpose = 1, pbt_gradient and
- * pbt_solve_batch do not take Stern surfaces (PBT_E_INVALID).  Before the
- * geometry is frozen (PBT_E_STATE after). */
+ * otherwise).  The transposed product and pbt_gradient take Stern surfaces
+ * (the molecule is isolated together with its Stern surface);
+ * pbt_solve_batch does not (PBT_E_INVALID).  Before the geometry is frozen
+ * (PBT_E_STATE after). */
 pbt_status pbt_set_stern(pbt_ctx* ctx, int32_t stern_id, int32_t mol_id, double eps_layer);
 
 /* Solvent-filled cavity (the other nested interface of Section 2's closing
@@ -161,8 +162,8 @@ pbt_status pbt_set_stern(pbt_ctx* ctx, int32_t stern_id, int32_t mol_id, double 
  * right-hand side), and the cavity's inside row is the cavity's Laplace
  * equation; the reaction potential at the charges includes the cavity's
  * terms.  A molecule may hold several cavities; each must be enabled
- * with its molecule (PBT_E_STATE otherwise).  Like Stern surfaces, not
- * taken by the transpose, pbt_gradient or pbt_solve_batch (PBT_E_INVALID).
+ * with its molecule (PBT_E_STATE otherwise).  Like Stern surfaces, taken by
+ * the transpose and pbt_gradient, not by pbt_solve_batch (PBT_E_INVALID).
  * Before the geometry is frozen (PBT_E_STATE after). */
 pbt_status pbt_set_cavity(pbt_ctx* ctx, int32_t cav_id, int32_t mol_id, double eps_cavity);
 

@@ -13,14 +13,17 @@ form in (p, u): F = 1/2 g(p)^T u + F_coul(q) with g(p) = C p + g0:
 
 Hence  dF/dp = 1/2 (C^T u + B^T lambda) + dF_coul/dp  with  A^T lambda = g.
 The interaction energy's gradient is the assembly's minus that of each
-isolated component that holds the parameter (the Coulomb part cancels).
+isolated component that holds the parameter (the Coulomb part cancels); a
+molecule's component includes its Stern surface and cavities, whose terms
+enter R (cavities: seen from outside) and whose outside rows carry the
+molecule's Coulomb sum (cavities).
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.linalg
 
-from .bem import CHARGED, MOLECULE, POTENTIAL, DenseBEM
+from .bem import CAVITY, CHARGED, MOLECULE, POTENTIAL, SOLVENT, STERN, TWO_ROWS, DenseBEM, components
 from .integrals import layer_blocks
 from .units import FOUR_PI, SIGMA_SI_TO_REDUCED, energy_to_kcal
 
@@ -36,25 +39,45 @@ def _system_gradient(sysm: DenseBEM):
     for s, ss in enumerate(sysm.surfs):
         c = sysm.col_off[s]
         if ss.kind == MOLECULE:
+            # phi_reac = R u: the molecule seen from inside, each of its
+            # cavities from outside (eq. phi_reac_bem over the region's boundary)
+            R = np.zeros((len(ss.q), sysm.n))
             vl, kl, _, _ = layer_blocks(ss.q_pos, sysm.panels[s], sysm.kappa, sysm.k_far,
                                         sysm.k_near, sysm.k_self_edge)
-            R = np.concatenate([-kl, vl], axis=1)          # (nq, 2 nt)
+            R[:, c:c + ss.nt] = -kl
+            R[:, c + ss.nt:c + 2 * ss.nt] = vl
+            for cv, sc in enumerate(sysm.surfs):
+                if sc.kind == CAVITY and sysm.outer[cv] == s:
+                    vc, kc, _, _ = layer_blocks(ss.q_pos, sysm.panels[cv], sysm.kappa, sysm.k_far,
+                                                sysm.k_near, sysm.k_self_edge)
+                    cc = sysm.col_off[cv]
+                    R[:, cc:cc + sc.nt] = kc
+                    R[:, cc + sc.nt:cc + 2 * sc.nt] = -(sc.eps_in / ss.eps_in) * vc
             R_ops[s] = R
-            g[c:c + 2 * ss.nt] += R.T @ ss.q
+            g += R.T @ ss.q
         elif ss.kind == CHARGED:
             g[c:c + ss.nt] += sysm.sigma[s] * sysm.panels[s].area
-        else:
+        elif ss.kind == POTENTIAL:
             g[c:c + ss.nt] += sysm.eps_out * sysm.phi0[s] * sysm.panels[s].area
     lam = scipy.linalg.lu_solve(lu, g, trans=1)
     grads = {}
     for s, ss in enumerate(sysm.surfs):
         c = sysm.col_off[s]
         if ss.kind == MOLECULE:
-            r = sysm.row_off[s]
-            x = sysm.panels[s].centroid
-            d = x[:, None, :] - ss.q_pos[None, :, :]
-            Bq = 1.0 / (FOUR_PI * ss.eps_in * np.sqrt(np.sum(d * d, axis=-1)))   # (nt, nq)
-            dq = 0.5 * (R_ops[s] @ u[c:c + 2 * ss.nt] + Bq.T @ lam[r:r + ss.nt])
+            # the Coulomb sum sits on every row of the molecule's interior:
+            # its own interior rows and its cavities' outside rows
+            bt = np.zeros(len(ss.q))
+            for t, st in enumerate(sysm.surfs):
+                if t == s:
+                    r = sysm.row_off[t]
+                elif st.kind == CAVITY and sysm.outer[t] == s:
+                    r = sysm.row_off[t] + st.nt
+                else:
+                    continue
+                d = sysm.panels[t].centroid[:, None, :] - ss.q_pos[None, :, :]
+                Bq = 1.0 / (FOUR_PI * ss.eps_in * np.sqrt(np.sum(d * d, axis=-1)))   # (nt, nq)
+                bt += Bq.T @ lam[r:r + st.nt]
+            dq = 0.5 * (R_ops[s] @ u + bt)
             # Coulomb part: dF_coul/dq_k = sum_{l != k} q_l / (4 pi eps r_kl)
             dd = ss.q_pos[:, None, :] - ss.q_pos[None, :, :]
             rr = np.sqrt(np.sum(dd * dd, axis=-1))
@@ -63,9 +86,12 @@ def _system_gradient(sysm: DenseBEM):
             grads[id(ss)] = ("q", dq)
         elif ss.kind == CHARGED:
             # b_sol(t) += V_Y^{ts} sigma_s / eps_out for every solvent row t
+            # only the solvent's rows see the charged surface (from outside)
             bt_lam = np.zeros(ss.nt)
             for t, st in enumerate(sysm.surfs):
-                r = sysm.row_off[t] + (st.nt if st.kind == MOLECULE else 0)
+                if sysm.outer[t] != SOLVENT:
+                    continue
+                r = sysm.row_off[t] + (st.nt if st.kind in TWO_ROWS else 0)
                 _, _, vy, _ = sysm._blocks(t, s)
                 bt_lam += vy.T @ lam[r:r + st.nt] / sysm.eps_out
             dsig = 0.5 * (sysm.panels[s].area * u[c:c + ss.nt] + bt_lam)
@@ -79,10 +105,14 @@ def interaction_gradient(problem, k_far=3, k_near=19, k_self_edge=9):
     [kcal/mol per C/m^2] for charged surfaces, None otherwise."""
     surfs = problem.surfaces
     g_all = _system_gradient(DenseBEM(problem, k_far, k_near, k_self_edge))
+    comp = {next(i for i, on in enumerate(en) if on and surfs[i].kind not in (STERN, CAVITY)): en
+            for en in components(problem)}
     out = []
     for i, ss in enumerate(surfs):
-        en = [j == i for j in range(len(surfs))]
-        g_iso = _system_gradient(DenseBEM(problem, k_far, k_near, k_self_edge, enabled=en))
+        if i not in comp:
+            out.append(None)
+            continue
+        g_iso = _system_gradient(DenseBEM(problem, k_far, k_near, k_self_edge, enabled=comp[i]))
         if id(ss) not in g_all:
             out.append(None)
             continue

@@ -539,12 +539,12 @@ pbt_status pbt_gradient(pbt_ctx* c, int32_t sigma_id, double* dF_dsigma, int32_t
       return fail(c, PBT_E_INVALID, "sigma_id must name a charged surface (and dF_dsigma be given)");
     if (mol_id >= 0 && (c->surfs[mol_id]->kind != PBT_MOLECULE || !dF_dq))
       return fail(c, PBT_E_INVALID, "mol_id must name a molecule (and dF_dq be given)");
-    for (int i = 0; i < ns; ++i)
-      if (c->surfs[i]->kind == PBT_STERN || c->surfs[i]->kind == PBT_CAVITY)
-        return fail(c, PBT_E_INVALID, "the gradient does not take Stern surfaces or cavities");
     std::vector<bool> saved = mask_of(c);
+    // a component: the surface alone, or a molecule with its Stern surface
+    // and cavities
     auto set_mask = [&](int only) {
-      for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = only < 0 ? true : i == only;
+      for (int i = 0; i < ns; ++i)
+        c->surfs[i]->enabled = only < 0 || i == only || (only >= 0 && c->surfs[i]->parent == c->surfs[only].get());
     };
     pbt_status worst = PBT_OK;
     std::vector<double> dq_a, ds_a, dq_i, ds_i;

@@ -82,6 +82,12 @@ __global__ __launch_bounds__(256) void k_p2p_t(const Task* __restrict__ tasks, i
   const int sbeg = tasks[wv].tbeg, scount = tasks[wv].tcount;
   const int lbeg = tasks[wv].lbeg, lend = tasks[wv].lend;
   const int fused = tasks[wv].fused;
+  // form bits of the forward task: kappa = 0 for its outside sum, the two
+  // sums stored in swapped rows, the outside sum dropped; the weights of the
+  // sums are the multipliers of the rows they went to
+  const int form = tasks[wv].form;
+  if (form & kFormKz) kappa = T(0);
+  const bool swap = (form & kFormSwap) != 0, drop = (form & kFormDropOut) != 0;
   const T ri = sizeof(T) == 4 ? (T)tasks[wv].rho_inv_f : (T)tasks[wv].rho_inv;
   const int sj = sbeg + (lane < scount ? lane : 0);
   const T sx = src[kSrcStride * (int64_t)sj], sy = src[kSrcStride * (int64_t)sj + 1],
@@ -99,11 +105,11 @@ __global__ __launch_bounds__(256) void k_p2p_t(const Task* __restrict__ tasks, i
       const T rr = r2 * rinv;
       const T e = AMath<T>::expm(kappa * rr);
       const T rinv3 = rinv * rinv * rinv;
-      const T u = t[4];
+      const T u = drop ? T(0) : swap ? t[3] : t[4];
       T c = u * (kappa * rr + T(1)) * e * rinv3;
       T g = u * e * rinv;
       if (fused) {
-        const T l = t[3];
+        const T l = swap ? t[4] : t[3];
         c -= l * rinv3;
         g -= ri * l * rinv;
       }
@@ -185,9 +191,15 @@ __global__ __launch_bounds__(64) void k_m2p_t(const Task* __restrict__ tasks, in
   const T* t = trec + 8 * (int64_t)ti;
   const T Rx = t[0] - (T)bcen[3 * b], Ry = t[1] - (T)bcen[3 * b + 1], Rz = t[2] - (T)bcen[3 * b + 2];
   T* out = mpart + (int64_t)slot * 2 * NC;
-  taylor_reduce<T, P>(Rx, Ry, Rz, kappa, act ? t[4] : T(0), true, out, lane);
+  // form bits as in the reverse P2P
+  const int form = tasks[wv].form;
+  const bool swap = (form & kFormSwap) != 0, drop = (form & kFormDropOut) != 0;
+  const T ku = (form & kFormKz) ? T(0) : kappa;
+  const T wu = act && !drop ? (swap ? t[3] : t[4]) : T(0);
+  const T wl = act ? (swap ? t[4] : t[3]) : T(0);
+  taylor_reduce<T, P>(Rx, Ry, Rz, ku, wu, true, out, lane);
   if (tasks[wv].fused) {
-    taylor_reduce<T, P>(Rx, Ry, Rz, kappa, act ? t[3] : T(0), false, out + NC, lane);
+    taylor_reduce<T, P>(Rx, Ry, Rz, kappa, wl, false, out + NC, lane);
   } else {
     for (int k = lane; k < NC; k += 64) out[NC + k] = T(0);
   }
@@ -346,7 +358,7 @@ __global__ void k_combine_t(AdjCombineArgs a, const T* __restrict__ partial, con
 //   sbar_j = sum_k q_k rho_inv / r,  Dbar_j = sum_k q_k (r_k - y_j) / r^3.
 __global__ void k_reac_t(int64_t s0, int64_t s1, const double* __restrict__ src, int64_t nq,
                          const double* __restrict__ qxyz, const double* __restrict__ q,
-                         double rho_inv, double* __restrict__ far) {
+                         double rho_inv, double dsign, double* __restrict__ far) {
   const int64_t j = s0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= s1) return;
   const double* s = src + (int64_t)kSrcStride * j;
@@ -355,7 +367,7 @@ __global__ void k_reac_t(int64_t s0, int64_t s1, const double* __restrict__ src,
     const double dx = qxyz[3 * k] - s[0], dy = qxyz[3 * k + 1] - s[1], dz = qxyz[3 * k + 2] - s[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
-    const double c = q[k] * rinv * rinv * rinv;
+    const double c = dsign * q[k] * rinv * rinv * rinv;
     sb += q[k] * rho_inv * rinv;
     gx += c * dx;
     gy += c * dy;
@@ -494,9 +506,9 @@ void launch_combine_t(const AdjCombineArgs& a, const T* partial, const T* far, d
 }
 
 void launch_reac_t(int64_t s0, int64_t s1, const double* src, int64_t nq, const double* qxyz,
-                   const double* q, double rho_inv, double* far, hipStream_t s) {
+                   const double* q, double rho_inv, double* far, double dsign, hipStream_t s) {
   if (s1 <= s0) return;
-  k_reac_t<<<nblocks(s1 - s0, 128), 128, 0, s>>>(s0, s1, src, nq, qxyz, q, rho_inv, far);
+  k_reac_t<<<nblocks(s1 - s0, 128), 128, 0, s>>>(s0, s1, src, nq, qxyz, q, rho_inv, dsign, far);
   PBT_HIP(hipGetLastError());
 }
 

@@ -251,7 +251,7 @@ template <typename T>
 void launch_combine_t(const AdjCombineArgs& a, const T* partial, const T* far, double* z, double* sigbar,
                       hipStream_t s);
 void launch_reac_t(int64_t s0, int64_t s1, const double* src, int64_t nq, const double* qxyz,
-                   const double* q, double rho_inv, double* far, hipStream_t s);
+                   const double* q, double rho_inv, double* far, double dsign, hipStream_t s);
 void launch_coulomb_t(int64_t nq, const double* qxyz, int64_t n, const double* tx, const int32_t* rows,
                       const double* lam, double inv_eps, double* out, hipStream_t s);
 

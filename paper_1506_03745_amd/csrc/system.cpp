@@ -98,6 +98,23 @@ void System::build_regions() {
     }
 }
 
+// The task flags for targets on surface t and sources on surface src: the
+// usual pair is (inside, Yukawa) = fused; the others occur with nested
+// interfaces.
+void System::task_form(int t, int src, int32_t& fused, int16_t& tform) const {
+  const int f = form(t, src), fi = f & 3, fo = f >> 2;
+  fused = fi == 1 ? 1 : 0;
+  tform = 0;
+  if (fi == 1 && fo == 3) tform = kFormKz;                          // seen from inside and from outside in a layer
+  else if (fi == 0 && fo == 1) {                                    // seen from inside by the outside row
+    fused = 1;
+    tform = kFormKz | kFormDropOut | kFormSwap;
+  } else if (fi == 3 && fo == 0) tform = kFormKz | kFormSwap;       // seen from outside by the interior row
+  else if (!((fi == 1 && fo == 2) || (fi == 0 && fo == 2) || (fi == 0 && fo == 3)))
+    throw Error(PBT_E_STATE, "unsupported arrangement of surfaces");
+  if (fi == 0 && fo == 3) tform = kFormKz;                          // seen from outside in a layer only
+}
+
 void System::build(hipStream_t s) {
   const int ns = (int)surfs_.size();
   build_regions();
@@ -660,18 +677,7 @@ void System::build_plan() {
       Task t{};
       t.lbeg = sg.lbeg;
       t.lend = sg.lend;
-      // the rows' forms of the source surface: (inside, Yukawa) is the usual
-      // fused pair; the others occur with Stern layers
-      const int f = form(e, sg.e2), fi = f & 3, fo = f >> 2;
-      t.fused = fi == 1 ? 1 : 0;
-      t.form = 0;
-      if (fi == 1 && fo == 3) t.form = kFormKz;                            // molecule in its layer
-      else if (fi == 0 && fo == 1) {                                       // its Stern surface, from inside
-        t.fused = 1;
-        t.form = kFormKz | kFormDropOut | kFormSwap;
-      } else if (fi == 3 && fo == 0) t.form = kFormKz | kFormSwap;         // the molecule inside, from outside
-      else if (!((fi == 1 && fo == 2) || (fi == 0 && fo == 2)))
-        throw Error(PBT_E_STATE, "unsupported arrangement of surfaces");
+      task_form(e, sg.e2, t.fused, t.form);
       t.known = two_rows(sg.e2) ? 0 : 1;
       t.rho_inv = mol ? eps_o_[e] / surfs_[e]->eps_in : 0.0;
       t.rho_inv_f = (float)t.rho_inv;

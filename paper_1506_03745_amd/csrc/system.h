@@ -277,6 +277,7 @@ class System {
     return surfs_[e]->kind == PBT_MOLECULE || surfs_[e]->kind == PBT_STERN || surfs_[e]->kind == PBT_CAVITY;
   }
   int form(int t, int s) const { return h_forms_[(size_t)t * surfs_.size() + s]; }
+  void task_form(int t, int src, int32_t& fused, int16_t& tform) const;
   void build_regions();
   int K_ = 3;
   int64_t n_ = 0, np_ = 0, ns_ = 0;

@@ -50,6 +50,12 @@ std::vector<double> System::reaction_potential(int e, hipStream_t s) {
   ChargeData& d = charges(e, s);
   launch_reac(nq, d.qx.p, p0 * K_, (p0 + S.nt) * K_, src64_.p, eps_o_[e] / S.eps_in, d.qn.ptr.p, d.qn.col.p,
               d.qn.val.p, sig_.p + p0, mu_.p + p0, d.phi.p, s);
+  for (size_t k = 0; k < d.cav.size(); ++k) {
+    const int c = d.cav[k];
+    const NearCSR& cq = *d.cav_qn[k];
+    launch_reac_cavity(nq, d.qx.p, poff_[c] * K_, (poff_[c] + surfs_[c]->nt) * K_, src64_.p, cq.ptr.p, cq.col.p,
+                       cq.val.p, sig_.p + poff_[c], mu_.p + poff_[c], d.phi.p, s);
+  }
   return d.phi.download(s);
 }
 
@@ -59,20 +65,22 @@ std::vector<double> System::reaction_potential(int e, hipStream_t s) {
 // by box, the near corrections re-indexed by source panel, and the M2M^T
 // schedule (levels from the root down).
 void System::build_tplan(hipStream_t s) {
-  if (has_nested_) throw Error(PBT_E_INVALID, "the transposed operator does not take Stern surfaces or cavities");
   if (tplan_ready_) return;
   const int ns = (int)surfs_.size();
-  // (surface, source leaf) -> target ranges (g0, g1, fused)
+  // (surface, source leaf) -> target ranges (g0, g1, key); key = the forward
+  // task's fused flag | its form bits << 1
   std::map<std::pair<int, int>, std::vector<std::tuple<int64_t, int64_t, int>>> lists;
   int64_t work = 0;
   for (size_t li = 0; li < leaves_.size(); ++li) {
     const LeafInfo& L = leaves_[li];
-    const bool mol = surfs_[L.e]->kind == PBT_MOLECULE;
     const std::vector<int>& gsf = group_surfs_[surfs_[L.e]->group];
     for (size_t k2 = 0; k2 < gsf.size(); ++k2)
       for (int b2 : lp2p_[li][k2]) {
         const int e2 = gsf[k2];
-        lists[{e2, b2}].push_back({L.g0, L.g1, (mol && e2 == L.e) ? 1 : 0});
+        int32_t fu = 0;
+        int16_t fm = 0;
+        task_form(L.e, e2, fu, fm);
+        lists[{e2, b2}].push_back({L.g0, L.g1, fu | (fm << 1)});
         const TreeBox& sb = trees_[e2].boxes[b2];
         work += (L.g1 - L.g0) * (int64_t)((sb.pend - sb.pbeg) * K_ + 63) / 64;
       }
@@ -91,9 +99,9 @@ void System::build_tplan(hipStream_t s) {
     std::sort(tl.begin(), tl.end(), [](const auto& a, const auto& b) {
       return std::get<2>(a) != std::get<2>(b) ? std::get<2>(a) < std::get<2>(b) : std::get<0>(a) < std::get<0>(b);
     });
-    // segments: (lbeg, lend, fused)
+    // segments: (lbeg, lend, key), one run per key
     std::vector<std::tuple<int32_t, int32_t, int>> segs;
-    for (int f = 0; f <= 1; ++f) {
+    for (int f = 0; f < 16; ++f) {
       int64_t acc = 0;
       int32_t start = (int32_t)(ranges.size() / 2);
       for (auto& t : tl) {
@@ -113,7 +121,7 @@ void System::build_tplan(hipStream_t s) {
       }
       if ((int32_t)(ranges.size() / 2) > start) segs.push_back({start, (int32_t)(ranges.size() / 2), f});
     }
-    const double rho = surfs_[e2]->kind == PBT_MOLECULE ? eps_out_ / surfs_[e2]->eps_in : 0.0;
+    const double rho = two_rows(e2) ? eps_o_[e2] / surfs_[e2]->eps_in : 0.0;
     for (int64_t c0 = s0; c0 < s1; c0 += 64) {
       ChunkSlots cs{(int32_t)c0, (int32_t)std::min<int64_t>(64, s1 - c0), slot, slot + (int32_t)segs.size()};
       for (int64_t j = c0; j < c0 + cs.tcount; ++j) chunk_of[j] = (int32_t)chunks.size();
@@ -124,7 +132,8 @@ void System::build_tplan(hipStream_t s) {
         t.lbeg = std::get<0>(segs[si]);
         t.lend = std::get<1>(segs[si]);
         t.slot = slot + (int)si;
-        t.fused = std::get<2>(segs[si]);
+        t.fused = std::get<2>(segs[si]) & 1;
+        t.form = (int16_t)(std::get<2>(segs[si]) >> 1);
         t.rho_inv = rho;
         t.rho_inv_f = (float)rho;
         tasks.push_back(t);
@@ -146,19 +155,22 @@ void System::build_tplan(hipStream_t s) {
   std::vector<std::vector<Task>> bybox(nbox_);
   for (size_t li = 0; li < leaves_.size(); ++li) {
     const LeafInfo& L = leaves_[li];
-    const bool mol = surfs_[L.e]->kind == PBT_MOLECULE;
     const std::vector<int>& gsf = group_surfs_[surfs_[L.e]->group];
     for (size_t k2 = 0; k2 < gsf.size(); ++k2)
       for (int b : lm2p_[li][k2]) {
         const int e2 = gsf[k2];
         const int gb = (int)(boff_[e2] + b);
+        int32_t fu = 0;
+        int16_t fm = 0;
+        task_form(L.e, e2, fu, fm);
         for (int64_t t0 = L.g0; t0 < L.g1; t0 += 64) {
           Task t{};
           t.tbeg = (int32_t)t0;
           t.tcount = (int32_t)std::min<int64_t>(64, L.g1 - t0);
           t.lbeg = gb;
           t.lend = gb + 1;
-          t.fused = (mol && e2 == L.e) ? 1 : 0;
+          t.fused = fu;
+          t.form = fm;
           bybox[gb].push_back(t);
         }
       }
@@ -288,35 +300,32 @@ void System::matvec_t(const double* lam, double* z, bool fp32, double* sigbar, h
 }
 
 void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
-  if (has_nested_) throw Error(PBT_E_INVALID, "the adjoint does not take Stern surfaces or cavities");
   const int ns = (int)surfs_.size();
   PBT_HIP(hipMemsetAsync(g, 0, n_ * sizeof(double), s));
   PanelMaps m{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p};
-  for (int e = 0; e < ns; ++e) {
-    const SurfIn& S = *surfs_[e];
-    if (S.kind != PBT_MOLECULE || S.q.empty()) continue;
-    const int64_t nq = (int64_t)S.q.size(), p0 = poff_[e];
-    ChargeData& d = charges(e, s);
+  // R^T q over the panels of surface e2 (the molecule itself, or one of its
+  // cavities seen from outside: far part with the opposite sign and unit
+  // single-layer factor), plus the near part qn
+  auto rt_q = [&](const SurfIn& S, ChargeData& d, int e2, const NearCSR& qn, double rho, double dsign) {
+    const int64_t nq = (int64_t)S.q.size(), p0 = poff_[e2], nt = surfs_[e2]->nt;
     DBuf<double> far;
-    far.alloc((size_t)S.nt * K_ * 4);
-    // R^T q: far part at every Gauss point of the molecule
-    launch_reac_t(p0 * K_, (p0 + S.nt) * K_, src64_.p, nq, d.qx.p, d.q.p, eps_out_ / S.eps_in, far.p, s);
-    // near part: phi_reac = -L, so d(q . phi_reac)/d(sigma, mu) = -q (cLs, cLm)
-    const NearCSR& qn = d.qn;
+    far.alloc((size_t)nt * K_ * 4);
+    launch_reac_t(p0 * K_, (p0 + nt) * K_, src64_.p, nq, d.qx.p, d.q.p, rho, far.p, dsign, s);
+    // near part: phi_reac holds -(corrections), so d(q . phi_reac)/d(sigma, mu) = -q (c_s, c_m)
     std::vector<int64_t> ptr = qn.ptr.download(s);
     std::vector<int32_t> col = qn.col.download(s);
     std::vector<double> val = qn.val.download(s);
-    std::vector<double> asg(S.nt, 0.0), amu(S.nt, 0.0);
+    std::vector<double> asg(nt, 0.0), amu(nt, 0.0);
     for (int64_t k = 0; k < nq; ++k)
-      for (int64_t e2 = ptr[k]; e2 < ptr[k + 1]; ++e2) {
-        asg[col[e2]] -= S.q[k] * val[4 * e2];
-        amu[col[e2]] -= S.q[k] * val[4 * e2 + 1];
+      for (int64_t e3 = ptr[k]; e3 < ptr[k + 1]; ++e3) {
+        asg[col[e3]] -= S.q[k] * val[4 * e3];
+        amu[col[e3]] -= S.q[k] * val[4 * e3 + 1];
       }
     DBuf<double> das, dam;
     das.upload(asg, s);
     dam.upload(amu, s);
     AdjCombineArgs a{};
-    a.np = S.nt;
+    a.np = nt;
     a.K = K_;
     a.wa = src_wa_.p + p0 * K_;
     a.nrm = nrm_.p + 3 * p0;
@@ -325,6 +334,13 @@ void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
     a.maps = PanelMaps{col_phi_.p + p0, col_psi_.p + p0, row_int_.p + p0, row_sol_.p + p0, dens_scale_.p + p0};
     launch_combine_t<double>(a, nullptr, far.p, g, nullptr, s);
     PBT_HIP(hipStreamSynchronize(s));
+  };
+  for (int e = 0; e < ns; ++e) {
+    const SurfIn& S = *surfs_[e];
+    if (S.kind != PBT_MOLECULE || S.q.empty()) continue;
+    ChargeData& d = charges(e, s);
+    rt_q(S, d, e, d.qn, eps_o_[e] / S.eps_in, 1.0);
+    for (size_t k = 0; k < d.cav.size(); ++k) rt_q(S, d, d.cav[k], *d.cav_qn[k], -1.0, -1.0);
   }
   (void)m;
   std::vector<double> hg(n_);
@@ -332,7 +348,7 @@ void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
   PBT_HIP(hipStreamSynchronize(s));
   for (int e = 0; e < ns; ++e) {
     const SurfIn& S = *surfs_[e];
-    if (S.kind == PBT_MOLECULE) continue;
+    if (S.kind != PBT_CHARGED && S.kind != PBT_POTENTIAL) continue;
     for (int64_t li = 0; li < S.nt; ++li) {
       const int64_t gi = poff_[e] + li;
       const int32_t o = h_panel_orig_[gi];
@@ -346,7 +362,6 @@ void System::adjoint_rhs(const double* x, double* g, hipStream_t s) {
 
 void System::gradient_terms(const double* x, const double* lam, std::vector<std::vector<double>>& dq,
                             std::vector<std::vector<double>>& dsig, hipStream_t s) {
-  if (has_nested_) throw Error(PBT_E_INVALID, "the adjoint does not take Stern surfaces or cavities");
   const int ns = (int)surfs_.size();
   dq.assign(ns, {});
   dsig.assign(ns, {});
@@ -373,6 +388,14 @@ void System::gradient_terms(const double* x, const double* lam, std::vector<std:
       launch_coulomb_t(nq, qx.p, S.nt, cen_.p + 3 * poff_[e], row_int_.p + poff_[e], lam, 1.0 / S.eps_in,
                        bt.p, s);
       std::vector<double> hb = bt.download(s);
+      // the charges' Coulomb sum is also on the outside rows of the cavities
+      for (int c = 0; c < ns; ++c) {
+        if (surfs_[c]->kind != PBT_CAVITY || outer_[c] != e) continue;
+        launch_coulomb_t(nq, qx.p, surfs_[c]->nt, cen_.p + 3 * poff_[c], row_sol_.p + poff_[c], lam,
+                         1.0 / S.eps_in, bt.p, s);
+        const std::vector<double> hc = bt.download(s);
+        for (int64_t k = 0; k < nq; ++k) hb[k] += hc[k];
+      }
       dq[e].resize(nq);
       for (int64_t k = 0; k < nq; ++k) dq[e][k] = 0.5 * (phi[k] + hb[k]);
     } else if (S.kind == PBT_CHARGED) {

@@ -26,7 +26,8 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("name", ["sphere_plate", "three_body", "twosphere_potential_l2"])
+@pytest.mark.parametrize("name", ["sphere_plate", "three_body", "twosphere_potential_l2", "stern_plate",
+                                  "nested_plate"])
 @pytest.mark.parametrize("treecode", [0, 1])
 def test_transpose_identity(name, treecode):
     s, _ = from_problem(case(name), treecode=treecode, ncrit=24, theta=0.5, taylor_p=6)
@@ -42,7 +43,7 @@ def test_transpose_identity(name, treecode):
         assert rel_inf(atl32, atl) < 5e-5
 
 
-@pytest.mark.parametrize("name", ["kirkwood_l1", "sphere_plate", "three_body"])
+@pytest.mark.parametrize("name", ["kirkwood_l1", "sphere_plate", "three_body", "stern_plate_k0", "nested_plate"])
 def test_direct_transpose_matches_oracle(name):
     A, _ = DenseBEM(case(name)).assemble()
     s, _ = from_problem(case(name), treecode=0)
@@ -62,6 +63,44 @@ def test_gradient_matches_oracle_dense_transpose():
     ds, dq = s.gradient(ids[1], pr.surfaces[1].nt, ids[0], len(pr.surfaces[0].q))
     assert rel_inf(dq, g_or[0]) < 1e-6
     assert rel_inf(ds, g_or[1]) < 1e-6
+
+
+def test_gradient_with_stern_layer_and_cavity():
+    """Nested interfaces on the adjoint path: the gradient of F_int with a
+    Stern layer and a cavity (the molecule isolated with both) against the
+    oracle's dense transpose, FP64 direct; and the treecode's against central
+    differences of its own F_int (exactly quadratic in q and sigma)."""
+    pr = case("nested_plate")
+    g_or = interaction_gradient(pr)
+    s, ids = from_problem(pr, treecode=0, tol=1e-11)
+    ds, dq = s.gradient(ids[2], pr.surfaces[2].nt, ids[0], len(pr.surfaces[0].q))
+    assert rel_inf(dq, g_or[0]) < 1e-6
+    assert rel_inf(ds, g_or[2]) < 1e-6
+    s.close()
+    s, ids = from_problem(pr, treecode=1, ncrit=24, theta=0.5, taylor_p=6, tol=1e-11)
+    ds, dq = s.gradient(ids[2], pr.surfaces[2].nt, ids[0], len(pr.surfaces[0].q))
+    q0, s0 = pr.surfaces[0].q.copy(), pr.surfaces[2].bc.copy()
+
+    def fint(q, sig):
+        s.set_charges(ids[0], pr.surfaces[0].eps_in, pr.surfaces[0].q_pos, q)
+        s.set_bc(ids[2], sig)
+        return s.interaction_energy(len(pr.surfaces))[0]
+
+    for j in (3, 200):
+        h = 0.05
+        sp, sm = s0.copy(), s0.copy()
+        sp[j] += h
+        sm[j] -= h
+        fd = (fint(q0, sp) - fint(q0, sm)) / (2 * h)
+        assert abs(fd - ds[j]) <= 2e-5 * np.max(np.abs(ds)), (j, fd, ds[j])
+    for k in range(len(q0)):
+        h = 0.5
+        qp, qm = q0.copy(), q0.copy()
+        qp[k] += h
+        qm[k] -= h
+        fd = (fint(qp, s0) - fint(qm, s0)) / (2 * h)
+        assert abs(fd - dq[k]) <= 2e-5 * np.max(np.abs(dq)), (k, fd, dq[k])
+    s.close()
 
 
 @pytest.mark.parametrize("prec", [FP64, MIXED])

@@ -245,15 +245,11 @@ def test_kirkwood_stern_against_closed_form():
 
 
 def test_stern_unsupported_paths():
-    """Paths without Stern-layer support refuse instead of computing
-    something else; a Stern surface cannot be solved without its molecule."""
+    """The batched path does not take Stern surfaces or cavities and refuses
+    instead of computing something else; a Stern surface or a cavity cannot
+    be solved without its molecule."""
     pr = case("stern_plate")
     s, ids = from_problem(pr, treecode=0)
-    n = s.num_unknowns()
-    with pytest.raises(PbtError, match="INVALID"):
-        s.matvec(np.ones(n), transpose=True)
-    with pytest.raises(PbtError, match="INVALID"):
-        s.gradient(ids[2], pr.surfaces[2].nt, ids[0], 2)
     with pytest.raises(PbtError, match="INVALID"):
         s.solve_batch(ids[0], np.eye(3)[None], np.zeros((1, 3)))
     s.close()
@@ -264,8 +260,6 @@ def test_stern_unsupported_paths():
     s2.close()
     pr3 = case("nested_plate")
     s3, ids3 = from_problem(pr3, treecode=0)
-    with pytest.raises(PbtError, match="INVALID"):
-        s3.matvec(np.ones(s3.num_unknowns()), transpose=True)
     s3.enable(ids3[1], False)   # the Stern surface off: molecule, cavity and plate remain
     s3.solve()
     s3.enable(ids3[0], False)   # the cavity without its molecule

@@ -255,3 +255,45 @@ def test_adjoint_gradient_is_exact_for_quadratic_form():
         pm.surfaces[0].q[k] -= h
         fd = (F(pp) - F(pm)) / (2 * h)
         assert abs(fd - g[0][k]) < 1e-8 * abs(g[0][k])
+
+
+def test_adjoint_gradient_with_stern_layer_and_cavity():
+    """The same exactness with a Stern layer and a cavity around / inside the
+    molecule: the gradient through the dense transpose (cavity terms in the
+    reaction potential, the Coulomb sum on the cavity's outside rows, the
+    charged surface seen only by the solvent's rows) matches central
+    differences of F_int, the molecule isolated with its Stern surface and
+    cavity."""
+    from workloads.meshes import icosphere
+    from workloads.problems import CAVITY, CHARGED, MOLECULE, STERN, Problem, Surface
+    rng = np.random.default_rng(1)
+    v, t = icosphere(1, 4.0, (0.0, 0.0, 0.0))
+    mol = Surface(MOLECULE, v, t, eps_in=4.0, q_pos=np.array([[0, 0, 0.0], [1.0, 0.5, 0.3]]),
+                  q=np.array([1.0, -0.5]))
+    v, t = icosphere(1, 5.5, (0.0, 0.0, 0.0))
+    stern = Surface(STERN, v, t, eps_in=40.0, parent=0)
+    v, t = icosphere(1, 1.0, (-1.8, 0.6, 0.0))
+    cav = Surface(CAVITY, v, t, eps_in=80.0, parent=0)
+    v, t = icosphere(1, 3.0, (0.0, 0.0, 11.0))
+    pl = Surface(CHARGED, v, t, bc=0.05 * (1 + 0.3 * rng.uniform(-1, 1, len(t))))
+    p = Problem([mol, stern, cav, pl], 80.0, 0.125, {}, "nested_gradient")
+    g = interaction_gradient(p)
+    assert g[1] is None and g[2] is None
+
+    def F(pp):
+        return interaction_energy(pp)[0]
+
+    for j in (0, 41):
+        h = 0.02
+        pp, pm = copy.deepcopy(p), copy.deepcopy(p)
+        pp.surfaces[3].bc[j] += h
+        pm.surfaces[3].bc[j] -= h
+        fd = (F(pp) - F(pm)) / (2 * h)
+        assert abs(fd - g[3][j]) < 1e-8 * abs(g[3][j])
+    for k in (0, 1):
+        h = 0.3
+        pp, pm = copy.deepcopy(p), copy.deepcopy(p)
+        pp.surfaces[0].q[k] += h
+        pm.surfaces[0].q[k] -= h
+        fd = (F(pp) - F(pm)) / (2 * h)
+        assert abs(fd - g[0][k]) < 1e-8 * abs(g[0][k])
