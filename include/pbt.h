@@ -148,9 +148,9 @@ pbt_status pbt_set_charges(pbt_ctx* ctx, int32_t mol_id, double eps_in, const do
  * carries phi and dphi/dn (layer side), like a molecule.  One Stern surface
  * per molecule; both must be enabled together in a solve (PBT_E_STATE
  * otherwise).  The transposed product and pbt_gradient take Stern surfaces
- * (the molecule is isolated together with its Stern surface);
- * pbt_solve_batch does not (PBT_E_INVALID).  Before the geometry is frozen
- * (PBT_E_STATE after). */
+ * (the molecule is isolated together with its Stern surface), and so does
+ * pbt_solve_batch (the Stern surface moves with its molecule).  Before the
+ * geometry is frozen (PBT_E_STATE after). */
 pbt_status pbt_set_stern(pbt_ctx* ctx, int32_t stern_id, int32_t mol_id, double eps_layer);
 
 /* Solvent-filled cavity (the other nested interface of Section 2's closing
@@ -163,7 +163,8 @@ pbt_status pbt_set_stern(pbt_ctx* ctx, int32_t stern_id, int32_t mol_id, double 
  * equation; the reaction potential at the charges includes the cavity's
  * terms.  A molecule may hold several cavities; each must be enabled
  * with its molecule (PBT_E_STATE otherwise).  Like Stern surfaces, taken by
- * the transpose and pbt_gradient, not by pbt_solve_batch (PBT_E_INVALID).
+ * the transpose, pbt_gradient and pbt_solve_batch (cavities move with their
+ * molecule).
  * Before the geometry is frozen (PBT_E_STATE after). */
 pbt_status pbt_set_cavity(pbt_ctx* ctx, int32_t cav_id, int32_t mol_id, double eps_cavity);
 
@@ -233,8 +234,9 @@ pbt_status pbt_gradient(pbt_ctx* ctx, int32_t sigma_id, double* dF_dsigma, int32
  * body-frame coordinates x map to R_b x + t_b with R_b = rot[9b..9b+8]
  * (row-major) and t_b = shift[3b..3b+2].  The isolated energies are computed
  * once; the nb assembly systems are solved together in lock-step batches.
- * F_int: nb doubles (kcal/mol).  The molecule's stored geometry is left
- * unchanged. */
+ * The molecule's Stern surface and cavities move with it; every other
+ * enabled surface stays.  F_int: nb doubles (kcal/mol).  The stored
+ * geometry is left unchanged. */
 pbt_status pbt_solve_batch(pbt_ctx* ctx, int32_t mol_id, const double* rot, const double* shift,
                            int32_t nb, double* F_int);
 

@@ -598,24 +598,27 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
       if (!std::isfinite(rot[i])) return fail(c, PBT_E_INVALID, "non-finite rotation");
     for (int64_t i = 0; i < 3LL * nb; ++i)
       if (!std::isfinite(shift[i])) return fail(c, PBT_E_INVALID, "non-finite shift");
-    for (int i = 0; i < ns; ++i)
-      if ((c->surfs[i]->kind == PBT_STERN || c->surfs[i]->kind == PBT_CAVITY) && c->surfs[i]->enabled)
-        return fail(c, PBT_E_INVALID, "batched placements do not take Stern surfaces or cavities");
     if (nb == 0) return PBT_OK;
     std::vector<bool> saved = mask_of(c);
     auto restore = [&] { for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = saved[i]; };
+    // the moving component: the molecule with its Stern surface and cavities
+    auto nested_in = [&](int i, int root) { return c->surfs[i]->parent == c->surfs[root].get(); };
+    std::vector<char> moving(ns, 0);
+    for (int i = 0; i < ns; ++i) moving[i] = i == mol_id || (saved[i] && nested_in(i, mol_id));
     std::vector<int> others;
     for (int i = 0; i < ns; ++i)
-      if (saved[i] && i != mol_id) others.push_back(i);
-    // isolated energies, once
+      if (saved[i] && !moving[i]) others.push_back(i);
+    // isolated energies, once: one solve per component (a molecule with its
+    // nested surfaces, or any other surface alone)
     double f_iso = 0.0;
     pbt_status worst = PBT_OK;
     try {
-      for (int k : std::vector<int>{mol_id}) (void)k;
-      std::vector<int> comps{mol_id};
-      comps.insert(comps.end(), others.begin(), others.end());
+      std::vector<int> comps;
+      for (int i = 0; i < ns; ++i)
+        if ((i == mol_id || saved[i]) && c->surfs[i]->kind != PBT_STERN && c->surfs[i]->kind != PBT_CAVITY)
+          comps.push_back(i);
       for (int k : comps) {
-        for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = i == k;
+        for (int i = 0; i < ns; ++i) c->surfs[i]->enabled = i == k || (saved[i] && nested_in(i, k));
         pbt_result r{};
         pbt_status st = solve_impl(c, nullptr, &r);
         if (st != PBT_OK && st != PBT_E_NOCONVERGE) { restore(); return st; }
@@ -628,7 +631,10 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
     }
     restore();
     const int kBatch = 64;
-    const SurfIn& M = *c->surfs[mol_id];
+    std::vector<int> placed;   // the surfaces of one placement: the moving ones, then the others
+    for (int i = 0; i < ns; ++i)
+      if (moving[i]) placed.push_back(i);
+    placed.insert(placed.end(), others.begin(), others.end());
     for (int b0 = 0; b0 < nb; b0 += kBatch) {
       const int G = std::min(kBatch, nb - b0);
       std::vector<std::unique_ptr<SurfIn>> own;
@@ -643,18 +649,24 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
               o[i + d] = R[3 * d] * in[i] + R[3 * d + 1] * in[i + 1] + R[3 * d + 2] * in[i + 2] + t[d];
           return o;
         };
-        auto m = std::make_unique<SurfIn>(M);
-        m->xyz = mv(M.xyz);
-        m->qxyz = mv(M.qxyz);
-        m->group = g;
-        list.push_back(m.get());
-        own.push_back(std::move(m));
-        for (int k : others) {
-          auto o = std::make_unique<SurfIn>(*c->surfs[k]);
+        std::vector<std::pair<const SurfIn*, SurfIn*>> copies;   // original -> this placement's copy
+        for (int k : placed) {
+          const SurfIn& S0 = *c->surfs[k];
+          auto o = std::make_unique<SurfIn>(S0);
+          if (moving[k]) {
+            o->xyz = mv(S0.xyz);
+            o->qxyz = mv(S0.qxyz);
+          }
           o->group = g;
+          copies.push_back({&S0, o.get()});
           list.push_back(o.get());
           own.push_back(std::move(o));
         }
+        // nested surfaces point at their molecule's copy in the same placement
+        for (auto& cp : copies)
+          if (cp.second->parent)
+            for (auto& q : copies)
+              if (q.first == cp.second->parent) cp.second->parent = q.second;
       }
       const double ts = wall_now();
       System S(list, c->prm, c->eps_out, c->kappa, c->stream);

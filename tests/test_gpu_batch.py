@@ -15,7 +15,7 @@ import pytest
 from oracle.bem import interaction_energy
 from paper_1506_03745_amd import MIXED, from_problem
 from workloads.meshes import box_plate, icosphere
-from workloads.problems import CHARGED, MOLECULE, Problem, Surface, random_rotations
+from workloads.problems import CAVITY, CHARGED, MOLECULE, STERN, Problem, Surface, random_rotations
 
 pytestmark = pytest.mark.gpu
 
@@ -31,9 +31,11 @@ def body_problem():
 
 def placed(pr, R, t):
     p = copy.deepcopy(pr)
-    m = p.surfaces[0]
-    m.verts = m.verts @ R.T + t
-    m.q_pos = m.q_pos @ R.T + t
+    for k, m in enumerate(p.surfaces):
+        if k == 0 or m.parent == 0:   # the molecule and its nested surfaces move
+            m.verts = m.verts @ R.T + t
+            if m.q_pos is not None:
+                m.q_pos = m.q_pos @ R.T + t
     return p
 
 
@@ -73,3 +75,35 @@ def test_batch_mixed_treecode():
     scale = abs(e.F_solv) + abs(e.F_surf)
     assert np.max(np.abs(f_batch - f_ref)) <= 2e-4 * scale
     assert len(set(np.round(f_ref, 8))) > 1   # placements differ
+
+
+def nested_body_problem():
+    """The batch body with a Stern layer (r = 3.6 A, permittivity 20) and an
+    off-centre water cavity that move with the molecule."""
+    pr = body_problem()
+    v, t = icosphere(2, 3.6, (0.0, 0.0, 0.0))
+    pr.surfaces.append(Surface(STERN, v, t, eps_in=20.0, parent=0))
+    v, t = icosphere(1, 0.8, (1.2, 0.8, -0.6))
+    pr.surfaces.append(Surface(CAVITY, v, t, eps_in=80.0, parent=0))
+    return pr
+
+
+def test_batch_with_stern_layer_and_cavity():
+    """Placements of a molecule with its Stern surface and cavity: each
+    batched F_int equals a separate solve of the moved assembly (FP64
+    direct), and one placement the oracle's."""
+    pr = nested_body_problem()
+    nb = 3
+    R, t = placements(nb)
+    t[:, 2] = 5.2      # the Stern surface clears the plate
+    s, ids = from_problem(pr, treecode=0, tol=1e-10)
+    f_batch = s.solve_batch(ids[0], R.reshape(nb, 9), t)
+    for b in range(nb):
+        pb = placed(pr, R[b], t[b])
+        sb, _ = from_problem(pb, treecode=0, tol=1e-10)
+        f, res = sb.interaction_energy(len(pb.surfaces))
+        scale = abs(res[0].F_solv) + abs(res[0].F_surf)
+        assert abs(f_batch[b] - f) <= 1e-7 * scale, (b, f_batch[b], f)
+        sb.close()
+    f_or, e_all, _ = interaction_energy(placed(pr, R[1], t[1]))
+    assert abs(f_batch[1] - f_or) <= 1e-6 * (abs(e_all.F_solv) + abs(e_all.F_surf))

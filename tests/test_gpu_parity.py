@@ -244,15 +244,9 @@ def test_kirkwood_stern_against_closed_form():
     s.close()
 
 
-def test_stern_unsupported_paths():
-    """The batched path does not take Stern surfaces or cavities and refuses
-    instead of computing something else; a Stern surface or a cavity cannot
-    be solved without its molecule."""
+def test_nested_surfaces_need_their_molecule():
+    """A Stern surface or a cavity cannot be solved without its molecule."""
     pr = case("stern_plate")
-    s, ids = from_problem(pr, treecode=0)
-    with pytest.raises(PbtError, match="INVALID"):
-        s.solve_batch(ids[0], np.eye(3)[None], np.zeros((1, 3)))
-    s.close()
     s2, ids2 = from_problem(pr, treecode=0)
     s2.enable(ids2[0], False)
     with pytest.raises(PbtError, match="STATE"):
