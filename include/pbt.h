@@ -133,7 +133,10 @@ pbt_status pbt_set_bc(pbt_ctx* ctx, int32_t id, const double* bc);
 
 /* Interior permittivity and point charges of molecule `mol_id` (eq. pde:
  * eps_1 and q_k at r_k).  xyz: nq*3 doubles (A), q: nq doubles (e).
- * Allowed at any time; nq may be 0. */
+ * Allowed at any time; nq may be 0.  PBT_E_INVALID if a charge lies outside
+ * the molecule's surface or inside one of its cavities (winding number of
+ * the triangle mesh about the charge, tested whenever the positions
+ * change). */
 pbt_status pbt_set_charges(pbt_ctx* ctx, int32_t mol_id, double eps_in, const double* xyz,
                            const double* q, int64_t nq);
 
@@ -165,6 +168,7 @@ pbt_status pbt_set_stern(pbt_ctx* ctx, int32_t stern_id, int32_t mol_id, double 
  * with its molecule (PBT_E_STATE otherwise).  Like Stern surfaces, taken by
  * the transpose, pbt_gradient and pbt_solve_batch (cavities move with their
  * molecule).
+ * PBT_E_INVALID if one of the molecule's charges lies inside the cavity.
  * Before the geometry is frozen (PBT_E_STATE after). */
 pbt_status pbt_set_cavity(pbt_ctx* ctx, int32_t cav_id, int32_t mol_id, double eps_cavity);
 

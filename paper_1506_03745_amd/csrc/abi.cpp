@@ -11,10 +11,55 @@
 #include <vector>
 
 #include "../../include/pbt.h"
+#include "parallel.h"
 #include "quadrature.h"
 #include "system.h"
 
 using namespace pbt;
+
+namespace {
+
+// Winding number of a closed triangle mesh (outward orientation) about point
+// p: the solid angles of its triangles summed over 4 pi, each from the
+// formula of Van Oosterom and Strackee, tan(Omega / 2) = a . (b x c) /
+// (|a||b||c| + (a . b)|c| + (a . c)|b| + (b . c)|a|) with a, b, c the
+// corners relative to p.  1 inside, 0 outside.
+double winding_number(const SurfIn& S, const double* p) {
+  double w = 0.0;
+  for (int64_t t = 0; t < S.nt; ++t) {
+    double v[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int d = 0; d < 3; ++d) v[k][d] = S.xyz[3 * S.tri[3 * t + k] + d] - p[d];
+    const double* a = v[0];
+    const double* b = v[1];
+    const double* c = v[2];
+    const double la = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    const double lb = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    const double lc = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    const double num = a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
+                       a[2] * (b[0] * c[1] - b[1] * c[0]);
+    const double ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    const double ac = a[0] * c[0] + a[1] * c[1] + a[2] * c[2];
+    const double bc = b[0] * c[0] + b[1] * c[1] + b[2] * c[2];
+    w += 2.0 * std::atan2(num, la * lb * lc + ab * lc + ac * lb + bc * la);
+  }
+  return w / (4.0 * M_PI);
+}
+
+// Index of the first of nq points whose winding number about S is on the
+// wrong side (inside = true: must be > 1/2), or -1.
+int64_t first_misplaced(const SurfIn& S, const double* xyz, int64_t nq, bool inside) {
+  std::vector<char> bad(nq, 0);
+  parallel_for(nq, [&](int64_t k) {
+    const double w = winding_number(S, xyz + 3 * k);
+    bad[k] = inside ? !(w > 0.5) : !(w < 0.5);
+  }, 4);
+  for (int64_t k = 0; k < nq; ++k)
+    if (bad[k]) return k;
+  return -1;
+}
+
+}  // namespace
 
 struct pbt_ctx {
   int device = 0;
@@ -328,6 +373,17 @@ pbt_status pbt_set_charges(pbt_ctx* c, int32_t mol_id, double eps_in, const doub
   for (int64_t i = 0; i < nq; ++i)
     if (!std::isfinite(q[i])) return fail(c, PBT_E_INVALID, "non-finite charge");
   SurfIn& s = *c->surfs[mol_id];
+  // charges lie in the molecule's interior region: inside its surface and
+  // outside its cavities (checked when their positions change)
+  if (nq > 0 && !(s.qxyz.size() == (size_t)(3 * nq) && std::equal(xyz, xyz + 3 * nq, s.qxyz.begin()))) {
+    const int64_t k = first_misplaced(s, xyz, nq, true);
+    if (k >= 0) return fail(c, PBT_E_INVALID, "charge " + std::to_string(k) + " lies outside its molecule");
+    for (const auto& cv : c->surfs)
+      if (cv->kind == PBT_CAVITY && cv->parent == &s) {
+        const int64_t kc = first_misplaced(*cv, xyz, nq, false);
+        if (kc >= 0) return fail(c, PBT_E_INVALID, "charge " + std::to_string(kc) + " lies inside a cavity");
+      }
+  }
   if (c->frozen && s.eps_in != eps_in) {
     // eps_in enters the operator: drop prepared systems that contain it
     c->systems.clear();
@@ -365,6 +421,9 @@ pbt_status pbt_set_cavity(pbt_ctx* c, int32_t cav_id, int32_t mol_id, double eps
     return fail(c, PBT_E_INVALID, "not a molecule id");
   if (!(eps_cavity > 0) || !std::isfinite(eps_cavity)) return fail(c, PBT_E_INVALID, "eps_cavity must be > 0");
   if (c->frozen) return fail(c, PBT_E_STATE, "geometry is frozen after the first solve");
+  const SurfIn& M = *c->surfs[mol_id];
+  const int64_t k = first_misplaced(*c->surfs[cav_id], M.qxyz.data(), (int64_t)M.q.size(), false);
+  if (k >= 0) return fail(c, PBT_E_INVALID, "charge " + std::to_string(k) + " lies inside the cavity");
   c->surfs[cav_id]->parent = c->surfs[mol_id].get();
   c->surfs[cav_id]->eps_in = eps_cavity;
   return PBT_OK;

@@ -244,6 +244,20 @@ def test_kirkwood_stern_against_closed_form():
     s.close()
 
 
+def test_cavity_must_not_hold_charges():
+    """A cavity is charge-free: declaring one around a charge, or moving a
+    charge into one, is refused."""
+    pr = case("nested_plate")
+    s, ids = from_problem(pr, treecode=0)
+    cav = pr.surfaces[3]
+    with pytest.raises(PbtError, match="inside a cavity"):
+        s.set_charges(ids[0], 2.0, np.array([[-1.2, 0.7, 4.3]]), np.array([1.0]))
+    c2 = s.add_surface(4, cav.verts - cav.verts.mean(0) + pr.surfaces[0].q_pos[0], cav.tris)
+    with pytest.raises(PbtError, match="inside the cavity"):
+        s.set_cavity(c2, ids[0], 80.0)
+    s.close()
+
+
 def test_nested_surfaces_need_their_molecule():
     """A Stern surface or a cavity cannot be solved without its molecule."""
     pr = case("stern_plate")
@@ -373,6 +387,10 @@ def test_error_paths():
         s2.add_surface(0, v, pr.surfaces[0].tris)
     with pytest.raises(PbtError, match="INVALID"):
         s2.set_solvent(-1.0, 0.1)
+    # charges must lie inside their molecule (winding number of its mesh)
+    with pytest.raises(PbtError, match="outside its molecule"):
+        s2.set_charges(0, 4.0, np.array([[0.0, 0.0, 4.5]]), np.array([1.0]))
+    s2.set_charges(0, 4.0, np.array([[0.0, 0.0, 3.5]]), np.array([1.0]))
     s2.solve()
     with pytest.raises(PbtError, match="STATE"):
         s2.add_surface(0, pr.surfaces[0].verts, pr.surfaces[0].tris)
