@@ -510,16 +510,39 @@ void System::build_plan() {
   Plan& P = plan_;
   P = Plan{};
   const int ns = (int)surfs_.size();
-  struct LeafRef { int e; int b; };
+  // Target groups: each leaf's panels in runs of at most 64 (one chunk each,
+  // spatially compact in the leaf's octant order), every group with the
+  // sphere of its own collocation points, so the acceptance test is taken
+  // per 64 targets rather than per leaf (Section 3.2 states it per target).
+  struct LeafRef { int e; int b; TreeBox tb; };
   std::vector<LeafRef> leaves;
   for (int e = 0; e < ns; ++e)
-    for (size_t b = 0; b < trees_[e].boxes.size(); ++b)
-      if (trees_[e].boxes[b].leaf) leaves.push_back({e, (int)b});
+    for (size_t b = 0; b < trees_[e].boxes.size(); ++b) {
+      const TreeBox& lb = trees_[e].boxes[b];
+      if (!lb.leaf) continue;
+      for (int32_t t0 = lb.pbeg; t0 < lb.pend; t0 += 64) {
+        TreeBox g = lb;
+        g.pbeg = t0;
+        g.pend = std::min<int32_t>(lb.pend, t0 + 64);
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int32_t k = g.pbeg; k < g.pend; ++k)
+          for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], h_cen_[3 * (poff_[e] + k) + d]);
+            hi[d] = std::max(hi[d], h_cen_[3 * (poff_[e] + k) + d]);
+          }
+        for (int d = 0; d < 3; ++d) g.tc[d] = 0.5 * (lo[d] + hi[d]);
+        double r2 = 0.0;
+        for (int32_t k = g.pbeg; k < g.pend; ++k) {
+          const double* x = &h_cen_[3 * (poff_[e] + k)];
+          r2 = std::max(r2, (x[0] - g.tc[0]) * (x[0] - g.tc[0]) + (x[1] - g.tc[1]) * (x[1] - g.tc[1]) +
+                                (x[2] - g.tc[2]) * (x[2] - g.tc[2]));
+        }
+        g.tr = std::sqrt(r2) * (1.0 + 1e-12);
+        leaves.push_back({e, (int)b, g});
+      }
+    }
   leaves_.clear();
-  for (const LeafRef& l : leaves) {
-    const TreeBox& tb = trees_[l.e].boxes[l.b];
-    leaves_.push_back({l.e, l.b, poff_[l.e] + tb.pbeg, poff_[l.e] + tb.pend});
-  }
+  for (const LeafRef& l : leaves) leaves_.push_back({l.e, l.b, poff_[l.e] + l.tb.pbeg, poff_[l.e] + l.tb.pend});
   // the surfaces of each group (a leaf only interacts with its own group's)
   group_surfs_.clear();
   for (int e = 0; e < ns; ++e) {
@@ -537,7 +560,7 @@ void System::build_plan() {
   // (per leaf in parallel; the counts are added up afterwards)
   std::vector<std::array<int64_t, 5>> cnt(leaves.size(), {0, 0, 0, 0, 0});
   parallel_for((int64_t)leaves.size(), [&](int64_t li) {
-    const TreeBox& tl = trees_[leaves[li].e].boxes[leaves[li].b];
+    const TreeBox& tl = leaves[li].tb;
     const int64_t nt = tl.pend - tl.pbeg;
     std::array<int64_t, 5>& c = cnt[li];   // tot_src, tot_box, p2p, m2p, fused
     const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
@@ -592,7 +615,7 @@ void System::build_plan() {
   P.chunk_of.assign(np_, 0);
   std::map<int, int32_t> gchunks;
   for (size_t li = 0; li < leaves.size(); ++li) {
-    const TreeBox& tl = trees_[leaves[li].e].boxes[leaves[li].b];
+    const TreeBox& tl = leaves[li].tb;
     leaf_chunk0[li] = (int)P.chunks.size();
     const int grp = surfs_[leaves[li].e]->group;
     const int64_t g0 = poff_[leaves[li].e] + tl.pbeg, g1 = poff_[leaves[li].e] + tl.pend;

@@ -3,10 +3,12 @@
 // by a multipole-acceptance criterion theta, direct sums otherwise).
 //
 // Boxes are cubes split into octants while they hold more than N_crit
-// panels; panels are reordered so that every box owns a contiguous range.
+// panels; panels are reordered so that every box owns a contiguous range,
+// and inside a leaf by finer octants (its 64-panel runs are compact).
 // Expansion centre of a box: centre of the bounding box of its Gauss points;
 // radius: the largest distance from that centre to one of them.  A target
-// leaf T accepts a source box B for the far field when
+// group T (a run of at most 64 collocation points of one leaf) accepts a
+// source box B for the far field when
 //     r_B < theta * (|c_T - c_B| - r_T),
 // r_T being the radius of T's collocation points about their own centre, so
 // that every target x in T satisfies r_B / |x - c_B| < theta.
@@ -19,6 +21,35 @@ namespace pbt {
 
 namespace {
 
+// Orders idx[beg, end) by recursive octants of the cube (c, half) down to
+// groups of at most 8 points, so that consecutive runs of a leaf's panels
+// (the 64-target chunks the work is cut into) are spatially compact.
+void order_octants(const double* cen, std::vector<int32_t>& idx, int beg, int end, const double c[3], double half,
+                   int depth) {
+  if (end - beg <= 8 || depth >= 20) return;
+  int cnt[8] = {0};
+  std::vector<int8_t> oct(end - beg);
+  for (int i = beg; i < end; ++i) {
+    const double* p = cen + 3 * (int64_t)idx[i];
+    const int o = (p[0] > c[0] ? 1 : 0) | (p[1] > c[1] ? 2 : 0) | (p[2] > c[2] ? 4 : 0);
+    oct[i - beg] = (int8_t)o;
+    ++cnt[o];
+  }
+  int start[8], pos[8];
+  start[0] = beg;
+  for (int o = 1; o < 8; ++o) start[o] = start[o - 1] + cnt[o - 1];
+  for (int o = 0; o < 8; ++o) pos[o] = start[o] - beg;
+  std::vector<int32_t> tmp(end - beg);
+  for (int i = beg; i < end; ++i) tmp[pos[oct[i - beg]]++] = idx[i];
+  std::copy(tmp.begin(), tmp.end(), idx.begin() + beg);
+  for (int o = 0; o < 8; ++o) {
+    if (cnt[o] == 0) continue;
+    const double h2 = half * 0.5;
+    const double cc[3] = {c[0] + ((o & 1) ? h2 : -h2), c[1] + ((o & 2) ? h2 : -h2), c[2] + ((o & 4) ? h2 : -h2)};
+    order_octants(cen, idx, start[o], start[o] + cnt[o], cc, h2, depth + 1);
+  }
+}
+
 void build_rec(SurfTree& t, const double* cen, std::vector<int32_t>& idx, int box, int beg, int end,
                const double c[3], double half, int level, int ncrit) {
   TreeBox& b = t.boxes[box];
@@ -27,6 +58,7 @@ void build_rec(SurfTree& t, const double* cen, std::vector<int32_t>& idx, int bo
   b.level = level;
   if (end - beg <= ncrit || level >= 40) {
     b.leaf = true;
+    order_octants(cen, idx, beg, end, c, half, 0);
     return;
   }
   // Counting partition into octants.
