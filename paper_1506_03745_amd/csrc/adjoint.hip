@@ -129,11 +129,19 @@ __global__ __launch_bounds__(256) void k_p2p_t(const Task* __restrict__ tasks, i
 }
 
 // M2P^T: one wavefront per (box, 64-target chunk).  Each lane computes the
-// Taylor coefficients of its target about the box centre; the weighted
-// coefficients are summed over the wavefront, one coefficient at a time.
+// Taylor coefficients of its target about the box centre; then, kBatch
+// coefficients at a time, the lanes store them weighted in LDS and lane k
+// adds up coefficient k over the 64 targets in lane order (four interleaved
+// partial sums, combined in a fixed order).  The reduction costs a few LDS
+// reads per lane and coefficient instead of a chain of cross-lane shuffles
+// per coefficient, and the batches keep the LDS per wave small enough not to
+// limit occupancy.
+constexpr int kLdsStride = 65;   // 64 targets + 1: lanes reading one column hit distinct banks
+constexpr int kBatch = 32;
+
 template <typename T, int P>
 __device__ __forceinline__ void taylor_reduce(T Rx, T Ry, T Rz, T kappa, T w, bool yuk,
-                                              T* __restrict__ out, int lane) {
+                                              T* __restrict__ out, int lane, T* lds) {
   constexpr int NC = ncoef(P);
   T A[NC];
   T B[NC];
@@ -144,8 +152,6 @@ __device__ __forceinline__ void taylor_reduce(T Rx, T Ry, T Rz, T kappa, T w, bo
   const T e = yuk ? AMath<T>::expm(kappa * (R2 * Rinv)) : T(1);
   A[0] = e * Rinv;
   B[0] = e;
-  T s0 = wave_sum(w * A[0]);
-  if (lane == 0) out[0] = s0;
 #pragma unroll
   for (int n = 1; n <= P; ++n) {
     const T c1 = T(2 * n - 1) / T(n) * invR2;
@@ -167,10 +173,27 @@ __device__ __forceinline__ void taylor_reduce(T Rx, T Ry, T Rz, T kappa, T w, bo
         if (c >= 2) { S2 += A[tidx(a, b, c - 2)]; T2 += B[tidx(a, b, c - 2)]; }
         A[k] = c1 * S1 - c2 * S2 + c3 * (T1 - T2);
         B[k] = c4 * (S1 - S2);
-        const T s = wave_sum(w * A[k]);
-        if (lane == 0) out[k] = s;
       }
     }
+  }
+#pragma unroll
+  for (int kb = 0; kb < NC; kb += kBatch) {
+#pragma unroll
+    for (int k = kb; k < kb + kBatch && k < NC; ++k) lds[(k - kb) * kLdsStride + lane] = w * A[k];
+    __syncthreads();
+    if (lane < kBatch && kb + lane < NC) {
+      const T* row = lds + lane * kLdsStride;
+      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll 4
+      for (int j = 0; j < 64; j += 4) {
+        s0 += row[j];
+        s1 += row[j + 1];
+        s2 += row[j + 2];
+        s3 += row[j + 3];
+      }
+      out[kb + lane] = (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
   }
 }
 
@@ -180,6 +203,7 @@ __global__ __launch_bounds__(64) void k_m2p_t(const Task* __restrict__ tasks, in
                                               const double* __restrict__ bcen, T kappa,
                                               T* __restrict__ mpart) {
   constexpr int NC = ncoef(P);
+  __shared__ T lds[kBatch * kLdsStride];
   const int wv = blockIdx.x;
   if (wv >= ntasks) return;
   const int lane = threadIdx.x;
@@ -197,26 +221,39 @@ __global__ __launch_bounds__(64) void k_m2p_t(const Task* __restrict__ tasks, in
   const T ku = (form & kFormKz) ? T(0) : kappa;
   const T wu = act && !drop ? (swap ? t[3] : t[4]) : T(0);
   const T wl = act ? (swap ? t[4] : t[3]) : T(0);
-  taylor_reduce<T, P>(Rx, Ry, Rz, ku, wu, true, out, lane);
+  taylor_reduce<T, P>(Rx, Ry, Rz, ku, wu, true, out, lane, lds);
   if (tasks[wv].fused) {
-    taylor_reduce<T, P>(Rx, Ry, Rz, kappa, wl, false, out + NC, lane);
+    taylor_reduce<T, P>(Rx, Ry, Rz, kappa, wl, false, out + NC, lane, lds);
   } else {
     for (int k = lane; k < NC; k += 64) out[NC + k] = T(0);
   }
 }
 
-// Per box: sum its M2P^T partial slots (fixed order) into Mbar[box][2][NC].
+// Per box: sum its M2P^T partial slots into Mbar[box][2][NC].  Block (box,
+// 64 coefficients): thread (k, p) adds every kParts-th slot from p on, then
+// the kParts partial sums are added in order; the order is fixed, and boxes
+// with thousands of slots no longer wait on one thread's chain of loads.
+constexpr int kParts = 16;
 template <typename T>
-__global__ void k_mbar_reduce(int nbox, int NC, const int32_t* __restrict__ sbeg,
-                              const int32_t* __restrict__ send, const T* __restrict__ mpart,
-                              T* __restrict__ mbar) {
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= (int64_t)nbox * 2 * NC) return;
-  const int b = (int)(id / (2 * NC));
-  const int rk = (int)(id - (int64_t)b * 2 * NC);
+__global__ __launch_bounds__(64 * kParts) void k_mbar_reduce(int nbox, int NC, const int32_t* __restrict__ sbeg,
+                                                             const int32_t* __restrict__ send,
+                                                             const T* __restrict__ mpart, T* __restrict__ mbar) {
+  __shared__ T red[kParts][64];
+  const int b = blockIdx.x;
+  const int kk = threadIdx.x & 63, p = threadIdx.x >> 6;
+  const int rk = blockIdx.y * 64 + kk;
   T s = 0;
-  for (int q = sbeg[b]; q < send[b]; ++q) s += mpart[(int64_t)q * 2 * NC + rk];
-  mbar[id] = s;
+  if (rk < 2 * NC) {
+#pragma unroll 4
+    for (int q = sbeg[b] + p; q < send[b]; q += kParts) s += mpart[(int64_t)q * 2 * NC + rk];
+  }
+  red[p][kk] = s;
+  __syncthreads();
+  if (p == 0 && rk < 2 * NC) {
+    T t = 0;
+    for (int i = 0; i < kParts; ++i) t += red[i][kk];
+    mbar[(int64_t)b * 2 * NC + rk] = t;
+  }
 }
 
 struct MidxT {
@@ -474,8 +511,8 @@ template <typename T>
 void launch_mbar_reduce(int nbox, int P, const int32_t* sbeg, const int32_t* send, const T* mpart,
                         T* mbar, hipStream_t s) {
   if (nbox <= 0) return;
-  const int64_t n = (int64_t)nbox * 2 * ncoef(P);
-  k_mbar_reduce<T><<<nblocks(n, 256), 256, 0, s>>>(nbox, ncoef(P), sbeg, send, mpart, mbar);
+  const dim3 grid((unsigned)nbox, (unsigned)((2 * ncoef(P) + 63) / 64));
+  k_mbar_reduce<T><<<grid, 64 * kParts, 0, s>>>(nbox, ncoef(P), sbeg, send, mpart, mbar);
   PBT_HIP(hipGetLastError());
 }
 
