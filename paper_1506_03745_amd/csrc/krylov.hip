@@ -138,6 +138,66 @@ __global__ __launch_bounds__(kBS) void k_gs_dots(const int64_t* __restrict__ gu,
   }
 }
 
+// The same partials for large groups (every thread several elements):
+// grid (nbj, 1, G), every block forms all mq outputs, kDotRows at a time, so
+// each element's basis entries are read about twice per pass instead of once
+// per group of 8 outputs (the y-split above reads the m rows of the update
+// ceil(mq / 8) times, which for long Krylov spaces dominates the traffic).
+// Per output the per-thread sums, wave sums and block sum are formed exactly
+// as in k_gs_dots, so both kernels give bitwise the same partials.
+constexpr int kDotRows = 32;
+template <bool UPDATE>
+__global__ __launch_bounds__(kBS) void k_gs_dots_rows(const int64_t* __restrict__ gu, int m, int R,
+                                                      const double* __restrict__ V, int64_t ldv,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ hpart, int nbh,
+                                                      double* __restrict__ hout, int self_dot,
+                                                      double* __restrict__ part) {
+  extern __shared__ double hs[];   // [m] (UPDATE)
+  __shared__ double red[kBS / 64][kDotRows];
+  const int nbj = gridDim.x;
+  const int g = blockIdx.z;
+  const int64_t u0 = gu[2 * g], u1 = gu[2 * g + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int mq = m + (self_dot ? 1 : 0);
+  const int64_t j0 = u0 + blockIdx.x * (int64_t)kBS + threadIdx.x;
+  if (UPDATE) {
+    reduce_rows(hpart + (int64_t)g * R * nbh, m, nbh, hs);
+    __syncthreads();
+    if (blockIdx.x == 0)
+      for (int i = threadIdx.x; i < m; i += kBS) hout[(int64_t)g * R + i] = hs[i];
+  }
+  for (int i0 = 0; i0 < mq; i0 += kDotRows) {
+    double acc[kDotRows];
+#pragma unroll
+    for (int q = 0; q < kDotRows; ++q) acc[q] = 0.0;
+    for (int64_t j = j0; j < u1; j += (int64_t)nbj * kBS) {
+      double wj = w[j];
+      if (UPDATE) {
+#pragma unroll 8
+        for (int i = 0; i < m; ++i) wj -= hs[i] * V[(int64_t)i * ldv + j];
+      }
+#pragma unroll
+      for (int q = 0; q < kDotRows; ++q) {
+        const int i = i0 + q;
+        if (i < mq) acc[q] += (i < m ? V[(int64_t)i * ldv + j] : wj) * wj;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kDotRows; ++q) {
+      const double sq = wave_sum(acc[q]);
+      if (lane == 0) red[wid][q] = sq;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDotRows && i0 + (int)threadIdx.x < mq) {
+      double sq = 0;
+      for (int k = 0; k < kBS / 64; ++k) sq += red[k][threadIdx.x];
+      part[((int64_t)g * R + i0 + threadIdx.x) * nbj + blockIdx.x] = sq;
+    }
+    __syncthreads();
+  }
+}
+
 // The rest of Arnoldi step j after the second Gram-Schmidt pass, grid
 // (blocks over the largest group, G).  Every block adds up its group's
 // partials of that pass (h2 and |w'|^2, j + 2 rows of nbj, in a fixed
@@ -360,9 +420,19 @@ int gs_blocks(int64_t n) { return (int)std::min<int64_t>(240, std::max<int64_t>(
 
 void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int64_t ldv, const double* w,
                     const double* hpart, int nbh, double* hout, int self_dot, double* part, int nbj,
-                    hipStream_t s) {
+                    hipStream_t s, bool all_rows) {
   const int mq = m + (self_dot ? 1 : 0);
   if (G <= 0 || mq <= 0) return;
+  if (all_rows && mq > 8) {
+    const dim3 grid(nbj, 1, G);
+    if (hpart)
+      k_gs_dots_rows<true><<<grid, kBS, (size_t)m * sizeof(double), s>>>(gu, m, R, V, ldv, w, hpart, nbh, hout,
+                                                                         self_dot, part);
+    else
+      k_gs_dots_rows<false><<<grid, kBS, 0, s>>>(gu, m, R, V, ldv, w, nullptr, 0, nullptr, self_dot, part);
+    PBT_HIP(hipGetLastError());
+    return;
+  }
   const dim3 grid(nbj, (mq + 7) / 8, G);
   if (hpart)
     k_gs_dots<true><<<grid, kBS, (size_t)m * sizeof(double), s>>>(gu, m, R, V, ldv, w, hpart, nbh, hout,

@@ -268,7 +268,7 @@ int gs_blocks(int64_t n);
 // hpart rows have stride nbh (the previous pass's block count).
 void launch_gs_dots(const int64_t* gu, int G, int m, int R, const double* V, int64_t ldv, const double* w,
                     const double* hpart, int nbh, double* hout, int self_dot, double* part, int nbj,
-                    hipStream_t s);
+                    hipStream_t s, bool all_rows = false);
 // Source records of the next Krylov vector, written by the Arnoldi update
 // (the strengths of launch_strengths_x, from the updated unknowns): panels
 // of group g are gp[2g] .. gp[2g+1], pmax is the largest group's panel

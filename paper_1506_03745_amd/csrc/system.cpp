@@ -1201,6 +1201,9 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   // The forward operator also forms the first Gram-Schmidt pass as it writes
   // its result (per-chunk partials, nbh per row).
   const int nbh = fuse ? plan_.nbh : nbj;
+  // groups of more than one element per thread: all dot rows per block
+  // (each basis entry read about twice per pass, not once per 8 rows)
+  const bool big = gmax_ > (int64_t)nbj * 256;
   auto enqueue_step = [&](int k) {
     double* vj1 = V_.p + (size_t)(k + 1) * n_;
     if (fuse) {
@@ -1208,9 +1211,9 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
       op(V_.p + (size_t)k * n_, vj1, fp32, s, k > 0, &dr);
     } else {
       op(V_.p + (size_t)k * n_, vj1, fp32, s);
-      launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, 0, nullptr, 0, part1, nbj, s);
+      launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, 0, nullptr, 0, part1, nbj, s, big);
     }
-    launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, nbh, h1, 1, part2, nbj, s);
+    launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, nbh, h1, 1, part2, nbj, s, big);
     launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, rs,
                           fuse ? &nsrc : nullptr, s);
   };
