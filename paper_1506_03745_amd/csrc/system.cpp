@@ -553,11 +553,11 @@ void System::build_plan() {
   lp2p_.assign(leaves.size(), {});
   lm2p_.assign(leaves.size(), {});
 
-  // Per leaf and source surface of its group (k-th of group_surfs_): merged
-  // P2P source ranges and M2P boxes.
+  // Per target group and source surface of its group of surfaces (k-th of
+  // group_surfs_): merged P2P source ranges and M2P boxes.
   struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
   std::vector<std::vector<Lists>> L(leaves.size());
-  // (per leaf in parallel; the counts are added up afterwards)
+  // (per target group in parallel; the counts are added up afterwards)
   std::vector<std::array<int64_t, 5>> cnt(leaves.size(), {0, 0, 0, 0, 0});
   parallel_for((int64_t)leaves.size(), [&](int64_t li) {
     const TreeBox& tl = leaves[li].tb;

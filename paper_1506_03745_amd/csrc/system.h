@@ -357,8 +357,9 @@ class System {
   int64_t seg_src_ = 0, seg_box_ = 0, seg_src_used_ = 0, seg_box_used_ = 0;
   void upload_plan(hipStream_t s);
 
-  // forward interaction lists per (target leaf, k-th source surface of the
-  // leaf's group in group_surfs_), for the transpose
+  // forward interaction lists per (target group, k-th source surface of the
+  // group's surfaces in group_surfs_), for the transpose; a target group is
+  // a run of at most 64 panels of leaf b of surface e, [g0, g1) globally
   struct LeafInfo { int e; int b; int64_t g0, g1; };
   std::vector<LeafInfo> leaves_;
   std::vector<std::vector<int>> group_surfs_;   // surfaces of each group, in order

@@ -31,8 +31,9 @@ SurfTree build_tree(const double* cen, int64_t nt, int ncrit);
 // src_local: (nt*K) x 3 Gauss points, both in the tree's internal order.
 void tree_geometry(SurfTree& t, const double* tgt_local, const double* src_local, int K);
 
-// Source boxes of tree `src` that target leaf `tleaf` (of any tree)
-// evaluates directly (leaves) or through their expansions.
+// Source boxes of tree `src` that the targets of `tleaf` (a target group:
+// its collocation-point sphere tc, tr) evaluate directly (leaves) or
+// through their expansions.
 void interaction_lists(const SurfTree& src, const TreeBox& tleaf, double theta,
                        std::vector<int>& p2p_boxes, std::vector<int>& m2p_boxes);
 
