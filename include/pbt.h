@@ -274,6 +274,18 @@ pbt_status pbt_set_schedule(pbt_ctx* ctx, int32_t mode);
  * pbt_set_schedule; pbt_autotune may have chosen it) in *mode.  Host-only. */
 pbt_status pbt_get_schedule(pbt_ctx* ctx, int32_t* mode);
 
+/* Orthogonalisation of the GMRES solver (Section 3.2 solves with GMRES) for
+ * every system of the context: passes = 2 applies classical Gram-Schmidt
+ * twice per Arnoldi step; passes = 1 applies it once and takes the new basis
+ * vector's norm from the same reduction by Pythagoras
+ * (|w - V h|^2 = |w|^2 - |h|^2), one pass over the basis fewer per step;
+ * passes = 0 (default) takes one pass for every GMRES run that aims at a
+ * relative residual reduction of at least 1e-7 (the inner solves of
+ * PBT_MIXED always do; PBT_FP64 solves with tol >= 1e-7 do) and two passes
+ * otherwise.  Takes effect from the next solve.  PBT_E_INVALID for another
+ * value.  Host-only. */
+pbt_status pbt_set_gram_schmidt(pbt_ctx* ctx, int32_t passes);
+
 /* Quadrature tables the library integrates with (Section 3.1): triangle rule
  * with npts points (1, 3, 4, 7 or 19) as barycentric coordinates
  * bary[3*npts] and weights w[npts] summing to 1, or, for npts < 0, the

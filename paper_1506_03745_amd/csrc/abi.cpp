@@ -70,6 +70,7 @@ struct pbt_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool frozen = false;
+  int gs_passes = 0;   // Gram-Schmidt passes per Arnoldi step (0 = automatic), every system
   // work of the last solve / interaction_energy / gradient / solve_batch call
   struct CallStats {
     double t0 = 0, t_setup = 0;
@@ -167,7 +168,10 @@ std::vector<bool> mask_of(const pbt_ctx* c) {
 System& system_for(pbt_ctx* c) {
   std::vector<bool> m = mask_of(c);
   auto it = c->systems.find(m);
-  if (it != c->systems.end()) return *it->second;
+  if (it != c->systems.end()) {
+    it->second->set_gs_passes(c->gs_passes);
+    return *it->second;
+  }
   std::vector<const SurfIn*> on;
   for (auto& s : c->surfs)
     if (s->enabled) on.push_back(s.get());
@@ -182,6 +186,7 @@ System& system_for(pbt_ctx* c) {
   auto sys = std::make_unique<System>(on, c->prm, c->eps_out, c->kappa, c->stream);
   c->cs.t_setup += wall_now() - t0;
   System& r = *sys;
+  r.set_gs_passes(c->gs_passes);
   c->systems[m] = std::move(sys);
   return r;
 }
@@ -848,6 +853,13 @@ pbt_status pbt_get_schedule(pbt_ctx* c, int32_t* mode) {
     *mode = system_for(c).far_mode();
     return PBT_OK;
   });
+}
+
+pbt_status pbt_set_gram_schmidt(pbt_ctx* c, int32_t passes) {
+  if (!c) return PBT_E_INVALID;
+  if (passes < 0 || passes > 2) return fail(c, PBT_E_INVALID, "Gram-Schmidt passes must be 0, 1 or 2");
+  c->gs_passes = passes;
+  return PBT_OK;
 }
 
 pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w) {

@@ -1,6 +1,6 @@
 // FP64 vector kernels of the GMRES solver (Section 3.2 names GMRES for the
 // discretised system; here restarted GMRES with classical Gram-Schmidt
-// applied twice).  Every kernel works on G independent systems at once:
+// applied twice, or once with the norm by Pythagoras).  Every kernel works on G independent systems at once:
 // the unknown vector is split into consecutive group ranges gu[2g] ..
 // gu[2g+1] and each group has its own Krylov space, Hessenberg matrix,
 // Givens rotations and residual estimate (one system is the case G = 1).
@@ -30,6 +30,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // zero.  The order of the additions is fixed, so every block that calls
 // this gets bitwise the same sums.
 constexpr int kRowBatch = 32;
+static_assert(8 * kRowBatch == kSumBatch, "one batch of loads per lane covers kSumBatch partials");
 __device__ __forceinline__ void reduce_rows(const double* __restrict__ part, int nrows, int nbj, double* out) {
   const int sub = threadIdx.x & 7;
   for (int r0 = 0; r0 < nrows; r0 += kBS / 8) {
@@ -207,7 +208,11 @@ __global__ __launch_bounds__(kBS) void k_gs_dots_rows(const int64_t* __restrict_
 // of each group also builds that group's Hessenberg column j: the previous
 // Givens rotations applied, the new one computed, and the residual estimate
 // |g_{j+1}| stored in resid[j].  Per group g: part + g R nbj, h1 + g R,
-// H + g (m + 1) m, cs/sn/resid + g m, gv + g (m + 1).  With SRC the threads
+// H + g (m + 1) m, cs/sn/resid + g m, gv + g (m + 1).  With h1 = null the
+// partials are those of a single pass (h and |w|^2) and the same formulas
+// give classical Gram-Schmidt once, |w'|^2 = |w|^2 - |h|^2 by Pythagoras
+// (Smoktunowicz, Barlow and Langou, Numer. Math. 105, 2006, bound its loss
+// of orthogonality like that of the pass itself).  With SRC the threads
 // run over the group's panels instead of its unknowns and also write the
 // panel densities and the source records (type T) of the new basis vector,
 // which the next operator application then takes as they are.
@@ -253,7 +258,7 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     rl = ns.rlap[p];
     dsc = ns.m.dens_scale[p];
   }
-  const double h1v = (int)threadIdx.x <= j ? h1[(int64_t)g * R + threadIdx.x] : 0.0;
+  const double h1v = h1 && (int)threadIdx.x <= j ? h1[(int64_t)g * R + threadIdx.x] : 0.0;
   const int32_t e = sub < 4 ? cphi : cpsi;
   constexpr int kPre = 8;
   double vr[kPre];
@@ -272,7 +277,7 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j; i += kBS) {
-    h[i] = (i == (int)threadIdx.x ? h1v : h1[(int64_t)g * R + i]) + h2[i];
+    h[i] = (i == (int)threadIdx.x ? h1v : h1 ? h1[(int64_t)g * R + i] : 0.0) + h2[i];
     col[i] = h[i];
   }
   if (threadIdx.x < 64) {
@@ -376,6 +381,17 @@ __global__ void k_group_row0(int R, int nbj, const double* __restrict__ part, do
   if (threadIdx.x == 0) out[g] = s;
 }
 
+// out[g R + i] = sum_b part[(g R + i) nbh + b], i < nrows: the rows of a
+// pass added up once, for the update to read as rows of one partial (with
+// many chunk partials per row, so that every block of the update does not
+// add them all up again).  Grid (ceil(nrows / 32), G); the sums are formed
+// by reduce_rows, in its fixed order.
+__global__ __launch_bounds__(kBS) void k_reduce_partials(int nrows, int R, int nbh,
+                                                         const double* __restrict__ part, double* out) {
+  const int g = blockIdx.y, r0 = blockIdx.x * (kBS / 8);
+  reduce_rows(part + ((int64_t)g * R + r0) * nbh, std::min(kBS / 8, nrows - r0), nbh, out + (int64_t)g * R + r0);
+}
+
 // Per group g: x += sum_{i < m} y[g ystride + i] V_i (y is zero past the
 // steps the group uses); grid (blocks over the largest group, G).
 __global__ void k_lincomb(const int64_t* __restrict__ gu, int m, int ystride, const double* __restrict__ V,
@@ -467,6 +483,12 @@ void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m,
 void launch_group_row0(int G, int R, int nbj, const double* part, double* out, hipStream_t s) {
   if (G <= 0) return;
   k_group_row0<<<G, 64, 0, s>>>(R, nbj, part, out);
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_reduce_partials(int G, int nrows, int R, int nbh, const double* part, double* out, hipStream_t s) {
+  if (G <= 0 || nrows <= 0) return;
+  k_reduce_partials<<<dim3((unsigned)((nrows + kBS / 8 - 1) / (kBS / 8)), G), kBS, 0, s>>>(nrows, R, nbh, part, out);
   PBT_HIP(hipGetLastError());
 }
 

@@ -203,11 +203,15 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(CombineArgs a, c
   }
   if (a.ndots <= 0) return;
   // first Gram-Schmidt pass: this chunk's rows of V_i . y, a wave per i
+  // (and y . y as row ndots when asked for)
   __syncthreads();
-  for (int k = w, t = 0; k < a.ndots; k += kCombineWaves, ++t) {
-    const double* Vk = a.V + (int64_t)k * a.ldv;
+  const int nd = a.ndots + (a.self_dot ? 1 : 0);
+  for (int k = w, t = 0; k < nd; k += kCombineWaves, ++t) {
     double pr = 0.0;
-    if (act) {
+    if (act && k == a.ndots) {
+      pr = yv[0][lane] * yv[0][lane] + yv[1][lane] * yv[1][lane];
+    } else if (act) {
+      const double* Vk = a.V + (int64_t)k * a.ldv;
       const double v0 = t == 0 ? vp[0][0] : t == 1 ? vp[1][0] : (ri >= 0 ? Vk[ri] : 0.0);
       const double v1 = t == 0 ? vp[0][1] : t == 1 ? vp[1][1] : Vk[rs];
       if (ri >= 0) pr = v0 * yv[0][lane];

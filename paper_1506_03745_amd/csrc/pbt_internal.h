@@ -157,10 +157,12 @@ struct CombineArgs {
   PanelMaps maps;
   int add_jump;
   // When ndots > 0, also the first Gram-Schmidt pass of the product: the
-  // chunk's part of V_i . y for i < ndots goes to dpart[(grp R + i) nbh + lchunk].
+  // chunk's part of V_i . y for i < ndots goes to dpart[(grp R + i) nbh + lchunk],
+  // and with self_dot that of y . y to row ndots.
   int ndots;
   const double* V; int64_t ldv;
   double* dpart; int R; int nbh;
+  int self_dot;
 };
 template <typename T>
 void launch_combine(const CombineArgs& a, const T* partial, const T* ppartial, double* y, hipStream_t s);
@@ -291,6 +293,11 @@ void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m,
                            double* H, double* cs, double* sn, double* gv, double* resid, const NextSrc* ns,
                            hipStream_t s);
 void launch_group_row0(int G, int R, int nbj, const double* part, double* out, hipStream_t s);
+// out[g R + i] = sum of the nbh partials of row i of group g, i < nrows
+// (rows of R per group in both), in a fixed order.  Rows of up to
+// kSumBatch partials are added with one batch of loads per lane.
+constexpr int kSumBatch = 256;
+void launch_reduce_partials(int G, int nrows, int R, int nbh, const double* part, double* out, hipStream_t s);
 // out[u2i[k]] = in[k] (to_internal) or out[k] = in[u2i[k]] (otherwise), k < n.
 void launch_permute(int64_t n, const int32_t* u2i, const double* in, double* out, bool to_internal,
                     hipStream_t s);

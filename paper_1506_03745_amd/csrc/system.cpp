@@ -959,6 +959,7 @@ void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStre
     a.dpart = dots->dpart;
     a.R = dots->R;
     a.nbh = plan_.nbh;
+    a.self_dot = dots->self_dot;
   }
   if (fp32) launch_combine<float>(a, part32_.p, ppart32_.p, y, s);
   else launch_combine<double>(a, part64_.p, ppart64_.p, y, s);
@@ -1181,6 +1182,17 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   // with x = 0 the residual is b, whose norms the caller may already have
   std::vector<double> beta = (x_zero && b_norms) ? *b_norms : group_norms(r_.p, s);
   resid_out = beta;
+  // Gram-Schmidt passes: automatic choice (0) takes one pass while every
+  // group aims at a relative reduction of at least 1e-7 (the basis then
+  // stays well enough conditioned for the loss of orthogonality of a single
+  // classical pass, about the rounding unit times the square of its
+  // condition, not to matter), two passes for tighter targets
+  int passes = gs_passes_;
+  if (passes == 0) {
+    passes = 1;
+    for (int g = 0; g < G; ++g)
+      if (beta[g] > 0 && tol_abs[g] < 1e-7 * beta[g]) passes = 2;
+  }
   auto pending = [&] {
     for (int g = 0; g < G; ++g)
       if (beta[g] > tol_abs[g]) return true;
@@ -1206,6 +1218,28 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   const bool big = gmax_ > (int64_t)nbj * 256;
   auto enqueue_step = [&](int k) {
     double* vj1 = V_.p + (size_t)(k + 1) * n_;
+    if (passes == 1) {
+      // one pass: h = V^T w and |w|^2 from one reduction, then the update
+      if (fuse) {
+        const DotReq dr{k + 1, V_.p, n_, part1, R, 1};
+        op(V_.p + (size_t)k * n_, vj1, fp32, s, k > 0, &dr);
+      } else {
+        op(V_.p + (size_t)k * n_, vj1, fp32, s);
+        launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, 0, nullptr, 1, part1, nbj, s, big);
+      }
+      // more chunk partials per row than one batch of loads per lane of the
+      // update's row sums: added up once, not again in every update block
+      const double* up = part1;
+      int ust = nbh;
+      if (nbh > kSumBatch) {
+        launch_reduce_partials(G, k + 2, R, nbh, part1, part2, s);
+        up = part2;
+        ust = 1;
+      }
+      launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, ust, up, nullptr, V_.p, n_, vj1, dH, dcs, dsn, dg, rs,
+                            fuse ? &nsrc : nullptr, s);
+      return;
+    }
     if (fuse) {
       const DotReq dr{k + 1, V_.p, n_, part1, R};
       op(V_.p + (size_t)k * n_, vj1, fp32, s, k > 0, &dr);

@@ -136,13 +136,15 @@ class System {
   void to_boundary(const double* xi, double* xu, hipStream_t s) const;
   // src_ready: the source records, sig and mu of x are already in place;
   // dots: also the first Gram-Schmidt pass V_i . y, i < ndots, as per-chunk
-  // partials (dpart rows of plan().nbh, R rows per group).
+  // partials (dpart rows of plan().nbh, R rows per group), and y . y as row
+  // ndots with self_dot.
   struct DotReq {
     int ndots;
     const double* V;
     int64_t ldv;
     double* dpart;
     int R;
+    int self_dot = 0;
   };
   void matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed = false, bool src_ready = false,
               const DotReq* dots = nullptr);
@@ -202,6 +204,11 @@ class System {
   //   4, 5, 6: moments inside a launch with 7/8, 3/4 or 1/2 of the P2P
   //      pairs, then M2P and the remaining P2P pairs in one launch.
   void set_far_mode(int mode) { far_mode_ = mode; }
+  // Gram-Schmidt passes per Arnoldi step: 2 (classical, twice), 1 (once,
+  // the new vector's norm by Pythagoras from the same reduction) or 0
+  // (one pass for GMRES targets of at least 1e-7 relative, else two).
+  void set_gs_passes(int n) { gs_passes_ = n; }
+  int gs_passes() const { return gs_passes_; }
   int far_mode() const { return far_mode_; }
 
  private:
@@ -352,6 +359,7 @@ class System {
   hipEvent_t evm_[3];          // on s2_: moments start, M2P start, M2P end
   int64_t napply_ = 0, nwasted_ = 0;
   int far_mode_ = 0;
+  int gs_passes_ = 0;
   bool transpose_ = false;
   bool far_timed_ = false;
   int64_t seg_src_ = 0, seg_box_ = 0, seg_src_used_ = 0, seg_box_used_ = 0;

@@ -27,8 +27,8 @@ EXPORTS = ("pbt_default_params", "pbt_create", "pbt_destroy", "pbt_last_error", 
            "pbt_set_cavity", "pbt_enable",
            "pbt_prepare", "pbt_num_unknowns", "pbt_solve", "pbt_get_solution", "pbt_interaction_energy",
            "pbt_matvec", "pbt_matvec_dev", "pbt_rhs", "pbt_gradient", "pbt_solve_batch",
-           "pbt_autotune", "pbt_last_stats", "pbt_set_schedule", "pbt_get_schedule", "pbt_quadrature_rule",
-           "pbt_last_matvec_timing")
+           "pbt_autotune", "pbt_last_stats", "pbt_set_schedule", "pbt_get_schedule", "pbt_set_gram_schmidt",
+           "pbt_quadrature_rule", "pbt_last_matvec_timing")
 
 
 class PbtParams(ctypes.Structure):
@@ -103,6 +103,7 @@ def lib():
         L.pbt_autotune.argtypes = [P, ctypes.c_char_p]
         L.pbt_set_schedule.argtypes = [P, I32]
         L.pbt_get_schedule.argtypes = [P, ctypes.POINTER(I32)]
+        L.pbt_set_gram_schmidt.argtypes = [P, I32]
         L.pbt_last_stats.argtypes = [P, ctypes.POINTER(PbtResult)]
         L.pbt_quadrature_rule.argtypes = [I32, P, P]
         L.pbt_last_matvec_timing.argtypes = [P, P]
@@ -311,6 +312,9 @@ class Solver:
         m = ctypes.c_int32()
         self._check(lib().pbt_get_schedule(self._h, ctypes.byref(m)))
         return m.value
+
+    def set_gram_schmidt(self, passes):
+        self._check(lib().pbt_set_gram_schmidt(self._h, int(passes)))
 
 
 def from_problem(problem, device=0, **params) -> tuple[Solver, list[int]]:

@@ -329,6 +329,37 @@ def test_kirkwood_full_size_fp64_and_mixed():
     assert r.rel_resid <= 1e-6
 
 
+def test_gram_schmidt_passes():
+    """GMRES with classical Gram-Schmidt once (norm by Pythagoras) or twice
+    per Arnoldi step: both meet the oracle's dense LU energy at the solve's
+    tolerance, FP64 and mixed, with the same iteration counts; the automatic
+    choice is bitwise one pass at tol 1e-6 and two passes at tol 1e-10."""
+    pr = case("twosphere_charge_l2")
+    e, _, _ = solve_problem(pr)
+    for prec in (FP64, MIXED):
+        s, _ = from_problem(pr, treecode=1, ncrit=32, theta=0.4, taylor_p=8, prec=prec, tol=1e-6)
+        res = {}
+        for passes in (1, 2, 0):
+            s.set_gram_schmidt(passes)
+            res[passes] = s.solve()
+            assert res[passes].rel_resid <= 1e-6
+            assert abs(res[passes].F_solv - e.F_solv) <= 1e-4 * abs(e.F_solv), (prec, passes)
+        assert abs(res[1].iters - res[2].iters) <= 1
+        assert res[0].F_solv == res[1].F_solv and res[0].iters == res[1].iters
+        with pytest.raises(PbtError):
+            s.set_gram_schmidt(3)
+        s.close()
+    s, _ = from_problem(pr, treecode=0, tol=1e-10)
+    res = {}
+    for passes in (2, 0):
+        s.set_gram_schmidt(passes)
+        res[passes] = s.solve()
+    assert res[0].rel_resid <= 1e-10
+    assert abs(res[0].F_solv - e.F_solv) <= 1e-8 * abs(e.F_solv)
+    assert res[0].F_solv == res[2].F_solv and res[0].iters == res[2].iters
+    s.close()
+
+
 def test_full_size_twosphere_sampled_rows():
     """Full 10240-panel two-sphere workload in the benchmark's launch
     configuration: oracle rows computed one by one at sampled indices."""
