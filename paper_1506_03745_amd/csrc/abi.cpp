@@ -795,30 +795,45 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
       const double a = S.time_products(fp32, reps, c->stream);
       return std::min(a, S.time_products(fp32, reps, c->stream));
     };
+    // two sweeps of coordinate search over (P2P segment, M2P segment,
+    // schedule): the schedule found in the first sweep can prefer other
+    // segment lengths.  Each phase re-times the incumbent first, so a lucky
+    // earlier measurement does not keep it.
     int64_t best_src = S.seg_src(), best_box = S.seg_box();
-    double best = timed();
-    for (int64_t cand : {64, 96, 128, 192, 256, 384, 512, 1024, 2048}) {
-      S.set_segments(cand, best_box, c->stream);
-      const double t = timed();
-      if (t < best) { best = t; best_src = cand; }
-    }
-    for (int64_t cand : {1, 2, 4, 8, 16, 32}) {
-      S.set_segments(best_src, cand, c->stream);
-      const double t = timed();
-      if (t < best) { best = t; best_box = cand; }
-    }
-    S.set_segments(best_src, best_box, c->stream);
-    // scheduling of the far field against P2P (serial, two streams, joint
-    // launch, moments inside P2P).  The split schedules 4-6 are not
-    // candidates: their joint launch runs P2P at the M2P kernel's occupancy,
-    // which the FP64 products (same schedule) pay for, and they were not
-    // faster in the FP32 products either
     int best_mode = S.far_mode();
-    for (int mode = 0; mode < kTunedFarModes; ++mode) {
-      if (mode == best_mode) continue;
-      S.set_far_mode(mode);
-      const double t = timed();
-      if (t < best) { best = t; best_mode = mode; }
+    double best = 0.0;
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      S.set_segments(best_src, best_box, c->stream);
+      best = timed();
+      for (int64_t cand : {64, 96, 128, 192, 256, 384, 512, 1024, 2048}) {
+        if (cand == best_src) continue;
+        S.set_segments(cand, best_box, c->stream);
+        const double t = timed();
+        if (t < best) { best = t; best_src = cand; }
+      }
+      S.set_segments(best_src, best_box, c->stream);
+      best = timed();
+      for (int64_t cand : {1, 2, 4, 8, 16, 32}) {
+        if (cand == best_box) continue;
+        S.set_segments(best_src, cand, c->stream);
+        const double t = timed();
+        if (t < best) { best = t; best_box = cand; }
+      }
+      S.set_segments(best_src, best_box, c->stream);
+      // scheduling of the far field against P2P (serial, two streams, joint
+      // launch, moments inside P2P).  The split schedules 4-6 are not
+      // candidates: their joint launch runs P2P at the M2P kernel's
+      // occupancy, which the FP64 products (same schedule) pay for, and they
+      // were not faster in the FP32 products either
+      best = timed();
+      for (int mode = 0; mode < kTunedFarModes; ++mode) {
+        if (mode == best_mode) continue;
+        S.set_far_mode(mode);
+        const double t = timed();
+        if (t < best) { best = t; best_mode = mode; }
+        S.set_far_mode(best_mode);
+      }
+      S.set_far_mode(best_mode);
     }
     S.set_far_mode(best_mode);
     memo[key] = {best_src, best_box * 8 + best_mode};
