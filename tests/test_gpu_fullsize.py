@@ -88,6 +88,23 @@ def test_orient_sweep_batch_matches_separate_solves():
         sk.close()
 
 
+def test_star_plate_gram_schmidt_passes():
+    """Full-size star/plate solve (832 chunk partials per Gram-Schmidt row, so
+    one pass adds them up in their own kernel before the update): one and two
+    passes reach the tolerance with the same iteration count and energies
+    equal to well inside it."""
+    pr = config_problem("star_plate")
+    s, _ = from_problem(pr, prec=MIXED, **PRM)
+    res = {}
+    for passes in (1, 2):
+        s.set_gram_schmidt(passes)
+        res[passes] = s.solve()
+        assert res[passes].rel_resid <= PRM["tol"]
+    assert abs(res[1].iters - res[2].iters) <= 1
+    assert abs(res[1].F_solv - res[2].F_solv) <= 1e-6 * abs(res[2].F_solv)
+    s.close()
+
+
 def test_last_stats_of_a_solve():
     pr = config_problem("twosphere_charge")
     s, _ = from_problem(pr, prec=MIXED, **PRM)
