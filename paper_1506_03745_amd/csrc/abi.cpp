@@ -824,15 +824,20 @@ pbt_status pbt_autotune(pbt_ctx* c, const char* cache_path) {
       // launch, moments inside P2P).  The split schedules 4-6 are not
       // candidates: their joint launch runs P2P at the M2P kernel's
       // occupancy, which the FP64 products (same schedule) pay for, and they
-      // were not faster in the FP32 products either
-      best = timed();
-      for (int mode = 0; mode < kTunedFarModes; ++mode) {
-        if (mode == best_mode) continue;
-        S.set_far_mode(mode);
-        const double t = timed();
-        if (t < best) { best = t; best_mode = mode; }
-        S.set_far_mode(best_mode);
-      }
+      // were not faster in the FP32 products either.  The schedules are
+      // timed round-robin, three rounds, each keeping its best time, so a
+      // drift of the clocks during the search favours none of them.
+      double tm[kTunedFarModes];
+      for (double& v : tm) v = 1e30;
+      for (int round = 0; round < 3; ++round)
+        for (int mode = 0; mode < kTunedFarModes; ++mode) {
+          S.set_far_mode(mode);
+          tm[mode] = std::min(tm[mode], timed());
+        }
+      best_mode = 0;
+      for (int mode = 1; mode < kTunedFarModes; ++mode)
+        if (tm[mode] < tm[best_mode]) best_mode = mode;
+      best = tm[best_mode];
       S.set_far_mode(best_mode);
     }
     S.set_far_mode(best_mode);
