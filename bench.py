@@ -38,10 +38,11 @@ P2P_SOURCES = (os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "p2p.hip"),
 PROFILED_WORKLOAD = "twosphere_charge"   # the workload of the committed counter summary
 
 
-def profiled_traffic(workload):
+def profiled_traffic(workload, grid):
     """HBM bytes per P2P launch from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken or
-    the counters were taken on another workload."""
+    or None when the kernel source changed since the counters were taken, the
+    counters were taken on another workload, or this run's P2P launch has
+    another shape (grid work-items) than the profiled one."""
     import hashlib
     if workload != PROFILED_WORKLOAD:
         return None
@@ -51,6 +52,7 @@ def profiled_traffic(workload):
     except (OSError, ValueError):
         return None
     same = prof.get("source_sha256") == sha[0] and prof.get("header_sha256") == sha[1]
+    same = same and prof.get("grid_size") == grid
     return prof.get("traffic_bytes_per_launch") if same else None
 
 
@@ -289,6 +291,7 @@ def main():
         return store
 
     schedule = s32.schedule()
+    shape = s32.launch_shape()
     acc, acc64 = op_timing(MIXED), op_timing(FP64)
     s32.set_schedule(0)
     acc_serial = op_timing(MIXED)
@@ -310,7 +313,8 @@ def main():
                    "self_per_edge": 9, "tol": 1e-6, "precision": "mixed"},
         "roofline": {"bound": "alu", "kernel": "k_p2p<float>", "achieved": round(achieved, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": profiled_traffic(a.workload),
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                     "traffic": profiled_traffic(a.workload, shape[2]), "p2p_grid": shape[2],
                      "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                      "flops_per_launch": int(p2p_flops), "avg_launch_ms": round(acc_serial["p2p_ms"], 5)},
         "gmres": {"iters": r.iters, "outer": r.outer, "rel_resid": r.rel_resid,

@@ -274,6 +274,13 @@ pbt_status pbt_set_schedule(pbt_ctx* ctx, int32_t mode);
  * pbt_set_schedule; pbt_autotune may have chosen it) in *mode.  Host-only. */
 pbt_status pbt_get_schedule(pbt_ctx* ctx, int32_t* mode);
 
+/* Launch shape of the enabled system's products (pbt_autotune may have
+ * chosen it): out[0] = Gauss points per P2P task segment, out[1] = boxes per
+ * M2P task, out[2] = work-items of a stand-alone P2P launch (wavefronts of
+ * two half-wave tasks, 256-thread blocks, a multiple of 8 blocks).  out: 3
+ * int64 (host).  Host-only. */
+pbt_status pbt_get_launch_shape(pbt_ctx* ctx, int64_t* out);
+
 /* Orthogonalisation of the GMRES solver (Section 3.2 solves with GMRES) for
  * every system of the context: passes = 2 applies classical Gram-Schmidt
  * twice per Arnoldi step; passes = 1 applies it once and takes the new basis

@@ -875,6 +875,18 @@ pbt_status pbt_get_schedule(pbt_ctx* c, int32_t* mode) {
   });
 }
 
+pbt_status pbt_get_launch_shape(pbt_ctx* c, int64_t* out) {
+  if (!c || !out) return PBT_E_INVALID;
+  return guarded(c, [&] {
+    System& S = system_for(c);
+    const int64_t npairs = (int64_t)S.plan().p2p.size() / 2;
+    out[0] = S.seg_src();
+    out[1] = S.seg_box();
+    out[2] = ((npairs + 3) / 4 + 7) / 8 * 8 * 256;
+    return PBT_OK;
+  });
+}
+
 pbt_status pbt_set_gram_schmidt(pbt_ctx* c, int32_t passes) {
   if (!c) return PBT_E_INVALID;
   if (passes < 0 || passes > 2) return fail(c, PBT_E_INVALID, "Gram-Schmidt passes must be 0, 1 or 2");

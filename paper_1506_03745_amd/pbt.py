@@ -28,6 +28,7 @@ EXPORTS = ("pbt_default_params", "pbt_create", "pbt_destroy", "pbt_last_error", 
            "pbt_prepare", "pbt_num_unknowns", "pbt_solve", "pbt_get_solution", "pbt_interaction_energy",
            "pbt_matvec", "pbt_matvec_dev", "pbt_rhs", "pbt_gradient", "pbt_solve_batch",
            "pbt_autotune", "pbt_last_stats", "pbt_set_schedule", "pbt_get_schedule", "pbt_set_gram_schmidt",
+           "pbt_get_launch_shape",
            "pbt_quadrature_rule", "pbt_last_matvec_timing")
 
 
@@ -104,6 +105,7 @@ def lib():
         L.pbt_set_schedule.argtypes = [P, I32]
         L.pbt_get_schedule.argtypes = [P, ctypes.POINTER(I32)]
         L.pbt_set_gram_schmidt.argtypes = [P, I32]
+        L.pbt_get_launch_shape.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
         L.pbt_last_stats.argtypes = [P, ctypes.POINTER(PbtResult)]
         L.pbt_quadrature_rule.argtypes = [I32, P, P]
         L.pbt_last_matvec_timing.argtypes = [P, P]
@@ -312,6 +314,12 @@ class Solver:
         m = ctypes.c_int32()
         self._check(lib().pbt_get_schedule(self._h, ctypes.byref(m)))
         return m.value
+
+    def launch_shape(self):
+        """(P2P segment length, M2P boxes per task, stand-alone P2P work-items)."""
+        out = (ctypes.c_int64 * 3)()
+        self._check(lib().pbt_get_launch_shape(self._h, out))
+        return tuple(int(v) for v in out)
 
     def set_gram_schmidt(self, passes):
         self._check(lib().pbt_set_gram_schmidt(self._h, int(passes)))

@@ -113,6 +113,20 @@ def test_far_field_schedules_agree_bitwise():
         s.close()
 
 
+def test_launch_shape_follows_segments():
+    """The reported launch shape: positive segment lengths, a P2P grid of
+    whole groups of 8 blocks of 256, and the grid's growth when P2P tasks
+    take shorter source segments."""
+    from workloads.problems import config_problem
+    s, _ = from_problem(config_problem("twosphere_charge"), treecode=1, ncrit=300, theta=0.5, taylor_p=6)
+    src, box, grid = s.launch_shape()
+    assert src > 0 and box > 0 and grid > 0 and grid % 2048 == 0
+    s.autotune()
+    src2, box2, grid2 = s.launch_shape()
+    assert src2 > 0 and box2 > 0 and grid2 % 2048 == 0
+    s.close()
+
+
 def test_treecode_small_theta_is_direct():
     """With a tiny acceptance parameter nothing is expanded: exact direct sums."""
     A, _ = oracle_Ab("twosphere_charge_l2")
