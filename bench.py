@@ -52,8 +52,12 @@ def profiled_traffic(workload, grid):
     except (OSError, ValueError):
         return None
     same = prof.get("source_sha256") == sha[0] and prof.get("header_sha256") == sha[1]
-    same = same and prof.get("grid_size") == grid
-    return prof.get("traffic_bytes_per_launch") if same else None
+    if not same:
+        return None
+    for shape in [prof] + prof.get("other_shapes", []):
+        if shape.get("grid_size") == grid:
+            return shape.get("traffic_bytes_per_launch")
+    return None
 
 
 def parse():
