@@ -1139,7 +1139,7 @@ void System::true_residual(const double* b, const double* x, double* r, hipStrea
   launch_axpby(n_, 1.0, b, -1.0, r, s);  // r = b - A x
 }
 
-// Restarted GMRES with classical Gram-Schmidt applied twice, for the G_
+// Restarted GMRES with classical Gram-Schmidt (once or twice, below), for the G_
 // independent systems of the groups at once (one Krylov space each; the
 // operator is applied to all of them in one product).  Everything of an
 // Arnoldi step runs on the device, including each group's Hessenberg column
