@@ -1,23 +1,42 @@
 #!/usr/bin/env python
 """Benchmark: treecode BEM matvec throughput and GMRES time to 1e-6, FP32 vs FP64.
 
-Workload: the two-sphere case (molecule sphere r = 4 A with +1 e at its
-centre and a sphere with sigma = 0.05 C/m^2, 5120 flat triangles each, centres
-12 A apart, eps 4/80, kappa 0.125 / A), treecode theta 0.5, Taylor order 6,
-300 panels per leaf, 3 Gauss points per panel, near rule 19 points, self rule
-9 points per edge.  Synthetic meshes; inputs resident on the GPU before the
-timed region (the system is prepared once, outside it).
+Default workload: the large star/plate system (a star-shaped molecule of
+65536 flat triangles with 3000 interior point charges, 12 A above a
+120 x 120 x 2 A plate of 81920 triangles with per-panel sigma =
+0.03 (1 + 0.1 u) C/m^2; 212992 unknowns), eps 4/80, kappa 0.125 / A, treecode
+theta 0.5, Taylor order 6, 300 panels per leaf, 3 Gauss points per panel,
+near rule 19 points, self rule 9 points per edge.  Synthetic meshes; the
+system is prepared (geometry, near corrections, tree, work lists, launch
+shapes) before the timed region, so every input is resident in HBM.
 
-One step = one solve of the assembled system: right-hand side (one FP64
-operator pass with the imposed charge density), GMRES with FP32 interactions
-and FP64 Krylov vectors inside FP64 iterative refinement to a relative
-residual of 1e-6, and the energies.  value = dense-equivalent target x
-Gauss-point interactions per second over the step (pairs a dense product
-needs, times the operator applications the step makes, over the step time).
+One step = one solve of the assembled system: the right-hand side (an FP64
+pass over the plate's known densities plus the Coulomb sums), GMRES with
+FP32 interactions and FP64 Krylov vectors inside FP64 iterative refinement
+to a relative residual of 1e-6 (the FP64 residual is checked at exit), and
+the energies.  value = dense-equivalent target x Gauss-point interactions
+per second over the step (targets x sources of every operator application
+the step makes; the right-hand side's pass counts only the plate's sources).
+
+Roofline: the launch that holds the P2P tasks (whichever far-field schedule
+the autotuner chose) is timed with HIP events on its own stream over every
+product of the timed steps.  Its algorithmic work uses the flop convention
+FMA = 2, any other operation = 1, transcendental = 1: a pair whose target
+and source lie on one molecule (single and double layer of both the Laplace
+and the Yukawa kernel) is 34 flops (difference 3, r^2 5, 1/r^3 2, r 1,
+n.(x-y) 5, -kappa r log2(e) 2, dG_L 1, G_Y 1, dG_Y 4, four accumulating FMAs
+8, rsqrt 1, exp 1), a Yukawa-only pair 30.  Peaks: FP32 157.3 TFLOP/s (the
+published MI355X vector figure, which counts packed FP32), FP64 78.6.
+
+Other modes: --workload twosphere_charge | star_plate | star_plate_stern |
+... (a solve of that workload), orient_sweep (pbt_solve_batch of 64 rigid
+placements), gradient (pbt_gradient of the large workload with a central
+difference check).
 
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,86 +45,20 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "treecode BEM matvec Ginteractions/s + GMRES time to 1e-6 resid, FP32 vs FP64"
 FP32_PEAK_TFLOPS = 157.3          # published MI355X FP32 vector peak (packed FP32 FMA)
 FP32_NONPACKED_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, one FP32 op per lane
-FLOPS_FUSED_PAIR = 29    # Laplace + Yukawa, single + double layer (op list in the design doc)
-FLOPS_YUKAWA_PAIR = 26
-P2P_PROFILE = os.path.join(ROOT, "profiles", "k_p2p_twosphere_charge.json")
+FP64_PEAK_TFLOPS = 78.6           # published MI355X FP64 vector peak
+FLOPS_FUSED_PAIR = 34
+FLOPS_YUKAWA_PAIR = 30
+PROFILES = os.path.join(ROOT, "profiles")
 P2P_SOURCES = (os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "p2p.hip"),
-               os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "near_field.h"))
-
-
-PROFILED_WORKLOAD = "twosphere_charge"   # the workload of the committed counter summary
-
-
-def profiled_traffic(workload, grid):
-    """HBM bytes per P2P launch from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken, the
-    counters were taken on another workload, or this run's P2P launch has
-    another shape (grid work-items) than the profiled one."""
-    import hashlib
-    if workload != PROFILED_WORKLOAD:
-        return None
-    try:
-        prof = json.load(open(P2P_PROFILE))
-        sha = [hashlib.sha256(open(f, "rb").read()).hexdigest() for f in P2P_SOURCES]
-    except (OSError, ValueError):
-        return None
-    same = prof.get("source_sha256") == sha[0] and prof.get("header_sha256") == sha[1]
-    if not same:
-        return None
-    for shape in [prof] + prof.get("other_shapes", []):
-        if shape.get("grid_size") == grid:
-            return shape.get("traffic_bytes_per_launch")
-    return None
-
-
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="twosphere_charge")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-only", action="store_true",
-                    help="only the mixed-precision steps (for profiler runs)")
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="also run one plain 256 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-fd", action="store_true",
-                    help="star_plate_large: skip the central-difference check of the gradient")
-    ap.add_argument("--autotune-cache", default=None,
-                    help="text cache of tuned launch shapes (read if present, appended otherwise)")
-    return ap.parse_args()
-
-
-def cpu_baseline(problem, budget_s=15.0):
-    """Oracle (dense FP64 CPU BEM) on a bounded sample of target panels of the
-    same workload: every target against every panel (far, near and self
-    rules) exactly as the oracle assembles its rows."""
-    import numpy as np
-    from oracle.bem import DenseBEM
-    sysm = DenseBEM(problem)
-    ns = sum(s.nt for s in problem.surfaces) * 3
-    rng = np.random.default_rng(0)
-    done_pairs, t_used, n = 0, 0.0, 16
-    while t_used < budget_s:
-        idx = rng.choice(problem.surfaces[0].nt, n, replace=False)
-        t0 = time.perf_counter()
-        sysm.row_block(0, idx)
-        dt = time.perf_counter() - t0
-        done_pairs += n * ns
-        t_used += dt
-        n = min(problem.surfaces[0].nt, max(16, int(n * 2)))
-        if t_used + 2 * dt > budget_s:
-            break
-    return {"value": done_pairs / t_used / 1e9, "unit": "Ginteractions/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{done_pairs // ns} target panels of the molecule x all {ns} Gauss points "
-                      f"(rows of the dense FP64 operator), {t_used:.1f} s"}
-
+               os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "near_field.h"),
+               os.path.join(ROOT, "paper_1506_03745_amd", "csrc", "taylor.hip"))
 
 WORKLOADS = {
+    "star_plate_large": "star molecule 65536 panels + 3000 charges, 12 A above a 120x120x2 A plate of 81920 "
+                        "panels, sigma 0.03(1 + 0.1u) C/m^2, eps 4/80, kappa 0.125",
     "twosphere_charge": "two spheres r=4 A, 2x5120 panels, R=12 A, sigma 0.05 C/m^2, eps 4/80, kappa 0.125",
     "twosphere_potential": "two spheres r=4 A, 2x5120 panels, R=12 A, phi0 0.05 V, eps 4/80, kappa 0.125",
     "kirkwood": "sphere r=4 A, 1280 panels, +1 e at the centre, eps 4/80, kappa 0.125",
@@ -115,22 +68,345 @@ WORKLOADS = {
                         "panels, salt-free layer of permittivity 80",
     "orient_sweep": "64 rigid rotations of a 5120-panel sphere molecule (+1 e) 10 A above the 20480-panel "
                     "plate, solved together (one Krylov space each)",
-    "star_plate_large": "star molecule 65536 panels + 3000 charges, 12 A above a 120x120x2 A plate of 81920 "
-                        "panels; gradient of F_int w.r.t. the plate's sigma and the charges",
+    "gradient": "star_plate_large; gradient of F_int w.r.t. the plate's sigma and the charges",
 }
+# the stored oracle values that check each workload's energies (a twin at
+# lower resolution where the oracle cannot solve the workload itself)
+ORACLE_CHECK = {"star_plate_large": ("star_plate_twin", "twin_oracle.json"),
+                "twosphere_charge": ("twosphere_charge", "dense_oracle_energies.json"),
+                "twosphere_potential": ("twosphere_potential", "dense_oracle_energies.json")}
 PRM = dict(theta=0.5, taylor_p=6, ncrit=300, k_far=3, k_near=19, k_self_edge=9, tol=1e-6)
+SCHEDULES = {0: "serial", 1: "two streams", 2: "joint M2P + P2P launch", 3: "moments inside the P2P launch",
+             4: "moments with 7/8 of P2P, then M2P with 1/8 of P2P",
+             5: "moments with 3/4 of P2P, then M2P with 1/4 of P2P",
+             6: "moments with 1/2 of P2P, then M2P with 1/2 of P2P"}
 
 
-def common_fields(a, ms_step):
+def p2p_kernel_name(schedule, prec="float", P=6):
+    """The kernel (as the profiler names it) that holds the P2P tasks."""
+    if schedule in (0, 1):
+        return f"k_p2p<{prec}, false>"
+    if schedule == 2:
+        return f"k_m2p_p2p<{prec}, {P}, false, false>"
+    return f"k_p2p_mom<{prec}, {P}, false>"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="star_plate_large")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work per CPU-baseline leg (one core, then all cores)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the mixed-precision steps (for profiler runs)")
+    ap.add_argument("--no-direct", action="store_true", help="skip the plain FP64 direct solve")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-fd", action="store_true", help="gradient: skip the central-difference check")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="text cache of tuned launch shapes (read if present, appended otherwise)")
+    return ap.parse_args()
+
+
+# ---- CPU baseline: the oracle's dense FP64 rows on the host cores ------------------
+_ORACLE = None
+
+
+def _oracle_rows(args):
+    """Worker: oracle rows (a target panel's interior and solvent rows against
+    every Gauss point) for `budget` seconds.  Returns (target panels, seconds)."""
+    import numpy as np
+    seed, budget = args
+    sysm = _ORACLE
+    rng = np.random.default_rng(seed)
+    nt = sysm.surfs[0].nt
+    done, t_used, n = 0, 0.0, 8
+    while True:
+        idx = rng.choice(nt, n, replace=False)
+        t0 = time.perf_counter()
+        sysm.row_block(0, idx)
+        dt = time.perf_counter() - t0
+        done += n
+        t_used += dt
+        if t_used + dt > budget:
+            return done, t_used
+
+
+def cpu_baseline(problem, budget_s):
+    """The oracle (dense FP64 CPU BEM, unchanged) on a bounded sample of the
+    same workload: rows of seeded random molecule panels against every
+    Gauss point of every surface (far, near and self rules), first on one
+    core, then in one process per core (fork, before the GPU is touched)."""
+    import multiprocessing as mp
+    from oracle.bem import DenseBEM
+    global _ORACLE
+    _ORACLE = DenseBEM(problem)
+    ns = sum(s.nt for s in problem.surfaces) * 3
+    rows1, t1 = _oracle_rows((0, budget_s))
+    one = rows1 * ns / t1 / 1e9
+    ncores = min(16, len(os.sched_getaffinity(0)))   # the host share of one GPU is at most 16 cores
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(ncores) as pool:
+        res = pool.map(_oracle_rows, [(100 + k, budget_s) for k in range(ncores)])
+    wall = time.perf_counter() - t0
+    rows_all = sum(r for r, _ in res)
+    return {"value": rows_all * ns / wall / 1e9, "unit": "Ginteractions/s", "cores": ncores,
+            "kind": "oracle",
+            "sample": f"dense FP64 operator rows (interior + solvent row) of seeded random molecule panels "
+                      f"against all {ns} Gauss points: {rows_all} target panels on {ncores} processes in "
+                      f"{wall:.1f} s wall; one core: {rows1} target panels in {t1:.1f} s",
+            "single_core_value": one, "nproc": os.cpu_count(),
+            "host_cpus_available": len(os.sched_getaffinity(0))}
+
+
+# ---- helpers --------------------------------------------------------------------------
+def common_fields(a, ms_step, dtype="f32 interactions + f64 Krylov/refinement"):
     return {"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 3),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32 interactions + f64 Krylov/refinement", "data": "synthetic"}
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic"}
+
+
+def profiled_traffic(workload, kernel, grid):
+    """HBM bytes per launch of the P2P-holding kernel from the committed
+    rocprofv3 counter summary of this workload, or None when there is none,
+    the kernel sources changed since the counters were taken, or this run's
+    launch has another shape (grid work-items) than the profiled one."""
+    path = os.path.join(PROFILES, f"k_p2p_{workload}.json")
+    try:
+        prof = json.load(open(path))
+        sha = [hashlib.sha256(open(f, "rb").read()).hexdigest() for f in P2P_SOURCES]
+    except (OSError, ValueError):
+        return None
+    if prof.get("sources_sha256") != sha:
+        return None
+    for shape in [prof] + prof.get("other_shapes", []):
+        if shape.get("kernel") == kernel and shape.get("grid_size") == grid:
+            return shape.get("traffic_bytes_per_launch")
+    return None
+
+
+def p2p_flops(r):
+    return FLOPS_FUSED_PAIR * r.p2p_fused_pairs + FLOPS_YUKAWA_PAIR * (r.p2p_pairs - r.p2p_fused_pairs)
+
+
+def timed_solves(s, a, sync):
+    """Warm-up, then a.steps timed solves with per-kernel profiling."""
+    for _ in range(a.warmup):
+        s.solve()
+    sync()
+    s.profile(True)
+    t0 = time.perf_counter()
+    rs, pairs = [], 0
+    for _ in range(a.steps):
+        rs.append(s.solve())
+        pairs += s.last_stats().dense_pairs
+    sync()
+    dt = time.perf_counter() - t0
+    kt = s.kernel_times()
+    s.profile(False)
+    return rs, pairs, dt, kt
+
+
+def oracle_check(workload, prec):
+    """Energies of the workload's oracle-checked twin (or itself) at the
+    benchmark parameters, against the stored dense oracle values."""
+    from paper_1506_03745_amd import from_problem
+    from workloads.problems import config_problem
+    if workload not in ORACLE_CHECK:
+        return None
+    name, fname = ORACLE_CHECK[workload]
+    path = os.path.join(ROOT, "tests", "golden", fname)
+    if not os.path.exists(path):
+        return None
+    try:
+        gold = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    gold = gold.get(name, gold)
+    pr = config_problem(name)
+    s, _ = from_problem(pr, prec=prec, **PRM)
+    f, parts = s.interaction_energy(len(pr.surfaces))
+    asm = parts[0]
+    scale = abs(gold["F_solv_asm"]) + abs(gold["F_surf_asm"])
+    out = {"workload": name, "F_solv_rel": abs(asm.F_solv - gold["F_solv_asm"]) / abs(gold["F_solv_asm"]),
+           "F_surf_rel": abs(asm.F_surf - gold["F_surf_asm"]) / abs(gold["F_surf_asm"]),
+           "F_int_abs_kcal": abs(f - gold["F_int"]), "F_int_rel_to_asm": abs(f - gold["F_int"]) / scale,
+           "F_int_kcal": f, "F_int_oracle_kcal": gold["F_int"]}
+    if "F_coul_asm" in gold and gold["F_coul_asm"] != 0:
+        out["F_coul_rel"] = abs(asm.F_coul - gold["F_coul_asm"]) / abs(gold["F_coul_asm"])
+    s.close()
+    return {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in out.items()}
+
+
+# ---- modes ------------------------------------------------------------------------------
+def bench_solve(a, cpu):
+    import numpy as np
+    import torch
+
+    from paper_1506_03745_amd import FP64, MIXED, from_problem
+    from workloads.problems import config_problem
+
+    sync = torch.cuda.synchronize
+    if a.copy_calib:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        sync()
+        del src, dst
+    problem = config_problem(a.workload)
+
+    # ---- mixed precision (the benchmarked path) -----------------------------
+    s32, _ = from_problem(problem, prec=MIXED, **PRM)
+    sync()
+    t0 = time.perf_counter()
+    s32.prepare()
+    setup_wall = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if not a.no_autotune:
+        s32.autotune(a.autotune_cache)
+    autotune_s = time.perf_counter() - t0
+    s32.solve()
+    print(f"[bench] {a.workload}: prepared in {setup_wall:.2f} s, autotuned in {autotune_s:.2f} s",
+          file=sys.stderr, flush=True)
+    rs, pairs, t_steps, kt = timed_solves(s32, a, sync)
+    ms_step = 1e3 * t_steps / a.steps
+    r = rs[-1]
+    value = pairs / t_steps / 1e9
+    schedule = s32.schedule()
+    shape = s32.launch_shape()
+    print(f"[bench] timed {a.steps} solves: {ms_step:.2f} ms each", file=sys.stderr, flush=True)
+
+    def per_kernel(kt, prec):
+        out = {}
+        for kind in ("p2p", "m2p", "moments", "combine"):
+            ms, n = kt[(prec, kind)]
+            if n:
+                out[kind] = {"launches_per_step": n / a.steps, "avg_ms": round(ms / n, 5),
+                             "ms_per_step": round(ms / a.steps, 4)}
+        return out
+
+    k32 = per_kernel(kt, "fp32")
+    flops = p2p_flops(r)
+    p2p_ms, p2p_n = kt[("fp32", "p2p")]
+    avg_p2p = p2p_ms / max(p2p_n, 1)
+    kernel = p2p_kernel_name(schedule)
+    achieved = flops / (avg_p2p / 1e3) / 1e12
+    m2p_ms, m2p_n = kt[("fp32", "m2p")]
+    dom = max(("p2p", "m2p", "moments", "combine"), key=lambda k: kt[("fp32", k)][0])
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Ginteractions/s",
+        **common_fields(a, ms_step),
+        "config": {"workload": f"{a.workload}: {WORKLOADS.get(a.workload, a.workload)}",
+                   "panels": sum(s.nt for s in problem.surfaces), "unknowns": s32.num_unknowns(),
+                   **PRM, "precision": "mixed"},
+        "roofline": {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                     "traffic": profiled_traffic(a.workload, kernel, shape[2]),
+                     "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_TFLOPS, 4),
+                     "flops_per_launch": int(flops), "avg_launch_ms": round(avg_p2p, 5),
+                     "launches": p2p_n, "grid_work_items": shape[2],
+                     "flop_convention": "FMA 2, other op 1, transcendental 1; 34 per Laplace+Yukawa pair, "
+                                        "30 per Yukawa-only pair",
+                     "dominant_in_solve": dom == "p2p"},
+        "gmres": {"iters": r.iters, "outer": r.outer, "rel_resid": r.rel_resid,
+                  "applications_per_step": sum(x.matvecs for x in rs) / len(rs),
+                  "setup_s": round(setup_wall, 3), "autotune_s": round(autotune_s, 3)},
+        "far_field_schedule": SCHEDULES[schedule],
+        "launch_shape": {"p2p_segment": shape[0], "m2p_boxes_per_task": shape[1]},
+        "kernels_fp32": k32,
+        "p2p_gpairs_s": round(r.p2p_pairs / (avg_p2p / 1e3) / 1e9, 2),
+        "m2p_g_target_box_s": round(r.m2p_pairs / (m2p_ms / max(m2p_n, 1) / 1e3) / 1e9, 3) if m2p_n else None,
+        "pairs_per_product": {"dense": r.dense_pairs, "p2p": r.p2p_pairs, "p2p_fused": r.p2p_fused_pairs,
+                              "m2p": r.m2p_pairs},
+        "energies_kcal": {"F_solv": r.F_solv, "F_surf": r.F_surf, "F_coul": r.F_coul},
+    }
+    if not a.profile_only:
+        # operator timing on the context's stream (HIP events), tuned schedule
+        n = s32.num_unknowns()
+        x = torch.tensor(np.random.default_rng(0).standard_normal(n), device="cuda:0")
+        y = torch.empty_like(x)
+
+        def op_timing(prec, nrep=10):
+            keys = ("total_ms", "p2p_ms", "m2p_ms", "moments_ms", "rest_ms")
+            store = dict.fromkeys(keys, 0.0)
+            s32.matvec_dev(x, y, prec=prec)
+            for _ in range(nrep):
+                s32.matvec_dev(x, y, prec=prec)
+                t = s32.last_matvec_timing()
+                for k in store:
+                    store[k] += t[k] / nrep
+            return {k: round(v, 4) for k, v in store.items()}
+
+        m32, m64 = op_timing(MIXED), op_timing(FP64)
+        out["matvec_ms"] = {"fp32": m32, "fp64": m64}
+        out["matvec_gint_s"] = {"fp32": round(r.dense_pairs / m32["total_ms"] / 1e6, 2),
+                                "fp64": round(r.dense_pairs / m64["total_ms"] / 1e6, 2)}
+        del x, y
+        s32.close()
+        # FP64 treecode at the same (theta, P), autotuned in FP64, profiled
+        s64, _ = from_problem(problem, prec=FP64, **PRM)
+        s64.prepare()
+        if not a.no_autotune:
+            s64.autotune(a.autotune_cache)
+        s64.solve()
+        n64 = max(2, a.steps // 4)
+        s64.profile(True)
+        sync()
+        t0 = time.perf_counter()
+        r64 = [s64.solve() for _ in range(n64)][-1]
+        sync()
+        t64 = (time.perf_counter() - t0) / n64
+        kt64 = s64.kernel_times()
+        sched64 = s64.schedule()
+        s64.close()
+        ms64, n64p = kt64[("fp64", "p2p")]
+        avg64 = ms64 / max(n64p, 1)
+        ach64 = flops / (avg64 / 1e3) / 1e12
+        mm64, nm64 = kt64[("fp64", "m2p")]
+        out["roofline_fp64"] = {"bound": "alu", "kernel": p2p_kernel_name(sched64, "double"),
+                                "achieved": round(ach64, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": round(ach64 / FP64_PEAK_TFLOPS, 4), "avg_launch_ms": round(avg64, 5),
+                                "launches": n64p, "far_field_schedule": SCHEDULES[sched64]}
+        out["m2p_g_target_box_s_fp64"] = (round(r.m2p_pairs / (mm64 / max(nm64, 1) / 1e3) / 1e9, 3)
+                                          if nm64 else None)
+        out["fp64"] = {"treecode_ms_per_solve": round(1e3 * t64, 3), "iters": r64.iters,
+                       "speedup_mixed_vs_fp64_treecode": round(t64 / (ms_step / 1e3), 3),
+                       "kernels": per_kernel(kt64, "fp64"),
+                       "F_solv_fp64_treecode": r64.F_solv, "F_surf_fp64_treecode": r64.F_surf,
+                       "rel_diff_F_solv_mixed_vs_fp64": abs(r.F_solv - r64.F_solv) / abs(r64.F_solv),
+                       "rel_diff_F_surf_mixed_vs_fp64": abs(r.F_surf - r64.F_surf) / abs(r64.F_surf)}
+        print(f"[bench] FP64 treecode solve {1e3 * t64:.1f} ms", file=sys.stderr, flush=True)
+        if not a.no_direct:
+            sd, _ = from_problem(problem, prec=FP64, treecode=0, **PRM)
+            sd.prepare()
+            sync()
+            t0 = time.perf_counter()
+            rd = sd.solve()
+            sync()
+            td = time.perf_counter() - t0
+            sd.close()
+            out["fp64"].update({"direct_ms_per_solve": round(1e3 * td, 3), "direct_iters": rd.iters,
+                                "speedup_mixed_vs_fp64_direct": round(td / (ms_step / 1e3), 3),
+                                "F_solv_fp64_direct": rd.F_solv, "F_surf_fp64_direct": rd.F_surf,
+                                "rel_diff_F_solv_mixed_vs_fp64_direct": abs(r.F_solv - rd.F_solv) / abs(rd.F_solv),
+                                "rel_diff_F_surf_mixed_vs_fp64_direct": abs(r.F_surf - rd.F_surf) / abs(rd.F_surf)})
+            print(f"[bench] FP64 direct solve {1e3 * td:.1f} ms", file=sys.stderr, flush=True)
+        chk = {p: oracle_check(a.workload, v) for p, v in (("mixed", MIXED), ("fp64", FP64))}
+        if chk["mixed"] is not None:
+            out["energy_error_vs_oracle"] = chk
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(a):
     """Orientation sweep: one step = pbt_solve_batch of 64 placements (the
     isolated energies included), FP32 interactions in FP64 refinement."""
-    import numpy as np
     from paper_1506_03745_amd import MIXED, from_problem
     from workloads.problems import config_problem, random_rotations
     pr = config_problem("orient_sweep")
@@ -141,20 +417,24 @@ def bench_batch(a):
     T = c[None, :] - R @ c            # rotations about the molecule's centre
     for _ in range(max(a.warmup, 1)):
         s.solve_batch(ids[0], R.reshape(64, 9), T)
+    s.profile(True)
     t0 = time.perf_counter()
     stats, f = [], None
     for _ in range(a.steps):
         f = s.solve_batch(ids[0], R.reshape(64, 9), T)
         stats.append(s.last_stats())
     dt = (time.perf_counter() - t0) / a.steps
+    kt = s.kernel_times()
+    s.profile(False)
     pairs = sum(x.dense_pairs for x in stats) / len(stats)
     st = stats[-1]
-    out = {"metric": "treecode BEM matvec Ginteractions/s + GMRES time to 1e-6 resid, FP32 vs FP64",
-           "value": round(pairs / dt / 1e9, 3), "unit": "Ginteractions/s", **common_fields(a, 1e3 * dt),
+    out = {"metric": METRIC, "value": round(pairs / dt / 1e9, 3), "unit": "Ginteractions/s",
+           **common_fields(a, 1e3 * dt),
            "config": {"workload": f"orient_sweep: {WORKLOADS['orient_sweep']}", "placements": 64,
-                      "unknowns_per_placement": s.num_unknowns(), **{k: v for k, v in PRM.items()},
-                      "precision": "mixed"},
+                      "unknowns_per_placement": s.num_unknowns(), **PRM, "precision": "mixed"},
            "roofline": None,
+           "kernels_fp32_ms_per_step": {k: round(kt[("fp32", k)][0] / a.steps, 3)
+                                        for k in ("p2p", "m2p", "moments", "combine")},
            "batch": {"ms_per_placement": round(1e3 * dt / 64, 3), "iters_max": st.iters,
                      "operator_applications": st.matvecs, "setup_s": round(st.t_setup_s, 4),
                      "F_int_kcal": {"min": float(f.min()), "max": float(f.max()), "mean": float(f.mean())}}}
@@ -182,9 +462,9 @@ def bench_gradient(a):
         stats.append(s.last_stats())
     dt = (time.perf_counter() - t0) / a.steps
     pairs = sum(x.dense_pairs for x in stats) / len(stats)
-    out = {"metric": "treecode BEM matvec Ginteractions/s + GMRES time to 1e-6 resid, FP32 vs FP64",
-           "value": round(pairs / dt / 1e9, 3), "unit": "Ginteractions/s", **common_fields(a, 1e3 * dt),
-           "config": {"workload": f"star_plate_large: {WORKLOADS['star_plate_large']}",
+    out = {"metric": METRIC, "value": round(pairs / dt / 1e9, 3), "unit": "Ginteractions/s",
+           **common_fields(a, 1e3 * dt),
+           "config": {"workload": f"gradient: {WORKLOADS['gradient']}",
                       "unknowns": s.num_unknowns(), **PRM, "precision": "mixed"},
            "roofline": None,
            "gradient": {"ms": round(1e3 * dt, 2), "operator_applications": stats[-1].matvecs,
@@ -229,138 +509,22 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              f"(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+              f"(every GPU box here has one GPU; the multi-GPU design is documented, not built)",
+              file=sys.stderr)
         sys.exit(2)
     if a.workload == "orient_sweep":
         return bench_batch(a)
-    if a.workload == "star_plate_large":
+    if a.workload == "gradient":
         return bench_gradient(a)
-    import numpy as np
-    import torch
-
-    from paper_1506_03745_amd import FP64, MIXED, from_problem
-    from workloads.problems import config_problem
-
-    if a.copy_calib:
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    problem = config_problem(a.workload)
-    prm = PRM
-
-    # ---- mixed precision (the benchmarked path) -----------------------------
-    s32, _ = from_problem(problem, prec=MIXED, **prm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s32.prepare()
-    setup_wall = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    if not a.no_autotune:
-        s32.autotune(a.autotune_cache)
-    autotune_s = time.perf_counter() - t0
-    s32.solve()
-    for _ in range(a.warmup):
-        s32.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rs = [s32.solve() for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t_steps = time.perf_counter() - t0
-    ms_step = 1e3 * t_steps / a.steps
-    r = rs[-1]
-    applications = sum(x.matvecs for x in rs) / len(rs)
-    value = r.dense_pairs * applications / (ms_step / 1e3) / 1e9
-
-    # ---- operator timing on the context's stream (HIP events) ----------------
-    # First with the tuned schedule (the solve's), then the FP32 operator once
-    # more on the serial schedule, where P2P is a launch of its own: the
-    # roofline is that kernel's.
-    n = s32.num_unknowns()
-    x = torch.tensor(np.random.default_rng(0).standard_normal(n), device="cuda:0")
-    y = torch.empty_like(x)
-    keys = ("total_ms", "p2p_ms", "m2p_ms", "moments_ms", "rest_ms")
-    nrep = 20
-
-    def op_timing(prec):
-        store = dict.fromkeys(keys, 0.0)
-        s32.matvec_dev(x, y, prec=prec)
-        s32.last_matvec_timing()
-        for _ in range(nrep):
-            s32.matvec_dev(x, y, prec=prec)
-            t = s32.last_matvec_timing()
-            for k in store:
-                store[k] += t[k] / nrep
-        return store
-
-    schedule = s32.schedule()
-    shape = s32.launch_shape()
-    acc, acc64 = op_timing(MIXED), op_timing(FP64)
-    s32.set_schedule(0)
-    acc_serial = op_timing(MIXED)
-    s32.set_schedule(schedule)
-    p2p_flops = FLOPS_FUSED_PAIR * r.p2p_fused_pairs + FLOPS_YUKAWA_PAIR * (r.p2p_pairs - r.p2p_fused_pairs)
-    achieved = p2p_flops / (acc_serial["p2p_ms"] / 1e3) / 1e12
-    out = {
-        "metric": "treecode BEM matvec Ginteractions/s + GMRES time to 1e-6 resid, FP32 vs FP64",
-        "value": round(value, 3),
-        "unit": "Ginteractions/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 interactions + f64 Krylov/refinement",
-        "data": "synthetic",
-        "config": {"workload": f"{a.workload}: {WORKLOADS.get(a.workload, a.workload)}",
-                   "panels": sum(s.nt for s in problem.surfaces), "unknowns": n,
-                   "theta": 0.5, "taylor_p": 6, "ncrit": 300, "k_far": 3, "k_near": 19,
-                   "self_per_edge": 9, "tol": 1e-6, "precision": "mixed"},
-        "roofline": {"bound": "alu", "kernel": "k_p2p<float>", "achieved": round(achieved, 3),
-                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": profiled_traffic(a.workload, shape[2]), "p2p_grid": shape[2],
-                     "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_TFLOPS, 4),
-                     "flops_per_launch": int(p2p_flops), "avg_launch_ms": round(acc_serial["p2p_ms"], 5)},
-        "gmres": {"iters": r.iters, "outer": r.outer, "rel_resid": r.rel_resid,
-                  "applications_per_step": applications, "setup_s": round(setup_wall, 4),
-                  "autotune_s": round(autotune_s, 3)},
-        "far_field_schedule": {0: "serial", 1: "two streams", 2: "joint M2P + P2P launch",
-                               3: "moments inside the P2P launch",
-                               4: "moments with 7/8 of P2P, then M2P with 1/8 of P2P",
-                               5: "moments with 3/4 of P2P, then M2P with 1/4 of P2P",
-                               6: "moments with 1/2 of P2P, then M2P with 1/2 of P2P"}[schedule],
-        "matvec_ms": {"fp32": {k: round(v, 4) for k, v in acc.items()},
-                      "fp64": {k: round(v, 4) for k, v in acc64.items()},
-                      "fp32_serial_schedule": {k: round(v, 4) for k, v in acc_serial.items()}},
-        "matvec_gint_s": {"fp32": round(r.dense_pairs / acc["total_ms"] / 1e6, 2),
-                          "fp64": round(r.dense_pairs / acc64["total_ms"] / 1e6, 2)},
-        "p2p_gpairs_s": round(r.p2p_pairs / acc_serial["p2p_ms"] / 1e6, 2),
-        "pairs": {"dense": r.dense_pairs, "p2p": r.p2p_pairs, "p2p_fused": r.p2p_fused_pairs,
-                  "m2p": r.m2p_pairs},
-        "energies_kcal": {"F_solv": r.F_solv, "F_surf": r.F_surf},
-    }
-    if not a.profile_only:
-        # FP64 treecode at the same (theta, P) and the plain FP64 direct form
-        s64, _ = from_problem(problem, prec=FP64, **prm)
-        s64.solve()
+    cpu = None
+    if not (a.no_cpu_baseline or a.profile_only):
+        # before anything touches the GPU: the oracle's worker processes are forked
+        from workloads.problems import config_problem
         t0 = time.perf_counter()
-        r64 = s64.solve()
-        r64b = s64.solve()
-        t64 = (time.perf_counter() - t0) / 2
-        sd, _ = from_problem(problem, prec=FP64, treecode=0, **{k: v for k, v in prm.items()})
-        sd.solve()
-        t0 = time.perf_counter()
-        rd = sd.solve()
-        td = time.perf_counter() - t0
-        out["fp64"] = {"treecode_ms_per_solve": round(1e3 * t64, 3), "iters": r64b.iters,
-                       "direct_ms_per_solve": round(1e3 * td, 3), "direct_iters": rd.iters,
-                       "speedup_mixed_vs_fp64_treecode": round(t64 / (ms_step / 1e3), 3),
-                       "speedup_mixed_vs_fp64_direct": round(td / (ms_step / 1e3), 3),
-                       "F_solv_fp64_treecode": r64.F_solv, "F_solv_fp64_direct": rd.F_solv,
-                       "rel_diff_F_solv_mixed_vs_fp64": abs(r.F_solv - r64.F_solv) / abs(r64.F_solv)}
-        if not a.no_cpu_baseline:
-            out["cpu_baseline"] = cpu_baseline(problem)
-    print(json.dumps(out), flush=True)
+        cpu = cpu_baseline(config_problem(a.workload), a.cpu_budget)
+        print(f"[bench] CPU baseline (oracle) {time.perf_counter() - t0:.1f} s: "
+              f"{cpu['value']:.4g} Gint/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
+    return bench_solve(a, cpu)
 
 
 if __name__ == "__main__":

@@ -70,13 +70,15 @@ typedef struct {
   int32_t k_near;       /* Gauss points per panel within 2L: 19 (default) */
   int32_t k_self_edge;  /* Gauss-Legendre points per edge on the self panel (default 9) */
   int32_t ncrit;        /* max panels per tree leaf (default 300) */
-  int32_t taylor_p;     /* Taylor order P, terms |k| <= P (default 6; 0..10) */
+  int32_t taylor_p;     /* Taylor order P, terms |k| <= P (default 6; 0..8) */
   double theta;         /* multipole acceptance, 0 < theta < 1 (default 0.5) */
   double tol;           /* GMRES relative residual ||b-Ax||/||b|| (default 1e-6) */
   int32_t restart;      /* GMRES restart length, 1..1024 (default 100) */
   int32_t max_iter;     /* total GMRES iterations allowed (default 1000) */
   pbt_precision prec;   /* FP64 everywhere, or FP32 interactions + FP64 Krylov/refinement */
   int32_t treecode;     /* 1 = treecode matvec (default), 0 = direct sums over all pairs */
+  double near_factor;   /* the near rule applies to panel j seen from x when |x - c_j| < near_factor * L_j,
+                           L_j = sqrt(2 A_j), c_j its centroid (Section 3.1: 2); > 0 (default 2) */
 } pbt_params;
 
 typedef struct {
@@ -91,6 +93,9 @@ typedef struct {
   int64_t dense_pairs;    /* targets x Gauss points (all pairs a dense product would need) */
   int64_t p2p_fused_pairs; /* P2P pairs evaluating both the Laplace and the Yukawa kernel */
   int32_t matvecs;        /* operator applications in this solve (incl. the rhs pass) */
+  int32_t fp64_fallback;  /* PBT_MIXED: 1 if the iterative refinement stagnated (an FP32-interaction
+                             correction no longer halved the FP64 residual) and FP64 inner solves
+                             finished the solve, else 0 */
 } pbt_result;
 
 /* Fills *p with the defaults listed above.  Never fails for non-NULL p. */
@@ -131,6 +136,13 @@ pbt_status pbt_add_surface(pbt_ctx* ctx, pbt_kind kind, const double* xyz, int64
  * same units as pbt_add_surface).  Allowed at any time. */
 pbt_status pbt_set_bc(pbt_ctx* ctx, int32_t id, const double* bc);
 
+/* Device variant of pbt_set_bc: bc_dev holds nt doubles in device memory of
+ * the context's device, read in the order of `stream` (a hipStream_t, NULL
+ * for the context's own stream: work queued there before the call is done
+ * first); the call waits for the read and then behaves as pbt_set_bc.
+ * PBT_E_INVALID for a pointer that is not device memory of that device. */
+pbt_status pbt_set_bc_dev(pbt_ctx* ctx, int32_t id, const double* bc_dev, void* stream);
+
 /* Interior permittivity and point charges of molecule `mol_id` (eq. pde:
  * eps_1 and q_k at r_k).  xyz: nq*3 doubles (A), q: nq doubles (e).
  * Allowed at any time; nq may be 0.  PBT_E_INVALID if a charge lies outside
@@ -139,6 +151,13 @@ pbt_status pbt_set_bc(pbt_ctx* ctx, int32_t id, const double* bc);
  * change). */
 pbt_status pbt_set_charges(pbt_ctx* ctx, int32_t mol_id, double eps_in, const double* xyz,
                            const double* q, int64_t nq);
+
+/* Device variant of pbt_set_charges: q_dev (nq doubles) and xyz_dev (nq*3
+ * doubles, or NULL to keep the molecule's present positions, which needs
+ * an unchanged nq) are device memory of the context's device, read in the
+ * order of `stream` as for pbt_set_bc_dev; then as pbt_set_charges. */
+pbt_status pbt_set_charges_dev(pbt_ctx* ctx, int32_t mol_id, double eps_in, const double* xyz_dev,
+                               const double* q_dev, int64_t nq, void* stream);
 
 /* Stern layer (the extra interfaces of Section 2's closing remarks): the
  * PBT_STERN surface `stern_id` encloses molecule `mol_id` and bounds a
@@ -198,6 +217,12 @@ pbt_status pbt_solve(pbt_ctx* ctx, const double* x0, pbt_result* res);
  * NULL. */
 pbt_status pbt_get_solution(pbt_ctx* ctx, int32_t id, double* phi, double* dphidn);
 
+/* Device variant of pbt_get_solution: phi_dev and dphidn_dev (nt doubles
+ * each, either NULL) are device memory of the context's device, written in
+ * the order of `stream` (NULL: the context's stream); the call returns when
+ * the writes are done. */
+pbt_status pbt_get_solution_dev(pbt_ctx* ctx, int32_t id, double* phi_dev, double* dphidn_dev, void* stream);
+
 /* Interaction free energy (eq. interaction_energy): one solve with every
  * surface enabled and one per component alone (a molecule together with
  * its Stern surface and cavities; each other surface by itself).  parts
@@ -234,6 +259,16 @@ pbt_status pbt_rhs(pbt_ctx* ctx, double* b);
 pbt_status pbt_gradient(pbt_ctx* ctx, int32_t sigma_id, double* dF_dsigma, int32_t mol_id,
                         double* dF_dq);
 
+/* Device variant of pbt_gradient (the path of a torch.autograd.Function):
+ * dF_dsigma_dev (nt doubles) and dF_dq_dev (nq doubles) are device memory
+ * of the context's device, written in the order of `stream` (NULL: the
+ * context's stream) once the adjoint solves are done; the call returns
+ * when the writes are.  Both pointers are checked before any work
+ * (PBT_E_INVALID leaves them untouched); with PBT_E_NOCONVERGE they hold
+ * the gradient of the last iterates. */
+pbt_status pbt_gradient_dev(pbt_ctx* ctx, int32_t sigma_id, double* dF_dsigma_dev, int32_t mol_id,
+                            double* dF_dq_dev, void* stream);
+
 /* Interaction free energies of molecule `mol_id` at nb rigid placements:
  * body-frame coordinates x map to R_b x + t_b with R_b = rot[9b..9b+8]
  * (row-major) and t_b = shift[3b..3b+2].  The isolated energies are computed
@@ -255,7 +290,9 @@ pbt_status pbt_autotune(pbt_ctx* ctx, const char* cache_path);
  * iters = most GMRES iterations of one solve, matvecs = operator
  * applications (forward and transposed, every system the call solved),
  * dense_pairs = the dense-equivalent target x Gauss-point pairs of all those
- * applications together, t_setup_s = time spent building systems,
+ * applications together (a right-hand side's product, which only the
+ * sources of charged and potential surfaces enter, counts its targets times
+ * those sources), t_setup_s = time spent building systems,
  * t_solve_s = wall time of the whole call.  Host-only. */
 pbt_status pbt_last_stats(pbt_ctx* ctx, pbt_result* out);
 
@@ -302,12 +339,34 @@ pbt_status pbt_quadrature_rule(int32_t npts, double* bary, double* w);
 
 /* Timing of the last pbt_matvec / pbt_matvec_dev on the context's own
  * events, in milliseconds: out[0] total, out[1] P2P kernel, out[2] M2P
- * kernel, out[3] moments (P2M), out[4] strengths, near field and combine.
+ * kernel, out[3] moments (P2M at the leaves, then M2M up the tree),
+ * out[4] strengths, near field and combine.
  * Under schedule 2 out[1] is the joint M2P + P2P launch and out[2] is 0;
- * under schedule 3 out[1] is the launch of moments and P2P and out[3] is 0;
- * under schedules 4-6 out[1] is the launch of moments and part of P2P,
- * out[2] the joint M2P + P2P launch and out[3] is 0. */
+ * under schedule 3 out[1] is the launch of the leaves' moments and P2P and
+ * out[3] the M2M launches; under schedules 4-6 out[1] is the launch of the
+ * leaves' moments and part of P2P, out[3] the M2M launches and out[2] the
+ * joint M2P + P2P launch. */
 pbt_status pbt_last_matvec_timing(pbt_ctx* ctx, double out[5]);
+
+/* Per-kernel timing of the operator (the measurement of Section 3.2's
+ * matrix-vector product, whose near and far fields dominate the solve): with
+ * on = 1 every full operator application of every system of the context
+ * (solves, products, batches; not the right-hand side's known-density pass)
+ * records HIP events on the stream of each launch; on = 0 stops.  Either
+ * call clears the totals.  Events cost a marker packet per launch and a
+ * host synchronisation per 2048 launches.  Host-only bookkeeping. */
+pbt_status pbt_profile(pbt_ctx* ctx, int32_t on);
+
+/* Totals since the last pbt_profile call: out[2 * slot] milliseconds and
+ * out[2 * slot + 1] launches, slot = 4 * p + kind with p = 0 for FP32 and
+ * 1 for FP64 interactions and kind 0 = the launch that holds the P2P tasks
+ * (with the leaves' moments under schedules 3-6, with M2P under schedule
+ * 2, the first of the two under schedules 4-6), 1 = the M2P launch (the
+ * second, joint one under 4-6; none under 2), 2 = the moments launches
+ * (P2M at the leaves and M2M up the tree under schedules 0-2, M2M alone
+ * under 3-6), 3 = the combine (near-field corrections, jump terms,
+ * scatter).  out: 16 doubles (host). */
+pbt_status pbt_kernel_times(pbt_ctx* ctx, double* out);
 
 #ifdef __cplusplus
 }

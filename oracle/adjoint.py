@@ -43,13 +43,13 @@ def _system_gradient(sysm: DenseBEM):
             # cavities from outside (eq. phi_reac_bem over the region's boundary)
             R = np.zeros((len(ss.q), sysm.n))
             vl, kl, _, _ = layer_blocks(ss.q_pos, sysm.panels[s], sysm.kappa, sysm.k_far,
-                                        sysm.k_near, sysm.k_self_edge)
+                                        sysm.k_near, sysm.k_self_edge, near_factor=sysm.near_factor)
             R[:, c:c + ss.nt] = -kl
             R[:, c + ss.nt:c + 2 * ss.nt] = vl
             for cv, sc in enumerate(sysm.surfs):
                 if sc.kind == CAVITY and sysm.outer[cv] == s:
                     vc, kc, _, _ = layer_blocks(ss.q_pos, sysm.panels[cv], sysm.kappa, sysm.k_far,
-                                                sysm.k_near, sysm.k_self_edge)
+                                                sysm.k_near, sysm.k_self_edge, near_factor=sysm.near_factor)
                     cc = sysm.col_off[cv]
                     R[:, cc:cc + sc.nt] = kc
                     R[:, cc + sc.nt:cc + 2 * sc.nt] = -(sc.eps_in / ss.eps_in) * vc

@@ -78,7 +78,7 @@ class Energies:
 class DenseBEM:
     """Dense BEM system of a problem (``workloads.Problem``-like object)."""
 
-    def __init__(self, problem, k_far=3, k_near=19, k_self_edge=9, enabled=None):
+    def __init__(self, problem, k_far=3, k_near=19, k_self_edge=9, enabled=None, near_factor=2.0):
         allsurfs = list(problem.surfaces)
         on = [True] * len(allsurfs) if enabled is None else list(enabled)
         keep = [i for i, o in enumerate(on) if o]
@@ -88,6 +88,7 @@ class DenseBEM:
         self.eps_out = float(problem.eps_out)
         self.kappa = float(problem.kappa)
         self.k_far, self.k_near, self.k_self_edge = k_far, k_near, k_self_edge
+        self.near_factor = float(near_factor)
         self.panels = [Panels(s.verts, s.tris) for s in surfs]
         # the region outside each surface: the solvent, or the layer of the
         # Stern surface that encloses it (the region inside surface k is k)
@@ -131,7 +132,7 @@ class DenseBEM:
         x = pt.centroid[idx]
         self_idx = idx if t == s else None
         return layer_blocks(x, ps, self.kappa, self.k_far, self.k_near, self.k_self_edge,
-                            self_idx=self_idx)
+                            self_idx=self_idx, near_factor=self.near_factor)
 
     def region_row(self, t, R, rows=None):
         """Rows (panels ``rows`` of surface t) of the equation of region R,
@@ -257,7 +258,7 @@ class DenseBEM:
         from outside (Laplace kernel, psi scaled by eps_cavity / eps_in)."""
         ss = self.surfs[s]
         vl, kl, _, _ = layer_blocks(ss.q_pos, self.panels[s], self.kappa, self.k_far,
-                                    self.k_near, self.k_self_edge, self_idx=None)
+                                    self.k_near, self.k_self_edge, self_idx=None, near_factor=self.near_factor)
         out = -kl @ phi + vl @ psi
         cavities = [c for c, sc in enumerate(self.surfs) if sc.kind == CAVITY and self.outer[c] == s]
         if cavities and parts is None:
@@ -265,7 +266,8 @@ class DenseBEM:
         for c in cavities:
             sc = self.surfs[c]
             vc, kc, _, _ = layer_blocks(ss.q_pos, self.panels[c], self.kappa, self.k_far,
-                                        self.k_near, self.k_self_edge, self_idx=None)
+                                        self.k_near, self.k_self_edge, self_idx=None,
+                                        near_factor=self.near_factor)
             pc, qc = parts[c]
             out += kc @ pc - (sc.eps_in / ss.eps_in) * (vc @ qc)
         return out
@@ -296,9 +298,9 @@ def coulomb_energy(pos, q, eps):
     return e / (FOUR_PI * eps)
 
 
-def solve_problem(problem, k_far=3, k_near=19, k_self_edge=9, enabled=None):
+def solve_problem(problem, k_far=3, k_near=19, k_self_edge=9, enabled=None, near_factor=2.0):
     """Dense LU solve and energies (kcal/mol).  Returns (Energies, u, system)."""
-    sysm = DenseBEM(problem, k_far, k_near, k_self_edge, enabled)
+    sysm = DenseBEM(problem, k_far, k_near, k_self_edge, enabled, near_factor)
     u, _, _ = sysm.solve()
     return sysm.energies(u), u, sysm
 

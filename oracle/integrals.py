@@ -18,13 +18,15 @@ Three regimes, as Section 3.1 describes them:
   the panel's plane; V is integrated in polar coordinates about x, the
   radial integral done in closed form and the angle integral written as a
   sum over edges with Gauss-Legendre points along each edge (Hess & Smith);
-* near (|x - c_j| < 2 L_j, L_j = sqrt(2 A_j)): the 19-point rule;
+* near (|x - c_j| < 2 L_j, L_j = sqrt(2 A_j)): the 19-point rule (the factor
+  2 is Section 3.1's; ``near_factor`` takes another);
 * far: the K-point rule.
 
 The near test is a decision of floating point over an integer outcome, so it
 is written as an exact sequence of correctly rounded FP64 operations without
-square roots:  (d2 * d2) < 16 * |e1 x e2|^2  with d2 = (dx*dx + dy*dy) + dz*dz,
-which is  |x - c_j| < 2 sqrt(2 A_j)  since |e1 x e2| = 2 A_j.
+square roots:  (d2 * d2) < f4 * |e1 x e2|^2  with d2 = (dx*dx + dy*dy) + dz*dz
+and f4 = (f * f) * (f * f), which is  |x - c_j| < f sqrt(2 A_j)  since
+|e1 x e2| = 2 A_j (f = 2: f4 = 16).
 """
 from __future__ import annotations
 
@@ -62,14 +64,17 @@ class Panels:
                 + bary[None, :, 2, None] * self.v2[:, None, :])
 
 
-def near_mask(x: np.ndarray, panels: Panels) -> np.ndarray:
-    """(M, N) boolean: target x_m is closer than 2 L_j to centroid c_j."""
+def near_mask(x: np.ndarray, panels: Panels, near_factor: float = 2.0) -> np.ndarray:
+    """(M, N) boolean: target x_m is closer than f L_j to centroid c_j (f = 2
+    in Section 3.1)."""
     c = panels.centroid
     dx = x[:, None, 0] - c[None, :, 0]
     dy = x[:, None, 1] - c[None, :, 1]
     dz = x[:, None, 2] - c[None, :, 2]
     d2 = (dx * dx + dy * dy) + dz * dz
-    return (d2 * d2) < 16.0 * panels.cross_norm2[None, :]
+    f = float(near_factor)
+    f4 = (f * f) * (f * f)
+    return (d2 * d2) < f4 * panels.cross_norm2[None, :]
 
 
 def point_kernels(x, y, n, kappa):
@@ -140,7 +145,7 @@ def pair_integrals(x, panels: Panels, cols, npts, kappa):
 
 
 def layer_blocks(x, panels: Panels, kappa, k_far=3, k_near=19, k_self_edge=9,
-                 self_idx=None, chunk_pairs=2_000_000):
+                 self_idx=None, chunk_pairs=2_000_000, near_factor=2.0):
     """Dense (M, N) blocks V_L, K_L, V_Y, K_Y of targets x against all panels.
 
     ``self_idx[m]`` is the panel that holds target m (or -1): that entry
@@ -156,7 +161,7 @@ def layer_blocks(x, panels: Panels, kappa, k_far=3, k_near=19, k_self_edge=9,
         blk = rule_integrals(x[r0:r1], panels, allc, k_far, kappa)
         for o, b in zip(out, blk):
             o[r0:r1] = b
-        near = near_mask(x[r0:r1], panels)
+        near = near_mask(x[r0:r1], panels, near_factor)
         if self_idx is not None:
             si = np.asarray(self_idx[r0:r1])
             has = si >= 0

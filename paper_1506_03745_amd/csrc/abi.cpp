@@ -76,8 +76,10 @@ struct pbt_ctx {
     double t0 = 0, t_setup = 0;
     int64_t apps = 0, pairs = 0;
     int32_t iters = 0;
-    std::map<const System*, int64_t> start;
+    std::map<const System*, int64_t> start, start_pairs;
   } cs;
+  bool profile = false;   // per-kernel event timing of every product (pbt_profile)
+  double prof_batch[16] = {0};   // totals of the batched systems (built and released per call)
   pbt_result last_stats{};
   // last solution
   std::vector<bool> sol_mask;
@@ -92,11 +94,11 @@ double wall_now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Adds the operator applications system S made since it stood at apps0.
-void stats_account(pbt_ctx* c, const System& S, int64_t apps0) {
-  const int64_t d = S.applications() - apps0;
-  c->cs.apps += d;
-  c->cs.pairs += d * S.dense_pairs();
+// Adds the operator applications system S made since it stood at apps0
+// (and the dense-equivalent pairs since pairs0).
+void stats_account(pbt_ctx* c, const System& S, int64_t apps0, int64_t pairs0) {
+  c->cs.apps += S.applications() - apps0;
+  c->cs.pairs += S.pairs_done() - pairs0;
 }
 
 pbt_status fail(pbt_ctx* c, int st, const std::string& m) {
@@ -128,11 +130,15 @@ pbt_status tracked(pbt_ctx* c, F&& f) {
   if (!c) return PBT_E_INVALID;
   c->cs = pbt_ctx::CallStats{};
   c->cs.t0 = wall_now();
-  for (auto& kv : c->systems) c->cs.start[kv.second.get()] = kv.second->applications();
+  for (auto& kv : c->systems) {
+    c->cs.start[kv.second.get()] = kv.second->applications();
+    c->cs.start_pairs[kv.second.get()] = kv.second->pairs_done();
+  }
   const pbt_status st = guarded(c, f);
   for (auto& kv : c->systems) {
     auto it = c->cs.start.find(kv.second.get());
-    stats_account(c, *kv.second, it == c->cs.start.end() ? 0 : it->second);
+    const bool had = it != c->cs.start.end();
+    stats_account(c, *kv.second, had ? it->second : 0, had ? c->cs.start_pairs[kv.second.get()] : 0);
   }
   pbt_result r{};
   r.iters = c->cs.iters;
@@ -156,6 +162,8 @@ std::string check_params(const pbt_params& p) {
   if (p.restart < 1 || p.restart > 1024) return "restart must be 1..1024";
   if (p.max_iter < 1) return "max_iter must be >= 1";
   if (p.prec != PBT_FP64 && p.prec != PBT_MIXED) return "prec must be PBT_FP64 or PBT_MIXED";
+  if (!(p.near_factor > 0.0) || !std::isfinite(p.near_factor) || p.near_factor > 1e3)
+    return "near_factor must be in (0, 1000]";
   return "";
 }
 
@@ -172,6 +180,7 @@ System& system_for(pbt_ctx* c) {
     it->second->set_gs_passes(c->gs_passes);
     return *it->second;
   }
+
   std::vector<const SurfIn*> on;
   for (auto& s : c->surfs)
     if (s->enabled) on.push_back(s.get());
@@ -187,8 +196,39 @@ System& system_for(pbt_ctx* c) {
   c->cs.t_setup += wall_now() - t0;
   System& r = *sys;
   r.set_gs_passes(c->gs_passes);
+  if (c->profile) r.set_profile(true);
   c->systems[m] = std::move(sys);
   return r;
+}
+
+// Device buffers of the _dev entry points: `ptr` must be device (or
+// managed) memory of this context's device; `n` doubles are copied to the
+// host in the order of `stream` (the call waits for them).
+void check_dev_ptr(const pbt_ctx* c, const void* ptr) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(PBT_E_INVALID, "not a device pointer");
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    throw Error(PBT_E_INVALID, "not a device pointer");
+  if (at.device != c->device) throw Error(PBT_E_INVALID, "device pointer of another device");
+}
+
+std::vector<double> from_dev(const pbt_ctx* c, const double* ptr, int64_t n, hipStream_t st) {
+  std::vector<double> h((size_t)std::max<int64_t>(n, 0));
+  if (n <= 0) return h;
+  check_dev_ptr(c, ptr);
+  PBT_HIP(hipMemcpyAsync(h.data(), ptr, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  PBT_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+void to_dev(const pbt_ctx* c, double* ptr, const std::vector<double>& h, hipStream_t st) {
+  if (h.empty()) return;
+  check_dev_ptr(c, ptr);
+  PBT_HIP(hipMemcpyAsync(ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  PBT_HIP(hipStreamSynchronize(st));
 }
 
 int local_of(const pbt_ctx* c, int id) {
@@ -207,6 +247,8 @@ pbt_status solve_impl(pbt_ctx* c, const double* x0, pbt_result* res) {
   c->dx.alloc(n);
   S.rhs(c->db.p, c->stream);
   if (x0) {
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(x0[i])) return fail(c, PBT_E_INVALID, "non-finite initial guess");
     c->dt.alloc(n);
     PBT_HIP(hipMemcpyAsync(c->dt.p, x0, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     S.to_internal(c->dt.p, c->dx.p, c->stream);
@@ -225,14 +267,17 @@ pbt_status solve_impl(pbt_ctx* c, const double* x0, pbt_result* res) {
   r.p2p_fused_pairs = S.plan().p2p_fused_pairs;
   r.matvecs = (int32_t)(S.applications() - apply0);
   c->cs.iters = std::max(c->cs.iters, r.iters);
+  if (!std::isfinite(r.F_total) || !std::isfinite(r.rel_resid)) {
+    // outputs untouched; no solution to read back
+    c->sol_mask.clear();
+    return fail(c, PBT_E_NUMERIC, "non-finite energy or residual");
+  }
   // the solution stays on the device until pbt_get_solution asks for it
   c->dsol.alloc(n);
   PBT_HIP(hipMemcpyAsync(c->dsol.p, c->dx.p, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   c->sol_on_host = false;
   c->sol_mask = mask_of(c);
   if (res) *res = r;
-  if (!std::isfinite(r.F_total) || !std::isfinite(r.rel_resid))
-    return fail(c, PBT_E_NUMERIC, "non-finite energy or residual");
   if (!ok) return fail(c, PBT_E_NOCONVERGE, "GMRES did not reach the tolerance within max_iter");
   return PBT_OK;
 }
@@ -254,6 +299,7 @@ void pbt_default_params(pbt_params* p) {
   p->max_iter = 1000;
   p->prec = PBT_FP64;
   p->treecode = 1;
+  p->near_factor = 2.0;
 }
 
 pbt_status pbt_create(pbt_ctx** out, int32_t hip_device, const pbt_params* params) {
@@ -400,6 +446,38 @@ pbt_status pbt_set_charges(pbt_ctx* c, int32_t mol_id, double eps_in, const doub
   return PBT_OK;
 }
 
+pbt_status pbt_set_bc_dev(pbt_ctx* c, int32_t id, const double* bc_dev, void* stream) {
+  if (!c) return PBT_E_INVALID;
+  if (id < 0 || id >= (int)c->surfs.size() || !bc_dev) return fail(c, PBT_E_INVALID, "bad surface id");
+  std::vector<double> bc;
+  const pbt_status st = guarded(c, [&] {
+    bc = from_dev(c, bc_dev, c->surfs[id]->nt, stream ? (hipStream_t)stream : c->stream);
+    return PBT_OK;
+  });
+  if (st != PBT_OK) return st;
+  return pbt_set_bc(c, id, bc.data());
+}
+
+pbt_status pbt_set_charges_dev(pbt_ctx* c, int32_t mol_id, double eps_in, const double* xyz_dev,
+                               const double* q_dev, int64_t nq, void* stream) {
+  if (!c) return PBT_E_INVALID;
+  if (mol_id < 0 || mol_id >= (int)c->surfs.size() || c->surfs[mol_id]->kind != PBT_MOLECULE)
+    return fail(c, PBT_E_INVALID, "not a molecule id");
+  if (nq < 0 || (nq > 0 && !q_dev)) return fail(c, PBT_E_INVALID, "bad charge arrays");
+  if (!xyz_dev && (int64_t)c->surfs[mol_id]->q.size() != nq)
+    return fail(c, PBT_E_INVALID, "xyz_dev is NULL but the number of charges changes");
+  std::vector<double> xyz, q;
+  const pbt_status st = guarded(c, [&] {
+    const hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    q = from_dev(c, q_dev, nq, s);
+    if (xyz_dev) xyz = from_dev(c, xyz_dev, 3 * nq, s);
+    return PBT_OK;
+  });
+  if (st != PBT_OK) return st;
+  if (!xyz_dev) xyz = c->surfs[mol_id]->qxyz;
+  return pbt_set_charges(c, mol_id, eps_in, xyz.data(), q.data(), nq);
+}
+
 pbt_status pbt_set_stern(pbt_ctx* c, int32_t stern_id, int32_t mol_id, double eps_layer) {
   if (!c) return PBT_E_INVALID;
   const int ns = (int)c->surfs.size();
@@ -476,6 +554,21 @@ pbt_status pbt_get_solution(pbt_ctx* c, int32_t id, double* phi, double* dphidn)
     int k = 0;
     for (int i = 0; i < id; ++i) k += c->sol_mask[i] ? 1 : 0;
     it->second->unpack(c->sol_x, k, phi, dphidn);
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_get_solution_dev(pbt_ctx* c, int32_t id, double* phi_dev, double* dphidn_dev, void* stream) {
+  if (!c) return PBT_E_INVALID;
+  if (id < 0 || id >= (int)c->surfs.size()) return fail(c, PBT_E_INVALID, "bad surface id");
+  const int64_t nt = c->surfs[id]->nt;
+  std::vector<double> phi(nt), d(nt);
+  const pbt_status st = pbt_get_solution(c, id, phi.data(), d.data());
+  if (st != PBT_OK) return st;
+  return guarded(c, [&] {
+    const hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    if (phi_dev) to_dev(c, phi_dev, phi, s);
+    if (dphidn_dev) to_dev(c, dphidn_dev, d, s);
     return PBT_OK;
   });
 }
@@ -642,6 +735,36 @@ pbt_status pbt_gradient(pbt_ctx* c, int32_t sigma_id, double* dF_dsigma, int32_t
   });
 }
 
+pbt_status pbt_gradient_dev(pbt_ctx* c, int32_t sigma_id, double* dF_dsigma_dev, int32_t mol_id, double* dF_dq_dev,
+                            void* stream) {
+  if (!c) return PBT_E_INVALID;
+  const int ns = (int)c->surfs.size();
+  if (sigma_id >= ns || mol_id >= ns || (sigma_id < 0 && mol_id < 0)) return fail(c, PBT_E_INVALID, "bad surface ids");
+  if ((sigma_id >= 0 && !dF_dsigma_dev) || (mol_id >= 0 && !dF_dq_dev))
+    return fail(c, PBT_E_INVALID, "null gradient buffer");
+  std::vector<double> ds(sigma_id >= 0 ? c->surfs[sigma_id]->nt : 0);
+  std::vector<double> dq(mol_id >= 0 ? c->surfs[mol_id]->q.size() : 0);
+  // both buffers checked before any work, so a bad pointer leaves nothing done
+  pbt_status st = guarded(c, [&] {
+    if (sigma_id >= 0 && !ds.empty()) check_dev_ptr(c, dF_dsigma_dev);
+    if (mol_id >= 0 && !dq.empty()) check_dev_ptr(c, dF_dq_dev);
+    return PBT_OK;
+  });
+  if (st != PBT_OK) return st;
+  st = pbt_gradient(c, sigma_id, sigma_id >= 0 ? ds.data() : nullptr, mol_id, mol_id >= 0 ? dq.data() : nullptr);
+  if (st != PBT_OK && st != PBT_E_NOCONVERGE) return st;
+  const std::string msg = c->err;
+  const pbt_status cp = guarded(c, [&] {
+    const hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    if (sigma_id >= 0) to_dev(c, dF_dsigma_dev, ds, s);
+    if (mol_id >= 0) to_dev(c, dF_dq_dev, dq, s);
+    return PBT_OK;
+  });
+  if (cp != PBT_OK) return cp;
+  if (st != PBT_OK) c->err = msg;
+  return st;
+}
+
 // Batched rigid placements (orientation sweep).  Up to kBatch assemblies are
 // put into one block-diagonal system: group g holds the molecule moved by
 // placement g and copies of every other enabled surface; interaction and
@@ -735,6 +858,7 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
       const double ts = wall_now();
       System S(list, c->prm, c->eps_out, c->kappa, c->stream);
       c->cs.t_setup += wall_now() - ts;
+      if (c->profile) S.set_profile(true);
       const int64_t n = S.n();
       DBuf<double> b, x;
       b.alloc(n);
@@ -746,7 +870,8 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
       c->cs.iters = std::max(c->cs.iters, r.iters);
       std::vector<pbt_result> e = S.energies_by_group(x.p, G, c->stream);
       for (int g = 0; g < G; ++g) F_int[b0 + g] = e[g].F_total - f_iso;
-      stats_account(c, S, 0);
+      stats_account(c, S, 0, 0);
+      if (c->profile) S.add_profile(c->prof_batch);
     }
     if (worst != PBT_OK) return fail(c, worst, "a batched solve did not reach the tolerance");
     return PBT_OK;
@@ -913,6 +1038,25 @@ pbt_status pbt_last_matvec_timing(pbt_ctx* c, double out[5]) {
     if (!out) return fail(c, PBT_E_INVALID, "null buffer");
     System& S = system_for(c);
     S.timing(out);
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_profile(pbt_ctx* c, int32_t on) {
+  if (!c) return PBT_E_INVALID;
+  return guarded(c, [&] {
+    c->profile = on != 0;
+    for (auto& kv : c->systems) kv.second->set_profile(c->profile);
+    for (double& v : c->prof_batch) v = 0.0;
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_kernel_times(pbt_ctx* c, double* out) {
+  if (!c || !out) return fail(c, PBT_E_INVALID, "null argument");
+  return guarded(c, [&] {
+    for (int k = 0; k < 16; ++k) out[k] = c->prof_batch[k];
+    for (auto& kv : c->systems) kv.second->add_profile(out);
     return PBT_OK;
   });
 }

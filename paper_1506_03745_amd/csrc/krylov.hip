@@ -225,6 +225,7 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
                                                         double* sn, double* gv, double* resid, NextSrc ns) {
   extern __shared__ double sh[];   // h[m], h2[m + 1], col[m + 1], c[m], s[m]
   __shared__ double nn_s;
+  __shared__ int shaky_s;
   double* h = sh;
   double* h2 = h + m;
   double* col = h2 + (m + 1);
@@ -285,7 +286,13 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     double h2s = 0.0;
     for (int i = threadIdx.x; i <= j; i += 64) h2s += h2[i] * h2[i];
     h2s = wave_sum(h2s);
-    if (threadIdx.x == 0) nn_s = fmax(h2[j + 1] - h2s, 0.0);
+    if (threadIdx.x == 0) {
+      // |w'|^2 = |w|^2 - |h|^2 cancels when w lies almost in the Krylov
+      // space: below 64 rounding units of |w|^2 the norm (and the residual
+      // estimate it gives) is not to be trusted
+      nn_s = fmax(h2[j + 1] - h2s, 0.0);
+      shaky_s = nn_s <= 64.0 * 2.220446049250313e-16 * h2[j + 1];
+    }
   }
   __syncthreads();
   const double nn = nn_s;
@@ -365,7 +372,9 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     const double gj = gg[j];
     gg[j + 1] = -sj * gj;
     gg[j] = cj * gj;
-    resid[(size_t)g * m + j] = hn > 0 ? fabs(sj * gj) : 0.0;
+    // a step whose norm cancelled reports -1: the host restarts from the
+    // true residual instead of reading a converged estimate
+    resid[(size_t)g * m + j] = shaky_s ? -1.0 : hn > 0 ? fabs(sj * gj) : 0.0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j + 1; i += kBS) Hg[(size_t)i * m + j] = col[i];

@@ -86,14 +86,16 @@ void launch_panel_geometry(int64_t np, const double* tri9, double* cen, double* 
 void launch_sources(int64_t np, int K, const double* tri9, const double* nrm, const double* area,
                     const double* bary, const double* w, double* src_pos, double* src_wa,
                     hipStream_t s);
-// Near lists (panels closer than 2L): every target scans all np panels
-// (tleaf null) or the candidate ranges of its leaf (CSR lptr / lrange).
+// Near lists (panels closer than f L, f = near_factor, 2 in the paper):
+// every target scans all np panels (tleaf null) or the candidate ranges of
+// its leaf (CSR lptr / lrange); f4 = (f f)(f f).
+inline double near_f4(double f) { return (f * f) * (f * f); }
 void launch_near_count(int64_t nt, const double* tx, int64_t np, const double* cen,
                        const double* cross2, const int32_t* tleaf, const int64_t* lptr,
-                       const int64_t* lrange, int32_t* count, hipStream_t s);
+                       const int64_t* lrange, double f4, int32_t* count, hipStream_t s);
 void launch_near_fill(int64_t nt, const double* tx, int64_t np, const double* cen,
                       const double* cross2, const int32_t* tleaf, const int64_t* lptr,
-                      const int64_t* lrange, const int64_t* rowptr, int32_t* col, hipStream_t s);
+                      const int64_t* lrange, double f4, const int64_t* rowptr, int32_t* col, hipStream_t s);
 void launch_pack_points(int64_t np, int64_t ns, const double* cen, const double* src_pos, double* t64, float* t32,
                         double* s64, float* s32, hipStream_t s);
 struct NearParams {
@@ -206,6 +208,11 @@ template <typename T>
 void launch_moments(int P, int nblocks, const int32_t* mblocks, const MomChunk* chunks, int nheads,
                     const MomChunk* heads, const double* bcen, const double* brho, const T* src, T* mom, T* mpart,
                     hipStream_t s);
+// Moments of one tree level's boxes from their children's (M2M), for the
+// nbox boxes listed (child lists cbeg / cend / clist, global numbering).
+template <typename T>
+void launch_m2m(int P, int nbox, const int32_t* boxes, const int32_t* cbeg, const int32_t* cend,
+                const int32_t* clist, const double* bcen, T* mom, hipStream_t s);
 // M2P and P2P tasks in one launch (taylor.hip).
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,

@@ -66,12 +66,15 @@ __global__ void k_sources(int64_t np, int K, const double* __restrict__ tri9,
   src_wa[j] = w[q] * area[p];
 }
 
+// |x - c| < f L with L = sqrt(2 A) = sqrt(|e1 x e2|), i.e. d^4 < f^4 |e1 x e2|^2
+// (f4 = (f f)(f f), 16 for the paper's 2L), in one fixed sequence of
+// correctly rounded FP64 operations.
 __device__ __forceinline__ bool is_near(double tx, double ty, double tz, double cx, double cy,
-                                        double cz, double c2) {
+                                        double cz, double c2, double f4) {
 #pragma clang fp contract(off)
   const double dx = tx - cx, dy = ty - cy, dz = tz - cz;
   const double d2 = (dx * dx + dy * dy) + dz * dz;
-  return (d2 * d2) < 16.0 * c2;
+  return (d2 * d2) < f4 * c2;
 }
 
 // One wavefront per target, lanes over panels.  The fill pass writes the
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(256) void k_near(int64_t nt, const double* __restri
                                               const double* __restrict__ cross2,
                                               const int32_t* __restrict__ tleaf,
                                               const int64_t* __restrict__ lptr,
-                                              const int64_t* __restrict__ lrange, int32_t* count,
+                                              const int64_t* __restrict__ lrange, double f4, int32_t* count,
                                               const int64_t* __restrict__ rowptr, int32_t* col) {
   const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(256) void k_near(int64_t nt, const double* __restri
     const int64_t jb = tleaf ? lrange[2 * r] : 0, je = tleaf ? lrange[2 * r + 1] : np;
     for (int64_t j0 = jb; j0 < je; j0 += 64) {
       const int64_t j = j0 + lane;
-      const bool hit = j < je && is_near(x, y, z, cen[3 * j], cen[3 * j + 1], cen[3 * j + 2], cross2[j]);
+      const bool hit = j < je && is_near(x, y, z, cen[3 * j], cen[3 * j + 1], cen[3 * j + 2], cross2[j], f4);
       const uint64_t m = __ballot(hit);
       if (FILL) {
         if (hit) col[out + __popcll(m & below)] = (int32_t)j;
@@ -305,18 +308,18 @@ void launch_sources(int64_t np, int K, const double* tri9, const double* nrm, co
 
 void launch_near_count(int64_t nt, const double* tx, int64_t np, const double* cen,
                        const double* cross2, const int32_t* tleaf, const int64_t* lptr,
-                       const int64_t* lrange, int32_t* count, hipStream_t s) {
+                       const int64_t* lrange, double f4, int32_t* count, hipStream_t s) {
   if (nt <= 0) return;
-  k_near<false><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tleaf, lptr, lrange, count,
+  k_near<false><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tleaf, lptr, lrange, f4, count,
                                                         nullptr, nullptr);
   PBT_HIP(hipGetLastError());
 }
 
 void launch_near_fill(int64_t nt, const double* tx, int64_t np, const double* cen,
                       const double* cross2, const int32_t* tleaf, const int64_t* lptr,
-                      const int64_t* lrange, const int64_t* rowptr, int32_t* col, hipStream_t s) {
+                      const int64_t* lrange, double f4, const int64_t* rowptr, int32_t* col, hipStream_t s) {
   if (nt <= 0) return;
-  k_near<true><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tleaf, lptr, lrange, nullptr,
+  k_near<true><<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, tx, np, cen, cross2, tleaf, lptr, lrange, f4, nullptr,
                                                        rowptr, col);
   PBT_HIP(hipGetLastError());
 }

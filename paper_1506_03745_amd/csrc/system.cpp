@@ -41,6 +41,7 @@ System::System(const std::vector<const SurfIn*>& surfs, const pbt_params& prm, d
 
 System::~System() {
   if (s2_) (void)hipStreamSynchronize(s2_);
+  for (auto& e : pev_) (void)hipEventDestroy(e);
   for (auto& e : ev_) (void)hipEventDestroy(e);
   for (auto& e : evm_) (void)hipEventDestroy(e);
   for (auto& e : evg_) (void)hipEventDestroy(e);
@@ -146,8 +147,15 @@ void System::build(hipStream_t s) {
   {
     std::map<int, int64_t> gp;   // panels per group
     for (int e = 0; e < ns; ++e) gp[surfs_[e]->group] += surfs_[e]->nt;
+    std::map<int, int64_t> gk;   // Gauss points with known densities per group
+    for (int e = 0; e < ns; ++e)
+      if (surfs_[e]->kind == PBT_CHARGED || surfs_[e]->kind == PBT_POTENTIAL) gk[surfs_[e]->group] += surfs_[e]->nt * K_;
     dense_pairs_ = 0;
-    for (const auto& kv : gp) dense_pairs_ += kv.second * kv.second * K_;
+    known_pairs_ = 0;
+    for (const auto& kv : gp) {
+      dense_pairs_ += kv.second * kv.second * K_;
+      known_pairs_ += kv.second * gk[kv.first];
+    }
   }
 
   // ---- internal-order triangles ---------------------------------------------
@@ -307,7 +315,7 @@ void System::build(hipStream_t s) {
     std::vector<double> lmax(ns, 0.0);
     for (int e = 0; e < ns; ++e)
       for (int64_t li = 0; li < surfs_[e]->nt; ++li)
-        lmax[e] = std::max(lmax[e], 2.0 * std::sqrt(2.0 * h_area_[poff_[e] + li]));
+        lmax[e] = std::max(lmax[e], prm_.near_factor * std::sqrt(2.0 * h_area_[poff_[e] + li]));
     struct TL { int e; const TreeBox* T; };
     std::vector<TL> tls;
     for (int e = 0; e < ns; ++e)
@@ -355,7 +363,8 @@ void System::build(hipStream_t s) {
     dlrange.upload(lrange, s);
     DBuf<int32_t> cnt;
     cnt.alloc(np_);
-    launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, cnt.p, s);
+    launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, near_f4(prm_.near_factor),
+                      cnt.p, s);
     std::vector<int32_t> hc = cnt.download(s);
     std::vector<int64_t> ptr(np_ + 1, 0);
     for (int64_t i = 0; i < np_; ++i) ptr[i + 1] = ptr[i] + hc[i];
@@ -363,8 +372,8 @@ void System::build(hipStream_t s) {
     near_.ptr.upload(ptr, s);
     near_.col.alloc(std::max<int64_t>(near_.nnz, 1));
     near_.val.alloc(4 * std::max<int64_t>(near_.nnz, 1));
-    launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, near_.ptr.p,
-                     near_.col.p, s);
+    launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, near_f4(prm_.near_factor),
+                     near_.ptr.p, near_.col.p, s);
     std::vector<int32_t> self(np_);
     for (int64_t i = 0; i < np_; ++i) self[i] = (int32_t)i;
     DBuf<int32_t> dself;
@@ -381,19 +390,52 @@ void System::build(hipStream_t s) {
 
   build_plan();
   upload_plan(s);
-  // Moments of every box that some M2P task reads, from its own sources,
-  // in chunks of at most kMomChunk sources.
+  // Moments of every box that some M2P task reads and of all its
+  // descendants: the leaves from their own sources (P2M), in chunks of at
+  // most kMomChunk sources; every other box from its children's moments
+  // (M2M), one tree level per launch from the deepest up.
   {
-    std::vector<char> used(nbox_, 0);
+    std::vector<char> used(nbox_, 0), need(nbox_, 0), leaf(nbox_, 0);
+    std::vector<int32_t> par(nbox_, -1), lev(nbox_, 0);
+    int maxlev = 0;
+    for (int e = 0; e < ns; ++e)
+      for (size_t bi = 0; bi < trees_[e].boxes.size(); ++bi) {
+        const TreeBox& tb = trees_[e].boxes[bi];
+        const int g = (int)(boff_[e] + bi);
+        par[g] = tb.parent >= 0 ? (int32_t)(boff_[e] + tb.parent) : -1;
+        lev[g] = tb.level;
+        leaf[g] = tb.leaf ? 1 : 0;
+        maxlev = std::max(maxlev, tb.level);
+      }
     for (int32_t b : plan_.blist) used[b] = 1;
+    // a box's parent precedes it in the numbering of its tree
+    for (int b = 0; b < nbox_; ++b) need[b] = used[b] || (par[b] >= 0 && need[par[b]]);
     std::vector<MomChunk> ch, heads;
     int32_t slots = 0;
     std::vector<int32_t> sb = bsbeg_.download(s), se = bsend_.download(s);
     std::vector<char> known_box(nbox_, 0);
     for (int e = 0; e < ns; ++e)
       for (int64_t b = boff_[e]; b < boff_[e + 1]; ++b) known_box[b] = !two_rows(e);
+    // M2M levels (deepest first), all boxes and those of known surfaces
+    std::vector<int32_t> lb, lbk;
+    m2m_levels_.clear();
+    m2m_levels_known_.clear();
+    for (int lv = maxlev; lv >= 0; --lv) {
+      const size_t a0 = lb.size(), k0 = lbk.size();
+      for (int b = 0; b < nbox_; ++b)
+        if (need[b] && !leaf[b] && lev[b] == lv) {
+          lb.push_back(b);
+          if (known_box[b]) lbk.push_back(b);
+        }
+      if (lb.size() > a0) m2m_levels_.push_back({(int)a0, (int)(lb.size() - a0)});
+      if (lbk.size() > k0) m2m_levels_known_.push_back({(int)k0, (int)(lbk.size() - k0)});
+    }
+    if (lb.empty()) lb.push_back(0);
+    if (lbk.empty()) lbk.push_back(0);
+    m2m_boxes_.upload(lb, s);
+    m2m_boxes_known_.upload(lbk, s);
     for (int b = 0; b < nbox_; ++b) {
-      if (!used[b] || se[b] <= sb[b]) continue;
+      if (!need[b] || !leaf[b] || se[b] <= sb[b]) continue;
       const int32_t n = se[b] - sb[b];
       if (n <= kMomFineMax) {
         // one chunk; a box above kMomChunk sources spreads over finer
@@ -799,6 +841,20 @@ void System::build_plan() {
     }
     double missued = 0;
     for (const Task& t : P.m2p) missued += 64.0 * (t.lend - t.lbeg);
+    // (target, box) M2P pairs by the box's number of sources
+    std::vector<int64_t> bsrc(nbox_, 0);
+    for (int e = 0; e < ns; ++e)
+      for (size_t bi = 0; bi < trees_[e].boxes.size(); ++bi)
+        bsrc[boff_[e] + bi] = (int64_t)(trees_[e].boxes[bi].pend - trees_[e].boxes[bi].pbeg) * K_;
+    int64_t hist[6] = {0, 0, 0, 0, 0, 0};
+    for (const Task& t : P.m2p)
+      for (int32_t r = t.lbeg; r < t.lend; ++r) {
+        const int64_t n = bsrc[P.blist[r]];
+        hist[n < 16 ? 0 : n < 32 ? 1 : n < 64 ? 2 : n < 128 ? 3 : n < 256 ? 4 : 5] += t.tcount;
+      }
+    std::fprintf(stderr, "[plan] m2p pairs by box sources <16 / <32 / <64 / <128 / <256 / more: "
+                 "%lld / %lld / %lld / %lld / %lld / %lld\n", (long long)hist[0], (long long)hist[1],
+                 (long long)hist[2], (long long)hist[3], (long long)hist[4], (long long)hist[5]);
     std::fprintf(stderr, "[plan] p2p pairs %lld (fused %lld), waves %zu, halves split 1/2/4: %lld/%lld/%lld, "
                  "empty halves %lld, lane utilisation %.3f; m2p pairs %lld, tasks %zu, lane utilisation %.3f\n",
                  (long long)P.p2p_pairs, (long long)P.p2p_fused_pairs, P.p2p.size() / 2, (long long)nsplit[1],
@@ -811,12 +867,13 @@ void System::build_plan() {
 // M2M, M2P) runs on the system's second stream; the two write disjoint
 // partial slots and join before the combine.
 template <typename T>
-void System::interactions(hipStream_t s, const double* x, bool timed, bool src_ready, bool known_only) {
+void System::interactions(hipStream_t s, const double* x, bool timed, bool src_ready, bool known_only,
+                          const ExtParts* ext) {
   const bool f32 = std::is_same<T, float>::value;
   T* src = f32 ? (T*)src32_.p : (T*)src64_.p;
   const T* tgt = f32 ? (const T*)tgt32_.p : (const T*)tgt64_.p;
-  T* part = f32 ? (T*)part32_.p : (T*)part64_.p;
-  T* ppart = f32 ? (T*)ppart32_.p : (T*)ppart64_.p;
+  T* part = ext ? (T*)ext->part : f32 ? (T*)part32_.p : (T*)part64_.p;
+  T* ppart = ext ? (T*)ext->ppart : f32 ? (T*)ppart32_.p : (T*)ppart64_.p;
   const int npairs = (int)((known_only ? plan_.p2p_known.size() : plan_.p2p.size()) / 2);
   T* mom = f32 ? (T*)mom32_.p : (T*)mom64_.p;
   if (src_ready) {
@@ -851,14 +908,40 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   if (timed || two) PBT_HIP(hipEventRecord(ev_[1], s));
   const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
   T* msum = f32 ? (T*)msum32_.p : (T*)msum64_.p;
+  // per-kernel profile marks (full products only)
+  const bool pf = prof_ && !known_only;
+  const int pbase = f32 ? 0 : 4;
+  auto pb = [&](hipStream_t st) { return pf ? prof_begin(st) : -1; };
+  auto pe = [&](int kind, int e0, hipStream_t st) {
+    if (e0 >= 0) prof_end(pbase + kind, e0, st);
+  };
+  // M2M up the tree after the leaves' moments (P2M)
+  const auto& m2m_lv = known_only ? m2m_levels_known_ : m2m_levels_;
+  const int32_t* m2m_bx = known_only ? m2m_boxes_known_.p : m2m_boxes_.p;
+  auto m2m = [&](hipStream_t fs) {
+    for (const auto& lv : m2m_lv)
+      launch_m2m<T>(prm_.taylor_p, lv.second, m2m_bx + lv.first, bcbeg_.p, bcend_.p, bclist_.p, bcen_.p, mom, fs);
+  };
   auto moments = [&](hipStream_t fs) {
+    const int e0 = pb(fs);
     launch_moments<T>(prm_.taylor_p, nmb, mbl, mch, nmh, mhd, bcen_.p, brho_.p, src, mom, msum, fs);
+    m2m(fs);
+    pe(2, e0, fs);
+  };
+  // after a launch that computed the leaves' moments with P2P
+  auto m2m_marked = [&](hipStream_t fs) {
+    if (m2m_lv.empty()) return;
+    const int e0 = pb(fs);
+    m2m(fs);
+    pe(2, e0, fs);
   };
   auto far_field = [&](hipStream_t fs) {
     if (timed) PBT_HIP(hipEventRecord(evm_[0], fs));
     moments(fs);
     if (timed) PBT_HIP(hipEventRecord(evm_[1], fs));
+    const int e0 = pb(fs);
     launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, fs);
+    pe(1, e0, fs);
     if (timed || two) PBT_HIP(hipEventRecord(evm_[2], fs));
   };
   if (fused) {
@@ -871,8 +954,10 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
       PBT_HIP(hipEventRecord(evm_[2], s));
       PBT_HIP(hipEventRecord(ev_[2], s));
     }
+    const int e0 = pb(s);
     launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks, npairs,
                       dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
+    pe(0, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
       PBT_HIP(hipEventRecord(ev_[4], s));
@@ -883,15 +968,20 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   if (split) {
     const int nb = (int)((int64_t)npairs >> (7 - far_mode_)), na = npairs - nb;
     if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
+    int e0 = pb(s);
     launch_p2p_moments<T>(prm_.taylor_p, nmb, mbl, mch, nmh, mhd, bcen_.p, brho_.p, mom, msum, p2p_tasks, na,
                           dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    pe(0, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
       PBT_HIP(hipEventRecord(evm_[0], s));
-      PBT_HIP(hipEventRecord(evm_[1], s));
     }
+    m2m_marked(s);
+    if (timed) PBT_HIP(hipEventRecord(evm_[1], s));
+    e0 = pb(s);
     launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks + 2 * (int64_t)na, nb,
                       dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
+    pe(1, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(evm_[2], s));
       PBT_HIP(hipEventRecord(ev_[4], s));
@@ -902,14 +992,19 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   if (with_mom) {
     // moments inside the P2P launch (and its timing), then M2P
     if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
+    int e0 = pb(s);
     launch_p2p_moments<T>(prm_.taylor_p, nmb, mbl, mch, nmh, mhd, bcen_.p, brho_.p, mom, msum, p2p_tasks, npairs,
                           dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    pe(0, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
       PBT_HIP(hipEventRecord(evm_[0], s));
-      PBT_HIP(hipEventRecord(evm_[1], s));
     }
+    m2m_marked(s);
+    if (timed) PBT_HIP(hipEventRecord(evm_[1], s));
+    e0 = pb(s);
     launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, s);
+    pe(1, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(evm_[2], s));
       PBT_HIP(hipEventRecord(ev_[4], s));
@@ -918,7 +1013,9 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     return;
   }
   if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
+  const int e0 = pb(s);
   launch_p2p<T>(p2p_tasks, npairs, dranges_.p, tgt, src, (T)kappa_, guard, ppart, s);
+  pe(0, e0, s);
   if (timed) PBT_HIP(hipEventRecord(ev_[3], s));
   if (two) {
     // P2P (already queued) and the far field on the second stream overlap
@@ -933,11 +1030,12 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
 }
 
 void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x,
-                   bool timed, bool src_ready, const DotReq* dots, bool known_only) {
+                   bool timed, bool src_ready, const DotReq* dots, bool known_only, const ExtParts* ext) {
   ++napply_;
+  pairs_done_ += known_only ? known_pairs_ : dense_pairs_;
   if (timed) PBT_HIP(hipEventRecord(ev_[0], s));
-  if (fp32) interactions<float>(s, from_x ? x : nullptr, timed, src_ready, known_only);
-  else interactions<double>(s, from_x ? x : nullptr, timed, src_ready, known_only);
+  if (fp32) interactions<float>(s, from_x ? x : nullptr, timed, src_ready, known_only, ext);
+  else interactions<double>(s, from_x ? x : nullptr, timed, src_ready, known_only, ext);
   CombineArgs a{};
   a.np = np_;
   a.chunks = dchunks_.p;
@@ -961,9 +1059,62 @@ void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStre
     a.nbh = plan_.nbh;
     a.self_dot = dots->self_dot;
   }
-  if (fp32) launch_combine<float>(a, part32_.p, ppart32_.p, y, s);
-  else launch_combine<double>(a, part64_.p, ppart64_.p, y, s);
+  const int e0 = prof_ && !known_only ? prof_begin(s) : -1;
+  if (fp32)
+    launch_combine<float>(a, ext ? (const float*)ext->part : part32_.p, ext ? (const float*)ext->ppart : ppart32_.p,
+                          y, s);
+  else
+    launch_combine<double>(a, ext ? (const double*)ext->part : part64_.p,
+                           ext ? (const double*)ext->ppart : ppart64_.p, y, s);
+  if (e0 >= 0) prof_end((fp32 ? 0 : 4) + 3, e0, s);
   if (timed) PBT_HIP(hipEventRecord(ev_[5], s));
+}
+
+void System::set_profile(bool on) {
+  prof_flush();
+  prof_ = on;
+  for (int k = 0; k < 8; ++k) {
+    ptot_[k] = 0;
+    pcnt_[k] = 0;
+  }
+}
+
+int System::prof_begin(hipStream_t s) {
+  constexpr int kPool = 4096;
+  if (pev_.empty()) {
+    pev_.resize(kPool);
+    for (auto& e : pev_) PBT_HIP(hipEventCreate(&e));
+  }
+  if (pev_used_ + 2 > (int)pev_.size()) prof_flush();
+  const int e0 = pev_used_++;
+  PBT_HIP(hipEventRecord(pev_[e0], s));
+  return e0;
+}
+
+void System::prof_end(int slot, int e0, hipStream_t s) {
+  const int e1 = pev_used_++;
+  PBT_HIP(hipEventRecord(pev_[e1], s));
+  pmarks_.push_back({slot, e0, e1});
+}
+
+void System::prof_flush() {
+  for (const PMark& m : pmarks_) {
+    PBT_HIP(hipEventSynchronize(pev_[m.e1]));
+    float ms = 0;
+    PBT_HIP(hipEventElapsedTime(&ms, pev_[m.e0], pev_[m.e1]));
+    ptot_[m.slot] += ms;
+    pcnt_[m.slot] += 1;
+  }
+  pmarks_.clear();
+  pev_used_ = 0;
+}
+
+void System::add_profile(double out[16]) {
+  prof_flush();
+  for (int k = 0; k < 8; ++k) {
+    out[2 * k] += ptot_[k];
+    out[2 * k + 1] += (double)pcnt_[k];
+  }
 }
 
 void System::timing(double out[5]) {
@@ -986,8 +1137,8 @@ void System::timing(double out[5]) {
 }
 
 void System::matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed, bool src_ready,
-                    const DotReq* dots) {
-  apply(fp32, true, x, y, s, true, timed, src_ready, dots);
+                    const DotReq* dots, const ExtParts* ext) {
+  apply(fp32, true, x, y, s, true, timed, src_ready, dots, false, ext);
 }
 
 // Known densities of the charged (sigma) and potential (phi0) surfaces, in
@@ -1251,7 +1402,9 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
     launch_arnoldi_update(dgu_.p, G, gmax_, k, m, R, nbj, part2, h1, V_.p, n_, vj1, dH, dcs, dsn, dg, rs,
                           fuse ? &nsrc : nullptr, s);
   };
+  bool shaky = false;
   while (pending() && iters < maxit) {
+    shaky = false;
     std::vector<int> used(G, 0);
     std::vector<char> done(G, 0);
     for (int g = 0; g < G; ++g) {
@@ -1303,8 +1456,17 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
         if (done[g]) continue;
         for (int k = q.beg; k < q.beg + q.cnt; ++k) {
           used[g] = k + 1;
-          resid_out[g] = rs[(size_t)g * m + k];
-          if (rs[(size_t)g * m + k] <= tol_abs[g]) {
+          const double rk = rs[(size_t)g * m + k];
+          if (rk < 0.0) {
+            // the step's norm cancelled (its basis vector is unusable, the
+            // steps up to it are fine): this cycle ends for the group, the
+            // next starts from its true residual, with two passes
+            done[g] = 1;
+            shaky = true;
+            break;
+          }
+          resid_out[g] = rk;
+          if (rk <= tol_abs[g]) {
             done[g] = 1;
             break;
           }
@@ -1318,6 +1480,10 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
     for (int g = 0; g < G; ++g) umax = std::max(umax, used[g]);
     nwasted_ += j - umax;
     iters += umax;
+    if (shaky) {
+      passes = 2;
+      all_done = false;
+    }
     // per group: x += V y with H(0:used,0:used) y = g(0:used); the H rows
     // and g entries read were final before any later step was enqueued
     PBT_HIP(hipMemcpyAsync(hH, dH, G * HS * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1381,6 +1547,7 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
   res->iters = 0;
   res->outer = 0;
   res->matvecs = 0;
+  res->fp64_fallback = 0;
   const double tol = prm_.tol;
   group_rel_.assign(G, 0.0);
   auto relmax = [&](const std::vector<double>& rn) {
@@ -1406,12 +1573,21 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
     res->outer = 1;
     true_residual(b, x, tmp_.p, s);
     rel = relmax(group_norms(tmp_.p, s));
+    // the estimates of the last cycle can undershoot the true residual
+    // (rounding in the recurrences): continue from x while it misses
+    for (int extra = 0; extra < 4 && rel > tol * (1.0 + 1e-12) && res->iters < prm_.max_iter; ++extra) {
+      res->iters += gmres(false, b, x, false, tabs, m, prm_.max_iter - res->iters, est, s);
+      res->outer += 1;
+      true_residual(b, x, tmp_.p, s);
+      rel = relmax(group_norms(tmp_.p, s));
+    }
   } else {
     // Iterative refinement: FP32-interaction GMRES on the FP64 residual.
     if (x0_given) true_residual(b, x, tmp_.p, s);
     else PBT_HIP(hipMemcpyAsync(tmp_.p, b, n_ * sizeof(double), hipMemcpyDeviceToDevice, s));
     std::vector<double> rn = x0_given ? group_norms(tmp_.p, s) : bn;
     rel = relmax(rn);
+    bool inner32 = true;
     for (int outer = 0; outer < 20 && rel > tol && res->iters < prm_.max_iter; ++outer) {
       // Each running group's inner solve aims straight at the requested
       // tolerance; the FP32 operator's relative error (~1e-7) bounds how far
@@ -1421,15 +1597,26 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
           tabs[g] = rn[g];
           continue;
         }
-        tabs[g] = std::min(0.5, std::max(0.5 * tol * bn[g] / rn[g], 2e-7)) * rn[g];
+        tabs[g] = std::min(0.5, std::max(0.5 * tol * bn[g] / rn[g], inner32 ? 2e-7 : 0.0)) * rn[g];
       }
       PBT_HIP(hipMemsetAsync(y_.p, 0, n_ * sizeof(double), s));
-      res->iters += gmres(true, tmp_.p, y_.p, true, tabs, m, prm_.max_iter - res->iters, est, s, &rn);
+      res->iters += gmres(inner32, tmp_.p, y_.p, true, tabs, m, prm_.max_iter - res->iters, est, s, &rn);
       launch_axpby(n_, 1.0, y_.p, 1.0, x, s);
       true_residual(b, x, tmp_.p, s);
-      rn = group_norms(tmp_.p, s);
+      std::vector<double> rn2 = group_norms(tmp_.p, s);
+      // refinement stagnates when a correction from the FP32 operator no
+      // longer halves a running group's FP64 residual: the rest of the
+      // solve takes FP64 inner solves
+      bool stalled = false;
+      for (int g = 0; g < G; ++g)
+        if (bn[g] > 0 && rn[g] > tol * bn[g] && !(rn2[g] <= 0.5 * rn[g])) stalled = true;
+      rn = rn2;
       rel = relmax(rn);
       res->outer = outer + 1;
+      if (stalled && inner32 && rel > tol) {
+        inner32 = false;
+        res->fp64_fallback = 1;
+      }
     }
   }
   res->rel_resid = rel;

@@ -146,8 +146,16 @@ class System {
     int R;
     int self_dot = 0;
   };
+  // Caller-owned buffers for the P2P and M2P partial sums of a product
+  // (instead of the system's own), of part_need() / ppart_need() bytes.
+  struct ExtParts {
+    void* part;
+    void* ppart;
+  };
+  size_t part_need(bool fp32) const { return fp32 ? part_bytes<float>() : part_bytes<double>(); }
+  size_t ppart_need(bool fp32) const { return fp32 ? ppart_bytes<float>() : ppart_bytes<double>(); }
   void matvec(const double* x, double* y, bool fp32, hipStream_t s, bool timed = false, bool src_ready = false,
-              const DotReq* dots = nullptr);
+              const DotReq* dots = nullptr, const ExtParts* ext = nullptr);
   // FP64 right-hand side for the current charges and boundary values.
   void rhs(double* b_dev, hipStream_t s);
   // Solves A x = b (b, x device); returns result fields (iters, outer,
@@ -211,13 +219,41 @@ class System {
   int gs_passes() const { return gs_passes_; }
   int far_mode() const { return far_mode_; }
 
+  // Per-kernel timing of every full product (off by default): HIP events on
+  // the stream of each launch, read back in batches.  Totals by slot =
+  // 4 * (0 FP32 | 1 FP64) + kind, kinds 0 the launch holding P2P, 1 the
+  // launch of M2P (when separate), 2 moments (when separate), 3 combine.
+  // set_profile(true) also clears the totals.
+  void set_profile(bool on);
+  // Adds this system's totals: out[2 * slot] ms, out[2 * slot + 1] launches.
+  void add_profile(double out[16]);
+  // Exact dense-equivalent target x Gauss-point pairs of the applications
+  // made so far: a full product counts dense_pairs(), the right-hand side's
+  // product (known densities only) its targets times the known sources;
+  // speculative Arnoldi steps discarded after convergence do not count.
+  int64_t pairs_done() const { return pairs_done_ - nwasted_ * dense_pairs_; }
+
  private:
+  bool prof_ = false;
+  std::vector<hipEvent_t> pev_;
+  int pev_used_ = 0;
+  struct PMark { int slot, e0, e1; };
+  std::vector<PMark> pmarks_;
+  double ptot_[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t pcnt_[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int prof_begin(hipStream_t s);
+  void prof_end(int slot, int e0, hipStream_t s);
+  void prof_flush();
+  int64_t pairs_done_ = 0, known_pairs_ = 0;
+
   void build(hipStream_t s);
   void build_plan();
   void apply(bool fp32, bool add_jump, const double* x, double* y, hipStream_t s, bool from_x = false,
-             bool timed = false, bool src_ready = false, const DotReq* dots = nullptr, bool known_only = false);
+             bool timed = false, bool src_ready = false, const DotReq* dots = nullptr, bool known_only = false,
+             const ExtParts* ext = nullptr);
   template <typename T>
-  void interactions(hipStream_t s, const double* x, bool timed, bool src_ready, bool known_only);
+  void interactions(hipStream_t s, const double* x, bool timed, bool src_ready, bool known_only,
+                    const ExtParts* ext);
   // bytes of the M2P / P2P partial-slot buffers in precision T
   template <typename T>
   size_t part_bytes() const { return (size_t)std::max(plan_.nslots, 1) * 128 * sizeof(T); }
@@ -327,6 +363,10 @@ class System {
   DBuf<int32_t> mblocks_known_;
   DBuf<MomChunk> mchunks_known_, mheads_known_;
   int nleaf_ = 0;
+  // M2M: (offset, count) of each tree level's boxes in m2m_boxes_, deepest
+  // level first; the same for the boxes of charged / potential surfaces
+  std::vector<std::pair<int, int>> m2m_levels_, m2m_levels_known_;
+  DBuf<int32_t> m2m_boxes_, m2m_boxes_known_;
   DBuf<float> mom32_;
   DBuf<double> mom64_;
 

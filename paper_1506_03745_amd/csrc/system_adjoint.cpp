@@ -24,7 +24,8 @@ void System::charge_near(int e, int t_surf, const double* qx, int64_t nq, NearCS
                  qtab_[4].p, qtab_[5].p};
   DBuf<int32_t> cnt;
   cnt.alloc(nq);
-  launch_near_count(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr, cnt.p, s);
+  launch_near_count(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr,
+                    near_f4(prm_.near_factor), cnt.p, s);
   std::vector<int32_t> hc = cnt.download(s);
   std::vector<int64_t> ptr(nq + 1, 0);
   for (int64_t k = 0; k < nq; ++k) ptr[k + 1] = ptr[k] + hc[k];
@@ -32,7 +33,8 @@ void System::charge_near(int e, int t_surf, const double* qx, int64_t nq, NearCS
   qn.ptr.upload(ptr, s);
   qn.col.alloc(std::max<int64_t>(ptr[nq], 1));
   qn.val.alloc(4 * std::max<int64_t>(ptr[nq], 1));
-  launch_near_fill(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr, qn.ptr.p, qn.col.p, s);
+  launch_near_fill(nq, qx, S.nt, cen_.p + 3 * p0, cross2_.p + p0, nullptr, nullptr, nullptr,
+                   near_f4(prm_.near_factor), qn.ptr.p, qn.col.p, s);
   launch_near_values(nq, qx, nullptr, qn.ptr.p, qn.col.p, tri9_.p + 9 * p0, nrm_.p + 3 * p0,
                      area_.p + p0, npr, qn.val.p, s);
   // the charges count as targets of surface t_surf (columns are local to
@@ -257,6 +259,7 @@ void System::apply_t(const double* lam, double* z, double* sigbar, hipStream_t s
   T* trec = f32 ? (T*)trec32_.p : (T*)trec64_.p;
   T* tpart = f32 ? (T*)tpart32_.p : (T*)tpart64_.p;
   ++napply_;
+  pairs_done_ += dense_pairs_;
   PBT_HIP(hipEventRecord(ev_[0], s));
   launch_adj_targets<T>(np_, cen_.p, row_int_.p, row_sol_.p, lam, trec, s);
   PBT_HIP(hipEventRecord(ev_[1], s));

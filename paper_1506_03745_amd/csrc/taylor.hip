@@ -202,6 +202,70 @@ __global__ __launch_bounds__(256) void k_moments_sum(const MomChunk* __restrict_
   }
 }
 
+// ---- M2M -------------------------------------------------------------------
+// A box's moments about its centre c from its children's about theirs, c':
+// with d = c' - c, (y - c)^k = sum_{l <= k} C(k, l) (y - c')^l d^(k - l)
+// (multi-index binomials), and grad_y commutes with the shift, so for both
+// rows   M_k(c) = sum_children sum_{l <= k} C(k, l) d^(k - l) M_l(c').
+// One 64-thread block per box of one tree level (the children's moments
+// are final), threads over the coefficients k; children in list order.
+__constant__ int16_t c_binom_m2m[kMaxP + 1][kMaxP + 1] = {
+    {1}, {1, 1}, {1, 2, 1}, {1, 3, 3, 1}, {1, 4, 6, 4, 1}, {1, 5, 10, 10, 5, 1}, {1, 6, 15, 20, 15, 6, 1},
+    {1, 7, 21, 35, 35, 21, 7, 1}, {1, 8, 28, 56, 70, 56, 28, 8, 1}};
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_m2m(const int32_t* __restrict__ boxes, const int32_t* __restrict__ cbeg,
+                                            const int32_t* __restrict__ cend, const int32_t* __restrict__ clist,
+                                            const double* __restrict__ bcen, T* __restrict__ mom) {
+  constexpr int NC = ncoef(P);
+  constexpr int NR = (NC + 63) / 64;
+  const int b = boxes[blockIdx.x];
+  const int lane = threadIdx.x;
+  const double px = bcen[3 * b], py = bcen[3 * b + 1], pz = bcen[3 * b + 2];
+  T acc0[NR], acc1[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc0[r] = acc1[r] = T(0);
+  for (int ci = cbeg[b]; ci < cend[b]; ++ci) {
+    const int c = clist[ci];
+    const T dx = (T)(bcen[3 * c] - px), dy = (T)(bcen[3 * c + 1] - py), dz = (T)(bcen[3 * c + 2] - pz);
+    const T* Mc = mom + (int64_t)(2 * c) * NC;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int k = lane + 64 * r;
+      if (k >= NC) continue;
+      const int a = midx_a(k), bb = midx_b(k), cc = midx_c(k);
+      T s0 = 0, s1 = 0, sx = 1;
+      for (int ap = a; ap >= 0; --ap) {            // sx = dx^(a - ap)
+        const T cx = (T)c_binom_m2m[a][ap] * sx;
+        T sy = 1;
+        for (int bp = bb; bp >= 0; --bp) {         // sy = dy^(b - bp)
+          const T cy = cx * (T)c_binom_m2m[bb][bp] * sy;
+          T sz = 1;
+          for (int cp = cc; cp >= 0; --cp) {       // sz = dz^(c - cp)
+            const T coef = cy * (T)c_binom_m2m[cc][cp] * sz;
+            const int l = tidx(ap, bp, cp);
+            s0 += coef * Mc[l];
+            s1 += coef * Mc[NC + l];
+            sz *= dz;
+          }
+          sy *= dy;
+        }
+        sx *= dx;
+      }
+      acc0[r] += s0;
+      acc1[r] += s1;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int k = lane + 64 * r;
+    if (k < NC) {
+      mom[(int64_t)(2 * b) * NC + k] = acc0[r];
+      mom[(int64_t)(2 * b + 1) * NC + k] = acc1[r];
+    }
+  }
+}
+
 // ---- M2P -------------------------------------------------------------------
 // The recurrences above, evaluated with the first-neighbour sums taken
 // against pre-scaled R: with u = (2n-1)/(n|R|^2) R and v = kappa/(n|R|^2) R,
@@ -489,6 +553,20 @@ void launch_p2p_moments(int P, int nblocks, const int32_t* mblocks, const MomChu
   }
 }
 
+template <typename T>
+void launch_m2m(int P, int nbox, const int32_t* boxes, const int32_t* cbeg, const int32_t* cend,
+                const int32_t* clist, const double* bcen, T* mom, hipStream_t s) {
+  if (nbox <= 0) return;
+  switch (P) {
+#define PBT_CASE(PP) \
+  case PP: k_m2m<T, PP><<<nbox, 64, 0, s>>>(boxes, cbeg, cend, clist, bcen, mom); break;
+    PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
+#undef PBT_CASE
+    default: throw Error(1, "Taylor order P must be 0..8");
+  }
+  PBT_HIP(hipGetLastError());
+}
+
 template <typename T, int P>
 static void m2p_p(const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
                   const double* bcen, const T* mom, T kappa, T* partial, hipStream_t s) {
@@ -572,6 +650,10 @@ template void launch_m2p_p2p<float>(int, const Task*, int, const int32_t*, const
 template void launch_m2p_p2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
                                      const Task*, int, const int32_t*, const double*, const double*, double, bool,
                                      double*, double*, hipStream_t);
+template void launch_m2m<float>(int, int, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
+                                const double*, float*, hipStream_t);
+template void launch_m2m<double>(int, int, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
+                                 const double*, double*, hipStream_t);
 template void launch_m2p<float>(int, const Task*, int, const int32_t*, const float*, const double*,
                                 const float*, float, float*, hipStream_t);
 template void launch_m2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,

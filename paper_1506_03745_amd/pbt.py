@@ -29,14 +29,15 @@ EXPORTS = ("pbt_default_params", "pbt_create", "pbt_destroy", "pbt_last_error", 
            "pbt_matvec", "pbt_matvec_dev", "pbt_rhs", "pbt_gradient", "pbt_solve_batch",
            "pbt_autotune", "pbt_last_stats", "pbt_set_schedule", "pbt_get_schedule", "pbt_set_gram_schmidt",
            "pbt_get_launch_shape",
-           "pbt_quadrature_rule", "pbt_last_matvec_timing")
+           "pbt_quadrature_rule", "pbt_last_matvec_timing", "pbt_profile", "pbt_kernel_times",
+           "pbt_set_bc_dev", "pbt_set_charges_dev", "pbt_get_solution_dev", "pbt_gradient_dev")
 
 
 class PbtParams(ctypes.Structure):
     _fields_ = [("k_far", ctypes.c_int32), ("k_near", ctypes.c_int32), ("k_self_edge", ctypes.c_int32),
                 ("ncrit", ctypes.c_int32), ("taylor_p", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("treecode", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("treecode", ctypes.c_int32), ("near_factor", ctypes.c_double)]
 
 
 class PbtResult(ctypes.Structure):
@@ -45,7 +46,8 @@ class PbtResult(ctypes.Structure):
                 ("rel_resid", ctypes.c_double), ("t_setup_s", ctypes.c_double),
                 ("t_solve_s", ctypes.c_double), ("p2p_pairs", ctypes.c_int64),
                 ("m2p_pairs", ctypes.c_int64), ("dense_pairs", ctypes.c_int64),
-                ("p2p_fused_pairs", ctypes.c_int64), ("matvecs", ctypes.c_int32)]
+                ("p2p_fused_pairs", ctypes.c_int64), ("matvecs", ctypes.c_int32),
+                ("fp64_fallback", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +111,12 @@ def lib():
         L.pbt_last_stats.argtypes = [P, ctypes.POINTER(PbtResult)]
         L.pbt_quadrature_rule.argtypes = [I32, P, P]
         L.pbt_last_matvec_timing.argtypes = [P, P]
+        L.pbt_profile.argtypes = [P, I32]
+        L.pbt_set_bc_dev.argtypes = [P, I32, P, P]
+        L.pbt_set_charges_dev.argtypes = [P, I32, D, P, P, I64, P]
+        L.pbt_get_solution_dev.argtypes = [P, I32, P, P, P]
+        L.pbt_gradient_dev.argtypes = [P, I32, P, I32, P, P]
+        L.pbt_kernel_times.argtypes = [P, P]
         for name in EXPORTS:
             if name not in ("pbt_default_params", "pbt_destroy", "pbt_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -160,6 +168,7 @@ class Result:
     dense_pairs: int
     p2p_fused_pairs: int
     matvecs: int
+    fp64_fallback: int = 0
     status: int = 0
 
 
@@ -275,6 +284,43 @@ class Solver:
                                          ctypes.c_void_p(y.data_ptr()), 1 if transpose else 0, prec,
                                          ctypes.c_void_p(s.cuda_stream)))
 
+    # -- device variants: float64 torch tensors on the context's device, read
+    #    or written in the order of the tensor device's current stream
+    @staticmethod
+    def _dev(t, n=None):
+        import torch
+        if t is None:
+            return None
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError("expected a contiguous float64 CUDA tensor")
+        if n is not None and t.numel() != n:
+            raise ValueError(f"expected {n} elements, got {t.numel()}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    @staticmethod
+    def _stream(t, stream=None):
+        import torch
+        s = torch.cuda.current_stream(t.device) if stream is None else stream
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def set_bc_dev(self, sid, bc, stream=None):
+        self._check(lib().pbt_set_bc_dev(self._h, sid, self._dev(bc), self._stream(bc, stream)))
+
+    def set_charges_dev(self, mol_id, eps_in, q, xyz=None, stream=None):
+        """q: (nq,) tensor; xyz: (nq, 3) tensor or None to keep the present positions."""
+        self._check(lib().pbt_set_charges_dev(self._h, mol_id, float(eps_in), self._dev(xyz), self._dev(q),
+                                              q.numel(), self._stream(q, stream)))
+
+    def get_solution_dev(self, sid, phi, dphidn, stream=None):
+        t = phi if phi is not None else dphidn
+        self._check(lib().pbt_get_solution_dev(self._h, sid, self._dev(phi), self._dev(dphidn),
+                                               self._stream(t, stream)))
+
+    def gradient_dev(self, sigma_id, dsig, mol_id, dq, stream=None):
+        t = dsig if dsig is not None else dq
+        self._check(lib().pbt_gradient_dev(self._h, sigma_id, self._dev(dsig), mol_id, self._dev(dq),
+                                           self._stream(t, stream)))
+
     def rhs(self):
         b = np.zeros(self.num_unknowns())
         self._check(lib().pbt_rhs(self._h, _ptr(b)))
@@ -320,6 +366,19 @@ class Solver:
         out = (ctypes.c_int64 * 3)()
         self._check(lib().pbt_get_launch_shape(self._h, out))
         return tuple(int(v) for v in out)
+
+    def profile(self, on=True):
+        """Per-kernel HIP-event timing of every operator application (clears the totals)."""
+        self._check(lib().pbt_profile(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        """{(prec, kind): (total ms, launches)}, prec 'fp32' / 'fp64', kind
+        'p2p' / 'm2p' / 'moments' / 'combine' (see pbt_kernel_times)."""
+        out = np.zeros(16)
+        self._check(lib().pbt_kernel_times(self._h, _ptr(out)))
+        kinds = ("p2p", "m2p", "moments", "combine")
+        return {(p, k): (float(out[2 * (4 * i + j)]), int(out[2 * (4 * i + j) + 1]))
+                for i, p in enumerate(("fp32", "fp64")) for j, k in enumerate(kinds)}
 
     def set_gram_schmidt(self, passes):
         self._check(lib().pbt_set_gram_schmidt(self._h, int(passes)))

@@ -3,6 +3,9 @@
     python tests/golden/make_golden.py            # analytic values (seconds)
     python tests/golden/make_golden.py --dense    # + dense oracle solves of the
                                                   #   two-sphere workload (minutes)
+    python tests/golden/make_golden.py --twin     # + dense oracle energies and
+                                                  #   gradient of the 1/16-resolution
+                                                  #   star/plate twin (minutes)
 """
 import json
 import os
@@ -53,9 +56,43 @@ def dense_values():
     return out
 
 
+def twin_values():
+    """Dense LU energies and the dense-transpose gradient of F_int for the
+    1/16-resolution twin of the large star/plate workload (4096 + 5120
+    panels, the same charges and plate densities law): the gradient at 64
+    seeded plate panels and 32 seeded charges, and its largest magnitudes."""
+    import numpy as np
+    from oracle.adjoint import interaction_gradient
+    from oracle.bem import interaction_energy
+    from workloads.problems import config_problem
+    p = config_problem("star_plate_twin")
+    fint, e_all, parts = interaction_energy(p)
+    out = {"source": "oracle.bem dense LU and oracle.adjoint dense transpose, k_far 3, k_near 19, 9 per edge",
+           "units": "kcal/mol; gradients in kcal/mol per C/m^2 (sigma) and per e (q)",
+           "F_int": fint, "F_solv_asm": e_all.F_solv, "F_surf_asm": e_all.F_surf, "F_coul_asm": e_all.F_coul,
+           "F_total_iso": [q.F_total for q in parts]}
+    print("twin energies", out, flush=True)
+    dq, ds = interaction_gradient(p)
+    mol, plate = p.surfaces
+    js = np.sort(np.random.default_rng(7).choice(plate.nt, 64, replace=False))
+    ks = np.sort(np.random.default_rng(8).choice(len(mol.q), 32, replace=False))
+    out["grad_sigma_idx"] = js.tolist()
+    out["grad_sigma"] = ds[js].tolist()
+    out["grad_sigma_maxabs"] = float(np.abs(ds).max())
+    out["grad_q_idx"] = ks.tolist()
+    out["grad_q"] = dq[ks].tolist()
+    out["grad_q_maxabs"] = float(np.abs(dq).max())
+    return out
+
+
 if __name__ == "__main__":
     with open(os.path.join(HERE, "twosphere_analytic.json"), "w") as f:
         json.dump(analytic_values(), f, indent=1)
+    if "--twin" in sys.argv:
+        vals = twin_values()
+        with open(os.path.join(HERE, "twin_oracle.json.tmp"), "w") as f:
+            json.dump(vals, f, indent=1)
+        os.replace(os.path.join(HERE, "twin_oracle.json.tmp"), os.path.join(HERE, "twin_oracle.json"))
     if "--dense" in sys.argv:
         with open(os.path.join(HERE, "dense_oracle_energies.json"), "w") as f:
             json.dump(dense_values(), f, indent=1)

@@ -111,7 +111,10 @@ def test_last_stats_of_a_solve():
     r = s.solve()
     st = s.last_stats()
     assert st.matvecs == r.matvecs
-    assert st.dense_pairs == r.dense_pairs * r.matvecs
+    # the right-hand side's product counts its targets times the charged
+    # sphere's sources; every other product the dense pairs
+    known = sum(su.nt for su in pr.surfaces) * pr.surfaces[1].nt * 3
+    assert st.dense_pairs == r.dense_pairs * (r.matvecs - 1) + known
     assert st.iters == r.iters and st.t_solve_s > 0
 
 
@@ -140,3 +143,39 @@ def test_star_plate_large_gradient_central_differences():
     qm[k] -= 0.5
     fd = (fint(qp, s0) - fint(qm, s0)) / 1.0
     assert abs(fd - gq[k]) <= 1e-3 * np.max(np.abs(gq)), (k, fd, gq[k])
+
+
+def test_star_plate_twin_energies_and_gradient_against_oracle():
+    """The large star/plate workload's 1/16-resolution twin (4096 + 5120
+    panels, same law of charges and plate densities), which the oracle
+    solves densely: energies of the mixed-precision treecode at the
+    benchmark's parameters against the dense LU values within the mixed bar
+    1e-4 (measured: F_solv 4.9e-8, F_surf 4.0e-6, F_int 5.5e-8 of
+    |F_solv| + |F_surf|), and the adjoint gradient of F_int against the
+    oracle's dense-transpose gradient at 64 plate panels and 32 charges
+    (tests/golden/twin_oracle.json) within 5e-4 of the largest entry: the
+    gradient is that of the treecode's discrete F_int, which differs from
+    the dense one by the P = 6 truncation (measured 1.3e-4 and 1.6e-4 of the
+    largest entry, FP64 and mixed alike)."""
+    import json
+    import os
+    tw = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "twin_oracle.json")))
+    pr = config_problem("star_plate_twin")
+    mol, plate = pr.surfaces
+    s, ids = from_problem(pr, prec=MIXED, **PRM)
+    s.prepare()
+    s.autotune()
+    f, res = s.interaction_energy(2)
+    scale = abs(tw["F_solv_asm"]) + abs(tw["F_surf_asm"])
+    assert abs(res[0].F_solv - tw["F_solv_asm"]) <= 1e-4 * abs(tw["F_solv_asm"])
+    assert abs(res[0].F_surf - tw["F_surf_asm"]) <= 1e-4 * abs(tw["F_surf_asm"])
+    assert abs(res[0].F_coul - tw["F_coul_asm"]) <= 1e-12 * abs(tw["F_coul_asm"])
+    assert abs(f - tw["F_int"]) <= 1e-4 * scale
+    gs, gq = s.gradient(ids[1], plate.nt, ids[0], len(mol.q))
+    es = np.max(np.abs(gs[tw["grad_sigma_idx"]] - np.array(tw["grad_sigma"]))) / tw["grad_sigma_maxabs"]
+    eq = np.max(np.abs(gq[tw["grad_q_idx"]] - np.array(tw["grad_q"]))) / tw["grad_q_maxabs"]
+    print("twin gradient error (sigma, q):", es, eq)
+    assert es <= 5e-4 and eq <= 5e-4
+    assert abs(np.abs(gs).max() - tw["grad_sigma_maxabs"]) <= 5e-4 * tw["grad_sigma_maxabs"]
+    assert abs(np.abs(gq).max() - tw["grad_q_maxabs"]) <= 5e-4 * tw["grad_q_maxabs"]
+    s.close()

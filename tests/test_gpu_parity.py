@@ -391,23 +391,35 @@ def test_full_size_twosphere_sampled_rows():
     s, _ = from_problem(pr)   # benchmark parameters: theta 0.5, P 6, N_crit 300
     for prec in (FP64, MIXED):
         y = s.matvec(x, prec=prec)
-        assert np.max(np.abs(y[rows] - ref)) < 2e-3 * np.max(np.abs(ref))
+        # Taylor truncation at P = 6, theta = 0.5: measured 3.8e-5 in both
+        # precisions; the bar is about three times that
+        assert np.max(np.abs(y[rows] - ref)) < 1.2e-4 * np.max(np.abs(ref))
 
 
-def test_full_size_twosphere_energies_against_stored_oracle():
-    path = os.path.join(GOLDEN, "dense_oracle_energies.json")
-    if not os.path.exists(path):
-        pytest.skip("dense oracle energies not generated (tests/golden/make_golden.py --dense)")
-    gold = json.load(open(path))
-    for name in ("twosphere_charge", "twosphere_potential"):
-        g = gold[name]
-        pr = config_problem(name)
-        s, _ = from_problem(pr, treecode=0, tol=1e-10)
-        f, res = s.interaction_energy(2)
-        assert abs(res[0].F_solv - g["F_solv_asm"]) <= 1e-7 * abs(g["F_solv_asm"])
-        assert abs(res[0].F_surf - g["F_surf_asm"]) <= 1e-7 * abs(g["F_surf_asm"])
-        scale = abs(g["F_solv_asm"]) + abs(g["F_surf_asm"])
-        assert abs(f - g["F_int"]) <= 1e-6 * scale
+@pytest.mark.parametrize("name", ["twosphere_charge", "twosphere_potential"])
+@pytest.mark.parametrize("form", ["direct_fp64", "treecode_mixed_P6", "treecode_fp64_P8"])
+def test_full_size_twosphere_energies_against_stored_oracle(name, form):
+    """The two-sphere workload at full size against the oracle's dense LU
+    energies (tests/golden/dense_oracle_energies.json): the plain FP64
+    direct form to 1e-7; the benchmark's mixed-precision treecode (theta 0.5,
+    P 6, N_crit 300, tol 1e-6) to the mixed bar 1e-4 (measured: F_solv 2e-7,
+    F_surf 5.7e-6, F_int 8e-8 of |F_solv| + |F_surf|); the FP64 treecode to
+    the FP64 bar 1e-6 at P = 8, the smallest order that meets it at theta 0.5
+    (P = 6 and 7 leave F_surf at 5.6e-6 and 1.4e-6 from the Taylor
+    truncation; P = 8: 7.6e-7 and 8.1e-7).  F_int, a small difference, is
+    held to the bar times |F_solv| + |F_surf| of the assembly."""
+    gold = json.load(open(os.path.join(GOLDEN, "dense_oracle_energies.json")))
+    g = gold[name]
+    pr = config_problem(name)
+    kw, bar = {"direct_fp64": (dict(treecode=0, tol=1e-10), 1e-7),
+               "treecode_mixed_P6": (dict(prec=MIXED, theta=0.5, taylor_p=6, ncrit=300, tol=1e-6), 1e-4),
+               "treecode_fp64_P8": (dict(prec=FP64, theta=0.5, taylor_p=8, ncrit=300, tol=1e-8), 1e-6)}[form]
+    s, _ = from_problem(pr, **kw)
+    f, res = s.interaction_energy(2)
+    assert abs(res[0].F_solv - g["F_solv_asm"]) <= bar * abs(g["F_solv_asm"])
+    assert abs(res[0].F_surf - g["F_surf_asm"]) <= bar * abs(g["F_surf_asm"])
+    scale = abs(g["F_solv_asm"]) + abs(g["F_surf_asm"])
+    assert abs(f - g["F_int"]) <= (1e-6 if form == "direct_fp64" else bar) * scale
 
 
 def test_error_paths():
@@ -451,3 +463,87 @@ def test_device_entry_point_with_torch_stream():
     s.matvec_dev(xd, yd)
     torch.cuda.synchronize()
     assert rel_inf(yd.cpu().numpy(), A @ x) < 1e-11
+
+
+@pytest.mark.parametrize("near_factor", [1.0, 3.0])
+def test_near_factor_operator_matches_oracle(near_factor):
+    """Another near distance than Section 3.1's 2L: the direct FP64 operator,
+    the right-hand side and the solvation energy against the oracle with the
+    same factor (the near lists change, bit-exact on both sides)."""
+    pr = case("sphere_plate")
+    sysm = DenseBEM(pr, near_factor=near_factor)
+    A, b = sysm.assemble()
+    s, _ = from_problem(pr, treecode=0, near_factor=near_factor, tol=1e-11)
+    x = rand_x(A.shape[0], 21)
+    assert rel_inf(s.matvec(x), A @ x) < 1e-11
+    assert rel_inf(s.rhs(), b) < 1e-12
+    e, _, _ = solve_problem(pr, near_factor=near_factor)
+    r = s.solve()
+    assert abs(r.F_solv - e.F_solv) <= 1e-8 * abs(e.F_solv)
+    # the factor matters: with 2L the operator differs
+    A2, _ = DenseBEM(pr).assemble()
+    assert rel_inf(A2 @ x, A @ x) > 1e-6
+
+
+def test_numeric_failure_leaves_outputs_untouched():
+    """A finite input whose solve overflows (sigma = 1e300 C/m^2: the
+    right-hand side's norm is infinite): the solve reports PBT_E_NUMERIC,
+    writes no result and keeps no solution; the context stays usable."""
+    import ctypes
+
+    from paper_1506_03745_amd.pbt import PbtResult, lib
+    pr = case("sphere_plate")
+    s, ids = from_problem(pr, treecode=0)
+    s.set_bc(ids[1], np.full(pr.surfaces[1].nt, 1e300))
+    r = PbtResult()
+    r.F_solv = 12345.0
+    r.iters = -7
+    st = lib().pbt_solve(s._h, None, ctypes.byref(r))
+    assert st == 5, lib().pbt_last_error(s._h)
+    assert r.F_solv == 12345.0 and r.iters == -7
+    with pytest.raises(PbtError, match="STATE"):
+        s.get_solution(ids[0], pr.surfaces[0].nt)
+    s.set_bc(ids[1], pr.surfaces[1].bc)
+    e, _, _ = solve_problem(pr)
+    assert abs(s.solve().F_solv - e.F_solv) <= 1e-6 * abs(e.F_solv)
+    # a non-finite initial guess is an invalid input, not a numeric failure
+    x0 = np.zeros(s.num_unknowns())
+    x0[3] = np.nan
+    with pytest.raises(PbtError, match="INVALID"):
+        s.solve(x0)
+
+
+def test_mixed_precision_tight_tolerance():
+    """tol 1e-12 with FP32 interactions: the FP64 refinement reaches it (the
+    FP32 operator's ~1e-7 relative error only bounds each inner solve)."""
+    pr = case("sphere_plate")
+    e, _, _ = solve_problem(pr)
+    s, _ = from_problem(pr, treecode=0, prec=MIXED, tol=1e-12)
+    r = s.solve()
+    assert r.rel_resid <= 1e-12 and r.outer >= 2
+    assert abs(r.F_solv - e.F_solv) <= 1e-9 * abs(e.F_solv)
+
+
+def test_refinement_stagnation_falls_back_to_fp64():
+    """A tolerance below the FP64 rounding floor of the residual: the
+    FP32-interaction corrections stop halving it, the solve switches to FP64
+    inner solves (reported), and ends at max_iter with the best residual."""
+    s, _ = from_problem(case("sphere_plate"), treecode=0, prec=MIXED, tol=1e-17, max_iter=300)
+    r = s.solve(allow_noconverge=True)
+    assert r.status == 4 and r.fp64_fallback == 1
+    assert r.rel_resid < 1e-12 and r.iters <= 300
+    s2, _ = from_problem(case("sphere_plate"), treecode=0, prec=MIXED, tol=1e-6)
+    assert s2.solve().fp64_fallback == 0
+
+
+def test_exhausted_krylov_space_with_one_pass():
+    """40 unknowns, tolerance 1e-13, one classical Gram-Schmidt pass: the
+    Krylov space fills up, the new vector's norm cancels, and the solver
+    restarts from the true residual instead of trusting a zero estimate."""
+    pr = config_problem("kirkwood", level=0)
+    e, _, _ = solve_problem(pr)
+    s, _ = from_problem(pr, treecode=0, tol=1e-13, restart=100)
+    s.set_gram_schmidt(1)
+    r = s.solve()
+    assert r.rel_resid <= 1e-13
+    assert abs(r.F_solv - e.F_solv) <= 1e-10 * abs(e.F_solv)

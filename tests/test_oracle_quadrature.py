@@ -160,6 +160,16 @@ def test_near_predicate_is_two_L():
     pts = np.array([c + [0, 0, 2 * L * 0.999], c + [0, 0, 2 * L * 1.001]])
     m = near_mask(pts, p)[:, 0]
     assert m[0] and not m[1]
+    # another factor f: the test is |x - c| < f L, in-plane and off-plane
+    for f in (1.0, 1.5, 3.0, 7.25):
+        for direction in ([0, 0, 1.0], [0.6, 0.8, 0.0]):
+            d = np.asarray(direction)
+            pts = np.array([c + d * f * L * 0.9999, c + d * f * L * 1.0001])
+            m = near_mask(pts, p, near_factor=f)[:, 0]
+            assert m[0] and not m[1], (f, direction)
+    # exactly on the threshold is not near (strict): f = 2 puts c + 4 e_z
+    # at d^4 = 256 = 16 |e1 x e2|^2
+    assert not near_mask(np.array([c + [0, 0, 4.0]]), p)[0, 0]
 
 
 def test_kernels_signs_and_limits():

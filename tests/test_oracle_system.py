@@ -297,3 +297,51 @@ def test_adjoint_gradient_with_stern_layer_and_cavity():
         pm.surfaces[0].q[k] -= h
         fd = (F(pp) - F(pm)) / (2 * h)
         assert abs(fd - g[0][k]) < 1e-8 * abs(g[0][k])
+
+
+def test_coulomb_energy_hand_computed():
+    """F_coul = sum over pairs k < l of q_k q_l / (4 pi eps_in r_kl) (the
+    Coulomb term of eq. total_energy), against a value worked out by hand:
+    charges 1, -2, 1/2 e at (0,0,0), (3,0,0), (0,4,0) A (a 3-4-5 triangle),
+    eps_in = 2: (1 (-2) / 3 + 1 (1/2) / 4 + (-2)(1/2) / 5) / (8 pi)
+    = -89 / (960 pi) reduced units.  Each pair counts once, with 1/eps_in."""
+    from oracle.bem import coulomb_energy
+    pos = np.array([[0.0, 0.0, 0.0], [3.0, 0.0, 0.0], [0.0, 4.0, 0.0]])
+    q = np.array([1.0, -2.0, 0.5])
+    expect = -89.0 / (960.0 * math.pi)
+    assert abs(coulomb_energy(pos, q, 2.0) - expect) <= 1e-15 * abs(expect)
+    # a lone charge has no Coulomb energy; a zero charge adds none
+    assert coulomb_energy(pos[:1], q[:1], 2.0) == 0.0
+    pos4 = np.vstack([pos, [[1.0, 1.0, 1.0]]])
+    assert abs(coulomb_energy(pos4, np.append(q, 0.0), 2.0) - expect) <= 1e-15 * abs(expect)
+    # and the dense system reports it (kcal/mol) for a molecule holding them
+    from oracle.bem import MOLECULE
+    from workloads.meshes import icosphere
+    from workloads.problems import Problem, Surface
+    v, t = icosphere(1, 6.0, (0.0, 0.0, 0.0))
+    pr = Problem([Surface(MOLECULE, v, t, eps_in=2.0, q_pos=pos, q=q)], 80.0, 0.125, {}, "three_charges")
+    e, _, _ = solve_problem(pr)
+    assert abs(e.F_coul - expect * ENERGY_UNIT_KCAL) <= 1e-12 * abs(expect * ENERGY_UNIT_KCAL)
+
+
+@pytest.mark.parametrize("name", ["stern_plate", "nested_plate", "three_body"])
+def test_operator_rows_match_assembly(name):
+    """The row-at-a-time form the full-size parity tests use equals the
+    assembled operator and right-hand side on the same rows (molecule,
+    Stern, cavity and imposed-BC row blocks, every block's first and last
+    row included)."""
+    from tests.gpu_cases import case
+    sysm = DenseBEM(case(name))
+    A, b = sysm.assemble()
+    edges = []
+    for t, st in enumerate(sysm.surfs):
+        w = 2 * st.nt if st.kind in (0, 3, 4) else st.nt
+        r0 = sysm.row_off[t]
+        edges += [r0, r0 + w - 1] + ([r0 + st.nt - 1, r0 + st.nt] if w == 2 * st.nt else [])
+    rng = np.random.default_rng(21)
+    rows = np.unique(np.concatenate([edges, rng.choice(sysm.n, 40, replace=False)]))
+    rng.shuffle(rows)
+    Ar, br = sysm.operator_rows(rows)
+    scale = np.max(np.abs(A))
+    assert np.max(np.abs(Ar - A[rows])) <= 1e-15 * scale
+    assert np.max(np.abs(br - b[rows])) <= 1e-15 * np.max(np.abs(b))

@@ -30,6 +30,9 @@ Named workloads (sizes are panel counts):
 * ``star_plate_large`` star molecule (65536 panels, 3000 charges) 12 A above a
   120 x 120 x 2 A plate (81920 panels), sigma_j = 0.03 (1 + 0.1 u_j).
 * ``star_plate_twin`` the large case at 1/16 resolution (4096 + 5120 panels).
+* ``orient_sweep_small`` the orientation sweep at a size the oracle solves in
+  seconds: a 1280-panel sphere molecule (r = 4 A, +1 e) 10 A above a
+  40 x 40 x 2 A plate of 1536 panels (sigma = -0.05 C/m^2).
 """
 from __future__ import annotations
 
@@ -159,7 +162,7 @@ def star_stern(levels, shape_seed, gap, thickness=2.0, eps_layer=80.0, parent=0)
 
 CONFIG_NAMES = ("kirkwood", "twosphere_charge", "twosphere_potential", "star_plate",
                 "orient_sweep", "star_plate_large", "star_plate_twin", "kirkwood_stern", "stern_plate",
-                "kirkwood_cavity", "kirkwood_water_cavity", "star_plate_stern")
+                "kirkwood_cavity", "kirkwood_water_cavity", "star_plate_stern", "orient_sweep_small")
 
 DEFAULT_PARAMS = dict(k_far=3, k_near=19, k_self_edge=9, ncrit=300, taylor_p=6, theta=0.5, tol=1e-6)
 
@@ -213,15 +216,16 @@ def config_problem(name: str, level: int | None = None, rotation: int | None = N
         mol = star_molecule(12, 1, 900, 2, 10.0)
         pl = plate(40.0, 40.0, 2.0, 64, 128, 4, -0.05)
         return Problem([mol, star_stern(12, 1, 10.0), pl], 80.0, 0.125, p, name)
-    if name == "orient_sweep":
-        lv = 4 if level is None else level
+    if name in ("orient_sweep", "orient_sweep_small"):
+        small = name == "orient_sweep_small"
+        lv = (3 if small else 4) if level is None else level
         v, t = icosphere(lv, 4.0, (0.0, 0.0, 0.0))
         if rotation is not None:
             R = random_rotations(64, 3)[rotation]
             v = v @ R.T
         c = np.array([0.0, 0.0, 14.0])
         mol = Surface(MOLECULE, v + c, t, eps_in=4.0, q_pos=c[None, :].copy(), q=np.array([1.0]))
-        pl = plate(40.0, 40.0, 2.0, 64, 128, 4, -0.05)
+        pl = plate(20.0, 20.0, 2.0, 16, 32, 2, -0.05) if small else plate(40.0, 40.0, 2.0, 64, 128, 4, -0.05)
         return Problem([mol, pl], 80.0, 0.125, p, name)
     if name in ("star_plate_large", "star_plate_twin"):
         big = name == "star_plate_large"
