@@ -299,7 +299,7 @@ pbt_status pbt_last_stats(pbt_ctx* ctx, pbt_result* out);
 /* Sets the schedule of the far field against P2P for the enabled system
  * (Section 3.2 splits every product into near-field P2P and far-field
  * P2M/M2M/M2P): 0 = P2P then the far field on the context's stream,
- * 1 = the far field on a second stream, concurrently with P2P, 2 = moments
+ * 1 = the moments, then M2P on a second stream concurrently with P2P, 2 = moments
  * first, then M2P and P2P tasks in one launch, 3 = moments and P2P tasks in
  * one launch, then M2P, 4 / 5 / 6 = moments with 7/8, 3/4 or 1/2 of the P2P
  * pairs in one launch, then M2P with the other P2P pairs in one launch.

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <limits>
 #include <map>
 
 #include "parallel.h"
@@ -289,6 +290,7 @@ void System::build(hipStream_t s) {
         sb[g] = (int32_t)((poff_[e] + b.pbeg) * K_);
         se[g] = (int32_t)((poff_[e] + b.pend) * K_);
         cb[g] = (int32_t)cl.size();
+        if (b.child_end - b.child_beg > 8) throw Error(PBT_E_STATE, "an octree box with more than 8 children");
         for (int k = b.child_beg; k < b.child_end; ++k) cl.push_back((int32_t)(boff_[e] + T.child_list[k]));
         ce[g] = (int32_t)cl.size();
         if (b.leaf) leaves.push_back(g);
@@ -490,7 +492,74 @@ void System::build(hipStream_t s) {
   }
 }
 
+// Host-side bounds check of the work lists before any kernel reads them:
+// every task's targets, source ranges, boxes and partial slot lie inside
+// their arrays, the two halves of a P2P wavefront agree on their kind, and
+// every partial slot a chunk's combine reads is written by exactly one task
+// (so no product reads a slot that it did not write).  Throws on violation.
+void System::check_plan() const {
+  const Plan& P = plan_;
+  auto bad = [](const std::string& m) { throw Error(PBT_E_STATE, "work list check: " + m); };
+  const int64_t nr = (int64_t)P.ranges.size() / 2, nbl = (int64_t)P.blist.size();
+  for (int64_t r = 0; r < nr; ++r)
+    if (!(0 <= P.ranges[2 * r] && P.ranges[2 * r] <= P.ranges[2 * r + 1] && P.ranges[2 * r + 1] <= ns_))
+      bad("source range out of bounds");
+  for (int32_t b : P.blist)
+    if (b < 0 || b >= nbox_) bad("box index out of bounds");
+  auto check_p2p = [&](const std::vector<Task>& L, bool cover) {
+    if (L.size() % 2) bad("odd number of P2P half tasks");
+    std::vector<int32_t> written(cover ? std::max(P.npslots, 0) : 0, 0);
+    for (size_t w = 0; w < L.size(); ++w) {
+      const Task& t = L[w];
+      const Task& o = L[w ^ 1];
+      if (t.fused != o.fused || t.split != o.split || ((t.form ^ o.form) & kFormKz)) bad("P2P halves of one wave differ");
+      if (!(t.split == 1 || t.split == 2 || t.split == 4)) bad("P2P split");
+      if (t.tcount < 0 || t.tcount > 32 / t.split) bad("P2P target count");
+      if (!(0 <= t.lbeg && t.lbeg <= t.lend && t.lend <= nr)) bad("P2P range list out of bounds");
+      int64_t ns = 0;
+      for (int32_t r = t.lbeg; r < t.lend; ++r) ns += P.ranges[2 * r + 1] - P.ranges[2 * r];
+      if (ns != t.nsrc) bad("P2P source count");
+      if (t.tcount == 0) continue;
+      if (t.tbeg < 0 || (int64_t)t.tbeg + t.tcount > np_) bad("P2P targets out of bounds");
+      if (t.slot < 0 || t.slot >= P.npslots) bad("P2P slot out of bounds");
+      if (cover && ++written[t.slot] != 1) bad("P2P slot written twice");
+    }
+    if (cover)
+      for (int32_t v : written)
+        if (v != 1) bad("P2P slot never written");
+  };
+  check_p2p(P.p2p, true);
+  check_p2p(P.p2p_known, false);
+  auto check_m2p = [&](const std::vector<Task>& L, bool cover) {
+    std::vector<int32_t> written(cover ? std::max(P.nslots, 0) : 0, 0);
+    for (const Task& t : L) {
+      if (t.tcount < 1 || t.tcount > 64) bad("M2P target count");
+      if (t.tbeg < 0 || (int64_t)t.tbeg + t.tcount > np_) bad("M2P targets out of bounds");
+      if (!(0 <= t.lbeg && t.lbeg <= t.lend && t.lend <= nbl)) bad("M2P box list out of bounds");
+      if (t.slot < 0 || t.slot >= P.nslots) bad("M2P slot out of bounds");
+      if (cover && ++written[t.slot] != 1) bad("M2P slot written twice");
+    }
+    if (cover)
+      for (int32_t v : written)
+        if (v != 1) bad("M2P slot never written");
+  };
+  check_m2p(P.m2p, true);
+  check_m2p(P.m2p_known, false);
+  if ((int64_t)P.chunk_of.size() != np_) bad("chunk map size");
+  for (int32_t c : P.chunk_of)
+    if (c < 0 || c >= (int)P.chunks.size()) bad("chunk index out of bounds");
+  for (const ChunkSlots& c : P.chunks) {
+    if (c.tbeg < 0 || c.tcount < 1 || c.tcount > 64 || (int64_t)c.tbeg + c.tcount > np_) bad("chunk targets");
+    if (!(0 <= c.sbeg && c.sbeg <= c.send && c.send <= P.nslots)) bad("chunk M2P slots");
+    if (!(0 <= c.hbeg0 && c.hbeg0 <= c.hend0 && c.hend0 <= P.npslots)) bad("chunk P2P slots (first half)");
+    if (!(0 <= c.hbeg1 && c.hbeg1 <= c.hend1 && c.hend1 <= P.npslots)) bad("chunk P2P slots (second half)");
+    if (c.tcount <= 32 && c.hend1 != c.hbeg1) bad("chunk without a second half has its slots");
+    if (c.lchunk < 0 || c.lchunk >= P.nbh) bad("chunk index within its group");
+  }
+}
+
 void System::upload_plan(hipStream_t s) {
+  check_plan();
   dp2p_.upload(plan_.p2p.empty() ? std::vector<Task>(1) : plan_.p2p, s);
   dm2p_.upload(plan_.m2p.empty() ? std::vector<Task>(1) : plan_.m2p, s);
   dp2p_known_.upload(plan_.p2p_known.empty() ? std::vector<Task>(1) : plan_.p2p_known, s);
@@ -905,11 +974,11 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   // the rest of them in one launch (P2P fills the M2P launch's tail); the
   // share of the P2P pairs in the second launch is 1/8, 1/4 or 1/2
   const bool split = far && far_mode_ >= 4 && far_mode_ <= 6;
-  if (timed || two) PBT_HIP(hipEventRecord(ev_[1], s));
+  if (timed) PBT_HIP(hipEventRecord(ev_[1], s));
   const bool guard = K_ == 1 || K_ == 4 || K_ == 7;
   T* msum = f32 ? (T*)msum32_.p : (T*)msum64_.p;
   // per-kernel profile marks (full products only)
-  const bool pf = prof_ && !known_only;
+  const bool pf = prof_ && !known_only && !ext;   // (caller-owned buffers: no bookkeeping)
   const int pbase = f32 ? 0 : 4;
   auto pb = [&](hipStream_t st) { return pf ? prof_begin(st) : -1; };
   auto pe = [&](int kind, int e0, hipStream_t st) {
@@ -1012,15 +1081,24 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     far_timed_ = timed;
     return;
   }
+  if (two) {
+    // the moments first (short launches, one tree level each, with the
+    // whole machine), then M2P on the second stream concurrently with P2P
+    if (timed) PBT_HIP(hipEventRecord(evm_[0], s));
+    moments(s);
+    PBT_HIP(hipEventRecord(evm_[1], s));
+    PBT_HIP(hipStreamWaitEvent(s2_, evm_[1], 0));
+    const int e1 = pb(s2_);
+    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, s2_);
+    pe(1, e1, s2_);
+    PBT_HIP(hipEventRecord(evm_[2], s2_));
+  }
   if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
   const int e0 = pb(s);
   launch_p2p<T>(p2p_tasks, npairs, dranges_.p, tgt, src, (T)kappa_, guard, ppart, s);
   pe(0, e0, s);
   if (timed) PBT_HIP(hipEventRecord(ev_[3], s));
   if (two) {
-    // P2P (already queued) and the far field on the second stream overlap
-    PBT_HIP(hipStreamWaitEvent(s2_, ev_[1], 0));
-    far_field(s2_);
     PBT_HIP(hipStreamWaitEvent(s, evm_[2], 0));
   } else if (far) {
     far_field(s);
@@ -1059,7 +1137,7 @@ void System::apply(bool fp32, bool add_jump, const double* x, double* y, hipStre
     a.nbh = plan_.nbh;
     a.self_dot = dots->self_dot;
   }
-  const int e0 = prof_ && !known_only ? prof_begin(s) : -1;
+  const int e0 = prof_ && !known_only && !ext ? prof_begin(s) : -1;
   if (fp32)
     launch_combine<float>(a, ext ? (const float*)ext->part : part32_.p, ext ? (const float*)ext->ppart : ppart32_.p,
                           y, s);
@@ -1550,16 +1628,20 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
   res->fp64_fallback = 0;
   const double tol = prm_.tol;
   group_rel_.assign(G, 0.0);
+  // the largest relative residual; a non-finite one (an overflowed norm or
+  // product) wins, so that it is reported instead of read as converged
   auto relmax = [&](const std::vector<double>& rn) {
     double r = 0;
+    bool finite = true;
     for (int g = 0; g < G; ++g) {
-      group_rel_[g] = bn[g] > 0 ? rn[g] / bn[g] : 0.0;
-      r = std::max(r, group_rel_[g]);
+      group_rel_[g] = bn[g] > 0 || !std::isfinite(bn[g]) ? rn[g] / bn[g] : 0.0;
+      if (!std::isfinite(group_rel_[g])) finite = false;
+      else r = std::max(r, group_rel_[g]);
     }
-    return r;
+    return finite ? r : std::numeric_limits<double>::quiet_NaN();
   };
   bool any_b = false;
-  for (double v : bn) any_b = any_b || v > 0;
+  for (double v : bn) any_b = any_b || v > 0 || !std::isfinite(v);
   if (!any_b) {
     PBT_HIP(hipMemsetAsync(x, 0, n_ * sizeof(double), s));
     res->rel_resid = 0.0;

@@ -206,7 +206,7 @@ class System {
   int64_t applications() const { return napply_ - nwasted_; }
   // How the far field (moments, M2P) and P2P are scheduled:
   //   0: P2P, then the far field, on the caller's stream;
-  //   1: the far field on a second stream, concurrently with P2P;
+  //   1: the moments, then M2P on a second stream concurrently with P2P;
   //   2: moments first, then M2P and P2P tasks in one launch;
   //   3: moments inside the P2P launch, then M2P;
   //   4, 5, 6: moments inside a launch with 7/8, 3/4 or 1/2 of the P2P
@@ -404,6 +404,7 @@ class System {
   bool far_timed_ = false;
   int64_t seg_src_ = 0, seg_box_ = 0, seg_src_used_ = 0, seg_box_used_ = 0;
   void upload_plan(hipStream_t s);
+  void check_plan() const;
 
   // forward interaction lists per (target group, k-th source surface of the
   // group's surfaces in group_surfs_), for the transpose; a target group is

@@ -207,62 +207,83 @@ __global__ __launch_bounds__(256) void k_moments_sum(const MomChunk* __restrict_
 // with d = c' - c, (y - c)^k = sum_{l <= k} C(k, l) (y - c')^l d^(k - l)
 // (multi-index binomials), and grad_y commutes with the shift, so for both
 // rows   M_k(c) = sum_children sum_{l <= k} C(k, l) d^(k - l) M_l(c').
-// One 64-thread block per box of one tree level (the children's moments
-// are final), threads over the coefficients k; children in list order.
-__constant__ int16_t c_binom_m2m[kMaxP + 1][kMaxP + 1] = {
-    {1}, {1, 1}, {1, 2, 1}, {1, 3, 3, 1}, {1, 4, 6, 4, 1}, {1, 5, 10, 10, 5, 1}, {1, 6, 15, 20, 15, 6, 1},
-    {1, 7, 21, 35, 35, 21, 7, 1}, {1, 8, 28, 56, 70, 56, 28, 8, 1}};
+// The multi-index sum factorises into three one-dimensional ones, taken as
+// three passes (x, then y, then z) over every child's moments, each output a
+// sum of at most P + 1 terms: (a, b, c) <- sum_{a' <= a} C(a, a') dx^(a - a')
+// (a', b, c), and so on (a' <= a keeps |(a', b, c)| <= P).  One block per
+// box of one tree level (the children's moments are final); the children's
+// moments, the powers of their shifts and the binomials in LDS; the
+// children's shifted moments are added in list order.
+constexpr int kM2MThreads = 128;
+constexpr int kMaxChildren = 8;
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_m2m(const int32_t* __restrict__ boxes, const int32_t* __restrict__ cbeg,
-                                            const int32_t* __restrict__ cend, const int32_t* __restrict__ clist,
-                                            const double* __restrict__ bcen, T* __restrict__ mom) {
+__global__ __launch_bounds__(kM2MThreads) void k_m2m(const int32_t* __restrict__ boxes,
+                                                     const int32_t* __restrict__ cbeg,
+                                                     const int32_t* __restrict__ cend,
+                                                     const int32_t* __restrict__ clist,
+                                                     const double* __restrict__ bcen, T* __restrict__ mom) {
   constexpr int NC = ncoef(P);
-  constexpr int NR = (NC + 63) / 64;
+  constexpr int NO = 2 * NC;   // outputs per child: (row, k)
+  __shared__ T sa[kMaxChildren][NO];
+  __shared__ T sb[kMaxChildren][NO];
+  __shared__ T sp[kMaxChildren][3][P + 1];
+  __shared__ T sbin[P + 1][P + 1];
+  __shared__ int8_t sk[NC][3];
   const int b = boxes[blockIdx.x];
-  const int lane = threadIdx.x;
-  const double px = bcen[3 * b], py = bcen[3 * b + 1], pz = bcen[3 * b + 2];
-  T acc0[NR], acc1[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) acc0[r] = acc1[r] = T(0);
-  for (int ci = cbeg[b]; ci < cend[b]; ++ci) {
-    const int c = clist[ci];
-    const T dx = (T)(bcen[3 * c] - px), dy = (T)(bcen[3 * c + 1] - py), dz = (T)(bcen[3 * c + 2] - pz);
-    const T* Mc = mom + (int64_t)(2 * c) * NC;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int k = lane + 64 * r;
-      if (k >= NC) continue;
-      const int a = midx_a(k), bb = midx_b(k), cc = midx_c(k);
-      T s0 = 0, s1 = 0, sx = 1;
-      for (int ap = a; ap >= 0; --ap) {            // sx = dx^(a - ap)
-        const T cx = (T)c_binom_m2m[a][ap] * sx;
-        T sy = 1;
-        for (int bp = bb; bp >= 0; --bp) {         // sy = dy^(b - bp)
-          const T cy = cx * (T)c_binom_m2m[bb][bp] * sy;
-          T sz = 1;
-          for (int cp = cc; cp >= 0; --cp) {       // sz = dz^(c - cp)
-            const T coef = cy * (T)c_binom_m2m[cc][cp] * sz;
-            const int l = tidx(ap, bp, cp);
-            s0 += coef * Mc[l];
-            s1 += coef * Mc[NC + l];
-            sz *= dz;
-          }
-          sy *= dy;
-        }
-        sx *= dx;
-      }
-      acc0[r] += s0;
-      acc1[r] += s1;
+  const int c0 = cbeg[b];
+  const int nch = min(cend[b] - c0, kMaxChildren);
+  for (int i = threadIdx.x; i < nch * NO; i += kM2MThreads) {
+    const int ci = i / NO, r = i - ci * NO;
+    sa[ci][r] = mom[(int64_t)(2 * clist[c0 + ci]) * NC + r];
+  }
+  for (int i = threadIdx.x; i < nch * 3; i += kM2MThreads) {
+    const int ci = i / 3, d = i - ci * 3;
+    const T dd = (T)(bcen[3 * clist[c0 + ci] + d] - bcen[3 * b + d]);
+    T pw = T(1);
+    for (int e = 0; e <= P; ++e) {
+      sp[ci][d][e] = pw;
+      pw *= dd;
     }
   }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int k = lane + 64 * r;
-    if (k < NC) {
-      mom[(int64_t)(2 * b) * NC + k] = acc0[r];
-      mom[(int64_t)(2 * b + 1) * NC + k] = acc1[r];
+  for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += kM2MThreads) {
+    const int n = i / (P + 1), k = i - n * (P + 1);
+    double v = 0.0;
+    if (k <= n) {
+      v = 1.0;
+      for (int q = 1; q <= k; ++q) v = v * (n - k + q) / q;
     }
+    sbin[n][k] = (T)v;
+  }
+  for (int k = threadIdx.x; k < NC; k += kM2MThreads) {
+    sk[k][0] = (int8_t)midx_a(k);
+    sk[k][1] = (int8_t)midx_b(k);
+    sk[k][2] = (int8_t)midx_c(k);
+  }
+  __syncthreads();
+  // pass along dimension D: dst(k) = sum_{e <= k_D} C(k_D, e) d_D^(k_D - e) src(k with k_D = e)
+  auto pass = [&](const T (*src)[NO], T (*dst)[NO], int D) {
+    for (int i = threadIdx.x; i < nch * NO; i += kM2MThreads) {
+      const int ci = i / NO, o = i - ci * NO;
+      const int row = o >= NC ? NC : 0, k = o - row;
+      int q[3] = {sk[k][0], sk[k][1], sk[k][2]};
+      const int top = q[D];
+      T acc = T(0);
+      for (int e = 0; e <= top; ++e) {
+        q[D] = e;
+        acc += sbin[top][e] * sp[ci][D][top - e] * src[ci][row + tidx(q[0], q[1], q[2])];
+      }
+      dst[ci][o] = acc;
+    }
+    __syncthreads();
+  };
+  pass(sa, sb, 0);
+  pass(sb, sa, 1);
+  pass(sa, sb, 2);
+  for (int o = threadIdx.x; o < NO; o += kM2MThreads) {
+    T acc = T(0);
+    for (int ci = 0; ci < nch; ++ci) acc += sb[ci][o];
+    mom[(int64_t)(2 * b) * NC + o] = acc;
   }
 }
 
@@ -559,7 +580,7 @@ void launch_m2m(int P, int nbox, const int32_t* boxes, const int32_t* cbeg, cons
   if (nbox <= 0) return;
   switch (P) {
 #define PBT_CASE(PP) \
-  case PP: k_m2m<T, PP><<<nbox, 64, 0, s>>>(boxes, cbeg, cend, clist, bcen, mom); break;
+  case PP: k_m2m<T, PP><<<nbox, kM2MThreads, 0, s>>>(boxes, cbeg, cend, clist, bcen, mom); break;
     PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
 #undef PBT_CASE
     default: throw Error(1, "Taylor order P must be 0..8");
