@@ -232,6 +232,23 @@ pbt_status pbt_get_solution_dev(pbt_ctx* ctx, int32_t id, double* phi_dev, doubl
  * Restores the enable flags afterwards. */
 pbt_status pbt_interaction_energy(pbt_ctx* ctx, double* F_int, pbt_result* parts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * product y = A x of pbt_matvec_dev (forward operator) without any
+ * allocation.  Its work vectors (2 n doubles) and the P2P / M2P partial
+ * sums live in a static device array of 128 MiB that the library holds on
+ * each device it runs on until the process ends; PBT_E_INVALID if the
+ * enabled system needs more (the error states how much).  The system must
+ * be prepared already (pbt_prepare or an earlier solve or product:
+ * PBT_E_STATE otherwise, since preparing allocates).  x_dev, y_dev: n
+ * doubles of device memory in the unknown layout; queued on `stream` (NULL
+ * for the context's stream) without synchronising.  Every call on one
+ * device shares that device's array: calls that overlap on one device
+ * (other streams, other contexts, other threads) race.  pbt_profile does
+ * not record its launches. */
+pbt_status pbt_matvec_dev_static(pbt_ctx* ctx, const double* x_dev, double* y_dev, pbt_precision prec,
+                                 void* stream);
+
 /* y = A x for the enabled system (eq. matrix_phi / matrix_dphi generalised
  * to any number of surfaces), host buffers of n doubles.  transpose = 1
  * applies the exact transpose of the same discrete operator (same tree,

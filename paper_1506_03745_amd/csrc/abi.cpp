@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,7 +18,40 @@
 
 using namespace pbt;
 
+// Scratch of pbt_matvec_dev_static, the product that allocates nothing: the
+// unknowns in the internal order, the product before it is permuted back,
+// and the P2P / M2P partial sums live in this array instead of buffers of
+// the context.  Each device the library runs on holds its own copy until the
+// process ends; every call on a device shares that copy, so calls that
+// overlap on one device race.  Host code never uses the array's name as an
+// address: pbt_create stores each device's address (hipGetSymbolAddress).
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {nullptr};
+
+// Address of `device`'s copy of the scratch array, looked up once per device
+// with that device current.
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[device] = p;
+  return hipSuccess;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
 
 // Winding number of a closed triangle mesh (outward orientation) about point
 // p: the solid angles of its triangles summed over 4 pi, each from the
@@ -312,6 +346,7 @@ pbt_status pbt_create(pbt_ctx** out, int32_t hip_device, const pbt_params* param
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return PBT_E_DEVICE;
   if (hipSetDevice(hip_device) != hipSuccess) return PBT_E_DEVICE;
+  if (scratch_init(hip_device) != hipSuccess) return PBT_E_DEVICE;
   auto c = new (std::nothrow) pbt_ctx();
   if (!c) return PBT_E_NOMEM;
   c->device = hip_device;
@@ -622,6 +657,43 @@ pbt_status pbt_matvec_dev(pbt_ctx* c, const double* x_dev, double* y_dev, int32_
     if (transpose) S.matvec_t(c->dx.p, c->dy.p, prec == PBT_MIXED, nullptr, st);
     else S.matvec(c->dx.p, c->dy.p, prec == PBT_MIXED, st, true);
     S.to_boundary(c->dy.p, y_dev, st);
+    return PBT_OK;
+  });
+}
+
+pbt_status pbt_matvec_dev_static(pbt_ctx* c, const double* x_dev, double* y_dev, pbt_precision prec,
+                                 void* stream) {
+  return guarded(c, [&] {
+    if (!x_dev || !y_dev) return fail(c, PBT_E_INVALID, "null buffer");
+    if (prec != PBT_FP64 && prec != PBT_MIXED) return fail(c, PBT_E_INVALID, "prec must be PBT_FP64 or PBT_MIXED");
+    // the prepared system of the enabled surfaces (found without building a key)
+    System* S = nullptr;
+    for (auto& kv : c->systems) {
+      bool same = kv.first.size() == c->surfs.size();
+      for (size_t i = 0; same && i < kv.first.size(); ++i) same = kv.first[i] == c->surfs[i]->enabled;
+      if (same) {
+        S = kv.second.get();
+        break;
+      }
+    }
+    if (!S) return fail(c, PBT_E_STATE, "no prepared system for the enabled surfaces (pbt_prepare allocates; call it first)");
+    unsigned char* base = static_cast<unsigned char*>(scratch_of(c->device));
+    if (!base) return fail(c, PBT_E_DEVICE, "no scratch address for this device");
+    const bool fp32 = prec == PBT_MIXED;
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t nb = up((size_t)S->n() * sizeof(double));
+    const size_t pb = up(S->part_need(fp32)), ppb = up(S->ppart_need(fp32));
+    if (2 * nb + pb + ppb > kStaticScratchBytes)
+      return fail(c, PBT_E_INVALID, "the system needs " + std::to_string(2 * nb + pb + ppb) +
+                                        " bytes of scratch; the static array holds " +
+                                        std::to_string(kStaticScratchBytes));
+    double* xi = reinterpret_cast<double*>(base);
+    double* yi = reinterpret_cast<double*>(base + nb);
+    const System::ExtParts ext{base + 2 * nb, base + 2 * nb + pb};
+    const hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    S->to_internal(x_dev, xi, st);
+    S->matvec(xi, yi, fp32, st, false, false, nullptr, &ext);
+    S->to_boundary(yi, y_dev, st);
     return PBT_OK;
   });
 }

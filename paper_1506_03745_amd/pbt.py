@@ -30,7 +30,8 @@ EXPORTS = ("pbt_default_params", "pbt_create", "pbt_destroy", "pbt_last_error", 
            "pbt_autotune", "pbt_last_stats", "pbt_set_schedule", "pbt_get_schedule", "pbt_set_gram_schmidt",
            "pbt_get_launch_shape",
            "pbt_quadrature_rule", "pbt_last_matvec_timing", "pbt_profile", "pbt_kernel_times",
-           "pbt_set_bc_dev", "pbt_set_charges_dev", "pbt_get_solution_dev", "pbt_gradient_dev")
+           "pbt_set_bc_dev", "pbt_set_charges_dev", "pbt_get_solution_dev", "pbt_gradient_dev",
+           "pbt_matvec_dev_static")
 
 
 class PbtParams(ctypes.Structure):
@@ -116,6 +117,7 @@ def lib():
         L.pbt_set_charges_dev.argtypes = [P, I32, D, P, P, I64, P]
         L.pbt_get_solution_dev.argtypes = [P, I32, P, P, P]
         L.pbt_gradient_dev.argtypes = [P, I32, P, I32, P, P]
+        L.pbt_matvec_dev_static.argtypes = [P, P, P, I32, P]
         L.pbt_kernel_times.argtypes = [P, P]
         for name in EXPORTS:
             if name not in ("pbt_default_params", "pbt_destroy", "pbt_last_error"):
@@ -320,6 +322,13 @@ class Solver:
         t = dsig if dsig is not None else dq
         self._check(lib().pbt_gradient_dev(self._h, sigma_id, self._dev(dsig), mol_id, self._dev(dq),
                                            self._stream(t, stream)))
+
+    def matvec_dev_static(self, x, y, prec=FP64, stream=None):
+        """The forward product without allocations (pbt_matvec_dev_static);
+        x, y: contiguous float64 torch tensors on the context's device."""
+        n = self.num_unknowns()
+        self._check(lib().pbt_matvec_dev_static(self._h, self._dev(x, n), self._dev(y, n), prec,
+                                                self._stream(x, stream)))
 
     def rhs(self):
         b = np.zeros(self.num_unknowns())
