@@ -25,8 +25,13 @@ FMA = 2, any other operation = 1, transcendental = 1: a pair whose target
 and source lie on one molecule (single and double layer of both the Laplace
 and the Yukawa kernel) is 34 flops (difference 3, r^2 5, 1/r^3 2, r 1,
 n.(x-y) 5, -kappa r log2(e) 2, dG_L 1, G_Y 1, dG_Y 4, four accumulating FMAs
-8, rsqrt 1, exp 1), a Yukawa-only pair 30.  Peaks: FP32 157.3 TFLOP/s (the
-published MI355X vector figure, which counts packed FP32), FP64 78.6.
+8, rsqrt 1, exp 1), a Yukawa-only pair 30.  An M2P (target, box) pair is
+counted from the Taylor recurrences as written (m2p_pair_flops below): 1,344
+flops at P = 6 for a Yukawa-only pair and 1,975 when the Laplace expansion of
+a molecule's interior row is formed too.  The line's roofline is that of
+the kernel that takes the most time in the timed solve (P2P or M2P); both
+are reported.  Peaks: FP32 157.3 TFLOP/s (the published MI355X vector
+figure, which counts packed FP32), FP64 78.6.
 
 Other modes: --workload twosphere_charge | star_plate | star_plate_stern |
 ... (a solve of that workload), orient_sweep (pbt_solve_batch of 64 rigid
@@ -80,6 +85,12 @@ SCHEDULES = {0: "serial", 1: "two streams", 2: "joint M2P + P2P launch", 3: "mom
              4: "moments with 7/8 of P2P, then M2P with 1/8 of P2P",
              5: "moments with 3/4 of P2P, then M2P with 1/4 of P2P",
              6: "moments with 1/2 of P2P, then M2P with 1/2 of P2P"}
+
+
+def m2p_kernel_name(schedule, prec="float", P=6):
+    if schedule == 2:
+        return f"k_m2p_p2p<{prec}, {P}, false, false>"
+    return f"k_m2p<{prec}, {P}, false>"
 
 
 def p2p_kernel_name(schedule, prec="float", P=6):
@@ -172,26 +183,58 @@ def common_fields(a, ms_step, dtype="f32 interactions + f64 Krylov/refinement"):
 
 
 def profiled_traffic(workload, kernel, grid):
-    """HBM bytes per launch of the P2P-holding kernel from the committed
-    rocprofv3 counter summary of this workload, or None when there is none,
-    the kernel sources changed since the counters were taken, or this run's
-    launch has another shape (grid work-items) than the profiled one."""
-    path = os.path.join(PROFILES, f"k_p2p_{workload}.json")
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (profiles/counters_<workload>.json), or None
+    when there is none, the interaction kernels' sources changed since the
+    counters were taken, or this run's launch has another shape (grid
+    work-items) than the profiled one."""
+    path = os.path.join(PROFILES, f"counters_{workload}.json")
     try:
         prof = json.load(open(path))
         sha = [hashlib.sha256(open(f, "rb").read()).hexdigest() for f in P2P_SOURCES]
     except (OSError, ValueError):
         return None
-    if prof.get("sources_sha256") != sha:
+    if prof.get("sources_sha256") != sha or grid is None:
         return None
-    for shape in [prof] + prof.get("other_shapes", []):
-        if shape.get("kernel") == kernel and shape.get("grid_size") == grid:
-            return shape.get("traffic_bytes_per_launch")
+    for k in prof.get("kernels", []):
+        if k.get("kernel") == kernel and k.get("grid_size") == grid:
+            return k.get("traffic_bytes_per_launch")
     return None
 
 
 def p2p_flops(r):
     return FLOPS_FUSED_PAIR * r.p2p_fused_pairs + FLOPS_YUKAWA_PAIR * (r.p2p_pairs - r.p2p_fused_pairs)
+
+
+def m2p_pair_flops(P, laplace_too):
+    """Flops of one M2P (target, box) pair, the Taylor coefficients of
+    e^(-kappa rho)/rho (coefficients a and the auxiliary b of e^(-kappa rho))
+    up to degree P by their recurrences and their dot with the box's moments;
+    with laplace_too also those of 1/rho and a second dot.  Per coefficient
+    k of degree n with f nonzero and s >= 2 entries: the first-neighbour sums
+    2f - 1 each, the second-neighbour sums s - 1 each, the combination, the
+    dot (FMA 2); per degree the scaled vectors; once the difference, r^2,
+    rsqrt and exp."""
+    f = 3 + 5 + 1 + 1 + 1 + 2 + 1 + 1 + 1      # R, R^2, rsqrt, 1/R^2, kappa R^2, -kappa r, exp, a_0, dot
+    lap = 1                                    # dot of a_0
+    for n in range(1, P + 1):
+        f += 10                                # c1, c2, c3, e4, u (3), v (3)
+        lap += 5                               # c1, c2, u (3)
+        for a in range(n, -1, -1):
+            for b in range(n - a, -1, -1):
+                k = (a, b, n - a - b)
+                nf = sum(1 for q in k if q >= 1)
+                ns = sum(1 for q in k if q >= 2)
+                f += 2 * (2 * nf - 1) + (2 * (ns - 1) + 4 if ns else 0) + 1 + 2
+                if n < P:
+                    f += 1 + (2 if ns else 0)
+                lap += (2 * nf - 1) + ((ns - 1) + 2 if ns else 0) + 2
+    return f + (lap if laplace_too else 0)
+
+
+def m2p_flops(r, P=6):
+    return (m2p_pair_flops(P, True) * r.m2p_fused_pairs
+            + m2p_pair_flops(P, False) * (r.m2p_pairs - r.m2p_fused_pairs))
 
 
 def timed_solves(s, a, sync):
@@ -291,38 +334,51 @@ def bench_solve(a, cpu):
         return out
 
     k32 = per_kernel(kt, "fp32")
-    flops = p2p_flops(r)
-    p2p_ms, p2p_n = kt[("fp32", "p2p")]
-    avg_p2p = p2p_ms / max(p2p_n, 1)
-    kernel = p2p_kernel_name(schedule)
-    achieved = flops / (avg_p2p / 1e3) / 1e12
-    m2p_ms, m2p_n = kt[("fp32", "m2p")]
+
+    def roofline(kind, prec, flops, peak, sched, shape_grid=None):
+        ms, n = kt_sel[prec][(prec, kind)]
+        avg = ms / max(n, 1)
+        ach = flops / (avg / 1e3) / 1e12
+        name = (p2p_kernel_name if kind == "p2p" else m2p_kernel_name)(sched, "float" if prec == "fp32" else "double")
+        return {"bound": "alu", "kernel": name, "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": profiled_traffic(a.workload, name, shape_grid)
+                if prec == "fp32" else None,
+                "flops_per_launch": int(flops), "avg_launch_ms": round(avg, 5), "launches": n}
+
+    kt_sel = {"fp32": kt}
+    fl_p2p, fl_m2p = p2p_flops(r), m2p_flops(r)
+    rf_p2p = roofline("p2p", "fp32", fl_p2p, FP32_PEAK_TFLOPS, schedule, shape[2])
+    rf_m2p = roofline("m2p", "fp32", fl_m2p, FP32_PEAK_TFLOPS, schedule, shape[3])
+    for rf, fl in ((rf_p2p, "34 per Laplace+Yukawa pair, 30 per Yukawa-only pair"),
+                   (rf_m2p, f"{m2p_pair_flops(6, True)} per (target, box) with the Laplace expansion too, "
+                            f"{m2p_pair_flops(6, False)} Yukawa only")):
+        rf["frac_of_nonpacked_fp32"] = round(rf["achieved"] / FP32_NONPACKED_TFLOPS, 4)
+        rf["flop_convention"] = "FMA 2, other op 1, transcendental 1; " + fl
     dom = max(("p2p", "m2p", "moments", "combine"), key=lambda k: kt[("fp32", k)][0])
+    main_rf = dict(rf_m2p if dom == "m2p" else rf_p2p)
+    main_rf["dominant_in_solve"] = dom
+    p2p_ms, p2p_n = kt[("fp32", "p2p")]
+    m2p_ms, m2p_n = kt[("fp32", "m2p")]
+    avg_p2p = p2p_ms / max(p2p_n, 1)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Ginteractions/s",
         **common_fields(a, ms_step),
         "config": {"workload": f"{a.workload}: {WORKLOADS.get(a.workload, a.workload)}",
                    "panels": sum(s.nt for s in problem.surfaces), "unknowns": s32.num_unknowns(),
                    **PRM, "precision": "mixed"},
-        "roofline": {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": profiled_traffic(a.workload, kernel, shape[2]),
-                     "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_TFLOPS, 4),
-                     "flops_per_launch": int(flops), "avg_launch_ms": round(avg_p2p, 5),
-                     "launches": p2p_n, "grid_work_items": shape[2],
-                     "flop_convention": "FMA 2, other op 1, transcendental 1; 34 per Laplace+Yukawa pair, "
-                                        "30 per Yukawa-only pair",
-                     "dominant_in_solve": dom == "p2p"},
+        "roofline": main_rf,
+        "roofline_p2p": rf_p2p, "roofline_m2p": rf_m2p,
         "gmres": {"iters": r.iters, "outer": r.outer, "rel_resid": r.rel_resid,
                   "applications_per_step": sum(x.matvecs for x in rs) / len(rs),
                   "setup_s": round(setup_wall, 3), "autotune_s": round(autotune_s, 3)},
         "far_field_schedule": SCHEDULES[schedule],
-        "launch_shape": {"p2p_segment": shape[0], "m2p_boxes_per_task": shape[1]},
+        "launch_shape": {"p2p_segment": shape[0], "m2p_boxes_per_task": shape[1], "p2p_grid_work_items": shape[2],
+                         "m2p_grid_work_items": shape[3]},
         "kernels_fp32": k32,
         "p2p_gpairs_s": round(r.p2p_pairs / (avg_p2p / 1e3) / 1e9, 2),
         "m2p_g_target_box_s": round(r.m2p_pairs / (m2p_ms / max(m2p_n, 1) / 1e3) / 1e9, 3) if m2p_n else None,
         "pairs_per_product": {"dense": r.dense_pairs, "p2p": r.p2p_pairs, "p2p_fused": r.p2p_fused_pairs,
-                              "m2p": r.m2p_pairs},
+                              "m2p": r.m2p_pairs, "m2p_fused": r.m2p_fused_pairs},
         "energies_kcal": {"F_solv": r.F_solv, "F_surf": r.F_surf, "F_coul": r.F_coul},
     }
     if not a.profile_only:
@@ -343,7 +399,10 @@ def bench_solve(a, cpu):
             return {k: round(v, 4) for k, v in store.items()}
 
         m32, m64 = op_timing(MIXED), op_timing(FP64)
-        out["matvec_ms"] = {"fp32": m32, "fp64": m64}
+        s32.set_schedule(0)              # serial: each kernel with the machine to itself
+        m32s = op_timing(MIXED)
+        s32.set_schedule(schedule)
+        out["matvec_ms"] = {"fp32": m32, "fp64": m64, "fp32_serial_schedule": m32s}
         out["matvec_gint_s"] = {"fp32": round(r.dense_pairs / m32["total_ms"] / 1e6, 2),
                                 "fp64": round(r.dense_pairs / m64["total_ms"] / 1e6, 2)}
         del x, y
@@ -364,14 +423,14 @@ def bench_solve(a, cpu):
         kt64 = s64.kernel_times()
         sched64 = s64.schedule()
         s64.close()
-        ms64, n64p = kt64[("fp64", "p2p")]
-        avg64 = ms64 / max(n64p, 1)
-        ach64 = flops / (avg64 / 1e3) / 1e12
+        kt_sel["fp64"] = kt64
+        r64_p2p = roofline("p2p", "fp64", fl_p2p, FP64_PEAK_TFLOPS, sched64)
+        r64_m2p = roofline("m2p", "fp64", fl_m2p, FP64_PEAK_TFLOPS, sched64)
+        dom64 = "m2p" if kt64[("fp64", "m2p")][0] > kt64[("fp64", "p2p")][0] else "p2p"
+        out["roofline_fp64"] = dict(r64_m2p if dom64 == "m2p" else r64_p2p, dominant_in_solve=dom64,
+                                    far_field_schedule=SCHEDULES[sched64])
+        out["roofline_fp64_p2p"], out["roofline_fp64_m2p"] = r64_p2p, r64_m2p
         mm64, nm64 = kt64[("fp64", "m2p")]
-        out["roofline_fp64"] = {"bound": "alu", "kernel": p2p_kernel_name(sched64, "double"),
-                                "achieved": round(ach64, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                "frac": round(ach64 / FP64_PEAK_TFLOPS, 4), "avg_launch_ms": round(avg64, 5),
-                                "launches": n64p, "far_field_schedule": SCHEDULES[sched64]}
         out["m2p_g_target_box_s_fp64"] = (round(r.m2p_pairs / (mm64 / max(nm64, 1) / 1e3) / 1e9, 3)
                                           if nm64 else None)
         out["fp64"] = {"treecode_ms_per_solve": round(1e3 * t64, 3), "iters": r64.iters,

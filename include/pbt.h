@@ -79,6 +79,10 @@ typedef struct {
   int32_t treecode;     /* 1 = treecode matvec (default), 0 = direct sums over all pairs */
   double near_factor;   /* the near rule applies to panel j seen from x when |x - c_j| < near_factor * L_j,
                            L_j = sqrt(2 A_j), c_j its centroid (Section 3.1: 2); > 0 (default 2) */
+  int32_t precond;      /* 1 (default): GMRES right-preconditioned by the inverses of the panels' own
+                           2x2 (molecule, Stern, cavity) or 1x1 (charged, potential) self blocks of the
+                           operator, so that it still minimises ||b - A x||; 0: none (Section 3.2 names
+                           GMRES only) */
 } pbt_params;
 
 typedef struct {
@@ -96,6 +100,8 @@ typedef struct {
   int32_t fp64_fallback;  /* PBT_MIXED: 1 if the iterative refinement stagnated (an FP32-interaction
                              correction no longer halved the FP64 residual) and FP64 inner solves
                              finished the solve, else 0 */
+  int64_t m2p_fused_pairs; /* M2P (target, box) pairs evaluating both the Laplace and the Yukawa
+                              expansion (a molecule's target and box) */
 } pbt_result;
 
 /* Fills *p with the defaults listed above.  Never fails for non-NULL p. */
@@ -331,8 +337,9 @@ pbt_status pbt_get_schedule(pbt_ctx* ctx, int32_t* mode);
 /* Launch shape of the enabled system's products (pbt_autotune may have
  * chosen it): out[0] = Gauss points per P2P task segment, out[1] = boxes per
  * M2P task, out[2] = work-items of a stand-alone P2P launch (wavefronts of
- * two half-wave tasks, 256-thread blocks, a multiple of 8 blocks).  out: 3
- * int64 (host).  Host-only. */
+ * two half-wave tasks, 256-thread blocks, a multiple of 8 blocks), out[3] =
+ * work-items of a stand-alone M2P launch (one wavefront per task, the same
+ * blocks).  out: 4 int64 (host).  Host-only. */
 pbt_status pbt_get_launch_shape(pbt_ctx* ctx, int64_t* out);
 
 /* Orthogonalisation of the GMRES solver (Section 3.2 solves with GMRES) for

@@ -198,6 +198,7 @@ std::string check_params(const pbt_params& p) {
   if (p.prec != PBT_FP64 && p.prec != PBT_MIXED) return "prec must be PBT_FP64 or PBT_MIXED";
   if (!(p.near_factor > 0.0) || !std::isfinite(p.near_factor) || p.near_factor > 1e3)
     return "near_factor must be in (0, 1000]";
+  if (p.precond != 0 && p.precond != 1) return "precond must be 0 or 1";
   return "";
 }
 
@@ -299,6 +300,7 @@ pbt_status solve_impl(pbt_ctx* c, const double* x0, pbt_result* res) {
   r.m2p_pairs = S.plan().m2p_pairs;
   r.dense_pairs = S.dense_pairs();
   r.p2p_fused_pairs = S.plan().p2p_fused_pairs;
+  r.m2p_fused_pairs = S.plan().m2p_fused_pairs;
   r.matvecs = (int32_t)(S.applications() - apply0);
   c->cs.iters = std::max(c->cs.iters, r.iters);
   if (!std::isfinite(r.F_total) || !std::isfinite(r.rel_resid)) {
@@ -334,6 +336,7 @@ void pbt_default_params(pbt_params* p) {
   p->prec = PBT_FP64;
   p->treecode = 1;
   p->near_factor = 2.0;
+  p->precond = 1;
 }
 
 pbt_status pbt_create(pbt_ctx** out, int32_t hip_device, const pbt_params* params) {
@@ -1076,10 +1079,11 @@ pbt_status pbt_get_launch_shape(pbt_ctx* c, int64_t* out) {
   if (!c || !out) return PBT_E_INVALID;
   return guarded(c, [&] {
     System& S = system_for(c);
-    const int64_t npairs = (int64_t)S.plan().p2p.size() / 2;
+    const int64_t npairs = (int64_t)S.plan().p2p.size() / 2, nm2p = (int64_t)S.plan().m2p.size();
     out[0] = S.seg_src();
     out[1] = S.seg_box();
     out[2] = ((npairs + 3) / 4 + 7) / 8 * 8 * 256;
+    out[3] = ((nm2p + 3) / 4 + 7) / 8 * 8 * 256;
     return PBT_OK;
   });
 }

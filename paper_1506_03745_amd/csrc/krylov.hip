@@ -313,7 +313,10 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
     // phi unknown, lanes 4-7 the psi unknown, each lane over every fourth
     // basis vector, added by a fixed butterfly; then the panel's densities
     // and source records for the next product, as the strengths kernel
-    // would write them from the updated unknowns
+    // would write them from the updated unknowns -- or, with the right
+    // preconditioner, from z = M^-1 v (the panel's inverse self block on its
+    // interior and outside rows, which share the indices of phi and psi),
+    // z also stored for the product's jump terms
     double acc = 0.0;
     if (e >= 0) {
 #pragma unroll
@@ -329,7 +332,16 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
       if (qi == 0) w[e] = v;
     }
     const double vo = __shfl_xor(v, 4, 8);
-    const double vphi = sub < 4 ? v : vo, vpsi = sub < 4 ? vo : v;
+    double vphi = sub < 4 ? v : vo, vpsi = sub < 4 ? vo : v;
+    if (on && ns.pinv) {
+      const double* mb = ns.pinv + 4 * p;
+      const double vin = cphi >= 0 && cpsi >= 0 ? vphi : 0.0;   // interior row (index of phi)
+      const double vout = cpsi >= 0 ? vpsi : vphi;                // outside row
+      const double zphi = mb[0] * vin + mb[1] * vout, zpsi = mb[2] * vin + mb[3] * vout;
+      vphi = zphi;
+      vpsi = zpsi;
+      if (qi == 0 && e >= 0) ns.zout[e] = sub < 4 ? zphi : zpsi;
+    }
     if (on) {
       const double sg = cpsi >= 0 ? dsc * vpsi : 0.0;
       const double mv = cphi >= 0 ? -vphi : 0.0;
@@ -378,6 +390,37 @@ __global__ __launch_bounds__(kBS) void k_arnoldi_update(const int64_t* __restric
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j + 1; i += kBS) Hg[(size_t)i * m + j] = col[i];
+}
+
+// z = M^-1 v (or M^-T v) for the right block-Jacobi preconditioner, per
+// panel: its inverse self block m on its interior and outside rows (the
+// indices of its phi and psi unknowns); with add, z is added to out.
+__global__ void k_precond(int64_t np, const int32_t* __restrict__ col_phi, const int32_t* __restrict__ col_psi,
+                          const double* __restrict__ pinv, const double* __restrict__ v, double* out, int transpose,
+                          int add) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int32_t cphi = col_phi[p], cpsi = col_psi[p];
+  const double* mb = pinv + 4 * p;
+  if (cphi >= 0 && cpsi >= 0) {
+    const double vin = v[cphi], vout = v[cpsi];
+    double zphi, zpsi;
+    if (transpose) {
+      zphi = mb[0] * vin + mb[2] * vout;   // (in, out) rows <- M^T (phi, psi)
+      zpsi = mb[1] * vin + mb[3] * vout;
+    } else {
+      zphi = mb[0] * vin + mb[1] * vout;
+      zpsi = mb[2] * vin + mb[3] * vout;
+    }
+    out[cphi] = add ? out[cphi] + zphi : zphi;
+    out[cpsi] = add ? out[cpsi] + zpsi : zpsi;
+  } else if (cphi >= 0) {
+    const double z = mb[1] * v[cphi];
+    out[cphi] = add ? out[cphi] + z : z;
+  } else {
+    const double z = mb[3] * v[cpsi];
+    out[cpsi] = add ? out[cpsi] + z : z;
+  }
 }
 
 // out[g] = sum_b part[g * R * nbj + b]: row 0 of each group's partials
@@ -486,6 +529,14 @@ void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m,
       k_arnoldi_update<double, true><<<grid, kBS, lds, s>>>(gu, j, m, R, nbj, part, h1, V, ldv, w, H, cs, sn, gv,
                                                             resid, *ns);
   }
+  PBT_HIP(hipGetLastError());
+}
+
+void launch_precond(int64_t np, const int32_t* col_phi, const int32_t* col_psi, const double* pinv, const double* v,
+                    double* out, bool transpose, bool add, hipStream_t s) {
+  if (np <= 0) return;
+  k_precond<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(np, col_phi, col_psi, pinv, v, out, transpose ? 1 : 0,
+                                                          add ? 1 : 0);
   PBT_HIP(hipGetLastError());
 }
 

@@ -109,6 +109,12 @@ struct NearParams {
 void launch_near_values(int64_t nt, const double* tx, const int32_t* tgt_self, const int64_t* rowptr,
                         const int32_t* col, const double* tri9, const double* nrm,
                         const double* area, const NearParams& p, double* vals, hipStream_t s);
+// Inverse self blocks of every panel (m[4 np]: z_phi = m0 v_int + m1 v_out,
+// z_psi = m2 v_int + m3 v_out), the right block-Jacobi preconditioner.
+void launch_self_blocks(int64_t np, const double* tri9, const double* cen, const int32_t* panel_surf,
+                        const uint8_t* forms, int nsurf, const double* surf_rhoinv, const double* dens_scale,
+                        const int32_t* col_phi, const int32_t* col_psi, const NearParams& p, double* m,
+                        hipStream_t s);
 // tgt_surf null: every target belongs to surface tsurf.
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
                       const int32_t* panel_surf, const uint8_t* forms, int nsurf, const double* surf_rhoinv,
@@ -294,12 +300,18 @@ struct NextSrc {
   double* sig;
   double* mu;
   void* src;
+  const double* pinv;   // inverse self blocks (right preconditioner), or null
+  double* zout;         // with pinv: z = M^-1 v of the new basis vector
 };
 void launch_arnoldi_update(const int64_t* gu, int G, int64_t nmax, int j, int m, int R, int nbj,
                            const double* part, const double* h1, const double* V, int64_t ldv, double* w,
                            double* H, double* cs, double* sn, double* gv, double* resid, const NextSrc* ns,
                            hipStream_t s);
 void launch_group_row0(int G, int R, int nbj, const double* part, double* out, hipStream_t s);
+// out = M^-1 v (M^-T v with transpose; out += with add), per panel from its
+// inverse self block pinv[4 p] (right block-Jacobi preconditioner).
+void launch_precond(int64_t np, const int32_t* col_phi, const int32_t* col_psi, const double* pinv, const double* v,
+                    double* out, bool transpose, bool add, hipStream_t s);
 // out[g R + i] = sum of the nbh partials of row i of group g, i < nrows
 // (rows of R per group in both), in a fixed order.  Rows of up to
 // kSumBatch partials are added with one batch of loads per lane.

@@ -277,9 +277,60 @@ __global__ void k_fold_near(int64_t nt, const int64_t* __restrict__ rowptr,
   }
 }
 
+// Inverse of each panel's self block of the operator (the right block-Jacobi
+// preconditioner of GMRES).  A panel's rows (interior, outside) against its
+// unknowns (phi, dphi/dn) hold the jump 1/2 on phi in both rows (the double
+// layer vanishes on the flat self panel) and the self single layers on
+// dphi/dn, folded with the same row factors as the near corrections and
+// scaled by the unknown's density factor: B = [[1/2, s_in], [1/2, s_out]].  A
+// charged panel has B = [1/2] (its outside row on phi), a potential panel
+// B = [s_out] (on dphi/dn).  m = (m00, m01, m10, m11) with
+// z_phi = m00 v_int + m01 v_out, z_psi = m10 v_int + m11 v_out.
+__global__ void k_self_blocks(int64_t np, const double* __restrict__ tri9, const double* __restrict__ cen,
+                              const int32_t* __restrict__ panel_surf, const uint8_t* __restrict__ forms, int nsurf,
+                              const double* __restrict__ surf_rhoinv, const double* __restrict__ dens_scale,
+                              const int32_t* __restrict__ col_phi, const int32_t* __restrict__ col_psi,
+                              NearParams p, double* __restrict__ m) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  double vl = 0.0, vy = 0.0;
+  self_single_layer(cen[3 * i], cen[3 * i + 1], cen[3 * i + 2], tri9 + 9 * i, p.Nedge, p.gl_t, p.gl_w, p.kappa, &vl,
+                    &vy);
+  const int32_t t = panel_surf[i];
+  const int f = forms[(int64_t)t * nsurf + t];
+  double a_in[2], a_out[2];
+  fold_pair(f & 3, vl, 0.0, vy, 0.0, surf_rhoinv[t], a_in);
+  fold_pair((f >> 2) & 3, vl, 0.0, vy, 0.0, surf_rhoinv[t], a_out);
+  const double ds = dens_scale[i];
+  double* o = m + 4 * i;
+  o[0] = o[1] = o[2] = o[3] = 0.0;
+  if (col_phi[i] >= 0 && col_psi[i] >= 0) {
+    const double s_in = a_in[0] * ds, s_out = a_out[0] * ds;
+    const double det = 0.5 * s_out - 0.5 * s_in;
+    o[0] = s_out / det;
+    o[1] = -s_in / det;
+    o[2] = -0.5 / det;
+    o[3] = 0.5 / det;
+  } else if (col_phi[i] >= 0) {
+    o[1] = 2.0;
+  } else {
+    o[3] = 1.0 / (a_out[0] * ds);
+  }
+}
+
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
+
+void launch_self_blocks(int64_t np, const double* tri9, const double* cen, const int32_t* panel_surf,
+                        const uint8_t* forms, int nsurf, const double* surf_rhoinv, const double* dens_scale,
+                        const int32_t* col_phi, const int32_t* col_psi, const NearParams& p, double* m,
+                        hipStream_t s) {
+  if (np <= 0) return;
+  k_self_blocks<<<nblocks(np, 256), 256, 0, s>>>(np, tri9, cen, panel_surf, forms, nsurf, surf_rhoinv, dens_scale,
+                                                  col_phi, col_psi, p, m);
+  PBT_HIP(hipGetLastError());
+}
 
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
                       const int32_t* panel_surf, const uint8_t* forms, int nsurf, const double* surf_rhoinv,

@@ -387,6 +387,10 @@ void System::build(hipStream_t s) {
                      surf_rhoinv_.p, near_.val.p, s);
     near_.val32.alloc(near_.val.n);
     launch_to_f32((int64_t)near_.val.n, near_.val.p, near_.val32.p, s);
+    // inverse self blocks: the right block-Jacobi preconditioner of GMRES
+    pinv_.alloc(4 * (size_t)np_);
+    launch_self_blocks(np_, tri9_.p, cen_.p, panel_surf_.p, forms_.p, ns, surf_rhoinv_.p, dens_scale_.p, col_phi_.p,
+                       col_psi_.p, np, pinv_.p, s);
     PBT_HIP(hipStreamSynchronize(s));
   }
 
@@ -669,11 +673,11 @@ void System::build_plan() {
   struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
   std::vector<std::vector<Lists>> L(leaves.size());
   // (per target group in parallel; the counts are added up afterwards)
-  std::vector<std::array<int64_t, 5>> cnt(leaves.size(), {0, 0, 0, 0, 0});
+  std::vector<std::array<int64_t, 6>> cnt(leaves.size(), {0, 0, 0, 0, 0, 0});
   parallel_for((int64_t)leaves.size(), [&](int64_t li) {
     const TreeBox& tl = leaves[li].tb;
     const int64_t nt = tl.pend - tl.pbeg;
-    std::array<int64_t, 5>& c = cnt[li];   // tot_src, tot_box, p2p, m2p, fused
+    std::array<int64_t, 6>& c = cnt[li];   // tot_src, tot_box, p2p, m2p, fused p2p, fused m2p
     const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
     L[li].resize(gsf.size());
     lp2p_[li].resize(gsf.size());
@@ -702,6 +706,12 @@ void System::build_plan() {
       for (int b : mb) o.box.push_back((int32_t)(boff_[e2] + b));
       c[1] += (int64_t)mb.size() * ((nt + 63) / 64);
       c[3] += (int64_t)mb.size() * nt;
+      {
+        int32_t fu = 0;
+        int16_t tf = 0;
+        task_form(leaves[li].e, e2, fu, tf);
+        if (fu) c[5] += (int64_t)mb.size() * nt;
+      }
       lp2p_[li][k2] = std::move(pb);
       lm2p_[li][k2] = std::move(mb);
     }
@@ -713,6 +723,7 @@ void System::build_plan() {
     P.p2p_pairs += c[2];
     P.m2p_pairs += c[3];
     P.p2p_fused_pairs += c[4];
+    P.m2p_fused_pairs += c[5];
   }
   // Segment sizes: aim at several thousand wavefront tasks in each launch.
   const int64_t want = 16384;
@@ -1435,10 +1446,22 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
   // the update that produced it (step k > 0); the transposed operator starts
   // from targets instead and does not use them.
   const bool fuse = !transpose_;
+  // right preconditioning, A M^-1 u = b with x = M^-1 u (M the panels' self
+  // blocks; A^T with M^-T): the product of step k acts on z = M^-1 v_k,
+  // which the update forming v_k also forms (fused steps) or a kernel forms
+  // before the product; GMRES still minimises the residual of A x = b
+  const bool pre = prm_.precond != 0;
   const NextSrc nsrc{dgp_.p, gpmax_, fp32 ? 1 : 0,
                      PanelMaps{col_phi_.p, col_psi_.p, row_int_.p, row_sol_.p, dens_scale_.p},
                      K_, src_wa_.p, nrm_.p, rlap_.p, sig_.p, mu_.p,
-                     fp32 ? (void*)src32_.p : (void*)src64_.p};
+                     fp32 ? (void*)src32_.p : (void*)src64_.p, pre ? pinv_.p : nullptr, pre ? zbuf_.p : nullptr};
+  // the vector a step's product acts on
+  auto operand = [&](int k) -> const double* {
+    const double* vk = V_.p + (size_t)k * n_;
+    if (!pre) return vk;
+    if (!fuse || k == 0) launch_precond(np_, col_phi_.p, col_psi_.p, pinv_.p, vk, zbuf_.p, transpose_, false, s);
+    return zbuf_.p;
+  };
   // The forward operator also forms the first Gram-Schmidt pass as it writes
   // its result (per-chunk partials, nbh per row).
   const int nbh = fuse ? plan_.nbh : nbj;
@@ -1451,9 +1474,9 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
       // one pass: h = V^T w and |w|^2 from one reduction, then the update
       if (fuse) {
         const DotReq dr{k + 1, V_.p, n_, part1, R, 1};
-        op(V_.p + (size_t)k * n_, vj1, fp32, s, k > 0, &dr);
+        op(operand(k), vj1, fp32, s, k > 0, &dr);
       } else {
-        op(V_.p + (size_t)k * n_, vj1, fp32, s);
+        op(operand(k), vj1, fp32, s);
         launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, 0, nullptr, 1, part1, nbj, s, big);
       }
       // more chunk partials per row than one batch of loads per lane of the
@@ -1471,9 +1494,9 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
     }
     if (fuse) {
       const DotReq dr{k + 1, V_.p, n_, part1, R};
-      op(V_.p + (size_t)k * n_, vj1, fp32, s, k > 0, &dr);
+      op(operand(k), vj1, fp32, s, k > 0, &dr);
     } else {
-      op(V_.p + (size_t)k * n_, vj1, fp32, s);
+      op(operand(k), vj1, fp32, s);
       launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, nullptr, 0, nullptr, 0, part1, nbj, s, big);
     }
     launch_gs_dots(dgu_.p, G, k + 1, R, V_.p, n_, vj1, part1, nbh, h1, 1, part2, nbj, s, big);
@@ -1578,7 +1601,14 @@ int System::gmres(bool fp32, const double* b, double* x, bool x_zero, const std:
       }
     }
     PBT_HIP(hipMemcpyAsync(dy, hy, (size_t)G * m * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_lincomb(dgu_.p, G, gmax_, umax, m, V_.p, n_, dy, x, s);
+    if (pre) {
+      // x += M^-1 (V y)
+      PBT_HIP(hipMemsetAsync(ztmp_.p, 0, n_ * sizeof(double), s));
+      launch_lincomb(dgu_.p, G, gmax_, umax, m, V_.p, n_, dy, ztmp_.p, s);
+      launch_precond(np_, col_phi_.p, col_psi_.p, pinv_.p, ztmp_.p, x, transpose_, true, s);
+    } else {
+      launch_lincomb(dgu_.p, G, gmax_, umax, m, V_.p, n_, dy, x, s);
+    }
     if (all_done || iters >= maxit) break;
     op(x, r_.p, fp32, s);
     launch_axpby(n_, 1.0, b, -1.0, r_.p, s);
@@ -1614,6 +1644,8 @@ bool System::solve_any(const double* b, double* x, bool x0_given, pbt_result* re
   r_.alloc(n_);
   tmp_.alloc(n_);
   y_.alloc(n_);
+  zbuf_.alloc(n_);
+  ztmp_.alloc(n_);
   pdb_ = gs_blocks(gmax_);
   part_.alloc((size_t)G * (m + 1) * (pdb_ + std::max(pdb_, plan_.nbh)));
   // per-chunk partials of groups with fewer chunks than nbh stay zero

@@ -108,7 +108,7 @@ struct Plan {
   int nslots = 0;    // M2P partial slots (64 lanes)
   int nbh = 1;       // most target chunks of one group
   int npslots = 0;   // P2P partial slots (32 lanes)
-  int64_t p2p_pairs = 0, m2p_pairs = 0, p2p_fused_pairs = 0;
+  int64_t p2p_pairs = 0, m2p_pairs = 0, p2p_fused_pairs = 0, m2p_fused_pairs = 0;
 };
 
 struct Timing {
@@ -383,6 +383,8 @@ class System {
   // Krylov workspace
   int restart_alloc_ = 0;
   DBuf<double> V_, r_, tmp_, hdev_, part_, y_, gm_, nrm_part_;
+  DBuf<double> pinv_;         // [np][4] inverse self blocks (right block-Jacobi preconditioner)
+  DBuf<double> zbuf_, ztmp_;  // z = M^-1 v of the current step; M^-1 (V y)
   int pdb_ = 1;
   // groups of surfaces = independent systems solved side by side
   int G_ = 1;

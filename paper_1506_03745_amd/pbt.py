@@ -38,7 +38,8 @@ class PbtParams(ctypes.Structure):
     _fields_ = [("k_far", ctypes.c_int32), ("k_near", ctypes.c_int32), ("k_self_edge", ctypes.c_int32),
                 ("ncrit", ctypes.c_int32), ("taylor_p", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("treecode", ctypes.c_int32), ("near_factor", ctypes.c_double)]
+                ("prec", ctypes.c_int32), ("treecode", ctypes.c_int32), ("near_factor", ctypes.c_double),
+                ("precond", ctypes.c_int32)]
 
 
 class PbtResult(ctypes.Structure):
@@ -48,7 +49,7 @@ class PbtResult(ctypes.Structure):
                 ("t_solve_s", ctypes.c_double), ("p2p_pairs", ctypes.c_int64),
                 ("m2p_pairs", ctypes.c_int64), ("dense_pairs", ctypes.c_int64),
                 ("p2p_fused_pairs", ctypes.c_int64), ("matvecs", ctypes.c_int32),
-                ("fp64_fallback", ctypes.c_int32)]
+                ("fp64_fallback", ctypes.c_int32), ("m2p_fused_pairs", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -171,6 +172,7 @@ class Result:
     p2p_fused_pairs: int
     matvecs: int
     fp64_fallback: int = 0
+    m2p_fused_pairs: int = 0
     status: int = 0
 
 
@@ -371,8 +373,8 @@ class Solver:
         return m.value
 
     def launch_shape(self):
-        """(P2P segment length, M2P boxes per task, stand-alone P2P work-items)."""
-        out = (ctypes.c_int64 * 3)()
+        """(P2P segment length, M2P boxes per task, stand-alone P2P and M2P work-items)."""
+        out = (ctypes.c_int64 * 4)()
         self._check(lib().pbt_get_launch_shape(self._h, out))
         return tuple(int(v) for v in out)
 

@@ -73,7 +73,7 @@ def test_invalid_rule_and_params_rejected_on_host():
         P.quadrature_rule(5)
     for bad in (dict(theta=1.5), dict(theta=0.0), dict(taylor_p=12), dict(k_far=2), dict(k_near=6),
                 dict(ncrit=0), dict(tol=0.0), dict(restart=0), dict(restart=1025), dict(taylor_p=9),
-                dict(near_factor=0.0), dict(near_factor=-1.0), dict(near_factor=float("nan"))):
+                dict(near_factor=0.0), dict(near_factor=-1.0), dict(near_factor=float("nan")), dict(precond=2)):
         p = B.default_params()
         for k, v in bad.items():
             setattr(p, k, v)
@@ -83,8 +83,8 @@ def test_invalid_rule_and_params_rejected_on_host():
 
 def test_struct_layouts_match_header():
     # field order and sizes of the two public structs
-    assert ctypes.sizeof(B.PbtParams) == 5 * 4 + 4 + 8 + 8 + 4 * 4 + 8
-    assert ctypes.sizeof(B.PbtResult) == 4 * 8 + 2 * 4 + 3 * 8 + 4 * 8 + 2 * 4
+    assert ctypes.sizeof(B.PbtParams) == 5 * 4 + 4 + 8 + 8 + 4 * 4 + 8 + 8
+    assert ctypes.sizeof(B.PbtResult) == 4 * 8 + 2 * 4 + 3 * 8 + 4 * 8 + 2 * 4 + 8
 
 
 def test_richardson_helpers_recover_order_and_limit():

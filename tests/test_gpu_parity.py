@@ -114,16 +114,15 @@ def test_far_field_schedules_agree_bitwise():
 
 
 def test_launch_shape_follows_segments():
-    """The reported launch shape: positive segment lengths, a P2P grid of
-    whole groups of 8 blocks of 256, and the grid's growth when P2P tasks
-    take shorter source segments."""
+    """The reported launch shape: positive segment lengths, P2P and M2P
+    grids of whole groups of 8 blocks of 256."""
     from workloads.problems import config_problem
     s, _ = from_problem(config_problem("twosphere_charge"), treecode=1, ncrit=300, theta=0.5, taylor_p=6)
-    src, box, grid = s.launch_shape()
-    assert src > 0 and box > 0 and grid > 0 and grid % 2048 == 0
+    src, box, grid, mgrid = s.launch_shape()
+    assert src > 0 and box > 0 and grid > 0 and grid % 2048 == 0 and mgrid > 0 and mgrid % 2048 == 0
     s.autotune()
-    src2, box2, grid2 = s.launch_shape()
-    assert src2 > 0 and box2 > 0 and grid2 % 2048 == 0
+    src2, box2, grid2, mgrid2 = s.launch_shape()
+    assert src2 > 0 and box2 > 0 and grid2 % 2048 == 0 and mgrid2 % 2048 == 0
     s.close()
 
 
@@ -547,3 +546,40 @@ def test_exhausted_krylov_space_with_one_pass():
     r = s.solve()
     assert r.rel_resid <= 1e-13
     assert abs(r.F_solv - e.F_solv) <= 1e-10 * abs(e.F_solv)
+
+
+@pytest.mark.parametrize("name", ["sphere_plate", "three_body", "stern_plate", "nested_plate",
+                                  "twosphere_potential_l2"])
+def test_block_jacobi_preconditioner(name):
+    """Right preconditioning by the panels' inverse self blocks: the same
+    solution of A x = b (energies against the oracle's dense LU within the
+    tolerance), fewer iterations, in FP64 and mixed precision, forward and
+    through the adjoint (gradient against the oracle's dense transpose)."""
+    pr = case(name)
+    e, _, _ = solve_problem(pr)
+    its = {}
+    for pre in (0, 1):
+        for prec in (FP64, MIXED):
+            s, _ = from_problem(pr, treecode=0, tol=1e-10, prec=prec, precond=pre)
+            r = s.solve()
+            assert r.rel_resid <= 1e-10
+            if e.F_solv != 0:
+                assert abs(r.F_solv - e.F_solv) <= 1e-7 * abs(e.F_solv)
+            if e.F_surf != 0:
+                assert abs(r.F_surf - e.F_surf) <= 1e-7 * abs(e.F_surf)
+            its[(pre, prec)] = r.iters
+            s.close()
+    print(name, its)
+    assert its[(1, FP64)] < its[(0, FP64)]
+    assert its[(1, MIXED)] < its[(0, MIXED)]
+
+
+def test_block_jacobi_preconditioner_adjoint():
+    from oracle.adjoint import interaction_gradient
+    pr = case("sphere_plate")
+    g = interaction_gradient(pr)
+    for pre in (0, 1):
+        s, ids = from_problem(pr, treecode=0, tol=1e-11, precond=pre)
+        ds, dq = s.gradient(ids[1], pr.surfaces[1].nt, ids[0], len(pr.surfaces[0].q))
+        assert rel_inf(dq, g[0]) < 1e-6 and rel_inf(ds, g[1]) < 1e-6
+        s.close()
