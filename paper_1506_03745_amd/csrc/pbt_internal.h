@@ -214,11 +214,13 @@ template <typename T>
 void launch_moments(int P, int nblocks, const int32_t* mblocks, const MomChunk* chunks, int nheads,
                     const MomChunk* heads, const double* bcen, const double* brho, const T* src, T* mom, T* mpart,
                     hipStream_t s);
-// Moments of one tree level's boxes from their children's (M2M), for the
-// nbox boxes listed (child lists cbeg / cend / clist, global numbering).
+// Moments of boxes from their leaves' (M2M): pairs[3 i] = (box, leaf,
+// slot) shift the leaf's moments to the box's centre into slot (2 ncoef(P)
+// values each), then heads[3 h] = (box, first slot, count) add a box's slots
+// in order into its moments.
 template <typename T>
-void launch_m2m(int P, int nbox, const int32_t* boxes, const int32_t* cbeg, const int32_t* cend,
-                const int32_t* clist, const double* bcen, T* mom, hipStream_t s);
+void launch_m2m(int P, int npairs, const int32_t* pairs, int nheads, const int32_t* heads, const double* bcen,
+                T* slots, T* mom, hipStream_t s);
 // M2P and P2P tasks in one launch (taylor.hip).
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,

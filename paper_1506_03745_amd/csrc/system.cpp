@@ -398,8 +398,9 @@ void System::build(hipStream_t s) {
   upload_plan(s);
   // Moments of every box that some M2P task reads and of all its
   // descendants: the leaves from their own sources (P2M), in chunks of at
-  // most kMomChunk sources; every other box from its children's moments
-  // (M2M), one tree level per launch from the deepest up.
+  // most kMomChunk sources; every other box from its leaves' moments, each
+  // shifted to the box's centre on its own (M2M by (box, leaf) pairs, all in
+  // one launch) and added per box in leaf order.
   {
     std::vector<char> used(nbox_, 0), need(nbox_, 0), leaf(nbox_, 0);
     std::vector<int32_t> par(nbox_, -1), lev(nbox_, 0);
@@ -422,24 +423,49 @@ void System::build(hipStream_t s) {
     std::vector<char> known_box(nbox_, 0);
     for (int e = 0; e < ns; ++e)
       for (int64_t b = boff_[e]; b < boff_[e + 1]; ++b) known_box[b] = !two_rows(e);
-    // M2M levels (deepest first), all boxes and those of known surfaces
-    std::vector<int32_t> lb, lbk;
-    m2m_levels_.clear();
-    m2m_levels_known_.clear();
-    for (int lv = maxlev; lv >= 0; --lv) {
-      const size_t a0 = lb.size(), k0 = lbk.size();
-      for (int b = 0; b < nbox_; ++b)
-        if (need[b] && !leaf[b] && lev[b] == lv) {
-          lb.push_back(b);
-          if (known_box[b]) lbk.push_back(b);
+    // M2M pairs (box, leaf under it, slot) and per box (box, first slot,
+    // leaves), all boxes and those of known surfaces; the leaves under a box
+    // are the leaves of its surface whose panels start inside its range
+    (void)maxlev;
+    std::vector<int32_t> pr, hd, prk, hdk;
+    int32_t nslot = 0;
+    for (int e = 0; e < ns; ++e) {
+      const SurfTree& T = trees_[e];
+      std::vector<std::pair<int32_t, int32_t>> lv;   // (first panel, global leaf id)
+      for (size_t bi = 0; bi < T.boxes.size(); ++bi)
+        if (T.boxes[bi].leaf) lv.push_back({T.boxes[bi].pbeg, (int32_t)(boff_[e] + bi)});
+      std::sort(lv.begin(), lv.end());
+      for (size_t bi = 0; bi < T.boxes.size(); ++bi) {
+        const int32_t g = (int32_t)(boff_[e] + bi);
+        if (!need[g] || leaf[g]) continue;
+        const TreeBox& tb = T.boxes[bi];
+        auto lo = std::lower_bound(lv.begin(), lv.end(), std::make_pair(tb.pbeg, (int32_t)-1));
+        auto hi = std::lower_bound(lv.begin(), lv.end(), std::make_pair(tb.pend, (int32_t)-1));
+        const int32_t s0 = nslot, n = (int32_t)(hi - lo);
+        for (auto it = lo; it != hi; ++it) {
+          pr.insert(pr.end(), {g, it->second, nslot});
+          if (known_box[g]) prk.insert(prk.end(), {g, it->second, nslot});
+          ++nslot;
         }
-      if (lb.size() > a0) m2m_levels_.push_back({(int)a0, (int)(lb.size() - a0)});
-      if (lbk.size() > k0) m2m_levels_known_.push_back({(int)k0, (int)(lbk.size() - k0)});
+        hd.insert(hd.end(), {g, s0, n});
+        if (known_box[g]) hdk.insert(hdk.end(), {g, s0, n});
+      }
     }
-    if (lb.empty()) lb.push_back(0);
-    if (lbk.empty()) lbk.push_back(0);
-    m2m_boxes_.upload(lb, s);
-    m2m_boxes_known_.upload(lbk, s);
+    npair_ = (int)pr.size() / 3;
+    nhead_ = (int)hd.size() / 3;
+    npair_known_ = (int)prk.size() / 3;
+    nhead_known_ = (int)hdk.size() / 3;
+    for (auto* v : {&pr, &hd, &prk, &hdk})
+      if (v->empty()) v->assign(3, 0);
+    m2m_pairs_.upload(pr, s);
+    m2m_heads_.upload(hd, s);
+    m2m_pairs_known_.upload(prk, s);
+    m2m_heads_known_.upload(hdk, s);
+    {
+      const size_t NC2 = 2 * (size_t)ncoef(prm_.taylor_p);
+      mslot32_.alloc(std::max<size_t>(nslot, 1) * NC2);
+      mslot64_.alloc(std::max<size_t>(nslot, 1) * NC2);
+    }
     for (int b = 0; b < nbox_; ++b) {
       if (!need[b] || !leaf[b] || se[b] <= sb[b]) continue;
       const int32_t n = se[b] - sb[b];
@@ -995,12 +1021,14 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   auto pe = [&](int kind, int e0, hipStream_t st) {
     if (e0 >= 0) prof_end(pbase + kind, e0, st);
   };
-  // M2M up the tree after the leaves' moments (P2M)
-  const auto& m2m_lv = known_only ? m2m_levels_known_ : m2m_levels_;
-  const int32_t* m2m_bx = known_only ? m2m_boxes_known_.p : m2m_boxes_.p;
+  // M2M after the leaves' moments (P2M): every (box, leaf) shift, then the
+  // sums per box
+  const int npr = known_only ? npair_known_ : npair_, nhd = known_only ? nhead_known_ : nhead_;
+  const int32_t* m2m_pr = known_only ? m2m_pairs_known_.p : m2m_pairs_.p;
+  const int32_t* m2m_hd = known_only ? m2m_heads_known_.p : m2m_heads_.p;
+  T* mslot = f32 ? (T*)mslot32_.p : (T*)mslot64_.p;
   auto m2m = [&](hipStream_t fs) {
-    for (const auto& lv : m2m_lv)
-      launch_m2m<T>(prm_.taylor_p, lv.second, m2m_bx + lv.first, bcbeg_.p, bcend_.p, bclist_.p, bcen_.p, mom, fs);
+    launch_m2m<T>(prm_.taylor_p, npr, m2m_pr, nhd, m2m_hd, bcen_.p, mslot, mom, fs);
   };
   auto moments = [&](hipStream_t fs) {
     const int e0 = pb(fs);
@@ -1010,7 +1038,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   };
   // after a launch that computed the leaves' moments with P2P
   auto m2m_marked = [&](hipStream_t fs) {
-    if (m2m_lv.empty()) return;
+    if (nhd == 0) return;
     const int e0 = pb(fs);
     m2m(fs);
     pe(2, e0, fs);

@@ -363,10 +363,13 @@ class System {
   DBuf<int32_t> mblocks_known_;
   DBuf<MomChunk> mchunks_known_, mheads_known_;
   int nleaf_ = 0;
-  // M2M: (offset, count) of each tree level's boxes in m2m_boxes_, deepest
-  // level first; the same for the boxes of charged / potential surfaces
-  std::vector<std::pair<int, int>> m2m_levels_, m2m_levels_known_;
-  DBuf<int32_t> m2m_boxes_, m2m_boxes_known_;
+  // M2M: (box, leaf under it, slot) pairs and (box, first slot, leaves) per
+  // box; the same for the boxes of charged / potential surfaces; slots of
+  // 2 ncoef(P) shifted moments
+  int npair_ = 0, nhead_ = 0, npair_known_ = 0, nhead_known_ = 0;
+  DBuf<int32_t> m2m_pairs_, m2m_heads_, m2m_pairs_known_, m2m_heads_known_;
+  DBuf<float> mslot32_;
+  DBuf<double> mslot64_;
   DBuf<float> mom32_;
   DBuf<double> mom64_;
 

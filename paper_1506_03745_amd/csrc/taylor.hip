@@ -203,46 +203,39 @@ __global__ __launch_bounds__(256) void k_moments_sum(const MomChunk* __restrict_
 }
 
 // ---- M2M -------------------------------------------------------------------
-// A box's moments about its centre c from its children's about theirs, c':
-// with d = c' - c, (y - c)^k = sum_{l <= k} C(k, l) (y - c')^l d^(k - l)
+// A box's moments about its centre c from a leaf's about its own, c': with
+// d = c' - c, (y - c)^k = sum_{l <= k} C(k, l) (y - c')^l d^(k - l)
 // (multi-index binomials), and grad_y commutes with the shift, so for both
-// rows   M_k(c) = sum_children sum_{l <= k} C(k, l) d^(k - l) M_l(c').
-// The multi-index sum factorises into three one-dimensional ones, taken as
-// three passes (x, then y, then z) over every child's moments, each output a
-// sum of at most P + 1 terms: (a, b, c) <- sum_{a' <= a} C(a, a') dx^(a - a')
-// (a', b, c), and so on (a' <= a keeps |(a', b, c)| <= P).  One block per
-// box of one tree level (the children's moments are final); the children's
-// moments, the powers of their shifts and the binomials in LDS; the
-// children's shifted moments are added in list order.
-constexpr int kM2MThreads = 128;
-constexpr int kMaxChildren = 8;
+// rows   M_k(c) = sum_leaves sum_{l <= k} C(k, l) d^(k - l) M_l(c').
+// Every leaf under a box is shifted straight to the box (no level-by-level
+// chain, so all shifts run in one launch); the multi-index sum factorises
+// into three one-dimensional ones, taken as passes x, y, z of at most P + 1
+// terms: (a, b, c) <- sum_{a' <= a} C(a, a') dx^(a - a') (a', b, c), and so
+// on (a' <= a keeps |(a', b, c)| <= P).  One wavefront per (box, leaf) pair,
+// the leaf's moments, the powers of the shift and the binomials in LDS; the
+// result goes to the pair's slot, and a second launch adds each box's slots
+// in leaf order.
+constexpr int kM2MThreads = 64;
 
 template <typename T, int P>
-__global__ __launch_bounds__(kM2MThreads) void k_m2m(const int32_t* __restrict__ boxes,
-                                                     const int32_t* __restrict__ cbeg,
-                                                     const int32_t* __restrict__ cend,
-                                                     const int32_t* __restrict__ clist,
-                                                     const double* __restrict__ bcen, T* __restrict__ mom) {
+__global__ __launch_bounds__(kM2MThreads) void k_m2m_shift(const int32_t* __restrict__ pairs,
+                                                           const double* __restrict__ bcen,
+                                                           const T* __restrict__ mom, T* __restrict__ slots) {
   constexpr int NC = ncoef(P);
-  constexpr int NO = 2 * NC;   // outputs per child: (row, k)
-  __shared__ T sa[kMaxChildren][NO];
-  __shared__ T sb[kMaxChildren][NO];
-  __shared__ T sp[kMaxChildren][3][P + 1];
+  constexpr int NO = 2 * NC;   // outputs: (row, k)
+  __shared__ T sa[NO];
+  __shared__ T sb[NO];
+  __shared__ T sp[3][P + 1];
   __shared__ T sbin[P + 1][P + 1];
   __shared__ int8_t sk[NC][3];
-  const int b = boxes[blockIdx.x];
-  const int c0 = cbeg[b];
-  const int nch = min(cend[b] - c0, kMaxChildren);
-  for (int i = threadIdx.x; i < nch * NO; i += kM2MThreads) {
-    const int ci = i / NO, r = i - ci * NO;
-    sa[ci][r] = mom[(int64_t)(2 * clist[c0 + ci]) * NC + r];
-  }
-  for (int i = threadIdx.x; i < nch * 3; i += kM2MThreads) {
-    const int ci = i / 3, d = i - ci * 3;
-    const T dd = (T)(bcen[3 * clist[c0 + ci] + d] - bcen[3 * b + d]);
+  const int b = pairs[3 * blockIdx.x], leaf = pairs[3 * blockIdx.x + 1], slot = pairs[3 * blockIdx.x + 2];
+  for (int i = threadIdx.x; i < NO; i += kM2MThreads) sa[i] = mom[(int64_t)(2 * leaf) * NC + i];
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x;
+    const T dd = (T)(bcen[3 * leaf + d] - bcen[3 * b + d]);
     T pw = T(1);
     for (int e = 0; e <= P; ++e) {
-      sp[ci][d][e] = pw;
+      sp[d][e] = pw;
       pw *= dd;
     }
   }
@@ -262,29 +255,43 @@ __global__ __launch_bounds__(kM2MThreads) void k_m2m(const int32_t* __restrict__
   }
   __syncthreads();
   // pass along dimension D: dst(k) = sum_{e <= k_D} C(k_D, e) d_D^(k_D - e) src(k with k_D = e)
-  auto pass = [&](const T (*src)[NO], T (*dst)[NO], int D) {
-    for (int i = threadIdx.x; i < nch * NO; i += kM2MThreads) {
-      const int ci = i / NO, o = i - ci * NO;
+  auto pass = [&](const T* src, T* dst, int D) {
+    for (int o = threadIdx.x; o < NO; o += kM2MThreads) {
       const int row = o >= NC ? NC : 0, k = o - row;
       int q[3] = {sk[k][0], sk[k][1], sk[k][2]};
       const int top = q[D];
       T acc = T(0);
       for (int e = 0; e <= top; ++e) {
         q[D] = e;
-        acc += sbin[top][e] * sp[ci][D][top - e] * src[ci][row + tidx(q[0], q[1], q[2])];
+        acc += sbin[top][e] * sp[D][top - e] * src[row + tidx(q[0], q[1], q[2])];
       }
-      dst[ci][o] = acc;
+      dst[o] = acc;
     }
     __syncthreads();
   };
   pass(sa, sb, 0);
   pass(sb, sa, 1);
   pass(sa, sb, 2);
-  for (int o = threadIdx.x; o < NO; o += kM2MThreads) {
-    T acc = T(0);
-    for (int ci = 0; ci < nch; ++ci) acc += sb[ci][o];
-    mom[(int64_t)(2 * b) * NC + o] = acc;
-  }
+  for (int o = threadIdx.x; o < NO; o += kM2MThreads) slots[(int64_t)slot * NO + o] = sb[o];
+}
+
+// Each box's shifted leaf moments added up: block (box, 8 outputs), 32
+// lanes per output each over every 32nd leaf slot in order, then a fixed
+// butterfly over the 32 (the same partition and order on every launch).
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2m_sum(int NO, const int32_t* __restrict__ heads,
+                                                 const T* __restrict__ slots, T* __restrict__ mom) {
+  const int b = heads[3 * blockIdx.x], s0 = heads[3 * blockIdx.x + 1], n = heads[3 * blockIdx.x + 2];
+  const int o = blockIdx.y * 8 + (threadIdx.x >> 5), lane = threadIdx.x & 31;
+  T acc = T(0);
+  if (o < NO)
+    for (int i = lane; i < n; i += 32) acc += slots[(int64_t)(s0 + i) * NO + o];
+  acc += __shfl_xor(acc, 16, 32);
+  acc += __shfl_xor(acc, 8, 32);
+  acc += __shfl_xor(acc, 4, 32);
+  acc += __shfl_xor(acc, 2, 32);
+  acc += __shfl_xor(acc, 1, 32);
+  if (o < NO && lane == 0) mom[(int64_t)b * NO + o] = acc;
 }
 
 // ---- M2P -------------------------------------------------------------------
@@ -575,16 +582,18 @@ void launch_p2p_moments(int P, int nblocks, const int32_t* mblocks, const MomChu
 }
 
 template <typename T>
-void launch_m2m(int P, int nbox, const int32_t* boxes, const int32_t* cbeg, const int32_t* cend,
-                const int32_t* clist, const double* bcen, T* mom, hipStream_t s) {
-  if (nbox <= 0) return;
+void launch_m2m(int P, int npairs, const int32_t* pairs, int nheads, const int32_t* heads, const double* bcen,
+                T* slots, T* mom, hipStream_t s) {
+  if (nheads <= 0) return;
   switch (P) {
 #define PBT_CASE(PP) \
-  case PP: k_m2m<T, PP><<<nbox, kM2MThreads, 0, s>>>(boxes, cbeg, cend, clist, bcen, mom); break;
+  case PP: k_m2m_shift<T, PP><<<npairs, kM2MThreads, 0, s>>>(pairs, bcen, mom, slots); break;
     PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
 #undef PBT_CASE
     default: throw Error(1, "Taylor order P must be 0..8");
   }
+  PBT_HIP(hipGetLastError());
+  k_m2m_sum<T><<<dim3(nheads, (2 * ncoef(P) + 7) / 8), 256, 0, s>>>(2 * ncoef(P), heads, slots, mom);
   PBT_HIP(hipGetLastError());
 }
 
@@ -671,10 +680,10 @@ template void launch_m2p_p2p<float>(int, const Task*, int, const int32_t*, const
 template void launch_m2p_p2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
                                      const Task*, int, const int32_t*, const double*, const double*, double, bool,
                                      double*, double*, hipStream_t);
-template void launch_m2m<float>(int, int, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
-                                const double*, float*, hipStream_t);
-template void launch_m2m<double>(int, int, const int32_t*, const int32_t*, const int32_t*, const int32_t*,
-                                 const double*, double*, hipStream_t);
+template void launch_m2m<float>(int, int, const int32_t*, int, const int32_t*, const double*, float*, float*,
+                                hipStream_t);
+template void launch_m2m<double>(int, int, const int32_t*, int, const int32_t*, const double*, double*, double*,
+                                 hipStream_t);
 template void launch_m2p<float>(int, const Task*, int, const int32_t*, const float*, const double*,
                                 const float*, float, float*, hipStream_t);
 template void launch_m2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
