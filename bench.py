@@ -44,6 +44,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -52,7 +53,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "treecode BEM matvec Ginteractions/s + GMRES time to 1e-6 resid, FP32 vs FP64"
 FP32_PEAK_TFLOPS = 157.3          # published MI355X FP32 vector peak (packed FP32 FMA)
-FP32_NONPACKED_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, one FP32 op per lane
 FP64_PEAK_TFLOPS = 78.6           # published MI355X FP64 vector peak
 FLOPS_FUSED_PAIR = 34
 FLOPS_YUKAWA_PAIR = 30
@@ -120,6 +120,10 @@ def parse():
     ap.add_argument("--no-fd", action="store_true", help="gradient: skip the central-difference check")
     ap.add_argument("--autotune-cache", default=None,
                     help="text cache of tuned launch shapes (read if present, appended otherwise)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                    help="no GPU work: reduce two rocprofv3 --pmc counter_collection CSVs (FETCH_SIZE, "
+                         "WRITE_SIZE of runs with --copy-calib) to HBM bytes per launch of each kernel "
+                         "and write them as JSON")
     return ap.parse_args()
 
 
@@ -352,7 +356,6 @@ def bench_solve(a, cpu):
     for rf, fl in ((rf_p2p, "34 per Laplace+Yukawa pair, 30 per Yukawa-only pair"),
                    (rf_m2p, f"{m2p_pair_flops(6, True)} per (target, box) with the Laplace expansion too, "
                             f"{m2p_pair_flops(6, False)} Yukawa only")):
-        rf["frac_of_nonpacked_fp32"] = round(rf["achieved"] / FP32_NONPACKED_TFLOPS, 4)
         rf["flop_convention"] = "FMA 2, other op 1, transcendental 1; " + fl
     dom = max(("p2p", "m2p", "moments", "combine"), key=lambda k: kt[("fp32", k)][0])
     main_rf = dict(rf_m2p if dom == "m2p" else rf_p2p)
@@ -564,12 +567,64 @@ def bench_gradient(a):
     print(json.dumps(out), flush=True)
 
 
+def summarize_counters(fetch_csv, write_csv, out_json):
+    """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, both in KiB per dispatch), each scaled by what the same
+    counter reads for the plain 256 MiB device-to-device copy that
+    --copy-calib runs (256 MiB read and 256 MiB written).  Averages over the
+    dispatches of each (kernel, grid size)."""
+    import collections
+    import csv
+
+    def load(path, counter):
+        per = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                per[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]) * 1024.0)
+        return per
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    copy_bytes = 256.0 * 2 ** 20
+
+    def calib(per, name):
+        # the copy: the runtime's copy kernel with the most bytes moved
+        cands = [(max(v), k) for k, v in per.items() if "copyBuffer" in k[0]]
+        if not cands:
+            raise SystemExit(f"no copy kernel in the {name} run (was it made with --copy-calib?)")
+        return copy_bytes / max(cands)[0]
+
+    ff, fw = calib(fetch, "FETCH_SIZE"), calib(write, "WRITE_SIZE")
+    kernels = []
+    for key in sorted(set(fetch) & set(write)):
+        name, grid = key
+        if "copyBuffer" in name or "fillBuffer" in name:
+            continue
+        f = sum(fetch[key]) / len(fetch[key]) * ff
+        w = sum(write[key]) / len(write[key]) * fw
+        m = re.search(r"::(k_\w+(?:<[^()]*>)?)\(", name)
+        if not m:
+            continue   # not a kernel of this library
+        short = m.group(1)
+        kernels.append({"kernel": short, "grid_size": grid, "dispatches": len(fetch[key]),
+                        "fetch_bytes_per_launch": round(f), "write_bytes_per_launch": round(w),
+                        "traffic_bytes_per_launch": round(f + w)})
+    sha = [hashlib.sha256(open(p, "rb").read()).hexdigest() for p in P2P_SOURCES]
+    out = {"fetch_scale": ff, "write_scale": fw, "calibration": "256 MiB device-to-device copy",
+           "sources": [os.path.relpath(p, ROOT) for p in P2P_SOURCES], "sources_sha256": sha,
+           "kernels": kernels}
+    with open(out_json, "w") as fh:   # one kernel a line
+        fh.write("{\n" + "".join(f" {json.dumps(k)}: {json.dumps(v)},\n" for k, v in out.items() if k != "kernels")
+                 + ' "kernels": [\n' + ",\n".join("  " + json.dumps(k) for k in kernels) + "\n ]\n}\n")
+    print(json.dumps({"written": out_json, "fetch_scale": ff, "write_scale": fw, "kernels": len(kernels)}))
+
+
 def main():
     a = parse()
+    if a.summarize_counters:
+        return summarize_counters(*a.summarize_counters)
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              f"(every GPU box here has one GPU; the multi-GPU design is documented, not built)",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {a.gpus} is not supported (the sharded multi-GPU path "
+              f"is not built)", file=sys.stderr)
         sys.exit(2)
     if a.workload == "orient_sweep":
         return bench_batch(a)

@@ -13,6 +13,8 @@
 // and, from sources on its own molecule, the interior row
 //   L(x) = -(eps_out/eps_s) sum s G_L - sum D.(x-y) / (4 pi r^3),
 // which is K_L phi - V_L dphi/dn of eq. integral_eq.
+#include <algorithm>
+
 #include "pbt_internal.h"
 
 namespace pbt {
@@ -231,18 +233,22 @@ __global__ void k_to_f32(int64_t n, const double* __restrict__ in, float* __rest
   if (i < n) out[i] = (float)in[i];
 }
 
-__global__ __launch_bounds__(256) void k_reac(int64_t nq, const double* __restrict__ qxyz, int64_t s0,
-                                              int64_t s1, const double* __restrict__ src, double rho_inv,
-                                              const int64_t* __restrict__ near_ptr,
-                                              const int32_t* __restrict__ near_col,
-                                              const double* __restrict__ near_val,
-                                              const double* __restrict__ sig,
-                                              const double* __restrict__ mu, double* phi) {
-  __shared__ double red[4];
-  const int64_t k = blockIdx.x;
-  const double x = qxyz[3 * k], y = qxyz[3 * k + 1], z = qxyz[3 * k + 2];
+// The reaction potential's far part in tiles: a wavefront holds 64 charges
+// (one per lane) and runs over one segment of the molecule's sources, read
+// with wave-uniform loads; part[seg nq + k] = -rho_inv sum s/r - sum D.(x-y)/r^3
+// over the segment.  k_reac_sum adds the segments in order, the near
+// corrections and the sign.
+__global__ __launch_bounds__(64) void k_reac_part(int64_t nq, const double* __restrict__ qxyz, int64_t s0,
+                                                  int64_t s1, int nseg, const double* __restrict__ src,
+                                                  double rho_inv, double* __restrict__ part) {
+  const int64_t k = blockIdx.x * (int64_t)64 + threadIdx.x;
+  const int seg = blockIdx.y;
+  const int64_t len = (s1 - s0 + nseg - 1) / nseg;
+  const int64_t j0 = s0 + seg * len, j1 = min(s1, j0 + len);
+  const int64_t kk = k < nq ? k : nq - 1;
+  const double x = qxyz[3 * kk], y = qxyz[3 * kk + 1], z = qxyz[3 * kk + 2];
   double a1 = 0.0, a2 = 0.0;
-  for (int64_t j = s0 + threadIdx.x; j < s1; j += blockDim.x) {
+  for (int64_t j = j0; j < j1; ++j) {
     const double* s = src + (int64_t)kSrcStride * j;
     const double dx = x - s[0], dy = y - s[1], dz = z - s[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -251,15 +257,25 @@ __global__ __launch_bounds__(256) void k_reac(int64_t nq, const double* __restri
     a1 += s[3] * rinv;
     a2 += dd * rinv * rinv * rinv;
   }
-  double l = (-rho_inv * a1 - a2) * kInv4Pi;
-  for (int64_t e = near_ptr[k] + threadIdx.x; e < near_ptr[k + 1]; e += blockDim.x) {
+  if (k < nq) part[(int64_t)seg * nq + k] = -rho_inv * a1 - a2;
+}
+
+__global__ __launch_bounds__(256) void k_reac_sum(int64_t nq, int nseg, const double* __restrict__ part,
+                                                  const int64_t* __restrict__ near_ptr,
+                                                  const int32_t* __restrict__ near_col,
+                                                  const double* __restrict__ near_val,
+                                                  const double* __restrict__ sig, const double* __restrict__ mu,
+                                                  double* phi) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nq) return;
+  double f = 0.0;
+  for (int g = 0; g < nseg; ++g) f += part[(int64_t)g * nq + k];
+  double l = f * kInv4Pi;
+  for (int64_t e = near_ptr[k]; e < near_ptr[k + 1]; ++e) {
     const int32_t j = near_col[e];
     l += near_val[4 * e] * sig[j] + near_val[4 * e + 1] * mu[j];
   }
-  for (int o = 32; o > 0; o >>= 1) l += __shfl_down(l, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
-  __syncthreads();
-  if (threadIdx.x == 0) phi[k] = -(red[0] + red[1] + red[2] + red[3]);
+  phi[k] = -l;
 }
 
 // A cavity's part of the reaction potential at the charges of its molecule:
@@ -311,10 +327,16 @@ void launch_reac_cavity(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, 
 void launch_reac(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
                  double rho_inv, const int64_t* near_ptr, const int32_t* near_col,
                  const double* near_val, const double* sig, const double* mu, double* phi,
-                 hipStream_t s) {
+                 double* part, hipStream_t s) {
   if (nq <= 0) return;
-  k_reac<<<(unsigned)nq, 256, 0, s>>>(nq, qxyz, s0, s1, src, rho_inv, near_ptr, near_col, near_val,
-                                       sig, mu, phi);
+  // enough wavefronts to fill the machine, segments of at least 256 sources
+  const int64_t ntile = (nq + 63) / 64;
+  const int64_t want = std::max<int64_t>(1, 4096 / ntile);
+  const int nseg = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kReacMaxSeg, want, (s1 - s0 + 255) / 256}));
+  k_reac_part<<<dim3((unsigned)ntile, (unsigned)nseg), 64, 0, s>>>(nq, qxyz, s0, s1, nseg, src, rho_inv, part);
+  PBT_HIP(hipGetLastError());
+  k_reac_sum<<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(nq, nseg, part, near_ptr, near_col, near_val, sig, mu,
+                                                            phi);
   PBT_HIP(hipGetLastError());
 }
 

@@ -122,10 +122,12 @@ void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, con
 void launch_reac_cavity(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
                         const int64_t* near_ptr, const int32_t* near_col, const double* near_val,
                         const double* sig, const double* mu, double* phi, hipStream_t s);
+// part: scratch of kReacMaxSeg nq doubles.
+constexpr int kReacMaxSeg = 64;
 void launch_reac(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
                  double rho_inv, const int64_t* near_ptr, const int32_t* near_col,
                  const double* near_val, const double* sig, const double* mu, double* phi,
-                 hipStream_t s);
+                 double* part, hipStream_t s);
 void launch_coulomb_rhs(int64_t n, const double* tx, const int32_t* rows, int64_t nq,
                         const double* qxyz, const double* q, double inv_eps, double* b,
                         hipStream_t s);
@@ -217,10 +219,11 @@ void launch_moments(int P, int nblocks, const int32_t* mblocks, const MomChunk* 
 // Moments of boxes from their leaves' (M2M): pairs[3 i] = (box, leaf,
 // slot) shift the leaf's moments to the box's centre into slot (2 ncoef(P)
 // values each), then heads[3 h] = (box, first slot, count) add a box's slots
-// in order into its moments.
+// in order into its moments; the first nsmall heads have count <= kM2MSmall.
+constexpr int kM2MSmall = 32;
 template <typename T>
-void launch_m2m(int P, int npairs, const int32_t* pairs, int nheads, const int32_t* heads, const double* bcen,
-                T* slots, T* mom, hipStream_t s);
+void launch_m2m(int P, int npairs, const int32_t* pairs, int nheads, int nsmall, const int32_t* heads,
+                const double* bcen, T* slots, T* mom, hipStream_t s);
 // M2P and P2P tasks in one launch (taylor.hip).
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,

@@ -455,6 +455,21 @@ void System::build(hipStream_t s) {
     nhead_ = (int)hd.size() / 3;
     npair_known_ = (int)prk.size() / 3;
     nhead_known_ = (int)hdk.size() / 3;
+    // heads of at most kM2MSmall leaves first (the sum takes them a thread
+    // per value), keeping the box order within each class
+    auto small_first = [](std::vector<int32_t>& h) {
+      std::vector<int32_t> a, b;
+      for (size_t i = 0; i < h.size(); i += 3) {
+        std::vector<int32_t>& to = h[i + 2] <= kM2MSmall ? a : b;
+        to.insert(to.end(), {h[i], h[i + 1], h[i + 2]});
+      }
+      const int ns = (int)a.size() / 3;
+      a.insert(a.end(), b.begin(), b.end());
+      h.swap(a);
+      return ns;
+    };
+    nhead_small_ = small_first(hd);
+    nhead_small_known_ = small_first(hdk);
     for (auto* v : {&pr, &hd, &prk, &hdk})
       if (v->empty()) v->assign(3, 0);
     m2m_pairs_.upload(pr, s);
@@ -1024,11 +1039,12 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   // M2M after the leaves' moments (P2M): every (box, leaf) shift, then the
   // sums per box
   const int npr = known_only ? npair_known_ : npair_, nhd = known_only ? nhead_known_ : nhead_;
+  const int nhs = known_only ? nhead_small_known_ : nhead_small_;
   const int32_t* m2m_pr = known_only ? m2m_pairs_known_.p : m2m_pairs_.p;
   const int32_t* m2m_hd = known_only ? m2m_heads_known_.p : m2m_heads_.p;
   T* mslot = f32 ? (T*)mslot32_.p : (T*)mslot64_.p;
   auto m2m = [&](hipStream_t fs) {
-    launch_m2m<T>(prm_.taylor_p, npr, m2m_pr, nhd, m2m_hd, bcen_.p, mslot, mom, fs);
+    launch_m2m<T>(prm_.taylor_p, npr, m2m_pr, nhd, nhs, m2m_hd, bcen_.p, mslot, mom, fs);
   };
   auto moments = [&](hipStream_t fs) {
     const int e0 = pb(fs);
@@ -1298,6 +1314,7 @@ System::ChargeData& System::charges(int e, hipStream_t s) {
   d.qx.upload(S.qxyz, s);
   d.q.upload(S.q, s);
   d.phi.alloc(nq);
+  d.reac_part.alloc((size_t)nq * kReacMaxSeg);
   if (nq > 0) charge_near(e, e, d.qx.p, nq, d.qn, s);
   // near corrections of the charges against each cavity of the molecule
   d.cav.clear();
@@ -1785,7 +1802,7 @@ std::vector<std::array<double, 3>> System::surface_energies(const double* x, hip
     if (nq == 0) continue;
     ChargeData& d = charges(e, s);
     launch_reac(nq, d.qx.p, poff_[e] * K_, (poff_[e] + S.nt) * K_, src64_.p, eps_o_[e] / S.eps_in, d.qn.ptr.p,
-                d.qn.col.p, d.qn.val.p, sig_.p + poff_[e], mu_.p + poff_[e], d.phi.p, s);
+                d.qn.col.p, d.qn.val.p, sig_.p + poff_[e], mu_.p + poff_[e], d.phi.p, d.reac_part.p, s);
     for (size_t k = 0; k < d.cav.size(); ++k) {
       const int c = d.cav[k];
       const NearCSR& cq = *d.cav_qn[k];

@@ -286,6 +286,7 @@ class System {
   struct ChargeData {
     uint64_t version = ~0ull;
     DBuf<double> qx, q, phi;
+    DBuf<double> reac_part;   // per-segment partial sums of the reaction potential
     NearCSR qn;           // near corrections charge <- molecule panel
     std::vector<int> cav;                            // the molecule's cavities
     std::vector<std::unique_ptr<NearCSR>> cav_qn;    // near corrections charge <- cavity panel
@@ -367,6 +368,7 @@ class System {
   // box; the same for the boxes of charged / potential surfaces; slots of
   // 2 ncoef(P) shifted moments
   int npair_ = 0, nhead_ = 0, npair_known_ = 0, nhead_known_ = 0;
+  int nhead_small_ = 0, nhead_small_known_ = 0;   // heads of at most kM2MSmall leaves (listed first)
   DBuf<int32_t> m2m_pairs_, m2m_heads_, m2m_pairs_known_, m2m_heads_known_;
   DBuf<float> mslot32_;
   DBuf<double> mslot64_;

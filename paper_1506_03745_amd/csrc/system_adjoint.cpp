@@ -51,7 +51,7 @@ std::vector<double> System::reaction_potential(int e, hipStream_t s) {
   const int64_t p0 = poff_[e];
   ChargeData& d = charges(e, s);
   launch_reac(nq, d.qx.p, p0 * K_, (p0 + S.nt) * K_, src64_.p, eps_o_[e] / S.eps_in, d.qn.ptr.p, d.qn.col.p,
-              d.qn.val.p, sig_.p + p0, mu_.p + p0, d.phi.p, s);
+              d.qn.val.p, sig_.p + p0, mu_.p + p0, d.phi.p, d.reac_part.p, s);
   for (size_t k = 0; k < d.cav.size(); ++k) {
     const int c = d.cav[k];
     const NearCSR& cq = *d.cav_qn[k];

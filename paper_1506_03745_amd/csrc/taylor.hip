@@ -22,6 +22,8 @@
 // Moments are kept per box in two rows: row 0 for the solvent (Yukawa) row,
 // M_Y = M_s + M_D, and row 1 for a molecule's interior (Laplace) row,
 // M_L = -(eps_out/eps_s) M_s - M_D, so that both rows are a plain sum a_k M_k.
+#include <type_traits>
+
 #include "pbt_internal.h"
 
 namespace pbt {
@@ -209,89 +211,120 @@ __global__ __launch_bounds__(256) void k_moments_sum(const MomChunk* __restrict_
 // rows   M_k(c) = sum_leaves sum_{l <= k} C(k, l) d^(k - l) M_l(c').
 // Every leaf under a box is shifted straight to the box (no level-by-level
 // chain, so all shifts run in one launch); the multi-index sum factorises
-// into three one-dimensional ones, taken as passes x, y, z of at most P + 1
-// terms: (a, b, c) <- sum_{a' <= a} C(a, a') dx^(a - a') (a', b, c), and so
-// on (a' <= a keeps |(a', b, c)| <= P).  One wavefront per (box, leaf) pair,
-// the leaf's moments, the powers of the shift and the binomials in LDS; the
-// result goes to the pair's slot, and a second launch adds each box's slots
-// in leaf order.
-constexpr int kM2MThreads = 64;
-
-template <typename T, int P>
-__global__ __launch_bounds__(kM2MThreads) void k_m2m_shift(const int32_t* __restrict__ pairs,
-                                                           const double* __restrict__ bcen,
-                                                           const T* __restrict__ mom, T* __restrict__ slots) {
-  constexpr int NC = ncoef(P);
-  constexpr int NO = 2 * NC;   // outputs: (row, k)
-  __shared__ T sa[NO];
-  __shared__ T sb[NO];
-  __shared__ T sp[3][P + 1];
-  __shared__ T sbin[P + 1][P + 1];
-  __shared__ int8_t sk[NC][3];
-  const int b = pairs[3 * blockIdx.x], leaf = pairs[3 * blockIdx.x + 1], slot = pairs[3 * blockIdx.x + 2];
-  for (int i = threadIdx.x; i < NO; i += kM2MThreads) sa[i] = mom[(int64_t)(2 * leaf) * NC + i];
-  if (threadIdx.x < 3) {
-    const int d = threadIdx.x;
-    const T dd = (T)(bcen[3 * leaf + d] - bcen[3 * b + d]);
-    T pw = T(1);
-    for (int e = 0; e <= P; ++e) {
-      sp[d][e] = pw;
-      pw *= dd;
-    }
-  }
-  for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += kM2MThreads) {
-    const int n = i / (P + 1), k = i - n * (P + 1);
-    double v = 0.0;
-    if (k <= n) {
-      v = 1.0;
-      for (int q = 1; q <= k; ++q) v = v * (n - k + q) / q;
-    }
-    sbin[n][k] = (T)v;
-  }
-  for (int k = threadIdx.x; k < NC; k += kM2MThreads) {
-    sk[k][0] = (int8_t)midx_a(k);
-    sk[k][1] = (int8_t)midx_b(k);
-    sk[k][2] = (int8_t)midx_c(k);
-  }
-  __syncthreads();
-  // pass along dimension D: dst(k) = sum_{e <= k_D} C(k_D, e) d_D^(k_D - e) src(k with k_D = e)
-  auto pass = [&](const T* src, T* dst, int D) {
-    for (int o = threadIdx.x; o < NO; o += kM2MThreads) {
-      const int row = o >= NC ? NC : 0, k = o - row;
-      int q[3] = {sk[k][0], sk[k][1], sk[k][2]};
-      const int top = q[D];
-      T acc = T(0);
-      for (int e = 0; e <= top; ++e) {
-        q[D] = e;
-        acc += sbin[top][e] * sp[D][top - e] * src[row + tidx(q[0], q[1], q[2])];
-      }
-      dst[o] = acc;
-    }
-    __syncthreads();
-  };
-  pass(sa, sb, 0);
-  pass(sb, sa, 1);
-  pass(sa, sb, 2);
-  for (int o = threadIdx.x; o < NO; o += kM2MThreads) slots[(int64_t)slot * NO + o] = sb[o];
+// into three one-dimensional Taylor shifts, along x, y and z in turn: on each
+// line of coefficients that differ only in that component (e = 0..L),
+// new(t) = sum_{e <= t} C(t, e) d^(t - e) old(e), done in place for t from L
+// down.  One thread per (pair, row) holds the row's coefficients in
+// registers (every index a compile-time constant); the result goes to the
+// pair's slot, and a second launch adds each box's slots in leaf order.
+__host__ __device__ constexpr int binom(int n, int k) {
+  int v = 1;
+  for (int q = 1; q <= k; ++q) v = v * (n - k + q) / q;
+  return v;
 }
 
-// Each box's shifted leaf moments added up: block (box, 8 outputs), 32
-// lanes per output each over every 32nd leaf slot in order, then a fixed
-// butterfly over the 32 (the same partition and order on every launch).
+template <int D>
+__host__ __device__ constexpr int line_idx(int e, int u, int v) {
+  return D == 0 ? tidx(e, u, v) : D == 1 ? tidx(u, e, v) : tidx(u, v, e);
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+template <typename T, int P, int D>
+__device__ __forceinline__ void shift_pass(T* m, T d) {
+  T pw[P + 1];
+  pw[0] = T(1);
+#pragma unroll
+  for (int e = 1; e <= P; ++e) pw[e] = pw[e - 1] * d;
+  static_for<0, P + 1>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    static_for<0, P + 1 - u>([&](auto V) {
+      constexpr int v = decltype(V)::value;
+      constexpr int L = P - u - v;
+      // t from L down to 1
+      static_for<0, L>([&](auto Q) {
+        constexpr int t = L - decltype(Q)::value;
+        T acc = m[line_idx<D>(t, u, v)];
+        static_for<0, t>([&](auto E) {
+          constexpr int e = decltype(E)::value;
+          acc += (T(binom(t, e)) * pw[t - e]) * m[line_idx<D>(e, u, v)];
+        });
+        m[line_idx<D>(t, u, v)] = acc;
+      });
+    });
+  });
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_m2m_shift(int npairs, const int32_t* __restrict__ pairs,
+                                                   const double* __restrict__ bcen,
+                                                   const T* __restrict__ mom, T* __restrict__ slots) {
+  constexpr int NC = ncoef(P);
+  const int t = blockIdx.x * 256 + (int)threadIdx.x;
+  if (t >= 2 * npairs) return;
+  const int pr = t >> 1, row = t & 1;
+  const int b = pairs[3 * pr], leaf = pairs[3 * pr + 1], slot = pairs[3 * pr + 2];
+  const T* in = mom + (int64_t)(2 * leaf + row) * NC;
+  T m[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) m[k] = in[k];
+  shift_pass<T, P, 0>(m, (T)(bcen[3 * leaf] - bcen[3 * b]));
+  shift_pass<T, P, 1>(m, (T)(bcen[3 * leaf + 1] - bcen[3 * b + 1]));
+  shift_pass<T, P, 2>(m, (T)(bcen[3 * leaf + 2] - bcen[3 * b + 2]));
+  T* out = slots + ((int64_t)slot * 2 + row) * NC;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) out[k] = m[k];
+}
+
+// Per box, its n slots added up.  Boxes of at most kM2MSmall leaves (heads
+// listed first): one block per box, a thread per output value, its slots
+// loaded in batches of 8 so that the loads are in flight together, and
+// added in slot order.  The others: a wavefront per output value, lane l
+// adding slots l, l + 64, ... (in batches of 8 loads), then a fixed xor
+// butterfly over the 64 lanes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2m_sum_small(int NO, const int32_t* __restrict__ heads,
+                                                       const T* __restrict__ slots, T* __restrict__ mom) {
+  const int b = heads[3 * blockIdx.x], s0 = heads[3 * blockIdx.x + 1], n = heads[3 * blockIdx.x + 2];
+  for (int o = threadIdx.x; o < NO; o += 256) {
+    const T* p = slots + (int64_t)s0 * NO + o;
+    T acc = T(0);
+    for (int i0 = 0; i0 < n; i0 += 8) {
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = i0 + q < n ? p[(int64_t)(i0 + q) * NO] : T(0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += v[q];
+    }
+    mom[(int64_t)b * NO + o] = acc;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_m2m_sum(int NO, const int32_t* __restrict__ heads,
                                                  const T* __restrict__ slots, T* __restrict__ mom) {
   const int b = heads[3 * blockIdx.x], s0 = heads[3 * blockIdx.x + 1], n = heads[3 * blockIdx.x + 2];
-  const int o = blockIdx.y * 8 + (threadIdx.x >> 5), lane = threadIdx.x & 31;
+  const int o = blockIdx.y * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (o >= NO) return;   // whole wavefronts
+  const T* p = slots + (int64_t)s0 * NO + o;
   T acc = T(0);
-  if (o < NO)
-    for (int i = lane; i < n; i += 32) acc += slots[(int64_t)(s0 + i) * NO + o];
-  acc += __shfl_xor(acc, 16, 32);
-  acc += __shfl_xor(acc, 8, 32);
-  acc += __shfl_xor(acc, 4, 32);
-  acc += __shfl_xor(acc, 2, 32);
-  acc += __shfl_xor(acc, 1, 32);
-  if (o < NO && lane == 0) mom[(int64_t)b * NO + o] = acc;
+  for (int i0 = lane; i0 < n; i0 += 8 * 64) {
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = i0 + 64 * q < n ? p[(int64_t)(i0 + 64 * q) * NO] : T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += v[q];
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if (lane == 0) mom[(int64_t)b * NO + o] = acc;
 }
 
 // ---- M2P -------------------------------------------------------------------
@@ -350,14 +383,26 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
       for (int b = n - a; b >= 0; --b) {
         const int c = n - a - b;
         const int k = tidx(a, b, c);
-        T S1 = 0, S2 = 0, T1 = 0, T2 = 0;
-        bool h2 = false;
-        if (a >= 1) { S1 += ux * A[tidx(a - 1, b, c)]; if (YUK) T1 += vx * B[tidx(a - 1, b, c)]; }
-        if (b >= 1) { S1 += uy * A[tidx(a, b - 1, c)]; if (YUK) T1 += vy * B[tidx(a, b - 1, c)]; }
-        if (c >= 1) { S1 += uz * A[tidx(a, b, c - 1)]; if (YUK) T1 += vz * B[tidx(a, b, c - 1)]; }
-        if (a >= 2) { S2 += A[tidx(a - 2, b, c)]; if (YUK) T2 += B[tidx(a - 2, b, c)]; h2 = true; }
-        if (b >= 2) { S2 += A[tidx(a, b - 2, c)]; if (YUK) T2 += B[tidx(a, b - 2, c)]; h2 = true; }
-        if (c >= 2) { S2 += A[tidx(a, b, c - 2)]; if (YUK) T2 += B[tidx(a, b, c - 2)]; h2 = true; }
+        // each sum starts from its first term (no zero start: x * y + 0 is
+        // an instruction of its own unless the compiler may drop the +0)
+        T S1, S2, T1, T2;
+        bool h1 = false, h2 = false;
+        auto first = [&](T u, T v, int i) {
+          if (!h1) { S1 = u * A[i]; if (YUK) T1 = v * B[i]; }
+          else { S1 += u * A[i]; if (YUK) T1 += v * B[i]; }
+          h1 = true;
+        };
+        auto second = [&](int i) {
+          if (!h2) { S2 = A[i]; if (YUK) T2 = B[i]; }
+          else { S2 += A[i]; if (YUK) T2 += B[i]; }
+          h2 = true;
+        };
+        if (a >= 1) first(ux, vx, tidx(a - 1, b, c));
+        if (b >= 1) first(uy, vy, tidx(a, b - 1, c));
+        if (c >= 1) first(uz, vz, tidx(a, b, c - 1));
+        if (a >= 2) second(tidx(a - 2, b, c));
+        if (b >= 2) second(tidx(a, b - 2, c));
+        if (c >= 2) second(tidx(a, b, c - 2));
         if (YUK) {
           A[k] = h2 ? (S1 + T1) - c2 * S2 - c3 * T2 : S1 + T1;
           if (n < P) B[k] = h2 ? e4 * S1 - c4 * S2 : e4 * S1;
@@ -398,14 +443,22 @@ __device__ __forceinline__ void taylor_dot_two(T Rx, T Ry, T Rz, const T* __rest
       for (int b = n - a; b >= 0; --b) {
         const int c = n - a - b;
         const int k = tidx(a, b, c);
-        T S1 = 0, S2 = 0;
-        bool h2 = false;
-        if (a >= 1) S1 += ux * A[tidx(a - 1, b, c)];
-        if (b >= 1) S1 += uy * A[tidx(a, b - 1, c)];
-        if (c >= 1) S1 += uz * A[tidx(a, b, c - 1)];
-        if (a >= 2) { S2 += A[tidx(a - 2, b, c)]; h2 = true; }
-        if (b >= 2) { S2 += A[tidx(a, b - 2, c)]; h2 = true; }
-        if (c >= 2) { S2 += A[tidx(a, b, c - 2)]; h2 = true; }
+        T S1, S2;
+        bool h1 = false, h2 = false;
+        auto first = [&](T u, int i) {
+          S1 = h1 ? S1 + u * A[i] : u * A[i];
+          h1 = true;
+        };
+        auto second = [&](int i) {
+          S2 = h2 ? S2 + A[i] : A[i];
+          h2 = true;
+        };
+        if (a >= 1) first(ux, tidx(a - 1, b, c));
+        if (b >= 1) first(uy, tidx(a, b - 1, c));
+        if (c >= 1) first(uz, tidx(a, b, c - 1));
+        if (a >= 2) second(tidx(a - 2, b, c));
+        if (b >= 2) second(tidx(a, b - 2, c));
+        if (c >= 2) second(tidx(a, b, c - 2));
         A[k] = h2 ? S1 - c2 * S2 : S1;
         a0 += A[k] * Mn[k];
         a1 += A[k] * Mn[NC + k];
@@ -582,19 +635,27 @@ void launch_p2p_moments(int P, int nblocks, const int32_t* mblocks, const MomChu
 }
 
 template <typename T>
-void launch_m2m(int P, int npairs, const int32_t* pairs, int nheads, const int32_t* heads, const double* bcen,
-                T* slots, T* mom, hipStream_t s) {
+void launch_m2m(int P, int npairs, const int32_t* pairs, int nheads, int nsmall, const int32_t* heads,
+                const double* bcen, T* slots, T* mom, hipStream_t s) {
   if (nheads <= 0) return;
+  const unsigned blocks = (unsigned)((2 * (int64_t)npairs + 255) / 256);
   switch (P) {
 #define PBT_CASE(PP) \
-  case PP: k_m2m_shift<T, PP><<<npairs, kM2MThreads, 0, s>>>(pairs, bcen, mom, slots); break;
+  case PP: k_m2m_shift<T, PP><<<blocks, 256, 0, s>>>(npairs, pairs, bcen, mom, slots); break;
     PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
 #undef PBT_CASE
     default: throw Error(1, "Taylor order P must be 0..8");
   }
   PBT_HIP(hipGetLastError());
-  k_m2m_sum<T><<<dim3(nheads, (2 * ncoef(P) + 7) / 8), 256, 0, s>>>(2 * ncoef(P), heads, slots, mom);
-  PBT_HIP(hipGetLastError());
+  const int NO = 2 * ncoef(P);
+  if (nsmall > 0) {
+    k_m2m_sum_small<T><<<nsmall, 256, 0, s>>>(NO, heads, slots, mom);
+    PBT_HIP(hipGetLastError());
+  }
+  if (nheads > nsmall) {
+    k_m2m_sum<T><<<dim3(nheads - nsmall, (NO + 3) / 4), 256, 0, s>>>(NO, heads + 3 * (int64_t)nsmall, slots, mom);
+    PBT_HIP(hipGetLastError());
+  }
 }
 
 template <typename T, int P>
@@ -680,9 +741,9 @@ template void launch_m2p_p2p<float>(int, const Task*, int, const int32_t*, const
 template void launch_m2p_p2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
                                      const Task*, int, const int32_t*, const double*, const double*, double, bool,
                                      double*, double*, hipStream_t);
-template void launch_m2m<float>(int, int, const int32_t*, int, const int32_t*, const double*, float*, float*,
+template void launch_m2m<float>(int, int, const int32_t*, int, int, const int32_t*, const double*, float*, float*,
                                 hipStream_t);
-template void launch_m2m<double>(int, int, const int32_t*, int, const int32_t*, const double*, double*, double*,
+template void launch_m2m<double>(int, int, const int32_t*, int, int, const int32_t*, const double*, double*, double*,
                                  hipStream_t);
 template void launch_m2p<float>(int, const Task*, int, const int32_t*, const float*, const double*,
                                 const float*, float, float*, hipStream_t);
