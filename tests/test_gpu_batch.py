@@ -107,3 +107,31 @@ def test_batch_with_stern_layer_and_cavity():
         sb.close()
     f_or, e_all, _ = interaction_energy(placed(pr, R[1], t[1]))
     assert abs(f_batch[1] - f_or) <= 1e-6 * (abs(e_all.F_solv) + abs(e_all.F_surf))
+
+
+def test_orientation_sweep_file_matches_one_batch(tmp_path):
+    """The sweep driver (chunks of 2, one JSON line per placement, then a
+    resumed call with nothing left) against one pbt_solve_batch of all five
+    placements: each placement is its own system solved to tol 1e-10, so the
+    chunking changes F_int only at the solver's tolerance (1e-7 of
+    |F_solv| + |F_surf| of one placement)."""
+    import json
+
+    from paper_1506_03745_amd.sweep import orientation_sweep
+    pr = body_problem()
+    nb = 5
+    R, t = placements(nb)
+    s, ids = from_problem(pr, treecode=0, tol=1e-10)
+    f_all = s.solve_batch(ids[0], R.reshape(nb, 9), t)
+    path = tmp_path / "sweep.jsonl"
+    f_sw = orientation_sweep(s, ids[0], R.reshape(nb, 9), t, str(path), chunk=2)
+    s0, _ = from_problem(placed(pr, R[0], t[0]), treecode=0, tol=1e-10)
+    _, res = s0.interaction_energy(2)
+    s0.close()
+    scale = abs(res[0].F_solv) + abs(res[0].F_surf)
+    assert np.max(np.abs(f_sw - f_all)) <= 1e-7 * scale
+    recs = [json.loads(x) for x in path.read_text().splitlines()]
+    assert sorted(r["index"] for r in recs) == list(range(nb))
+    assert all(r["chunk_rel_resid"] <= 1e-10 for r in recs)
+    np.testing.assert_array_equal(orientation_sweep(s, ids[0], R.reshape(nb, 9), t, str(path)), f_sw)
+    s.close()
