@@ -338,8 +338,8 @@ pbt_status pbt_get_schedule(pbt_ctx* ctx, int32_t* mode);
  * chosen it): out[0] = Gauss points per P2P task segment, out[1] = boxes per
  * M2P task, out[2] = work-items of a stand-alone P2P launch (wavefronts of
  * two half-wave tasks, 256-thread blocks, a multiple of 8 blocks), out[3] =
- * work-items of a stand-alone M2P launch (one wavefront per task, the same
- * blocks).  out: 4 int64 (host).  Host-only. */
+ * work-items of a stand-alone M2P launch (likewise wavefronts of two half-wave
+ * tasks, the same blocks).  out: 4 int64 (host).  Host-only. */
 pbt_status pbt_get_launch_shape(pbt_ctx* ctx, int64_t* out);
 
 /* Orthogonalisation of the GMRES solver (Section 3.2 solves with GMRES) for

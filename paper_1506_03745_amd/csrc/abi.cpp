@@ -1083,7 +1083,7 @@ pbt_status pbt_get_launch_shape(pbt_ctx* c, int64_t* out) {
   if (!c || !out) return PBT_E_INVALID;
   return guarded(c, [&] {
     System& S = system_for(c);
-    const int64_t npairs = (int64_t)S.plan().p2p.size() / 2, nm2p = (int64_t)S.plan().m2p.size();
+    const int64_t npairs = (int64_t)S.plan().p2p.size() / 2, nm2p = (int64_t)S.plan().m2p.size() / 2;
     out[0] = S.seg_src();
     out[1] = S.seg_box();
     out[2] = ((npairs + 3) / 4 + 7) / 8 * 8 * 256;

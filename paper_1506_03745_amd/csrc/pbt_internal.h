@@ -29,9 +29,9 @@ struct Error : std::runtime_error {
 // partial (L, Y) sums for its lanes into partial slot `slot`.
 // ---------------------------------------------------------------------------
 // A work item of the interaction kernels: targets tbeg .. tbeg+tcount-1
-// against the source ranges (P2P) or boxes (M2P) lbeg .. lend-1.  An M2P
-// task holds up to 64 targets (one per lane); a P2P task up to 32 (half a
-// wavefront: P2P tasks come in pairs, one per half).
+// against the source ranges (P2P) or boxes (M2P) lbeg .. lend-1.  A task
+// holds up to 32 targets, half a wavefront: tasks come in pairs, one per
+// half, each writing slot `slot` of the half-wave partials [slot][32][2].
 struct Task {
   int32_t tbeg;    // first target (internal order)
   int32_t tcount;  // 0..64 (M2P), 0..32 (P2P; 0 = an empty half)
@@ -57,8 +57,9 @@ struct Task {
 // stores the pair in the opposite rows (outside sum to the interior row).
 constexpr int kFormKz = 1, kFormSwap = 2, kFormDropOut = 4;
 
-// Per 64-target chunk: its M2P slots [sbeg, send) (64 lanes each) and, per
-// half (targets 0..31 and 32..63), its P2P slots [hbeg, hend) (32 lanes).
+// Per 64-target chunk: per half (targets 0..31 and 32..63), the half-wave
+// slots [hbeg, hend) of its P2P and M2P tasks; [sbeg, send), slots of 64
+// lanes, is empty in the forward plan (the transpose plan uses it).
 struct ChunkSlots {
   int32_t tbeg, tcount, sbeg, send;
   int32_t hbeg0, hend0, hbeg1, hend1;
@@ -224,11 +225,13 @@ constexpr int kM2MSmall = 32;
 template <typename T>
 void launch_m2m(int P, int npairs, const int32_t* pairs, int nheads, int nsmall, const int32_t* heads,
                 const double* bcen, T* slots, T* mom, hipStream_t s);
+// M2P half tasks (ntasks / nm2p of them, consecutive pairs sharing a
+// wavefront) write the half-wave partials [slot][32][2], like P2P.
 // M2P and P2P tasks in one launch (taylor.hip).
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
                     const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
-                    bool guard, T* partial, T* ppartial, hipStream_t s);
+                    bool guard, T* ppartial, hipStream_t s);
 template <typename T>
 void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
                 const double* box_center, const T* mom, T kappa, T* partial, hipStream_t s);

@@ -539,9 +539,10 @@ void System::build(hipStream_t s) {
 
 // Host-side bounds check of the work lists before any kernel reads them:
 // every task's targets, source ranges, boxes and partial slot lie inside
-// their arrays, the two halves of a P2P wavefront agree on their kind, and
-// every partial slot a chunk's combine reads is written by exactly one task
-// (so no product reads a slot that it did not write).  Throws on violation.
+// their arrays, the two halves of a P2P or M2P wavefront agree on their
+// kind, and every partial slot a chunk's combine reads is written by exactly
+// one task (so no product reads a slot that it did not write).  Throws on
+// violation.
 void System::check_plan() const {
   const Plan& P = plan_;
   auto bad = [](const std::string& m) { throw Error(PBT_E_STATE, "work list check: " + m); };
@@ -551,9 +552,10 @@ void System::check_plan() const {
       bad("source range out of bounds");
   for (int32_t b : P.blist)
     if (b < 0 || b >= nbox_) bad("box index out of bounds");
+  // every half-wave slot is written by exactly one task, P2P or M2P
+  std::vector<int32_t> written(std::max(P.npslots, 0), 0);
   auto check_p2p = [&](const std::vector<Task>& L, bool cover) {
     if (L.size() % 2) bad("odd number of P2P half tasks");
-    std::vector<int32_t> written(cover ? std::max(P.npslots, 0) : 0, 0);
     for (size_t w = 0; w < L.size(); ++w) {
       const Task& t = L[w];
       const Task& o = L[w ^ 1];
@@ -569,33 +571,33 @@ void System::check_plan() const {
       if (t.slot < 0 || t.slot >= P.npslots) bad("P2P slot out of bounds");
       if (cover && ++written[t.slot] != 1) bad("P2P slot written twice");
     }
-    if (cover)
-      for (int32_t v : written)
-        if (v != 1) bad("P2P slot never written");
   };
-  check_p2p(P.p2p, true);
-  check_p2p(P.p2p_known, false);
   auto check_m2p = [&](const std::vector<Task>& L, bool cover) {
-    std::vector<int32_t> written(cover ? std::max(P.nslots, 0) : 0, 0);
-    for (const Task& t : L) {
-      if (t.tcount < 1 || t.tcount > 64) bad("M2P target count");
-      if (t.tbeg < 0 || (int64_t)t.tbeg + t.tcount > np_) bad("M2P targets out of bounds");
+    if (L.size() % 2) bad("odd number of M2P half tasks");
+    for (size_t w = 0; w < L.size(); ++w) {
+      const Task& t = L[w];
+      const Task& o = L[w ^ 1];
+      if (t.fused != o.fused || ((t.form ^ o.form) & kFormKz)) bad("M2P halves of one wave differ");
+      if (t.tcount < 0 || t.tcount > 32) bad("M2P target count");
       if (!(0 <= t.lbeg && t.lbeg <= t.lend && t.lend <= nbl)) bad("M2P box list out of bounds");
-      if (t.slot < 0 || t.slot >= P.nslots) bad("M2P slot out of bounds");
+      if (t.tcount == 0) continue;
+      if (t.tbeg < 0 || (int64_t)t.tbeg + t.tcount > np_) bad("M2P targets out of bounds");
+      if (t.slot < 0 || t.slot >= P.npslots) bad("M2P slot out of bounds");
       if (cover && ++written[t.slot] != 1) bad("M2P slot written twice");
     }
-    if (cover)
-      for (int32_t v : written)
-        if (v != 1) bad("M2P slot never written");
   };
+  check_p2p(P.p2p, true);
   check_m2p(P.m2p, true);
+  for (int32_t v : written)
+    if (v != 1) bad("partial slot never written");
+  check_p2p(P.p2p_known, false);
   check_m2p(P.m2p_known, false);
   if ((int64_t)P.chunk_of.size() != np_) bad("chunk map size");
   for (int32_t c : P.chunk_of)
     if (c < 0 || c >= (int)P.chunks.size()) bad("chunk index out of bounds");
   for (const ChunkSlots& c : P.chunks) {
     if (c.tbeg < 0 || c.tcount < 1 || c.tcount > 64 || (int64_t)c.tbeg + c.tcount > np_) bad("chunk targets");
-    if (!(0 <= c.sbeg && c.sbeg <= c.send && c.send <= P.nslots)) bad("chunk M2P slots");
+    if (c.sbeg != c.send) bad("chunk with 64-lane slots");
     if (!(0 <= c.hbeg0 && c.hbeg0 <= c.hend0 && c.hend0 <= P.npslots)) bad("chunk P2P slots (first half)");
     if (!(0 <= c.hbeg1 && c.hbeg1 <= c.hend1 && c.hend1 <= P.npslots)) bad("chunk P2P slots (second half)");
     if (c.tcount <= 32 && c.hend1 != c.hbeg1) bad("chunk without a second half has its slots");
@@ -666,20 +668,23 @@ void System::build_plan() {
   Plan& P = plan_;
   P = Plan{};
   const int ns = (int)surfs_.size();
-  // Target groups: each leaf's panels in runs of at most 64 (one chunk each,
-  // spatially compact in the leaf's octant order), every group with the
-  // sphere of its own collocation points, so the acceptance test is taken
-  // per 64 targets rather than per leaf (Section 3.2 states it per target).
+  // Target groups: each leaf's panels in runs of at most kGroup = 32 (half a
+  // wavefront; spatially compact in the leaf's octant order), every group
+  // with the sphere of its own collocation points, so the acceptance test is
+  // taken per 32 targets rather than per leaf (Section 3.2 states it per
+  // target).  Two consecutive groups of a leaf form a 64-target chunk of the
+  // combine, one per half.
+  constexpr int kGroup = 32;
   struct LeafRef { int e; int b; TreeBox tb; };
   std::vector<LeafRef> leaves;
   for (int e = 0; e < ns; ++e)
     for (size_t b = 0; b < trees_[e].boxes.size(); ++b) {
       const TreeBox& lb = trees_[e].boxes[b];
       if (!lb.leaf) continue;
-      for (int32_t t0 = lb.pbeg; t0 < lb.pend; t0 += 64) {
+      for (int32_t t0 = lb.pbeg; t0 < lb.pend; t0 += kGroup) {
         TreeBox g = lb;
         g.pbeg = t0;
-        g.pend = std::min<int32_t>(lb.pend, t0 + 64);
+        g.pend = std::min<int32_t>(lb.pend, t0 + kGroup);
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int32_t k = g.pbeg; k < g.pend; ++k)
           for (int d = 0; d < 3; ++d) {
@@ -740,12 +745,12 @@ void System::build_plan() {
         const int32_t j0 = (int32_t)((poff_[e2] + sb.pbeg) * K_), j1 = (int32_t)((poff_[e2] + sb.pend) * K_);
         if (!o.rng.empty() && o.rng.back().second == j0) o.rng.back().second = j1;
         else o.rng.push_back({j0, j1});
-        c[0] += (int64_t)(j1 - j0) * ((nt + 63) / 64);
+        c[0] += (int64_t)(j1 - j0);
         c[2] += (int64_t)(j1 - j0) * nt;
         if (fused_pair) c[4] += (int64_t)(j1 - j0) * nt;
       }
       for (int b : mb) o.box.push_back((int32_t)(boff_[e2] + b));
-      c[1] += (int64_t)mb.size() * ((nt + 63) / 64);
+      c[1] += (int64_t)mb.size();
       c[3] += (int64_t)mb.size() * nt;
       {
         int32_t fu = 0;
@@ -766,32 +771,46 @@ void System::build_plan() {
     P.p2p_fused_pairs += c[4];
     P.m2p_fused_pairs += c[5];
   }
-  // Segment sizes: aim at several thousand wavefront tasks in each launch.
-  const int64_t want = 16384;
+  // Segment sizes: aim at several thousand wavefront tasks (two half tasks
+  // each) in each launch.
+  const int64_t want = 2 * 16384;
   const int64_t seg_src = seg_src_ > 0 ? seg_src_ : std::min<int64_t>(16384, std::max<int64_t>(256, tot_src / want));
   const int64_t seg_box = seg_box_ > 0 ? seg_box_ : std::min<int64_t>(64, std::max<int64_t>(2, tot_box / want));
   seg_src_used_ = seg_src;
   seg_box_used_ = seg_box;
 
-  // Chunks (numbered per group too, for the Gram-Schmidt partials).
-  std::vector<int> leaf_chunk0(leaves.size());
+  // Chunks (numbered per group of surfaces too, for the Gram-Schmidt
+  // partials): a group that starts a 64-target run of its leaf opens a chunk
+  // (its first half), the next group of the same leaf is the second half.
+  std::vector<int> chunk_of_leaf(leaves.size()), half_of_leaf(leaves.size());
   P.chunk_of.assign(np_, 0);
   std::map<int, int32_t> gchunks;
   for (size_t li = 0; li < leaves.size(); ++li) {
     const TreeBox& tl = leaves[li].tb;
-    leaf_chunk0[li] = (int)P.chunks.size();
-    const int grp = surfs_[leaves[li].e]->group;
+    const TreeBox& lb = trees_[leaves[li].e].boxes[leaves[li].b];
     const int64_t g0 = poff_[leaves[li].e] + tl.pbeg, g1 = poff_[leaves[li].e] + tl.pend;
-    for (int64_t t = g0; t < g1; t += 64) {
-      ChunkSlots c{(int32_t)t, (int32_t)std::min<int64_t>(64, g1 - t), 0, 0, 0, 0, 0, 0, grp, gchunks[grp]++};
-      for (int64_t k = t; k < t + c.tcount; ++k) P.chunk_of[k] = (int32_t)P.chunks.size();
-      P.chunks.push_back(c);
+    if ((tl.pbeg - lb.pbeg) % 64 == 0) {
+      const int grp = surfs_[leaves[li].e]->group;
+      P.chunks.push_back(ChunkSlots{(int32_t)g0, 0, 0, 0, 0, 0, 0, 0, grp, gchunks[grp]++});
+      half_of_leaf[li] = 0;
+    } else {
+      half_of_leaf[li] = 1;
     }
+    chunk_of_leaf[li] = (int)P.chunks.size() - 1;
+    ChunkSlots& c = P.chunks.back();
+    c.tcount += (int32_t)(g1 - g0);
+    for (int64_t k = g0; k < g1; ++k) P.chunk_of[k] = (int32_t)(P.chunks.size() - 1);
   }
   P.nbh = 1;
   for (const auto& kv : gchunks) P.nbh = std::max(P.nbh, (int)kv.second);
+  // Full chunks: both groups of 32 targets.
+  std::vector<char> full_first(leaves.size(), 0);
+  for (size_t li = 0; li + 1 < leaves.size(); ++li)
+    if (half_of_leaf[li] == 0 && half_of_leaf[li + 1] == 1 && leaves[li].tb.pend - leaves[li].tb.pbeg == 32 &&
+        leaves[li + 1].tb.pend - leaves[li + 1].tb.pbeg == 32)
+      full_first[li] = 1;
   // Segments per (leaf, source surface).
-  struct Seg { int32_t lbeg, lend; int e2; bool m2p; };
+  struct Seg { int32_t lbeg, lend; int e2; bool m2p; };   // e2: the source surface
   std::vector<std::vector<Seg>> segs(leaves.size());
   for (size_t li = 0; li < leaves.size(); ++li) {
     const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
@@ -814,7 +833,8 @@ void System::build_plan() {
           }
         }
       }
-      if ((int32_t)(P.ranges.size() / 2) > start) segs[li].push_back({start, (int32_t)(P.ranges.size() / 2), e2, false});
+      if ((int32_t)(P.ranges.size() / 2) > start)
+        segs[li].push_back({start, (int32_t)(P.ranges.size() / 2), e2, false});
       for (size_t k = 0; k < o.box.size(); k += seg_box) {
         const int32_t b0 = (int32_t)P.blist.size();
         for (size_t q = k; q < std::min(o.box.size(), (size_t)(k + seg_box)); ++q) P.blist.push_back(o.box[q]);
@@ -822,129 +842,139 @@ void System::build_plan() {
       }
     }
   }
-  // Slots.  Per 64-target chunk: its M2P slots (64 lanes), then per half of
-  // the chunk (targets 0..31, 32..63) its P2P slots (32 lanes, own buffer).
-  int slot = 0, pslot = 0;
-  std::vector<int> nseg_p(leaves.size(), 0), nseg_m(leaves.size(), 0);
+  // Slots: every task of a group writes one half-wave partial slot
+  // [slot][32][2]; per chunk half, the group's P2P slots then its M2P slots
+  // (a chunk's combine reads hbeg0..hend0 for its first 32 targets,
+  // hbeg1..hend1 for the others).  No 64-lane slots.
+  int pslot = 0;
+  std::vector<int> slot0(leaves.size(), 0);
   for (size_t li = 0; li < leaves.size(); ++li) {
-    for (const Seg& sg : segs[li]) (sg.m2p ? nseg_m : nseg_p)[li]++;
-    const int nchunk = (li + 1 < leaves.size() ? leaf_chunk0[li + 1] : (int)P.chunks.size()) - leaf_chunk0[li];
-    for (int c = 0; c < nchunk; ++c) {
-      ChunkSlots& cs = P.chunks[leaf_chunk0[li] + c];
-      cs.sbeg = slot;
-      slot += nseg_m[li];
-      cs.send = slot;
-      cs.hbeg0 = pslot;
-      pslot += nseg_p[li];
+    ChunkSlots& cs = P.chunks[chunk_of_leaf[li]];
+    slot0[li] = pslot;
+    pslot += (int)segs[li].size();
+    if (half_of_leaf[li] == 0) {
+      cs.hbeg0 = slot0[li];
       cs.hend0 = pslot;
       cs.hbeg1 = cs.hend1 = pslot;
-      if (cs.tcount > 32) {
-        pslot += nseg_p[li];
-        cs.hend1 = pslot;
-      }
+    } else {
+      cs.hbeg1 = slot0[li];
+      cs.hend1 = pslot;
     }
   }
-  P.nslots = slot;
+  P.nslots = 0;
   P.npslots = pslot;
-  // M2P tasks ordered by (leaf, segment, chunk).  P2P half tasks (<= 32
-  // targets) likewise; the two halves of a full chunk share a wavefront (same
-  // sources), the other halves are paired across leaves among tasks of the
-  // same kind and similar source count, so lanes are not left idle by leaves
-  // whose size is not a multiple of 64.
-  std::vector<Task> spare;
-  for (size_t li = 0; li < leaves.size(); ++li) {
+  // Half tasks of every group and segment, P2P and M2P alike.  The two
+  // halves of a full chunk (both groups of 32 targets) are put on one
+  // wavefront segment by segment for each source surface (their lists are
+  // nearly the same: same sources, balanced work); every other half is
+  // paired below with a half of the same kind.
+  auto make_task = [&](size_t li, const Seg& sg, int slot) {
     const int e = leaves[li].e;
     const bool mol = two_rows(e);
-    const int c0 = leaf_chunk0[li];
-    const int nchunk = (li + 1 < leaves.size() ? leaf_chunk0[li + 1] : (int)P.chunks.size()) - c0;
-    int mi = 0, pi = 0;
-    for (size_t si = 0; si < segs[li].size(); ++si) {
-      const Seg& sg = segs[li][si];
-      Task t{};
-      t.lbeg = sg.lbeg;
-      t.lend = sg.lend;
-      task_form(e, sg.e2, t.fused, t.form);
-      t.known = two_rows(sg.e2) ? 0 : 1;
-      t.rho_inv = mol ? eps_o_[e] / surfs_[e]->eps_in : 0.0;
-      t.rho_inv_f = (float)t.rho_inv;
-      if (sg.m2p) {
-        for (int c = 0; c < nchunk; ++c) {
-          const ChunkSlots& cs = P.chunks[c0 + c];
-          t.tbeg = cs.tbeg;
-          t.tcount = cs.tcount;
-          t.slot = cs.sbeg + mi;
-          P.m2p.push_back(t);
-        }
-        ++mi;
-        continue;
-      }
-      t.nsrc = 0;
+    Task t{};
+    t.tbeg = (int32_t)(poff_[e] + leaves[li].tb.pbeg);
+    t.tcount = leaves[li].tb.pend - leaves[li].tb.pbeg;
+    t.lbeg = sg.lbeg;
+    t.lend = sg.lend;
+    t.slot = slot;
+    task_form(e, sg.e2, t.fused, t.form);
+    t.known = two_rows(sg.e2) ? 0 : 1;
+    t.rho_inv = mol ? eps_o_[e] / surfs_[e]->eps_in : 0.0;
+    t.rho_inv_f = (float)t.rho_inv;
+    t.split = 1;
+    t.nsrc = 0;
+    if (!sg.m2p)
       for (int32_t r = sg.lbeg; r < sg.lend; ++r) t.nsrc += P.ranges[2 * r + 1] - P.ranges[2 * r];
-      for (int c = 0; c < nchunk; ++c) {
-        const ChunkSlots& cs = P.chunks[c0 + c];
-        Task h0 = t, h1 = t;
-        h0.tbeg = cs.tbeg;
-        h0.tcount = std::min(32, cs.tcount);
-        h0.slot = cs.hbeg0 + pi;
-        h1.tbeg = cs.tbeg + 32;
-        h1.tcount = cs.tcount - 32;
-        h1.slot = cs.hbeg1 + pi;
-        h0.split = h1.split = 1;
-        if (cs.tcount == 64) {
-          P.p2p.push_back(h0);
-          P.p2p.push_back(h1);
-        } else {
-          spare.push_back(h0);
-          if (h1.tcount > 0) spare.push_back(h1);
-        }
+    return t;
+  };
+  std::vector<Task> spare, mspare;
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    if (half_of_leaf[li] != 0) continue;
+    const bool pair = full_first[li] != 0;
+    if (!pair) {
+      for (int h = 0; h < 2; ++h) {
+        const size_t lj = li + h;
+        if (h == 1 && !(lj < leaves.size() && half_of_leaf[lj] == 1)) break;
+        for (size_t si = 0; si < segs[lj].size(); ++si)
+          (segs[lj][si].m2p ? mspare : spare).push_back(make_task(lj, segs[lj][si], slot0[lj] + (int)si));
       }
-      ++pi;
+      continue;
     }
+    // per source surface and kind, the k-th segment of each half together
+    const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
+    for (int e2 : gsf)
+      for (int m = 0; m < 2; ++m) {
+        std::vector<std::pair<size_t, int>> sa, sb;   // (segment index, slot)
+        for (size_t si = 0; si < segs[li].size(); ++si)
+          if (segs[li][si].e2 == e2 && segs[li][si].m2p == (m == 1)) sa.push_back({si, slot0[li] + (int)si});
+        for (size_t si = 0; si < segs[li + 1].size(); ++si)
+          if (segs[li + 1][si].e2 == e2 && segs[li + 1][si].m2p == (m == 1))
+            sb.push_back({si, slot0[li + 1] + (int)si});
+        std::vector<Task>& out = m ? P.m2p : P.p2p;
+        std::vector<Task>& rest = m ? mspare : spare;
+        const size_t k2 = std::min(sa.size(), sb.size());
+        for (size_t k = 0; k < k2; ++k) {
+          out.push_back(make_task(li, segs[li][sa[k].first], sa[k].second));
+          out.push_back(make_task(li + 1, segs[li + 1][sb[k].first], sb[k].second));
+        }
+        for (size_t k = k2; k < sa.size(); ++k) rest.push_back(make_task(li, segs[li][sa[k].first], sa[k].second));
+        for (size_t k = k2; k < sb.size(); ++k)
+          rest.push_back(make_task(li + 1, segs[li + 1][sb[k].first], sb[k].second));
+      }
   }
-  // A half of at most 8 (16) targets has its lanes in 4 (2) groups that split
-  // the sources; halves are paired with halves of the same kind and split.
-  for (Task& t : spare) t.split = t.tcount <= 8 ? 4 : t.tcount <= 16 ? 2 : 1;
+  // The other halves, paired with halves of the same kind (both halves of a
+  // wavefront agree on fused and kFormKz, for P2P also on the split; a half
+  // of at most 8 (16) targets has its lanes in 4 (2) groups that split the
+  // sources), similar work next to each other; an odd one out gets an empty
+  // partner (no targets, no sources).
   auto kz = [](const Task& t) { return (t.form & kFormKz) ? 1 : 0; };
-  std::stable_sort(spare.begin(), spare.end(), [&](const Task& a, const Task& b) {
-    if (a.fused != b.fused) return a.fused < b.fused;
-    if (kz(a) != kz(b)) return kz(a) < kz(b);
-    if (a.split != b.split) return a.split < b.split;
-    return a.nsrc > b.nsrc;
-  });
-  for (size_t k = 0; k < spare.size();) {
-    P.p2p.push_back(spare[k]);
-    if (k + 1 < spare.size() && spare[k + 1].fused == spare[k].fused && kz(spare[k + 1]) == kz(spare[k]) &&
-        spare[k + 1].split == spare[k].split) {
-      P.p2p.push_back(spare[k + 1]);
-      k += 2;
-    } else {
-      Task empty = spare[k];   // an empty half: no targets, no sources
-      empty.tcount = 0;
-      empty.lbeg = empty.lend = 0;
-      empty.nsrc = 0;
-      empty.slot = 0;
-      P.p2p.push_back(empty);
-      k += 1;
+  auto pair_up = [&](std::vector<Task>& sp, std::vector<Task>& out, bool p2p) {
+    if (p2p)
+      for (Task& t : sp) t.split = t.tcount <= 8 ? 4 : t.tcount <= 16 ? 2 : 1;
+    std::stable_sort(sp.begin(), sp.end(), [&](const Task& a, const Task& b) {
+      if (a.fused != b.fused) return a.fused < b.fused;
+      if (kz(a) != kz(b)) return kz(a) < kz(b);
+      if (a.split != b.split) return a.split < b.split;
+      return p2p ? a.nsrc > b.nsrc : a.lend - a.lbeg > b.lend - b.lbeg;
+    });
+    for (size_t k = 0; k < sp.size();) {
+      out.push_back(sp[k]);
+      if (k + 1 < sp.size() && sp[k + 1].fused == sp[k].fused && kz(sp[k + 1]) == kz(sp[k]) &&
+          sp[k + 1].split == sp[k].split) {
+        out.push_back(sp[k + 1]);
+        k += 2;
+      } else {
+        Task empty = sp[k];
+        empty.tcount = 0;
+        empty.lbeg = empty.lend = 0;
+        empty.nsrc = 0;
+        empty.slot = 0;
+        out.push_back(empty);
+        k += 1;
+      }
     }
-  }
+  };
+  pair_up(spare, P.p2p, true);
+  pair_up(mspare, P.m2p, false);
   // The right-hand side's product: only the tasks whose sources carry known
   // densities (a wavefront pair stays together, its other half emptied); the
   // partial slots of the others are cleared before that product.
-  P.p2p_known.clear();
-  for (size_t w = 0; w + 1 < P.p2p.size(); w += 2) {
-    Task a = P.p2p[w], b = P.p2p[w + 1];
-    if (!a.known && !b.known) continue;
-    for (Task* t : {&a, &b})
-      if (!t->known) {
-        t->lbeg = t->lend = 0;
-        t->nsrc = 0;
-      }
-    P.p2p_known.push_back(a);
-    P.p2p_known.push_back(b);
-  }
-  P.m2p_known.clear();
-  for (const Task& t : P.m2p)
-    if (t.known) P.m2p_known.push_back(t);
+  auto known_only = [](const std::vector<Task>& all, std::vector<Task>& out) {
+    out.clear();
+    for (size_t w = 0; w + 1 < all.size(); w += 2) {
+      Task a = all[w], b = all[w + 1];
+      if (!a.known && !b.known) continue;
+      for (Task* t : {&a, &b})
+        if (!t->known) {
+          t->lbeg = t->lend = 0;
+          t->nsrc = 0;
+        }
+      out.push_back(a);
+      out.push_back(b);
+    }
+  };
+  known_only(P.p2p, P.p2p_known);
+  known_only(P.m2p, P.m2p_known);
   if (std::getenv("PBT_PLAN_STATS")) {
     // lane utilisation of the P2P wavefronts: pair evaluations issued (64
     // lanes x records per round x rounds) against useful target x source pairs
@@ -961,18 +991,21 @@ void System::build_plan() {
       empty += (a.tcount == 0) + (b.tcount == 0);
     }
     double missued = 0;
-    for (const Task& t : P.m2p) missued += 64.0 * (t.lend - t.lbeg);
+    for (size_t w = 0; w + 1 < P.m2p.size(); w += 2)
+      missued += 64.0 * std::max(P.m2p[w].lend - P.m2p[w].lbeg, P.m2p[w + 1].lend - P.m2p[w + 1].lbeg);
     // (target, box) M2P pairs by the box's number of sources
     std::vector<int64_t> bsrc(nbox_, 0);
     for (int e = 0; e < ns; ++e)
       for (size_t bi = 0; bi < trees_[e].boxes.size(); ++bi)
         bsrc[boff_[e] + bi] = (int64_t)(trees_[e].boxes[bi].pend - trees_[e].boxes[bi].pbeg) * K_;
     int64_t hist[6] = {0, 0, 0, 0, 0, 0};
-    for (const Task& t : P.m2p)
+    for (size_t w = 0; w < P.m2p.size(); ++w) {
+      const Task& t = P.m2p[w];
       for (int32_t r = t.lbeg; r < t.lend; ++r) {
         const int64_t n = bsrc[P.blist[r]];
         hist[n < 16 ? 0 : n < 32 ? 1 : n < 64 ? 2 : n < 128 ? 3 : n < 256 ? 4 : 5] += t.tcount;
       }
+    }
     std::fprintf(stderr, "[plan] m2p pairs by box sources <16 / <32 / <64 / <128 / <256 / more: "
                  "%lld / %lld / %lld / %lld / %lld / %lld\n", (long long)hist[0], (long long)hist[1],
                  (long long)hist[2], (long long)hist[3], (long long)hist[4], (long long)hist[5]);
@@ -1064,7 +1097,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     moments(fs);
     if (timed) PBT_HIP(hipEventRecord(evm_[1], fs));
     const int e0 = pb(fs);
-    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, fs);
+    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, ppart, fs);
     pe(1, e0, fs);
     if (timed || two) PBT_HIP(hipEventRecord(evm_[2], fs));
   };
@@ -1080,7 +1113,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     }
     const int e0 = pb(s);
     launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks, npairs,
-                      dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
+                      dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
     pe(0, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
@@ -1104,7 +1137,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     if (timed) PBT_HIP(hipEventRecord(evm_[1], s));
     e0 = pb(s);
     launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks + 2 * (int64_t)na, nb,
-                      dranges_.p, src, tgt, (T)kappa_, guard, part, ppart, s);
+                      dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
     pe(1, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(evm_[2], s));
@@ -1127,7 +1160,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     m2m_marked(s);
     if (timed) PBT_HIP(hipEventRecord(evm_[1], s));
     e0 = pb(s);
-    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, s);
+    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, ppart, s);
     pe(1, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(evm_[2], s));
@@ -1144,7 +1177,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     PBT_HIP(hipEventRecord(evm_[1], s));
     PBT_HIP(hipStreamWaitEvent(s2_, evm_[1], 0));
     const int e1 = pb(s2_);
-    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, part, s2_);
+    launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, ppart, s2_);
     pe(1, e1, s2_);
     PBT_HIP(hipEventRecord(evm_[2], s2_));
   }

@@ -153,29 +153,44 @@ void System::build_tplan(hipStream_t s) {
   tpart32_.alloc((size_t)std::max(slot, 1) * 256);
   tpart64_.alloc((size_t)std::max(slot, 1) * 256);
 
-  // M2P^T tasks grouped by box
-  std::vector<std::vector<Task>> bybox(nbox_);
+  // M2P^T tasks grouped by box: per box, the target ranges of the groups
+  // that list it, contiguous ranges of one kind merged (the forward groups
+  // are runs of 32 targets), in chunks of 64
+  std::vector<std::vector<std::tuple<int, int64_t, int64_t>>> ranges_of(nbox_);   // (key, t0, t1)
   for (size_t li = 0; li < leaves_.size(); ++li) {
     const LeafInfo& L = leaves_[li];
     const std::vector<int>& gsf = group_surfs_[surfs_[L.e]->group];
     for (size_t k2 = 0; k2 < gsf.size(); ++k2)
       for (int b : lm2p_[li][k2]) {
         const int e2 = gsf[k2];
-        const int gb = (int)(boff_[e2] + b);
         int32_t fu = 0;
         int16_t fm = 0;
         task_form(L.e, e2, fu, fm);
-        for (int64_t t0 = L.g0; t0 < L.g1; t0 += 64) {
-          Task t{};
-          t.tbeg = (int32_t)t0;
-          t.tcount = (int32_t)std::min<int64_t>(64, L.g1 - t0);
-          t.lbeg = gb;
-          t.lend = gb + 1;
-          t.fused = fu;
-          t.form = fm;
-          bybox[gb].push_back(t);
-        }
+        ranges_of[boff_[e2] + b].push_back({fu | (fm << 1), L.g0, L.g1});
       }
+  }
+  std::vector<std::vector<Task>> bybox(nbox_);
+  for (int gb = 0; gb < nbox_; ++gb) {
+    auto& rl = ranges_of[gb];
+    std::sort(rl.begin(), rl.end());
+    for (size_t k = 0; k < rl.size();) {
+      const int key = std::get<0>(rl[k]);
+      const int64_t a = std::get<1>(rl[k]);
+      int64_t e = std::get<2>(rl[k]);
+      size_t q = k + 1;
+      while (q < rl.size() && std::get<0>(rl[q]) == key && std::get<1>(rl[q]) == e) e = std::get<2>(rl[q++]);
+      for (int64_t t0 = a; t0 < e; t0 += 64) {
+        Task t{};
+        t.tbeg = (int32_t)t0;
+        t.tcount = (int32_t)std::min<int64_t>(64, e - t0);
+        t.lbeg = gb;
+        t.lend = gb + 1;
+        t.fused = key & 1;
+        t.form = (int16_t)(key >> 1);
+        bybox[gb].push_back(t);
+      }
+      k = q;
+    }
   }
   std::vector<Task> mt;
   std::vector<int32_t> mb(nbox_), me(nbox_);

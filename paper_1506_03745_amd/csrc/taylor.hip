@@ -336,9 +336,7 @@ __global__ __launch_bounds__(256) void k_m2m_sum(int NO, const int32_t* __restri
 //            b_k = kappa |R|^2/(2n-1) sum_i u_i a_{k-e_i} - kappa/n sum_i a_{k-2e_i}
 // (the same quantities, one multiplication fewer per coefficient).
 // A wave-uniform zero that the compiler cannot see through, produced after
-// v: moment offsets built from it keep a degree's (scalar) moment loads from
-// being hoisted above the arithmetic of the degree two below, which would
-// hold every moment of the box in scalar registers at once and spill them.
+// v (orders a computation after v's).
 template <typename T>
 __device__ __forceinline__ int zero_after(T v) {
   int z;
@@ -346,14 +344,14 @@ __device__ __forceinline__ int zero_after(T v) {
   return z;
 }
 
+// The moments M are in LDS (a per-lane address): each degree's are read at
+// its start, kept there by scheduling barriers, so that the degree's
+// recurrence hides their latency and one degree of them is live at a time.
 template <typename T, int P, bool YUK>
 __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
   constexpr int NC = ncoef(P);
   T A[NC];
   T B[YUK ? NC : 1];
-  int dz[P + 3];
-#pragma unroll
-  for (int n = 0; n < P + 3; ++n) dz[n] = 0;
   const T R2 = Rx * Rx + Ry * Ry + Rz * Rz;
   const T Rinv = TMath<T>::rsq(R2);
   const T invR2 = Rinv * Rinv;
@@ -368,7 +366,11 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
   T acc = A[0] * M[0];
 #pragma unroll
   for (int n = 1; n <= P; ++n) {
-    const T* Mn = M + dz[n];
+    T mo[(P + 1) * (P + 2) / 2];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k) mo[k - tidx(n, 0, 0)] = M[k];
+    __builtin_amdgcn_sched_barrier(0);
     const T c1 = T(2 * n - 1) / T(n) * invR2;
     const T c2 = T(n - 1) / T(n) * invR2;
     const T c3 = kappa * (T(1) / T(n)) * invR2;
@@ -409,10 +411,10 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
         } else {
           A[k] = h2 ? S1 - c2 * S2 : S1;
         }
-        acc += A[k] * Mn[k];
       }
     }
-    if (n + 2 <= P) dz[n + 2] = zero_after(acc);
+#pragma unroll
+    for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k) acc += A[k] * mo[k - tidx(n, 0, 0)];
   }
   return acc;
 }
@@ -423,9 +425,6 @@ template <typename T, int P>
 __device__ __forceinline__ void taylor_dot_two(T Rx, T Ry, T Rz, const T* __restrict__ M, T& yy, T& l) {
   constexpr int NC = ncoef(P);
   T A[NC];
-  int dz[P + 3];
-#pragma unroll
-  for (int n = 0; n < P + 3; ++n) dz[n] = 0;
   const T R2 = Rx * Rx + Ry * Ry + Rz * Rz;
   const T Rinv = TMath<T>::rsq(R2);
   const T invR2 = Rinv * Rinv;
@@ -433,7 +432,15 @@ __device__ __forceinline__ void taylor_dot_two(T Rx, T Ry, T Rz, const T* __rest
   T a0 = A[0] * M[0], a1 = A[0] * M[NC];
 #pragma unroll
   for (int n = 1; n <= P; ++n) {
-    const T* Mn = M + dz[n];
+    // both rows' moments of the degree (as in taylor_dot)
+    T m0[(P + 1) * (P + 2) / 2], m1[(P + 1) * (P + 2) / 2];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k) {
+      m0[k - tidx(n, 0, 0)] = M[k];
+      m1[k - tidx(n, 0, 0)] = M[NC + k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     const T c1 = T(2 * n - 1) / T(n) * invR2;
     const T c2 = T(n - 1) / T(n) * invR2;
     const T ux = c1 * Rx, uy = c1 * Ry, uz = c1 * Rz;
@@ -460,85 +467,143 @@ __device__ __forceinline__ void taylor_dot_two(T Rx, T Ry, T Rz, const T* __rest
         if (b >= 2) second(tidx(a, b - 2, c));
         if (c >= 2) second(tidx(a, b, c - 2));
         A[k] = h2 ? S1 - c2 * S2 : S1;
-        a0 += A[k] * Mn[k];
-        a1 += A[k] * Mn[NC + k];
       }
     }
-    if (n + 2 <= P) dz[n + 2] = zero_after(a0 + a1);
+#pragma unroll
+    for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k) {
+      a0 += A[k] * m0[k - tidx(n, 0, 0)];
+      a1 += A[k] * m1[k - tidx(n, 0, 0)];
+    }
   }
   yy += a0;
   l += a1;
 }
 
-// One M2P task (64 targets x a list of boxes) on one wavefront, one target
-// per lane; the box moments are wave-uniform and read through the scalar
-// cache.
+// A pair of M2P tasks on one wavefront: lanes 0..31 serve tp[0], lanes
+// 32..63 tp[1], each up to 32 targets (one a lane) against its own list of
+// boxes; both have the same `fused` and kFormKz.  Box by box, each half
+// copies its box's moments (both rows with `fused`, the Yukawa row
+// otherwise) from registers into its part of the wave's LDS region, and the
+// lanes read them back as LDS broadcasts, so the dot products take their
+// moments from vector registers; the next box's moments are loaded into
+// registers while the current box is evaluated.  A half with fewer boxes
+// idles (masked) while the other finishes.  Partials [slot][32][2].
 template <typename T, int P, bool SALTFREE>
-__device__ __forceinline__ void m2p_task(const Task& task, const int32_t* __restrict__ blist,
-                                         const T* __restrict__ tgt, const double* __restrict__ bcen,
-                                         const T* __restrict__ mom, T kappa, T* __restrict__ partial) {
-  constexpr int NC = ncoef(P);
-  const int lane = threadIdx.x & 63;
-  const int tbeg = task.tbeg, tcount = task.tcount;
-  const int lbeg = task.lbeg, lend = task.lend;
-  const int fused = task.fused;
+__device__ __forceinline__ void m2p_task_pair(const Task* __restrict__ tp, T* __restrict__ mlds,
+                                              const int32_t* __restrict__ blist, const T* __restrict__ tgt,
+                                              const double* __restrict__ bcen, const T* __restrict__ mom, T kappa,
+                                              T* __restrict__ partial) {
+  constexpr int NC = ncoef(P), NM = 2 * NC, PER = (NM + 31) / 32;
+  const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  const Task t = tp[half];
+  // both halves agree on these: wave-uniform
+  const int fused = __builtin_amdgcn_readfirstlane(tp[0].fused);
   // an outside sum inside a salt-free Stern layer: kappa = 0 (the Yukawa
   // recurrence then reduces to the Laplace one)
-  if (task.form & kFormKz) kappa = T(0);
-  const int ti = tbeg + (lane < tcount ? lane : 0);
+  if (__builtin_amdgcn_readfirstlane(tp[0].form) & kFormKz) kappa = T(0);
+  const int nm = fused ? NM : NC;
+  const int n = t.lend - t.lbeg;
+  const int nmax = __builtin_amdgcn_readfirstlane(max(tp[0].lend - tp[0].lbeg, tp[1].lend - tp[1].lbeg));
+  const int ti = t.tbeg + (hl < t.tcount ? hl : 0);
   const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
-  T l = 0, yy = 0;
-  for (int r = lbeg; r < lend; ++r) {
-    const int b = blist[r];
-    const T Rx = tx - (T)bcen[3 * b], Ry = ty - (T)bcen[3 * b + 1], Rz = tz - (T)bcen[3 * b + 2];
+  T* mine = mlds + half * NM;
+  // every lane evaluates a box of its half's list each round (the last one
+  // again once its list is done, entry 0 of the list array for an empty
+  // half) and keeps the result only while its list lasts: no divergence.
+  // Box indices, centres and moments are loaded a round ahead, so a round
+  // waits on no memory latency but the LDS reads of its own moments.
+  const int last = t.lbeg + max(n - 1, 0);
+  auto box = [&](int r) { return blist[min(t.lbeg + r, last)]; };
+  T pre[PER];
+  auto fetch = [&](int b) {
     const T* M = mom + (int64_t)(2 * b) * NC;
-    if (SALTFREE) {
-      if (fused) taylor_dot_two<T, P>(Rx, Ry, Rz, M, yy, l);
-      else yy += taylor_dot<T, P, false>(Rx, Ry, Rz, kappa, M);
-      continue;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = hl + 32 * q;
+      pre[q] = i < nm ? M[i] : T(0);
     }
-    yy += taylor_dot<T, P, true>(Rx, Ry, Rz, kappa, M);
-    if (fused) l += taylor_dot<T, P, false>(Rx, Ry, Rz, kappa, M + NC);
+  };
+  int b = box(0);
+  fetch(b);
+  double cx = bcen[3 * b], cy = bcen[3 * b + 1], cz = bcen[3 * b + 2];
+  int bn = box(1);
+  T l = 0, yy = 0;
+  for (int r = 0; r < nmax; ++r) {
+    wave_lds_sync();   // the previous box's reads are done
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = hl + 32 * q;
+      if (i < nm) mine[i] = pre[q];
+    }
+    wave_lds_sync();
+    const T Rx = tx - (T)cx, Ry = ty - (T)cy, Rz = tz - (T)cz;
+    if (r + 1 < nmax) {
+      fetch(bn);
+      cx = bcen[3 * bn];
+      cy = bcen[3 * bn + 1];
+      cz = bcen[3 * bn + 2];
+      bn = box(r + 2);
+    }
+    T dy = 0, dl = 0;
+    if (SALTFREE) {
+      if (fused) taylor_dot_two<T, P>(Rx, Ry, Rz, mine, dy, dl);
+      else dy = taylor_dot<T, P, false>(Rx, Ry, Rz, kappa, mine);
+    } else {
+      dy = taylor_dot<T, P, true>(Rx, Ry, Rz, kappa, mine);
+      if (fused) {
+        // the Laplace expansion after the Yukawa one (an opaque zero taken
+        // from its result): interleaving the two would hold both sets of
+        // coefficients in registers at once
+        const T z = (T)zero_after(dy);
+        dl = taylor_dot<T, P, false>(Rx + z, Ry + z, Rz + z, kappa, mine + NC);
+      }
+    }
+    const bool on = r < n;
+    yy += on ? dy : T(0);
+    l += on ? dl : T(0);
   }
-  if (lane < tcount) {
+  if (hl < t.tcount) {
     T o0 = l, o1 = yy;
-    if (task.form & kFormDropOut) o1 = T(0);
-    if (task.form & kFormSwap) {
+    if (t.form & kFormDropOut) o1 = T(0);
+    if (t.form & kFormSwap) {
       const T sw = o0;
       o0 = o1;
       o1 = sw;
     }
-    partial[2 * ((int64_t)task.slot * 64 + lane) + 0] = o0;
-    partial[2 * ((int64_t)task.slot * 64 + lane) + 1] = o1;
+    partial[2 * ((int64_t)t.slot * 32 + hl) + 0] = o0;
+    partial[2 * ((int64_t)t.slot * 32 + hl) + 1] = o1;
   }
 }
 
+// One wavefront per pair of M2P tasks (four per block).
 template <typename T, int P, bool SALTFREE>
-__global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int ntasks,
+__global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int npairs,
                                              const int32_t* __restrict__ blist,
                                              const T* __restrict__ tgt,
                                              const double* __restrict__ bcen,
                                              const T* __restrict__ mom, T kappa,
                                              T* __restrict__ partial) {
+  __shared__ T mlds[4][4 * ncoef(P)];
   const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
-  if (wv >= ntasks) return;
-  m2p_task<T, P, SALTFREE>(tasks[wv], blist, tgt, bcen, mom, kappa, partial);
+  if (wv >= npairs) return;
+  m2p_task_pair<T, P, SALTFREE>(tasks + 2 * wv, mlds[threadIdx.x >> 6], blist, tgt, bcen, mom, kappa, partial);
 }
 
-// M2P tasks and P2P task pairs in one launch (M2P first): the far field's wavefronts
-// and the near field's share the machine instead of running one after the
-// other.
+// M2P task pairs and P2P task pairs in one launch (M2P first): the far
+// field's wavefronts and the near field's share the machine instead of
+// running one after the other.  Both write the half-wave partials.
 template <typename T, int P, bool GUARD, bool SALTFREE>
 __global__ __launch_bounds__(256) void k_m2p_p2p(const Task* __restrict__ m2p, int nm2p,
                                                  const int32_t* __restrict__ blist,
                                                  const double* __restrict__ bcen, const T* __restrict__ mom,
                                                  const Task* __restrict__ p2p, int np2p,
                                                  const int32_t* __restrict__ ranges, const T* __restrict__ src,
-                                                 const T* __restrict__ tgt, T kappa, T* __restrict__ partial,
-                                                 T* __restrict__ ppartial) {
+                                                 const T* __restrict__ tgt, T kappa, T* __restrict__ ppartial) {
   __shared__ SrcRec<T> tiles[4][64];
+  __shared__ T mlds[4][4 * ncoef(P)];
   const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
-  if (wv < nm2p) m2p_task<T, P, SALTFREE>(m2p[wv], blist, tgt, bcen, mom, kappa, partial);
+  if (wv < nm2p)
+    m2p_task_pair<T, P, SALTFREE>(m2p + 2 * wv, mlds[threadIdx.x >> 6], blist, tgt, bcen, mom, kappa, ppartial);
   else if (wv < nm2p + np2p)
     p2p_task_pair<T, GUARD>(p2p + 2 * (wv - nm2p), tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, ppartial);
 }
@@ -659,29 +724,31 @@ void launch_m2m(int P, int npairs, const int32_t* pairs, int nheads, int nsmall,
 }
 
 template <typename T, int P>
-static void m2p_p(const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
+static void m2p_p(const Task* tasks, int npairs, const int32_t* blist, const T* tgt,
                   const double* bcen, const T* mom, T kappa, T* partial, hipStream_t s) {
-  const int blocks = ((ntasks + 3) / 4 + 7) / 8 * 8;
+  const int blocks = ((npairs + 3) / 4 + 7) / 8 * 8;
   if (kappa == T(0))
-    k_m2p<T, P, true><<<blocks, 256, 0, s>>>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial);
+    k_m2p<T, P, true><<<blocks, 256, 0, s>>>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial);
   else
-    k_m2p<T, P, false><<<blocks, 256, 0, s>>>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial);
+    k_m2p<T, P, false><<<blocks, 256, 0, s>>>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial);
 }
 
 template <typename T>
 void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
                 const double* bcen, const T* mom, T kappa, T* partial, hipStream_t s) {
   if (ntasks <= 0) return;
+  if (ntasks % 2) throw Error(1, "M2P half tasks come in pairs");
+  const int npairs = ntasks / 2;
   switch (P) {
-    case 0: m2p_p<T, 0>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
-    case 1: m2p_p<T, 1>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
-    case 2: m2p_p<T, 2>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
-    case 3: m2p_p<T, 3>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
-    case 4: m2p_p<T, 4>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
-    case 5: m2p_p<T, 5>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
-    case 6: m2p_p<T, 6>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
-    case 7: m2p_p<T, 7>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
-    case 8: m2p_p<T, 8>(tasks, ntasks, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 0: m2p_p<T, 0>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 1: m2p_p<T, 1>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 2: m2p_p<T, 2>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 3: m2p_p<T, 3>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 4: m2p_p<T, 4>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 5: m2p_p<T, 5>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 6: m2p_p<T, 6>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 7: m2p_p<T, 7>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
+    case 8: m2p_p<T, 8>(tasks, npairs, blist, tgt, bcen, mom, kappa, partial, s); break;
     default: throw Error(1, "Taylor order P must be 0..8");
   }
   PBT_HIP(hipGetLastError());
@@ -690,11 +757,11 @@ void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, cons
 template <typename T, int P>
 static void m2p_p2p_p(const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
                       const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
-                      bool guard, T* partial, T* ppartial, hipStream_t s) {
+                      bool guard, T* ppartial, hipStream_t s) {
   const int blocks = ((nm2p + np2p + 3) / 4 + 7) / 8 * 8;
 #define PBT_LAUNCH(G, SF)                                                                                  \
   k_m2p_p2p<T, P, G, SF><<<blocks, 256, 0, s>>>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt, kappa, \
-                                                partial, ppartial)
+                                                ppartial)
   const bool sf = kappa == T(0);
   if (guard) {
     if (sf) PBT_LAUNCH(true, true);
@@ -709,13 +776,14 @@ static void m2p_p2p_p(const Task* m2p, int nm2p, const int32_t* blist, const dou
 template <typename T>
 void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
                     const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
-                    bool guard, T* partial, T* ppartial, hipStream_t s) {
+                    bool guard, T* ppartial, hipStream_t s) {
+  if (nm2p % 2) throw Error(1, "M2P half tasks come in pairs");
+  nm2p /= 2;   // wavefronts
   if (nm2p + np2p <= 0) return;
   switch (P) {
 #define PBT_CASE(PP)                                                                                      \
   case PP:                                                                                                \
-    m2p_p2p_p<T, PP>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt, kappa, guard, partial, ppartial, \
-                     s);                                                                                  \
+    m2p_p2p_p<T, PP>(m2p, nm2p, blist, bcen, mom, p2p, np2p, ranges, src, tgt, kappa, guard, ppartial, s);   \
     break;
     PBT_CASE(0) PBT_CASE(1) PBT_CASE(2) PBT_CASE(3) PBT_CASE(4) PBT_CASE(5) PBT_CASE(6) PBT_CASE(7) PBT_CASE(8)
 #undef PBT_CASE
@@ -737,10 +805,10 @@ template void launch_moments<double>(int, int, const int32_t*, const MomChunk*, 
                                      const double*, const double*, const double*, double*, double*, hipStream_t);
 template void launch_m2p_p2p<float>(int, const Task*, int, const int32_t*, const double*, const float*,
                                     const Task*, int, const int32_t*, const float*, const float*, float, bool,
-                                    float*, float*, hipStream_t);
+                                    float*, hipStream_t);
 template void launch_m2p_p2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
                                      const Task*, int, const int32_t*, const double*, const double*, double, bool,
-                                     double*, double*, hipStream_t);
+                                     double*, hipStream_t);
 template void launch_m2m<float>(int, int, const int32_t*, int, int, const int32_t*, const double*, float*, float*,
                                 hipStream_t);
 template void launch_m2m<double>(int, int, const int32_t*, int, int, const int32_t*, const double*, double*, double*,

@@ -4,10 +4,10 @@
 //
 // Boxes are cubes split into octants while they hold more than N_crit
 // panels; panels are reordered so that every box owns a contiguous range,
-// and inside a leaf by finer octants (its 64-panel runs are compact).
+// and inside a leaf by finer octants (its 32-panel runs are compact).
 // Expansion centre of a box: centre of the bounding box of its Gauss points;
 // radius: the largest distance from that centre to one of them.  A target
-// group T (a run of at most 64 collocation points of one leaf) accepts a
+// group T (a run of at most 32 collocation points of one leaf) accepts a
 // source box B for the far field when
 //     r_B < theta * (|c_T - c_B| - r_T),
 // r_T being the radius of T's collocation points about their own centre, so
@@ -23,7 +23,7 @@ namespace {
 
 // Orders idx[beg, end) by recursive octants of the cube (c, half) down to
 // groups of at most 8 points, so that consecutive runs of a leaf's panels
-// (the 64-target chunks the work is cut into) are spatially compact.
+// (the 32-target groups the work is cut into) are spatially compact.
 void order_octants(const double* cen, std::vector<int32_t>& idx, int beg, int end, const double c[3], double half,
                    int depth) {
   if (end - beg <= 8 || depth >= 20) return;

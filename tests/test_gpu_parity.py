@@ -403,16 +403,17 @@ def test_full_size_twosphere_energies_against_stored_oracle(name, form):
     direct form to 1e-7; the benchmark's mixed-precision treecode (theta 0.5,
     P 6, N_crit 300, tol 1e-6) to the mixed bar 1e-4 (measured: F_solv 2e-7,
     F_surf 5.7e-6, F_int 8e-8 of |F_solv| + |F_surf|); the FP64 treecode to
-    the FP64 bar 1e-6 at P = 8, the smallest order that meets it at theta 0.5
-    (P = 6 and 7 leave F_surf at 5.6e-6 and 1.4e-6 from the Taylor
-    truncation; P = 8: 7.6e-7 and 8.1e-7).  F_int, a small difference, is
-    held to the bar times |F_solv| + |F_surf| of the assembly."""
+    the FP64 bar 1e-6 at P = 8 and theta 0.4.  The Taylor truncation sets
+    that error: with the acceptance test taken per 32 targets, theta 0.5
+    leaves F_surf at 1.1e-6 at P = 8, so the test takes the next smaller
+    theta.  F_int, a small difference, is held to the bar times
+    |F_solv| + |F_surf| of the assembly."""
     gold = json.load(open(os.path.join(GOLDEN, "dense_oracle_energies.json")))
     g = gold[name]
     pr = config_problem(name)
     kw, bar = {"direct_fp64": (dict(treecode=0, tol=1e-10), 1e-7),
                "treecode_mixed_P6": (dict(prec=MIXED, theta=0.5, taylor_p=6, ncrit=300, tol=1e-6), 1e-4),
-               "treecode_fp64_P8": (dict(prec=FP64, theta=0.5, taylor_p=8, ncrit=300, tol=1e-8), 1e-6)}[form]
+               "treecode_fp64_P8": (dict(prec=FP64, theta=0.4, taylor_p=8, ncrit=300, tol=1e-8), 1e-6)}[form]
     s, _ = from_problem(pr, **kw)
     f, res = s.interaction_energy(2)
     assert abs(res[0].F_solv - g["F_solv_asm"]) <= bar * abs(g["F_solv_asm"])
