@@ -202,7 +202,7 @@ struct MomChunk {
   int32_t slot0, nparts, idx;
   int32_t fine, pad_;
 };
-constexpr int kMomChunk = 1024;     // sources of a plain chunk (4 a thread)
+constexpr int kMomChunk = 1024;     // sources of a plain chunk (16 a lane)
 constexpr int kMomFineMax = 16384;  // largest box done as one fine chunk
 constexpr int kMomGroup = 12;       // coefficients per block
 constexpr int kMomGroupFine = 4;

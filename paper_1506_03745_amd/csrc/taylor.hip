@@ -52,17 +52,16 @@ struct TMath<double> {
 #include "near_field.h"
 
 // ---- Moments (P2M) -----------------------------------------------------------
-// Every box that some M2P task reads gets its moments straight from its own
-// sources (a box's sources are contiguous in tree order), so boxes of all
-// levels are done in one launch with no level-by-level shifting.  Large boxes
-// are cut into chunks of at most kMomChunk sources; one block per (chunk,
-// group of kMomGroup coefficients), threads over the chunk's sources, each
-// thread accumulating the group's coefficients of both rows in registers:
+// The leaves' moments (and those of any box given to P2M) straight from
+// their sources (a box's sources are contiguous in tree order).  Large boxes
+// are cut into chunks of at most kMomChunk sources; one wavefront per (chunk,
+// group of kMomGroup coefficients), lanes over the chunk's sources, each lane
+// accumulating the group's coefficients of both rows in registers:
 //   row 0: sum_j s_j h^k + D_j . grad h^k,   row 1: -rho_inv s_j h^k - D_j . grad h^k
-// with grad h^k = (a h^(k-e_x), b h^(k-e_y), c h^(k-e_z)).  The block adds its
-// threads' sums up through LDS in a fixed order.  A box of several chunks has
-// its chunk sums written to partial slots, which a second launch adds in
-// chunk order, so results do not depend on block scheduling.
+// with grad h^k = (a h^(k-e_x), b h^(k-e_y), c h^(k-e_z)).  The wavefront adds
+// its lanes' sums up by a fixed butterfly (no LDS, no barrier).  A box of
+// several chunks has its chunk sums written to partial slots, which a second
+// launch adds in chunk order, so results do not depend on scheduling.
 constexpr int kMomThreads = 256;
 
 __host__ __device__ constexpr int midx_n(int k) {
@@ -83,10 +82,10 @@ __host__ __device__ constexpr int midx_a(int k) { return midx_n(k) - midx_m(k); 
 template <typename T, int P, int K0, int K1>
 __device__ __forceinline__ void moments_group(const MomChunk& ch, const double* __restrict__ bcen,
                                               const double* __restrict__ brho, const T* __restrict__ src,
-                                              T* __restrict__ mom, T* __restrict__ mpart,
-                                              T* red /* [kMomThreads][9] */) {
+                                              T* __restrict__ mom, T* __restrict__ mpart) {
   constexpr int NC = ncoef(P);
   constexpr int NG = K1 - K0;
+  const int lane = threadIdx.x & 63;
   const int b = ch.box;
   const T cx = (T)bcen[3 * b], cy = (T)bcen[3 * b + 1], cz = (T)bcen[3 * b + 2];
   const T ri = (T)brho[b];
@@ -94,7 +93,7 @@ __device__ __forceinline__ void moments_group(const MomChunk& ch, const double* 
 #pragma unroll
   for (int q = 0; q < 2 * NG; ++q) acc[q] = 0;
   const SrcRec<T>* srec = reinterpret_cast<const SrcRec<T>*>(src);
-  for (int j = ch.sbeg + (int)threadIdx.x; j < ch.send; j += kMomThreads) {
+  for (int j = ch.sbeg + lane; j < ch.send; j += 64) {
     const SrcRec<T> r = load_rec(srec + j);
     const T hx = r.v[0] - cx, hy = r.v[1] - cy, hz = r.v[2] - cz;
     const T s = r.v[3], sl = -ri * r.v[3];
@@ -124,70 +123,62 @@ __device__ __forceinline__ void moments_group(const MomChunk& ch, const double* 
       acc[2 * (k - K0) + 1] += sl * hk - d;
     }
   }
-  // the block's sums, 8 columns (coefficient K0 + q/2, row q%2) a pass
-  // through LDS: 32 lanes a column, each over 8 rows, then a fixed xor
-  // butterfly over the 32
-  const int col = threadIdx.x >> 5, part = threadIdx.x & 31;
+  // the wavefront's sums by a fixed xor butterfly; lane q keeps sum q
+  // (coefficient K0 + q/2, row q%2) and writes it
+  T out = 0;
 #pragma unroll
-  for (int q0 = 0; q0 < 2 * NG; q0 += 8) {
-    if (q0) __syncthreads();
+  for (int q = 0; q < 2 * NG; ++q) {
+    T v = acc[q];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (q0 + q < 2 * NG) red[threadIdx.x * 9 + q] = acc[q0 + q];
-    __syncthreads();
-    T v = 0;
-#pragma unroll
-    for (int i = 0; i < kMomThreads / 32; ++i) v += red[(part + 32 * i) * 9 + col];
-    v += __shfl_xor(v, 16, 32);
-    v += __shfl_xor(v, 8, 32);
-    v += __shfl_xor(v, 4, 32);
-    v += __shfl_xor(v, 2, 32);
-    v += __shfl_xor(v, 1, 32);
-    const int q = q0 + col;
-    if (q < 2 * NG && part == 0) {
-      const int k = K0 + (q >> 1), row = q & 1;
-      if (ch.nparts == 1) mom[(int64_t)(2 * b + row) * NC + k] = v;
-      else mpart[((int64_t)(ch.slot0 + ch.idx) * NC + k) * 2 + row] = v;
-    }
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if (lane == q) out = v;
+  }
+  if (lane < 2 * NG) {
+    const int k = K0 + (lane >> 1), row = lane & 1;
+    if (ch.nparts == 1) mom[(int64_t)(2 * b + row) * NC + k] = out;
+    else mpart[((int64_t)(ch.slot0 + ch.idx) * NC + k) * 2 + row] = out;
   }
 }
 
 template <typename T, int P, int GS, int G>
 __device__ __forceinline__ void moments_dispatch(const MomChunk& ch, int gi, const double* bcen, const double* brho,
-                                                 const T* src, T* mom, T* mpart, T* red) {
+                                                 const T* src, T* mom, T* mpart) {
   constexpr int K0 = G * GS;
   if constexpr (K0 < ncoef(P)) {
     constexpr int K1 = K0 + GS < ncoef(P) ? K0 + GS : ncoef(P);
     if (gi == G) {
-      moments_group<T, P, K0, K1>(ch, bcen, brho, src, mom, mpart, red);
+      moments_group<T, P, K0, K1>(ch, bcen, brho, src, mom, mpart);
       return;
     }
-    moments_dispatch<T, P, GS, G + 1>(ch, gi, bcen, brho, src, mom, mpart, red);
+    moments_dispatch<T, P, GS, G + 1>(ch, gi, bcen, brho, src, mom, mpart);
   }
 }
 
-// One moments block: entry b of the block list is (chunk, coefficient group);
-// a chunk marked fine takes groups of kMomGroupFine coefficients (a large box
-// done by one chunk, its work spread over more blocks), otherwise kMomGroup.
+// One moments item on one wavefront: entry b of the item list is (chunk,
+// coefficient group); a chunk marked fine takes groups of kMomGroupFine
+// coefficients (a large box done by one chunk, its work spread over more
+// wavefronts), otherwise kMomGroup.
 template <typename T, int P>
-__device__ __forceinline__ void moments_block(int b, const int32_t* __restrict__ mblocks,
-                                              const MomChunk* __restrict__ chunks, const double* bcen,
-                                              const double* brho, const T* src, T* mom, T* mpart, T* red) {
+__device__ __forceinline__ void moments_item(int b, const int32_t* __restrict__ mblocks,
+                                             const MomChunk* __restrict__ chunks, const double* bcen,
+                                             const double* brho, const T* src, T* mom, T* mpart) {
   const MomChunk ch = chunks[mblocks[2 * b]];
   const int gi = mblocks[2 * b + 1];
-  if (ch.fine) moments_dispatch<T, P, kMomGroupFine, 0>(ch, gi, bcen, brho, src, mom, mpart, red);
-  else moments_dispatch<T, P, kMomGroup, 0>(ch, gi, bcen, brho, src, mom, mpart, red);
+  if (ch.fine) moments_dispatch<T, P, kMomGroupFine, 0>(ch, gi, bcen, brho, src, mom, mpart);
+  else moments_dispatch<T, P, kMomGroup, 0>(ch, gi, bcen, brho, src, mom, mpart);
 }
 
+// Four moments items a block, one a wavefront.
 template <typename T, int P>
-__global__ __launch_bounds__(kMomThreads) void k_moments(const int32_t* __restrict__ mblocks,
+__global__ __launch_bounds__(kMomThreads) void k_moments(int nitems, const int32_t* __restrict__ mblocks,
                                                          const MomChunk* __restrict__ chunks,
                                                          const double* __restrict__ bcen,
                                                          const double* __restrict__ brho,
                                                          const T* __restrict__ src, T* __restrict__ mom,
                                                          T* __restrict__ mpart) {
-  __shared__ T red[kMomThreads * 9];
-  moments_block<T, P>((int)blockIdx.x, mblocks, chunks, bcen, brho, src, mom, mpart, red);
+  const int it = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  if (it >= nitems) return;
+  moments_item<T, P>(it, mblocks, chunks, bcen, brho, src, mom, mpart);
 }
 
 // Boxes of several chunks: their moments are the chunk sums added in chunk
@@ -620,27 +611,26 @@ __global__ __launch_bounds__(256) void k_p2p_mom(int nmreal, int nmb, const int3
                                                  T* __restrict__ mpart, const Task* __restrict__ p2p, int npairs,
                                                  const int32_t* __restrict__ ranges, const T* __restrict__ src,
                                                  const T* __restrict__ tgt, T kappa, T* __restrict__ ppartial) {
-  constexpr int kTile = 4 * 64 * (int)sizeof(SrcRec<T>);
-  constexpr int kRed = kMomThreads * 9 * (int)sizeof(T);
-  __shared__ __align__(16) unsigned char lds[kTile > kRed ? kTile : kRed];
+  __shared__ SrcRec<T> tiles[4][64];
   if ((int)blockIdx.x < nmb) {
-    if ((int)blockIdx.x >= nmreal) return;
-    moments_block<T, P>((int)blockIdx.x, mblocks, chunks, bcen, brho, src, mom, mpart, reinterpret_cast<T*>(lds));
+    // moments items, one a wavefront
+    const int it = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+    if (it >= nmreal) return;
+    moments_item<T, P>(it, mblocks, chunks, bcen, brho, src, mom, mpart);
     return;
   }
   const int l = (int)blockIdx.x - nmb, per = ((int)gridDim.x - nmb) >> 3;
   const int wv = __builtin_amdgcn_readfirstlane(((l & 7) * per + (l >> 3)) * 4 + (int)(threadIdx.x >> 6));
   if (wv >= npairs) return;
-  SrcRec<T>* tiles = reinterpret_cast<SrcRec<T>*>(lds);
-  p2p_task_pair<T, GUARD>(p2p + 2 * wv, tiles + 64 * (threadIdx.x >> 6), ranges, tgt, src, kappa, ppartial);
+  p2p_task_pair<T, GUARD>(p2p + 2 * wv, tiles[threadIdx.x >> 6], ranges, tgt, src, kappa, ppartial);
 }
 
 }  // namespace
 
 template <typename T, int P>
-static void moments_p(int nblocks, const int32_t* mblocks, const MomChunk* chunks, const double* bcen,
+static void moments_p(int nitems, const int32_t* mblocks, const MomChunk* chunks, const double* bcen,
                       const double* brho, const T* src, T* mom, T* mpart, hipStream_t s) {
-  k_moments<T, P><<<nblocks, kMomThreads, 0, s>>>(mblocks, chunks, bcen, brho, src, mom, mpart);
+  k_moments<T, P><<<(nitems + 3) / 4, kMomThreads, 0, s>>>(nitems, mblocks, chunks, bcen, brho, src, mom, mpart);
 }
 
 template <typename T>
@@ -666,7 +656,7 @@ template <typename T, int P>
 static void p2p_mom_p(int nmreal, const int32_t* mblocks, const MomChunk* chunks, const double* bcen,
                       const double* brho, T* mom, T* mpart, const Task* p2p, int npairs, const int32_t* ranges,
                       const T* src, const T* tgt, T kappa, bool guard, T* ppartial, hipStream_t s) {
-  const int nmb = (nmreal + 7) / 8 * 8;
+  const int nmb = ((nmreal + 3) / 4 + 7) / 8 * 8;   // blocks of four moments items
   const int blocks = nmb + ((npairs + 3) / 4 + 7) / 8 * 8;
   if (guard)
     k_p2p_mom<T, P, true><<<blocks, 256, 0, s>>>(nmreal, nmb, mblocks, chunks, bcen, brho, mom, mpart, p2p, npairs,
