@@ -4,6 +4,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -874,6 +875,15 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
     // nested surfaces, or any other surface alone)
     double f_iso = 0.0;
     pbt_status worst = PBT_OK;
+    const bool say = std::getenv("PBT_SETUP_TIMES") != nullptr;
+    double tb = wall_now();
+    auto phase = [&](const char* what) {
+      if (!say) return;
+      PBT_HIP(hipStreamSynchronize(c->stream));
+      const double u = wall_now();
+      std::fprintf(stderr, "[batch] %-16s %8.2f ms\n", what, 1e3 * (u - tb));
+      tb = u;
+    };
     try {
       std::vector<int> comps;
       for (int i = 0; i < ns; ++i)
@@ -892,6 +902,7 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
       throw;
     }
     restore();
+    phase("isolated solves");
     const int kBatch = 64;
     std::vector<int> placed;   // the surfaces of one placement: the moving ones, then the others
     for (int i = 0; i < ns; ++i)
@@ -920,6 +931,7 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
             o->qxyz = mv(S0.qxyz);
           }
           o->group = g;
+          o->shared = moving[k] ? -1 : k;
           copies.push_back({&S0, o.get()});
           list.push_back(o.get());
           own.push_back(std::move(o));
@@ -930,21 +942,26 @@ pbt_status pbt_solve_batch(pbt_ctx* c, int32_t mol_id, const double* rot, const 
             for (auto& q : copies)
               if (q.first == cp.second->parent) cp.second->parent = q.second;
       }
+      phase("placements");
       const double ts = wall_now();
       System S(list, c->prm, c->eps_out, c->kappa, c->stream);
       c->cs.t_setup += wall_now() - ts;
+      phase("system");
       if (c->profile) S.set_profile(true);
       const int64_t n = S.n();
       DBuf<double> b, x;
       b.alloc(n);
       x.alloc(n);
       S.rhs(b.p, c->stream);
+      phase("rhs");
       // one Krylov space per placement, each to the requested tolerance
       pbt_result r{};
       if (!S.solve(b.p, x.p, false, &r, c->stream)) worst = PBT_E_NOCONVERGE;
+      phase("solve");
       c->cs.iters = std::max(c->cs.iters, r.iters);
       std::vector<pbt_result> e = S.energies_by_group(x.p, G, c->stream);
       for (int g = 0; g < G; ++g) F_int[b0 + g] = e[g].F_total - f_iso;
+      phase("energies");
       stats_account(c, S, 0, 0);
       if (c->profile) S.add_profile(c->prof_batch);
     }

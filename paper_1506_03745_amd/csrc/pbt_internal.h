@@ -157,6 +157,17 @@ template <typename T>
 // partials [slot][32][2].
 void launch_p2p(const Task* tasks, int npairs, const int32_t* ranges, const T* tgt, const T* src,
                 T kappa, bool guard, T* partial, hipStream_t s);
+// P2P tasks between surfaces shared by G groups: each task (group 0's
+// targets and source ranges) is evaluated for every group g, with group g's
+// source strengths (group 0's sources shifted by goff[g] panels of K points)
+// and written to partial slot mslot[task.slot * G + g]; nrm holds the
+// panels' unit normals (FP64).
+// Groups served by one shared-surface task (Task::split = its first group).
+constexpr int kMultiBlock = 16;
+template <typename T>
+void launch_p2p_multi(const Task* tasks, int npairs, const int32_t* ranges, const T* tgt, const T* src,
+                      const double* nrm, int K, const int32_t* goff, const int32_t* mslot, int G, T kappa,
+                      bool guard, T* partial, hipStream_t s);
 struct CombineArgs {
   int64_t np;
   const ChunkSlots* chunks; int nchunks;

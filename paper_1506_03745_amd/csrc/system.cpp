@@ -28,6 +28,25 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Wall time of the set-up phases, printed to stderr when PBT_SETUP_TIMES is
+// set in the environment (the stream is drained at each mark so that device
+// work is charged to its own phase).
+struct PhaseClock {
+  bool on = std::getenv("PBT_SETUP_TIMES") != nullptr;
+  double t = now_s();
+  void mark(const char* what, hipStream_t s) {
+    if (!on) return;
+    PBT_HIP(hipStreamSynchronize(s));
+    mark_host(what);
+  }
+  void mark_host(const char* what) {
+    if (!on) return;
+    const double u = now_s();
+    std::fprintf(stderr, "[setup] %-16s %8.2f ms\n", what, 1e3 * (u - t));
+    t = u;
+  }
+};
+
 }  // namespace
 
 System::System(const std::vector<const SurfIn*>& surfs, const pbt_params& prm, double eps_out,
@@ -119,6 +138,7 @@ void System::task_form(int t, int src, int32_t& fused, int16_t& tform) const {
 
 void System::build(hipStream_t s) {
   const int ns = (int)surfs_.size();
+  PhaseClock clk;
   build_regions();
   // ---- offsets, trees ------------------------------------------------------
   poff_.assign(ns + 1, 0);
@@ -145,6 +165,7 @@ void System::build(hipStream_t s) {
   np_ = poff_[ns];
   n_ = col_off_[ns];
   ns_ = np_ * K_;
+  clk.mark("trees", s);
   {
     std::map<int, int64_t> gp;   // panels per group
     for (int e = 0; e < ns; ++e) gp[surfs_[e]->group] += surfs_[e]->nt;
@@ -160,7 +181,38 @@ void System::build(hipStream_t s) {
   }
 
   // ---- internal-order triangles ---------------------------------------------
-  std::vector<double> tri9(9 * np_);
+  clk.mark("counts", s);
+  std::vector<double> bf, wf, bn, wn, gt, gw;
+  if (!triangle_rule(prm_.k_far, bf, wf)) throw Error(1, "k_far must be 1, 3, 4 or 7");
+  if (!triangle_rule(prm_.k_near, bn, wn)) throw Error(1, "k_near must be 19 (or 1, 3, 4, 7)");
+  gauss_legendre01(prm_.k_self_edge, gt, gw);
+  // Host copies of the centroids, areas and Gauss points, in the same
+  // sequence of correctly rounded operations as the device's geometry
+  // kernels (so they agree bit for bit), formed while the triangles are
+  // gathered instead of read back.
+  std::unique_ptr<double[]> tri9(new double[9 * (size_t)np_]);
+  std::unique_ptr<double[]> hsrc(new double[3 * (size_t)ns_]);
+  h_cen_.resize(3 * np_);
+  h_area_.resize(np_);
+  const double third = 1.0 / 3.0;
+  auto host_geometry = [&](int64_t g) {
+    const double* v = &tri9[9 * g];
+    const double e1x = v[3] - v[0], e1y = v[4] - v[1], e1z = v[5] - v[2];
+    const double e2x = v[6] - v[0], e2y = v[7] - v[1], e2z = v[8] - v[2];
+    const double cx = e1y * e2z - e1z * e2y;
+    const double cy = e1z * e2x - e1x * e2z;
+    const double cz = e1x * e2y - e1y * e2x;
+    h_area_[g] = 0.5 * std::sqrt((cx * cx + cy * cy) + cz * cz);
+    for (int d = 0; d < 3; ++d) h_cen_[3 * g + d] = ((v[d] + v[3 + d]) + v[6 + d]) * third;
+    for (int q = 0; q < K_; ++q) {
+      const double b0 = bf[3 * q], b1 = bf[3 * q + 1], b2 = bf[3 * q + 2];
+      double* p = &hsrc[3 * (g * K_ + q)];
+      if (b0 == third && b1 == third && b2 == third)
+        for (int d = 0; d < 3; ++d) p[d] = ((v[d] + v[3 + d]) + v[6 + d]) * third;
+      else
+        for (int d = 0; d < 3; ++d) p[d] = (b0 * v[d] + b1 * v[3 + d]) + b2 * v[6 + d];
+    }
+  };
   h_panel_orig_.resize(np_);
   std::vector<int32_t> col_phi(np_), col_psi(np_), row_int(np_), row_sol(np_), psurf(np_);
   std::vector<double> dscale(np_), ksig(np_, 0.0), kmu(np_, 0.0);
@@ -172,6 +224,7 @@ void System::build(hipStream_t s) {
       h_panel_orig_[g] = o;
       for (int v = 0; v < 3; ++v)
         for (int d = 0; d < 3; ++d) tri9[9 * g + 3 * v + d] = S.xyz[3 * S.tri[3 * o + v] + d];
+      host_geometry(g);
       psurf[g] = e;
       switch (S.kind) {
         case PBT_MOLECULE:
@@ -199,6 +252,7 @@ void System::build(hipStream_t s) {
       }
     }
   });
+  clk.mark("tri9", s);
   {
     // The unknowns (and rows) of a surface follow its panels' internal order;
     // the boundary's layout follows the original order: u2i maps a boundary
@@ -214,7 +268,7 @@ void System::build(hipStream_t s) {
     }
     u2i_.upload(u2i, s);
   }
-  tri9_.upload(tri9, s);
+  tri9_.upload(tri9.get(), 9 * (size_t)np_, s);
   col_phi_.upload(col_phi, s);
   col_psi_.upload(col_psi, s);
   row_int_.upload(row_int, s);
@@ -236,6 +290,7 @@ void System::build(hipStream_t s) {
   surf_mol_.upload(smol, s);
   surf_rhoinv_.upload(srho, s);
   forms_.upload(h_forms_, s);
+  clk.mark("maps upload", s);
 
   // ---- geometry and sources on the device ------------------------------------
   cen_.alloc(3 * np_);
@@ -243,10 +298,6 @@ void System::build(hipStream_t s) {
   area_.alloc(np_);
   cross2_.alloc(np_);
   launch_panel_geometry(np_, tri9_.p, cen_.p, nrm_.p, area_.p, cross2_.p, s);
-  std::vector<double> bf, wf, bn, wn, gt, gw;
-  if (!triangle_rule(prm_.k_far, bf, wf)) throw Error(1, "k_far must be 1, 3, 4 or 7");
-  if (!triangle_rule(prm_.k_near, bn, wn)) throw Error(1, "k_near must be 19 (or 1, 3, 4, 7)");
-  gauss_legendre01(prm_.k_self_edge, gt, gw);
   // the rules on the device, kept for later near-correction tables
   qtab_[0].upload(bf, s);
   qtab_[1].upload(wf, s);
@@ -258,9 +309,15 @@ void System::build(hipStream_t s) {
   src_pos_.alloc(3 * ns_);
   src_wa_.alloc(ns_);
   launch_sources(np_, K_, tri9_.p, nrm_.p, area_.p, dbf.p, dwf.p, src_pos_.p, src_wa_.p, s);
-  h_cen_ = cen_.download(s);
-  h_area_ = area_.download(s);
-  std::vector<double> hsrc = src_pos_.download(s);
+  clk.mark("geom kernels", s);
+  if (std::getenv("PBT_CHECK_HOST_GEOMETRY")) {
+    // the host's centroids, areas and Gauss points against the device's
+    const std::vector<double> dc = cen_.download(s), da = area_.download(s), ds = src_pos_.download(s);
+    if (std::memcmp(dc.data(), h_cen_.data(), dc.size() * sizeof(double)) != 0 ||
+        std::memcmp(da.data(), h_area_.data(), da.size() * sizeof(double)) != 0 ||
+        std::memcmp(ds.data(), hsrc.get(), ds.size() * sizeof(double)) != 0)
+      throw Error(PBT_E_STATE, "host and device panel geometry differ");
+  }
   tgt64_.alloc(4 * np_);
   tgt32_.alloc(4 * np_);
   src64_.alloc(kSrcStride * ns_);
@@ -269,6 +326,7 @@ void System::build(hipStream_t s) {
   sig_.alloc(np_);
   mu_.alloc(np_);
 
+  clk.mark("geometry", s);
   // ---- tree geometry (global box numbering) --------------------------------
   boff_.assign(ns + 1, 0);
   parallel_for(ns, [&](int64_t e) {
@@ -307,6 +365,7 @@ void System::build(hipStream_t s) {
     leaf_boxes_.upload(leaves, s);
     nleaf_ = (int)leaves.size();
   }
+  clk.mark("tree geometry", s);
   // ---- near / self corrections for the collocation points ------------------
   {
     // candidate panel ranges per target leaf: boxes of the same group whose
@@ -358,6 +417,7 @@ void System::build(hipStream_t s) {
       lptr.push_back((int64_t)lrange.size() / 2);
     }
     if (lrange.empty()) lrange = {0, 0};
+    clk.mark("near candidates", s);
     DBuf<int32_t> dtleaf;
     DBuf<int64_t> dlptr, dlrange;
     dtleaf.upload(tleaf, s);
@@ -368,6 +428,7 @@ void System::build(hipStream_t s) {
     launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, near_f4(prm_.near_factor),
                       cnt.p, s);
     std::vector<int32_t> hc = cnt.download(s);
+    clk.mark(" near count", s);
     std::vector<int64_t> ptr(np_ + 1, 0);
     for (int64_t i = 0; i < np_; ++i) ptr[i + 1] = ptr[i] + hc[i];
     near_.nnz = ptr[np_];
@@ -376,6 +437,7 @@ void System::build(hipStream_t s) {
     near_.val.alloc(4 * std::max<int64_t>(near_.nnz, 1));
     launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, near_f4(prm_.near_factor),
                      near_.ptr.p, near_.col.p, s);
+    clk.mark(" near fill", s);
     std::vector<int32_t> self(np_);
     for (int64_t i = 0; i < np_; ++i) self[i] = (int32_t)i;
     DBuf<int32_t> dself;
@@ -385,6 +447,7 @@ void System::build(hipStream_t s) {
                        near_.val.p, s);
     launch_fold_near(np_, near_.ptr.p, near_.col.p, panel_surf_.p, panel_surf_.p, forms_.p, ns,
                      surf_rhoinv_.p, near_.val.p, s);
+    clk.mark(" near values", s);
     near_.val32.alloc(near_.val.n);
     launch_to_f32((int64_t)near_.val.n, near_.val.p, near_.val32.p, s);
     // inverse self blocks: the right block-Jacobi preconditioner of GMRES
@@ -392,10 +455,13 @@ void System::build(hipStream_t s) {
     launch_self_blocks(np_, tri9_.p, cen_.p, panel_surf_.p, forms_.p, ns, surf_rhoinv_.p, dens_scale_.p, col_phi_.p,
                        col_psi_.p, np, pinv_.p, s);
     PBT_HIP(hipStreamSynchronize(s));
+    clk.mark("near values", s);
   }
 
   build_plan();
+  clk.mark("plan", s);
   upload_plan(s);
+  clk.mark("plan upload", s);
   // Moments of every box that some M2P task reads and of all its
   // descendants: the leaves from their own sources (P2M), in chunks of at
   // most kMomChunk sources; every other box from its leaves' moments, each
@@ -535,6 +601,7 @@ void System::build(hipStream_t s) {
     msum32_.alloc(std::max<size_t>(slots, 1) * 2 * NC);
     msum64_.alloc(std::max<size_t>(slots, 1) * 2 * NC);
   }
+  clk.mark("moment lists", s);
 }
 
 // Host-side bounds check of the work lists before any kernel reads them:
@@ -588,6 +655,35 @@ void System::check_plan() const {
   };
   check_p2p(P.p2p, true);
   check_m2p(P.m2p, true);
+  if (!P.p2pm.empty()) {
+    const int G = P.mgroups;
+    if (G < 1 || (int)P.goff.size() != G) bad("shared-surface groups");
+    if (P.p2pm.size() % 2) bad("odd number of shared-surface half tasks");
+    const int64_t rows = (int64_t)P.mslot.size() / G;
+    if ((int64_t)P.mslot.size() != rows * G) bad("shared-surface slot table");
+    for (size_t w = 0; w < P.p2pm.size(); ++w) {
+      const Task& t = P.p2pm[w];
+      if (t.split != P.p2pm[w ^ 1].split) bad("shared-surface halves of one wave differ");
+      if (t.fused || (t.form & kFormKz) || !t.known) bad("shared-surface task kind");
+      if (t.tcount < 0 || t.tcount > 32) bad("shared-surface target count");
+      if (!(0 <= t.lbeg && t.lbeg <= t.lend && t.lend <= nr)) bad("shared-surface range list out of bounds");
+      int64_t nsrc = 0;
+      for (int32_t r = t.lbeg; r < t.lend; ++r) nsrc += P.ranges[2 * r + 1] - P.ranges[2 * r];
+      if (nsrc != t.nsrc) bad("shared-surface source count");
+      if (t.tcount == 0) continue;
+      if (t.tbeg < 0 || (int64_t)t.tbeg + t.tcount > np_) bad("shared-surface targets out of bounds");
+      if (t.slot < 0 || t.slot >= rows) bad("shared-surface slot row out of bounds");
+      if (t.split < 0 || t.split >= G || t.split % kMultiBlock) bad("shared-surface group block");
+      for (int g = t.split; g < std::min(G, t.split + kMultiBlock); ++g) {
+        const int64_t off = (int64_t)P.goff[g] * K_;
+        for (int32_t r = t.lbeg; r < t.lend; ++r)
+          if (P.ranges[2 * r] + off < 0 || P.ranges[2 * r + 1] + off > ns_) bad("shared-surface sources out of bounds");
+        const int32_t sl = P.mslot[(int64_t)t.slot * G + g];
+        if (sl < 0 || sl >= P.npslots) bad("shared-surface slot out of bounds");
+        if (++written[sl] != 1) bad("shared-surface slot written twice");
+      }
+    }
+  }
   for (int32_t v : written)
     if (v != 1) bad("partial slot never written");
   check_p2p(P.p2p_known, false);
@@ -612,6 +708,9 @@ void System::upload_plan(hipStream_t s) {
   dp2p_known_.upload(plan_.p2p_known.empty() ? std::vector<Task>(1) : plan_.p2p_known, s);
   dm2p_known_.upload(plan_.m2p_known.empty() ? std::vector<Task>(1) : plan_.m2p_known, s);
   dranges_.upload(plan_.ranges.empty() ? std::vector<int32_t>{0, 0} : plan_.ranges, s);
+  dp2pm_.upload(plan_.p2pm.empty() ? std::vector<Task>(1) : plan_.p2pm, s);
+  dmslot_.upload(plan_.mslot.empty() ? std::vector<int32_t>{0} : plan_.mslot, s);
+  dgoff_.upload(plan_.goff.empty() ? std::vector<int32_t>{0} : plan_.goff, s);
   dblist_.upload(plan_.blist.empty() ? std::vector<int32_t>{0} : plan_.blist, s);
   dchunks_.upload(plan_.chunks, s);
   dchunk_of_.upload(plan_.chunk_of, s);
@@ -668,6 +767,7 @@ void System::build_plan() {
   Plan& P = plan_;
   P = Plan{};
   const int ns = (int)surfs_.size();
+  PhaseClock clk;
   // Target groups: each leaf's panels in runs of at most kGroup = 32 (half a
   // wavefront; spatially compact in the leaf's octant order), every group
   // with the sphere of its own collocation points, so the acceptance test is
@@ -702,6 +802,7 @@ void System::build_plan() {
         leaves.push_back({e, (int)b, g});
       }
     }
+  clk.mark_host(" groups");
   leaves_.clear();
   for (const LeafRef& l : leaves) leaves_.push_back({l.e, l.b, poff_[l.e] + l.tb.pbeg, poff_[l.e] + l.tb.pend});
   // the surfaces of each group (a leaf only interacts with its own group's)
@@ -714,16 +815,76 @@ void System::build_plan() {
   lp2p_.assign(leaves.size(), {});
   lm2p_.assign(leaves.size(), {});
 
+  // Surfaces that every group holds unmoved (copies with one `shared` id, in
+  // the same place in each group's panel layout, without an interior row):
+  // the P2P pairs between them are the same in every group up to the source
+  // strengths, so they go to tasks on group 0's copies that serve all groups
+  // at once (P.p2pm).  Anything that does not fit leaves them to the usual
+  // per-group tasks.
+  const int ngroups = (int)group_surfs_.size();
+  std::vector<int32_t> lfirst(ns + 1, 0);   // first target group of each surface
+  for (const LeafRef& l : leaves) ++lfirst[l.e + 1];
+  for (int e = 0; e < ns; ++e) lfirst[e + 1] += lfirst[e];
+  std::vector<char> mshared(ns, 0);
+  std::vector<std::map<int, int>> copy_in(ngroups);   // per group: shared id -> surface
+  std::vector<int32_t> goff(ngroups, 0);
+  bool multi = false;
+  if (ngroups >= 2) {
+    multi = true;
+    for (int e = 0; e < ns; ++e)
+      if (surfs_[e]->shared >= 0 && !two_rows(e)) {
+        auto& m = copy_in[surfs_[e]->group];
+        if (m.count(surfs_[e]->shared)) multi = false;   // one copy per group
+        m[surfs_[e]->shared] = e;
+      }
+    if (copy_in[0].empty()) multi = false;
+    for (int g = 0; multi && g < ngroups; ++g) {
+      if (copy_in[g].size() != copy_in[0].size()) multi = false;
+      bool first = true;
+      for (const auto& kv : copy_in[0]) {
+        auto it = copy_in[g].find(kv.first);
+        if (it == copy_in[g].end()) { multi = false; break; }
+        const int e0 = kv.second, e = it->second;
+        const int64_t d = poff_[e] - poff_[e0];
+        if (first) goff[g] = (int32_t)d;
+        first = false;
+        const SurfTree& A = trees_[e0];
+        const SurfTree& B = trees_[e];
+        bool same = d == goff[g] && surfs_[e]->nt == surfs_[e0]->nt && surfs_[e]->kind == surfs_[e0]->kind &&
+                    A.boxes.size() == B.boxes.size() && lfirst[e + 1] - lfirst[e] == lfirst[e0 + 1] - lfirst[e0];
+        for (size_t k = 0; same && k < A.boxes.size(); ++k)
+          same = A.boxes[k].pbeg == B.boxes[k].pbeg && A.boxes[k].pend == B.boxes[k].pend &&
+                 A.boxes[k].leaf == B.boxes[k].leaf;
+        for (int64_t k = 0; same && k < surfs_[e]->nt; ++k) same = trees_[e].perm[k] == trees_[e0].perm[k];
+        if (!same) multi = false;
+      }
+    }
+    for (int g = 0; multi && g < ngroups; ++g)
+      for (const auto& kv : copy_in[g]) {
+        mshared[kv.second] = 1;
+        for (const auto& kw : copy_in[g]) {
+          int32_t fu = 0;
+          int16_t tf = 0;
+          task_form(kv.second, kw.second, fu, tf);
+          if (fu || (tf & kFormKz)) multi = false;
+        }
+      }
+    if (!multi) std::fill(mshared.begin(), mshared.end(), 0);
+  }
+
   // Per target group and source surface of its group of surfaces (k-th of
   // group_surfs_): merged P2P source ranges and M2P boxes.
   struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
   std::vector<std::vector<Lists>> L(leaves.size());
   // (per target group in parallel; the counts are added up afterwards)
-  std::vector<std::array<int64_t, 6>> cnt(leaves.size(), {0, 0, 0, 0, 0, 0});
+  std::vector<std::array<int64_t, 7>> cnt(leaves.size(), {0, 0, 0, 0, 0, 0, 0});
   parallel_for((int64_t)leaves.size(), [&](int64_t li) {
     const TreeBox& tl = leaves[li].tb;
     const int64_t nt = tl.pend - tl.pbeg;
-    std::array<int64_t, 6>& c = cnt[li];   // tot_src, tot_box, p2p, m2p, fused p2p, fused m2p
+    // tot_src (pairs of shared surfaces left out), tot_box, p2p, m2p, fused
+    // p2p, fused m2p, group 0's sources of shared-surface pairs
+    std::array<int64_t, 7>& c = cnt[li];
+    const bool g0 = surfs_[leaves[li].e]->group == 0;
     const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
     L[li].resize(gsf.size());
     lp2p_[li].resize(gsf.size());
@@ -745,7 +906,8 @@ void System::build_plan() {
         const int32_t j0 = (int32_t)((poff_[e2] + sb.pbeg) * K_), j1 = (int32_t)((poff_[e2] + sb.pend) * K_);
         if (!o.rng.empty() && o.rng.back().second == j0) o.rng.back().second = j1;
         else o.rng.push_back({j0, j1});
-        c[0] += (int64_t)(j1 - j0);
+        if (!(mshared[leaves[li].e] && mshared[e2])) c[0] += (int64_t)(j1 - j0);
+        else if (g0) c[6] += (int64_t)(j1 - j0);
         c[2] += (int64_t)(j1 - j0) * nt;
         if (fused_pair) c[4] += (int64_t)(j1 - j0) * nt;
       }
@@ -762,9 +924,11 @@ void System::build_plan() {
       lm2p_[li][k2] = std::move(mb);
     }
   });
-  int64_t tot_src = 0, tot_box = 0;
+  clk.mark_host(" lists");
+  int64_t tot_src = 0, tot_box = 0, tot_shared = 0;
   for (const auto& c : cnt) {
     tot_src += c[0];
+    tot_shared += c[6];
     tot_box += c[1];
     P.p2p_pairs += c[2];
     P.m2p_pairs += c[3];
@@ -778,6 +942,10 @@ void System::build_plan() {
   const int64_t seg_box = seg_box_ > 0 ? seg_box_ : std::min<int64_t>(64, std::max<int64_t>(2, tot_box / want));
   seg_src_used_ = seg_src;
   seg_box_used_ = seg_box;
+  // shared-surface segments: each serves kMultiBlock groups of every task,
+  // so as many half tasks again from group 0's sources alone
+  const int64_t mblocks = multi ? (ngroups + kMultiBlock - 1) / kMultiBlock : 1;
+  const int64_t seg_m = std::min<int64_t>(16384, std::max<int64_t>(128, tot_shared * mblocks / want));
 
   // Chunks (numbered per group of surfaces too, for the Gram-Schmidt
   // partials): a group that starts a 64-target run of its leaf opens a chunk
@@ -809,39 +977,68 @@ void System::build_plan() {
     if (half_of_leaf[li] == 0 && half_of_leaf[li + 1] == 1 && leaves[li].tb.pend - leaves[li].tb.pbeg == 32 &&
         leaves[li + 1].tb.pend - leaves[li + 1].tb.pbeg == 32)
       full_first[li] = 1;
-  // Segments per (leaf, source surface).
-  struct Seg { int32_t lbeg, lend; int e2; bool m2p; };   // e2: the source surface
+  // Segments per (leaf, source surface): each group's ranges and boxes cut
+  // into its own arrays in parallel, then laid end to end in group order.
+  struct Seg { int32_t lbeg, lend; int e2; bool m2p; bool shared = false; };   // e2: the source surface
   std::vector<std::vector<Seg>> segs(leaves.size());
-  for (size_t li = 0; li < leaves.size(); ++li) {
+  std::vector<std::vector<int32_t>> lranges(leaves.size()), lblist(leaves.size());
+  parallel_for((int64_t)leaves.size(), [&](int64_t li) {
     const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
+    std::vector<int32_t>& rg_out = lranges[li];
+    std::vector<int32_t>& bl_out = lblist[li];
     for (size_t k2 = 0; k2 < gsf.size(); ++k2) {
       const int e2 = gsf[k2];
       const Lists& o = L[li][k2];
+      const bool shp = mshared[leaves[li].e] && mshared[e2];
+      const int64_t seg = shp ? seg_m : seg_src;
       int64_t acc = 0;
-      int32_t start = (int32_t)(P.ranges.size() / 2);
+      int32_t start = (int32_t)(rg_out.size() / 2);
       for (auto rg : o.rng) {
         for (int32_t a = rg.first; a < rg.second;) {
-          const int32_t b = (int32_t)std::min<int64_t>(rg.second, a + (seg_src - acc));
-          P.ranges.push_back(a);
-          P.ranges.push_back(b);
+          const int32_t b = (int32_t)std::min<int64_t>(rg.second, a + (seg - acc));
+          rg_out.push_back(a);
+          rg_out.push_back(b);
           acc += b - a;
           a = b;
-          if (acc >= seg_src) {
-            segs[li].push_back({start, (int32_t)(P.ranges.size() / 2), e2, false});
-            start = (int32_t)(P.ranges.size() / 2);
+          if (acc >= seg) {
+            segs[li].push_back({start, (int32_t)(rg_out.size() / 2), e2, false});
+            start = (int32_t)(rg_out.size() / 2);
             acc = 0;
           }
         }
       }
-      if ((int32_t)(P.ranges.size() / 2) > start)
-        segs[li].push_back({start, (int32_t)(P.ranges.size() / 2), e2, false});
+      if ((int32_t)(rg_out.size() / 2) > start) segs[li].push_back({start, (int32_t)(rg_out.size() / 2), e2, false});
+      if (shp)
+        for (Seg& sg : segs[li])
+          if (sg.e2 == e2 && !sg.m2p) sg.shared = true;
       for (size_t k = 0; k < o.box.size(); k += seg_box) {
-        const int32_t b0 = (int32_t)P.blist.size();
-        for (size_t q = k; q < std::min(o.box.size(), (size_t)(k + seg_box)); ++q) P.blist.push_back(o.box[q]);
-        segs[li].push_back({b0, (int32_t)P.blist.size(), e2, true});
+        const int32_t b0 = (int32_t)bl_out.size();
+        for (size_t q = k; q < std::min(o.box.size(), (size_t)(k + seg_box)); ++q) bl_out.push_back(o.box[q]);
+        segs[li].push_back({b0, (int32_t)bl_out.size(), e2, true});
       }
     }
+  });
+  {
+    std::vector<int64_t> roff(leaves.size() + 1, 0), boff(leaves.size() + 1, 0);
+    for (size_t li = 0; li < leaves.size(); ++li) {
+      roff[li + 1] = roff[li] + (int64_t)lranges[li].size();
+      boff[li + 1] = boff[li] + (int64_t)lblist[li].size();
+    }
+    if (roff.back() / 2 > INT32_MAX || boff.back() > INT32_MAX)
+      throw Error(PBT_E_NOMEM, "interaction lists exceed 32-bit indexing");
+    P.ranges.resize(roff.back());
+    P.blist.resize(boff.back());
+    parallel_for((int64_t)leaves.size(), [&](int64_t li) {
+      std::copy(lranges[li].begin(), lranges[li].end(), P.ranges.begin() + roff[li]);
+      std::copy(lblist[li].begin(), lblist[li].end(), P.blist.begin() + boff[li]);
+      for (Seg& sg : segs[li]) {
+        const int32_t d = (int32_t)(sg.m2p ? boff[li] : roff[li] / 2);
+        sg.lbeg += d;
+        sg.lend += d;
+      }
+    });
   }
+  clk.mark_host(" segments");
   // Slots: every task of a group writes one half-wave partial slot
   // [slot][32][2]; per chunk half, the group's P2P slots then its M2P slots
   // (a chunk's combine reads hbeg0..hend0 for its first 32 targets,
@@ -896,7 +1093,8 @@ void System::build_plan() {
         const size_t lj = li + h;
         if (h == 1 && !(lj < leaves.size() && half_of_leaf[lj] == 1)) break;
         for (size_t si = 0; si < segs[lj].size(); ++si)
-          (segs[lj][si].m2p ? mspare : spare).push_back(make_task(lj, segs[lj][si], slot0[lj] + (int)si));
+          if (!segs[lj][si].shared)
+            (segs[lj][si].m2p ? mspare : spare).push_back(make_task(lj, segs[lj][si], slot0[lj] + (int)si));
       }
       continue;
     }
@@ -906,9 +1104,10 @@ void System::build_plan() {
       for (int m = 0; m < 2; ++m) {
         std::vector<std::pair<size_t, int>> sa, sb;   // (segment index, slot)
         for (size_t si = 0; si < segs[li].size(); ++si)
-          if (segs[li][si].e2 == e2 && segs[li][si].m2p == (m == 1)) sa.push_back({si, slot0[li] + (int)si});
+          if (segs[li][si].e2 == e2 && segs[li][si].m2p == (m == 1) && !segs[li][si].shared)
+            sa.push_back({si, slot0[li] + (int)si});
         for (size_t si = 0; si < segs[li + 1].size(); ++si)
-          if (segs[li + 1][si].e2 == e2 && segs[li + 1][si].m2p == (m == 1))
+          if (segs[li + 1][si].e2 == e2 && segs[li + 1][si].m2p == (m == 1) && !segs[li + 1][si].shared)
             sb.push_back({si, slot0[li + 1] + (int)si});
         std::vector<Task>& out = m ? P.m2p : P.p2p;
         std::vector<Task>& rest = m ? mspare : spare;
@@ -954,8 +1153,105 @@ void System::build_plan() {
       }
     }
   };
+  clk.mark_host(" tasks");
   pair_up(spare, P.p2p, true);
   pair_up(mspare, P.m2p, false);
+  clk.mark_host(" pairing");
+  if (multi) {
+    // shared-surface tasks on group 0's target groups; row r of mslot holds
+    // the slot of the same segment in every group (the k-th shared segment
+    // of group g's copy of the target group, whose ranges are group 0's
+    // shifted by goff[g] panels)
+    P.mgroups = ngroups;
+    P.goff = goff;
+    // per group-0 target group in parallel (its rows of mslot and tasks,
+    // rows numbered locally), then laid end to end
+    std::vector<int64_t> mleaves;
+    for (size_t li = 0; li < leaves.size(); ++li)
+      if (mshared[leaves[li].e] && surfs_[leaves[li].e]->group == 0) mleaves.push_back((int64_t)li);
+    std::vector<std::vector<int32_t>> lrows(mleaves.size());
+    std::vector<std::vector<Task>> ltasks(mleaves.size());
+    std::vector<const char*> lerr(mleaves.size(), nullptr);
+    parallel_for((int64_t)mleaves.size(), [&](int64_t m) {
+      const size_t li = (size_t)mleaves[m];
+      const int e0 = leaves[li].e;
+      std::vector<int> s0;
+      for (size_t si = 0; si < segs[li].size(); ++si)
+        if (segs[li][si].shared) s0.push_back((int)si);
+      if (s0.empty()) return;
+      std::vector<size_t> lg(ngroups);
+      std::vector<std::vector<int>> sg(ngroups);
+      for (int g = 0; g < ngroups; ++g) {
+        const int e = copy_in[g].at(surfs_[e0]->shared);
+        lg[g] = (size_t)(lfirst[e] + ((int64_t)li - lfirst[e0]));
+        if (lg[g] >= leaves.size() || leaves[lg[g]].e != e || leaves[lg[g]].tb.pbeg != leaves[li].tb.pbeg ||
+            leaves[lg[g]].tb.pend != leaves[li].tb.pend) {
+          lerr[m] = "shared surfaces: target groups differ between groups";
+          return;
+        }
+        for (size_t si = 0; si < segs[lg[g]].size(); ++si)
+          if (segs[lg[g]][si].shared) sg[g].push_back((int)si);
+        if (sg[g].size() != s0.size()) {
+          lerr[m] = "shared surfaces: lists differ between groups";
+          return;
+        }
+      }
+      for (size_t k = 0; k < s0.size(); ++k) {
+        const Seg& a0 = segs[li][s0[k]];
+        const int row = (int)(lrows[m].size() / ngroups);
+        for (int g = 0; g < ngroups; ++g) {
+          const Seg& ag = segs[lg[g]][sg[g][k]];
+          const int64_t off = (int64_t)goff[g] * K_;
+          bool same = ag.lend - ag.lbeg == a0.lend - a0.lbeg && mshared[ag.e2] &&
+                      surfs_[ag.e2]->shared == surfs_[a0.e2]->shared;
+          for (int32_t q = 0; same && q < a0.lend - a0.lbeg; ++q)
+            same = P.ranges[2 * (ag.lbeg + q)] == P.ranges[2 * (a0.lbeg + q)] + off &&
+                   P.ranges[2 * (ag.lbeg + q) + 1] == P.ranges[2 * (a0.lbeg + q) + 1] + off;
+          if (!same) {
+            lerr[m] = "shared surfaces: source ranges differ between groups";
+            return;
+          }
+          lrows[m].push_back(slot0[lg[g]] + sg[g][k]);
+        }
+        // one task per block of kMultiBlock groups (split = its first group)
+        for (int gb = 0; gb < ngroups; gb += kMultiBlock) {
+          Task t = make_task(li, a0, row);
+          t.split = gb;
+          ltasks[m].push_back(t);
+        }
+      }
+    });
+    std::vector<Task> mt;
+    for (size_t m = 0; m < mleaves.size(); ++m) {
+      if (lerr[m]) throw Error(PBT_E_STATE, lerr[m]);
+      const int base = (int)(P.mslot.size() / ngroups);
+      P.mslot.insert(P.mslot.end(), lrows[m].begin(), lrows[m].end());
+      for (Task t : ltasks[m]) {
+        t.slot += base;
+        mt.push_back(t);
+      }
+    }
+    // the two halves of a wavefront serve the same block of groups
+    std::stable_sort(mt.begin(), mt.end(), [](const Task& a, const Task& b) {
+      return a.split != b.split ? a.split < b.split : a.nsrc > b.nsrc;
+    });
+    for (size_t k = 0; k < mt.size();) {
+      P.p2pm.push_back(mt[k]);
+      if (k + 1 < mt.size() && mt[k + 1].split == mt[k].split) {
+        P.p2pm.push_back(mt[k + 1]);
+        k += 2;
+      } else {
+        Task empty = mt[k];   // same group block
+        empty.tcount = 0;
+        empty.lbeg = empty.lend = 0;
+        empty.nsrc = 0;
+        empty.slot = 0;
+        P.p2pm.push_back(empty);
+        k += 1;
+      }
+    }
+  }
+  clk.mark_host(" shared tasks");
   // The right-hand side's product: only the tasks whose sources carry known
   // densities (a wavefront pair stays together, its other half emptied); the
   // partial slots of the others are cleared before that product.
@@ -975,6 +1271,7 @@ void System::build_plan() {
   };
   known_only(P.p2p, P.p2p_known);
   known_only(P.m2p, P.m2p_known);
+  clk.mark_host(" known lists");
   if (std::getenv("PBT_PLAN_STATS")) {
     // lane utilisation of the P2P wavefronts: pair evaluations issued (64
     // lanes x records per round x rounds) against useful target x source pairs
@@ -1006,6 +1303,19 @@ void System::build_plan() {
         hist[n < 16 ? 0 : n < 32 ? 1 : n < 64 ? 2 : n < 128 ? 3 : n < 256 ? 4 : 5] += t.tcount;
       }
     }
+    // pairs whose target and source surfaces both lack an interior row
+    // (plates: the same in every placement of a batch)
+    std::vector<char> known_panel(np_, 0);
+    for (int e = 0; e < ns; ++e)
+      for (int64_t k = poff_[e]; k < poff_[e + 1]; ++k) known_panel[k] = !two_rows(e);
+    int64_t kk_p2p = 0, kk_m2p = 0;
+    for (const Task& t : P.p2p)
+      if (t.tcount > 0 && known_panel[t.tbeg] && t.known) kk_p2p += (int64_t)t.tcount * t.nsrc;
+    for (const Task& t : P.m2p)
+      if (t.tcount > 0 && known_panel[t.tbeg] && t.known) kk_m2p += (int64_t)t.tcount * (t.lend - t.lbeg);
+    std::fprintf(stderr, "[plan] pairs between surfaces without interior rows: p2p %lld, m2p %lld; "
+                 "shared-surface P2P tasks %zu for %d groups\n",
+                 (long long)kk_p2p, (long long)kk_m2p, P.p2pm.size(), P.mgroups);
     std::fprintf(stderr, "[plan] m2p pairs by box sources <16 / <32 / <64 / <128 / <256 / more: "
                  "%lld / %lld / %lld / %lld / %lld / %lld\n", (long long)hist[0], (long long)hist[1],
                  (long long)hist[2], (long long)hist[3], (long long)hist[4], (long long)hist[5]);
@@ -1015,6 +1325,16 @@ void System::build_plan() {
                  (long long)nsplit[2], (long long)nsplit[4], (long long)empty, useful / std::max(issued, 1.0),
                  (long long)P.m2p_pairs, P.m2p.size(), (double)P.m2p_pairs / std::max(missued, 1.0));
   }
+  clk.mark_host(" statistics");
+  // the per-group work vectors, released in parallel (most were allocated
+  // by the worker threads)
+  parallel_for((int64_t)leaves.size(), [&](int64_t li) {
+    std::vector<Lists>().swap(L[li]);
+    std::vector<Seg>().swap(segs[li]);
+    std::vector<int32_t>().swap(lranges[li]);
+    std::vector<int32_t>().swap(lblist[li]);
+  });
+  clk.mark_host(" release");
 }
 
 // Strengths, then P2P on the caller's stream while the far field (P2M,
@@ -1069,6 +1389,13 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   auto pe = [&](int kind, int e0, hipStream_t st) {
     if (e0 >= 0) prof_end(pbase + kind, e0, st);
   };
+  // P2P between surfaces shared by every group: launched right after the
+  // usual P2P tasks on the same stream, inside their timing marks
+  const int nmp = (int)(plan_.p2pm.size() / 2);
+  auto multi = [&](hipStream_t st) {
+    launch_p2p_multi<T>(dp2pm_.p, nmp, dranges_.p, tgt, src, nrm_.p, K_, dgoff_.p, dmslot_.p, plan_.mgroups,
+                        (T)kappa_, guard, ppart, st);
+  };
   // M2M after the leaves' moments (P2M): every (box, leaf) shift, then the
   // sums per box
   const int npr = known_only ? npair_known_ : npair_, nhd = known_only ? nhead_known_ : nhead_;
@@ -1114,6 +1441,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     const int e0 = pb(s);
     launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks, npairs,
                       dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    multi(s);
     pe(0, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
@@ -1128,6 +1456,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     int e0 = pb(s);
     launch_p2p_moments<T>(prm_.taylor_p, nmb, mbl, mch, nmh, mhd, bcen_.p, brho_.p, mom, msum, p2p_tasks, na,
                           dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    multi(s);
     pe(0, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
@@ -1152,6 +1481,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     int e0 = pb(s);
     launch_p2p_moments<T>(prm_.taylor_p, nmb, mbl, mch, nmh, mhd, bcen_.p, brho_.p, mom, msum, p2p_tasks, npairs,
                           dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    multi(s);
     pe(0, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(ev_[3], s));
@@ -1184,6 +1514,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   if (timed) PBT_HIP(hipEventRecord(ev_[2], s));
   const int e0 = pb(s);
   launch_p2p<T>(p2p_tasks, npairs, dranges_.p, tgt, src, (T)kappa_, guard, ppart, s);
+  multi(s);
   pe(0, e0, s);
   if (timed) PBT_HIP(hipEventRecord(ev_[3], s));
   if (two) {

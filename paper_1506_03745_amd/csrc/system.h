@@ -37,6 +37,13 @@ struct DBuf {
     n = m;
   }
   // Synchronous with respect to the host vector: it may be released on return.
+  void upload(const T* v, size_t m, hipStream_t s) {
+    alloc(m);
+    if (m) {
+      PBT_HIP(hipMemcpyAsync(p, v, m * sizeof(T), hipMemcpyHostToDevice, s));
+      PBT_HIP(hipStreamSynchronize(s));
+    }
+  }
   void upload(const std::vector<T>& v, hipStream_t s) {
     alloc(v.size());
     if (!v.empty()) {
@@ -88,6 +95,7 @@ struct SurfIn {
   bool enabled = true;
   int group = 0;  // surfaces of different groups belong to independent systems
   const SurfIn* parent = nullptr;  // Stern surface: the molecule it encloses; cavity: the molecule around it
+  int shared = -1;  // >= 0: a copy, in every group, of one surface that the groups share unmoved
 };
 
 struct NearCSR {
@@ -109,6 +117,13 @@ struct Plan {
   int nbh = 1;       // most target chunks of one group
   int npslots = 0;   // P2P partial slots (32 lanes)
   int64_t p2p_pairs = 0, m2p_pairs = 0, p2p_fused_pairs = 0, m2p_fused_pairs = 0;
+  // P2P between surfaces that every group holds unmoved: tasks on group 0's
+  // copies (pairs of half tasks), each evaluated for all mgroups groups at
+  // once; task.slot is a row of mslot, whose entry g is the partial slot of
+  // group g, and group g's sources are group 0's shifted by goff[g] panels
+  std::vector<Task> p2pm;
+  std::vector<int32_t> mslot, goff;
+  int mgroups = 0;
 };
 
 struct Timing {
@@ -380,6 +395,8 @@ class System {
   DBuf<Task> dp2p_, dm2p_;
   DBuf<Task> dp2p_known_, dm2p_known_;   // the same with tasks of unknown-density sources emptied
   DBuf<int32_t> dranges_, dblist_;
+  DBuf<Task> dp2pm_;
+  DBuf<int32_t> dmslot_, dgoff_;
   DBuf<ChunkSlots> dchunks_;
   DBuf<int32_t> dchunk_of_;
   DBuf<float> part32_, ppart32_;
