@@ -246,6 +246,13 @@ void launch_m2p_p2p(int P, const Task* m2p, int nm2p, const int32_t* blist, cons
 template <typename T>
 void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
                 const double* box_center, const T* mom, T kappa, T* partial, hipStream_t s);
+// M2P tasks between surfaces shared by G groups (like launch_p2p_multi):
+// group g's copy of box b is b + boxoff[task.nsrc * G + g]; each task
+// serves groups split .. split + kMultiBlock - 1.
+template <typename T>
+void launch_m2p_multi(int P, const Task* tasks, int ntasks, const int32_t* blist, const T* tgt,
+                      const double* box_center, const T* mom, const int32_t* boxoff, const int32_t* mslot, int G,
+                      T kappa, T* partial, hipStream_t s);
 
 // --- transpose operator (adjoint.hip) ---------------------------------------
 struct AdjCombineArgs {

@@ -684,6 +684,34 @@ void System::check_plan() const {
       }
     }
   }
+  if (!P.m2pm.empty()) {
+    const int G = P.mgroups;
+    if (G < 1 || P.mboxoff.empty() || P.mboxoff.size() % G) bad("shared-surface box offsets");
+    if (P.m2pm.size() % 2) bad("odd number of shared-surface M2P half tasks");
+    const int64_t rows = (int64_t)P.mslot.size() / G, orows = (int64_t)P.mboxoff.size() / G;
+    for (size_t w = 0; w < P.m2pm.size(); ++w) {
+      const Task& t = P.m2pm[w];
+      if (t.split != P.m2pm[w ^ 1].split || t.nsrc != P.m2pm[w ^ 1].nsrc) bad("shared-surface M2P halves differ");
+      if (t.fused || (t.form & kFormKz) || !t.known) bad("shared-surface M2P task kind");
+      if (t.tcount < 0 || t.tcount > 32) bad("shared-surface M2P target count");
+      if (!(0 <= t.lbeg && t.lbeg <= t.lend && t.lend <= nbl)) bad("shared-surface M2P box list out of bounds");
+      if (t.nsrc < 0 || t.nsrc >= orows) bad("shared-surface M2P offset row");
+      if (t.split < 0 || t.split >= G || t.split % kMultiBlock) bad("shared-surface M2P group block");
+      if (t.tcount == 0) continue;
+      if (t.tbeg < 0 || (int64_t)t.tbeg + t.tcount > np_) bad("shared-surface M2P targets out of bounds");
+      if (t.slot < 0 || t.slot >= rows) bad("shared-surface M2P slot row out of bounds");
+      for (int g = 0; g < G; ++g) {
+        const int32_t off = P.mboxoff[(size_t)t.nsrc * G + g];
+        for (int32_t r = t.lbeg; r < t.lend; ++r)
+          if (P.blist[r] + (int64_t)off < 0 || P.blist[r] + (int64_t)off >= nbox_) bad("shared-surface box out of bounds");
+      }
+      for (int g = t.split; g < std::min(G, t.split + kMultiBlock); ++g) {
+        const int32_t sl = P.mslot[(int64_t)t.slot * G + g];
+        if (sl < 0 || sl >= P.npslots) bad("shared-surface M2P slot out of bounds");
+        if (++written[sl] != 1) bad("shared-surface M2P slot written twice");
+      }
+    }
+  }
   for (int32_t v : written)
     if (v != 1) bad("partial slot never written");
   check_p2p(P.p2p_known, false);
@@ -709,13 +737,15 @@ void System::upload_plan(hipStream_t s) {
   dm2p_known_.upload(plan_.m2p_known.empty() ? std::vector<Task>(1) : plan_.m2p_known, s);
   dranges_.upload(plan_.ranges.empty() ? std::vector<int32_t>{0, 0} : plan_.ranges, s);
   dp2pm_.upload(plan_.p2pm.empty() ? std::vector<Task>(1) : plan_.p2pm, s);
+  dm2pm_.upload(plan_.m2pm.empty() ? std::vector<Task>(1) : plan_.m2pm, s);
+  dmboxoff_.upload(plan_.mboxoff.empty() ? std::vector<int32_t>{0} : plan_.mboxoff, s);
   dmslot_.upload(plan_.mslot.empty() ? std::vector<int32_t>{0} : plan_.mslot, s);
   dgoff_.upload(plan_.goff.empty() ? std::vector<int32_t>{0} : plan_.goff, s);
   dblist_.upload(plan_.blist.empty() ? std::vector<int32_t>{0} : plan_.blist, s);
   dchunks_.upload(plan_.chunks, s);
   dchunk_of_.upload(plan_.chunk_of, s);
   const int NC = ncoef(prm_.taylor_p);
-  if (!plan_.m2p.empty()) {
+  if (!plan_.m2p.empty() || !plan_.m2pm.empty()) {
     mom32_.alloc((size_t)nbox_ * 2 * NC);
     mom64_.alloc((size_t)nbox_ * 2 * NC);
   }
@@ -877,13 +907,14 @@ void System::build_plan() {
   struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
   std::vector<std::vector<Lists>> L(leaves.size());
   // (per target group in parallel; the counts are added up afterwards)
-  std::vector<std::array<int64_t, 7>> cnt(leaves.size(), {0, 0, 0, 0, 0, 0, 0});
+  std::vector<std::array<int64_t, 8>> cnt(leaves.size(), {0, 0, 0, 0, 0, 0, 0, 0});
   parallel_for((int64_t)leaves.size(), [&](int64_t li) {
     const TreeBox& tl = leaves[li].tb;
     const int64_t nt = tl.pend - tl.pbeg;
-    // tot_src (pairs of shared surfaces left out), tot_box, p2p, m2p, fused
-    // p2p, fused m2p, group 0's sources of shared-surface pairs
-    std::array<int64_t, 7>& c = cnt[li];
+    // tot_src and tot_box (pairs of shared surfaces left out), p2p, m2p,
+    // fused p2p, fused m2p, group 0's sources and boxes of shared-surface
+    // pairs
+    std::array<int64_t, 8>& c = cnt[li];
     const bool g0 = surfs_[leaves[li].e]->group == 0;
     const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
     L[li].resize(gsf.size());
@@ -912,7 +943,8 @@ void System::build_plan() {
         if (fused_pair) c[4] += (int64_t)(j1 - j0) * nt;
       }
       for (int b : mb) o.box.push_back((int32_t)(boff_[e2] + b));
-      c[1] += (int64_t)mb.size();
+      if (!(mshared[leaves[li].e] && mshared[e2])) c[1] += (int64_t)mb.size();
+      else if (g0) c[7] += (int64_t)mb.size();
       c[3] += (int64_t)mb.size() * nt;
       {
         int32_t fu = 0;
@@ -925,10 +957,11 @@ void System::build_plan() {
     }
   });
   clk.mark_host(" lists");
-  int64_t tot_src = 0, tot_box = 0, tot_shared = 0;
+  int64_t tot_src = 0, tot_box = 0, tot_shared = 0, tot_shared_box = 0;
   for (const auto& c : cnt) {
     tot_src += c[0];
     tot_shared += c[6];
+    tot_shared_box += c[7];
     tot_box += c[1];
     P.p2p_pairs += c[2];
     P.m2p_pairs += c[3];
@@ -946,6 +979,7 @@ void System::build_plan() {
   // so as many half tasks again from group 0's sources alone
   const int64_t mblocks = multi ? (ngroups + kMultiBlock - 1) / kMultiBlock : 1;
   const int64_t seg_m = std::min<int64_t>(16384, std::max<int64_t>(128, tot_shared * mblocks / want));
+  const int64_t seg_box_m = std::min<int64_t>(64, std::max<int64_t>(2, tot_shared_box * mblocks / want));
 
   // Chunks (numbered per group of surfaces too, for the Gram-Schmidt
   // partials): a group that starts a 64-target run of its leaf opens a chunk
@@ -1008,14 +1042,15 @@ void System::build_plan() {
         }
       }
       if ((int32_t)(rg_out.size() / 2) > start) segs[li].push_back({start, (int32_t)(rg_out.size() / 2), e2, false});
-      if (shp)
-        for (Seg& sg : segs[li])
-          if (sg.e2 == e2 && !sg.m2p) sg.shared = true;
-      for (size_t k = 0; k < o.box.size(); k += seg_box) {
+      const int64_t sbox = shp ? seg_box_m : seg_box;
+      for (size_t k = 0; k < o.box.size(); k += sbox) {
         const int32_t b0 = (int32_t)bl_out.size();
-        for (size_t q = k; q < std::min(o.box.size(), (size_t)(k + seg_box)); ++q) bl_out.push_back(o.box[q]);
+        for (size_t q = k; q < std::min(o.box.size(), (size_t)(k + sbox)); ++q) bl_out.push_back(o.box[q]);
         segs[li].push_back({b0, (int32_t)bl_out.size(), e2, true});
       }
+      if (shp)
+        for (Seg& sg : segs[li])
+          if (sg.e2 == e2) sg.shared = true;
     }
   });
   {
@@ -1169,8 +1204,17 @@ void System::build_plan() {
     std::vector<int64_t> mleaves;
     for (size_t li = 0; li < leaves.size(); ++li)
       if (mshared[leaves[li].e] && surfs_[leaves[li].e]->group == 0) mleaves.push_back((int64_t)li);
+    // box-number offsets of each shared surface's copies (row per shared id)
+    std::map<int, int> sid_index;
+    std::vector<int32_t> boxoff;
+    for (const auto& kv : copy_in[0]) {
+      sid_index[kv.first] = (int)sid_index.size();
+      for (int g = 0; g < ngroups; ++g)
+        boxoff.push_back((int32_t)(boff_[copy_in[g].at(kv.first)] - boff_[kv.second]));
+    }
+    P.mboxoff = boxoff;
     std::vector<std::vector<int32_t>> lrows(mleaves.size());
-    std::vector<std::vector<Task>> ltasks(mleaves.size());
+    std::vector<std::vector<Task>> ltasks(mleaves.size()), ltasksm(mleaves.size());
     std::vector<const char*> lerr(mleaves.size(), nullptr);
     parallel_for((int64_t)mleaves.size(), [&](int64_t m) {
       const size_t li = (size_t)mleaves[m];
@@ -1199,16 +1243,23 @@ void System::build_plan() {
       for (size_t k = 0; k < s0.size(); ++k) {
         const Seg& a0 = segs[li][s0[k]];
         const int row = (int)(lrows[m].size() / ngroups);
+        const int sidx = sid_index.at(surfs_[a0.e2]->shared);
         for (int g = 0; g < ngroups; ++g) {
           const Seg& ag = segs[lg[g]][sg[g][k]];
-          const int64_t off = (int64_t)goff[g] * K_;
-          bool same = ag.lend - ag.lbeg == a0.lend - a0.lbeg && mshared[ag.e2] &&
+          bool same = ag.lend - ag.lbeg == a0.lend - a0.lbeg && ag.m2p == a0.m2p && mshared[ag.e2] &&
                       surfs_[ag.e2]->shared == surfs_[a0.e2]->shared;
-          for (int32_t q = 0; same && q < a0.lend - a0.lbeg; ++q)
-            same = P.ranges[2 * (ag.lbeg + q)] == P.ranges[2 * (a0.lbeg + q)] + off &&
-                   P.ranges[2 * (ag.lbeg + q) + 1] == P.ranges[2 * (a0.lbeg + q) + 1] + off;
+          if (a0.m2p) {
+            const int32_t off = boxoff[(size_t)sidx * ngroups + g];
+            for (int32_t q = 0; same && q < a0.lend - a0.lbeg; ++q)
+              same = P.blist[ag.lbeg + q] == P.blist[a0.lbeg + q] + off;
+          } else {
+            const int64_t off = (int64_t)goff[g] * K_;
+            for (int32_t q = 0; same && q < a0.lend - a0.lbeg; ++q)
+              same = P.ranges[2 * (ag.lbeg + q)] == P.ranges[2 * (a0.lbeg + q)] + off &&
+                     P.ranges[2 * (ag.lbeg + q) + 1] == P.ranges[2 * (a0.lbeg + q) + 1] + off;
+          }
           if (!same) {
-            lerr[m] = "shared surfaces: source ranges differ between groups";
+            lerr[m] = "shared surfaces: interaction lists differ between groups";
             return;
           }
           lrows[m].push_back(slot0[lg[g]] + sg[g][k]);
@@ -1217,11 +1268,12 @@ void System::build_plan() {
         for (int gb = 0; gb < ngroups; gb += kMultiBlock) {
           Task t = make_task(li, a0, row);
           t.split = gb;
-          ltasks[m].push_back(t);
+          if (a0.m2p) t.nsrc = sidx;
+          (a0.m2p ? ltasksm : ltasks)[m].push_back(t);
         }
       }
     });
-    std::vector<Task> mt;
+    std::vector<Task> mt, mtm;
     for (size_t m = 0; m < mleaves.size(); ++m) {
       if (lerr[m]) throw Error(PBT_E_STATE, lerr[m]);
       const int base = (int)(P.mslot.size() / ngroups);
@@ -1230,26 +1282,38 @@ void System::build_plan() {
         t.slot += base;
         mt.push_back(t);
       }
-    }
-    // the two halves of a wavefront serve the same block of groups
-    std::stable_sort(mt.begin(), mt.end(), [](const Task& a, const Task& b) {
-      return a.split != b.split ? a.split < b.split : a.nsrc > b.nsrc;
-    });
-    for (size_t k = 0; k < mt.size();) {
-      P.p2pm.push_back(mt[k]);
-      if (k + 1 < mt.size() && mt[k + 1].split == mt[k].split) {
-        P.p2pm.push_back(mt[k + 1]);
-        k += 2;
-      } else {
-        Task empty = mt[k];   // same group block
-        empty.tcount = 0;
-        empty.lbeg = empty.lend = 0;
-        empty.nsrc = 0;
-        empty.slot = 0;
-        P.p2pm.push_back(empty);
-        k += 1;
+      for (Task t : ltasksm[m]) {
+        t.slot += base;
+        mtm.push_back(t);
       }
     }
+    // the two halves of a wavefront serve the same block of groups (and,
+    // for M2P, the same source surface); similar work side by side
+    auto pair_blocks = [](std::vector<Task>& v, std::vector<Task>& out, bool m2p) {
+      auto work = [m2p](const Task& t) { return m2p ? t.lend - t.lbeg : t.nsrc; };
+      std::stable_sort(v.begin(), v.end(), [&](const Task& a, const Task& b) {
+        if (a.split != b.split) return a.split < b.split;
+        if (m2p && a.nsrc != b.nsrc) return a.nsrc < b.nsrc;
+        return work(a) > work(b);
+      });
+      for (size_t k = 0; k < v.size();) {
+        out.push_back(v[k]);
+        if (k + 1 < v.size() && v[k + 1].split == v[k].split && (!m2p || v[k + 1].nsrc == v[k].nsrc)) {
+          out.push_back(v[k + 1]);
+          k += 2;
+        } else {
+          Task empty = v[k];   // same group block (and source surface)
+          empty.tcount = 0;
+          empty.lbeg = empty.lend = 0;
+          if (!m2p) empty.nsrc = 0;
+          empty.slot = 0;
+          out.push_back(empty);
+          k += 1;
+        }
+      }
+    };
+    pair_blocks(mt, P.p2pm, false);
+    pair_blocks(mtm, P.m2pm, true);
   }
   clk.mark_host(" shared tasks");
   // The right-hand side's product: only the tasks whose sources carry known
@@ -1314,8 +1378,8 @@ void System::build_plan() {
     for (const Task& t : P.m2p)
       if (t.tcount > 0 && known_panel[t.tbeg] && t.known) kk_m2p += (int64_t)t.tcount * (t.lend - t.lbeg);
     std::fprintf(stderr, "[plan] pairs between surfaces without interior rows: p2p %lld, m2p %lld; "
-                 "shared-surface P2P tasks %zu for %d groups\n",
-                 (long long)kk_p2p, (long long)kk_m2p, P.p2pm.size(), P.mgroups);
+                 "shared-surface P2P / M2P tasks %zu / %zu for %d groups\n",
+                 (long long)kk_p2p, (long long)kk_m2p, P.p2pm.size(), P.m2pm.size(), P.mgroups);
     std::fprintf(stderr, "[plan] m2p pairs by box sources <16 / <32 / <64 / <128 / <256 / more: "
                  "%lld / %lld / %lld / %lld / %lld / %lld\n", (long long)hist[0], (long long)hist[1],
                  (long long)hist[2], (long long)hist[3], (long long)hist[4], (long long)hist[5]);
@@ -1371,7 +1435,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   const int32_t* mbl = known_only ? mblocks_known_.p : mblocks_.p;
   const MomChunk* mch = known_only ? mchunks_known_.p : mchunks_.p;
   const MomChunk* mhd = known_only ? mheads_known_.p : mheads_.p;
-  const bool far = !plan_.m2p.empty();
+  const bool far = !plan_.m2p.empty() || !plan_.m2pm.empty();
   const bool two = far && far_mode_ == 1;
   const bool fused = far && far_mode_ == 2;
   const bool with_mom = far && far_mode_ == 3;
@@ -1395,6 +1459,11 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
   auto multi = [&](hipStream_t st) {
     launch_p2p_multi<T>(dp2pm_.p, nmp, dranges_.p, tgt, src, nrm_.p, K_, dgoff_.p, dmslot_.p, plan_.mgroups,
                         (T)kappa_, guard, ppart, st);
+  };
+  // M2P between them, right after the usual M2P tasks (the moments are done)
+  auto mmulti = [&](hipStream_t st) {
+    launch_m2p_multi<T>(prm_.taylor_p, dm2pm_.p, (int)plan_.m2pm.size(), dblist_.p, tgt, bcen_.p, mom,
+                        dmboxoff_.p, dmslot_.p, plan_.mgroups, (T)kappa_, ppart, st);
   };
   // M2M after the leaves' moments (P2M): every (box, leaf) shift, then the
   // sums per box
@@ -1425,6 +1494,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     if (timed) PBT_HIP(hipEventRecord(evm_[1], fs));
     const int e0 = pb(fs);
     launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, ppart, fs);
+    mmulti(fs);
     pe(1, e0, fs);
     if (timed || two) PBT_HIP(hipEventRecord(evm_[2], fs));
   };
@@ -1441,6 +1511,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     const int e0 = pb(s);
     launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks, npairs,
                       dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    mmulti(s);
     multi(s);
     pe(0, e0, s);
     if (timed) {
@@ -1467,6 +1538,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     e0 = pb(s);
     launch_m2p_p2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, bcen_.p, mom, p2p_tasks + 2 * (int64_t)na, nb,
                       dranges_.p, src, tgt, (T)kappa_, guard, ppart, s);
+    mmulti(s);
     pe(1, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(evm_[2], s));
@@ -1491,6 +1563,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     if (timed) PBT_HIP(hipEventRecord(evm_[1], s));
     e0 = pb(s);
     launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, ppart, s);
+    mmulti(s);
     pe(1, e0, s);
     if (timed) {
       PBT_HIP(hipEventRecord(evm_[2], s));
@@ -1508,6 +1581,7 @@ void System::interactions(hipStream_t s, const double* x, bool timed, bool src_r
     PBT_HIP(hipStreamWaitEvent(s2_, evm_[1], 0));
     const int e1 = pb(s2_);
     launch_m2p<T>(prm_.taylor_p, m2p_tasks, nm2p, dblist_.p, tgt, bcen_.p, mom, (T)kappa_, ppart, s2_);
+    mmulti(s2_);
     pe(1, e1, s2_);
     PBT_HIP(hipEventRecord(evm_[2], s2_));
   }

@@ -124,6 +124,11 @@ struct Plan {
   std::vector<Task> p2pm;
   std::vector<int32_t> mslot, goff;
   int mgroups = 0;
+  // M2P between them likewise (m2pm, rows of mslot too): task.nsrc is a row
+  // of mboxoff, whose entry g is the offset of group g's box numbers of the
+  // source surface from group 0's
+  std::vector<Task> m2pm;
+  std::vector<int32_t> mboxoff;
 };
 
 struct Timing {
@@ -395,8 +400,8 @@ class System {
   DBuf<Task> dp2p_, dm2p_;
   DBuf<Task> dp2p_known_, dm2p_known_;   // the same with tasks of unknown-density sources emptied
   DBuf<int32_t> dranges_, dblist_;
-  DBuf<Task> dp2pm_;
-  DBuf<int32_t> dmslot_, dgoff_;
+  DBuf<Task> dp2pm_, dm2pm_;
+  DBuf<int32_t> dmslot_, dgoff_, dmboxoff_;
   DBuf<ChunkSlots> dchunks_;
   DBuf<int32_t> dchunk_of_;
   DBuf<float> part32_, ppart32_;

@@ -335,11 +335,13 @@ __device__ __forceinline__ int zero_after(T v) {
   return z;
 }
 
-// The moments M are in LDS (a per-lane address): each degree's are read at
-// its start, kept there by scheduling barriers, so that the degree's
-// recurrence hides their latency and one degree of them is live at a time.
-template <typename T, int P, bool YUK>
-__device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
+// The Taylor coefficients of the kernel (Yukawa, or Laplace), degree by
+// degree: pre(n) runs at the start of degree n >= 1, between scheduling
+// barriers (reads that the degree's use of its coefficients waits for are
+// issued there, so that the recurrence hides their latency), and post(n, A)
+// once A holds the coefficients of degrees 0..n.
+template <typename T, int P, bool YUK, typename Pre, typename Post>
+__device__ __forceinline__ void taylor_series(T Rx, T Ry, T Rz, T kappa, Pre&& pre, Post&& post) {
   constexpr int NC = ncoef(P);
   T A[NC];
   T B[YUK ? NC : 1];
@@ -354,13 +356,11 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
   } else {
     A[0] = Rinv;
   }
-  T acc = A[0] * M[0];
-#pragma unroll
-  for (int n = 1; n <= P; ++n) {
-    T mo[(P + 1) * (P + 2) / 2];
+  post(std::integral_constant<int, 0>{}, A);
+  static_for<1, P + 1>([&](auto N) {
+    constexpr int n = decltype(N)::value;
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k) mo[k - tidx(n, 0, 0)] = M[k];
+    pre(N);
     __builtin_amdgcn_sched_barrier(0);
     const T c1 = T(2 * n - 1) / T(n) * invR2;
     const T c2 = T(n - 1) / T(n) * invR2;
@@ -404,9 +404,34 @@ __device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
         }
       }
     }
+    post(N, A);
+  });
+}
+
+// sum_k a_k M_k with the moments M in LDS (a per-lane address): each
+// degree's are read at its start, kept there by scheduling barriers, so
+// that the degree's recurrence hides their latency and one degree of them
+// is live at a time.
+template <typename T, int P, bool YUK>
+__device__ __forceinline__ T taylor_dot(T Rx, T Ry, T Rz, T kappa, const T* M) {
+  T acc = T(0);
+  T mo[(P + 1) * (P + 2) / 2];
+  taylor_series<T, P, YUK>(
+      Rx, Ry, Rz, kappa,
+      [&](auto N) {
+        constexpr int n = decltype(N)::value;
 #pragma unroll
-    for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k) acc += A[k] * mo[k - tidx(n, 0, 0)];
-  }
+        for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k) mo[k - tidx(n, 0, 0)] = M[k];
+      },
+      [&](auto N, const T* A) {
+        constexpr int n = decltype(N)::value;
+        if constexpr (n == 0) {
+          acc = A[0] * M[0];
+        } else {
+#pragma unroll
+          for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k) acc += A[k] * mo[k - tidx(n, 0, 0)];
+        }
+      });
   return acc;
 }
 
@@ -580,6 +605,120 @@ __global__ __launch_bounds__(256) void k_m2p(const Task* __restrict__ tasks, int
   m2p_task_pair<T, P, SALTFREE>(tasks + 2 * wv, mlds[threadIdx.x >> 6], blist, tgt, bcen, mom, kappa, partial);
 }
 
+// ---- M2P between surfaces shared by every group of a batch ------------------
+// A target and a box of two surfaces that every group holds unmoved have the
+// same R = x - c in every group, so the coefficients a_k(R) are formed once
+// and dotted with the moments of the box's copy in kMultiPass groups at a
+// time.  The moments of a pass are staged in LDS as rows of coefficients,
+// one column per group (row stride kMultiRow, 16-byte aligned).
+constexpr int kMultiPass = 8, kMultiRow = 12;
+
+template <typename T, int P, bool YUK>
+__device__ __forceinline__ void taylor_dot_multi(T Rx, T Ry, T Rz, T kappa, const T* __restrict__ M,
+                                                 T (&d)[kMultiPass]) {
+  taylor_series<T, P, YUK>(
+      Rx, Ry, Rz, kappa, [&](auto) {},
+      [&](auto N, const T* A) {
+        constexpr int n = decltype(N)::value;
+#pragma unroll
+        for (int k = tidx(n, 0, 0); k < tidx(n + 1, 0, 0); ++k)
+#pragma unroll
+          for (int g = 0; g < kMultiPass; ++g) {
+            if (n == 0) d[g] = A[k] * M[k * kMultiRow + g];
+            else d[g] += A[k] * M[k * kMultiRow + g];
+          }
+      });
+}
+
+// A pair of shared-surface M2P tasks on one wavefront (lanes 0..31: tp[0],
+// 32..63: tp[1], one target a lane, Yukawa-only rows, both serving groups
+// split .. split + kMultiBlock - 1; nsrc is the row of boxoff that holds, per
+// group, the offset of its copy's box numbers from group 0's).  Box by box
+// and pass by pass, each half stages the moments of the box's copies in the
+// pass's groups (row 0) and every lane adds sum_k a_k M_k per group; a half
+// with fewer boxes evaluates its last box again and discards it.
+template <typename T, int P, bool SALTFREE>
+__device__ __forceinline__ void m2p_multi_pair(const Task* __restrict__ tp, T* __restrict__ mlds,
+                                               const int32_t* __restrict__ blist, const T* __restrict__ tgt,
+                                               const double* __restrict__ bcen, const T* __restrict__ mom,
+                                               const int32_t* __restrict__ boxoff, const int32_t* __restrict__ mslot,
+                                               int G, T kappa, T* __restrict__ partial) {
+  constexpr int NC = ncoef(P), PER = (NC + 31) / 32;
+  const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  const Task t = tp[half];
+  const int n = t.lend - t.lbeg;
+  const int nmax = __builtin_amdgcn_readfirstlane(max(tp[0].lend - tp[0].lbeg, tp[1].lend - tp[1].lbeg));
+  const int ti = t.tbeg + (hl < t.tcount ? hl : 0);
+  const T tx = tgt[kTgtStride * ti], ty = tgt[kTgtStride * ti + 1], tz = tgt[kTgtStride * ti + 2];
+  const int g0 = tp[0].split, g1 = min(G, g0 + kMultiBlock);
+  const int32_t* off = boxoff + (int64_t)t.nsrc * G;
+  const int last = t.lbeg + max(n - 1, 0);
+  T* mine = mlds + half * (NC * kMultiRow);
+  for (int gb = g0; gb < g1; gb += kMultiPass) {
+    const int nb = min(kMultiPass, g1 - gb);
+    T acc[kMultiPass];
+#pragma unroll
+    for (int g = 0; g < kMultiPass; ++g) acc[g] = T(0);
+    for (int r = 0; r < nmax; ++r) {
+      const int b = blist[min(t.lbeg + r, last)];
+      // stage: coefficient i of group gb + g at mine[i * kMultiRow + g]
+      // (groups past the block's last read its last group's and are
+      // never used)
+      T v[PER][kMultiPass];
+#pragma unroll
+      for (int g = 0; g < kMultiPass; ++g) {
+        const T* M = mom + (int64_t)(2 * (b + off[min(gb + g, g1 - 1)])) * NC;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) v[q][g] = M[min(hl + 32 * q, NC - 1)];
+      }
+      wave_lds_sync();   // the previous box's reads are done
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (hl + 32 * q < NC)
+#pragma unroll
+          for (int g = 0; g < kMultiPass; ++g) mine[(hl + 32 * q) * kMultiRow + g] = v[q][g];
+      wave_lds_sync();
+      const T Rx = tx - (T)bcen[3 * b], Ry = ty - (T)bcen[3 * b + 1], Rz = tz - (T)bcen[3 * b + 2];
+      T d[kMultiPass];
+      taylor_dot_multi<T, P, !SALTFREE>(Rx, Ry, Rz, kappa, mine, d);
+      const bool on = r < n;
+#pragma unroll
+      for (int g = 0; g < kMultiPass; ++g) acc[g] += on ? d[g] : T(0);
+    }
+    if (hl < t.tcount) {
+#pragma unroll
+      for (int g = 0; g < kMultiPass; ++g) {
+        if (g >= nb) break;
+        T o0 = T(0), o1 = acc[g];
+        if (t.form & kFormDropOut) o1 = T(0);
+        if (t.form & kFormSwap) {
+          const T sw = o0;
+          o0 = o1;
+          o1 = sw;
+        }
+        const int64_t slot = mslot[(int64_t)t.slot * G + gb + g];
+        partial[2 * (slot * 32 + hl) + 0] = o0;
+        partial[2 * (slot * 32 + hl) + 1] = o1;
+      }
+    }
+  }
+}
+
+// One wavefront per pair of shared-surface M2P tasks (four per block).
+template <typename T, int P, bool SALTFREE>
+__global__ __launch_bounds__(256) void k_m2p_multi(const Task* __restrict__ tasks, int npairs,
+                                                   const int32_t* __restrict__ blist, const T* __restrict__ tgt,
+                                                   const double* __restrict__ bcen, const T* __restrict__ mom,
+                                                   const int32_t* __restrict__ boxoff,
+                                                   const int32_t* __restrict__ mslot, int G, T kappa,
+                                                   T* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) T mlds[4][2 * ncoef(P) * kMultiRow];
+  const int wv = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + (int)(threadIdx.x >> 6));
+  if (wv >= npairs) return;
+  m2p_multi_pair<T, P, SALTFREE>(tasks + 2 * wv, mlds[threadIdx.x >> 6], blist, tgt, bcen, mom, boxoff, mslot, G,
+                                 kappa, partial);
+}
+
 // M2P task pairs and P2P task pairs in one launch (M2P first): the far
 // field's wavefronts and the near field's share the machine instead of
 // running one after the other.  Both write the half-wave partials.
@@ -745,6 +884,36 @@ void launch_m2p(int P, const Task* tasks, int ntasks, const int32_t* blist, cons
 }
 
 template <typename T, int P>
+static void m2p_multi_p(const Task* tasks, int npairs, const int32_t* blist, const T* tgt, const double* bcen,
+                        const T* mom, const int32_t* boxoff, const int32_t* mslot, int G, T kappa, T* partial,
+                        hipStream_t s) {
+  const int blocks = ((npairs + 3) / 4 + 7) / 8 * 8;
+  if (kappa == T(0))
+    k_m2p_multi<T, P, true><<<blocks, 256, 0, s>>>(tasks, npairs, blist, tgt, bcen, mom, boxoff, mslot, G, kappa,
+                                                   partial);
+  else
+    k_m2p_multi<T, P, false><<<blocks, 256, 0, s>>>(tasks, npairs, blist, tgt, bcen, mom, boxoff, mslot, G, kappa,
+                                                    partial);
+}
+
+template <typename T>
+void launch_m2p_multi(int P, const Task* tasks, int ntasks, const int32_t* blist, const T* tgt, const double* bcen,
+                      const T* mom, const int32_t* boxoff, const int32_t* mslot, int G, T kappa, T* partial,
+                      hipStream_t s) {
+  if (ntasks <= 0 || G <= 0) return;
+  if (ntasks % 2) throw Error(1, "M2P half tasks come in pairs");
+  const int npairs = ntasks / 2;
+  switch (P) {
+#define PBT_MM(Q) \
+  case Q: m2p_multi_p<T, Q>(tasks, npairs, blist, tgt, bcen, mom, boxoff, mslot, G, kappa, partial, s); break;
+    PBT_MM(0) PBT_MM(1) PBT_MM(2) PBT_MM(3) PBT_MM(4) PBT_MM(5) PBT_MM(6) PBT_MM(7) PBT_MM(8)
+#undef PBT_MM
+    default: throw Error(1, "Taylor order P must be 0..8");
+  }
+  PBT_HIP(hipGetLastError());
+}
+
+template <typename T, int P>
 static void m2p_p2p_p(const Task* m2p, int nm2p, const int32_t* blist, const double* bcen, const T* mom,
                       const Task* p2p, int np2p, const int32_t* ranges, const T* src, const T* tgt, T kappa,
                       bool guard, T* ppartial, hipStream_t s) {
@@ -803,6 +972,11 @@ template void launch_m2m<float>(int, int, const int32_t*, int, int, const int32_
                                 hipStream_t);
 template void launch_m2m<double>(int, int, const int32_t*, int, int, const int32_t*, const double*, double*, double*,
                                  hipStream_t);
+template void launch_m2p_multi<float>(int, const Task*, int, const int32_t*, const float*, const double*,
+                                      const float*, const int32_t*, const int32_t*, int, float, float*, hipStream_t);
+template void launch_m2p_multi<double>(int, const Task*, int, const int32_t*, const double*, const double*,
+                                       const double*, const int32_t*, const int32_t*, int, double, double*,
+                                       hipStream_t);
 template void launch_m2p<float>(int, const Task*, int, const int32_t*, const float*, const double*,
                                 const float*, float, float*, hipStream_t);
 template void launch_m2p<double>(int, const Task*, int, const int32_t*, const double*, const double*,
