@@ -859,7 +859,9 @@ void System::build_plan() {
   std::vector<std::map<int, int>> copy_in(ngroups);   // per group: shared id -> surface
   std::vector<int32_t> goff(ngroups, 0);
   bool multi = false;
-  if (ngroups >= 2) {
+  // (PBT_NO_SHARED in the environment keeps them in per-group tasks: the
+  // reference the shared-surface kernels are tested against)
+  if (ngroups >= 2 && !std::getenv("PBT_NO_SHARED")) {
     multi = true;
     for (int e = 0; e < ns; ++e)
       if (surfs_[e]->shared >= 0 && !two_rows(e)) {

@@ -77,6 +77,37 @@ def test_batch_mixed_treecode():
     assert len(set(np.round(f_ref, 8))) > 1   # placements differ
 
 
+@pytest.mark.parametrize("kappa,k_far", [(0.125, 3), (0.0, 7), (0.125, 1)])
+def test_batch_shared_surfaces_treecode(kappa, k_far, monkeypatch):
+    """The plate is the same in every placement, so its P2P and M2P pairs
+    with itself are evaluated once for 16 placements at a time.  With 18
+    placements (a block of 16 and a block of 2), FP64 treecode: the batched
+    F_int equals that of the same batch with those pairs in per-placement
+    tasks (PBT_NO_SHARED) to the solver's tolerance, and a separate solve of
+    a moved pair to the treecode's accuracy (its isolated energies come from
+    the moved molecule's own tree).  Salt-free and Yukawa solvent; rules with
+    and without the barycentre, whose self pair is skipped."""
+    pr = body_problem()
+    pr.kappa = kappa
+    prm = dict(treecode=1, ncrit=24, theta=0.5, taylor_p=6, k_far=k_far, tol=1e-10)
+    nb = 18
+    R, t = placements(nb)
+    s, ids = from_problem(pr, **prm)
+    f_batch = s.solve_batch(ids[0], R.reshape(nb, 9), t)
+    monkeypatch.setenv("PBT_NO_SHARED", "1")
+    f_plain = s.solve_batch(ids[0], R.reshape(nb, 9), t)
+    monkeypatch.delenv("PBT_NO_SHARED")
+    e = s.solve()
+    scale = abs(e.F_solv) + abs(e.F_surf)
+    assert np.max(np.abs(f_batch - f_plain)) <= 1e-8 * scale
+    for b in (0, 17):
+        pb = placed(pr, R[b], t[b])
+        sb, _ = from_problem(pb, **prm)
+        f, res = sb.interaction_energy(2)
+        assert abs(f_batch[b] - f) <= 1e-5 * scale, (b, f_batch[b], f)
+        sb.close()
+
+
 def nested_body_problem():
     """The batch body with a Stern layer (r = 3.6 A, permittivity 20) and an
     off-centre water cavity that move with the molecule."""
