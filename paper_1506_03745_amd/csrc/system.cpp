@@ -28,6 +28,15 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Host staging arrays of the set-up (triangles, Gauss points), kept per
+// thread and reused by later set-ups: for the largest systems, mapping a few
+// hundred MB of fresh pages costs more than filling them.
+double* host_stage(int which, size_t n) {
+  thread_local std::vector<double> buf[2];
+  if (buf[which].size() < n) buf[which].resize(n);
+  return buf[which].data();
+}
+
 // Wall time of the set-up phases, printed to stderr when PBT_SETUP_TIMES is
 // set in the environment (the stream is drained at each mark so that device
 // work is charged to its own phase).
@@ -190,8 +199,8 @@ void System::build(hipStream_t s) {
   // sequence of correctly rounded operations as the device's geometry
   // kernels (so they agree bit for bit), formed while the triangles are
   // gathered instead of read back.
-  std::unique_ptr<double[]> tri9(new double[9 * (size_t)np_]);
-  std::unique_ptr<double[]> hsrc(new double[3 * (size_t)ns_]);
+  double* tri9 = host_stage(0, 9 * (size_t)np_);
+  double* hsrc = host_stage(1, 3 * (size_t)ns_);
   h_cen_.resize(3 * np_);
   h_area_.resize(np_);
   const double third = 1.0 / 3.0;
@@ -213,18 +222,39 @@ void System::build(hipStream_t s) {
         for (int d = 0; d < 3; ++d) p[d] = (b0 * v[d] + b1 * v[3 + d]) + b2 * v[6 + d];
     }
   };
+  // A copy of a surface that the groups share unmoved (a batch's plate: the
+  // same vertices, triangles and octree as group 0's copy) takes its
+  // triangles from group 0's on the device and its host geometry from
+  // group 0's on the host, instead of gathering them again.
+  std::vector<int> twin(ns, -1);
+  {
+    std::map<int, int> first;   // shared id -> group 0's surface
+    for (int e = 0; e < ns; ++e)
+      if (surfs_[e]->shared >= 0 && surfs_[e]->group == 0) first.emplace(surfs_[e]->shared, e);
+    parallel_for(ns, [&](int64_t e) {
+      const SurfIn& S = *surfs_[e];
+      if (S.shared < 0 || S.group == 0) return;
+      auto it = first.find(S.shared);
+      if (it == first.end()) return;
+      const SurfIn& S0 = *surfs_[it->second];
+      if (S.nt == S0.nt && S.xyz == S0.xyz && S.tri == S0.tri && trees_[e].perm == trees_[it->second].perm)
+        twin[e] = it->second;
+    });
+  }
   h_panel_orig_.resize(np_);
   std::vector<int32_t> col_phi(np_), col_psi(np_), row_int(np_), row_sol(np_), psurf(np_);
-  std::vector<double> dscale(np_), ksig(np_, 0.0), kmu(np_, 0.0);
+  std::vector<double> dscale(np_);
   parallel_for(ns, [&](int64_t e) {
     const SurfIn& S = *surfs_[e];
     for (int64_t li = 0; li < S.nt; ++li) {
       const int64_t g = poff_[e] + li;
       const int32_t o = trees_[e].perm[li];
       h_panel_orig_[g] = o;
-      for (int v = 0; v < 3; ++v)
-        for (int d = 0; d < 3; ++d) tri9[9 * g + 3 * v + d] = S.xyz[3 * S.tri[3 * o + v] + d];
-      host_geometry(g);
+      if (twin[e] < 0) {
+        for (int v = 0; v < 3; ++v)
+          for (int d = 0; d < 3; ++d) tri9[9 * g + 3 * v + d] = S.xyz[3 * S.tri[3 * o + v] + d];
+        host_geometry(g);
+      }
       psurf[g] = e;
       switch (S.kind) {
         case PBT_MOLECULE:
@@ -252,6 +282,15 @@ void System::build(hipStream_t s) {
       }
     }
   });
+  // the twins' host geometry from group 0's copies (formed above)
+  parallel_for(ns, [&](int64_t e) {
+    const int e0 = twin[e];
+    if (e0 < 0) return;
+    const int64_t nt = surfs_[e]->nt, g = poff_[e], g0 = poff_[e0];
+    std::memcpy(&h_cen_[3 * g], &h_cen_[3 * g0], 3 * nt * sizeof(double));
+    std::memcpy(&h_area_[g], &h_area_[g0], nt * sizeof(double));
+    std::memcpy(&hsrc[3 * g * K_], &hsrc[3 * g0 * K_], 3 * nt * K_ * sizeof(double));
+  });
   clk.mark("tri9", s);
   {
     // The unknowns (and rows) of a surface follow its panels' internal order;
@@ -268,7 +307,18 @@ void System::build(hipStream_t s) {
     }
     u2i_.upload(u2i, s);
   }
-  tri9_.upload(tri9.get(), 9 * (size_t)np_, s);
+  // triangles: each surface's own from the host, a twin's copied from group
+  // 0's on the device
+  tri9_.alloc(9 * (size_t)np_);
+  for (int e = 0; e < ns; ++e)
+    if (twin[e] < 0 && surfs_[e]->nt > 0)
+      PBT_HIP(hipMemcpyAsync(tri9_.p + 9 * poff_[e], &tri9[9 * poff_[e]], 9 * surfs_[e]->nt * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+  for (int e = 0; e < ns; ++e)
+    if (twin[e] >= 0 && surfs_[e]->nt > 0)
+      PBT_HIP(hipMemcpyAsync(tri9_.p + 9 * poff_[e], tri9_.p + 9 * poff_[twin[e]], 9 * surfs_[e]->nt * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+  PBT_HIP(hipStreamSynchronize(s));
   col_phi_.upload(col_phi, s);
   col_psi_.upload(col_psi, s);
   row_int_.upload(row_int, s);
@@ -315,7 +365,7 @@ void System::build(hipStream_t s) {
     const std::vector<double> dc = cen_.download(s), da = area_.download(s), ds = src_pos_.download(s);
     if (std::memcmp(dc.data(), h_cen_.data(), dc.size() * sizeof(double)) != 0 ||
         std::memcmp(da.data(), h_area_.data(), da.size() * sizeof(double)) != 0 ||
-        std::memcmp(ds.data(), hsrc.get(), ds.size() * sizeof(double)) != 0)
+        std::memcmp(ds.data(), hsrc, ds.size() * sizeof(double)) != 0)
       throw Error(PBT_E_STATE, "host and device panel geometry differ");
   }
   tgt64_.alloc(4 * np_);
@@ -1121,9 +1171,12 @@ void System::build_plan() {
       for (int32_t r = sg.lbeg; r < sg.lend; ++r) t.nsrc += P.ranges[2 * r + 1] - P.ranges[2 * r];
     return t;
   };
-  std::vector<Task> spare, mspare;
-  for (size_t li = 0; li < leaves.size(); ++li) {
-    if (half_of_leaf[li] != 0) continue;
+  // (per chunk in parallel, then laid end to end in chunk order)
+  struct ChunkTasks { std::vector<Task> p2p, m2p, spare, mspare; };
+  std::vector<ChunkTasks> ct(leaves.size());
+  parallel_for((int64_t)leaves.size(), [&](int64_t li) {
+    if (half_of_leaf[li] != 0) return;
+    ChunkTasks& c = ct[li];
     const bool pair = full_first[li] != 0;
     if (!pair) {
       for (int h = 0; h < 2; ++h) {
@@ -1131,9 +1184,9 @@ void System::build_plan() {
         if (h == 1 && !(lj < leaves.size() && half_of_leaf[lj] == 1)) break;
         for (size_t si = 0; si < segs[lj].size(); ++si)
           if (!segs[lj][si].shared)
-            (segs[lj][si].m2p ? mspare : spare).push_back(make_task(lj, segs[lj][si], slot0[lj] + (int)si));
+            (segs[lj][si].m2p ? c.mspare : c.spare).push_back(make_task(lj, segs[lj][si], slot0[lj] + (int)si));
       }
-      continue;
+      return;
     }
     // per source surface and kind, the k-th segment of each half together
     const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
@@ -1146,8 +1199,8 @@ void System::build_plan() {
         for (size_t si = 0; si < segs[li + 1].size(); ++si)
           if (segs[li + 1][si].e2 == e2 && segs[li + 1][si].m2p == (m == 1) && !segs[li + 1][si].shared)
             sb.push_back({si, slot0[li + 1] + (int)si});
-        std::vector<Task>& out = m ? P.m2p : P.p2p;
-        std::vector<Task>& rest = m ? mspare : spare;
+        std::vector<Task>& out = m ? c.m2p : c.p2p;
+        std::vector<Task>& rest = m ? c.mspare : c.spare;
         const size_t k2 = std::min(sa.size(), sb.size());
         for (size_t k = 0; k < k2; ++k) {
           out.push_back(make_task(li, segs[li][sa[k].first], sa[k].second));
@@ -1157,7 +1210,16 @@ void System::build_plan() {
         for (size_t k = k2; k < sb.size(); ++k)
           rest.push_back(make_task(li + 1, segs[li + 1][sb[k].first], sb[k].second));
       }
+  });
+  std::vector<Task> spare, mspare;
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    ChunkTasks& c = ct[li];
+    P.p2p.insert(P.p2p.end(), c.p2p.begin(), c.p2p.end());
+    P.m2p.insert(P.m2p.end(), c.m2p.begin(), c.m2p.end());
+    spare.insert(spare.end(), c.spare.begin(), c.spare.end());
+    mspare.insert(mspare.end(), c.mspare.begin(), c.mspare.end());
   }
+  parallel_for((int64_t)leaves.size(), [&](int64_t li) { ct[li] = ChunkTasks(); });
   // The other halves, paired with halves of the same kind (both halves of a
   // wavefront agree on fused and kFormKz, for P2P also on the split; a half
   // of at most 8 (16) targets has its lanes in 4 (2) groups that split the
