@@ -97,8 +97,12 @@ def rule_integrals(x, panels: Panels, cols, npts, kappa):
     sub = panels.points(bary)[cols]                # (C, Q, 3)
     nrm = panels.normal[cols]                      # (C, 3)
     area = panels.area[cols]                       # (C,)
-    gl, kl, gy, ky = point_kernels(x[:, None, None, :], sub[None, :, :, :],
-                                   nrm[None, :, None, :], kappa)
+    # a rule point that coincides with x (the self panel of the rules that
+    # contain the centroid) gives inf / nan here; callers replace the self
+    # entries by the self integrals, so those values are never used
+    with np.errstate(divide="ignore", invalid="ignore"):
+        gl, kl, gy, ky = point_kernels(x[:, None, None, :], sub[None, :, :, :],
+                                       nrm[None, :, None, :], kappa)
     wa = w[None, None, :] * area[None, :, None]
     return ((gl * wa).sum(-1), (kl * wa).sum(-1), (gy * wa).sum(-1), (ky * wa).sum(-1))
 
