@@ -747,14 +747,17 @@ void System::check_plan() const {
       if (!(0 <= t.lbeg && t.lbeg <= t.lend && t.lend <= nbl)) bad("shared-surface M2P box list out of bounds");
       if (t.nsrc < 0 || t.nsrc >= orows) bad("shared-surface M2P offset row");
       if (t.split < 0 || t.split >= G || t.split % kMultiBlock) bad("shared-surface M2P group block");
-      if (t.tcount == 0) continue;
-      if (t.tbeg < 0 || (int64_t)t.tbeg + t.tcount > np_) bad("shared-surface M2P targets out of bounds");
-      if (t.slot < 0 || t.slot >= rows) bad("shared-surface M2P slot row out of bounds");
-      for (int g = 0; g < G; ++g) {
+      // every half reads its boxes (an empty one too) in the groups of its block
+      if (t.lend <= t.lbeg && (t.tcount > 0 || P.m2pm[w ^ 1].lend > P.m2pm[w ^ 1].lbeg))
+        bad("shared-surface M2P half without boxes");
+      for (int g = t.split; g < std::min(G, t.split + kMultiBlock); ++g) {
         const int32_t off = P.mboxoff[(size_t)t.nsrc * G + g];
         for (int32_t r = t.lbeg; r < t.lend; ++r)
           if (P.blist[r] + (int64_t)off < 0 || P.blist[r] + (int64_t)off >= nbox_) bad("shared-surface box out of bounds");
       }
+      if (t.tcount == 0) continue;
+      if (t.tbeg < 0 || (int64_t)t.tbeg + t.tcount > np_) bad("shared-surface M2P targets out of bounds");
+      if (t.slot < 0 || t.slot >= rows) bad("shared-surface M2P slot row out of bounds");
       for (int g = t.split; g < std::min(G, t.split + kMultiBlock); ++g) {
         const int32_t sl = P.mslot[(int64_t)t.slot * G + g];
         if (sl < 0 || sl >= P.npslots) bad("shared-surface M2P slot out of bounds");
@@ -1366,10 +1369,15 @@ void System::build_plan() {
           out.push_back(v[k + 1]);
           k += 2;
         } else {
-          Task empty = v[k];   // same group block (and source surface)
+          // an empty partner: same group block; an M2P one also keeps the
+          // boxes (valid in every group of the block, evaluated and thrown
+          // away), a P2P one has no sources
+          Task empty = v[k];
           empty.tcount = 0;
-          empty.lbeg = empty.lend = 0;
-          if (!m2p) empty.nsrc = 0;
+          if (!m2p) {
+            empty.lbeg = empty.lend = 0;
+            empty.nsrc = 0;
+          }
           empty.slot = 0;
           out.push_back(empty);
           k += 1;
