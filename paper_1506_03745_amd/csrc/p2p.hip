@@ -1,8 +1,9 @@
-// Near-field (P2P) kernel of the operator (Section 3.2): Gauss points as
+// Near-field (P2P) kernels of the operator (Section 3.2): Gauss points as
 // sources, collocation points as targets, direct sums over the source ranges
-// of each target leaf's near list.  The pair interaction and the task layout
-// are in near_field.h; this file only launches them, so that its profile
-// stays tied to these two files.
+// of each target group's near list.  The pair interaction and the task
+// layout of the per-group kernel are in near_field.h (shared with the joint
+// launches in taylor.hip); this file launches it and holds the kernel for the
+// pairs between surfaces that every group of a batch holds unmoved.
 #include "pbt_internal.h"
 
 namespace pbt {
