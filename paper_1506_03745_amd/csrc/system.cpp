@@ -1449,6 +1449,8 @@ void System::build_plan() {
       if (t.tcount > 0 && known_panel[t.tbeg] && t.known) kk_p2p += (int64_t)t.tcount * t.nsrc;
     for (const Task& t : P.m2p)
       if (t.tcount > 0 && known_panel[t.tbeg] && t.known) kk_m2p += (int64_t)t.tcount * (t.lend - t.lbeg);
+    std::fprintf(stderr, "[plan] segments: p2p %lld, m2p %lld, shared p2p %lld, shared m2p %lld\n", (long long)seg_src,
+                 (long long)seg_box, (long long)seg_m, (long long)seg_box_m);
     std::fprintf(stderr, "[plan] pairs between surfaces without interior rows: p2p %lld, m2p %lld; "
                  "shared-surface P2P / M2P tasks %zu / %zu for %d groups\n",
                  (long long)kk_p2p, (long long)kk_m2p, P.p2pm.size(), P.m2pm.size(), P.mgroups);
