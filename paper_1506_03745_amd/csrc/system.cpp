@@ -531,6 +531,11 @@ void System::build(hipStream_t s) {
         maxlev = std::max(maxlev, tb.level);
       }
     for (int32_t b : plan_.blist) used[b] = 1;
+    // the boxes that shared-surface M2P tasks read in every group
+    for (const Task& t : plan_.m2pm)
+      for (int32_t r = t.lbeg; r < t.lend; ++r)
+        for (int g = t.split; g < std::min(plan_.mgroups, t.split + kMultiBlock); ++g)
+          used[plan_.blist[r] + plan_.mboxoff[(size_t)t.nsrc * plan_.mgroups + g]] = 1;
     // a box's parent precedes it in the numbering of its tree
     for (int b = 0; b < nbox_; ++b) need[b] = used[b] || (par[b] >= 0 && need[par[b]]);
     std::vector<MomChunk> ch, heads;
@@ -957,6 +962,34 @@ void System::build_plan() {
     if (!multi) std::fill(mshared.begin(), mshared.end(), 0);
   }
 
+  // A target group on a shared surface in a group other than 0 is a replica
+  // of group 0's: its lists against shared surfaces are group 0's (the same
+  // trees), so they are neither searched nor cut into ranges again; such
+  // pairs only reserve the replica's partial slots, one per segment of
+  // group 0's (rep: group 0's target group, -1 for the others).  kshared:
+  // per source surface, the index of group 0's copy in group 0's surfaces.
+  std::vector<int64_t> rep(leaves.size(), -1);
+  std::vector<int> kshared(ns, -1);
+  if (multi) {
+    const std::vector<int>& gs0 = group_surfs_[0];
+    for (int e = 0; e < ns; ++e)
+      if (mshared[e]) {
+        const int e0 = copy_in[0].at(surfs_[e]->shared);
+        for (size_t k = 0; k < gs0.size(); ++k)
+          if (gs0[k] == e0) kshared[e] = (int)k;
+      }
+    for (size_t li = 0; li < leaves.size(); ++li) {
+      const int e = leaves[li].e;
+      if (!mshared[e] || surfs_[e]->group == 0) continue;
+      const int e0 = copy_in[0].at(surfs_[e]->shared);
+      const int64_t l0 = lfirst[e0] + ((int64_t)li - lfirst[e]);
+      if (leaves[l0].e != e0 || leaves[l0].tb.pbeg != leaves[li].tb.pbeg || leaves[l0].tb.pend != leaves[li].tb.pend)
+        throw Error(PBT_E_STATE, "shared surfaces: target groups differ between groups");
+      rep[li] = l0;
+    }
+  }
+  auto replica_pair = [&](size_t li, int e2) { return rep[li] >= 0 && mshared[e2]; };
+
   // Per target group and source surface of its group of surfaces (k-th of
   // group_surfs_): merged P2P source ranges and M2P boxes.
   struct Lists { std::vector<std::pair<int32_t, int32_t>> rng; std::vector<int32_t> box; };
@@ -979,6 +1012,7 @@ void System::build_plan() {
       const int e2 = gsf[k2];
       const int f = form(leaves[li].e, e2);
       if (f == 0) continue;   // neither row of the leaf's surface sees e2
+      if (replica_pair(li, e2)) continue;   // group 0's lists (below)
       const bool fused_pair = (f & 3) != 0 && (f >> 2) != 0;
       std::vector<int> pb, mb;
       if (prm_.treecode) interaction_lists(trees_[e2], tl, prm_.theta, pb, mb);
@@ -1009,6 +1043,23 @@ void System::build_plan() {
       }
       lp2p_[li][k2] = std::move(pb);
       lm2p_[li][k2] = std::move(mb);
+    }
+  });
+  // the replicas' lists against shared surfaces (box numbers are local to
+  // the source tree, the same in every group) and their pair counts
+  parallel_for((int64_t)leaves.size(), [&](int64_t li) {
+    if (rep[li] < 0) return;
+    const int64_t nt = leaves[li].tb.pend - leaves[li].tb.pbeg;
+    const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
+    for (size_t k2 = 0; k2 < gsf.size(); ++k2) {
+      const int e2 = gsf[k2];
+      if (!replica_pair(li, e2) || form(leaves[li].e, e2) == 0) continue;
+      const int k0 = kshared[e2];
+      lp2p_[li][k2] = lp2p_[rep[li]][k0];
+      lm2p_[li][k2] = lm2p_[rep[li]][k0];
+      std::array<int64_t, 8>& c = cnt[li];
+      for (int b : lp2p_[li][k2]) c[2] += (int64_t)(trees_[e2].boxes[b].pend - trees_[e2].boxes[b].pbeg) * K_ * nt;
+      c[3] += (int64_t)lm2p_[li][k2].size() * nt;
     }
   });
   clk.mark_host(" lists");
@@ -1068,7 +1119,8 @@ void System::build_plan() {
       full_first[li] = 1;
   // Segments per (leaf, source surface): each group's ranges and boxes cut
   // into its own arrays in parallel, then laid end to end in group order.
-  struct Seg { int32_t lbeg, lend; int e2; bool m2p; bool shared = false; };   // e2: the source surface
+  // e2: the source surface; a replica segment only reserves a slot
+  struct Seg { int32_t lbeg, lend; int e2; bool m2p; bool shared = false; bool replica = false; };
   std::vector<std::vector<Seg>> segs(leaves.size());
   std::vector<std::vector<int32_t>> lranges(leaves.size()), lblist(leaves.size());
   parallel_for((int64_t)leaves.size(), [&](int64_t li) {
@@ -1077,6 +1129,7 @@ void System::build_plan() {
     std::vector<int32_t>& bl_out = lblist[li];
     for (size_t k2 = 0; k2 < gsf.size(); ++k2) {
       const int e2 = gsf[k2];
+      if (replica_pair(li, e2)) continue;   // placeholders below
       const Lists& o = L[li][k2];
       const bool shp = mshared[leaves[li].e] && mshared[e2];
       const int64_t seg = shp ? seg_m : seg_src;
@@ -1108,6 +1161,18 @@ void System::build_plan() {
           if (sg.e2 == e2) sg.shared = true;
     }
   });
+  // a replica's shared segments: one placeholder per segment of group 0's
+  // target group, in the same order (after the replica's own segments)
+  parallel_for((int64_t)leaves.size(), [&](int64_t li) {
+    if (rep[li] < 0) return;
+    const std::vector<int>& gsf = group_surfs_[surfs_[leaves[li].e]->group];
+    for (int e2 : gsf) {
+      if (!replica_pair(li, e2)) continue;
+      const int e20 = group_surfs_[0][kshared[e2]];
+      for (const Seg& s0 : segs[rep[li]])
+        if (s0.shared && s0.e2 == e20) segs[li].push_back({0, 0, e2, s0.m2p, true, true});
+    }
+  });
   {
     std::vector<int64_t> roff(leaves.size() + 1, 0), boff(leaves.size() + 1, 0);
     for (size_t li = 0; li < leaves.size(); ++li) {
@@ -1122,6 +1187,7 @@ void System::build_plan() {
       std::copy(lranges[li].begin(), lranges[li].end(), P.ranges.begin() + roff[li]);
       std::copy(lblist[li].begin(), lblist[li].end(), P.blist.begin() + boff[li]);
       for (Seg& sg : segs[li]) {
+        if (sg.replica) continue;
         const int32_t d = (int32_t)(sg.m2p ? boff[li] : roff[li] / 2);
         sg.lbeg += d;
         sg.lend += d;
@@ -1313,9 +1379,12 @@ void System::build_plan() {
         const int sidx = sid_index.at(surfs_[a0.e2]->shared);
         for (int g = 0; g < ngroups; ++g) {
           const Seg& ag = segs[lg[g]][sg[g][k]];
-          bool same = ag.lend - ag.lbeg == a0.lend - a0.lbeg && ag.m2p == a0.m2p && mshared[ag.e2] &&
-                      surfs_[ag.e2]->shared == surfs_[a0.e2]->shared;
-          if (a0.m2p) {
+          bool same = ag.m2p == a0.m2p && mshared[ag.e2] && surfs_[ag.e2]->shared == surfs_[a0.e2]->shared;
+          if (ag.replica) {
+            // (group 0's lists by construction)
+          } else if (ag.lend - ag.lbeg != a0.lend - a0.lbeg) {
+            same = false;
+          } else if (a0.m2p) {
             const int32_t off = boxoff[(size_t)sidx * ngroups + g];
             for (int32_t q = 0; same && q < a0.lend - a0.lbeg; ++q)
               same = P.blist[ag.lbeg + q] == P.blist[a0.lbeg + q] + off;
