@@ -107,9 +107,16 @@ struct NearParams {
   const double* gl_t; const double* gl_w;
 };
 // vals[4*e] = (V_L, K_L, V_Y, K_Y) corrections: fine (or self) minus the K-point rule.
+// Rows i with skip[i] >= 0 (skip nullable) are left alone.
 void launch_near_values(int64_t nt, const double* tx, const int32_t* tgt_self, const int64_t* rowptr,
                         const int32_t* col, const double* tri9, const double* nrm,
-                        const double* area, const NearParams& p, double* vals, hipStream_t s);
+                        const double* area, const NearParams& p, double* vals, hipStream_t s,
+                        const int32_t* skip = nullptr);
+// Rows of targets i with rep[i] >= 0 taken from row rep[i] (the same length):
+// columns shifted by i - rep[i] (a copy of a surface, its panels at that
+// offset), then, after the values, the values copied.
+void launch_near_copy_cols(int64_t nt, const int32_t* rep, const int64_t* rowptr, int32_t* col, hipStream_t s);
+void launch_near_copy_vals(int64_t nt, const int32_t* rep, const int64_t* rowptr, double* vals, hipStream_t s);
 // Inverse self blocks of every panel (m[4 np]: z_phi = m0 v_int + m1 v_out,
 // z_psi = m2 v_int + m3 v_out), the right block-Jacobi preconditioner.
 void launch_self_blocks(int64_t np, const double* tri9, const double* cen, const int32_t* panel_surf,
@@ -119,7 +126,7 @@ void launch_self_blocks(int64_t np, const double* tri9, const double* cen, const
 // tgt_surf null: every target belongs to surface tsurf.
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
                       const int32_t* panel_surf, const uint8_t* forms, int nsurf, const double* surf_rhoinv,
-                      double* vals, hipStream_t s, int32_t tsurf = 0);
+                      double* vals, hipStream_t s, int32_t tsurf = 0, const int32_t* skip = nullptr);
 void launch_reac_cavity(int64_t nq, const double* qxyz, int64_t s0, int64_t s1, const double* src,
                         const int64_t* near_ptr, const int32_t* near_col, const double* near_val,
                         const double* sig, const double* mu, double* phi, hipStream_t s);

@@ -207,9 +207,9 @@ __global__ void k_near_values(int64_t nt, const double* __restrict__ tx,
                               const int32_t* __restrict__ tgt_self, const int64_t* __restrict__ rowptr,
                               const int32_t* __restrict__ col, const double* __restrict__ tri9,
                               const double* __restrict__ nrm, const double* __restrict__ area,
-                              NearParams p, double* vals) {
+                              NearParams p, double* vals, const int32_t* __restrict__ skip) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nt) return;
+  if (i >= nt || (skip && skip[i] >= 0)) return;
   const double x = tx[3 * i], y = tx[3 * i + 1], z = tx[3 * i + 2];
   const int32_t self = tgt_self ? tgt_self[i] : -1;
   for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
@@ -260,12 +260,34 @@ __device__ __forceinline__ void fold_pair(int f, double vl, double kl, double vy
   a[1] = f == 1 ? -kl : f == 2 ? ky : f == 3 ? kl : 0.0;
 }
 
+// A copy's near rows from the master rows (rep[i] >= 0): columns shifted by
+// the copy's panel offset, then values copied.
+__global__ void k_near_copy_cols(int64_t nt, const int32_t* __restrict__ rep, const int64_t* __restrict__ rowptr,
+                                 int32_t* col) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const int32_t m = rep[i];
+  if (m < 0) return;
+  const int64_t a = rowptr[i], b = rowptr[m], n = rowptr[i + 1] - a;
+  for (int64_t k = 0; k < n; ++k) col[a + k] = col[b + k] + (int32_t)(i - m);
+}
+
+__global__ void k_near_copy_vals(int64_t nt, const int32_t* __restrict__ rep, const int64_t* __restrict__ rowptr,
+                                 double* vals) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const int32_t m = rep[i];
+  if (m < 0) return;
+  const int64_t a = rowptr[i], b = rowptr[m], n = rowptr[i + 1] - a;
+  for (int64_t k = 0; k < 4 * n; ++k) vals[4 * a + k] = vals[4 * b + k];
+}
+
 __global__ void k_fold_near(int64_t nt, const int64_t* __restrict__ rowptr,
                             const int32_t* __restrict__ col, const int32_t* __restrict__ tgt_surf, int32_t tsurf,
                             const int32_t* __restrict__ panel_surf, const uint8_t* __restrict__ forms, int nsurf,
-                            const double* __restrict__ surf_rhoinv, double* vals) {
+                            const double* __restrict__ surf_rhoinv, double* vals, const int32_t* __restrict__ skip) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nt) return;
+  if (i >= nt || (skip && skip[i] >= 0)) return;
   const int32_t t = tgt_surf ? tgt_surf[i] : tsurf;
   for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
     const int32_t s = panel_surf[col[e]];
@@ -334,10 +356,10 @@ void launch_self_blocks(int64_t np, const double* tri9, const double* cen, const
 
 void launch_fold_near(int64_t nt, const int64_t* rowptr, const int32_t* col, const int32_t* tgt_surf,
                       const int32_t* panel_surf, const uint8_t* forms, int nsurf, const double* surf_rhoinv,
-                      double* vals, hipStream_t s, int32_t tsurf) {
+                      double* vals, hipStream_t s, int32_t tsurf, const int32_t* skip) {
   if (nt <= 0) return;
   k_fold_near<<<nblocks(nt, 256), 256, 0, s>>>(nt, rowptr, col, tgt_surf, tsurf, panel_surf, forms, nsurf,
-                                                surf_rhoinv, vals);
+                                                surf_rhoinv, vals, skip);
   PBT_HIP(hipGetLastError());
 }
 
@@ -385,10 +407,21 @@ void launch_pack_points(int64_t np, int64_t ns, const double* cen, const double*
 
 void launch_near_values(int64_t nt, const double* tx, const int32_t* tgt_self, const int64_t* rowptr,
                         const int32_t* col, const double* tri9, const double* nrm,
-                        const double* area, const NearParams& p, double* vals, hipStream_t s) {
+                        const double* area, const NearParams& p, double* vals, hipStream_t s,
+                        const int32_t* skip) {
   if (nt <= 0) return;
   k_near_values<<<nblocks(nt, 128), 128, 0, s>>>(nt, tx, tgt_self, rowptr, col, tri9, nrm, area, p,
-                                                  vals);
+                                                  vals, skip);
+  PBT_HIP(hipGetLastError());
+}
+void launch_near_copy_cols(int64_t nt, const int32_t* rep, const int64_t* rowptr, int32_t* col, hipStream_t s) {
+  if (nt <= 0) return;
+  k_near_copy_cols<<<nblocks(nt, 256), 256, 0, s>>>(nt, rep, rowptr, col);
+  PBT_HIP(hipGetLastError());
+}
+void launch_near_copy_vals(int64_t nt, const int32_t* rep, const int64_t* rowptr, double* vals, hipStream_t s) {
+  if (nt <= 0) return;
+  k_near_copy_vals<<<nblocks(nt, 256), 256, 0, s>>>(nt, rep, rowptr, vals);
   PBT_HIP(hipGetLastError());
 }
 

@@ -429,17 +429,31 @@ void System::build(hipStream_t s) {
         lmax[e] = std::max(lmax[e], prm_.near_factor * std::sqrt(2.0 * h_area_[poff_[e] + li]));
     struct TL { int e; const TreeBox* T; };
     std::vector<TL> tls;
-    for (int e = 0; e < ns; ++e)
+    std::vector<int64_t> tls_first(ns + 1, 0);   // first target leaf of each surface
+    for (int e = 0; e < ns; ++e) {
+      tls_first[e] = (int64_t)tls.size();
       for (const TreeBox& T : trees_[e].boxes)
         if (T.leaf) tls.push_back({e, &T});
-    std::vector<std::vector<std::pair<int64_t, int64_t>>> cand(tls.size());
-    parallel_for((int64_t)tls.size(), [&](int64_t k) {
+    }
+    tls_first[ns] = (int64_t)tls.size();
+    // A leaf of a shared surface's copy (twin) takes the near rows of group
+    // 0's leaf, shifted by the copy's panel offset, when nothing of its own
+    // group but its own surface comes near it and group 0's leaf's near
+    // panels all lie on group 0's copy (its own surface is not searched).
+    const bool replicate = !std::getenv("PBT_NO_SHARED");
+    std::vector<int64_t> mleaf(tls.size(), -1);
+    if (replicate)
+      for (size_t k = 0; k < tls.size(); ++k) {
+        const int e = tls[k].e;
+        if (twin[e] >= 0) mleaf[k] = tls_first[twin[e]] + ((int64_t)k - tls_first[e]);
+      }
+    // candidate ranges of leaf k on the surfaces of its group (only >= 0:
+    // that surface alone; skip >= 0: all but that surface)
+    auto search = [&](int64_t k, int only, int skip, std::vector<std::pair<int64_t, int64_t>>& rg) {
       const int e = tls[k].e;
       const TreeBox& T = *tls[k].T;
-      for (int64_t g = poff_[e] + T.pbeg; g < poff_[e] + T.pend; ++g) tleaf[g] = (int32_t)k;
-      std::vector<std::pair<int64_t, int64_t>>& rg = cand[k];
       for (int e2 = 0; e2 < ns; ++e2) {
-        if (surfs_[e2]->group != surfs_[e]->group) continue;
+        if (surfs_[e2]->group != surfs_[e]->group || (only >= 0 && e2 != only) || e2 == skip) continue;
         const SurfTree& S2 = trees_[e2];
         std::vector<int> stack{0};
         while (!stack.empty()) {
@@ -454,7 +468,30 @@ void System::build(hipStream_t s) {
         }
       }
       std::sort(rg.begin(), rg.end());
+    };
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> cand(tls.size());
+    parallel_for((int64_t)tls.size(), [&](int64_t k) {
+      const int e = tls[k].e;
+      const TreeBox& T = *tls[k].T;
+      for (int64_t g = poff_[e] + T.pbeg; g < poff_[e] + T.pend; ++g) tleaf[g] = (int32_t)k;
+      search(k, -1, mleaf[k] >= 0 ? e : -1, cand[k]);
     });
+    std::vector<int32_t> rep_tgt(np_, -1);
+    parallel_for((int64_t)tls.size(), [&](int64_t k) {
+      if (mleaf[k] < 0) return;
+      const int e = tls[k].e, e0 = twin[e];
+      bool ok = cand[k].empty();
+      for (const auto& r : cand[mleaf[k]]) ok = ok && r.first >= poff_[e0] && r.second <= poff_[e0 + 1];
+      const TreeBox& T = *tls[k].T;
+      if (ok) {
+        for (int64_t g = poff_[e] + T.pbeg; g < poff_[e] + T.pend; ++g) rep_tgt[g] = (int32_t)(g - poff_[e] + poff_[e0]);
+      } else {
+        mleaf[k] = -1;
+        search(k, e, -1, cand[k]);   // its own surface too
+      }
+    });
+    bool any_rep = false;
+    for (int32_t r : rep_tgt) any_rep = any_rep || r >= 0;
     for (const auto& rg : cand) {
       for (const auto& r : rg) {
         if (!lrange.empty() && (int64_t)lrange.size() / 2 > lptr.back() && lrange.back() == r.first)
@@ -479,6 +516,8 @@ void System::build(hipStream_t s) {
                       cnt.p, s);
     std::vector<int32_t> hc = cnt.download(s);
     clk.mark(" near count", s);
+    for (int64_t i = 0; i < np_; ++i)
+      if (rep_tgt[i] >= 0) hc[i] = hc[rep_tgt[i]];   // (its own count was 0: no candidates)
     std::vector<int64_t> ptr(np_ + 1, 0);
     for (int64_t i = 0; i < np_; ++i) ptr[i + 1] = ptr[i] + hc[i];
     near_.nnz = ptr[np_];
@@ -487,6 +526,11 @@ void System::build(hipStream_t s) {
     near_.val.alloc(4 * std::max<int64_t>(near_.nnz, 1));
     launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlptr.p, dlrange.p, near_f4(prm_.near_factor),
                      near_.ptr.p, near_.col.p, s);
+    DBuf<int32_t> drep;
+    if (any_rep) {
+      drep.upload(rep_tgt, s);
+      launch_near_copy_cols(np_, drep.p, near_.ptr.p, near_.col.p, s);
+    }
     clk.mark(" near fill", s);
     std::vector<int32_t> self(np_);
     for (int64_t i = 0; i < np_; ++i) self[i] = (int32_t)i;
@@ -494,9 +538,52 @@ void System::build(hipStream_t s) {
     dself.upload(self, s);
     NearParams np{K_, prm_.k_near, prm_.k_self_edge, kappa_, dbf.p, dwf.p, dbn.p, dwn.p, dgt.p, dgw.p};
     launch_near_values(np_, cen_.p, dself.p, near_.ptr.p, near_.col.p, tri9_.p, nrm_.p, area_.p, np,
-                       near_.val.p, s);
+                       near_.val.p, s, drep.p);
     launch_fold_near(np_, near_.ptr.p, near_.col.p, panel_surf_.p, panel_surf_.p, forms_.p, ns,
-                     surf_rhoinv_.p, near_.val.p, s);
+                     surf_rhoinv_.p, near_.val.p, s, 0, drep.p);
+    if (any_rep) launch_near_copy_vals(np_, drep.p, near_.ptr.p, near_.val.p, s);
+    if (any_rep && std::getenv("PBT_CHECK_NEAR")) {
+      // every target's rows searched and evaluated again, without copies,
+      // and compared bit for bit
+      std::vector<int64_t> lp2{0}, lr2;
+      for (size_t k = 0; k < tls.size(); ++k) {
+        std::vector<std::pair<int64_t, int64_t>> rg;
+        search((int64_t)k, -1, -1, rg);
+        for (const auto& r : rg) {
+          if (!lr2.empty() && (int64_t)lr2.size() / 2 > lp2.back() && lr2.back() == r.first) {
+            lr2.back() = r.second;
+          } else {
+            lr2.push_back(r.first);
+            lr2.push_back(r.second);
+          }
+        }
+        lp2.push_back((int64_t)lr2.size() / 2);
+      }
+      if (lr2.empty()) lr2 = {0, 0};
+      DBuf<int64_t> dlp2, dlr2;
+      dlp2.upload(lp2, s);
+      dlr2.upload(lr2, s);
+      DBuf<int32_t> c2, col2;
+      c2.alloc(np_);
+      launch_near_count(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlp2.p, dlr2.p, near_f4(prm_.near_factor),
+                        c2.p, s);
+      const std::vector<int32_t> h2 = c2.download(s);
+      std::vector<int64_t> p2(np_ + 1, 0);
+      for (int64_t i = 0; i < np_; ++i) p2[i + 1] = p2[i] + h2[i];
+      if (p2 != ptr) throw Error(PBT_E_STATE, "copied near rows differ in length from searched ones");
+      DBuf<double> val2;
+      col2.alloc(std::max<int64_t>(near_.nnz, 1));
+      val2.alloc(4 * std::max<int64_t>(near_.nnz, 1));
+      launch_near_fill(np_, cen_.p, np_, cen_.p, cross2_.p, dtleaf.p, dlp2.p, dlr2.p, near_f4(prm_.near_factor),
+                       near_.ptr.p, col2.p, s);
+      launch_near_values(np_, cen_.p, dself.p, near_.ptr.p, col2.p, tri9_.p, nrm_.p, area_.p, np, val2.p, s);
+      launch_fold_near(np_, near_.ptr.p, col2.p, panel_surf_.p, panel_surf_.p, forms_.p, ns, surf_rhoinv_.p,
+                       val2.p, s);
+      const std::vector<int32_t> ca = near_.col.download(s), cb = col2.download(s);
+      const std::vector<double> va = near_.val.download(s), vb = val2.download(s);
+      if (ca != cb || std::memcmp(va.data(), vb.data(), va.size() * sizeof(double)) != 0)
+        throw Error(PBT_E_STATE, "copied near rows differ from searched ones");
+    }
     clk.mark(" near values", s);
     near_.val32.alloc(near_.val.n);
     launch_to_f32((int64_t)near_.val.n, near_.val.p, near_.val32.p, s);

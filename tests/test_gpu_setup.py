@@ -35,3 +35,22 @@ def test_host_geometry_matches_device_batched(monkeypatch):
     t = c[None, :] - R @ c   # rotations about the molecule's centre
     f = s.solve_batch(ids[0], R.reshape(nb, 9), t)
     assert np.all(np.isfinite(f))
+
+
+def test_batched_near_rows_copied_match_searched(monkeypatch):
+    """In a batch the plate's copies take the near rows of group 0's copy
+    (shifted to their own panels) where nothing else comes near them; with
+    PBT_CHECK_NEAR set the library searches and evaluates every row again
+    and fails the set-up unless the copies agree bit for bit.  One placement
+    brings the molecule within the near distance of the plate, so that some
+    of its plate copy's rows are searched instead of copied."""
+    monkeypatch.setenv("PBT_CHECK_NEAR", "1")
+    pr = config_problem("orient_sweep_small")
+    s, ids = from_problem(pr, treecode=1)
+    nb = 3
+    R = random_rotations(nb, 7)
+    c = pr.surfaces[0].q_pos[0]
+    t = c[None, :] - R @ c
+    t[2, 2] -= 8.5   # the last placement's sphere ends 1.5 A above the plate
+    f = s.solve_batch(ids[0], R.reshape(nb, 9), t)
+    assert np.all(np.isfinite(f))
