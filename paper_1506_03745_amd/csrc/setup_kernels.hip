@@ -261,25 +261,28 @@ __device__ __forceinline__ void fold_pair(int f, double vl, double kl, double vy
 }
 
 // A copy's near rows from the master rows (rep[i] >= 0): columns shifted by
-// the copy's panel offset, then values copied.
+// the copy's panel offset, then values copied.  One wavefront per row, lanes
+// over its entries (coalesced).
 __global__ void k_near_copy_cols(int64_t nt, const int32_t* __restrict__ rep, const int64_t* __restrict__ rowptr,
                                  int32_t* col) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= nt) return;
   const int32_t m = rep[i];
   if (m < 0) return;
   const int64_t a = rowptr[i], b = rowptr[m], n = rowptr[i + 1] - a;
-  for (int64_t k = 0; k < n; ++k) col[a + k] = col[b + k] + (int32_t)(i - m);
+  for (int64_t k = lane; k < n; k += 64) col[a + k] = col[b + k] + (int32_t)(i - m);
 }
 
 __global__ void k_near_copy_vals(int64_t nt, const int32_t* __restrict__ rep, const int64_t* __restrict__ rowptr,
                                  double* vals) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= nt) return;
   const int32_t m = rep[i];
   if (m < 0) return;
   const int64_t a = rowptr[i], b = rowptr[m], n = rowptr[i + 1] - a;
-  for (int64_t k = 0; k < 4 * n; ++k) vals[4 * a + k] = vals[4 * b + k];
+  for (int64_t k = lane; k < 4 * n; k += 64) vals[4 * a + k] = vals[4 * b + k];
 }
 
 __global__ void k_fold_near(int64_t nt, const int64_t* __restrict__ rowptr,
@@ -416,12 +419,12 @@ void launch_near_values(int64_t nt, const double* tx, const int32_t* tgt_self, c
 }
 void launch_near_copy_cols(int64_t nt, const int32_t* rep, const int64_t* rowptr, int32_t* col, hipStream_t s) {
   if (nt <= 0) return;
-  k_near_copy_cols<<<nblocks(nt, 256), 256, 0, s>>>(nt, rep, rowptr, col);
+  k_near_copy_cols<<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, rep, rowptr, col);
   PBT_HIP(hipGetLastError());
 }
 void launch_near_copy_vals(int64_t nt, const int32_t* rep, const int64_t* rowptr, double* vals, hipStream_t s) {
   if (nt <= 0) return;
-  k_near_copy_vals<<<nblocks(nt, 256), 256, 0, s>>>(nt, rep, rowptr, vals);
+  k_near_copy_vals<<<nblocks(64 * nt, 256), 256, 0, s>>>(nt, rep, rowptr, vals);
   PBT_HIP(hipGetLastError());
 }
 
