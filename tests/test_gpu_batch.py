@@ -15,7 +15,7 @@ import pytest
 from oracle.bem import interaction_energy
 from paper_1506_03745_amd import MIXED, from_problem
 from workloads.meshes import box_plate, icosphere
-from workloads.problems import CAVITY, CHARGED, MOLECULE, STERN, Problem, Surface, random_rotations
+from workloads.problems import CAVITY, CHARGED, MOLECULE, POTENTIAL, STERN, Problem, Surface, random_rotations
 
 pytestmark = pytest.mark.gpu
 
@@ -100,12 +100,36 @@ def test_batch_shared_surfaces_treecode(kappa, k_far, monkeypatch):
     e = s.solve()
     scale = abs(e.F_solv) + abs(e.F_surf)
     assert np.max(np.abs(f_batch - f_plain)) <= 1e-8 * scale
+    assert np.any(f_batch != f_plain)   # the two paths did differ (summation order)
     for b in (0, 17):
         pb = placed(pr, R[b], t[b])
         sb, _ = from_problem(pb, **prm)
         f, res = sb.interaction_energy(2)
         assert abs(f_batch[b] - f) <= 1e-5 * scale, (b, f_batch[b], f)
         sb.close()
+
+
+def test_batch_two_shared_surfaces(monkeypatch):
+    """Two unmoved surfaces (the plate and a second, potential-carrying
+    plate beside it): the pairs within each and between the two go to the
+    shared-surface tasks (two box-offset rows); 18 placements, mixed
+    precision, against the same batch in per-placement tasks."""
+    pr = body_problem()
+    pv, pt = box_plate(8, 14, -6, 6, -2, 0, 4, 8, 2)
+    pr.surfaces.append(Surface(POTENTIAL, pv, pt, bc=np.full(len(pt), 0.02)))
+    prm = dict(treecode=1, ncrit=24, theta=0.5, taylor_p=6, prec=MIXED, tol=1e-8)
+    nb = 18
+    R, t = placements(nb)
+    s, ids = from_problem(pr, **prm)
+    f_batch = s.solve_batch(ids[0], R.reshape(nb, 9), t)
+    monkeypatch.setenv("PBT_NO_SHARED", "1")
+    f_plain = s.solve_batch(ids[0], R.reshape(nb, 9), t)
+    monkeypatch.delenv("PBT_NO_SHARED")
+    e = s.solve()
+    scale = abs(e.F_solv) + abs(e.F_surf)
+    assert np.max(np.abs(f_batch - f_plain)) <= 1e-5 * scale
+    assert np.any(f_batch != f_plain)   # the two paths did differ (summation order)
+    assert len(set(np.round(f_batch, 8))) > 1
 
 
 def nested_body_problem():
